@@ -1,0 +1,354 @@
+"""FP64 CPU oracle for the DGFEM S_n sweep of Tano & Ragusa (arXiv 1906.04017).
+
+TEST INFRASTRUCTURE -- NOT PART OF THE PRODUCT.  Only ``tests/``, the smoke
+check in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import
+this package.  It is a plain, slow, obviously-correct implementation written
+from the paper: element matrices by Gauss quadrature, cell systems assembled
+term by term, Gaussian elimination with partial pivoting, sweeps by nested
+loops in upwind order, source iteration, the exact discrete adjoint, and the
+FP64 forward pass of a shallow ANN.  It shares no code with the HIP library.
+
+Array conventions (identical to the library's public layout, but implemented
+separately): cell index c = i + nx (j + ny k); nodal fields are
+[G][ncell][8] with local node n = ix + 2 iy + 4 iz fastest; per-cell fields are
+[G][ncell]; faces f = 2 axis + side (side 1 = high face).
+
+Parity status of each function is recorded in its docstring; every function
+here is pinned by the ``-m "not gpu"`` tests (closed forms, brute force,
+invariants, finite differences), except where a docstring says
+"parity unpinned".
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .quadrature import lq_n  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    src = os.path.join(_HERE, "dgfem.c")
+    if (not os.path.exists(_LIB_PATH)) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        from .build import build
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_element_matrices.argtypes = [_D, _D, _D, _D]
+    lib.orc_ge_solve.argtypes = [ctypes.c_int, _D, _D, _D]
+    lib.orc_sweep.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [ctypes.c_int] * 2 + \
+        [_D] * 5 + [_D, _D, ctypes.c_int]
+    lib.orc_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 6 + [_D, ctypes.c_double, ctypes.c_int, _I, _D, _D, _D,
+                                          ctypes.c_int]
+    lib.orc_adjoint.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [ctypes.c_int] * 2 + \
+        [_D] * 7 + [ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _I, ctypes.c_int]
+    lib.orc_cell_balance.argtypes = [_D, _D, ctypes.c_double, _D, _D, _D]
+    lib.orc_cell_balance.restype = ctypes.c_double
+    lib.orc_cell_solve_batch.argtypes = [ctypes.c_long, _D, _D, _D, _D, _D, _D, ctypes.c_int]
+    lib.orc_ann_features.argtypes = [_D, _D, ctypes.c_double, _D, _D, _D, _D]
+    lib.orc_ann_forward.argtypes = [ctypes.c_int] * 4 + [_D] * 6
+    lib.orc_ann_cell_batch.argtypes = [ctypes.c_long, _D, _D, _D, _D, _D, ctypes.c_int,
+                                       ctypes.c_int, _D, _D, _D, _D, _D]
+    lib.orc_ann_sweep.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 5 + [ctypes.c_int, ctypes.c_int] + [_D] * 5 + [ctypes.c_int]
+    lib.orc_ann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 6 + [ctypes.c_int, ctypes.c_int] + [_D] * 5 + \
+        [ctypes.c_double, ctypes.c_int, _I, _D, _D, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+ORC_ENOTCONV = -4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc not in (0, ORC_ENOTCONV):
+        raise OracleError(f"{what} failed with code {rc}")
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# element level
+# ---------------------------------------------------------------------------
+
+def element_matrices(h):
+    """Mass M, gradient G[a] (test-function derivative) and face masses Mf[f]
+    of one hexahedron with edge lengths h, by 2-point Gauss quadrature
+    (weak form under Eq. (T9)).  Pinned by the Kronecker closed form."""
+    lib = _load()
+    h = _f64(h, (3,))
+    M = np.zeros(64)
+    G = np.zeros(3 * 64)
+    Mf = np.zeros(6 * 64)
+    lib.orc_element_matrices(_p(h), _p(M), _p(G), _p(Mf))
+    return M.reshape(8, 8), G.reshape(3, 8, 8), Mf.reshape(6, 8, 8)
+
+
+def ge_solve(A, b):
+    """Gaussian elimination with partial pivoting (Eq. (T12) solve)."""
+    lib = _load()
+    A = _f64(A)
+    n = A.shape[0]
+    b = _f64(b, (n,))
+    x = np.zeros(n)
+    rc = lib.orc_ge_solve(n, _p(A), _p(b), _p(x))
+    if rc:
+        raise OracleError(f"ge_solve failed ({rc})")
+    return x
+
+
+def cell_balance(h, omega, sigma_t, S, psi_up, psi):
+    """1^T (A psi - b) of one cell system (particle balance residual)."""
+    lib = _load()
+    return lib.orc_cell_balance(_p(_f64(h, (3,))), _p(_f64(omega, (3,))), float(sigma_t),
+                                _p(_f64(S, (8,))), _p(_f64(psi_up, (6, 8))), _p(_f64(psi, (8,))))
+
+
+def cell_solve_batch(h, omega, sigma_t, S, psi_up, nthreads=0):
+    """Batched one-cell assemble + GE in physical orientation.
+    h, omega [n,3]; sigma_t [n]; S [n,8]; psi_up [n,6,8] (inflow faces only)."""
+    lib = _load()
+    omega = _f64(omega)
+    n = omega.shape[0]
+    h = _f64(np.broadcast_to(np.asarray(h, np.float64), (n, 3)))
+    out = np.zeros((n, 8))
+    rc = lib.orc_cell_solve_batch(n, _p(h), _p(omega), _p(_f64(sigma_t, (n,))), _p(_f64(S, (n, 8))),
+                                  _p(_f64(psi_up, (n, 6, 8))), _p(out), int(nthreads))
+    _check(rc, "cell_solve_batch")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# sweep / source iteration / adjoint
+# ---------------------------------------------------------------------------
+
+def _mesh_args(mesh):
+    nx, ny, nz, lx, ly, lz = mesh
+    return int(nx), int(ny), int(nz), float(lx), float(ly), float(lz)
+
+
+def sweep(mesh, omega, weight, sigma_t, src, psi_inc=None, store_psi=False, nthreads=0):
+    """One full sweep (all directions, all groups).
+
+    mesh = (nx, ny, nz, lx, ly, lz); omega [D,3]; weight [D];
+    sigma_t [G, ncell]; src [G, ncell, 8] total nodal source per steradian;
+    psi_inc [6] per domain face.  Returns phi [G, ncell, 8] (and psi
+    [D, G, ncell, 8] with store_psi).  Pinned by brute force and invariants.
+    """
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    src = _f64(src, (ng, ncell, 8))
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    phi = np.zeros((ng, ncell, 8))
+    psi = np.zeros((nd, ng, ncell, 8)) if store_psi else None
+    rc = lib.orc_sweep(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                       _p(sigma_t), _p(src), _p(inc), _p(phi), _p(psi), int(nthreads))
+    _check(rc, "sweep")
+    return (phi, psi) if store_psi else phi
+
+
+def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-8,
+                   max_iter=1000, phi0=None, store_psi=False, nthreads=0):
+    """Scattering source iteration to max-norm relative change < tol.
+    Returns dict(phi, iters, resid, eps_s, converged[, psi])."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    sigma_s = _f64(sigma_s, (ng, ncell))
+    q = _f64(q, (ng, ncell))
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    phi = np.zeros((ng, ncell, 8)) if phi0 is None else _f64(phi0, (ng, ncell, 8)).copy()
+    psi = np.zeros((nd, ng, ncell, 8)) if store_psi else None
+    it = ctypes.c_int(0)
+    resid = ctypes.c_double(0)
+    eps = ctypes.c_double(0)
+    rc = lib.orc_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                                _p(sigma_t), _p(sigma_s), _p(q), _p(inc), _p(phi), float(tol),
+                                int(max_iter), ctypes.byref(it), ctypes.byref(resid),
+                                ctypes.byref(eps), _p(psi), int(nthreads))
+    _check(rc, "source_iterate")
+    out = dict(phi=phi, iters=it.value, resid=resid.value, eps_s=eps.value, converged=(rc == 0))
+    if store_psi:
+        out["psi"] = psi
+    return out
+
+
+def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, max_iter=2000,
+            nthreads=0):
+    """Exact discrete adjoint of the converged source iteration.
+    gphi = dJ/dphi [G, ncell, 8].  Returns dict(grad_sigma_t, grad_q,
+    grad_sigma_s [G, ncell], phi_dag [G, ncell, 8], iters); direct partial
+    derivatives of J are not included.  Pinned by duality, the dense transpose
+    and central finite differences."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    gst = np.zeros((ng, ncell))
+    gq = np.zeros((ng, ncell))
+    gss = np.zeros((ng, ncell))
+    pd = np.zeros((ng, ncell, 8))
+    it = ctypes.c_int(0)
+    rc = lib.orc_adjoint(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                         _p(sigma_t), _p(_f64(sigma_s, (ng, ncell))),
+                         _p(_f64(psi, (nd, ng, ncell, 8))), _p(_f64(phi, (ng, ncell, 8))),
+                         _p(_f64(gphi, (ng, ncell, 8))), float(tol), int(max_iter), _p(gst),
+                         _p(gq), _p(gss), _p(pd), ctypes.byref(it), int(nthreads))
+    _check(rc, "adjoint")
+    return dict(grad_sigma_t=gst, grad_q=gq, grad_sigma_s=gss, phi_dag=pd, iters=it.value,
+                converged=(rc == 0))
+
+
+# ---------------------------------------------------------------------------
+# shallow ANN (Sec. 3)
+# ---------------------------------------------------------------------------
+
+ACT_RELU = 0
+ACT_TANH = 1
+
+
+def ann_features(h, omega, sigma_t, S, psi_up):
+    """Canonical 24-feature input and homogeneity scale m of one cell."""
+    lib = _load()
+    x = np.zeros(24)
+    m = np.zeros(1)
+    lib.orc_ann_features(_p(_f64(h, (3,))), _p(_f64(omega, (3,))), float(sigma_t), _p(_f64(S, (8,))),
+                         _p(_f64(psi_up, (6, 8))), _p(x), _p(m))
+    return x, float(m[0])
+
+
+def ann_forward(net, x):
+    """FP64 forward pass, Eq. (ANN:Eq1) with a linear output layer."""
+    lib = _load()
+    W1, b1, W2, b2 = (_f64(net[k]) for k in ("W1", "b1", "W2", "b2"))
+    nh, nin = W1.shape
+    nout = W2.shape[0]
+    x = _f64(x, (nin,))
+    y = np.zeros(nout)
+    lib.orc_ann_forward(nin, nh, nout, int(net.get("act", ACT_RELU)), _p(W1), _p(b1), _p(W2),
+                        _p(b2), _p(x), _p(y))
+    return y
+
+
+def _net_args(net):
+    W1, b1, W2, b2 = (_f64(net[k]) for k in ("W1", "b1", "W2", "b2"))
+    return W1.shape[0], int(net.get("act", ACT_RELU)), W1, b1, W2, b2
+
+
+def ann_cell_batch(net, h, omega, sigma_t, S, psi_up):
+    lib = _load()
+    omega = _f64(omega)
+    n = omega.shape[0]
+    h = _f64(np.broadcast_to(np.asarray(h, np.float64), (n, 3)))
+    nh, act, W1, b1, W2, b2 = _net_args(net)
+    out = np.zeros((n, 8))
+    rc = lib.orc_ann_cell_batch(n, _p(h), _p(omega), _p(_f64(sigma_t, (n,))), _p(_f64(S, (n, 8))),
+                                _p(_f64(psi_up, (n, 6, 8))), nh, act, _p(W1), _p(b1), _p(W2),
+                                _p(b2), _p(out))
+    _check(rc, "ann_cell_batch")
+    return out
+
+
+def ann_sweep(net, mesh, omega, weight, sigma_t, src, psi_inc=None, nthreads=0):
+    """Sweep with the ANN forward pass in place of assembly + GE."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    nh, act, W1, b1, W2, b2 = _net_args(net)
+    phi = np.zeros((ng, ncell, 8))
+    rc = lib.orc_ann_sweep(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                           _p(sigma_t), _p(_f64(src, (ng, ncell, 8))), _p(inc), nh, act, _p(W1),
+                           _p(b1), _p(W2), _p(b2), _p(phi), int(nthreads))
+    _check(rc, "ann_sweep")
+    return phi
+
+
+def ann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-4,
+                       max_iter=1000, nthreads=0):
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    nh, act, W1, b1, W2, b2 = _net_args(net)
+    phi = np.zeros((ng, ncell, 8))
+    it = ctypes.c_int(0)
+    resid = ctypes.c_double(0)
+    eps = ctypes.c_double(0)
+    rc = lib.orc_ann_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                    _p(_f64(weight, (nd,))), _p(sigma_t),
+                                    _p(_f64(sigma_s, (ng, ncell))), _p(_f64(q, (ng, ncell))),
+                                    _p(inc), nh, act, _p(W1), _p(b1), _p(W2), _p(b2), _p(phi),
+                                    float(tol), int(max_iter), ctypes.byref(it),
+                                    ctypes.byref(resid), ctypes.byref(eps), int(nthreads))
+    _check(rc, "ann_source_iterate")
+    return dict(phi=phi, iters=it.value, resid=resid.value, eps_s=eps.value, converged=(rc == 0))
+
+
+# ---------------------------------------------------------------------------
+# error metrics (Sec. 4)
+# ---------------------------------------------------------------------------
+
+def cell_average(phi):
+    """Cell average of a nodal trilinear field [G, ncell, 8] -> [G, ncell]."""
+    return np.asarray(phi, np.float64).mean(axis=-1)
+
+
+def eps_p(phi_ref, phi, m=1e-8):
+    """Eq. (Test:Eq2): mean over cells of |phi - phi_ann| / (|phi| + m), on
+    cell averages, per group."""
+    a = cell_average(phi_ref)
+    b = cell_average(phi)
+    return (np.abs(a - b) / (np.abs(a) + m)).mean(axis=-1)
+
+
+def rel_err(phi_ref, phi):
+    """Norm-wise relative error max|phi - ref| / max|ref| per group."""
+    a = np.asarray(phi_ref, np.float64)
+    b = np.asarray(phi, np.float64)
+    ax = tuple(range(1, a.ndim))
+    return np.abs(a - b).max(axis=ax) / np.abs(a).max(axis=ax)

@@ -1,0 +1,848 @@
+/*
+ * FP64 CPU oracle for the trilinear-hexahedron DGFEM S_n transport sweep of
+ * Tano & Ragusa, "Acceleration of Radiation Transport Solves Using Artificial
+ * Neural Networks" (arXiv 1906.04017).
+ *
+ * THIS IS TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  It is a plain, slow,
+ * obviously-correct reference used only by the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark.  It shares no code with the HIP
+ * library (no headers, helpers, tables or constant generators) and must never
+ * be linked into it.
+ *
+ * What it follows in the paper:
+ *   - Sec. 2, Eq. (T1): steady mono-energetic transport, Omega.grad psi + sigma_t psi = Q.
+ *   - Eq. (T2)-(T8), P0 (isotropic) part only: Q = q_ext + sigma_s/(4 pi) phi,
+ *     phi = sum_d w_d psi_d.  Groups are decoupled (in-group scattering only).
+ *   - Eq. (T9): trilinear nodal trial space on each hexahedron, 8 vertex nodes,
+ *     local node n = ix + 2 iy + 4 iz.
+ *   - The weak form below Eq. (T9): streaming by Green's theorem, element mass
+ *     M, gradient matrices, face mass matrices on the inflow / outflow parts of
+ *     the cell boundary, full upwinding of the inflow trace (Sec. 2, the
+ *     "first order interpolation" paragraph), boundary inflow Eq. (TBC).
+ *   - Eq. (T12): the per-cell system A psi_d = b solved by Gaussian elimination
+ *     (partial pivoting, lowest row index on ties; the paper does not state the
+ *     pivoting rule).
+ *   - Sec. 2, the sweep paragraph after Eq. (T12): cells are visited from the
+ *     inflow boundaries downstream; here by plain nested loops in upwind order.
+ *   - Source iteration (Sec. 2, after Eq. (T6)); stopping metric Eq. (Test:Eq3).
+ *
+ * Element matrices are integrated with a 2-point Gauss-Legendre tensor rule
+ * (exact for these polynomial integrands).  Everything is double precision.
+ *
+ * The adjoint (discrete transpose of the source-iteration system) is not in the
+ * paper; it is the exact transpose of the operator above, written out with
+ * explicit transposed matrices and a reversed (downwind-to-upwind) sweep.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+#define ORC_ESINGULAR -3
+#define ORC_ENOTCONV -4
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------ */
+/* Basis functions on the reference cube [0,1]^3                        */
+/* ------------------------------------------------------------------ */
+
+/* 1D Lagrange basis on [0,1]: l0(s) = 1 - s, l1(s) = s. */
+static double lag(int i, double s) { return i ? s : 1.0 - s; }
+static double dlag(int i) { return i ? 1.0 : -1.0; }
+
+static int node_bit(int n, int axis) { return (n >> axis) & 1; }
+
+/* b_n at reference point (xi[0], xi[1], xi[2]). */
+static double basis(int n, const double xi[3])
+{
+    return lag(node_bit(n, 0), xi[0]) * lag(node_bit(n, 1), xi[1]) * lag(node_bit(n, 2), xi[2]);
+}
+
+/* d b_n / d x_axis in physical units, cell sizes h[3]. */
+static double dbasis(int n, int axis, const double xi[3], const double h[3])
+{
+    double v = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (a == axis) v *= dlag(node_bit(n, a)) / h[a];
+        else v *= lag(node_bit(n, a), xi[a]);
+    }
+    return v;
+}
+
+/*
+ * Element matrices of one hexahedron with edge lengths h[3]
+ * (weak form under Eq. (T9)):
+ *   M[k][j]     = int_V b_k b_j dV                      (mass)
+ *   G[a][k][j]  = int_V (d_a b_k) b_j dV                (gradient of the test function)
+ *   Mf[f][k][j] = int_{face f} b_k b_j dA               (face mass)
+ * Faces: f = 2*axis + side, side 0 is the low face (outward normal -e_axis),
+ * side 1 the high face (+e_axis).  2-point Gauss-Legendre per direction.
+ */
+void orc_element_matrices(const double h[3], double M[64], double G[3][64], double Mf[6][64])
+{
+    const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+    const double gw = 0.5;
+    const double vol = h[0] * h[1] * h[2];
+    memset(M, 0, 64 * sizeof(double));
+    memset(G, 0, 3 * 64 * sizeof(double));
+    memset(Mf, 0, 6 * 64 * sizeof(double));
+    for (int qx = 0; qx < 2; ++qx)
+        for (int qy = 0; qy < 2; ++qy)
+            for (int qz = 0; qz < 2; ++qz) {
+                const double xi[3] = {gp[qx], gp[qy], gp[qz]};
+                const double wq = gw * gw * gw * vol;
+                for (int k = 0; k < 8; ++k)
+                    for (int j = 0; j < 8; ++j) {
+                        M[k * 8 + j] += wq * basis(k, xi) * basis(j, xi);
+                        for (int a = 0; a < 3; ++a)
+                            G[a][k * 8 + j] += wq * dbasis(k, a, xi, h) * basis(j, xi);
+                    }
+            }
+    for (int axis = 0; axis < 3; ++axis) {
+        const int t1 = (axis + 1) % 3, t2 = (axis + 2) % 3;
+        const double area = h[t1] * h[t2];
+        for (int side = 0; side < 2; ++side) {
+            const int f = 2 * axis + side;
+            for (int q1 = 0; q1 < 2; ++q1)
+                for (int q2 = 0; q2 < 2; ++q2) {
+                    double xi[3];
+                    xi[axis] = (double)side;
+                    xi[t1] = gp[q1];
+                    xi[t2] = gp[q2];
+                    const double wq = gw * gw * area;
+                    for (int k = 0; k < 8; ++k)
+                        for (int j = 0; j < 8; ++j)
+                            Mf[f][k * 8 + j] += wq * basis(k, xi) * basis(j, xi);
+                }
+        }
+    }
+}
+
+/* Outward normal component of face f along its axis: -1 (low) or +1 (high). */
+static double face_sign(int f) { return (f & 1) ? 1.0 : -1.0; }
+
+/* ------------------------------------------------------------------ */
+/* Gaussian elimination with partial pivoting (Eq. (T12) solve)         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Solves A x = b for an n-by-n row-major A (n <= 8).  A and b are copied.
+ * Partial pivoting: the pivot of column k is the row i >= k with the largest
+ * |a_ik|; on ties the lowest index wins (strict comparison).
+ */
+int orc_ge_solve(int n, const double *A_in, const double *b_in, double *x)
+{
+    double A[64], b[8];
+    if (n < 1 || n > 8) return ORC_EINVAL;
+    memcpy(A, A_in, (size_t)n * n * sizeof(double));
+    memcpy(b, b_in, (size_t)n * sizeof(double));
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > best) { best = fabs(A[i * n + k]); p = i; }
+        if (best == 0.0) return ORC_ESINGULAR;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t;
+            }
+            double t = b[k]; b[k] = b[p]; b[p] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double l = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+        x[i] = s / A[i * n + i];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Local system of one cell and one direction (Eq. (T10)-(T12))         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Cell matrix for direction omega (integration-by-parts form):
+ *   A = - sum_a omega_a G_a + sum_{f: omega.n_f > 0} (omega.n_f) Mf_f + sigma_t M
+ * The outflow face terms stay on the left, the inflow ones go to the right
+ * hand side (the A_psi / b_psi split stated under Eq. (T12)).
+ */
+void orc_cell_matrix(const double omega[3], double sigma_t, const double M[64],
+                     const double G[3][64], const double Mf[6][64], double A[64])
+{
+    for (int e = 0; e < 64; ++e) {
+        double v = sigma_t * M[e];
+        for (int a = 0; a < 3; ++a) v -= omega[a] * G[a][e];
+        A[e] = v;
+    }
+    for (int f = 0; f < 6; ++f) {
+        const double on = omega[f / 2] * face_sign(f);
+        if (on > 0.0)
+            for (int e = 0; e < 64; ++e) A[e] += on * Mf[f][e];
+    }
+}
+
+/*
+ * Right-hand side:
+ *   b = sum_{f: omega.n_f < 0} |omega.n_f| Mf_f psi_up_f + M S
+ * psi_up[f][n] holds the upwind trace at the face-f nodes n of this cell
+ * (entries at nodes off the face are ignored by Mf_f).
+ */
+void orc_cell_rhs(const double omega[3], const double M[64], const double Mf[6][64],
+                  const double S[8], const double psi_up[6][8], double b[8])
+{
+    for (int k = 0; k < 8; ++k) {
+        double v = 0.0;
+        for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * S[j];
+        b[k] = v;
+    }
+    for (int f = 0; f < 6; ++f) {
+        const double on = omega[f / 2] * face_sign(f);
+        if (on < 0.0)
+            for (int k = 0; k < 8; ++k)
+                for (int j = 0; j < 8; ++j) b[k] += -on * Mf[f][k * 8 + j] * psi_up[f][j];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Mesh helpers                                                         */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int n[3];      /* cells per axis */
+    double h[3];   /* cell edge lengths */
+} orc_mesh;
+
+static long cell_index(const orc_mesh *m, const int c[3])
+{
+    return (long)c[0] + (long)m->n[0] * ((long)c[1] + (long)m->n[1] * (long)c[2]);
+}
+
+/* Neighbour across face f; returns 0 if the face lies on the domain boundary. */
+static int neighbour(const orc_mesh *m, const int c[3], int f, int nb[3])
+{
+    const int axis = f / 2;
+    nb[0] = c[0]; nb[1] = c[1]; nb[2] = c[2];
+    nb[axis] += (f & 1) ? 1 : -1;
+    return nb[axis] >= 0 && nb[axis] < m->n[axis];
+}
+
+/*
+ * Upwind trace for face f of cell c in direction omega (only called for
+ * inflow faces): the neighbour's nodal values at the coincident nodes (node
+ * index with the face-axis bit flipped), or the domain inflow value psi_inc[f]
+ * on the boundary (Eq. (TBC); vacuum is 0).
+ */
+static void upwind_trace(const orc_mesh *m, const int c[3], int f, const double *psi_dir,
+                         const double psi_inc[6], double out[8])
+{
+    int nb[3];
+    const int axis = f / 2;
+    if (neighbour(m, c, f, nb)) {
+        const double *pn = psi_dir + 8 * cell_index(m, nb);
+        for (int n = 0; n < 8; ++n) out[n] = pn[n ^ (1 << axis)];
+    } else {
+        for (int n = 0; n < 8; ++n) out[n] = psi_inc[f];
+    }
+}
+
+/* Visit order along one axis: upwind to downwind. */
+static int axis_start(int nax, double om) { return om >= 0.0 ? 0 : nax - 1; }
+static int axis_step(double om) { return om >= 0.0 ? 1 : -1; }
+
+/*
+ * One transport sweep for one direction and one group: solves the per-cell
+ * systems of Eq. (T12) cell by cell in upwind order (nested k, j, i loops, each
+ * running from the inflow side; a valid topological order of the upwind
+ * dependency graph).  psi_dir receives [ncell][8] nodal angular fluxes.
+ */
+typedef struct orc_ann orc_ann;
+static int ann_cell(const orc_ann *net, const double h[3], const double omega[3], double sigma_t,
+                    const double S[8], const double psi_up[6][8], double psi[8]);
+
+static int sweep_one(const orc_mesh *m, const double omega[3], const double *sigma_t,
+                     const double *src, const double psi_inc[6], const double M[64],
+                     const double G[3][64], const double Mf[6][64], const orc_ann *net,
+                     double *psi_dir)
+{
+    int c[3];
+    const int s0 = axis_start(m->n[0], omega[0]), d0 = axis_step(omega[0]);
+    const int s1 = axis_start(m->n[1], omega[1]), d1 = axis_step(omega[1]);
+    const int s2 = axis_start(m->n[2], omega[2]), d2 = axis_step(omega[2]);
+    for (int kk = 0; kk < m->n[2]; ++kk) {
+        c[2] = s2 + d2 * kk;
+        for (int jj = 0; jj < m->n[1]; ++jj) {
+            c[1] = s1 + d1 * jj;
+            for (int ii = 0; ii < m->n[0]; ++ii) {
+                c[0] = s0 + d0 * ii;
+                const long ci = cell_index(m, c);
+                double up[6][8], A[64], b[8];
+                memset(up, 0, sizeof(up));
+                for (int f = 0; f < 6; ++f)
+                    if (omega[f / 2] * face_sign(f) < 0.0)
+                        upwind_trace(m, c, f, psi_dir, psi_inc, up[f]);
+                int rc;
+                if (net) {
+                    rc = ann_cell(net, m->h, omega, sigma_t[ci], src + 8 * ci,
+                                  (const double(*)[8])up, psi_dir + 8 * ci);
+                } else {
+                    orc_cell_matrix(omega, sigma_t[ci], M, G, Mf, A);
+                    orc_cell_rhs(omega, M, Mf, src + 8 * ci, (const double(*)[8])up, b);
+                    rc = orc_ge_solve(8, A, b, psi_dir + 8 * ci);
+                }
+                if (rc) return rc;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+static int set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/*
+ * Full sweep over all directions and groups (one application of the inverse
+ * streaming-collision operator):
+ *   sigma_t [G][ncell], src [G][ncell][8] total nodal source per steradian,
+ *   psi_inc[6] per domain face, phi [G][ncell][8] out = sum_d w_d psi_d
+ *   (Eq. (T11)), accumulated in direction order for every (g, cell, node).
+ *   psi_store, if not NULL, receives [D][G][ncell][8].
+ * Work units (d, g) are independent; blocks of them run in parallel and are
+ * summed into phi in unit order afterwards, so the result does not depend on
+ * the thread count.
+ */
+static int sweep_all(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                     const double *omega, const double *weight, const double *sigma_t,
+                     const double *src, const double psi_inc[6], double *phi, double *psi_store,
+                     const orc_ann *net, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || ng < 1 || nd < 1) return ORC_EINVAL;
+    orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
+    const long ncell = (long)nx * ny * nz;
+    double M[64], G[3][64], Mf[6][64];
+    orc_element_matrices(m.h, M, G, Mf);
+    const int nt = set_threads(nthreads);
+    const long nunits = (long)nd * ng;
+    double *buf = (double *)malloc((size_t)nt * ncell * 8 * sizeof(double));
+    if (!buf) return ORC_ENOMEM;
+    memset(phi, 0, (size_t)ng * ncell * 8 * sizeof(double));
+    int err = ORC_OK;
+    for (long u0 = 0; u0 < nunits && !err; u0 += nt) {
+        const long nb = (nunits - u0 < nt) ? nunits - u0 : nt;
+#pragma omp parallel for schedule(static, 1)
+        for (long t = 0; t < nb; ++t) {
+            const long u = u0 + t;
+            const int d = (int)(u / ng), g = (int)(u % ng);
+            int rc = sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, src + 8 * g * ncell,
+                               psi_inc, M, G, Mf, net, buf + t * ncell * 8);
+            if (rc) {
+#pragma omp critical
+                err = rc;
+            }
+        }
+        if (err) break;
+#pragma omp parallel for schedule(static)
+        for (long ci = 0; ci < ncell; ++ci)
+            for (long t = 0; t < nb; ++t) {
+                const long u = u0 + t;
+                const int d = (int)(u / ng), g = (int)(u % ng);
+                const double *p = buf + (t * ncell + ci) * 8;
+                double *f = phi + ((long)g * ncell + ci) * 8;
+                for (int n = 0; n < 8; ++n) f[n] += weight[d] * p[n];
+            }
+        if (psi_store)
+            for (long t = 0; t < nb; ++t) {
+                const long u = u0 + t;
+                const int d = (int)(u / ng), g = (int)(u % ng);
+                memcpy(psi_store + ((long)d * ng + g) * ncell * 8, buf + t * ncell * 8,
+                       (size_t)ncell * 8 * sizeof(double));
+            }
+    }
+    free(buf);
+    return err;
+}
+
+int orc_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+              const double *omega, const double *weight, const double *sigma_t,
+              const double *src, const double psi_inc[6], double *phi, double *psi_store,
+              int nthreads)
+{
+    return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
+                     psi_store, NULL, nthreads);
+}
+
+/* Nodal total source S = q_ext + sigma_s / (4 pi) phi (isotropic, Eq. (T5) P0 term). */
+static void build_source(long n, const double *q, const double *sigma_s, const double *phi,
+                         double *S)
+{
+    for (long gc = 0; gc < n; ++gc)
+        for (int k = 0; k < 8; ++k)
+            S[gc * 8 + k] = q[gc] + sigma_s[gc] / (4.0 * ORC_PI) * phi[gc * 8 + k];
+}
+
+/*
+ * Scattering source iteration.  phi [G][ncell][8] holds the initial guess on
+ * entry and the last iterate on exit.  Iterate: S = q + sigma_s/(4 pi) phi^n,
+ * sweep, phi^{n+1}.  Residual r = max|phi^{n+1} - phi^n| / max|phi^{n+1}| over
+ * all entries; eps_s is Eq. (Test:Eq3) on cell averages.  Stops when r < tol.
+ * Returns ORC_ENOTCONV when max_iter sweeps did not reach tol.
+ */
+static int source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                          int nd, const double *omega, const double *weight,
+                          const double *sigma_t, const double *sigma_s, const double *q,
+                          const double psi_inc[6], double *phi, double tol, int max_iter,
+                          int *iters, double *resid, double *eps_s, double *psi_store,
+                          const orc_ann *net, int nthreads)
+{
+    const long ncell = (long)nx * ny * nz;
+    const long nv = (long)ng * ncell;
+    double *S = (double *)malloc((size_t)nv * 8 * sizeof(double));
+    double *phin = (double *)malloc((size_t)nv * 8 * sizeof(double));
+    if (!S || !phin) { free(S); free(phin); return ORC_ENOMEM; }
+    int it = 0, rc = ORC_OK;
+    double r = INFINITY, es = INFINITY;
+    while (it < max_iter) {
+        build_source(nv, q, sigma_s, phi, S);
+        rc = sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, S, psi_inc, phin,
+                       psi_store, net, nthreads);
+        if (rc) break;
+        double dmax = 0.0, fmax = 0.0, esum = 0.0;
+        for (long i = 0; i < nv * 8; ++i) {
+            const double dd = fabs(phin[i] - phi[i]);
+            if (dd > dmax) dmax = dd;
+            if (fabs(phin[i]) > fmax) fmax = fabs(phin[i]);
+        }
+        for (long gc = 0; gc < nv; ++gc) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 8; ++k) { a += phin[gc * 8 + k]; b += phi[gc * 8 + k]; }
+            a /= 8.0; b /= 8.0;
+            esum += (a != 0.0) ? fabs(a - b) / fabs(a) : (b != 0.0 ? 1.0 : 0.0);
+        }
+        r = fmax > 0.0 ? dmax / fmax : 0.0;
+        es = esum / (double)nv;
+        memcpy(phi, phin, (size_t)nv * 8 * sizeof(double));
+        ++it;
+        if (r < tol) break;
+    }
+    free(S);
+    free(phin);
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (eps_s) *eps_s = es;
+    if (rc) return rc;
+    return (r < tol) ? ORC_OK : ORC_ENOTCONV;
+}
+
+int orc_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                       const double *omega, const double *weight, const double *sigma_t,
+                       const double *sigma_s, const double *q, const double psi_inc[6],
+                       double *phi, double tol, int max_iter, int *iters, double *resid,
+                       double *eps_s, double *psi_store, int nthreads)
+{
+    return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
+                          nthreads);
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint (exact discrete transpose)                                   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Inflow coupling of cell c' through its face f (omega.n_f < 0) to its upwind
+ * neighbour: b_c' += U psi_nb, U = |omega.n_f| Mf_f P_f, where
+ * (P_f psi_nb)[n] = psi_nb[n ^ bit(axis f)] for the face nodes n.  Built as an
+ * explicit 8x8 matrix so that its transpose can be applied literally.
+ */
+static void coupling_matrix(const double omega[3], int f, const double Mf[6][64], double U[64])
+{
+    const int axis = f / 2;
+    const double on = fabs(omega[axis]);
+    double P[64];
+    memset(P, 0, sizeof(P));
+    for (int n = 0; n < 8; ++n)
+        if (node_bit(n, axis) == (f & 1)) P[n * 8 + (n ^ (1 << axis))] = 1.0;
+    for (int k = 0; k < 8; ++k)
+        for (int j = 0; j < 8; ++j) {
+            double v = 0.0;
+            for (int l = 0; l < 8; ++l) v += Mf[f][k * 8 + l] * P[l * 8 + j];
+            U[k * 8 + j] = on * v;
+        }
+}
+
+/*
+ * Transposed sweep for one direction and group: solves A_c^T mu_c = rhs_c
+ * with rhs_c = load_c + sum over downwind neighbours c' of U_{c'}^T mu_{c'},
+ * visiting cells from downwind to upwind (the exact reverse of sweep_one).
+ * Homogeneous boundary condition.
+ */
+static int adjoint_sweep_one(const orc_mesh *m, const double omega[3], const double *sigma_t,
+                             const double *load, const double M[64], const double G[3][64],
+                             const double Mf[6][64], double *mu_dir)
+{
+    int c[3];
+    double U[6][64];
+    for (int f = 0; f < 6; ++f)
+        if (omega[f / 2] * face_sign(f) < 0.0) coupling_matrix(omega, f, Mf, U[f]);
+    /* reversed visit order: each axis runs from its downwind end */
+    const int d0 = -axis_step(omega[0]), e0 = omega[0] >= 0.0 ? m->n[0] - 1 : 0;
+    const int d1 = -axis_step(omega[1]), e1 = omega[1] >= 0.0 ? m->n[1] - 1 : 0;
+    const int d2 = -axis_step(omega[2]), e2 = omega[2] >= 0.0 ? m->n[2] - 1 : 0;
+    for (int kk = 0; kk < m->n[2]; ++kk) {
+        c[2] = e2 + d2 * kk;
+        for (int jj = 0; jj < m->n[1]; ++jj) {
+            c[1] = e1 + d1 * jj;
+            for (int ii = 0; ii < m->n[0]; ++ii) {
+                c[0] = e0 + d0 * ii;
+                const long ci = cell_index(m, c);
+                double A[64], At[64], rhs[8];
+                orc_cell_matrix(omega, sigma_t[ci], M, G, Mf, A);
+                for (int k = 0; k < 8; ++k)
+                    for (int j = 0; j < 8; ++j) At[k * 8 + j] = A[j * 8 + k];
+                for (int k = 0; k < 8; ++k) rhs[k] = load[8 * ci + k];
+                /* downwind neighbours: cells c' across the outflow faces of c;
+                   c is upwind of c' through the opposite face f' of c'. */
+                for (int f = 0; f < 6; ++f) {
+                    if (!(omega[f / 2] * face_sign(f) > 0.0)) continue;
+                    int nb[3];
+                    if (!neighbour(m, c, f, nb)) continue;
+                    const int fp = f ^ 1; /* face of c' shared with c */
+                    const double *mun = mu_dir + 8 * cell_index(m, nb);
+                    for (int j = 0; j < 8; ++j) {
+                        double v = 0.0;
+                        for (int k = 0; k < 8; ++k) v += U[fp][k * 8 + j] * mun[k];
+                        rhs[j] += v;
+                    }
+                }
+                int rc = orc_ge_solve(8, At, rhs, mu_dir + 8 * ci);
+                if (rc) return rc;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * Adjoint of the source-iteration fixed point for a response J(phi):
+ *   (L - K)^T lambda = W^T g,   lambda_d = w_d mu_d,
+ *   L_d^T mu_d = g + sigma_s/(4 pi) M phi_dag,  phi_dag = sum_d w_d mu_d,
+ * iterated (adjoint source iteration) until the max-norm relative change of
+ * phi_dag is below tol, then contracted with the stored forward psi:
+ *   dJ/dsigma_t[g][c] = - sum_d w_d mu_dc^T M psi_dc   (sigma_s held fixed)
+ *   dJ/dq[g][c]       =   sum_d w_d mu_dc^T M 1
+ *   dJ/dsigma_s[g][c] =   sum_d w_d mu_dc^T M phi_c / (4 pi)
+ * g = dJ/dphi [G][ncell][8]; psi [D][G][ncell][8] and phi [G][ncell][8] are the
+ * converged forward solution.  Direct partial derivatives of J are not added.
+ */
+int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                const double *omega, const double *weight, const double *sigma_t,
+                const double *sigma_s, const double *psi, const double *phi,
+                const double *gphi, double tol, int max_iter, double *grad_sigma_t,
+                double *grad_q, double *grad_sigma_s, double *phi_dag_out, int *iters,
+                int nthreads)
+{
+    orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
+    const long ncell = (long)nx * ny * nz;
+    const long nv = (long)ng * ncell;
+    double M[64], G[3][64], Mf[6][64];
+    orc_element_matrices(m.h, M, G, Mf);
+    set_threads(nthreads);
+    double *phid = (double *)calloc((size_t)nv * 8, sizeof(double));
+    double *phidn = (double *)malloc((size_t)nv * 8 * sizeof(double));
+    double *load = (double *)malloc((size_t)nv * 8 * sizeof(double));
+    double *mu = (double *)malloc((size_t)nd * nv * 8 * sizeof(double));
+    if (!phid || !phidn || !load || !mu) {
+        free(phid); free(phidn); free(load); free(mu);
+        return ORC_ENOMEM;
+    }
+    int it = 0, rc = ORC_OK;
+    double r = INFINITY;
+    while (it < max_iter) {
+        /* load = g + sigma_s/(4 pi) M phi_dag */
+        for (long gc = 0; gc < nv; ++gc)
+            for (int k = 0; k < 8; ++k) {
+                double v = 0.0;
+                for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * phid[gc * 8 + j];
+                load[gc * 8 + k] = gphi[gc * 8 + k] + sigma_s[gc] / (4.0 * ORC_PI) * v;
+            }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (long u = 0; u < (long)nd * ng; ++u) {
+            const int d = (int)(u / ng), g = (int)(u % ng);
+            int e = adjoint_sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, load + 8 * g * ncell,
+                                      M, G, Mf, mu + ((long)d * ng + g) * ncell * 8);
+            if (e) {
+#pragma omp critical
+                rc = e;
+            }
+        }
+        if (rc) break;
+        memset(phidn, 0, (size_t)nv * 8 * sizeof(double));
+        for (int d = 0; d < nd; ++d)
+            for (long i = 0; i < nv * 8; ++i) phidn[i] += weight[d] * mu[(long)d * nv * 8 + i];
+        double dmax = 0.0, fmax = 0.0;
+        for (long i = 0; i < nv * 8; ++i) {
+            if (fabs(phidn[i] - phid[i]) > dmax) dmax = fabs(phidn[i] - phid[i]);
+            if (fabs(phidn[i]) > fmax) fmax = fabs(phidn[i]);
+        }
+        memcpy(phid, phidn, (size_t)nv * 8 * sizeof(double));
+        ++it;
+        r = fmax > 0.0 ? dmax / fmax : 0.0;
+        if (r < tol) break;
+    }
+    if (!rc) {
+        /* the mu of the last sweep are consistent with the phi_dag used to build
+           its load; one more sweep with the converged phi_dag refines them */
+        for (long gc = 0; gc < nv; ++gc)
+            for (int k = 0; k < 8; ++k) {
+                double v = 0.0;
+                for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * phid[gc * 8 + j];
+                load[gc * 8 + k] = gphi[gc * 8 + k] + sigma_s[gc] / (4.0 * ORC_PI) * v;
+            }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (long u = 0; u < (long)nd * ng; ++u) {
+            const int d = (int)(u / ng), g = (int)(u % ng);
+            int e = adjoint_sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, load + 8 * g * ncell,
+                                      M, G, Mf, mu + ((long)d * ng + g) * ncell * 8);
+            if (e) {
+#pragma omp critical
+                rc = e;
+            }
+        }
+    }
+    if (!rc) {
+        for (long gc = 0; gc < nv; ++gc) {
+            double gs = 0.0, gq = 0.0, gss = 0.0;
+            for (int d = 0; d < nd; ++d) {
+                const double *md = mu + ((long)d * nv + gc) * 8;
+                const double *pd = psi + ((long)d * nv + gc) * 8;
+                for (int k = 0; k < 8; ++k)
+                    for (int j = 0; j < 8; ++j) {
+                        const double mk = weight[d] * md[k] * M[k * 8 + j];
+                        gs -= mk * pd[j];
+                        gq += mk;
+                        gss += mk * phi[gc * 8 + j] / (4.0 * ORC_PI);
+                    }
+            }
+            if (grad_sigma_t) grad_sigma_t[gc] = gs;
+            if (grad_q) grad_q[gc] = gq;
+            if (grad_sigma_s) grad_sigma_s[gc] = gss;
+        }
+        if (phi_dag_out) memcpy(phi_dag_out, phid, (size_t)nv * 8 * sizeof(double));
+    }
+    free(phid); free(phidn); free(load); free(mu);
+    if (iters) *iters = it;
+    if (rc) return rc;
+    return (r < tol) ? ORC_OK : ORC_ENOTCONV;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-cell particle balance                                            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * 1^T (A psi - b) for one cell system: by the partition of unity of the
+ * basis, this is outflow - inflow + sigma_t int psi - int S, which vanishes
+ * for the exact solution of the cell system.
+ */
+double orc_cell_balance(const double h[3], const double omega[3], double sigma_t,
+                        const double S[8], const double psi_up[6][8], const double psi[8])
+{
+    double M[64], G[3][64], Mf[6][64], A[64], b[8];
+    orc_element_matrices(h, M, G, Mf);
+    orc_cell_matrix(omega, sigma_t, M, G, Mf, A);
+    orc_cell_rhs(omega, M, Mf, S, psi_up, b);
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double v = -b[k];
+        for (int j = 0; j < 8; ++j) v += A[k * 8 + j] * psi[j];
+        s += v;
+    }
+    return s;
+}
+
+/* One-cell solve in physical orientation: assemble and GE. */
+int orc_cell_solve(const double h[3], const double omega[3], double sigma_t, const double S[8],
+                   const double psi_up[6][8], double psi[8])
+{
+    double M[64], G[3][64], Mf[6][64], A[64], b[8];
+    orc_element_matrices(h, M, G, Mf);
+    orc_cell_matrix(omega, sigma_t, M, G, Mf, A);
+    orc_cell_rhs(omega, M, Mf, S, psi_up, b);
+    return orc_ge_solve(8, A, b, psi);
+}
+
+/* Batched one-cell solves (training targets / local-solve parity). */
+int orc_cell_solve_batch(long n, const double *h, const double *omega, const double *sigma_t,
+                         const double *S, const double *psi_up, double *psi, int nthreads)
+{
+    set_threads(nthreads);
+    int err = ORC_OK;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        int rc = orc_cell_solve(h + 3 * i, omega + 3 * i, sigma_t[i], S + 8 * i,
+                                (const double(*)[8])(psi_up + 48 * i), psi + 8 * i);
+        if (rc) {
+#pragma omp critical
+            err = rc;
+        }
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------ */
+/* Shallow-ANN local solver (Sec. 3, Eq. (ANN:Eq1))                     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One hidden layer MLP, FP64 forward of the stored (float32) parameters:
+ *   hidden = act(W1 x + b1), y = W2 hidden + b2       (Eq. (ANN:Eq1))
+ * W1 is [nh][nin] row-major, W2 is [nout][nh].  act 0 = ReLU, 1 = tanh.
+ */
+struct orc_ann {
+    int nin, nh, nout, act;
+    const double *W1, *b1, *W2, *b2;
+};
+
+/*
+ * Input vector of the reduced one-cell problem (Sec. 3: the cell is fully
+ * determined by its inflow face values, direction, source nodes, sigma_t and
+ * shape).  The cell is first reflected so that every direction component is
+ * non-negative (canonical octant); canonical node n' is physical node
+ * n' ^ mask, mask bit a set when omega_a < 0.  With h = (dx dy dz)^(1/3):
+ *   x[0..2]   = |omega_a| h / dx_a          (streaming weights)
+ *   x[3]      = sigma_t h                   (optical size)
+ *   x[4..15]  = inflow face values / m: canonical x face (node order iy+2iz),
+ *               y face (ix+2iz), z face (ix+2iy)
+ *   x[16..23] = h S[n'] / m
+ *   m = max(max|psi_in|, max|h S| / (x[3] + max_a x[a]))
+ * The cell solution is linear in (psi_in, h S) at fixed (x[0..3]), so the net
+ * predicts psi/m and the result is rescaled by m; m = 0 gives psi = 0.
+ * Faces with omega_a = 0 carry no inflow and are fed as 0.
+ */
+int orc_ann_features(const double h[3], const double omega[3], double sigma_t, const double S[8],
+                     const double psi_up[6][8], double x[24], double *scale)
+{
+    int mask = 0;
+    for (int a = 0; a < 3; ++a)
+        if (omega[a] < 0.0) mask |= 1 << a;
+    const double hh = cbrt(h[0] * h[1] * h[2]);
+    double kmax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        x[a] = fabs(omega[a]) * hh / h[a];
+        if (x[a] > kmax) kmax = x[a];
+    }
+    x[3] = sigma_t * hh;
+    double pmax = 0.0, smax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const int f = 2 * a + ((mask >> a) & 1); /* physical inflow face */
+        const int t1 = (a + 1) % 3 < (a + 2) % 3 ? (a + 1) % 3 : (a + 2) % 3;
+        const int t2 = (a + 1) % 3 < (a + 2) % 3 ? (a + 2) % 3 : (a + 1) % 3;
+        for (int fn = 0; fn < 4; ++fn) {
+            const int np = ((fn & 1) << t1) | (((fn >> 1) & 1) << t2); /* canonical, bit a = 0 */
+            const double v = omega[a] != 0.0 ? psi_up[f][np ^ mask] : 0.0;
+            x[4 + 4 * a + fn] = v;
+            if (fabs(v) > pmax) pmax = fabs(v);
+        }
+    }
+    for (int np = 0; np < 8; ++np) {
+        x[16 + np] = hh * S[np ^ mask];
+        if (fabs(x[16 + np]) > smax) smax = fabs(x[16 + np]);
+    }
+    double m = pmax;
+    const double den = x[3] + kmax;
+    if (den > 0.0 && smax / den > m) m = smax / den;
+    if (m > 0.0)
+        for (int i = 4; i < 24; ++i) x[i] /= m;
+    *scale = m;
+    return mask;
+}
+
+void orc_ann_forward(int nin, int nh, int nout, int act, const double *W1, const double *b1,
+                     const double *W2, const double *b2, const double *x, double *y)
+{
+    double hid[1024];
+    for (int k = 0; k < nh; ++k) {
+        double v = b1[k];
+        for (int j = 0; j < nin; ++j) v += W1[k * nin + j] * x[j];
+        hid[k] = act == 1 ? tanh(v) : (v > 0.0 ? v : 0.0);
+    }
+    for (int t = 0; t < nout; ++t) {
+        double v = b2[t];
+        for (int k = 0; k < nh; ++k) v += W2[t * nh + k] * hid[k];
+        y[t] = v;
+    }
+}
+
+static int ann_cell(const orc_ann *net, const double h[3], const double omega[3], double sigma_t,
+                    const double S[8], const double psi_up[6][8], double psi[8])
+{
+    double x[24], y[8], m;
+    const int mask = orc_ann_features(h, omega, sigma_t, S, psi_up, x, &m);
+    if (m == 0.0) {
+        for (int n = 0; n < 8; ++n) psi[n] = 0.0;
+        return ORC_OK;
+    }
+    orc_ann_forward(net->nin, net->nh, net->nout, net->act, net->W1, net->b1, net->W2, net->b2, x,
+                    y);
+    for (int np = 0; np < 8; ++np) psi[np ^ mask] = m * y[np];
+    return ORC_OK;
+}
+
+/* Batched ANN one-cell solves in physical orientation. */
+int orc_ann_cell_batch(long n, const double *h, const double *omega, const double *sigma_t,
+                       const double *S, const double *psi_up, int nh, int act, const double *W1,
+                       const double *b1, const double *W2, const double *b2, double *psi)
+{
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    if (nh < 1 || nh > 1024) return ORC_EINVAL;
+    for (long i = 0; i < n; ++i)
+        ann_cell(&net, h + 3 * i, omega + 3 * i, sigma_t[i], S + 8 * i,
+                 (const double(*)[8])(psi_up + 48 * i), psi + 8 * i);
+    return ORC_OK;
+}
+
+/* Sweep / source iteration with the ANN replacing assembly + GE (Sec. 4 intro). */
+int orc_ann_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                  const double *omega, const double *weight, const double *sigma_t,
+                  const double *src, const double psi_inc[6], int nh, int act, const double *W1,
+                  const double *b1, const double *W2, const double *b2, double *phi,
+                  int nthreads)
+{
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    if (nh < 1 || nh > 1024) return ORC_EINVAL;
+    return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
+                     NULL, &net, nthreads);
+}
+
+int orc_ann_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                           int nd, const double *omega, const double *weight,
+                           const double *sigma_t, const double *sigma_s, const double *q,
+                           const double psi_inc[6], int nh, int act, const double *W1,
+                           const double *b1, const double *W2, const double *b2, double *phi,
+                           double tol, int max_iter, int *iters, double *resid, double *eps_s,
+                           int nthreads)
+{
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    if (nh < 1 || nh > 1024) return ORC_EINVAL;
+    return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads);
+}
