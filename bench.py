@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the DGFEM S_n sweep hot path on one MI355X.
+
+Workload (default): blocky_scatter -- unit cube, 64^3 hexahedra, S8 (80
+directions), 8 groups, 8x8x8 random material blocks (sigma_t lognormal
+clipped to [0.1, 50], scattering ratio U[0, 0.9]), q = 1, vacuum; FP32
+Gaussian-elimination local solver.  One step = one source iteration: source
+build, one full sweep (all hyperplanes, octants, directions, groups), octant
+reduction and the FP64 residual.  value = cell*direction*group solves per
+second over the timed steps.
+
+Also reported: the roofline of the dominant kernel (the hyperplane sweep
+kernel, HBM-bound by its algorithmic bytes s*(24*solves + 17*cells*groups)),
+timed with HIP events around every sweep launch, and the FP64 CPU oracle on a
+bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--groups", type=int, default=8)
+    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-groups", type=int, default=8,
+                    help="groups of the workload swept by the CPU oracle sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(groups, directions or KBA slabs would shard across GPUs; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1906_04017_amd import api, inputs
+
+    p = inputs.blocky_scatter(n=args.n, groups=args.groups, seed=2, order=args.order)
+    log(f"workload {p['name']}")
+    ctx = api.Context(0)
+    om, w = api.quadrature_ls(p["order"])
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.set_inflow(p["psi_inc"])
+    st = prob.stats()
+    solves = st["solves_per_sweep"]
+    phi = torch.zeros((p["groups"], prob.ncell, 8), dtype=torch.float32, device="cuda")
+
+    for i in range(args.warmup):
+        prob.si_step(phi)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    prob.set_timing(True)
+    kern_ms = 0.0
+    kern_launches = 0
+    resid = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        resid = prob.si_step(phi)
+        ms, nl = prob.kernel_time()
+        kern_ms += ms
+        kern_launches += nl
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.set_timing(False)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = solves * args.steps / wall
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, residual {resid:.3e}")
+
+    # roofline of the sweep kernel: algorithmic bytes of one sweep over the
+    # summed duration of that sweep's kernel launches
+    sweep_kernel_ms = kern_ms / args.steps
+    achieved = st["algo_bytes_per_sweep"] / (sweep_kernel_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "sweep_plane_ge<float>", "launches_per_sweep": kern_launches // args.steps,
+            "kernel_ms_per_sweep": round(sweep_kernel_ms, 4),
+            "avg_launch_us": round(1e3 * kern_ms / max(kern_launches, 1), 3),
+            "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, args.cpu_groups)
+
+    out = {
+        "metric": "cell*dir*group solves/s (FP32 GE sweep, one source iteration per step)",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": p["name"], "cells": prob.ncell, "directions": prob.n_dirs,
+                   "groups": p["groups"], "solver": "GE", "precision": "fp32",
+                   "solves_per_step": solves, "last_residual": resid},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, groups):
+    """FP64 oracle sweep of a bounded sample: the same mesh, quadrature and
+    materials restricted to the first `groups` groups, on all host cores."""
+    import oracle
+    ncell = p["sigma_t"].shape[1]
+    om, w = oracle.lq_n(p["order"])
+    cores = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    st = p["sigma_t"][:groups]
+    S = np.repeat(p["q"][:groups, :, None], 8, axis=-1)
+    mesh = (*p["n"], *p["length"])
+    log(f"cpu baseline: oracle sweep of {groups} group(s) on {cores} threads")
+    t0 = time.perf_counter()
+    oracle.sweep(mesh, om, w, st, S, p["psi_inc"], nthreads=cores)
+    dt = time.perf_counter() - t0
+    solves = ncell * len(w) * groups
+    return {"value": solves / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 sweep of {p['name']} restricted to {groups} group(s) "
+                      f"({solves} solves, {dt:.2f} s)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * dgsn.h -- C ABI of libdgsn, an MI355X (gfx950) implementation of the
+ * trilinear-hexahedron DGFEM S_n transport sweep with Gaussian-elimination
+ * and shallow-ANN local solvers (Tano & Ragusa, arXiv 1906.04017).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh: nx*ny*nz uniform hexahedra on [0,lx]x[0,ly]x[0,lz]; cell index
+ *   c = i + nx*(j + ny*k).
+ * Local node n = ix + 2*iy + 4*iz (ix,iy,iz in {0,1}) is the cell vertex at
+ *   (ix*dx, iy*dy, iz*dz) (trial space of Sec. 2, Eq. (T9), trilinear).
+ * Domain faces: 0 = x-, 1 = x+, 2 = y-, 3 = y+, 4 = z-, 5 = z+.
+ * Per-cell fields are [G][nz][ny][nx]; nodal fields are [G][nz][ny][nx][8]
+ *   (node fastest).  Device arrays are in the problem precision
+ *   (float for DGSN_FP32, double for DGSN_FP64) unless stated otherwise.
+ * Sources are per steradian: the total nodal source of a sweep is
+ *   S = q + sigma_s/(4 pi) * phi  (isotropic in-group scattering, the P0 term
+ *   of Eq. (T5)); phi = sum_d w_d psi_d (Eq. (T8)/(T11)) with sum_d w_d = 4 pi.
+ *
+ * Ownership: the caller owns every pointer it passes.  Device pointers must
+ * stay valid until the work enqueued on the given stream has completed.  The
+ * library owns everything behind its opaque handles and keeps no user pointer
+ * after a call returns.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Device work is enqueued asynchronously on it; calls that return host
+ * scalars (iteration counts, residuals, latencies) synchronize that stream.
+ * A problem handle must be used from one stream at a time.
+ *
+ * Errors: every call returns DGSN_OK (0) or a negative DGSN_E* code and sets a
+ * thread-local message readable with dgsn_last_error().  Arguments are
+ * validated on the host before any device work is enqueued.
+ */
+#ifndef DGSN_H
+#define DGSN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgsn_ctx dgsn_ctx;
+typedef struct dgsn_problem dgsn_problem;
+typedef struct dgsn_ann dgsn_ann;
+typedef struct dgsn_batch dgsn_batch;
+
+enum {
+    DGSN_OK = 0,
+    DGSN_EINVAL = -1,        /* invalid argument */
+    DGSN_ENOMEM = -2,        /* host or device allocation failed */
+    DGSN_EHIP = -3,          /* a HIP runtime call failed */
+    DGSN_ENOTCONV = -4,      /* iteration limit reached; outputs hold the last iterate */
+    DGSN_EFORMAT = -5,       /* malformed ANN artifact */
+    DGSN_EUNSUPPORTED = -6,  /* valid request outside what this build supports */
+    DGSN_ETIMEOUT = -7       /* a bounded device-side wait expired */
+};
+
+enum { DGSN_FP32 = 0, DGSN_FP64 = 1 };
+enum { DGSN_GE = 0, DGSN_ANN = 1 };
+
+/* Library version as major*10000 + minor*100 + patch. */
+int dgsn_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dgsn_last_error(void);
+
+/* Bind a HIP device.  out receives a context handle. */
+int dgsn_ctx_create(int hip_device, dgsn_ctx **out);
+int dgsn_ctx_destroy(dgsn_ctx *ctx);
+
+/*
+ * Level-symmetric LQ_N quadrature (the S_N discretisation of Sec. 2,
+ * Eq. (T7)-(T8); the paper does not name the family, LQ_N is the standard set
+ * of the transport text it cites).  Host only, no device needed.
+ * order: even, 2..12.  omega: host [n][3] out, weight: host [n] out with
+ * sum = 4 pi.  *n_inout: capacity on entry (>= order*(order+2)), count on
+ * exit.  Directions are octant-major (octant o = [Ox<0] + 2[Oy<0] + 4[Oz<0]).
+ * Passing omega = weight = NULL only returns the count.
+ */
+int dgsn_quadrature_ls(int order, double *omega, double *weight, int *n_inout);
+
+typedef struct {
+    int nx, ny, nz;          /* cells per axis, >= 1, <= 1024 */
+    double lx, ly, lz;       /* domain lengths, > 0 */
+    int n_groups;            /* independent groups (in-group scattering), >= 1 */
+    int n_dirs;              /* directions; every octant must hold n_dirs/8 */
+    const double *omega;     /* host [n_dirs][3], unit vectors (|1 - |O|| <= 1e-12) */
+    const double *weight;    /* host [n_dirs], > 0, sum 4 pi (+-1e-10) */
+    int precision;           /* DGSN_FP32 or DGSN_FP64 */
+    int solver;              /* DGSN_GE or DGSN_ANN (ANN: FP32 problems only) */
+    int store_psi;           /* keep the last sweep's angular flux (adjoint) */
+} dgsn_problem_desc;
+
+/* Host-side validation of a descriptor (no device work).  DGSN_OK or EINVAL. */
+int dgsn_problem_validate(const dgsn_problem_desc *desc);
+
+/*
+ * Create a problem on ctx: validates desc, allocates device buffers
+ * (materials, sources, scalar flux, per-octant partials, face fronts, the
+ * hyperplane schedule and the direction tables).  Materials default to zero,
+ * inflow to vacuum.
+ */
+int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *desc, dgsn_problem **out);
+int dgsn_problem_destroy(dgsn_problem *p);
+
+/*
+ * Copy materials (device arrays [G][nz][ny][nx], problem precision) into the
+ * problem: total cross section sigma_t >= 0, isotropic in-group scattering
+ * cross section sigma_s >= 0 (sigma_s may be NULL = 0), external source q per
+ * steradian (NULL = 0).  Enqueued on stream.  Table P1-P4 of Sec. 4 give the
+ * paper's values.
+ */
+int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void *sigma_s,
+                               const void *q, void *stream);
+
+/* Boundary inflow psi_inc per domain face (host [6]); applied to every
+   direction entering through that face (Eq. (TBC)); 0 = vacuum. */
+int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
+
+/* Attach an ANN (required before sweeping with solver = DGSN_ANN).  The
+   problem keeps a reference; the ANN must outlive its use by the problem. */
+int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
+
+/* Select the local solver of subsequent sweeps (DGSN_GE or DGSN_ANN). */
+int dgsn_problem_set_solver(dgsn_problem *p, int solver);
+
+/*
+ * One transport sweep (Sec. 2, the sweep paragraph after Eq. (T12)): for
+ * every direction and group solve the per-cell systems A psi_d = b of
+ * Eq. (T12) in dependency order, cells of one hyperplane in parallel, and
+ * return phi = sum_d w_d psi_d.
+ * src: device [G][nz][ny][nx][8] total nodal source per steradian.
+ * phi: device [G][nz][ny][nx][8] out.  src and phi must not overlap.
+ */
+int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream);
+
+/*
+ * Scattering source iteration (Sec. 2, the paragraph after Eq. (T6)):
+ * repeat S = q + sigma_s/(4 pi) phi, sweep, until the max-norm relative change
+ * max|phi_new - phi_old| / max|phi_new| (computed in FP64) is below tol.
+ * phi: device [G][nz][ny][nx][8]; initial guess on entry, last iterate on
+ * exit (a saved phi resumes an interrupted run).  max_iter >= 1.
+ * FP32 problems also stop when the residual has not decreased for 5
+ * iterations (the FP32 noise floor) and then return DGSN_ENOTCONV unless
+ * resid < tol.  iters, resid, eps_s (host out, may be NULL): iterations done,
+ * last residual, and the paper's mean pointwise criterion Eq. (Test:Eq3) on
+ * cell averages.  Synchronizes stream.
+ */
+int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
+                        double *resid, double *eps_s, void *stream);
+
+/*
+ * Gradient of a scalar response J(phi) through the converged source
+ * iteration by the discrete adjoint (not in the paper).  Requires the
+ * problem's last source_iterate to have run with store_psi = 1.
+ * dJ_dphi: device [G][nz][ny][nx][8].  grad_sigma_t, grad_q: device
+ * [G][nz][ny][nx] out (may be NULL): dJ/dsigma_t at fixed sigma_s and dJ/dq,
+ * without any direct partial derivative of J.  The adjoint iteration stops at
+ * relative change < tol or max_iter (DGSN_ENOTCONV).  iters may be NULL.
+ * Synchronizes stream.
+ */
+int dgsn_adjoint_solve(dgsn_problem *p, const void *dJ_dphi, void *grad_sigma_t, void *grad_q,
+                       double tol, int max_iter, int *iters, void *stream);
+
+/*
+ * Batched one-cell GE solves of the canonical cell system (Sec. 3: the cell
+ * problem is fixed by its streaming weights, optical size, inflow faces and
+ * source nodes).  x: device [n][24] = [|Ox| h/dx, |Oy| h/dy, |Oz| h/dz,
+ * sigma_t h, inflow x-face (4, node iy+2iz), y-face (4, ix+2iz), z-face (4,
+ * ix+2iy), h*S (8)] with h = (dx dy dz)^(1/3), all direction components taken
+ * non-negative.  psi: device [n][8] out.  precision selects float/double for
+ * both arrays.
+ */
+int dgsn_local_solve(dgsn_ctx *ctx, const void *x, void *psi, long long n, int precision,
+                     void *stream);
+
+/*
+ * Load a shallow-ANN artifact (Sec. 3, Eq. (ANN:Eq1): one hidden layer,
+ * 24 inputs as in dgsn_local_solve but homogeneity-normalised, 8 outputs).
+ * File format (little endian): "DGSNANN1" magic, u32 version=1, u32 n_in=24,
+ * u32 n_hidden (<= 256), u32 n_out=8, u32 activation (0 = ReLU), u32 flags,
+ * then float32 W1[n_hidden][n_in], b1[n_hidden], W2[n_out][n_hidden],
+ * b2[n_out], then u32 CRC-32 (IEEE) of everything before it.
+ * Returns DGSN_EFORMAT for a bad magic, shape, size or checksum.
+ */
+int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out);
+int dgsn_ann_destroy(dgsn_ann *ann);
+
+/*
+ * Raw network evaluation on the device with BF16 matrix cores and FP32
+ * accumulation: y = W2 relu(W1 x + b1) + b2.  x: device float [n][24],
+ * y: device float [n][8].
+ */
+int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream);
+
+/*
+ * Problem statistics (host out): solves per sweep (cells*dirs*groups),
+ * hyperplane count, and the algorithmic HBM bytes of one sweep
+ * (s*(24*solves + 17*cells*groups), s = sizeof(real)).
+ */
+int dgsn_problem_stats(const dgsn_problem *p, long long *solves_per_sweep, int *n_planes,
+                       double *algo_bytes_per_sweep);
+
+/*
+ * Kernel timing of the sweep (instrumentation).  With enable != 0 every
+ * sweep kernel launch of this problem is bracketed by HIP events on its
+ * stream.  dgsn_problem_kernel_time returns, for the most recent sweep, the
+ * sum of the kernel durations in milliseconds and the number of launches;
+ * it synchronizes the problem's last stream.
+ */
+int dgsn_problem_set_timing(dgsn_problem *p, int enable);
+int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
+
+/*
+ * Batched persistent execution of many independent problems (each FP32, any
+ * size, quadrature, group count and solver) in one launch, captured in a HIP
+ * graph.  probs must stay alive while the batch exists.
+ */
+int dgsn_batch_create(dgsn_ctx *ctx, dgsn_problem *const *probs, int n, dgsn_batch **out);
+/* One sweep of every problem; src/phi are taken from each problem's own
+   internal buffers (set with dgsn_batch_set_io). */
+int dgsn_batch_set_io(dgsn_batch *b, int index, const void *src, void *phi);
+int dgsn_batch_run(dgsn_batch *b, void *stream);
+/* Per-problem completion latency of the last run in microseconds, host [n]. */
+int dgsn_batch_latencies_us(const dgsn_batch *b, double *out);
+int dgsn_batch_destroy(dgsn_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGSN_H */

@@ -1,0 +1,271 @@
+"""Python binding of libdgsn: argument marshalling only.
+
+Every step of the transport path runs in the HIP library; torch tensors are
+used for device memory and the current HIP stream.  Array layouts follow
+include/dgsn.h: per-cell fields [G][nz][ny][nx], nodal fields
+[G][nz][ny][nx][8] (node n = ix + 2 iy + 4 iz fastest).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DgsnError, ProblemDesc  # noqa: F401
+
+FP32 = _lib.DGSN_FP32
+FP64 = _lib.DGSN_FP64
+GE = _lib.DGSN_GE
+ANN = _lib.DGSN_ANN
+
+_PREC = {"fp32": FP32, "fp64": FP64, FP32: FP32, FP64: FP64}
+_SOLVER = {"ge": GE, "ann": ANN, GE: GE, ANN: ANN}
+_DTYPE = {FP32: torch.float32, FP64: torch.float64}
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def version():
+    return _lib.load().dgsn_version()
+
+
+def quadrature_ls(order):
+    """Level-symmetric LQ_N set from the library: (omega [D,3], weight [D])."""
+    lib = _lib.load()
+    n = ctypes.c_int(0)
+    _lib.check(lib.dgsn_quadrature_ls(int(order), None, None, ctypes.byref(n)))
+    om = np.zeros((n.value, 3))
+    w = np.zeros(n.value)
+    _lib.check(lib.dgsn_quadrature_ls(int(order), om.ctypes.data_as(_lib._PD),
+                                      w.ctypes.data_as(_lib._PD), ctypes.byref(n)))
+    return om, w
+
+
+def _desc(n, length, groups, omega, weight, precision, solver, store_psi):
+    omega = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(-1, 3))
+    weight = np.ascontiguousarray(np.asarray(weight, np.float64).reshape(-1))
+    d = ProblemDesc(int(n[0]), int(n[1]), int(n[2]), float(length[0]), float(length[1]),
+                    float(length[2]), int(groups), int(omega.shape[0]),
+                    omega.ctypes.data_as(_lib._PD), weight.ctypes.data_as(_lib._PD),
+                    _PREC[precision], _SOLVER[solver], int(bool(store_psi)))
+    return d, (omega, weight)   # keep the arrays alive with the descriptor
+
+
+def validate(n, length, groups, omega, weight, precision="fp32", solver="ge", store_psi=False):
+    """Host-side descriptor validation (no device needed)."""
+    d, keep = _desc(n, length, groups, omega, weight, precision, solver, store_psi)
+    _lib.check(_lib.load().dgsn_problem_validate(ctypes.byref(d)))
+
+
+class Context:
+    def __init__(self, device=0):
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().dgsn_ctx_create(int(device), ctypes.byref(self._h)))
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if self._h:
+            _lib.load().dgsn_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ann:
+    """A loaded shallow-ANN artifact (device-resident operand images)."""
+
+    def __init__(self, ctx, path):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().dgsn_ann_load(ctx._h, str(path).encode(), ctypes.byref(self._h)))
+
+    def infer(self, x, out=None):
+        """y = W2 relu(W1 x + b1) + b2 on the BF16 matrix cores; x [n,24] float32."""
+        x = x.contiguous()
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 24:
+            raise ValueError("x must be a float32 [n, 24] tensor")
+        y = out if out is not None else torch.empty((x.shape[0], 8), dtype=torch.float32,
+                                                    device=x.device)
+        _lib.check(_lib.load().dgsn_ann_infer(self._h, _ptr(x), _ptr(y), x.shape[0],
+                                              _stream(x.device)))
+        return y
+
+    def close(self):
+        if self._h:
+            _lib.load().dgsn_ann_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def local_solve(ctx, x):
+    """Batched canonical one-cell GE; x [n,24] (float32 or float64) -> psi [n,8]."""
+    x = x.contiguous()
+    prec = FP64 if x.dtype == torch.float64 else FP32
+    if x.dtype not in (torch.float32, torch.float64) or x.dim() != 2 or x.shape[1] != 24:
+        raise ValueError("x must be a float32/float64 [n, 24] tensor")
+    y = torch.empty((x.shape[0], 8), dtype=x.dtype, device=x.device)
+    _lib.check(_lib.load().dgsn_local_solve(ctx._h, _ptr(x), _ptr(y), x.shape[0], prec,
+                                            _stream(x.device)))
+    return y
+
+
+class Problem:
+    """One DGFEM S_n problem on the GPU (uniform hex mesh, one quadrature)."""
+
+    def __init__(self, ctx, n, length, groups, omega, weight, precision="fp32", solver="ge",
+                 store_psi=False):
+        self.ctx = ctx
+        self.n = tuple(int(v) for v in n)
+        self.length = tuple(float(v) for v in length)
+        self.groups = int(groups)
+        self.precision = _PREC[precision]
+        self.dtype = _DTYPE[self.precision]
+        self.ncell = self.n[0] * self.n[1] * self.n[2]
+        d, keep = _desc(self.n, self.length, groups, omega, weight, precision, solver, store_psi)
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().dgsn_problem_create(ctx._h, ctypes.byref(d), ctypes.byref(self._h)))
+        self.n_dirs = int(d.n_dirs)
+        self._ann = None
+
+    # -- setup --------------------------------------------------------------
+    def _dev(self, a, shape):
+        if a is None:
+            return None
+        t = torch.as_tensor(a).to(device=self.ctx.device, dtype=self.dtype).contiguous()
+        return t.reshape(shape)
+
+    def set_materials(self, sigma_t, sigma_s=None, q=None):
+        shape = (self.groups, self.ncell)
+        st, ss, qq = self._dev(sigma_t, shape), self._dev(sigma_s, shape), self._dev(q, shape)
+        _lib.check(_lib.load().dgsn_problem_set_materials(self._h, _ptr(st), _ptr(ss), _ptr(qq),
+                                                          _stream(self.ctx.device)))
+        torch.cuda.current_stream(self.ctx.device).synchronize()
+
+    def set_inflow(self, psi_inc):
+        arr = np.ascontiguousarray(np.asarray(psi_inc, np.float64).reshape(6))
+        _lib.check(_lib.load().dgsn_problem_set_inflow(self._h, arr.ctypes.data_as(_lib._PD)))
+
+    def set_ann(self, ann):
+        self._ann = ann
+        _lib.check(_lib.load().dgsn_problem_set_ann(self._h, ann._h if ann else None))
+
+    def set_solver(self, solver):
+        _lib.check(_lib.load().dgsn_problem_set_solver(self._h, _SOLVER[solver]))
+
+    def stats(self):
+        s = ctypes.c_longlong(0)
+        p = ctypes.c_int(0)
+        b = ctypes.c_double(0)
+        _lib.check(_lib.load().dgsn_problem_stats(self._h, ctypes.byref(s), ctypes.byref(p),
+                                                  ctypes.byref(b)))
+        return dict(solves_per_sweep=s.value, n_planes=p.value, algo_bytes_per_sweep=b.value)
+
+    def set_timing(self, enable=True):
+        _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))
+
+    def kernel_time(self):
+        """(sum of sweep-kernel durations in ms, launches) of the last sweep."""
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int(0)
+        _lib.check(_lib.load().dgsn_problem_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    # -- solves -------------------------------------------------------------
+    def nodal_empty(self):
+        return torch.empty((self.groups, self.ncell, 8), dtype=self.dtype,
+                           device=self.ctx.device)
+
+    def sweep(self, src, phi=None):
+        """phi = sum_d w_d psi_d of one sweep with total nodal source src."""
+        src = self._dev(src, (self.groups, self.ncell, 8))
+        phi = phi if phi is not None else self.nodal_empty()
+        _lib.check(_lib.load().dgsn_sweep(self._h, _ptr(src), _ptr(phi), _stream(self.ctx.device)))
+        return phi
+
+    def source_iterate(self, phi0=None, tol=1e-8, max_iter=1000, allow_notconv=False):
+        phi = (self._dev(phi0, (self.groups, self.ncell, 8)).clone() if phi0 is not None
+               else torch.zeros((self.groups, self.ncell, 8), dtype=self.dtype,
+                                device=self.ctx.device))
+        it = ctypes.c_int(0)
+        r = ctypes.c_double(0)
+        es = ctypes.c_double(0)
+        rc = _lib.load().dgsn_source_iterate(self._h, _ptr(phi), float(tol), int(max_iter),
+                                             ctypes.byref(it), ctypes.byref(r), ctypes.byref(es),
+                                             _stream(self.ctx.device))
+        _lib.check(rc, allow=(_lib.DGSN_ENOTCONV,) if allow_notconv else ())
+        return phi, dict(iters=it.value, resid=r.value, eps_s=es.value,
+                         converged=(rc == _lib.DGSN_OK))
+
+    def si_step(self, phi):
+        """One source iteration in place on phi (source build, sweep, octant
+        reduction, FP64 residual); returns the residual."""
+        it = ctypes.c_int(0)
+        r = ctypes.c_double(0)
+        es = ctypes.c_double(0)
+        rc = _lib.load().dgsn_source_iterate(self._h, _ptr(phi), 0.0, 1, ctypes.byref(it),
+                                             ctypes.byref(r), ctypes.byref(es),
+                                             _stream(self.ctx.device))
+        _lib.check(rc, allow=(_lib.DGSN_ENOTCONV,))
+        return r.value
+
+    def adjoint(self, dj_dphi, tol=1e-8, max_iter=1000, allow_notconv=False):
+        g = self._dev(dj_dphi, (self.groups, self.ncell, 8))
+        gst = torch.empty((self.groups, self.ncell), dtype=self.dtype, device=self.ctx.device)
+        gq = torch.empty_like(gst)
+        it = ctypes.c_int(0)
+        rc = _lib.load().dgsn_adjoint_solve(self._h, _ptr(g), _ptr(gst), _ptr(gq), float(tol),
+                                            int(max_iter), ctypes.byref(it),
+                                            _stream(self.ctx.device))
+        _lib.check(rc, allow=(_lib.DGSN_ENOTCONV,) if allow_notconv else ())
+        return gst, gq, dict(iters=it.value, converged=(rc == _lib.DGSN_OK))
+
+    def close(self):
+        if self._h:
+            _lib.load().dgsn_problem_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TransportSolve(torch.autograd.Function):
+    """phi = SI-solution(sigma_t, q) with sigma_s held fixed; backward by the
+    library's adjoint sweep (reversed directions, transposed cell systems).
+
+    forward(problem, sigma_t [G,ncell], q [G,ncell], sigma_s [G,ncell], tol,
+    max_iter) -> phi [G,ncell,8].  The problem must be created with
+    store_psi=True.
+    """
+
+    @staticmethod
+    def forward(ctx, problem, sigma_t, q, sigma_s, tol, max_iter):
+        problem.set_materials(sigma_t.detach(), sigma_s.detach(), q.detach())
+        phi, info = problem.source_iterate(tol=tol, max_iter=max_iter, allow_notconv=True)
+        ctx.problem = problem
+        ctx.tol = tol
+        ctx.max_iter = max_iter
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        gst, gq, _ = ctx.problem.adjoint(grad_phi.contiguous(), tol=ctx.tol,
+                                         max_iter=ctx.max_iter, allow_notconv=True)
+        return None, gst, gq, None, None, None

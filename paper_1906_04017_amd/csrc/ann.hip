@@ -1,0 +1,434 @@
+// Shallow-ANN local solver (Sec. 3): one hidden layer, Eq. (ANN:Eq1) with a
+// ReLU hidden activation and a linear output layer, evaluated on the BF16
+// matrix cores with FP32 accumulation, and its use inside the sweep in place
+// of assembly + Gaussian elimination (Sec. 4, first paragraphs).
+//
+// Matrix-core mapping (v_mfma_f32_16x16x32_bf16, one wave = 64 samples in 4
+// batches of 16).  The layers are evaluated transposed so that no data moves
+// between them:
+//   H^T[64 x 16] = W1[64 x 32] X^T[32 x 16]   (4 tiles of 16 hidden units)
+//   Y^T[16 x 16] = W2p[16 x 64] relu(H^T)     (2 K-chunks of 32)
+// The B operand of layer 1 is the sample's 24 features padded to 32: lane l
+// holds 8 features (index 8 (l/16) + e) of sample l % 16.  Layer 1 returns in
+// lane l the hidden units 16 m + 4 (l/16) + r of sample l % 16; after bias
+// (accumulator initialised with b1), ReLU and BF16 rounding these 16 values
+// are exactly the lane's B operand of layer 2 if the columns of W2 are
+// permuted accordingly on the host (W2p).  The contraction order inside one
+// MFMA is irrelevant because A and B use the same lane/element pairing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "cell.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dgsn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kParamW1 = 0;                  // [4][64] bf16x8
+constexpr int kParamW2 = 4 * 64 * 16;        // [2][64] bf16x8
+constexpr int kParamB1 = kParamW2 + 2 * 64 * 16;  // [4][64] f32x4
+constexpr int kParamB2 = kParamB1 + 4 * 64 * 16;  // [64] f32x4
+constexpr int kParamBytes = kParamB2 + 64 * 16;
+constexpr int kHiddenPad = 64;
+
+struct AnnRegs {
+    bf16x8 w1[4];
+    bf16x8 w2[2];
+    f32x4 b1[4];
+    f32x4 b2;
+};
+
+__device__ __forceinline__ void ann_load(const unsigned char *__restrict__ prm, int lane,
+                                         AnnRegs &R)
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        R.w1[m] = *reinterpret_cast<const bf16x8 *>(prm + kParamW1 + (m * 64 + lane) * 16);
+        R.b1[m] = *reinterpret_cast<const f32x4 *>(prm + kParamB1 + (m * 64 + lane) * 16);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        R.w2[c] = *reinterpret_cast<const bf16x8 *>(prm + kParamW2 + (c * 64 + lane) * 16);
+    R.b2 = *reinterpret_cast<const f32x4 *>(prm + kParamB2 + lane * 16);
+}
+
+// Evaluates the network for the 64 samples held by the 64 lanes of the wave
+// (one sample per lane, 24 FP32 features).  lds_in: 64*32 bf16 of this wave,
+// lds_out: 64*8 floats of this wave.  Must be reached by every thread of the
+// block (it synchronises the block).
+__device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
+                                         __bf16 *lds_in, float *lds_out, float out[8])
+{
+    const int lane = threadIdx.x & 63;
+    {
+        bf16x8 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int f = 8 * q + e;
+                v[q][e] = (__bf16)(f < 24 ? feat[f] : 0.0f);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(lds_in + lane * 32 + 8 * q) = v[q];
+    }
+    __syncthreads();
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(lds_in + (16 * b + col) * 32 + 8 * grp);
+        f32x4 h[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            h[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w1[m], xb, R.b1[m], 0, 0, 0);
+        bf16x8 hb[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = h[2 * c + (e >> 2)][e & 3];
+                hb[c][e] = (__bf16)(v > 0.0f ? v : 0.0f);
+            }
+        f32x4 y = R.b2;
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[0], hb[0], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[1], hb[1], y, 0, 0, 0);
+        if (grp < 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds_out[(16 * b + col) * 8 + 4 * grp + r] = y[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = lds_out[lane * 8 + k];
+}
+
+__global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__restrict__ prm,
+                                                        const float *__restrict__ x,
+                                                        float *__restrict__ y, long long n)
+{
+    __shared__ __bf16 lin[4][64 * 32];
+    __shared__ float lout[4][64 * 8];
+    AnnRegs R;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    ann_load(prm, lane, R);
+    const long long nblk = (n + 255) / 256;
+    for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long long s = blk * 256 + threadIdx.x;
+        float f[24], o[8];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) f[k] = s < n ? x[s * 24 + k] : 0.0f;
+        ann_wave(R, f, lin[wv], lout[wv], o);
+        if (s < n) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
+        }
+        __syncthreads();
+    }
+}
+
+// Hyperplane step with the ANN local solver.  Same lane mapping, fronts and
+// reduction as the GE kernel; blocks are 256 threads of which the first
+// Do * floor(256 / Do) carry work (full waves are required by the matrix
+// cores).  Features of one cell (canonical orientation, h = V^(1/3)):
+//   [kappa_a h (3), sigma_t h, inflow x/y/z faces (12) / m, h S (8) / m],
+//   m = max(max|psi_in|, max|h S| / (sigma_t h + max_a kappa_a h)),
+// and psi = m * y (m = 0 gives psi = 0): the cell solution is linear in the
+// inflow and source, so the network only sees unit-scale inputs.
+__global__ __launch_bounds__(256) void sweep_plane_ann(PlaneArgs<float> A, int work_lanes)
+{
+    __shared__ float red[8][256];
+    __shared__ __bf16 lin[4][64 * 32];
+    __shared__ float lout[4][64 * 8];
+    const int tid = threadIdx.x;
+    AnnRegs R;
+    ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
+    const bool in_block = tid < work_lanes;
+    const long long lin_idx = (long long)blockIdx.x * work_lanes + tid;
+    const long long seg = lin_idx / A.Do;
+    const int d = (int)(lin_idx - seg * A.Do);
+    const int g = (int)(seg % A.G);
+    const long long t = seg / A.G;
+    const int o = (int)(t / A.ncp);
+    const int ci = (int)(t - (long long)o * A.ncp);
+    const bool valid = in_block && o < 8;
+
+    float feat[24];
+    float mscale = 0.0f, w = 0.0f;
+    int mask = 0, ic = 0, jc = 0, kc = 0, dg = 0;
+    long long c = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) feat[k] = 0.0f;
+    if (valid) {
+        const uint32_t pc = A.cells[ci];
+        ic = pc & 1023;
+        jc = (pc >> 10) & 1023;
+        kc = pc >> 20;
+        mask = o;
+        const int i = (mask & 1) ? A.nx - 1 - ic : ic;
+        const int j = (mask & 2) ? A.ny - 1 - jc : jc;
+        const int k = (mask & 4) ? A.nz - 1 - kc : kc;
+        c = (long long)i + (long long)A.nx * ((long long)j + (long long)A.ny * k);
+        dg = d + A.Do * g;
+        const long long gc = (long long)g * A.ncell + c;
+        const float *dp = A.dir + (long long)(o * A.Do + d) * kDirStride;
+        float kh[3];
+        float kmax = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            kh[a] = dp[64 + a] * (36.0f * A.hh);
+            feat[a] = kh[a];
+            kmax = fmaxf(kmax, kh[a]);
+        }
+        w = dp[67];
+        const float tau = A.sigma_t[gc] * A.hh;
+        feat[3] = tau;
+        const long long DG = A.DG;
+        const long long ix_x = (((long long)o * A.nz + kc) * A.ny + jc) * 4 * DG + dg;
+        const long long ix_y = (((long long)o * A.nz + kc) * A.nx + ic) * 4 * DG + dg;
+        const long long ix_z = (((long long)o * A.ny + jc) * A.nx + ic) * 4 * DG + dg;
+        float pmax = 0.0f, smax = 0.0f;
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) {
+            float vx = ic ? A.fx[ix_x + fn * DG] : A.inc[o][0];
+            float vy = jc ? A.fy[ix_y + fn * DG] : A.inc[o][1];
+            float vz = kc ? A.fz[ix_z + fn * DG] : A.inc[o][2];
+            vx = kh[0] != 0.0f ? vx : 0.0f;
+            vy = kh[1] != 0.0f ? vy : 0.0f;
+            vz = kh[2] != 0.0f ? vz : 0.0f;
+            feat[4 + fn] = vx;
+            feat[8 + fn] = vy;
+            feat[12 + fn] = vz;
+            pmax = fmaxf(pmax, fmaxf(fabsf(vx), fmaxf(fabsf(vy), fabsf(vz))));
+        }
+        const float *sp = A.src + gc * 8;
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const float hs = A.hh * sp[n ^ mask];
+            feat[16 + n] = hs;
+            smax = fmaxf(smax, fabsf(hs));
+        }
+        float m = pmax;
+        const float den = tau + kmax;
+        if (den > 0.0f) m = fmaxf(m, smax / den);
+        mscale = m;
+        const float rm = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+        for (int k = 4; k < 24; ++k) feat[k] *= rm;
+    }
+    float y[8], psi[8];
+    ann_wave(R, feat, lin[tid >> 6], lout[tid >> 6], y);
+#pragma unroll
+    for (int n = 0; n < 8; ++n) psi[n] = valid ? mscale * y[n] : 0.0f;
+    if (valid) {
+        const long long DG = A.DG;
+        const long long ix_x = (((long long)o * A.nz + kc) * A.ny + jc) * 4 * DG + dg;
+        const long long ix_y = (((long long)o * A.nz + kc) * A.nx + ic) * 4 * DG + dg;
+        const long long ix_z = (((long long)o * A.ny + jc) * A.nx + ic) * 4 * DG + dg;
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) {
+            A.fx[ix_x + fn * DG] = psi[1 + 2 * fn];
+            A.fy[ix_y + fn * DG] = psi[(fn & 1) + 2 + 4 * (fn >> 1)];
+            A.fz[ix_z + fn * DG] = psi[4 + fn];
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n) red[n][tid] = w * psi[n];
+    __syncthreads();
+    if (valid) {
+        const int base = tid - d;
+        for (int n = d; n < 8; n += A.Do) {
+            float s = 0.0f;
+            for (int e = 0; e < A.Do; ++e) s += red[n][base + e];
+            A.phi_oct[(((long long)o * A.G + g) * A.ncell + c) * 8 + (n ^ mask)] = s;
+        }
+    }
+}
+
+// ---- artifact I/O ----------------------------------------------------------
+
+uint32_t crc32_ieee(const unsigned char *p, size_t n)
+{
+    uint32_t c = 0xFFFFFFFFu;
+    for (size_t i = 0; i < n; ++i) {
+        c ^= p[i];
+        for (int k = 0; k < 8; ++k) c = (c >> 1) ^ (0xEDB88320u & (0u - (c & 1u)));
+    }
+    return c ^ 0xFFFFFFFFu;
+}
+
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));
+    const uint32_t round = 0x7FFFu + ((u >> 16) & 1u);   // nearest, ties to even
+    return (uint16_t)((u + round) >> 16);
+}
+
+int build_params(dgsn_ann *a)
+{
+    std::vector<unsigned char> buf(kParamBytes, 0);
+    auto put_bf16 = [&](size_t off, float v) {
+        const uint16_t b = bf16_bits(v);
+        std::memcpy(&buf[off], &b, 2);
+    };
+    auto put_f32 = [&](size_t off, float v) { std::memcpy(&buf[off], &v, 4); };
+    const int H = a->n_hidden, NI = a->n_in, NO = a->n_out;
+    for (int lane = 0; lane < 64; ++lane) {
+        const int col = lane & 15, grp = lane >> 4;
+        for (int m = 0; m < 4; ++m) {
+            const int hid = 16 * m + col;
+            for (int e = 0; e < 8; ++e) {
+                const int f = 8 * grp + e;
+                const float v = (hid < H && f < NI) ? a->W1[hid * NI + f] : 0.0f;
+                put_bf16(kParamW1 + (m * 64 + lane) * 16 + 2 * e, v);
+            }
+            for (int r = 0; r < 4; ++r) {
+                const int hid2 = 16 * m + 4 * grp + r;
+                put_f32(kParamB1 + (m * 64 + lane) * 16 + 4 * r, hid2 < H ? a->b1[hid2] : 0.0f);
+            }
+        }
+        for (int c = 0; c < 2; ++c)
+            for (int e = 0; e < 8; ++e) {
+                const int out = col;
+                const int hid = 16 * (2 * c + (e >> 2)) + 4 * grp + (e & 3);
+                const float v = (out < NO && hid < H) ? a->W2[out * H + hid] : 0.0f;
+                put_bf16(kParamW2 + (c * 64 + lane) * 16 + 2 * e, v);
+            }
+        for (int r = 0; r < 4; ++r) {
+            const int out = 4 * grp + r;
+            put_f32(kParamB2 + lane * 16 + 4 * r, out < NO ? a->b2[out] : 0.0f);
+        }
+    }
+    DGSN_TRY(a->d_params.alloc(buf.size()));
+    DGSN_HIP(hipMemcpy(a->d_params.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    return DGSN_OK;
+}
+
+}  // namespace
+
+int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s)
+{
+    const int work = block_size_for(A.Do);
+    const long long total = 8LL * A.ncp * A.G * A.Do;
+    const long long grid = (total + work - 1) / work;
+    if (grid > 0x7fffffffLL) return set_error(DGSN_EUNSUPPORTED, "hyperplane too large");
+    hipLaunchKernelGGL(sweep_plane_ann, dim3((unsigned)grid), dim3(256), 0, s, A, work);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+const void *ann_device_params(const dgsn_ann *a) { return a ? a->d_params.ptr : nullptr; }
+
+}  // namespace dgsn
+
+using namespace dgsn;
+
+extern "C" {
+
+int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
+{
+    clear_error();
+    if (!path || !out) return set_error(DGSN_EINVAL, "path and out must be set");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_error(DGSN_EINVAL, "cannot open ANN artifact %s", path);
+    std::vector<unsigned char> data;
+    unsigned char chunk[4096];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) {
+        data.insert(data.end(), chunk, chunk + got);
+        if (data.size() > (1u << 24)) break;
+    }
+    std::fclose(f);
+    const size_t hdr = 8 + 6 * 4;
+    if (data.size() < hdr + 4 || std::memcmp(data.data(), "DGSNANN1", 8) != 0)
+        return set_error(DGSN_EFORMAT, "%s: not a DGSNANN1 artifact", path);
+    uint32_t v[6];
+    std::memcpy(v, data.data() + 8, sizeof(v));
+    const uint32_t version = v[0], n_in = v[1], n_hidden = v[2], n_out = v[3], act = v[4];
+    if (version != 1 || n_in != 24 || n_out != 8 || n_hidden < 1 || n_hidden > kMaxHidden)
+        return set_error(DGSN_EFORMAT, "%s: unsupported shape (version %u, %u-%u-%u)", path,
+                         version, n_in, n_hidden, n_out);
+    const size_t nparam = (size_t)n_hidden * n_in + n_hidden + (size_t)n_out * n_hidden + n_out;
+    if (data.size() != hdr + 4 * nparam + 4)
+        return set_error(DGSN_EFORMAT, "%s: size %zu does not match the header", path,
+                         data.size());
+    uint32_t crc;
+    std::memcpy(&crc, data.data() + data.size() - 4, 4);
+    if (crc != crc32_ieee(data.data(), data.size() - 4))
+        return set_error(DGSN_EFORMAT, "%s: checksum mismatch", path);
+    if (act != 0)
+        return set_error(DGSN_EUNSUPPORTED, "%s: only ReLU hidden layers run on the matrix cores",
+                         path);
+    if (n_hidden > kHiddenPad)
+        return set_error(DGSN_EUNSUPPORTED, "%s: at most %d hidden units are supported", path,
+                         kHiddenPad);
+    {
+        const float *pw = reinterpret_cast<const float *>(data.data() + hdr);
+        for (size_t i = 0; i < nparam; ++i)
+            if (!std::isfinite(pw[i]))
+                return set_error(DGSN_EFORMAT, "%s: non-finite parameter %zu", path, i);
+    }
+    // the file is fully checked before a device is needed
+    if (!ctx) return set_error(DGSN_EINVAL, "ctx is NULL");
+    dgsn_ann *a = new (std::nothrow) dgsn_ann();
+    if (!a) return set_error(DGSN_ENOMEM, "host allocation failed");
+    a->ctx = ctx;
+    a->n_in = (int)n_in;
+    a->n_hidden = (int)n_hidden;
+    a->n_out = (int)n_out;
+    a->act = (int)act;
+    const float *pf = reinterpret_cast<const float *>(data.data() + hdr);
+    a->W1.assign(pf, pf + (size_t)n_hidden * n_in);
+    pf += (size_t)n_hidden * n_in;
+    a->b1.assign(pf, pf + n_hidden);
+    pf += n_hidden;
+    a->W2.assign(pf, pf + (size_t)n_out * n_hidden);
+    pf += (size_t)n_out * n_hidden;
+    a->b2.assign(pf, pf + n_out);
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        delete a;
+        return set_error(DGSN_EHIP, "hipSetDevice failed");
+    }
+    int rc = build_params(a);
+    if (rc) {
+        delete a;
+        return rc;
+    }
+    *out = a;
+    return DGSN_OK;
+}
+
+int dgsn_ann_destroy(dgsn_ann *ann)
+{
+    clear_error();
+    delete ann;
+    return DGSN_OK;
+}
+
+int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream)
+{
+    clear_error();
+    if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
+    if (n < 0) return set_error(DGSN_EINVAL, "n must be >= 0");
+    if (n == 0) return DGSN_OK;
+    if (!x || !y) return set_error(DGSN_EINVAL, "x and y must be set");
+    DGSN_HIP(hipSetDevice(ann->ctx->device));
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(ann_infer_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream),
+                       static_cast<const unsigned char *>(ann->d_params.ptr), x, y, n);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+}  // extern "C"

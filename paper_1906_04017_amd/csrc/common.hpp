@@ -1,0 +1,104 @@
+// Internal declarations of libdgsn (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dgsn.h"
+
+namespace dgsn {
+
+// ---- error reporting -------------------------------------------------------
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define DGSN_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::dgsn::set_error(DGSN_EHIP, "%s failed: %s (%s:%d)", #call,          \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);         \
+    } while (0)
+
+#define DGSN_TRY(expr)              \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_ != DGSN_OK) return rc_; \
+    } while (0)
+
+// ---- constants -------------------------------------------------------------
+constexpr int kMaxCellsPerAxis = 1024;   // packed (i, j, k) in 10 bits each
+constexpr int kDirStride = 68;           // per direction: S_d[64], kappa[3], weight
+constexpr int kMaxHidden = 256;
+
+// ---- host-side quadrature ---------------------------------------------------
+int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
+
+const void *ann_device_params(const dgsn_ann *a);
+
+// ---- device allocation helper ------------------------------------------------
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int alloc(size_t n);
+    void release();
+    ~DevBuf() { release(); }
+};
+
+}  // namespace dgsn
+
+struct dgsn_ctx {
+    int device = 0;
+    int num_cu = 0;
+    dgsn::DevBuf scratch;   // small reduction scratch shared by local solves
+};
+
+struct dgsn_ann {
+    dgsn_ctx *ctx = nullptr;
+    int n_in = 24, n_hidden = 0, n_out = 8, act = 0;
+    std::vector<float> W1, b1, W2, b2;   // host copies (fp32)
+    // device: bf16 packed operand images and fp32 biases (layout in ann.hip)
+    dgsn::DevBuf d_params;
+};
+
+struct dgsn_problem {
+    dgsn_ctx *ctx = nullptr;
+    int n[3] = {0, 0, 0};
+    double len[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    long long ncell = 0;
+    int G = 0, D = 0, Do = 0;
+    int precision = DGSN_FP32;
+    int solver = DGSN_GE;
+    int store_psi = 0;
+    int n_planes = 0;
+    size_t real_size = 4;
+    double psi_inc[6] = {0, 0, 0, 0, 0, 0};
+    const dgsn_ann *ann = nullptr;
+
+    std::vector<int> dir_user;       // octant-sorted slot -> user direction index
+    std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64
+    std::vector<int> plane_off;      // [n_planes + 1]
+
+    dgsn::DevBuf d_dir;              // [8][Do][kDirStride] real
+    dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major
+    dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
+    dgsn::DevBuf src;                         // [G][ncell][8]
+    dgsn::DevBuf phi_oct;                     // [8][G][ncell][8]
+    dgsn::DevBuf front_x, front_y, front_z;   // [8][..][..][4][Do*G]
+    dgsn::DevBuf psi;                         // [D][G][ncell][8] (store_psi)
+    dgsn::DevBuf adj_phi, adj_src, grad_oct;  // adjoint work buffers
+    dgsn::DevBuf red_partials;                // FP64 reduction partials
+    dgsn::DevBuf red_result;                  // FP64 [4]
+    int red_blocks = 0;
+
+    // optional per-launch kernel timing of the last sweep
+    int timing = 0;
+    std::vector<hipEvent_t> ev;               // [2 * n_planes]
+    int ev_used = 0;
+    hipStream_t last_stream = nullptr;
+    ~dgsn_problem();
+};

@@ -1,0 +1,64 @@
+// Kernel argument blocks and launch wrappers shared by the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgsn {
+
+__device__ __forceinline__ double fmax_d(double a, double b) { return a > b ? a : b; }
+
+// One hyperplane step of a sweep (all octants, directions, groups).
+template <typename Real>
+struct PlaneArgs {
+    const uint32_t *cells;     // packed canonical cells of the plane (i | j<<10 | k<<20)
+    int ncp;                   // number of cells in the plane
+    int nx, ny, nz;
+    int G, Do, DG;
+    long long ncell;
+    const Real *dir;           // [8][Do][kDirStride]
+    const Real *sigma_t;       // [G][ncell]
+    const Real *src;           // [G][ncell][8]
+    Real *fx, *fy, *fz;        // face fronts
+    Real *phi_oct;             // [8][G][ncell][8]
+    Real *psi;                 // [8*Do][G][ncell][8] (store or adjoint contraction)
+    Real *grad_oct;            // [8][G][ncell][2] adjoint contraction output (or null)
+    Real vol;                  // cell volume
+    Real hh;                   // cube root of the cell volume (ANN features)
+    const void *ann_params;    // device ANN operand images (ANN solver)
+    Real inc[8][3];            // inflow value per octant slot and canonical axis
+};
+
+template <typename Real>
+struct ReduceArgs {
+    const Real *phi_oct;       // [8][nv][8]
+    Real *phi;                 // [nv][8] in: previous iterate (if resid), out: new
+    long long nv;              // G * ncell
+    int resid;                 // compute residual partials
+    double *partials;          // [blocks][3]
+    double *result;            // [3]: max|dphi|, max|phi|, sum eps_s terms
+    Real *src_next;            // next source (or null)
+    const Real *q_cell;        // [nv] per-cell source (or null)
+    const Real *q_nodal;       // [nv][8] nodal source (or null)
+    const Real *sigma_s;       // [nv] (or null)
+};
+
+int block_size_for(int Do);
+int reduce_blocks_for(long long nv);
+
+template <typename Real>
+int launch_plane(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, hipStream_t s);
+int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s);
+
+template <typename Real>
+int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);
+template <typename Real>
+int launch_build_source(long long nv, const Real *q, const Real *ss, const Real *phi, Real *src,
+                        hipStream_t s);
+template <typename Real>
+int launch_adjoint_load(long long nv, const Real *gphi, double vol, Real *gl, hipStream_t s);
+template <typename Real>
+int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, hipStream_t s);
+
+}  // namespace dgsn

@@ -1,0 +1,631 @@
+// Host runtime and C ABI of libdgsn: contexts, problem objects, validation,
+// the hyperplane schedule, the source-iteration driver and the adjoint driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "cell.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dgsn {
+
+namespace {
+thread_local char g_msg[1024] = "";
+}
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_msg[0] = '\0'; }
+
+int DevBuf::alloc(size_t n)
+{
+    release();
+    if (n == 0) return DGSN_OK;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return set_error(DGSN_ENOMEM, "hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+    }
+    bytes = n;
+    return DGSN_OK;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+}  // namespace dgsn
+
+using namespace dgsn;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// 1D factors of the canonical cell system (see cell.hpp).
+double m1(int k, int j) { return k == j ? 1.0 / 3.0 : 1.0 / 6.0; }
+double t1(int k, int j) { return (k == 1 && j == 0) ? -0.5 : 0.5; }
+
+// S_d[k][j] = sum_a kappa_a T_a[k][j], T_a = T on axis a, M1 on the others.
+void streaming_matrix(const double kappa[3], double S[64])
+{
+    for (int k = 0; k < 8; ++k)
+        for (int j = 0; j < 8; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double v = kappa[a];
+                for (int b = 0; b < 3; ++b) {
+                    const int kb = (k >> b) & 1, jb = (j >> b) & 1;
+                    v *= (b == a) ? t1(kb, jb) : m1(kb, jb);
+                }
+                s += v;
+            }
+            S[k * 8 + j] = s;
+        }
+}
+
+int validate_desc(const dgsn_problem_desc *d)
+{
+    if (!d) return set_error(DGSN_EINVAL, "descriptor is NULL");
+    const int n[3] = {d->nx, d->ny, d->nz};
+    const double L[3] = {d->lx, d->ly, d->lz};
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1 || n[a] > kMaxCellsPerAxis)
+            return set_error(DGSN_EINVAL, "cells per axis must be in 1..%d (axis %d: %d)",
+                             kMaxCellsPerAxis, a, n[a]);
+        if (!(L[a] > 0.0) || !std::isfinite(L[a]))
+            return set_error(DGSN_EINVAL, "domain length must be finite and > 0 (axis %d)", a);
+    }
+    if (d->n_groups < 1) return set_error(DGSN_EINVAL, "n_groups must be >= 1");
+    if (d->n_dirs < 8 || d->n_dirs % 8)
+        return set_error(DGSN_EINVAL, "n_dirs must be a positive multiple of 8 (got %d)",
+                         d->n_dirs);
+    if (!d->omega || !d->weight) return set_error(DGSN_EINVAL, "omega/weight must not be NULL");
+    if (d->precision != DGSN_FP32 && d->precision != DGSN_FP64)
+        return set_error(DGSN_EINVAL, "precision must be DGSN_FP32 or DGSN_FP64");
+    if (d->solver != DGSN_GE && d->solver != DGSN_ANN)
+        return set_error(DGSN_EINVAL, "solver must be DGSN_GE or DGSN_ANN");
+    if (d->solver == DGSN_ANN && d->precision != DGSN_FP32)
+        return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    int count[8] = {0};
+    double wsum = 0.0;
+    for (int i = 0; i < d->n_dirs; ++i) {
+        const double *o = d->omega + 3 * i;
+        const double nrm = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+        if (!std::isfinite(nrm) || std::fabs(nrm - 1.0) > 1e-12)
+            return set_error(DGSN_EINVAL, "direction %d is not a unit vector (|O| = %.17g)", i,
+                             nrm);
+        const double w = d->weight[i];
+        if (!(w > 0.0) || !std::isfinite(w))
+            return set_error(DGSN_EINVAL, "weight %d must be finite and > 0", i);
+        wsum += w;
+        count[(o[0] < 0) + 2 * (o[1] < 0) + 4 * (o[2] < 0)]++;
+    }
+    if (std::fabs(wsum - 4.0 * M_PI) > 1e-10)
+        return set_error(DGSN_EINVAL, "weights must sum to 4 pi (sum = %.17g)", wsum);
+    for (int o = 0; o < 8; ++o)
+        if (count[o] != d->n_dirs / 8)
+            return set_error(DGSN_EINVAL, "octant %d holds %d directions, expected %d", o,
+                             count[o], d->n_dirs / 8);
+    return DGSN_OK;
+}
+
+template <typename Real>
+int upload_real(DevBuf &buf, const std::vector<double> &host)
+{
+    std::vector<Real> tmp(host.begin(), host.end());
+    DGSN_TRY(buf.alloc(tmp.size() * sizeof(Real)));
+    DGSN_HIP(hipMemcpy(buf.ptr, tmp.data(), tmp.size() * sizeof(Real), hipMemcpyHostToDevice));
+    return DGSN_OK;
+}
+
+template <typename Real>
+PlaneArgs<Real> plane_args(dgsn_problem *p, const void *src, bool adjoint)
+{
+    PlaneArgs<Real> A{};
+    A.nx = p->n[0];
+    A.ny = p->n[1];
+    A.nz = p->n[2];
+    A.G = p->G;
+    A.Do = p->Do;
+    A.DG = p->Do * p->G;
+    A.ncell = p->ncell;
+    A.dir = static_cast<const Real *>(p->d_dir.ptr);
+    A.sigma_t = static_cast<const Real *>(p->sigma_t.ptr);
+    A.src = static_cast<const Real *>(src);
+    A.fx = static_cast<Real *>(p->front_x.ptr);
+    A.fy = static_cast<Real *>(p->front_y.ptr);
+    A.fz = static_cast<Real *>(p->front_z.ptr);
+    A.phi_oct = static_cast<Real *>(p->phi_oct.ptr);
+    A.psi = static_cast<Real *>(p->psi.ptr);
+    A.grad_oct = nullptr;
+    A.vol = Real(p->h[0] * p->h[1] * p->h[2]);
+    A.hh = Real(std::cbrt(p->h[0] * p->h[1] * p->h[2]));
+    for (int o = 0; o < 8; ++o)
+        for (int a = 0; a < 3; ++a) {
+            // forward: Omega enters through the low face of axis a when its
+            // component is positive, through the high face otherwise
+            const int face = 2 * a + ((o >> a) & 1);
+            A.inc[o][a] = adjoint ? Real(0) : Real(p->psi_inc[face]);
+        }
+    return A;
+}
+
+template <typename Real>
+int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Real *grad_oct,
+              hipStream_t s)
+{
+    PlaneArgs<Real> A = plane_args<Real>(p, src, adjoint);
+    A.grad_oct = grad_oct;
+    const bool ann = p->solver == DGSN_ANN && !adjoint;
+    if (ann) {
+        if (!p->ann) return set_error(DGSN_EINVAL, "solver is DGSN_ANN but no ANN is attached");
+        if (store_psi)
+            return set_error(DGSN_EUNSUPPORTED, "store_psi is not available with the ANN solver");
+        A.ann_params = ann_device_params(p->ann);
+    }
+    const uint32_t *cells = static_cast<const uint32_t *>(p->d_plane_cells.ptr);
+    p->last_stream = s;
+    p->ev_used = 0;
+    for (int pl = 0; pl < p->n_planes; ++pl) {
+        A.cells = cells + p->plane_off[pl];
+        A.ncp = p->plane_off[pl + 1] - p->plane_off[pl];
+        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[2 * pl], s));
+        bool done = false;
+        if constexpr (sizeof(Real) == 4) {
+            if (ann) {
+                DGSN_TRY(launch_plane_ann(A, s));
+                done = true;
+            }
+        }
+        if (!done) DGSN_TRY(launch_plane<Real>(A, store_psi, adjoint, s));
+        if (p->timing) {
+            DGSN_HIP(hipEventRecord(p->ev[2 * pl + 1], s));
+            p->ev_used = pl + 1;
+        }
+    }
+    return DGSN_OK;
+}
+
+template <typename Real>
+ReduceArgs<Real> reduce_args(dgsn_problem *p, void *phi)
+{
+    ReduceArgs<Real> R{};
+    R.phi_oct = static_cast<const Real *>(p->phi_oct.ptr);
+    R.phi = static_cast<Real *>(phi);
+    R.nv = (long long)p->G * p->ncell;
+    R.partials = static_cast<double *>(p->red_partials.ptr);
+    R.result = static_cast<double *>(p->red_result.ptr);
+    return R;
+}
+
+int read_result(dgsn_problem *p, hipStream_t s, double out[3])
+{
+    DGSN_HIP(hipMemcpyAsync(out, p->red_result.ptr, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DGSN_HIP(hipStreamSynchronize(s));
+    return DGSN_OK;
+}
+
+template <typename Real>
+int sweep_impl(dgsn_problem *p, const void *src, void *phi, hipStream_t s)
+{
+    DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
+    ReduceArgs<Real> R = reduce_args<Real>(p, phi);
+    return launch_reduce<Real>(R, p->red_blocks, s);
+}
+
+template <typename Real>
+int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
+                        double *resid, double *eps_s, hipStream_t s)
+{
+    const long long nv = (long long)p->G * p->ncell;
+    Real *src = static_cast<Real *>(p->src.ptr);
+    DGSN_TRY(launch_build_source<Real>(nv, static_cast<const Real *>(p->q.ptr),
+                                       static_cast<const Real *>(p->sigma_s.ptr),
+                                       static_cast<const Real *>(phi), src, s));
+    ReduceArgs<Real> R = reduce_args<Real>(p, phi);
+    R.resid = 1;
+    R.src_next = src;
+    R.q_cell = static_cast<const Real *>(p->q.ptr);
+    R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    double r = INFINITY, es = INFINITY, best = INFINITY;
+    int it = 0, stall = 0;
+    const bool fp32 = p->precision == DGSN_FP32;
+    while (it < max_iter) {
+        DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
+        DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        double res[3];
+        DGSN_TRY(read_result(p, s, res));
+        ++it;
+        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+        es = res[2] / (double)nv;
+        if (!std::isfinite(r))
+            return set_error(DGSN_EINVAL, "source iteration produced a non-finite residual");
+        if (r < tol) break;
+        if (fp32) {
+            if (r < best) { best = r; stall = 0; }
+            else if (++stall >= 5) break;
+        }
+    }
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (eps_s) *eps_s = es;
+    if (!(r < tol))
+        return set_error(DGSN_ENOTCONV, "source iteration stopped after %d sweeps at residual %.3e",
+                         it, r);
+    return DGSN_OK;
+}
+
+template <typename Real>
+int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double tol, int max_iter,
+                 int *iters, hipStream_t s)
+{
+    const long long nv = (long long)p->G * p->ncell;
+    if (!p->adj_phi.ptr) {
+        DGSN_TRY(p->adj_phi.alloc(nv * 8 * p->real_size));
+        DGSN_TRY(p->adj_src.alloc(2 * nv * 8 * p->real_size));   // load and source
+        DGSN_TRY(p->grad_oct.alloc(8 * nv * 2 * p->real_size));
+    }
+    Real *phid = static_cast<Real *>(p->adj_phi.ptr);
+    Real *load = static_cast<Real *>(p->adj_src.ptr);
+    Real *asrc = load + nv * 8;
+    const double vol = p->h[0] * p->h[1] * p->h[2];
+    DGSN_TRY(launch_adjoint_load<Real>(nv, static_cast<const Real *>(gphi), vol, load, s));
+    DGSN_HIP(hipMemsetAsync(phid, 0, nv * 8 * sizeof(Real), s));
+    DGSN_HIP(hipMemcpyAsync(asrc, load, nv * 8 * sizeof(Real), hipMemcpyDeviceToDevice, s));
+    ReduceArgs<Real> R = reduce_args<Real>(p, phid);
+    R.resid = 1;
+    R.src_next = asrc;
+    R.q_nodal = load;
+    R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    double r = INFINITY, best = INFINITY;
+    int it = 0, stall = 0;
+    const bool fp32 = p->precision == DGSN_FP32;
+    while (it < max_iter) {
+        DGSN_TRY(run_sweep<Real>(p, asrc, false, true, nullptr, s));
+        DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        double res[3];
+        DGSN_TRY(read_result(p, s, res));
+        ++it;
+        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+        if (!std::isfinite(r))
+            return set_error(DGSN_EINVAL, "adjoint iteration produced a non-finite residual");
+        if (r < tol) break;
+        if (fp32) {
+            if (r < best) { best = r; stall = 0; }
+            else if (++stall >= 5) break;
+        }
+    }
+    // contraction sweep with the converged adjoint scalar flux
+    Real *goct = static_cast<Real *>(p->grad_oct.ptr);
+    DGSN_TRY(run_sweep<Real>(p, asrc, false, true, goct, s));
+    DGSN_TRY(launch_reduce_grad<Real>(nv, goct, static_cast<Real *>(gst), static_cast<Real *>(gq),
+                                      s));
+    DGSN_HIP(hipStreamSynchronize(s));
+    if (iters) *iters = it;
+    if (!(r < tol))
+        return set_error(DGSN_ENOTCONV, "adjoint iteration stopped after %d sweeps at %.3e", it, r);
+    return DGSN_OK;
+}
+
+}  // namespace
+
+dgsn_problem::~dgsn_problem()
+{
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+int dgsn_version(void) { return 10000; }
+
+const char *dgsn_last_error(void) { return dgsn::g_msg; }
+
+int dgsn_ctx_create(int hip_device, dgsn_ctx **out)
+{
+    clear_error();
+    if (!out) return set_error(DGSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    DGSN_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev)
+        return set_error(DGSN_EINVAL, "device %d out of range (%d devices)", hip_device, ndev);
+    DGSN_HIP(hipSetDevice(hip_device));
+    hipDeviceProp_t prop;
+    DGSN_HIP(hipGetDeviceProperties(&prop, hip_device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(DGSN_EUNSUPPORTED, "libdgsn is built for gfx950, device is %s",
+                         prop.gcnArchName);
+    dgsn_ctx *c = new (std::nothrow) dgsn_ctx();
+    if (!c) return set_error(DGSN_ENOMEM, "host allocation failed");
+    c->device = hip_device;
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return DGSN_OK;
+}
+
+int dgsn_ctx_destroy(dgsn_ctx *ctx)
+{
+    clear_error();
+    delete ctx;
+    return DGSN_OK;
+}
+
+int dgsn_quadrature_ls(int order, double *omega, double *weight, int *n_inout)
+{
+    clear_error();
+    if (!n_inout) return set_error(DGSN_EINVAL, "n_inout is NULL");
+    std::vector<double> om, w;
+    DGSN_TRY(level_symmetric(order, om, w));
+    const int n = (int)w.size();
+    if (omega || weight) {
+        if (!omega || !weight) return set_error(DGSN_EINVAL, "omega and weight must both be set");
+        if (*n_inout < n)
+            return set_error(DGSN_EINVAL, "capacity %d < %d directions", *n_inout, n);
+        std::memcpy(omega, om.data(), om.size() * sizeof(double));
+        std::memcpy(weight, w.data(), w.size() * sizeof(double));
+    }
+    *n_inout = n;
+    return DGSN_OK;
+}
+
+int dgsn_problem_validate(const dgsn_problem_desc *desc)
+{
+    clear_error();
+    return validate_desc(desc);
+}
+
+int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem **out)
+{
+    clear_error();
+    if (!out) return set_error(DGSN_EINVAL, "out is NULL");
+    *out = nullptr;
+    DGSN_TRY(validate_desc(d));
+    if (!ctx) return set_error(DGSN_EINVAL, "ctx is NULL");
+    DGSN_HIP(hipSetDevice(ctx->device));
+    dgsn_problem *p = new (std::nothrow) dgsn_problem();
+    if (!p) return set_error(DGSN_ENOMEM, "host allocation failed");
+    auto fail = [&](int rc) {
+        delete p;
+        return rc;
+    };
+    p->ctx = ctx;
+    p->n[0] = d->nx;
+    p->n[1] = d->ny;
+    p->n[2] = d->nz;
+    p->len[0] = d->lx;
+    p->len[1] = d->ly;
+    p->len[2] = d->lz;
+    for (int a = 0; a < 3; ++a) p->h[a] = p->len[a] / p->n[a];
+    p->ncell = (long long)d->nx * d->ny * d->nz;
+    p->G = d->n_groups;
+    p->D = d->n_dirs;
+    p->Do = d->n_dirs / 8;
+    p->precision = d->precision;
+    p->solver = d->solver;
+    p->store_psi = d->store_psi ? 1 : 0;
+    p->real_size = d->precision == DGSN_FP64 ? 8 : 4;
+    p->n_planes = d->nx + d->ny + d->nz - 2;
+
+    // directions sorted by octant, user order inside an octant
+    p->dir_user.assign(p->D, -1);
+    p->dir_host.assign((size_t)8 * p->Do * kDirStride, 0.0);
+    int fill[8] = {0};
+    for (int u = 0; u < p->D; ++u) {
+        const double *om = d->omega + 3 * u;
+        const int o = (om[0] < 0) + 2 * (om[1] < 0) + 4 * (om[2] < 0);
+        const int slot = o * p->Do + fill[o]++;
+        p->dir_user[slot] = u;
+        double kappa[3];
+        for (int a = 0; a < 3; ++a) kappa[a] = std::fabs(om[a]) / p->h[a];
+        double *e = &p->dir_host[(size_t)slot * kDirStride];
+        streaming_matrix(kappa, e);
+        for (int a = 0; a < 3; ++a) e[64 + a] = kappa[a] / 36.0;
+        e[67] = d->weight[u];
+    }
+
+    // hyperplane schedule in canonical coordinates
+    std::vector<uint32_t> cells;
+    cells.reserve(p->ncell);
+    p->plane_off.assign(p->n_planes + 1, 0);
+    for (int pl = 0; pl < p->n_planes; ++pl) {
+        p->plane_off[pl] = (int)cells.size();
+        for (int k = 0; k < d->nz; ++k)
+            for (int j = 0; j < d->ny; ++j) {
+                const int i = pl - j - k;
+                if (i < 0 || i >= d->nx) continue;
+                cells.push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
+            }
+    }
+    p->plane_off[p->n_planes] = (int)cells.size();
+
+    int rc;
+    if ((rc = p->d_plane_cells.alloc(cells.size() * sizeof(uint32_t)))) return fail(rc);
+    if (hipMemcpy(p->d_plane_cells.ptr, cells.data(), cells.size() * sizeof(uint32_t),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return fail(set_error(DGSN_EHIP, "upload of the hyperplane schedule failed"));
+    rc = p->precision == DGSN_FP64 ? upload_real<double>(p->d_dir, p->dir_host)
+                                   : upload_real<float>(p->d_dir, p->dir_host);
+    if (rc) return fail(rc);
+
+    const size_t rs = p->real_size;
+    const long long nv = (long long)p->G * p->ncell;
+    const long long DG = (long long)p->Do * p->G;
+    if ((rc = p->sigma_t.alloc(nv * rs)) || (rc = p->sigma_s.alloc(nv * rs)) ||
+        (rc = p->q.alloc(nv * rs)) || (rc = p->src.alloc(nv * 8 * rs)) ||
+        (rc = p->phi_oct.alloc(8 * nv * 8 * rs)) ||
+        (rc = p->front_x.alloc(8LL * d->nz * d->ny * 4 * DG * rs)) ||
+        (rc = p->front_y.alloc(8LL * d->nz * d->nx * 4 * DG * rs)) ||
+        (rc = p->front_z.alloc(8LL * d->ny * d->nx * 4 * DG * rs)))
+        return fail(rc);
+    if (p->store_psi && (rc = p->psi.alloc((size_t)p->D * nv * 8 * rs))) return fail(rc);
+    p->red_blocks = reduce_blocks_for(nv);
+    if ((rc = p->red_partials.alloc((size_t)p->red_blocks * 3 * sizeof(double))) ||
+        (rc = p->red_result.alloc(4 * sizeof(double))))
+        return fail(rc);
+    if (hipMemset(p->sigma_t.ptr, 0, nv * rs) != hipSuccess ||
+        hipMemset(p->sigma_s.ptr, 0, nv * rs) != hipSuccess ||
+        hipMemset(p->q.ptr, 0, nv * rs) != hipSuccess)
+        return fail(set_error(DGSN_EHIP, "initialising material buffers failed"));
+    *out = p;
+    return DGSN_OK;
+}
+
+int dgsn_problem_destroy(dgsn_problem *p)
+{
+    clear_error();
+    if (p) {
+        (void)hipSetDevice(p->ctx->device);
+        delete p;
+    }
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void *sigma_s,
+                               const void *q, void *stream)
+{
+    clear_error();
+    if (!p || !sigma_t) return set_error(DGSN_EINVAL, "problem and sigma_t must be set");
+    const size_t bytes = (size_t)p->G * p->ncell * p->real_size;
+    hipStream_t s = as_stream(stream);
+    DGSN_HIP(hipMemcpyAsync(p->sigma_t.ptr, sigma_t, bytes, hipMemcpyDeviceToDevice, s));
+    if (sigma_s) DGSN_HIP(hipMemcpyAsync(p->sigma_s.ptr, sigma_s, bytes, hipMemcpyDeviceToDevice, s));
+    else DGSN_HIP(hipMemsetAsync(p->sigma_s.ptr, 0, bytes, s));
+    if (q) DGSN_HIP(hipMemcpyAsync(p->q.ptr, q, bytes, hipMemcpyDeviceToDevice, s));
+    else DGSN_HIP(hipMemsetAsync(p->q.ptr, 0, bytes, s));
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6])
+{
+    clear_error();
+    if (!p || !psi_inc) return set_error(DGSN_EINVAL, "problem and psi_inc must be set");
+    for (int f = 0; f < 6; ++f)
+        if (!std::isfinite(psi_inc[f]))
+            return set_error(DGSN_EINVAL, "psi_inc[%d] is not finite", f);
+    std::memcpy(p->psi_inc, psi_inc, sizeof(p->psi_inc));
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (ann && p->precision != DGSN_FP32)
+        return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    p->ann = ann;
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_solver(dgsn_problem *p, int solver)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (solver != DGSN_GE && solver != DGSN_ANN)
+        return set_error(DGSN_EINVAL, "solver must be DGSN_GE or DGSN_ANN");
+    if (solver == DGSN_ANN && p->precision != DGSN_FP32)
+        return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    p->solver = solver;
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_timing(dgsn_problem *p, int enable)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    if (enable && p->ev.empty()) {
+        p->ev.assign(2 * p->n_planes, nullptr);
+        for (auto &e : p->ev) DGSN_HIP(hipEventCreate(&e));
+    }
+    p->timing = enable ? 1 : 0;
+    p->ev_used = 0;
+    return DGSN_OK;
+}
+
+int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    double total = 0.0;
+    if (p->ev_used > 0) {
+        DGSN_HIP(hipEventSynchronize(p->ev[2 * p->ev_used - 1]));
+        for (int i = 0; i < p->ev_used; ++i) {
+            float ms = 0.0f;
+            DGSN_HIP(hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]));
+            total += ms;
+        }
+    }
+    if (ms_sum) *ms_sum = total;
+    if (launches) *launches = p->ev_used;
+    return DGSN_OK;
+}
+
+int dgsn_problem_stats(const dgsn_problem *p, long long *solves, int *n_planes, double *bytes)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    const long long s = p->ncell * p->D * (long long)p->G;
+    if (solves) *solves = s;
+    if (n_planes) *n_planes = p->n_planes;
+    if (bytes) *bytes = (double)p->real_size * (24.0 * s + 17.0 * p->ncell * p->G);
+    return DGSN_OK;
+}
+
+int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream)
+{
+    clear_error();
+    if (!p || !src || !phi) return set_error(DGSN_EINVAL, "problem, src and phi must be set");
+    if (src == phi) return set_error(DGSN_EINVAL, "src and phi must not overlap");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    return p->precision == DGSN_FP64 ? sweep_impl<double>(p, src, phi, as_stream(stream))
+                                     : sweep_impl<float>(p, src, phi, as_stream(stream));
+}
+
+int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
+                        double *resid, double *eps_s, void *stream)
+{
+    clear_error();
+    if (!p || !phi) return set_error(DGSN_EINVAL, "problem and phi must be set");
+    if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
+    if (!(tol >= 0.0)) return set_error(DGSN_EINVAL, "tol must be >= 0");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    return p->precision == DGSN_FP64
+               ? source_iterate_impl<double>(p, phi, tol, max_iter, iters, resid, eps_s,
+                                             as_stream(stream))
+               : source_iterate_impl<float>(p, phi, tol, max_iter, iters, resid, eps_s,
+                                            as_stream(stream));
+}
+
+int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, double tol,
+                       int max_iter, int *iters, void *stream)
+{
+    clear_error();
+    if (!p || !gphi) return set_error(DGSN_EINVAL, "problem and dJ_dphi must be set");
+    if (!p->store_psi || !p->psi.ptr)
+        return set_error(DGSN_EINVAL, "the adjoint needs a problem created with store_psi = 1");
+    if (p->solver != DGSN_GE)
+        return set_error(DGSN_EUNSUPPORTED, "the adjoint is defined for the GE solver");
+    if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    return p->precision == DGSN_FP64
+               ? adjoint_impl<double>(p, gphi, gst, gq, tol, max_iter, iters, as_stream(stream))
+               : adjoint_impl<float>(p, gphi, gst, gq, tol, max_iter, iters, as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every entry point declared in include/dgsn.h,
+and do its host-only work (quadrature, descriptor validation, artifact
+parsing) correctly.  No device call is made here.
+"""
+import ctypes
+import os
+import re
+import struct
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_04017_amd import _lib, ann_format
+from paper_1906_04017_amd._lib import ProblemDesc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1906_04017_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "dgsn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgsn_\w+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_symbols()
+    for required in ("dgsn_problem_create", "dgsn_sweep", "dgsn_source_iterate",
+                     "dgsn_adjoint_solve", "dgsn_ann_load", "dgsn_ann_infer",
+                     "dgsn_local_solve", "dgsn_batch_run"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(declared_symbols()) == set(_lib.SIGNATURES)
+
+
+def test_version(lib):
+    assert lib.dgsn_version() >= 10000
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10, 12])
+def test_library_quadrature_matches_oracle(lib, order):
+    from paper_1906_04017_amd import api
+    om, w = api.quadrature_ls(order)
+    om_o, w_o = oracle.lq_n(order)
+    assert om.shape == om_o.shape
+    # two independent root searches on an increasingly ill-conditioned
+    # weight system (S10, S12): agreement to a few hundred ulps
+    assert np.abs(om - om_o).max() < 1e-13
+    assert np.abs(w - w_o).max() < 1e-13
+
+
+def test_quadrature_rejects_bad_orders(lib):
+    n = ctypes.c_int(0)
+    for order in (0, 3, 14, -2):
+        assert lib.dgsn_quadrature_ls(order, None, None, ctypes.byref(n)) == _lib.DGSN_EINVAL
+    assert lib.dgsn_quadrature_ls(8, None, None, ctypes.byref(n)) == 0 and n.value == 80
+    small = ctypes.c_int(10)
+    om = np.zeros((80, 3))
+    w = np.zeros(80)
+    rc = lib.dgsn_quadrature_ls(8, om.ctypes.data_as(_lib._PD), w.ctypes.data_as(_lib._PD),
+                                ctypes.byref(small))
+    assert rc == _lib.DGSN_EINVAL and b"capacity" in lib.dgsn_last_error()
+
+
+def _desc(**kw):
+    om, w = oracle.lq_n(4)
+    a = dict(n=(4, 4, 4), L=(1.0, 1.0, 1.0), G=1, om=om, w=w, prec=0, solver=0, store=0)
+    a.update(kw)
+    om = np.ascontiguousarray(a["om"], np.float64)
+    w = np.ascontiguousarray(a["w"], np.float64)
+    d = ProblemDesc(a["n"][0], a["n"][1], a["n"][2], a["L"][0], a["L"][1], a["L"][2], a["G"],
+                    len(w), om.ctypes.data_as(_lib._PD), w.ctypes.data_as(_lib._PD), a["prec"],
+                    a["solver"], a["store"])
+    return d, (om, w)
+
+
+def test_validation_accepts_good_descriptor(lib):
+    d, keep = _desc()
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == 0
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(n=(0, 4, 4)), b"cells per axis"),
+    (dict(n=(4, 4, 2000)), b"cells per axis"),
+    (dict(L=(1.0, -1.0, 1.0)), b"domain length"),
+    (dict(L=(1.0, float("nan"), 1.0)), b"domain length"),
+    (dict(G=0), b"n_groups"),
+    (dict(prec=7), b"precision"),
+    (dict(solver=5), b"solver"),
+    (dict(prec=1, solver=1), b"FP32"),
+])
+def test_validation_rejects_bad_descriptors(lib, kw, needle):
+    d, keep = _desc(**kw)
+    rc = lib.dgsn_problem_validate(ctypes.byref(d))
+    assert rc in (_lib.DGSN_EINVAL, _lib.DGSN_EUNSUPPORTED)
+    assert needle in lib.dgsn_last_error()
+
+
+def test_validation_rejects_bad_quadratures(lib):
+    om, w = oracle.lq_n(4)
+    bad = om.copy()
+    bad[3] *= 1.001
+    d, keep = _desc(om=bad)
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == _lib.DGSN_EINVAL
+    assert b"unit vector" in lib.dgsn_last_error()
+    d, keep = _desc(w=w * 1.01)
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == _lib.DGSN_EINVAL
+    assert b"4 pi" in lib.dgsn_last_error()
+    w2 = w.copy()
+    w2[0] = -w2[0]
+    d, keep = _desc(w=w2)
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == _lib.DGSN_EINVAL
+    # unbalanced octants: flip the sign of one direction
+    om2 = om.copy()
+    om2[0] = -om2[0]
+    d, keep = _desc(om=om2)
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == _lib.DGSN_EINVAL
+    assert b"octant" in lib.dgsn_last_error()
+    d, keep = _desc(om=om[:20], w=w[:20] * 24 / 20)
+    assert lib.dgsn_problem_validate(ctypes.byref(d)) == _lib.DGSN_EINVAL
+    assert lib.dgsn_problem_validate(None) == _lib.DGSN_EINVAL
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.dgsn_sweep(None, None, None, None) == _lib.DGSN_EINVAL
+    assert lib.dgsn_source_iterate(None, None, 1e-8, 10, None, None, None, None) == _lib.DGSN_EINVAL
+    assert lib.dgsn_adjoint_solve(None, None, None, None, 1e-8, 10, None, None) == _lib.DGSN_EINVAL
+    assert lib.dgsn_problem_set_inflow(None, None) == _lib.DGSN_EINVAL
+    out = ctypes.c_void_p()
+    d, keep = _desc()
+    assert lib.dgsn_problem_create(None, ctypes.byref(d), ctypes.byref(out)) == _lib.DGSN_EINVAL
+    assert lib.dgsn_local_solve(None, None, None, 10, 0, None) == _lib.DGSN_EINVAL
+
+
+def _artifact(tmp_path, nh=64, act=0, seed=0):
+    rng = np.random.default_rng(seed)
+    p = tmp_path / f"net_{nh}_{act}.dgsnann"
+    ann_format.write(p, rng.normal(size=(nh, 24)), rng.normal(size=nh), rng.normal(size=(8, nh)),
+                     rng.normal(size=8), activation=act)
+    return p
+
+
+def test_artifact_roundtrip(tmp_path):
+    p = _artifact(tmp_path)
+    net = ann_format.read(p)
+    assert net["W1"].shape == (64, 24) and net["W2"].shape == (8, 64)
+    raw = open(p, "rb").read()
+    assert raw[:8] == b"DGSNANN1"
+    assert struct.unpack("<I", raw[-4:])[0] == zlib.crc32(raw[:-4]) & 0xFFFFFFFF
+
+
+def test_ann_load_checks_file_before_device(lib, tmp_path):
+    out = ctypes.c_void_p()
+    good = _artifact(tmp_path)
+    # valid file, no context: the format passes, the missing context is reported
+    assert lib.dgsn_ann_load(None, str(good).encode(), ctypes.byref(out)) == _lib.DGSN_EINVAL
+    assert b"ctx" in lib.dgsn_last_error()
+    raw = bytearray(open(good, "rb").read())
+    bad = tmp_path / "bad_magic.dgsnann"
+    bad.write_bytes(b"XXXXXXXX" + bytes(raw[8:]))
+    assert lib.dgsn_ann_load(None, str(bad).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    flip = bytearray(raw)
+    flip[100] ^= 0x40
+    bad.write_bytes(bytes(flip))
+    assert lib.dgsn_ann_load(None, str(bad).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    assert b"checksum" in lib.dgsn_last_error()
+    bad.write_bytes(bytes(raw[:-10]))
+    assert lib.dgsn_ann_load(None, str(bad).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    tanh = _artifact(tmp_path, act=1)
+    assert lib.dgsn_ann_load(None, str(tanh).encode(), ctypes.byref(out)) == _lib.DGSN_EUNSUPPORTED
+    wide = _artifact(tmp_path, nh=96)
+    assert lib.dgsn_ann_load(None, str(wide).encode(), ctypes.byref(out)) == _lib.DGSN_EUNSUPPORTED
+    missing = tmp_path / "nope.dgsnann"
+    assert lib.dgsn_ann_load(None, str(missing).encode(), ctypes.byref(out)) == _lib.DGSN_EINVAL

@@ -1,0 +1,332 @@
+"""GPU parity of the HIP transport path against the FP64 CPU oracle.
+
+Every device call goes through the C ABI (paper_1906_04017_amd.api is plain
+ctypes marshalling).  Both sides get the same seeded inputs from
+paper_1906_04017_amd.inputs; the GPU uses the library's own LQ_N quadrature,
+the oracle its own independent construction (they agree to 1e-13).
+
+Tolerances (norm-wise relative error max|a - b| / max|b| unless stated):
+  FP64 sweep / SI / adjoint  1e-12 / 1e-10 / 1e-10  (rounding only; different
+                             assembly order and element-matrix construction)
+  FP32 sweep and SI          1e-5   (the stated FP32 GE target)
+  FP32 adjoint gradients     1e-4
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1906_04017_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_SWEEP_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1906_04017_amd import api as _api
+    return _api
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mesh_of(p):
+    return (*p["n"], *p["length"])
+
+
+def gpu_problem(api, ctx, p, precision, solver="ge", store_psi=False):
+    om, w = api.quadrature_ls(p["order"])
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision=precision,
+                       solver=solver, store_psi=store_psi)
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.set_inflow(p["psi_inc"])
+    return prob
+
+
+def nodal_source(p, seed=None):
+    """q as a nodal field, plus an optional random nodal part."""
+    S = np.repeat(p["q"][..., None], 8, axis=-1)
+    if seed is not None:
+        S = S + inputs.random_nodal(p["sigma_t"].shape[1], p["groups"], seed, -0.2, 0.5)
+    return S
+
+
+def print_case(case, **kw):
+    print(f"[case] {case} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# one-cell GE
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_local_solve_matches_oracle(api, ctx, precision, tol):
+    print_case("local_solve", precision=precision)
+    rng = np.random.default_rng(101)
+    n = 4099
+    om = np.abs(rng.normal(size=(n, 3)))
+    om /= np.linalg.norm(om, axis=1, keepdims=True)
+    h = rng.uniform(0.2, 2.0, size=(n, 3))
+    st = 10 ** rng.uniform(-4, 1.3, size=n)
+    S = rng.uniform(-0.1, 1.0, size=(n, 8))
+    pin = rng.uniform(-0.1, 1.0, size=(n, 12))
+    up = np.zeros((n, 6, 8))
+    for fn in range(4):
+        up[:, 0, 2 * fn] = pin[:, fn]
+        up[:, 2, (fn & 1) + 4 * (fn >> 1)] = pin[:, 4 + fn]
+        up[:, 4, fn] = pin[:, 8 + fn]
+    ref = oracle.cell_solve_batch(h, om, st, S, up)
+    hh = np.cbrt(h.prod(axis=1))
+    x = np.concatenate([om * hh[:, None] / h, (st * hh)[:, None], pin, S * hh[:, None]], axis=1)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    y = api.local_solve(ctx, torch.tensor(x, dtype=dt, device="cuda")).cpu().numpy()
+    err = np.abs(y - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert err.max() < tol
+
+
+# ---------------------------------------------------------------------------
+# sweep
+# ---------------------------------------------------------------------------
+
+def test_sweep_absorber_cube_fp64(api, ctx):
+    p = inputs.absorber_cube()
+    print_case("sweep", name=p["name"], precision="fp64")
+    prob = gpu_problem(api, ctx, p, "fp64")
+    S = nodal_source(p)
+    phi = prob.sweep(torch.tensor(S, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(p["order"])
+    ref = oracle.sweep(mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= FP64_SWEEP_TOL
+
+
+RAGGED = [
+    ((1, 1, 1), (0.3, 0.3, 0.3), 2, 1),
+    ((5, 3, 2), (1.0, 0.6, 0.5), 4, 3),
+    ((7, 2, 9), (0.7, 0.2, 1.8), 6, 2),
+    ((4, 6, 3), (1.0, 1.5, 0.75), 12, 1),
+    ((9, 9, 9), (1.0, 1.0, 1.0), 8, 5),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in RAGGED])
+def test_sweep_ragged_meshes(api, ctx, precision, case):
+    n, L, order, G = case
+    print_case("sweep", n=n, order=order, G=G, precision=precision)
+    p = inputs.random_problem(n, order, G, seed=hash(case) % 1000, length=L)
+    prob = gpu_problem(api, ctx, p, precision)
+    S = nodal_source(p, seed=7)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    phi = prob.sweep(torch.tensor(S, dtype=dt, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(order)
+    ref = oracle.sweep(mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= (FP64_SWEEP_TOL if precision == "fp64" else FP32_TOL)
+
+
+def test_sweep_multi_group_multi_tile(api, ctx):
+    # several blocks per hyperplane and a ragged last block (Do = 10, G = 7)
+    p = inputs.random_problem((12, 10, 11), 8, 7, seed=5, length=(1.2, 1.0, 1.1))
+    print_case("sweep", name=p["name"], precision="fp32")
+    prob = gpu_problem(api, ctx, p, "fp32")
+    S = nodal_source(p, seed=9)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(8)
+    ref = oracle.sweep(mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= FP32_TOL
+
+
+def test_sweep_is_deterministic(api, ctx):
+    p = inputs.random_problem((10, 9, 8), 6, 3, seed=11)
+    print_case("determinism", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32")
+    S = torch.tensor(nodal_source(p, seed=3), dtype=torch.float32, device="cuda")
+    a = prob.sweep(S).cpu()
+    b = prob.sweep(S).cpu()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+def test_constant_solution_invariant(api, ctx, precision, tol):
+    # uniform sigma_t and q with matching inflow q/sigma_t on every face:
+    # psi == q/sigma_t at every node, so phi == 4 pi q / sigma_t
+    n = (6, 5, 7)
+    print_case("constant_solution", n=n, precision=precision)
+    ncell = 6 * 5 * 7
+    st, qv = 3.3, 1.7
+    p = inputs.problem(n, (0.6, 0.5, 0.9), 8, 2, np.full((2, ncell), st), np.zeros((2, ncell)),
+                       np.full((2, ncell), qv), np.full(6, qv / st), "const")
+    prob = gpu_problem(api, ctx, p, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    phi = prob.sweep(torch.full((2, ncell, 8), qv, dtype=dt, device="cuda")).cpu().numpy()
+    assert np.abs(phi / (4 * np.pi * qv / st) - 1).max() < tol
+
+
+# ---------------------------------------------------------------------------
+# source iteration
+# ---------------------------------------------------------------------------
+
+def test_source_iteration_fp64(api, ctx):
+    p = inputs.random_problem((6, 5, 4), 4, 2, seed=21, c_max=0.8)
+    print_case("source_iterate", name=p["name"], precision="fp64")
+    prob = gpu_problem(api, ctx, p, "fp64")
+    phi, info = prob.source_iterate(tol=1e-13, max_iter=500)
+    om, w = oracle.lq_n(4)
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-14, max_iter=1000)
+    assert info["converged"] and ref["converged"]
+    assert rel(phi.cpu().numpy(), ref["phi"]) <= 1e-10
+
+
+def test_source_iteration_fp32_blocky(api, ctx):
+    p = inputs.blocky_scatter(n=16, groups=3, seed=2, order=8)
+    print_case("source_iterate", name=p["name"], precision="fp32")
+    prob = gpu_problem(api, ctx, p, "fp32")
+    phi, info = prob.source_iterate(tol=1e-8, max_iter=400, allow_notconv=True)
+    om, w = oracle.lq_n(8)
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-12, max_iter=2000)
+    assert ref["converged"]
+    assert info["resid"] < 1e-6
+    for g in range(p["groups"]):
+        assert rel(phi.cpu().numpy()[g], ref["phi"][g]) <= FP32_TOL
+
+
+def test_source_iteration_resume_from_saved_phi(api, ctx):
+    p = inputs.random_problem((5, 5, 5), 4, 1, seed=23, c_max=0.9)
+    print_case("source_iterate_resume", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp64")
+    full, info_full = prob.source_iterate(tol=1e-12, max_iter=1000)
+    part, info_part = prob.source_iterate(tol=1e-12, max_iter=5, allow_notconv=True)
+    assert not info_part["converged"] and info_part["iters"] == 5
+    rest, info_rest = prob.source_iterate(phi0=part, tol=1e-12, max_iter=1000)
+    assert info_rest["converged"]
+    assert rel(rest.cpu().numpy(), full.cpu().numpy()) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_adjoint_matches_oracle(api, ctx, precision, tol):
+    p = inputs.adjoint_box(n=6, groups=2, seed=4, box=(2, 4))
+    print_case("adjoint", name=p["name"], precision=precision)
+    prob = gpu_problem(api, ctx, p, precision, store_psi=True)
+    si_tol = 1e-13 if precision == "fp64" else 1e-7
+    phi, info = prob.source_iterate(tol=si_tol, max_iter=1000, allow_notconv=True)
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    g = np.zeros((p["groups"], 216, 8))
+    g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    gst, gq, ainfo = prob.adjoint(torch.tensor(g, dtype=dt, device="cuda"), tol=si_tol,
+                                  max_iter=1000, allow_notconv=True)
+    om, w = oracle.lq_n(p["order"])
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-14, max_iter=2000, store_psi=True)
+    a = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], ref["psi"], ref["phi"], g,
+                       tol=1e-14)
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= tol
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= tol
+
+
+# ---------------------------------------------------------------------------
+# ANN
+# ---------------------------------------------------------------------------
+
+def _random_net(seed, nh=64):
+    rng = np.random.default_rng(seed)
+    return dict(W1=(rng.normal(size=(nh, 24)) / 5).astype(np.float32),
+                b1=(rng.normal(size=nh) / 5).astype(np.float32),
+                W2=(rng.normal(size=(8, nh)) / 8).astype(np.float32),
+                b2=(rng.normal(size=8) / 5).astype(np.float32))
+
+
+def _write_net(tmp_path, net, name):
+    from paper_1906_04017_amd import ann_format
+    path = tmp_path / name
+    ann_format.write(path, net["W1"], net["b1"], net["W2"], net["b2"])
+    return path
+
+
+@pytest.mark.parametrize("nh", [64, 40, 8])
+def test_ann_infer_within_bf16_bound(api, ctx, tmp_path, nh):
+    print_case("ann_infer", nh=nh)
+    net = _random_net(300 + nh, nh)
+    ann = api.Ann(ctx, _write_net(tmp_path, net, f"r{nh}.dgsnann"))
+    rng = np.random.default_rng(7)
+    n = 1000 + 37
+    x = rng.uniform(-1, 1, size=(n, 24)).astype(np.float32)
+    y = ann.infer(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    W1, b1, W2, b2 = (net[k].astype(np.float64) for k in ("W1", "b1", "W2", "b2"))
+    xd = x.astype(np.float64)
+    ref = np.stack([oracle.ann_forward(net, xi) for xi in xd])
+    hid = np.maximum(xd @ W1.T + b1, 0)
+    u = 3 * 2.0 ** -8
+    dh = u * (np.abs(xd) @ np.abs(W1).T + np.abs(b1))
+    bound = u * (np.abs(hid) @ np.abs(W2).T + np.abs(b2)) + (dh @ np.abs(W2).T)
+    assert np.all(np.abs(y - ref) <= bound + 1e-6)
+
+
+def _identity_net(select):
+    W1 = np.zeros((48, 24))
+    for j in range(24):
+        W1[2 * j, j] = 1.0
+        W1[2 * j + 1, j] = -1.0
+    W2 = np.zeros((8, 48))
+    for t, j in enumerate(select):
+        W2[t, 2 * j] = 1.0
+        W2[t, 2 * j + 1] = -1.0
+    return dict(W1=W1.astype(np.float32), b1=np.zeros(48, np.float32),
+                W2=W2.astype(np.float32), b2=np.zeros(8, np.float32))
+
+
+def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path):
+    # psi = h S exactly (network y[n'] = x[16 + n']): checks features,
+    # reflection, normalisation and rescaling of the ANN sweep kernel; the
+    # only error is BF16 rounding of the normalised input and hidden value
+    net = _identity_net([16 + n for n in range(8)])
+    ann = api.Ann(ctx, _write_net(tmp_path, net, "src_pass.dgsnann"))
+    p = inputs.random_problem((7, 5, 6), 6, 2, seed=31, length=(0.7, 0.5, 0.6))
+    print_case("ann_sweep_source_passthrough", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    S = nodal_source(p, seed=13)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(6)
+    ref = oracle.ann_sweep(net, mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= 2 * 2.0 ** -8
+
+
+def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path):
+    # psi[n] = x-face inflow at the partner node: values are copied cell to
+    # cell along x, so the fronts and their boundary values are exercised;
+    # each hop re-rounds to BF16 at most twice
+    sel = [4 + (((n >> 1) & 1) + 2 * ((n >> 2) & 1)) for n in range(8)]
+    net = _identity_net(sel)
+    ann = api.Ann(ctx, _write_net(tmp_path, net, "inflow_pass.dgsnann"))
+    p = inputs.random_problem((6, 4, 3), 4, 1, seed=33)
+    p["psi_inc"] = np.array([0.8, 0.3, 0.0, 0.0, 0.0, 0.0])
+    p["q"][:] = 0.0
+    print_case("ann_sweep_inflow_passthrough", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    S = nodal_source(p)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(4)
+    ref = oracle.ann_sweep(net, mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= 2 * 6 * 2.0 ** -8
