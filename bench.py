@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="skip the FP64 and the ANN-vs-GE side measurements")
+    ap.add_argument("--ann", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "paper_1906_04017_amd", "data",
+                                                  "ann_s8_relu64.dgsnann"))
     ap.add_argument("--cpu-groups", type=int, default=8,
                     help="groups of the workload swept by the CPU oracle sample")
     return ap.parse_args()
@@ -102,6 +107,9 @@ def main():
             "avg_launch_us": round(1e3 * kern_ms / max(kern_launches, 1), 3),
             "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
 
+    fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
+    ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_groups)
@@ -116,8 +124,93 @@ def main():
                    "solves_per_step": solves, "last_residual": resid},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fp64_ge": fp64,
+        "ann_vs_ge": ann,
     }
     print(json.dumps(out), flush=True)
+
+
+def time_sweeps(prob, src, reps):
+    import torch
+    phi = prob.nodal_empty()
+    prob.sweep(src, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.sweep(src, phi)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, phi
+
+
+def plain_fp64(api, ctx, p, reps=3):
+    """Plain (FP64) GE sweep throughput on the same workload."""
+    import torch
+    om, w = api.quadrature_ls(p["order"])
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp64")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    src = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float64,
+                       device="cuda")
+    dt, _ = time_sweeps(prob, src, reps)
+    solves = prob.stats()["solves_per_sweep"]
+    log(f"fp64 GE sweep: {dt * 1e3:.3f} ms")
+    prob.close()
+    return {"solves_per_s": solves / dt, "ms_per_sweep": dt * 1e3, "solver": "GE", "dtype": "f64"}
+
+
+def ann_vs_ge(api, ctx, ann_path, n=128, reps=3):
+    """The paper's comparison on its four problems (one group each, 10 cm
+    cube, psi_inc = 1 on three faces), 128^3, S8: one sweep of all groups with
+    the FP32 GE solvers and with the BF16-MFMA ANN, and the ANN error eps_P
+    (cell-average mean relative difference) against GE per group; group 4
+    (c = 0.99) by source iteration to the paper's eps_S < 1e-4."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    p = inputs.paper_problems(n=n, groups=4, order=8)
+    om, w = api.quadrature_ls(8)
+    ann = api.Ann(ctx, ann_path)
+    S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32, device="cuda")
+    out = {"workload": p["name"], "ann_artifact": os.path.basename(ann_path)}
+    res = {}
+    for solver in ("ge", "ge_dense", "ann"):
+        prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32", solver=solver)
+        prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+        prob.set_inflow(p["psi_inc"])
+        if solver == "ann":
+            prob.set_ann(ann)
+        dt, phi = time_sweeps(prob, S, reps)
+        solves = prob.stats()["solves_per_sweep"]
+        out[f"{solver}_solves_per_s"] = solves / dt
+        out[f"{solver}_ms_per_sweep"] = dt * 1e3
+        res[solver] = phi.double().mean(-1)        # cell averages [G, ncell]
+        log(f"paper problems {solver}: {dt * 1e3:.3f} ms per sweep")
+        prob.close()
+    out["ann_over_ge_speed"] = out["ann_solves_per_s"] / out["ge_solves_per_s"]
+    out["ann_over_ge_dense_speed"] = out["ann_solves_per_s"] / out["ge_dense_solves_per_s"]
+    ref, got = res["ge"], res["ann"]
+    eps = ((got - ref).abs() / (ref.abs() + 1e-8)).mean(-1).cpu().numpy()
+    # group 4: scattering, converged by SI with both solvers (paper criterion)
+    p4 = inputs.problem(p["n"], p["length"], 8, 1, p["sigma_t"][3:4], p["sigma_s"][3:4],
+                        p["q"][3:4], p["psi_inc"], "problem4")
+    si = {}
+    for solver in ("ge", "ann"):
+        prob = api.Problem(ctx, p4["n"], p4["length"], 1, om, w, precision="fp32", solver=solver)
+        prob.set_materials(p4["sigma_t"], p4["sigma_s"], p4["q"])
+        prob.set_inflow(p4["psi_inc"])
+        if solver == "ann":
+            prob.set_ann(ann)
+        prob.set_si_criterion("eps_s")
+        phi, info = prob.source_iterate(tol=1e-4, max_iter=2000, allow_notconv=True)
+        si[solver] = (phi.double().mean(-1), info)
+        log(f"problem 4 SI {solver}: {info['iters']} iterations, eps_S {info['eps_s']:.2e}")
+        prob.close()
+    e4 = ((si["ann"][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
+    out["eps_p_percent_single_sweep"] = [round(100 * float(v), 3) for v in eps]
+    out["eps_p_percent_problem4_si"] = round(100 * e4, 3)
+    out["problem4_si_iterations"] = {"ge": si["ge"][1]["iters"], "ann": si["ann"][1]["iters"]}
+    out["paper_context"] = ("paper, 100^3 S8, unstated hardware: ANN saves 68.4 % of the solve time "
+                            "(3.16x); eps_P 1.59 / 2.45 / 0.45 / 0.87 % on Problems 1-4")
+    ann.close()
+    return out
 
 
 def cpu_baseline(p, groups):

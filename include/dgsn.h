@@ -55,7 +55,19 @@ enum {
 };
 
 enum { DGSN_FP32 = 0, DGSN_FP64 = 1 };
-enum { DGSN_GE = 0, DGSN_ANN = 1 };
+
+/*
+ * Local solvers of the cell system (Eq. (T12)):
+ *   DGSN_GE        Gaussian elimination (partial pivoting) of the cell system
+ *                  premultiplied by the inverse element mass matrix, known in
+ *                  closed form; the matrix has 32 structural zeros, which the
+ *                  elimination skips.  Same solution, about half the flops.
+ *   DGSN_ANN       the shallow network of Sec. 3 in place of assembly + GE.
+ *   DGSN_GE_DENSE  the cell matrix and right-hand side assembled as in Sec. 2
+ *                  (streaming, sigma_t times mass, upwind face terms) and
+ *                  solved by dense Gaussian elimination.
+ */
+enum { DGSN_GE = 0, DGSN_ANN = 1, DGSN_GE_DENSE = 2 };
 
 /* Library version as major*10000 + minor*100 + patch. */
 int dgsn_version(void);
@@ -86,7 +98,7 @@ typedef struct {
     const double *omega;     /* host [n_dirs][3], unit vectors (|1 - |O|| <= 1e-12) */
     const double *weight;    /* host [n_dirs], > 0, sum 4 pi (+-1e-10) */
     int precision;           /* DGSN_FP32 or DGSN_FP64 */
-    int solver;              /* DGSN_GE or DGSN_ANN (ANN: FP32 problems only) */
+    int solver;              /* DGSN_GE, DGSN_GE_DENSE or DGSN_ANN (ANN: FP32 only) */
     int store_psi;           /* keep the last sweep's angular flux (adjoint) */
 } dgsn_problem_desc;
 
@@ -120,7 +132,8 @@ int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
    problem keeps a reference; the ANN must outlive its use by the problem. */
 int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
 
-/* Select the local solver of subsequent sweeps (DGSN_GE or DGSN_ANN). */
+/* Select the local solver of subsequent sweeps (DGSN_GE, DGSN_GE_DENSE or
+   DGSN_ANN). */
 int dgsn_problem_set_solver(dgsn_problem *p, int solver);
 
 /*
@@ -147,6 +160,14 @@ int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream);
  */
 int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
                         double *resid, double *eps_s, void *stream);
+
+/*
+ * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses
+ * the FP64 max-norm relative change; DGSN_SI_EPS_S uses the paper's mean
+ * pointwise relative change of the cell-average scalar flux, Eq. (Test:Eq3).
+ */
+enum { DGSN_SI_MAXNORM = 0, DGSN_SI_EPS_S = 1 };
+int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion);
 
 /*
  * Gradient of a scalar response J(phi) through the converged source

@@ -16,10 +16,13 @@ error of the node sum relative to the solution size (Eq. (Test:Eq1),
 lambda = 0.2, gamma_1 = 10, gamma_2 = 0.01).  Optimiser: Adam.
 
 Sampling (the paper samples uniformly but does not give ranges):
-  direction uniform on the positive-octant sphere, cubic cells;
+  directions: the canonical-octant directions of the LQ_N set the artifact
+  serves (--order; the paper trains one net per octant, here every octant is
+  reflected onto the canonical one), or uniform on the octant sphere
+  (--order 0); cubic cells;
   tau = sigma_t h log-uniform on [1e-5, 4];
-  inflow faces: half the samples smooth (per-face level U[0, 1] plus a small
-  bilinear variation), half independent U[-0.1, 1] node values;
+  inflow faces: 90 % smooth (per-face level U[0, 1] plus a small bilinear
+  variation), 10 % independent U[-0.1, 1] node values;
   sources h S = tau U[0, 2] (1 + U[-0.3, 0.3] per node); 10 % pure-inflow and
   10 % pure-source problems.
 
@@ -38,13 +41,18 @@ import oracle
 LAMBDA, GAMMA1, GAMMA2 = 0.2, 10.0, 0.01
 
 
-def sample_problems(n, seed):
+def sample_problems(n, seed, order=None, rough=0.1):
     rng = np.random.default_rng(seed)
     om = np.abs(rng.normal(size=(n, 3)))
     om /= np.linalg.norm(om, axis=1, keepdims=True)
+    if order:
+        # directions of the canonical octant of the LQ_N set the net serves
+        oq, _ = oracle.lq_n(order)
+        oq = oq[:len(oq) // 8]
+        om = oq[rng.integers(0, len(oq), size=n)]
     tau = 10.0 ** rng.uniform(-5.0, np.log10(4.0), size=n)
     pin = np.empty((n, 12))
-    smooth = rng.uniform(size=n) < 0.5
+    smooth = rng.uniform(size=n) >= rough
     lev = rng.uniform(0.0, 1.0, size=(n, 3, 1))
     grad = rng.uniform(-0.15, 0.15, size=(n, 3, 2))
     fn = np.arange(4)
@@ -118,10 +126,10 @@ def loss_fn(pred, y):
 
 
 def train(n_train=1_000_000, n_test=20_000, hidden=64, epochs=40, batch=2048, lr=2e-3, seed=3,
-          threads=8, log=print):
+          threads=8, order=8, log=print):
     torch.manual_seed(seed)
     torch.set_num_threads(threads)
-    om, tau, pin, hs = sample_problems(n_train + n_test, seed)
+    om, tau, pin, hs = sample_problems(n_train + n_test, seed, order=order)
     t0 = time.time()
     psi = solve_targets(om, tau, pin, hs)
     x, m = features(om, tau, pin, hs)
@@ -175,9 +183,10 @@ def main():
     ap.add_argument("--hidden", type=int, default=64)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--threads", type=int, default=8)
+    ap.add_argument("--order", type=int, default=8)
     a = ap.parse_args()
     W1, b1, W2, b2, stats = train(n_train=a.n_train, hidden=a.hidden, epochs=a.epochs,
-                                  seed=a.seed, threads=a.threads)
+                                  seed=a.seed, threads=a.threads, order=a.order)
     write_artifact(a.out, W1, b1, W2, b2)
     print(f"wrote {a.out}: {stats}")
 

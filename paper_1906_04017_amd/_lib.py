@@ -21,6 +21,9 @@ DGSN_FP32 = 0
 DGSN_FP64 = 1
 DGSN_GE = 0
 DGSN_ANN = 1
+DGSN_GE_DENSE = 2
+DGSN_SI_MAXNORM = 0
+DGSN_SI_EPS_S = 1
 
 ERROR_NAMES = {
     DGSN_EINVAL: "DGSN_EINVAL", DGSN_ENOMEM: "DGSN_ENOMEM", DGSN_EHIP: "DGSN_EHIP",
@@ -75,6 +78,7 @@ SIGNATURES = {
     "dgsn_ann_infer": (_I, [_VP, _VP, _VP, _LL, _VP]),
     "dgsn_problem_stats": (_I, [_VP, ctypes.POINTER(_LL), _PI, _PD]),
     "dgsn_problem_set_timing": (_I, [_VP, _I]),
+    "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_kernel_time": (_I, [_VP, _PD, _PI]),
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),

@@ -17,9 +17,10 @@ FP32 = _lib.DGSN_FP32
 FP64 = _lib.DGSN_FP64
 GE = _lib.DGSN_GE
 ANN = _lib.DGSN_ANN
+GE_DENSE = _lib.DGSN_GE_DENSE
 
 _PREC = {"fp32": FP32, "fp64": FP64, FP32: FP32, FP64: FP64}
-_SOLVER = {"ge": GE, "ann": ANN, GE: GE, ANN: ANN}
+_SOLVER = {"ge": GE, "ann": ANN, "ge_dense": GE_DENSE, GE: GE, ANN: ANN, GE_DENSE: GE_DENSE}
 _DTYPE = {FP32: torch.float32, FP64: torch.float64}
 
 
@@ -174,6 +175,11 @@ class Problem:
         _lib.check(_lib.load().dgsn_problem_stats(self._h, ctypes.byref(s), ctypes.byref(p),
                                                   ctypes.byref(b)))
         return dict(solves_per_sweep=s.value, n_planes=p.value, algo_bytes_per_sweep=b.value)
+
+    def set_si_criterion(self, criterion):
+        """'maxnorm' (FP64 max-norm relative change) or 'eps_s' (Eq. (Test:Eq3))."""
+        c = {"maxnorm": _lib.DGSN_SI_MAXNORM, "eps_s": _lib.DGSN_SI_EPS_S}[criterion]
+        _lib.check(_lib.load().dgsn_problem_set_si_criterion(self._h, c))
 
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))

@@ -141,64 +141,64 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
 //   m = max(max|psi_in|, max|h S| / (sigma_t h + max_a kappa_a h)),
 // and psi = m * y (m = 0 gives psi = 0): the cell solution is linear in the
 // inflow and source, so the network only sees unit-scale inputs.
-__global__ __launch_bounds__(256) void sweep_plane_ann(PlaneArgs<float> A, int work_lanes)
+__global__ __launch_bounds__(256) void sweep_plane_ann(PlaneArgs<float> A)
 {
-    __shared__ float red[8][256];
+    __shared__ float red[256 * 9];
     __shared__ __bf16 lin[4][64 * 32];
     __shared__ float lout[4][64 * 8];
     const int tid = threadIdx.x;
     AnnRegs R;
     ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
-    const bool in_block = tid < work_lanes;
-    const long long lin_idx = (long long)blockIdx.x * work_lanes + tid;
-    const long long seg = lin_idx / A.Do;
-    const int d = (int)(lin_idx - seg * A.Do);
-    const int g = (int)(seg % A.G);
-    const long long t = seg / A.G;
-    const int o = (int)(t / A.ncp);
-    const int ci = (int)(t - (long long)o * A.ncp);
-    const bool valid = in_block && o < 8;
+    // lanes decode as (direction, group, cell) like the GE kernel; tid < 256,
+    // so q = (tid * ceil(2^16 / div)) >> 16 is the exact quotient
+    const int nc = 256 / (int)(A.Do * A.G);
+    const int work = nc * (int)(A.Do * A.G);
+    const int q1 = (tid * (int)A.mag_do) >> 16;          // tid / Do
+    const int d = tid - q1 * (int)A.Do;
+    const int z = (tid * (int)A.mag_dog) >> 16;          // tid / (Do G)
+    const int g = q1 - z * (int)A.G;
+    const int ci = blockIdx.x * nc + z;
+    const int o = blockIdx.y;
+    const bool valid = tid < work && ci < (int)A.ncp;
 
     float feat[24];
     float mscale = 0.0f, w = 0.0f;
-    int mask = 0, ic = 0, jc = 0, kc = 0, dg = 0;
-    long long c = 0;
+    const int mask = o;
+    uint32_t ic = 0, jc = 0, kc = 0, dg = 0, c = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) feat[k] = 0.0f;
     if (valid) {
         const uint32_t pc = A.cells[ci];
-        ic = pc & 1023;
-        jc = (pc >> 10) & 1023;
+        ic = pc & 1023u;
+        jc = (pc >> 10) & 1023u;
         kc = pc >> 20;
-        mask = o;
-        const int i = (mask & 1) ? A.nx - 1 - ic : ic;
-        const int j = (mask & 2) ? A.ny - 1 - jc : jc;
-        const int k = (mask & 4) ? A.nz - 1 - kc : kc;
-        c = (long long)i + (long long)A.nx * ((long long)j + (long long)A.ny * k);
+        const uint32_t i = (mask & 1) ? A.nx - 1 - ic : ic;
+        const uint32_t j = (mask & 2) ? A.ny - 1 - jc : jc;
+        const uint32_t k = (mask & 4) ? A.nz - 1 - kc : kc;
+        c = i + A.nx * (j + A.ny * k);
         dg = d + A.Do * g;
-        const long long gc = (long long)g * A.ncell + c;
-        const float *dp = A.dir + (long long)(o * A.Do + d) * kDirStride;
+        const uint32_t gc = g * A.ncell + c;
+        const float *dp = A.dir + (o * A.Do + d) * kDirStride;
         float kh[3];
         float kmax = 0.0f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            kh[a] = dp[64 + a] * (36.0f * A.hh);
+            kh[a] = dp[kDirK + a] * A.hh;
             feat[a] = kh[a];
             kmax = fmaxf(kmax, kh[a]);
         }
-        w = dp[67];
+        w = dp[kDirW];
         const float tau = A.sigma_t[gc] * A.hh;
         feat[3] = tau;
-        const long long DG = A.DG;
-        const long long ix_x = (((long long)o * A.nz + kc) * A.ny + jc) * 4 * DG + dg;
-        const long long ix_y = (((long long)o * A.nz + kc) * A.nx + ic) * 4 * DG + dg;
-        const long long ix_z = (((long long)o * A.ny + jc) * A.nx + ic) * 4 * DG + dg;
+        const float *fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
+        const float *fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
+        const float *fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
         float pmax = 0.0f, smax = 0.0f;
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn) {
-            float vx = ic ? A.fx[ix_x + fn * DG] : A.inc[o][0];
-            float vy = jc ? A.fy[ix_y + fn * DG] : A.inc[o][1];
-            float vz = kc ? A.fz[ix_z + fn * DG] : A.inc[o][2];
+            float vx = ic ? fxp[fn] : A.inc[o][0];
+            float vy = jc ? fyp[fn] : A.inc[o][1];
+            float vz = kc ? fzp[fn] : A.inc[o][2];
             vx = kh[0] != 0.0f ? vx : 0.0f;
             vy = kh[1] != 0.0f ? vy : 0.0f;
             vz = kh[2] != 0.0f ? vz : 0.0f;
@@ -227,26 +227,23 @@ __global__ __launch_bounds__(256) void sweep_plane_ann(PlaneArgs<float> A, int w
 #pragma unroll
     for (int n = 0; n < 8; ++n) psi[n] = valid ? mscale * y[n] : 0.0f;
     if (valid) {
-        const long long DG = A.DG;
-        const long long ix_x = (((long long)o * A.nz + kc) * A.ny + jc) * 4 * DG + dg;
-        const long long ix_y = (((long long)o * A.nz + kc) * A.nx + ic) * 4 * DG + dg;
-        const long long ix_z = (((long long)o * A.ny + jc) * A.nx + ic) * 4 * DG + dg;
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
-            A.fx[ix_x + fn * DG] = psi[1 + 2 * fn];
-            A.fy[ix_y + fn * DG] = psi[(fn & 1) + 2 + 4 * (fn >> 1)];
-            A.fz[ix_z + fn * DG] = psi[4 + fn];
-        }
+        float *fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
+        float *fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
+        float *fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
+        fxp[0] = psi[1]; fxp[1] = psi[3]; fxp[2] = psi[5]; fxp[3] = psi[7];
+        fyp[0] = psi[2]; fyp[1] = psi[3]; fyp[2] = psi[6]; fyp[3] = psi[7];
+        fzp[0] = psi[4]; fzp[1] = psi[5]; fzp[2] = psi[6]; fzp[3] = psi[7];
     }
 #pragma unroll
-    for (int n = 0; n < 8; ++n) red[n][tid] = w * psi[n];
+    for (int n = 0; n < 8; ++n) red[tid * 9 + n] = w * psi[n];
     __syncthreads();
     if (valid) {
         const int base = tid - d;
-        for (int n = d; n < 8; n += A.Do) {
+        const uint32_t out = ((o * A.G + g) * A.ncell + c) * 8;
+        for (int n = d; n < 8; n += (int)A.Do) {
             float s = 0.0f;
-            for (int e = 0; e < A.Do; ++e) s += red[n][base + e];
-            A.phi_oct[(((long long)o * A.G + g) * A.ncell + c) * 8 + (n ^ mask)] = s;
+            for (int e = 0; e < (int)A.Do; ++e) s += red[(base + e) * 9 + n];
+            A.phi_oct[out + (n ^ mask)] = s;
         }
     }
 }
@@ -316,11 +313,9 @@ int build_params(dgsn_ann *a)
 
 int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s)
 {
-    const int work = block_size_for(A.Do);
-    const long long total = 8LL * A.ncp * A.G * A.Do;
-    const long long grid = (total + work - 1) / work;
-    if (grid > 0x7fffffffLL) return set_error(DGSN_EUNSUPPORTED, "hyperplane too large");
-    hipLaunchKernelGGL(sweep_plane_ann, dim3((unsigned)grid), dim3(256), 0, s, A, work);
+    const int nc = cells_per_block(A.Do, A.G);
+    const dim3 grid((A.ncp + nc - 1) / nc, 8);
+    hipLaunchKernelGGL(sweep_plane_ann, grid, dim3(256), 0, s, A);
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

@@ -14,6 +14,17 @@
 // The per-direction streaming part S_d = sum_a kappa_a T_a is built once per
 // direction on the host (the paper's observation that a direction only
 // re-weights L and L-, Sec. 2).
+//
+// Mass-inverse form.  M3 is known in closed form and M1^{-1} = [[4,-2],[-2,4]],
+// so the same cell system premultiplied by M3^{-1} reads
+//   (P_d + sigma_t I) psi = S + sum_a kappa_a c_a,
+//   P_d = sum_a kappa_a (I (x) .. Q .. (x) I),  Q = M1^{-1} T = [[3, 1], [-3, 1]],
+//   c_a = 4 psi_in,a on the inflow-face rows of axis a, -2 psi_in,a on the
+//         opposite rows (M1^{-1} e_0 = [4, -2]).
+// P_d couples a node only with itself and its three edge neighbours, so 32
+// of the 64 entries are structurally zero; Gaussian elimination then touches
+// only the entries that become non-zero (the fill), about half the work of
+// the dense elimination, with the same solution.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -141,6 +152,109 @@ __device__ __forceinline__ void ge_solve8(Real a[8][8], Real b[8])
         Real s = b[i];
 #pragma unroll
         for (int j = i + 1; j < 8; ++j) s = fma(-a[i][j], b[j], s);
+        b[i] = s * rinv[i];
+    }
+}
+
+// Structural pattern of Gaussian elimination (natural order) on a matrix
+// whose initial non-zeros are the diagonal and the single-bit neighbours:
+// pattern(k, i, j) is true when entry (i, j) may be non-zero before column k
+// is eliminated (k = 8: the final upper-triangular factor).
+struct CubeFill {
+    unsigned char row[9][8];   // bit j of row[k][i]
+    constexpr CubeFill() : row()
+    {
+        unsigned char cur[8] = {};
+        for (int i = 0; i < 8; ++i) cur[i] = (unsigned char)((1u << i) | (1u << (i ^ 1)) |
+                                                             (1u << (i ^ 2)) | (1u << (i ^ 4)));
+        for (int k = 0; k <= 8; ++k) {
+            for (int i = 0; i < 8; ++i) row[k][i] = cur[i];
+            if (k == 8) break;
+            for (int i = k + 1; i < 8; ++i)
+                if (cur[i] & (1u << k))
+                    for (int j = k + 1; j < 8; ++j)
+                        if (cur[k] & (1u << j)) cur[i] |= (unsigned char)(1u << j);
+        }
+    }
+};
+constexpr CubeFill kCubeFill{};
+
+__host__ __device__ constexpr bool cube_nz(int k, int i, int j)
+{
+    return (kCubeFill.row[k][i] >> j) & 1;
+}
+
+// Gaussian elimination with the same wave-level partial pivoting as
+// ge_solve8, restricted to the structurally non-zero entries of the
+// mass-inverse cell matrix.  Pivoting is only tested against the entries that
+// can be non-zero in the pivot column; the row exchange (never needed for
+// these matrices: the diagonal dominates its column) falls back to the dense
+// exchange, after which the remaining elimination is done densely.
+template <typename Real>
+__device__ __forceinline__ void ge_solve8_cube(Real a[8][8], Real b[8])
+{
+    Real rinv[8];
+    bool dense = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k < 7) {
+            Real cm = Real(0);
+#pragma unroll
+            for (int i = k + 1; i < 8; ++i)
+                if (cube_nz(k, i, k)) cm = fmax(cm, fabs(a[i][k]));
+            const bool need = cm > fabs(a[k][k]);
+            if (__any(need)) {
+                dense = true;
+                int p = k;
+                Real best = fabs(a[k][k]);
+#pragma unroll
+                for (int i = k + 1; i < 8; ++i) {
+                    const bool gt = fabs(a[i][k]) > best;
+                    best = gt ? fabs(a[i][k]) : best;
+                    p = gt ? i : p;
+                }
+#pragma unroll
+                for (int i = k + 1; i < 8; ++i) {
+                    const bool sw = (p == i);
+#pragma unroll
+                    for (int j = k; j < 8; ++j) {
+                        const Real t = a[k][j];
+                        a[k][j] = sw ? a[i][j] : t;
+                        a[i][j] = sw ? t : a[i][j];
+                    }
+                    const Real t = b[k];
+                    b[k] = sw ? b[i] : t;
+                    b[i] = sw ? t : b[i];
+                }
+            }
+        }
+        rinv[k] = recip(a[k][k]);
+        if (dense) {
+#pragma unroll
+            for (int i = k + 1; i < 8; ++i) {
+                const Real l = a[i][k] * rinv[k];
+#pragma unroll
+                for (int j = k + 1; j < 8; ++j) a[i][j] = fma(-l, a[k][j], a[i][j]);
+                b[i] = fma(-l, b[k], b[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = k + 1; i < 8; ++i) {
+                if (!cube_nz(k, i, k)) continue;
+                const Real l = a[i][k] * rinv[k];
+#pragma unroll
+                for (int j = k + 1; j < 8; ++j)
+                    if (cube_nz(k, k, j)) a[i][j] = fma(-l, a[k][j], a[i][j]);
+                b[i] = fma(-l, b[k], b[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+        Real s = b[i];
+#pragma unroll
+        for (int j = i + 1; j < 8; ++j)
+            if (dense || cube_nz(8, i, j)) s = fma(-a[i][j], b[j], s);
         b[i] = s * rinv[i];
     }
 }

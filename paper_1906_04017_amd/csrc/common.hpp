@@ -31,7 +31,11 @@ void clear_error();
 
 // ---- constants -------------------------------------------------------------
 constexpr int kMaxCellsPerAxis = 1024;   // packed (i, j, k) in 10 bits each
-constexpr int kDirStride = 68;           // per direction: S_d[64], kappa[3], weight
+// per direction: S_d[64] (paper form), kappa_a / 36 [3], weight, kappa_a [3], pad
+constexpr int kDirStride = 72;
+constexpr int kDirK36 = 64;
+constexpr int kDirW = 67;
+constexpr int kDirK = 68;
 constexpr int kMaxHidden = 256;
 
 // ---- host-side quadrature ---------------------------------------------------
@@ -74,6 +78,7 @@ struct dgsn_problem {
     int precision = DGSN_FP32;
     int solver = DGSN_GE;
     int store_psi = 0;
+    int si_criterion = DGSN_SI_MAXNORM;
     int n_planes = 0;
     size_t real_size = 4;
     double psi_inc[6] = {0, 0, 0, 0, 0, 0};

@@ -13,10 +13,15 @@ __device__ __forceinline__ double fmax_d(double a, double b) { return a > b ? a 
 template <typename Real>
 struct PlaneArgs {
     const uint32_t *cells;     // packed canonical cells of the plane (i | j<<10 | k<<20)
-    int ncp;                   // number of cells in the plane
-    int nx, ny, nz;
-    int G, Do, DG;
-    long long ncell;
+    uint32_t ncp;              // number of cells in the plane
+    uint32_t nx, ny, nz;
+    uint32_t G, Do, DG;
+    uint32_t ncell;
+    uint32_t fx_o, fx_k, fx_j; // front strides (elements): octant, outer, inner cell index
+    uint32_t fy_o, fy_k, fy_j;
+    uint32_t fz_o, fz_k, fz_j;
+    uint32_t mag_do, mag_dog;  // ceil(2^16 / Do), ceil(2^16 / (Do G)) for lane decoding
+    uint32_t cpt;              // cell tiles visited by one block
     const Real *dir;           // [8][Do][kDirStride]
     const Real *sigma_t;       // [G][ncell]
     const Real *src;           // [G][ncell][8]
@@ -45,10 +50,16 @@ struct ReduceArgs {
 };
 
 int block_size_for(int Do);
+int cells_per_block(int Do, int G);
+int tiles_per_block(int tiles);
 int reduce_blocks_for(long long nv);
 
+// local-system forms of the GE solver
+constexpr int kFormMassInv = 0;   // mass-inverse form, structured elimination
+constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense elimination
+
 template <typename Real>
-int launch_plane(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, hipStream_t s);
+int launch_plane(const PlaneArgs<Real> &A, int form, bool store_psi, bool adjoint, hipStream_t s);
 int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s);
 
 template <typename Real>

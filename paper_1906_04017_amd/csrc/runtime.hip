@@ -97,8 +97,8 @@ int validate_desc(const dgsn_problem_desc *d)
     if (!d->omega || !d->weight) return set_error(DGSN_EINVAL, "omega/weight must not be NULL");
     if (d->precision != DGSN_FP32 && d->precision != DGSN_FP64)
         return set_error(DGSN_EINVAL, "precision must be DGSN_FP32 or DGSN_FP64");
-    if (d->solver != DGSN_GE && d->solver != DGSN_ANN)
-        return set_error(DGSN_EINVAL, "solver must be DGSN_GE or DGSN_ANN");
+    if (d->solver != DGSN_GE && d->solver != DGSN_ANN && d->solver != DGSN_GE_DENSE)
+        return set_error(DGSN_EINVAL, "solver must be DGSN_GE, DGSN_GE_DENSE or DGSN_ANN");
     if (d->solver == DGSN_ANN && d->precision != DGSN_FP32)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
     int count[8] = {0};
@@ -143,7 +143,19 @@ PlaneArgs<Real> plane_args(dgsn_problem *p, const void *src, bool adjoint)
     A.G = p->G;
     A.Do = p->Do;
     A.DG = p->Do * p->G;
-    A.ncell = p->ncell;
+    A.ncell = (uint32_t)p->ncell;
+    const uint32_t f4 = 4u * A.DG;   // one cell's slot: [direction-group][4 face nodes]
+    A.fx_j = f4;
+    A.fx_k = A.ny * f4;
+    A.fx_o = A.nz * A.fx_k;
+    A.fy_j = f4;
+    A.fy_k = A.nx * f4;
+    A.fy_o = A.nz * A.fy_k;
+    A.fz_j = f4;
+    A.fz_k = A.nx * f4;
+    A.fz_o = A.ny * A.fz_k;
+    A.mag_do = (65536u + A.Do - 1) / A.Do;
+    A.mag_dog = (65536u + A.Do * A.G - 1) / (A.Do * A.G);
     A.dir = static_cast<const Real *>(p->d_dir.ptr);
     A.sigma_t = static_cast<const Real *>(p->sigma_t.ptr);
     A.src = static_cast<const Real *>(src);
@@ -192,7 +204,9 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
                 done = true;
             }
         }
-        if (!done) DGSN_TRY(launch_plane<Real>(A, store_psi, adjoint, s));
+        if (!done)
+            DGSN_TRY(launch_plane<Real>(A, p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv,
+                                        store_psi, adjoint, s));
         if (p->timing) {
             DGSN_HIP(hipEventRecord(p->ev[2 * pl + 1], s));
             p->ev_used = pl + 1;
@@ -242,7 +256,7 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     R.src_next = src;
     R.q_cell = static_cast<const Real *>(p->q.ptr);
     R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
-    double r = INFINITY, es = INFINITY, best = INFINITY;
+    double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
     while (it < max_iter) {
@@ -255,18 +269,19 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         es = res[2] / (double)nv;
         if (!std::isfinite(r))
             return set_error(DGSN_EINVAL, "source iteration produced a non-finite residual");
-        if (r < tol) break;
+        crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
+        if (crit < tol) break;
         if (fp32) {
-            if (r < best) { best = r; stall = 0; }
+            if (crit < best) { best = crit; stall = 0; }
             else if (++stall >= 5) break;
         }
     }
     if (iters) *iters = it;
     if (resid) *resid = r;
     if (eps_s) *eps_s = es;
-    if (!(r < tol))
+    if (!(crit < tol))
         return set_error(DGSN_ENOTCONV, "source iteration stopped after %d sweeps at residual %.3e",
-                         it, r);
+                         it, crit);
     return DGSN_OK;
 }
 
@@ -435,8 +450,11 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
         for (int a = 0; a < 3; ++a) kappa[a] = std::fabs(om[a]) / p->h[a];
         double *e = &p->dir_host[(size_t)slot * kDirStride];
         streaming_matrix(kappa, e);
-        for (int a = 0; a < 3; ++a) e[64 + a] = kappa[a] / 36.0;
-        e[67] = d->weight[u];
+        for (int a = 0; a < 3; ++a) {
+            e[kDirK36 + a] = kappa[a] / 36.0;
+            e[kDirK + a] = kappa[a];
+        }
+        e[kDirW] = d->weight[u];
     }
 
     // hyperplane schedule in canonical coordinates
@@ -466,6 +484,19 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     const size_t rs = p->real_size;
     const long long nv = (long long)p->G * p->ncell;
     const long long DG = (long long)p->Do * p->G;
+    // kernels index with 32-bit element offsets: every per-sweep array must
+    // hold fewer than 2^31 elements, and a block holds >= 1 (cell) segment
+    {
+        const long long lim = (1LL << 31) - 1;
+        const long long nmax = std::max(std::max(d->nx, d->ny), d->nz);
+        if (8 * nv * 8 > lim || 8LL * nmax * nmax * 4 * DG > lim)
+            return fail(set_error(DGSN_EUNSUPPORTED,
+                                  "problem too large for 32-bit sweep indexing (%lld cells x %d "
+                                  "groups x %d directions)", p->ncell, p->G, p->D));
+        if (DG > 256)
+            return fail(set_error(DGSN_EUNSUPPORTED,
+                                  "directions per octant x groups must be <= 256 (got %lld)", DG));
+    }
     if ((rc = p->sigma_t.alloc(nv * rs)) || (rc = p->sigma_s.alloc(nv * rs)) ||
         (rc = p->q.alloc(nv * rs)) || (rc = p->src.alloc(nv * 8 * rs)) ||
         (rc = p->phi_oct.alloc(8 * nv * 8 * rs)) ||
@@ -536,11 +567,21 @@ int dgsn_problem_set_solver(dgsn_problem *p, int solver)
 {
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
-    if (solver != DGSN_GE && solver != DGSN_ANN)
-        return set_error(DGSN_EINVAL, "solver must be DGSN_GE or DGSN_ANN");
+    if (solver != DGSN_GE && solver != DGSN_ANN && solver != DGSN_GE_DENSE)
+        return set_error(DGSN_EINVAL, "solver must be DGSN_GE, DGSN_GE_DENSE or DGSN_ANN");
     if (solver == DGSN_ANN && p->precision != DGSN_FP32)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
     p->solver = solver;
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (criterion != DGSN_SI_MAXNORM && criterion != DGSN_SI_EPS_S)
+        return set_error(DGSN_EINVAL, "criterion must be DGSN_SI_MAXNORM or DGSN_SI_EPS_S");
+    p->si_criterion = criterion;
     return DGSN_OK;
 }
 
@@ -619,8 +660,8 @@ int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, d
     if (!p || !gphi) return set_error(DGSN_EINVAL, "problem and dJ_dphi must be set");
     if (!p->store_psi || !p->psi.ptr)
         return set_error(DGSN_EINVAL, "the adjoint needs a problem created with store_psi = 1");
-    if (p->solver != DGSN_GE)
-        return set_error(DGSN_EUNSUPPORTED, "the adjoint is defined for the GE solver");
+    if (p->solver == DGSN_ANN)
+        return set_error(DGSN_EUNSUPPORTED, "the adjoint is defined for the GE solvers");
     if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     return p->precision == DGSN_FP64

@@ -27,152 +27,236 @@ namespace {
 
 constexpr double kInv4Pi = 0.07957747154594767;   // 1 / (4 pi)
 
+// Reflect an 8-node vector between physical and canonical node order
+// (v[n] <-> v[n ^ mask]); mask is uniform over the block, so each stage is a
+// scalar branch around register moves.
 template <typename Real>
-__device__ __forceinline__ void load_dir(const Real *__restrict__ dp, Real sd[64], Real k36[3],
-                                         Real &w)
+__device__ __forceinline__ void reflect8(Real v[8], int mask)
 {
+    if (mask & 1) {
 #pragma unroll
-    for (int e = 0; e < 64; ++e) sd[e] = dp[e];
-    k36[0] = dp[64];
-    k36[1] = dp[65];
-    k36[2] = dp[66];
-    w = dp[67];
+        for (int n = 0; n < 8; n += 2) { const Real t = v[n]; v[n] = v[n + 1]; v[n + 1] = t; }
+    }
+    if (mask & 2) {
+#pragma unroll
+        for (int n = 0; n < 8; ++n)
+            if (!(n & 2)) { const Real t = v[n]; v[n] = v[n + 2]; v[n + 2] = t; }
+    }
+    if (mask & 4) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) { const Real t = v[n]; v[n] = v[n + 4]; v[n + 4] = t; }
+    }
 }
 
-template <typename Real, bool kStorePsi, bool kAdjoint>
+template <typename Real>
+__device__ __forceinline__ void load4(const Real *p, Real v[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = p[e];
+}
+
+template <typename Real>
+__device__ __forceinline__ void store4(Real *p, Real a, Real b, Real c, Real d)
+{
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+    p[3] = d;
+}
+
+// Canonical cell solve of one lane: builds the system in the chosen form from
+// the direction entry, sigma_t, the canonical source and the three inflow
+// faces, and returns psi (canonical node order) in b.
+template <typename Real, int Form>
+__device__ __forceinline__ void cell_solve(const Real *__restrict__ dp, const Real k[3], Real st,
+                                           const Real sc[8], const Real vx[4], const Real vy[4],
+                                           const Real vz[4], Real b[8])
+{
+    Real a[8][8];
+    if (Form == kFormDense) {
+        // paper form: A' = S_d + sigma_t M3, b' = M3 S + sum_a kappa_a Mf psi_a
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[r][c] = fma(st, Real(m3_entry(r, c)), dp[r * 8 + c]);
+        Real m[8], f[4];
+        mass3_216(sc, m);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) b[n] = m[n] * Real(1.0 / 216.0);
+        face_mass(vx, k[0] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[2 * fn] += f[fn];
+        face_mass(vy, k[1] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[(fn & 1) + 4 * (fn >> 1)] += f[fn];
+        face_mass(vz, k[2] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[fn] += f[fn];
+        ge_solve8(a, b);
+    } else {
+        // mass-inverse form: (P_d + sigma_t I) psi = S + sum_a kappa_a c_a
+        const Real base = fma(Real(3), k[0] + k[1] + k[2], st);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[r][c] = Real(0);
+            Real dg = base;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const bool hi = (r >> ax) & 1;
+                if (hi) dg = fma(Real(-2), k[ax], dg);
+                a[r][r ^ (1 << ax)] = hi ? Real(-3) * k[ax] : k[ax];
+            }
+            a[r][r] = dg;
+        }
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int ix = n & 1, iy = (n >> 1) & 1, iz = (n >> 2) & 1;
+            Real v = sc[n];
+            v = fma(ix ? Real(-2) * k[0] : Real(4) * k[0], vx[iy + 2 * iz], v);
+            v = fma(iy ? Real(-2) * k[1] : Real(4) * k[1], vy[ix + 2 * iz], v);
+            v = fma(iz ? Real(-2) * k[2] : Real(4) * k[2], vz[ix + 2 * iy], v);
+            b[n] = v;
+        }
+        ge_solve8_cube(a, b);
+    }
+}
+
+// Inputs of one cell solve, gathered ahead of the solve that uses them.
+template <typename Real>
+struct CellIn {
+    bool ok;
+    uint32_t c, ic, jc, kc;
+    Real st;
+    Real sc[8];
+    Real vx[4], vy[4], vz[4];
+};
+
+template <typename Real>
+__device__ __forceinline__ void gather_cell(const PlaneArgs<Real> &A, int ci, int o, int mask,
+                                            uint32_t g, uint32_t dg, CellIn<Real> &in)
+{
+    in.ok = ci < (int)A.ncp;
+    if (!in.ok) return;
+    const uint32_t pc = A.cells[ci];
+    in.ic = pc & 1023u;
+    in.jc = (pc >> 10) & 1023u;
+    in.kc = pc >> 20;
+    const uint32_t i = (mask & 1) ? A.nx - 1 - in.ic : in.ic;
+    const uint32_t j = (mask & 2) ? A.ny - 1 - in.jc : in.jc;
+    const uint32_t k = (mask & 4) ? A.nz - 1 - in.kc : in.kc;
+    in.c = i + A.nx * (j + A.ny * k);
+    const uint32_t gc = g * A.ncell + in.c;
+    in.st = A.sigma_t[gc];
+    const Real *sp = A.src + gc * 8;
+    load4(sp, in.sc);
+    load4(sp + 4, in.sc + 4);
+    reflect8(in.sc, mask);
+    // inflow faces: boundary value or the upwind neighbour's outflow;
+    // fronts are [octant][outer][inner][direction-group][4 face nodes]
+    if (in.ic) load4(A.fx + (o * A.fx_o + in.kc * A.fx_k + in.jc * A.fx_j + dg * 4), in.vx);
+    else in.vx[0] = in.vx[1] = in.vx[2] = in.vx[3] = A.inc[o][0];
+    if (in.jc) load4(A.fy + (o * A.fy_o + in.kc * A.fy_k + in.ic * A.fy_j + dg * 4), in.vy);
+    else in.vy[0] = in.vy[1] = in.vy[2] = in.vy[3] = A.inc[o][1];
+    if (in.kc) load4(A.fz + (o * A.fz_o + in.jc * A.fz_k + in.ic * A.fz_j + dg * 4), in.vz);
+    else in.vz[0] = in.vz[1] = in.vz[2] = in.vz[3] = A.inc[o][2];
+}
+
+template <typename Real, int Form, bool kStorePsi, bool kAdjoint>
 __global__ __launch_bounds__(256) void sweep_plane_ge(PlaneArgs<Real> A)
 {
-    __shared__ Real red[8][256];
-    __shared__ Real gred[2][256];
-    const int tid = threadIdx.x;
-    const long long lin = (long long)blockIdx.x * blockDim.x + tid;
-    const long long seg = lin / A.Do;
-    const int d = (int)(lin - seg * A.Do);
-    const int g = (int)(seg % A.G);
-    const long long t = seg / A.G;
-    const int o = (int)(t / A.ncp);
-    const int ci = (int)(t - (long long)o * A.ncp);
-    const bool valid = o < 8;
+    // block = (direction, group, cell) lanes, grid = (cell tiles, octant); each
+    // block visits A.cpt tiles of blockDim.z cells, the inputs of the next
+    // tile being loaded before the current one is solved.
+    __shared__ Real red[2][256 * 9];      // [lane][node], padded: conflict-free
+    __shared__ Real gred[256 * 2];
+    const int d = threadIdx.x, g = threadIdx.y;
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int o = blockIdx.y;                         // octant slot (block-uniform)
+    const int mask = kAdjoint ? (o ^ 7) : o;
+    const uint32_t dg = d + A.Do * g;
+    const Real *dp = A.dir + (o * A.Do + d) * kDirStride;
+    const Real w = dp[kDirW];
+    const Real kap[3] = {dp[kDirK], dp[kDirK + 1], dp[kDirK + 2]};
+    const int tile0 = blockIdx.x * A.cpt;
+    const int nc = blockDim.z;
 
-    Real psi[8];
-    Real w = 0;
-    int mask = 0;
-    long long c = 0;
-    Real gs = 0, gq = 0;
-    if (valid) {
-        const uint32_t pc = A.cells[ci];
-        const int ic = pc & 1023, jc = (pc >> 10) & 1023, kc = pc >> 20;
-        mask = kAdjoint ? (o ^ 7) : o;
-        const int i = (mask & 1) ? A.nx - 1 - ic : ic;
-        const int j = (mask & 2) ? A.ny - 1 - jc : jc;
-        const int k = (mask & 4) ? A.nz - 1 - kc : kc;
-        c = (long long)i + (long long)A.nx * ((long long)j + (long long)A.ny * k);
-        const int dg = d + A.Do * g;
-        const long long gc = (long long)g * A.ncell + c;
-
-        Real a[8][8], k36[3];
-        {
-            Real sd[64];
-            load_dir(A.dir + (long long)(o * A.Do + d) * kDirStride, sd, k36, w);
-            const Real st = A.sigma_t[gc];
+    CellIn<Real> nxt;
+    gather_cell(A, tile0 * nc + (int)threadIdx.z, o, mask, g, dg, nxt);
+    for (int t = 0; t < (int)A.cpt; ++t) {
+        const CellIn<Real> cur = nxt;
+        if (t + 1 < (int)A.cpt)
+            gather_cell(A, (tile0 + t + 1) * nc + (int)threadIdx.z, o, mask, g, dg, nxt);
+        Real psi[8];
+        Real gs = 0, gq = 0;
+        if (cur.ok) {
+            cell_solve<Real, Form>(dp, kap, cur.st, cur.sc, cur.vx, cur.vy, cur.vz, psi);
+            // outflow faces into the fronts (same slots, consumed next step)
+            store4(A.fx + (o * A.fx_o + cur.kc * A.fx_k + cur.jc * A.fx_j + dg * 4), psi[1], psi[3],
+                   psi[5], psi[7]);
+            store4(A.fy + (o * A.fy_o + cur.kc * A.fy_k + cur.ic * A.fy_j + dg * 4), psi[2], psi[3],
+                   psi[6], psi[7]);
+            store4(A.fz + (o * A.fz_o + cur.jc * A.fz_k + cur.ic * A.fz_j + dg * 4), psi[4], psi[5],
+                   psi[6], psi[7]);
+            const uint32_t slot = (o * A.Do + d) * A.G + g;
+            if (kStorePsi || (kAdjoint && A.grad_oct)) {
+                Real *pp = A.psi + ((size_t)slot * A.ncell + cur.c) * 8;
+                if (kStorePsi) {
+                    Real ph[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
+                    for (int n = 0; n < 8; ++n) ph[n] = psi[n];
+                    reflect8(ph, mask);
+                    store4(pp, ph[0], ph[1], ph[2], ph[3]);
+                    store4(pp + 4, ph[4], ph[5], ph[6], ph[7]);
+                } else {
+                    // contraction with the stored forward flux of the same
+                    // direction: mu^T M psi, M = V M3 (invariant under reflection)
+                    Real pf[8], m[8];
+                    load4(pp, pf);
+                    load4(pp + 4, pf + 4);
+                    reflect8(pf, mask);
+                    mass3_216(pf, m);
+                    Real s = 0, sm = 0;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) a[r][s] = fma(st, Real(m3_entry(r, s)), sd[r * 8 + s]);
-        }
-        // right-hand side: M3 S (source reflected into canonical order)
-        Real b[8];
-        {
-            Real sc[8], m[8];
-            const Real *sp = A.src + gc * 8;
-#pragma unroll
-            for (int n = 0; n < 8; ++n) sc[n] = sp[n ^ mask];
-            mass3_216(sc, m);
-#pragma unroll
-            for (int n = 0; n < 8; ++n) b[n] = m[n] * Real(1.0 / 216.0);
-        }
-        // inflow faces: boundary value or the upwind neighbour's outflow
-        const long long DG = A.DG;
-        const long long ix_x = (((long long)o * A.nz + kc) * A.ny + jc) * 4 * DG + dg;
-        const long long ix_y = (((long long)o * A.nz + kc) * A.nx + ic) * 4 * DG + dg;
-        const long long ix_z = (((long long)o * A.ny + jc) * A.nx + ic) * 4 * DG + dg;
-        {
-            Real v[4], f[4];
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) v[fn] = ic ? A.fx[ix_x + fn * DG] : A.inc[o][0];
-            face_mass(v, k36[0], f);
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) b[2 * fn] += f[fn];
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) v[fn] = jc ? A.fy[ix_y + fn * DG] : A.inc[o][1];
-            face_mass(v, k36[1], f);
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) b[(fn & 1) + 4 * (fn >> 1)] += f[fn];
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) v[fn] = kc ? A.fz[ix_z + fn * DG] : A.inc[o][2];
-            face_mass(v, k36[2], f);
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn) b[fn] += f[fn];
-        }
-        ge_solve8(a, b);
-#pragma unroll
-        for (int n = 0; n < 8; ++n) psi[n] = b[n];
-        // outflow faces into the fronts (same slots, consumed next step)
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
-            A.fx[ix_x + fn * DG] = psi[1 + 2 * fn];
-            A.fy[ix_y + fn * DG] = psi[(fn & 1) + 2 + 4 * (fn >> 1)];
-            A.fz[ix_z + fn * DG] = psi[4 + fn];
-        }
-        const long long slot = (long long)(o * A.Do + d) * A.G + g;
-        if (kStorePsi) {
-            Real *pp = A.psi + (slot * A.ncell + c) * 8;
-#pragma unroll
-            for (int n = 0; n < 8; ++n) pp[n ^ mask] = psi[n];
-        }
-        if (kAdjoint && A.grad_oct) {
-            // contraction with the stored forward flux of the same direction:
-            // mu^T M psi with M = V M3 (M3 is invariant under the reflection)
-            const Real *pp = A.psi + (slot * A.ncell + c) * 8;
-            Real pf[8], m[8];
-#pragma unroll
-            for (int n = 0; n < 8; ++n) pf[n] = pp[n ^ mask];
-            mass3_216(pf, m);
-            Real s = 0, sm = 0;
-#pragma unroll
-            for (int n = 0; n < 8; ++n) {
-                s = fma(psi[n], m[n], s);
-                sm += psi[n];
+                    for (int n = 0; n < 8; ++n) {
+                        s = fma(psi[n], m[n], s);
+                        sm += psi[n];
+                    }
+                    gs = -w * A.vol * s * Real(1.0 / 216.0);
+                    gq = w * A.vol * sm * Real(0.125);
+                }
             }
-            gs = -w * A.vol * s * Real(1.0 / 216.0);
-            gq = w * A.vol * sm * Real(0.125);
-        }
-    } else {
+        } else {
 #pragma unroll
-        for (int n = 0; n < 8; ++n) psi[n] = 0;
-    }
-    // deterministic per-octant reduction over the directions of the segment
-#pragma unroll
-    for (int n = 0; n < 8; ++n) red[n][tid] = w * psi[n];
-    if (kAdjoint) {
-        gred[0][tid] = gs;
-        gred[1][tid] = gq;
-    }
-    __syncthreads();
-    if (valid) {
-        const int base = tid - d;
-        for (int n = d; n < 8; n += A.Do) {
-            Real s = 0;
-            for (int e = 0; e < A.Do; ++e) s += red[n][base + e];
-            A.phi_oct[(((long long)o * A.G + g) * A.ncell + c) * 8 + (n ^ mask)] = s;
+            for (int n = 0; n < 8; ++n) psi[n] = 0;
         }
-        if (kAdjoint && A.grad_oct) {
-            for (int k2 = d; k2 < 2; k2 += A.Do) {
+        // deterministic per-octant reduction over the directions of the segment
+        Real *rb = red[t & 1];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) rb[tid * 9 + n] = w * psi[n];
+        if (kAdjoint) {
+            gred[tid * 2 + 0] = gs;
+            gred[tid * 2 + 1] = gq;
+        }
+        __syncthreads();
+        if (cur.ok) {
+            const int base = tid - d;
+            const uint32_t out = ((o * A.G + g) * A.ncell + cur.c) * 8;
+            for (int n = d; n < 8; n += (int)A.Do) {
                 Real s = 0;
-                for (int e = 0; e < A.Do; ++e) s += gred[k2][base + e];
-                A.grad_oct[(((long long)o * A.G + g) * A.ncell + c) * 2 + k2] = s;
+                for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
+                A.phi_oct[out + (n ^ mask)] = s;
+            }
+            if (kAdjoint && A.grad_oct) {
+                for (int k2 = d; k2 < 2; k2 += (int)A.Do) {
+                    Real s = 0;
+                    for (int e = 0; e < (int)A.Do; ++e) s += gred[(base + e) * 2 + k2];
+                    A.grad_oct[((o * A.G + g) * A.ncell + cur.c) * 2 + k2] = s;
+                }
             }
         }
+        // red alternates between two buffers; gred is single: fence its reuse
+        if (kAdjoint) __syncthreads();
     }
 }
 
@@ -329,22 +413,44 @@ int grid_for(long long n, int cap = 4096)
 
 int block_size_for(int Do) { return Do * (256 / Do); }
 
-template <typename Real>
-int launch_plane(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, hipStream_t s)
+int cells_per_block(int Do, int G) { return 256 / (Do * G); }
+
+// Tiles visited by one block: enough blocks to keep every CU busy (about
+// 8 per CU over the 8 octants), the rest of the work is looped over so that
+// each lane overlaps the loads of its next cell with the current solve.
+int tiles_per_block(int tiles)
 {
-    const long long total = 8LL * A.ncp * A.G * A.Do;
-    const int bs = block_size_for(A.Do);
-    const long long grid = (total + bs - 1) / bs;
-    if (grid > 0x7fffffffLL) return set_error(DGSN_EUNSUPPORTED, "hyperplane too large");
+    const int target = 256;   // blocks per octant
+    int cpt = tiles / target;
+    if (cpt < 1) cpt = 1;
+    if (cpt > 8) cpt = 8;
+    return cpt;
+}
+
+template <typename Real, int Form>
+void launch_plane_form(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, dim3 grid,
+                       dim3 block, hipStream_t s)
+{
     if (adjoint)
-        hipLaunchKernelGGL((sweep_plane_ge<Real, false, true>), dim3((unsigned)grid), dim3(bs), 0,
-                           s, A);
+        hipLaunchKernelGGL((sweep_plane_ge<Real, Form, false, true>), grid, block, 0, s, A);
     else if (store_psi)
-        hipLaunchKernelGGL((sweep_plane_ge<Real, true, false>), dim3((unsigned)grid), dim3(bs), 0,
-                           s, A);
+        hipLaunchKernelGGL((sweep_plane_ge<Real, Form, true, false>), grid, block, 0, s, A);
     else
-        hipLaunchKernelGGL((sweep_plane_ge<Real, false, false>), dim3((unsigned)grid), dim3(bs),
-                           0, s, A);
+        hipLaunchKernelGGL((sweep_plane_ge<Real, Form, false, false>), grid, block, 0, s, A);
+}
+
+template <typename Real>
+int launch_plane(const PlaneArgs<Real> &A, int form, bool store_psi, bool adjoint, hipStream_t s)
+{
+    const dim3 block(A.Do, A.G, cells_per_block(A.Do, A.G));
+    const int tiles = (int)((A.ncp + block.z - 1) / block.z);
+    PlaneArgs<Real> B = A;
+    B.cpt = tiles_per_block(tiles);
+    const dim3 grid((tiles + B.cpt - 1) / B.cpt, 8);
+    if (form == kFormDense)
+        launch_plane_form<Real, kFormDense>(B, store_psi, adjoint, grid, block, s);
+    else
+        launch_plane_form<Real, kFormMassInv>(B, store_psi, adjoint, grid, block, s);
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }
@@ -393,7 +499,7 @@ int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, 
 int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
 
 #define DGSN_INST(Real)                                                                        \
-    template int launch_plane<Real>(const PlaneArgs<Real> &, bool, bool, hipStream_t);         \
+    template int launch_plane<Real>(const PlaneArgs<Real> &, int, bool, bool, hipStream_t);         \
     template int launch_reduce<Real>(const ReduceArgs<Real> &, int, hipStream_t);              \
     template int launch_build_source<Real>(long long, const Real *, const Real *, const Real *, \
                                            Real *, hipStream_t);                               \
