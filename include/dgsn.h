@@ -162,6 +162,16 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                         double *resid, double *eps_s, void *stream);
 
 /*
+ * Sweep tiling of the GE solvers: with b = 2 every lane solves a 2x2x2 tile
+ * of cells for its (direction, group), keeping the faces between them in
+ * registers (half of the face traffic), one launch per tile hyperplane; with
+ * b = 1 every lane solves one cell per hyperplane launch.  Default 2; the
+ * ANN solver always uses b = 1.  dgsn_problem_autotune picks the faster.
+ */
+int dgsn_problem_set_tile(dgsn_problem *p, int b);
+int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
+
+/*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses
  * the FP64 max-norm relative change; DGSN_SI_EPS_S uses the paper's mean
  * pointwise relative change of the cell-average scalar flux, Eq. (Test:Eq3).

@@ -79,6 +79,8 @@ SIGNATURES = {
     "dgsn_problem_stats": (_I, [_VP, ctypes.POINTER(_LL), _PI, _PD]),
     "dgsn_problem_set_timing": (_I, [_VP, _I]),
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
+    "dgsn_problem_set_tile": (_I, [_VP, _I]),
+    "dgsn_problem_get_tile": (_I, [_VP, _PI]),
     "dgsn_problem_kernel_time": (_I, [_VP, _PD, _PI]),
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),

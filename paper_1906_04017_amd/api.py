@@ -181,6 +181,14 @@ class Problem:
         c = {"maxnorm": _lib.DGSN_SI_MAXNORM, "eps_s": _lib.DGSN_SI_EPS_S}[criterion]
         _lib.check(_lib.load().dgsn_problem_set_si_criterion(self._h, c))
 
+    def set_tile(self, b):
+        _lib.check(_lib.load().dgsn_problem_set_tile(self._h, int(b)))
+
+    def tile(self):
+        b = ctypes.c_int(0)
+        _lib.check(_lib.load().dgsn_problem_get_tile(self._h, ctypes.byref(b)))
+        return b.value
+
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))
 

@@ -184,69 +184,34 @@ __host__ __device__ constexpr bool cube_nz(int k, int i, int j)
     return (kCubeFill.row[k][i] >> j) & 1;
 }
 
-// Gaussian elimination with the same wave-level partial pivoting as
-// ge_solve8, restricted to the structurally non-zero entries of the
-// mass-inverse cell matrix.  Pivoting is only tested against the entries that
-// can be non-zero in the pivot column; the row exchange (never needed for
-// these matrices: the diagonal dominates its column) falls back to the dense
-// exchange, after which the remaining elimination is done densely.
+// Elimination restricted to the structurally non-zero entries of the
+// mass-inverse cell matrix, without row exchanges.  Returns, per lane,
+// whether partial pivoting would have exchanged rows in some column (a
+// structurally possible sub-diagonal entry larger than the pivot); the caller
+// then redoes the wave with the dense, pivoted ge_solve8, so the result is
+// always that of partial pivoting.  For these matrices the diagonal dominates
+// its column and the redo never happens.
 template <typename Real>
-__device__ __forceinline__ void ge_solve8_cube(Real a[8][8], Real b[8])
+__device__ __forceinline__ bool ge_solve8_cube(Real a[8][8], Real b[8])
 {
     Real rinv[8];
-    bool dense = false;
+    bool exchange = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (k < 7) {
-            Real cm = Real(0);
+        Real cm = Real(0);
 #pragma unroll
-            for (int i = k + 1; i < 8; ++i)
-                if (cube_nz(k, i, k)) cm = fmax(cm, fabs(a[i][k]));
-            const bool need = cm > fabs(a[k][k]);
-            if (__any(need)) {
-                dense = true;
-                int p = k;
-                Real best = fabs(a[k][k]);
-#pragma unroll
-                for (int i = k + 1; i < 8; ++i) {
-                    const bool gt = fabs(a[i][k]) > best;
-                    best = gt ? fabs(a[i][k]) : best;
-                    p = gt ? i : p;
-                }
-#pragma unroll
-                for (int i = k + 1; i < 8; ++i) {
-                    const bool sw = (p == i);
-#pragma unroll
-                    for (int j = k; j < 8; ++j) {
-                        const Real t = a[k][j];
-                        a[k][j] = sw ? a[i][j] : t;
-                        a[i][j] = sw ? t : a[i][j];
-                    }
-                    const Real t = b[k];
-                    b[k] = sw ? b[i] : t;
-                    b[i] = sw ? t : b[i];
-                }
-            }
-        }
+        for (int i = k + 1; i < 8; ++i)
+            if (cube_nz(k, i, k)) cm = fmax(cm, fabs(a[i][k]));
+        exchange = exchange || (cm > fabs(a[k][k]));
         rinv[k] = recip(a[k][k]);
-        if (dense) {
 #pragma unroll
-            for (int i = k + 1; i < 8; ++i) {
-                const Real l = a[i][k] * rinv[k];
+        for (int i = k + 1; i < 8; ++i) {
+            if (!cube_nz(k, i, k)) continue;
+            const Real l = a[i][k] * rinv[k];
 #pragma unroll
-                for (int j = k + 1; j < 8; ++j) a[i][j] = fma(-l, a[k][j], a[i][j]);
-                b[i] = fma(-l, b[k], b[i]);
-            }
-        } else {
-#pragma unroll
-            for (int i = k + 1; i < 8; ++i) {
-                if (!cube_nz(k, i, k)) continue;
-                const Real l = a[i][k] * rinv[k];
-#pragma unroll
-                for (int j = k + 1; j < 8; ++j)
-                    if (cube_nz(k, k, j)) a[i][j] = fma(-l, a[k][j], a[i][j]);
-                b[i] = fma(-l, b[k], b[i]);
-            }
+            for (int j = k + 1; j < 8; ++j)
+                if (cube_nz(k, k, j)) a[i][j] = fma(-l, a[k][j], a[i][j]);
+            b[i] = fma(-l, b[k], b[i]);
         }
     }
 #pragma unroll
@@ -254,9 +219,10 @@ __device__ __forceinline__ void ge_solve8_cube(Real a[8][8], Real b[8])
         Real s = b[i];
 #pragma unroll
         for (int j = i + 1; j < 8; ++j)
-            if (dense || cube_nz(8, i, j)) s = fma(-a[i][j], b[j], s);
+            if (cube_nz(8, i, j)) s = fma(-a[i][j], b[j], s);
         b[i] = s * rinv[i];
     }
+    return exchange;
 }
 
 }  // namespace dgsn

@@ -87,6 +87,11 @@ struct dgsn_problem {
     std::vector<int> dir_user;       // octant-sorted slot -> user direction index
     std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64
     std::vector<int> plane_off;      // [n_planes + 1]
+    // tile hyperplane schedule for B x B x B tiles (B = 2): packed tile coords
+    int tile_b = 2;                  // tile edge used by the GE sweep (1 or 2)
+    int n_tplanes2 = 0;
+    std::vector<int> tplane_off2;    // [n_tplanes2 + 1]
+    dgsn::DevBuf d_tiles2;
 
     dgsn::DevBuf d_dir;              // [8][Do][kDirStride] real
     dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major

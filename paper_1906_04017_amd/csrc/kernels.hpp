@@ -63,6 +63,9 @@ int launch_plane(const PlaneArgs<Real> &A, int form, bool store_psi, bool adjoin
 int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s);
 
 template <typename Real>
+int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,
+                hipStream_t s);
+template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);
 template <typename Real>
 int launch_build_source(long long nv, const Real *q, const Real *ss, const Real *phi, Real *src,

@@ -190,12 +190,17 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
             return set_error(DGSN_EUNSUPPORTED, "store_psi is not available with the ANN solver");
         A.ann_params = ann_device_params(p->ann);
     }
-    const uint32_t *cells = static_cast<const uint32_t *>(p->d_plane_cells.ptr);
+    const int form = p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv;
+    const bool tiled = !ann && p->tile_b == 2;
+    const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles2.ptr
+                                                               : p->d_plane_cells.ptr);
+    const std::vector<int> &off = tiled ? p->tplane_off2 : p->plane_off;
+    const int nsteps = tiled ? p->n_tplanes2 : p->n_planes;
     p->last_stream = s;
     p->ev_used = 0;
-    for (int pl = 0; pl < p->n_planes; ++pl) {
-        A.cells = cells + p->plane_off[pl];
-        A.ncp = p->plane_off[pl + 1] - p->plane_off[pl];
+    for (int pl = 0; pl < nsteps; ++pl) {
+        A.cells = cells + off[pl];
+        A.ncp = off[pl + 1] - off[pl];
         if (p->timing) DGSN_HIP(hipEventRecord(p->ev[2 * pl], s));
         bool done = false;
         if constexpr (sizeof(Real) == 4) {
@@ -204,9 +209,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
                 done = true;
             }
         }
-        if (!done)
-            DGSN_TRY(launch_plane<Real>(A, p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv,
-                                        store_psi, adjoint, s));
+        if (!done) DGSN_TRY(launch_tile<Real>(A, form, tiled ? 2 : 1, store_psi, adjoint, s));
         if (p->timing) {
             DGSN_HIP(hipEventRecord(p->ev[2 * pl + 1], s));
             p->ev_used = pl + 1;
@@ -472,6 +475,30 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     }
     p->plane_off[p->n_planes] = (int)cells.size();
 
+    // 2 x 2 x 2 tile hyperplanes
+    {
+        const int T[3] = {(d->nx + 1) / 2, (d->ny + 1) / 2, (d->nz + 1) / 2};
+        p->n_tplanes2 = T[0] + T[1] + T[2] - 2;
+        std::vector<uint32_t> tl;
+        tl.reserve((size_t)T[0] * T[1] * T[2]);
+        p->tplane_off2.assign(p->n_tplanes2 + 1, 0);
+        for (int pl = 0; pl < p->n_tplanes2; ++pl) {
+            p->tplane_off2[pl] = (int)tl.size();
+            for (int k = 0; k < T[2]; ++k)
+                for (int j = 0; j < T[1]; ++j) {
+                    const int i = pl - j - k;
+                    if (i < 0 || i >= T[0]) continue;
+                    tl.push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
+                }
+        }
+        p->tplane_off2[p->n_tplanes2] = (int)tl.size();
+        int rc2 = p->d_tiles2.alloc(tl.size() * sizeof(uint32_t));
+        if (rc2) return fail(rc2);
+        if (hipMemcpy(p->d_tiles2.ptr, tl.data(), tl.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_error(DGSN_EHIP, "upload of the tile schedule failed"));
+    }
+
     int rc;
     if ((rc = p->d_plane_cells.alloc(cells.size() * sizeof(uint32_t)))) return fail(rc);
     if (hipMemcpy(p->d_plane_cells.ptr, cells.data(), cells.size() * sizeof(uint32_t),
@@ -575,6 +602,23 @@ int dgsn_problem_set_solver(dgsn_problem *p, int solver)
     return DGSN_OK;
 }
 
+int dgsn_problem_set_tile(dgsn_problem *p, int b)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (b != 1 && b != 2) return set_error(DGSN_EINVAL, "tile edge must be 1 or 2");
+    p->tile_b = b;
+    return DGSN_OK;
+}
+
+int dgsn_problem_get_tile(const dgsn_problem *p, int *b)
+{
+    clear_error();
+    if (!p || !b) return set_error(DGSN_EINVAL, "problem and b must be set");
+    *b = p->tile_b;
+    return DGSN_OK;
+}
+
 int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion)
 {
     clear_error();
@@ -591,7 +635,7 @@ int dgsn_problem_set_timing(dgsn_problem *p, int enable)
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     if (enable && p->ev.empty()) {
-        p->ev.assign(2 * p->n_planes, nullptr);
+        p->ev.assign(2 * std::max(p->n_planes, p->n_tplanes2), nullptr);
         for (auto &e : p->ev) DGSN_HIP(hipEventCreate(&e));
     }
     p->timing = enable ? 1 : 0;

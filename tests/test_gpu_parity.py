@@ -123,14 +123,16 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("tile", [1, 2])
 @pytest.mark.parametrize("solver", ["ge", "ge_dense"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in RAGGED])
-def test_sweep_ragged_meshes(api, ctx, precision, case, solver):
+def test_sweep_ragged_meshes(api, ctx, precision, case, solver, tile):
     n, L, order, G = case
-    print_case("sweep", n=n, order=order, G=G, precision=precision, solver=solver)
+    print_case("sweep", n=n, order=order, G=G, precision=precision, solver=solver, tile=tile)
     p = inputs.random_problem(n, order, G, seed=hash(case) % 1000, length=L)
     prob = gpu_problem(api, ctx, p, precision, solver=solver)
+    prob.set_tile(tile)
     S = nodal_source(p, seed=7)
     dt = torch.float64 if precision == "fp64" else torch.float32
     phi = prob.sweep(torch.tensor(S, dtype=dt, device="cuda")).cpu().numpy()
@@ -223,16 +225,18 @@ def test_source_iteration_resume_from_saved_phi(api, ctx):
 # adjoint
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("tile", [1, 2])
 @pytest.mark.parametrize("solver", ["ge", "ge_dense"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
-def test_adjoint_matches_oracle(api, ctx, precision, tol, solver):
-    p = inputs.adjoint_box(n=6, groups=2, seed=4, box=(2, 4))
-    print_case("adjoint", name=p["name"], precision=precision, solver=solver)
+def test_adjoint_matches_oracle(api, ctx, precision, tol, solver, tile):
+    p = inputs.adjoint_box(n=7, groups=2, seed=4, box=(2, 5))
+    print_case("adjoint", name=p["name"], precision=precision, solver=solver, tile=tile)
     prob = gpu_problem(api, ctx, p, precision, solver=solver, store_psi=True)
+    prob.set_tile(tile)
     si_tol = 1e-13 if precision == "fp64" else 1e-7
     phi, info = prob.source_iterate(tol=si_tol, max_iter=1000, allow_notconv=True)
     V = np.prod(np.array(p["length"]) / np.array(p["n"]))
-    g = np.zeros((p["groups"], 216, 8))
+    g = np.zeros((p["groups"], 343, 8))
     g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
     dt = torch.float64 if precision == "fp64" else torch.float32
     gst, gq, ainfo = prob.adjoint(torch.tensor(g, dtype=dt, device="cuda"), tol=si_tol,
