@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (memory-counter scale)")
     ap.add_argument("--skip-extras", action="store_true",
                     help="skip the FP64 and the ANN-vs-GE side measurements")
     ap.add_argument("--ann", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -50,8 +52,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def copy_calibration(mib):
+    """Plain device copy of a known size, for scaling memory counters."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {mib} MiB (read {mib} MiB + write {mib} MiB each)")
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(groups, directions or KBA slabs would shard across GPUs; see DESIGN.md)",
@@ -68,6 +85,8 @@ def main():
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
     prob.set_inflow(p["psi_inc"])
+    tile, ms1, ms2 = prob.autotune()
+    log(f"autotune: tile {tile} (one sweep {ms1:.3f} ms with 1x1x1, {ms2:.3f} ms with 2x2x2)")
     st = prob.stats()
     solves = st["solves_per_sweep"]
     phi = torch.zeros((p["groups"], prob.ncell, 8), dtype=torch.float32, device="cuda")
@@ -102,7 +121,8 @@ def main():
     achieved = st["algo_bytes_per_sweep"] / (sweep_kernel_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "sweep_plane_ge<float>", "launches_per_sweep": kern_launches // args.steps,
+            "kernel": f"sweep_tile_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles>",
+            "launches_per_sweep": kern_launches // args.steps,
             "kernel_ms_per_sweep": round(sweep_kernel_ms, 4),
             "avg_launch_us": round(1e3 * kern_ms / max(kern_launches, 1), 3),
             "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
@@ -148,6 +168,7 @@ def plain_fp64(api, ctx, p, reps=3):
     om, w = api.quadrature_ls(p["order"])
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp64")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.autotune()
     src = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float64,
                        device="cuda")
     dt, _ = time_sweeps(prob, src, reps)
@@ -177,6 +198,7 @@ def ann_vs_ge(api, ctx, ann_path, n=128, reps=3):
         prob.set_inflow(p["psi_inc"])
         if solver == "ann":
             prob.set_ann(ann)
+        prob.autotune()
         dt, phi = time_sweeps(prob, S, reps)
         solves = prob.stats()["solves_per_sweep"]
         out[f"{solver}_solves_per_s"] = solves / dt

@@ -165,11 +165,20 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
  * Sweep tiling of the GE solvers: with b = 2 every lane solves a 2x2x2 tile
  * of cells for its (direction, group), keeping the faces between them in
  * registers (half of the face traffic), one launch per tile hyperplane; with
- * b = 1 every lane solves one cell per hyperplane launch.  Default 2; the
- * ANN solver always uses b = 1.  dgsn_problem_autotune picks the faster.
+ * b = 1 every lane solves one cell per hyperplane launch.  Default 2 for
+ * FP32 problems, 1 for FP64; dgsn_problem_autotune picks the faster.
  */
 int dgsn_problem_set_tile(dgsn_problem *p, int b);
 int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
+
+/*
+ * Autotuner: times one sweep of the problem with each tile edge (on its
+ * internal buffers; user arrays are not touched), keeps the faster, and
+ * returns the choice and both times in ms (any pointer may be NULL).
+ * Synchronizes stream.
+ */
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_tile1,
+                          double *ms_tile2);
 
 /*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses
@@ -242,16 +251,30 @@ int dgsn_problem_set_timing(dgsn_problem *p, int enable);
 int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
 
 /*
- * Batched persistent execution of many independent problems (each FP32, any
- * size, quadrature, group count and solver) in one launch, captured in a HIP
- * graph.  probs must stay alive while the batch exists.
+ * Batched execution of many independent problems (FP32, any mesh size,
+ * quadrature and group count, solver DGSN_GE or DGSN_ANN per problem): one
+ * sweep of every problem in a single HIP-graph launch.  Step t of the graph
+ * is one batched kernel that advances every problem that still has a step t
+ * (a tile hyperplane for GE, a cell hyperplane for ANN); the per-problem
+ * octant reductions follow.  Not in the paper.
+ * dgsn_batch_create: probs must stay alive while the batch exists; each
+ *   problem's materials, inflow and ANN are read at run time.
+ * dgsn_batch_set_io: device src / phi of problem `index`, layouts as in
+ *   dgsn_sweep; must be set for every problem before the first run.
+ * dgsn_batch_set_tiles: per-problem GE tile edge (1 or 2), host [n].
+ * dgsn_batch_autotune: times the batch with candidate tile assignments (all
+ *   2, all 1, 2 for meshes of >= 32^3 cells) and keeps the fastest; returns
+ *   its time in ms.  Runs the batch several times; synchronizes stream.
+ * dgsn_batch_run: enqueues the graph on stream.
+ * dgsn_batch_latencies_us: per-problem time from the start of the last run to
+ *   the end of that problem's last sweep step, device wall clock, host [n];
+ *   synchronizes the device.
  */
 int dgsn_batch_create(dgsn_ctx *ctx, dgsn_problem *const *probs, int n, dgsn_batch **out);
-/* One sweep of every problem; src/phi are taken from each problem's own
-   internal buffers (set with dgsn_batch_set_io). */
 int dgsn_batch_set_io(dgsn_batch *b, int index, const void *src, void *phi);
+int dgsn_batch_set_tiles(dgsn_batch *b, const int *tile_edges);
+int dgsn_batch_autotune(dgsn_batch *b, void *stream, double *best_ms);
 int dgsn_batch_run(dgsn_batch *b, void *stream);
-/* Per-problem completion latency of the last run in microseconds, host [n]. */
 int dgsn_batch_latencies_us(const dgsn_batch *b, double *out);
 int dgsn_batch_destroy(dgsn_batch *b);
 

@@ -81,9 +81,12 @@ SIGNATURES = {
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_set_tile": (_I, [_VP, _I]),
     "dgsn_problem_get_tile": (_I, [_VP, _PI]),
+    "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PD, _PD]),
     "dgsn_problem_kernel_time": (_I, [_VP, _PD, _PI]),
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),
+    "dgsn_batch_set_tiles": (_I, [_VP, _PI]),
+    "dgsn_batch_autotune": (_I, [_VP, _VP, _PD]),
     "dgsn_batch_run": (_I, [_VP, _VP]),
     "dgsn_batch_latencies_us": (_I, [_VP, _PD]),
     "dgsn_batch_destroy": (_I, [_VP]),

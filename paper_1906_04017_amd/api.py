@@ -189,6 +189,17 @@ class Problem:
         _lib.check(_lib.load().dgsn_problem_get_tile(self._h, ctypes.byref(b)))
         return b.value
 
+    def autotune(self):
+        """Time one sweep with each tile edge and keep the faster;
+        returns (tile, ms_tile1, ms_tile2)."""
+        t = ctypes.c_int(0)
+        a = ctypes.c_double(0)
+        b = ctypes.c_double(0)
+        _lib.check(_lib.load().dgsn_problem_autotune(self._h, _stream(self.ctx.device),
+                                                     ctypes.byref(t), ctypes.byref(a),
+                                                     ctypes.byref(b)))
+        return t.value, a.value, b.value
+
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))
 
@@ -283,3 +294,49 @@ class TransportSolve(torch.autograd.Function):
         gst, gq, _ = ctx.problem.adjoint(grad_phi.contiguous(), tol=ctx.tol,
                                          max_iter=ctx.max_iter, allow_notconv=True)
         return None, gst, gq, None, None, None
+
+
+class Batch:
+    """One sweep of many independent FP32 problems in one HIP-graph launch."""
+
+    def __init__(self, ctx, problems):
+        self.ctx = ctx
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().dgsn_batch_create(ctx._h, arr, len(self.problems),
+                                                 ctypes.byref(self._h)))
+        self._io = [None] * len(self.problems)
+
+    def set_io(self, index, src, phi):
+        self._io[index] = (src, phi)   # keep the tensors alive
+        _lib.check(_lib.load().dgsn_batch_set_io(self._h, int(index), _ptr(src), _ptr(phi)))
+
+    def set_tiles(self, tiles):
+        arr = (ctypes.c_int * len(self.problems))(*[int(t) for t in tiles])
+        _lib.check(_lib.load().dgsn_batch_set_tiles(self._h, arr))
+
+    def autotune(self):
+        ms = ctypes.c_double(0)
+        _lib.check(_lib.load().dgsn_batch_autotune(self._h, _stream(self.ctx.device),
+                                                   ctypes.byref(ms)))
+        return ms.value
+
+    def run(self):
+        _lib.check(_lib.load().dgsn_batch_run(self._h, _stream(self.ctx.device)))
+
+    def latencies_us(self):
+        out = np.zeros(len(self.problems))
+        _lib.check(_lib.load().dgsn_batch_latencies_us(self._h, out.ctypes.data_as(_lib._PD)))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.load().dgsn_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

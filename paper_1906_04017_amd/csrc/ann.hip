@@ -20,101 +20,18 @@
 #include <cstring>
 #include <vector>
 
-#include "cell.hpp"
-#include "common.hpp"
-#include "kernels.hpp"
+#include "ann_body.hpp"
 
 namespace dgsn {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 namespace {
-
-constexpr int kParamW1 = 0;                  // [4][64] bf16x8
-constexpr int kParamW2 = 4 * 64 * 16;        // [2][64] bf16x8
-constexpr int kParamB1 = kParamW2 + 2 * 64 * 16;  // [4][64] f32x4
-constexpr int kParamB2 = kParamB1 + 4 * 64 * 16;  // [64] f32x4
-constexpr int kParamBytes = kParamB2 + 64 * 16;
-constexpr int kHiddenPad = 64;
-
-struct AnnRegs {
-    bf16x8 w1[4];
-    bf16x8 w2[2];
-    f32x4 b1[4];
-    f32x4 b2;
-};
-
-__device__ __forceinline__ void ann_load(const unsigned char *__restrict__ prm, int lane,
-                                         AnnRegs &R)
-{
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        R.w1[m] = *reinterpret_cast<const bf16x8 *>(prm + kParamW1 + (m * 64 + lane) * 16);
-        R.b1[m] = *reinterpret_cast<const f32x4 *>(prm + kParamB1 + (m * 64 + lane) * 16);
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-        R.w2[c] = *reinterpret_cast<const bf16x8 *>(prm + kParamW2 + (c * 64 + lane) * 16);
-    R.b2 = *reinterpret_cast<const f32x4 *>(prm + kParamB2 + lane * 16);
-}
-
-// Evaluates the network for the 64 samples held by the 64 lanes of the wave
-// (one sample per lane, 24 FP32 features).  lds_in: 64*32 bf16 of this wave,
-// lds_out: 64*8 floats of this wave.  Must be reached by every thread of the
-// block (it synchronises the block).
-__device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
-                                         __bf16 *lds_in, float *lds_out, float out[8])
-{
-    const int lane = threadIdx.x & 63;
-    {
-        bf16x8 v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int f = 8 * q + e;
-                v[q][e] = (__bf16)(f < 24 ? feat[f] : 0.0f);
-            }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(lds_in + lane * 32 + 8 * q) = v[q];
-    }
-    __syncthreads();
-    const int col = lane & 15, grp = lane >> 4;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(lds_in + (16 * b + col) * 32 + 8 * grp);
-        f32x4 h[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            h[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w1[m], xb, R.b1[m], 0, 0, 0);
-        bf16x8 hb[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = h[2 * c + (e >> 2)][e & 3];
-                hb[c][e] = (__bf16)(v > 0.0f ? v : 0.0f);
-            }
-        f32x4 y = R.b2;
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[0], hb[0], y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[1], hb[1], y, 0, 0, 0);
-        if (grp < 2) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) lds_out[(16 * b + col) * 8 + 4 * grp + r] = y[r];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = lds_out[lane * 8 + k];
-}
 
 __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__restrict__ prm,
                                                         const float *__restrict__ x,
                                                         float *__restrict__ y, long long n)
 {
-    __shared__ __bf16 lin[4][64 * 32];
-    __shared__ float lout[4][64 * 8];
+    __shared__ __bf16 lin[4 * 64 * 32];
+    __shared__ float lout[4 * 64 * 8];
     AnnRegs R;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     ann_load(prm, lane, R);
@@ -124,7 +41,7 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
         float f[24], o[8];
 #pragma unroll
         for (int k = 0; k < 24; ++k) f[k] = s < n ? x[s * 24 + k] : 0.0f;
-        ann_wave(R, f, lin[wv], lout[wv], o);
+        ann_wave(R, f, lin + wv * (64 * 32), lout + wv * (64 * 8), o);
         if (s < n) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
@@ -141,113 +58,6 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
 //   m = max(max|psi_in|, max|h S| / (sigma_t h + max_a kappa_a h)),
 // and psi = m * y (m = 0 gives psi = 0): the cell solution is linear in the
 // inflow and source, so the network only sees unit-scale inputs.
-__global__ __launch_bounds__(256) void sweep_plane_ann(PlaneArgs<float> A)
-{
-    __shared__ float red[256 * 9];
-    __shared__ __bf16 lin[4][64 * 32];
-    __shared__ float lout[4][64 * 8];
-    const int tid = threadIdx.x;
-    AnnRegs R;
-    ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
-    // lanes decode as (direction, group, cell) like the GE kernel; tid < 256,
-    // so q = (tid * ceil(2^16 / div)) >> 16 is the exact quotient
-    const int nc = 256 / (int)(A.Do * A.G);
-    const int work = nc * (int)(A.Do * A.G);
-    const int q1 = (tid * (int)A.mag_do) >> 16;          // tid / Do
-    const int d = tid - q1 * (int)A.Do;
-    const int z = (tid * (int)A.mag_dog) >> 16;          // tid / (Do G)
-    const int g = q1 - z * (int)A.G;
-    const int ci = blockIdx.x * nc + z;
-    const int o = blockIdx.y;
-    const bool valid = tid < work && ci < (int)A.ncp;
-
-    float feat[24];
-    float mscale = 0.0f, w = 0.0f;
-    const int mask = o;
-    uint32_t ic = 0, jc = 0, kc = 0, dg = 0, c = 0;
-#pragma unroll
-    for (int k = 0; k < 24; ++k) feat[k] = 0.0f;
-    if (valid) {
-        const uint32_t pc = A.cells[ci];
-        ic = pc & 1023u;
-        jc = (pc >> 10) & 1023u;
-        kc = pc >> 20;
-        const uint32_t i = (mask & 1) ? A.nx - 1 - ic : ic;
-        const uint32_t j = (mask & 2) ? A.ny - 1 - jc : jc;
-        const uint32_t k = (mask & 4) ? A.nz - 1 - kc : kc;
-        c = i + A.nx * (j + A.ny * k);
-        dg = d + A.Do * g;
-        const uint32_t gc = g * A.ncell + c;
-        const float *dp = A.dir + (o * A.Do + d) * kDirStride;
-        float kh[3];
-        float kmax = 0.0f;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            kh[a] = dp[kDirK + a] * A.hh;
-            feat[a] = kh[a];
-            kmax = fmaxf(kmax, kh[a]);
-        }
-        w = dp[kDirW];
-        const float tau = A.sigma_t[gc] * A.hh;
-        feat[3] = tau;
-        const float *fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
-        const float *fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
-        const float *fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
-        float pmax = 0.0f, smax = 0.0f;
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
-            float vx = ic ? fxp[fn] : A.inc[o][0];
-            float vy = jc ? fyp[fn] : A.inc[o][1];
-            float vz = kc ? fzp[fn] : A.inc[o][2];
-            vx = kh[0] != 0.0f ? vx : 0.0f;
-            vy = kh[1] != 0.0f ? vy : 0.0f;
-            vz = kh[2] != 0.0f ? vz : 0.0f;
-            feat[4 + fn] = vx;
-            feat[8 + fn] = vy;
-            feat[12 + fn] = vz;
-            pmax = fmaxf(pmax, fmaxf(fabsf(vx), fmaxf(fabsf(vy), fabsf(vz))));
-        }
-        const float *sp = A.src + gc * 8;
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            const float hs = A.hh * sp[n ^ mask];
-            feat[16 + n] = hs;
-            smax = fmaxf(smax, fabsf(hs));
-        }
-        float m = pmax;
-        const float den = tau + kmax;
-        if (den > 0.0f) m = fmaxf(m, smax / den);
-        mscale = m;
-        const float rm = m > 0.0f ? 1.0f / m : 0.0f;
-#pragma unroll
-        for (int k = 4; k < 24; ++k) feat[k] *= rm;
-    }
-    float y[8], psi[8];
-    ann_wave(R, feat, lin[tid >> 6], lout[tid >> 6], y);
-#pragma unroll
-    for (int n = 0; n < 8; ++n) psi[n] = valid ? mscale * y[n] : 0.0f;
-    if (valid) {
-        float *fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
-        float *fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
-        float *fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
-        fxp[0] = psi[1]; fxp[1] = psi[3]; fxp[2] = psi[5]; fxp[3] = psi[7];
-        fyp[0] = psi[2]; fyp[1] = psi[3]; fyp[2] = psi[6]; fyp[3] = psi[7];
-        fzp[0] = psi[4]; fzp[1] = psi[5]; fzp[2] = psi[6]; fzp[3] = psi[7];
-    }
-#pragma unroll
-    for (int n = 0; n < 8; ++n) red[tid * 9 + n] = w * psi[n];
-    __syncthreads();
-    if (valid) {
-        const int base = tid - d;
-        const uint32_t out = ((o * A.G + g) * A.ncell + c) * 8;
-        for (int n = d; n < 8; n += (int)A.Do) {
-            float s = 0.0f;
-            for (int e = 0; e < (int)A.Do; ++e) s += red[(base + e) * 9 + n];
-            A.phi_oct[out + (n ^ mask)] = s;
-        }
-    }
-}
-
 // ---- artifact I/O ----------------------------------------------------------
 
 uint32_t crc32_ieee(const unsigned char *p, size_t n)
@@ -310,15 +120,6 @@ int build_params(dgsn_ann *a)
 }
 
 }  // namespace
-
-int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s)
-{
-    const int nc = cells_per_block(A.Do, A.G);
-    const dim3 grid((A.ncp + nc - 1) / nc, 8);
-    hipLaunchKernelGGL(sweep_plane_ann, grid, dim3(256), 0, s, A);
-    DGSN_HIP(hipGetLastError());
-    return DGSN_OK;
-}
 
 const void *ann_device_params(const dgsn_ann *a) { return a ? a->d_params.ptr : nullptr; }
 

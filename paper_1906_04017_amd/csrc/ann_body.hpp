@@ -1,0 +1,93 @@
+// Device code of the shallow-ANN local solver shared by the ANN kernels and
+// the batched kernel (see ann.hip for the matrix-core mapping).
+#pragma once
+
+#include "cell.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dgsn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+
+constexpr int kParamW1 = 0;                  // [4][64] bf16x8
+constexpr int kParamW2 = 4 * 64 * 16;        // [2][64] bf16x8
+constexpr int kParamB1 = kParamW2 + 2 * 64 * 16;  // [4][64] f32x4
+constexpr int kParamB2 = kParamB1 + 4 * 64 * 16;  // [64] f32x4
+constexpr int kParamBytes = kParamB2 + 64 * 16;
+constexpr int kHiddenPad = 64;
+
+struct AnnRegs {
+    bf16x8 w1[4];
+    bf16x8 w2[2];
+    f32x4 b1[4];
+    f32x4 b2;
+};
+
+__device__ __forceinline__ void ann_load(const unsigned char *__restrict__ prm, int lane,
+                                         AnnRegs &R)
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        R.w1[m] = *reinterpret_cast<const bf16x8 *>(prm + kParamW1 + (m * 64 + lane) * 16);
+        R.b1[m] = *reinterpret_cast<const f32x4 *>(prm + kParamB1 + (m * 64 + lane) * 16);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+        R.w2[c] = *reinterpret_cast<const bf16x8 *>(prm + kParamW2 + (c * 64 + lane) * 16);
+    R.b2 = *reinterpret_cast<const f32x4 *>(prm + kParamB2 + lane * 16);
+}
+
+// Evaluates the network for the 64 samples held by the 64 lanes of the wave
+// (one sample per lane, 24 FP32 features).  lds_in: 64*32 bf16 of this wave,
+// lds_out: 64*8 floats of this wave.  Must be reached by every thread of the
+// block (it synchronises the block).
+__device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
+                                         __bf16 *lds_in, float *lds_out, float out[8])
+{
+    const int lane = threadIdx.x & 63;
+    {
+        bf16x8 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int f = 8 * q + e;
+                v[q][e] = (__bf16)(f < 24 ? feat[f] : 0.0f);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(lds_in + lane * 32 + 8 * q) = v[q];
+    }
+    __syncthreads();
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(lds_in + (16 * b + col) * 32 + 8 * grp);
+        f32x4 h[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            h[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w1[m], xb, R.b1[m], 0, 0, 0);
+        bf16x8 hb[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = h[2 * c + (e >> 2)][e & 3];
+                hb[c][e] = (__bf16)(v > 0.0f ? v : 0.0f);
+            }
+        f32x4 y = R.b2;
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[0], hb[0], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[1], hb[1], y, 0, 0, 0);
+        if (grp < 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds_out[(16 * b + col) * 8 + 4 * grp + r] = y[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = lds_out[lane * 8 + k];
+}
+
+}  // namespace dgsn

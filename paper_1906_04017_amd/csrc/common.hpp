@@ -9,6 +9,8 @@
 
 #include "../../include/dgsn.h"
 
+struct dgsn_problem;
+
 namespace dgsn {
 
 // ---- error reporting -------------------------------------------------------
@@ -42,6 +44,7 @@ constexpr int kMaxHidden = 256;
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
 
 const void *ann_device_params(const dgsn_ann *a);
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2]);
 
 // ---- device allocation helper ------------------------------------------------
 struct DevBuf {

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+struct dgsn_problem;
+
 namespace dgsn {
 
 __device__ __forceinline__ double fmax_d(double a, double b) { return a > b ? a : b; }
@@ -21,7 +23,6 @@ struct PlaneArgs {
     uint32_t fy_o, fy_k, fy_j;
     uint32_t fz_o, fz_k, fz_j;
     uint32_t mag_do, mag_dog;  // ceil(2^16 / Do), ceil(2^16 / (Do G)) for lane decoding
-    uint32_t cpt;              // cell tiles visited by one block
     const Real *dir;           // [8][Do][kDirStride]
     const Real *sigma_t;       // [G][ncell]
     const Real *src;           // [G][ncell][8]
@@ -50,17 +51,19 @@ struct ReduceArgs {
 };
 
 int block_size_for(int Do);
+
+// helpers of the batched path (runtime.hip)
+PlaneArgs<float> batch_plane_args(dgsn_problem *p, const void *src);
+int batch_reduce(dgsn_problem *p, void *phi, hipStream_t s);
 int cells_per_block(int Do, int G);
-int tiles_per_block(int tiles);
 int reduce_blocks_for(long long nv);
 
 // local-system forms of the GE solver
 constexpr int kFormMassInv = 0;   // mass-inverse form, structured elimination
 constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense elimination
+constexpr int kFormAnn = 2;       // the shallow network in place of assembly + elimination
 
-template <typename Real>
-int launch_plane(const PlaneArgs<Real> &A, int form, bool store_psi, bool adjoint, hipStream_t s);
-int launch_plane_ann(const PlaneArgs<float> &A, hipStream_t s);
+int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 
 template <typename Real>
 int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,

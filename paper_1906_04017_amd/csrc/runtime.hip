@@ -191,7 +191,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         A.ann_params = ann_device_params(p->ann);
     }
     const int form = p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv;
-    const bool tiled = !ann && p->tile_b == 2;
+    const bool tiled = p->tile_b == 2;
     const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles2.ptr
                                                                : p->d_plane_cells.ptr);
     const std::vector<int> &off = tiled ? p->tplane_off2 : p->plane_off;
@@ -205,7 +205,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         bool done = false;
         if constexpr (sizeof(Real) == 4) {
             if (ann) {
-                DGSN_TRY(launch_plane_ann(A, s));
+                DGSN_TRY(launch_tile_ann(A, tiled ? 2 : 1, s));
                 done = true;
             }
         }
@@ -348,9 +348,76 @@ dgsn_problem::~dgsn_problem()
         if (e) (void)hipEventDestroy(e);
 }
 
+namespace dgsn {
+
+PlaneArgs<float> batch_plane_args(dgsn_problem *p, const void *src)
+{
+    PlaneArgs<float> A = plane_args<float>(p, src, false);
+    if (p->solver == DGSN_ANN) A.ann_params = ann_device_params(p->ann);
+    return A;
+}
+
+int batch_reduce(dgsn_problem *p, void *phi, hipStream_t s)
+{
+    ReduceArgs<float> R = reduce_args<float>(p, phi);
+    return launch_reduce<float>(R, p->red_blocks, s);
+}
+
+// Time one sweep of the problem with each tile edge on its internal source
+// buffer and keep the faster (ties keep 2).  The problem's outputs are not
+// touched (only its internal partials and fronts).
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2])
+{
+    if (p->solver == DGSN_ANN && !p->ann) return set_error(DGSN_EINVAL, "no ANN attached");
+    hipEvent_t e0, e1;
+    DGSN_HIP(hipEventCreate(&e0));
+    DGSN_HIP(hipEventCreate(&e1));
+    const int saved_timing = p->timing;
+    p->timing = 0;
+    double best[2] = {INFINITY, INFINITY};
+    int rc = DGSN_OK;
+    for (int b = 1; b <= 2 && rc == DGSN_OK; ++b) {
+        p->tile_b = b;
+        for (int rep = 0; rep < 3 && rc == DGSN_OK; ++rep) {
+            (void)hipEventRecord(e0, s);
+            rc = p->precision == DGSN_FP64
+                     ? run_sweep<double>(p, p->src.ptr, false, false, nullptr, s)
+                     : run_sweep<float>(p, p->src.ptr, false, false, nullptr, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = set_error(DGSN_EHIP, "timing failed");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best[b - 1] = std::min(best[b - 1], (double)ms);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->timing = saved_timing;
+    p->tile_b = best[0] < best[1] ? 1 : 2;
+    ms_out[0] = best[0];
+    ms_out[1] = best[1];
+    return rc;
+}
+
+}  // namespace dgsn
+
 extern "C" {
 
 int dgsn_version(void) { return 10000; }
+
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_tile1,
+                          double *ms_tile2)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    double ms[2];
+    DGSN_TRY(autotune_problem(p, as_stream(stream), ms));
+    if (tile) *tile = p->tile_b;
+    if (ms_tile1) *ms_tile1 = ms[0];
+    if (ms_tile2) *ms_tile2 = ms[1];
+    return DGSN_OK;
+}
 
 const char *dgsn_last_error(void) { return dgsn::g_msg; }
 
@@ -437,6 +504,9 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     p->precision = d->precision;
     p->solver = d->solver;
     p->store_psi = d->store_psi ? 1 : 0;
+    // 2x2x2 tiles pay off in FP32; in FP64 they exceed the register file of
+    // one wave slot and single cells are faster (the autotuner can revisit)
+    p->tile_b = d->precision == DGSN_FP64 ? 1 : 2;
     p->real_size = d->precision == DGSN_FP64 ? 8 : 4;
     p->n_planes = d->nx + d->ny + d->nz - 2;
 

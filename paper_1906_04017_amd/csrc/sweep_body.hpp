@@ -1,0 +1,351 @@
+// Device code of the GE transport sweep shared by the per-problem kernels
+// and the batched kernel: canonical cell systems (paper and mass-inverse
+// forms), their solves, and the tile sweep body.
+#pragma once
+
+#include "ann_body.hpp"
+#include "cell.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace dgsn {
+
+constexpr double kInv4Pi = 0.07957747154594767;   // 1 / (4 pi)
+
+// Reflect an 8-node vector between physical and canonical node order
+// (v[n] <-> v[n ^ mask]); mask is uniform over the block, so each stage is a
+// scalar branch around register moves.
+template <typename Real>
+__device__ __forceinline__ void reflect8(Real v[8], int mask)
+{
+    if (mask & 1) {
+#pragma unroll
+        for (int n = 0; n < 8; n += 2) { const Real t = v[n]; v[n] = v[n + 1]; v[n + 1] = t; }
+    }
+    if (mask & 2) {
+#pragma unroll
+        for (int n = 0; n < 8; ++n)
+            if (!(n & 2)) { const Real t = v[n]; v[n] = v[n + 2]; v[n + 2] = t; }
+    }
+    if (mask & 4) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) { const Real t = v[n]; v[n] = v[n + 4]; v[n + 4] = t; }
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void load4(const Real *p, Real v[4])
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = p[e];
+}
+
+template <typename Real>
+__device__ __forceinline__ void store4(Real *p, Real a, Real b, Real c, Real d)
+{
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+    p[3] = d;
+}
+
+// Mass-inverse cell system (P_d + sigma_t I, S + sum_a kappa_a c_a), with the
+// structural zeros of P_d as literal zeros.
+template <typename Real>
+__device__ __forceinline__ void massinv_system(const Real k[3], Real st, const Real sc[8],
+                                               const Real vx[4], const Real vy[4],
+                                               const Real vz[4], Real a[8][8], Real b[8])
+{
+    const Real base = fma(Real(3), k[0] + k[1] + k[2], st);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[r][c] = Real(0);
+        Real dg = base;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const bool hi = (r >> ax) & 1;
+            if (hi) dg = fma(Real(-2), k[ax], dg);
+            a[r][r ^ (1 << ax)] = hi ? Real(-3) * k[ax] : k[ax];
+        }
+        a[r][r] = dg;
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const int ix = n & 1, iy = (n >> 1) & 1, iz = (n >> 2) & 1;
+        Real v = sc[n];
+        v = fma(ix ? Real(-2) * k[0] : Real(4) * k[0], vx[iy + 2 * iz], v);
+        v = fma(iy ? Real(-2) * k[1] : Real(4) * k[1], vy[ix + 2 * iz], v);
+        v = fma(iz ? Real(-2) * k[2] : Real(4) * k[2], vz[ix + 2 * iy], v);
+        b[n] = v;
+    }
+}
+
+// Canonical cell solve of one lane: builds the system in the chosen form from
+// the direction entry, sigma_t, the canonical source and the three inflow
+// faces, and returns psi (canonical node order) in b.
+template <typename Real, int Form>
+__device__ __forceinline__ void cell_solve(const Real *__restrict__ dp, const Real k[3], Real st,
+                                           const Real sc[8], const Real vx[4], const Real vy[4],
+                                           const Real vz[4], Real b[8])
+{
+    Real a[8][8];
+    if (Form == kFormDense) {
+        // paper form: A' = S_d + sigma_t M3, b' = M3 S + sum_a kappa_a Mf psi_a
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) a[r][c] = fma(st, Real(m3_entry(r, c)), dp[r * 8 + c]);
+        Real m[8], f[4];
+        mass3_216(sc, m);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) b[n] = m[n] * Real(1.0 / 216.0);
+        face_mass(vx, k[0] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[2 * fn] += f[fn];
+        face_mass(vy, k[1] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[(fn & 1) + 4 * (fn >> 1)] += f[fn];
+        face_mass(vz, k[2] * Real(1.0 / 36.0), f);
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn) b[fn] += f[fn];
+        ge_solve8(a, b);
+    } else {
+        // mass-inverse form: (P_d + sigma_t I) psi = S + sum_a kappa_a c_a
+        massinv_system(k, st, sc, vx, vy, vz, a, b);
+        if (__any(ge_solve8_cube(a, b))) {
+            // some lane of the wave needs a row exchange: redo the wave with
+            // the dense elimination and its partial pivoting
+            massinv_system(k, st, sc, vx, vy, vz, a, b);
+            ge_solve8(a, b);
+        }
+    }
+}
+
+// Tile sweep.  Each lane owns one (octant, B x B x B tile of cells,
+// direction, group) and solves the tile's cells in upwind lexicographic order,
+// carrying the faces between its own cells in registers: only the faces on the
+// tile boundary go through the fronts in HBM (24/B face values per solve
+// instead of 24).  Tiles with I + J + K = s are independent; one launch per
+// tile hyperplane s.  B = 1 is the plain cell hyperplane sweep.
+// ANN features of one canonical cell (see ann.hip): returns the scale m;
+// feat[4..23] are divided by m.
+__device__ __forceinline__ float ann_features(const float kap[3], float hh, float st,
+                                              const float sc[8], const float vx[4],
+                                              const float vy[4], const float vz[4],
+                                              float feat[24])
+{
+    float kmax = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        feat[a] = kap[a] * hh;
+        kmax = fmaxf(kmax, feat[a]);
+    }
+    const float tau = st * hh;
+    feat[3] = tau;
+    float pmax = 0.0f, smax = 0.0f;
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn) {
+        feat[4 + fn] = feat[0] != 0.0f ? vx[fn] : 0.0f;
+        feat[8 + fn] = feat[1] != 0.0f ? vy[fn] : 0.0f;
+        feat[12 + fn] = feat[2] != 0.0f ? vz[fn] : 0.0f;
+        pmax = fmaxf(pmax, fmaxf(fabsf(feat[4 + fn]), fmaxf(fabsf(feat[8 + fn]),
+                                                          fabsf(feat[12 + fn]))));
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        feat[16 + n] = hh * sc[n];
+        smax = fmaxf(smax, fabsf(feat[16 + n]));
+    }
+    float m = pmax;
+    const float den = tau + kmax;
+    if (den > 0.0f) m = fmaxf(m, smax / den);
+    const float rm = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+    for (int k = 4; k < 24; ++k) feat[k] *= rm;
+    return m;
+}
+
+// LDS of the tile body: the direction reduction (double buffered), the
+// adjoint contraction reduction, and the ANN operand staging.
+template <typename Real>
+struct TileLds {
+    Real red[2 * 256 * 9];
+    Real gred[256 * 2];
+};
+struct AnnLds {
+    __bf16 lin[4 * 64 * 32];
+    float lout[4 * 64 * 8];
+};
+
+// Device body of the tile sweep for one lane.  d, g: direction-in-octant and
+// group of the lane; tid: its index in the block (segments of Do lanes with
+// equal (group, tile) are contiguous); ti: its tile in the tile hyperplane;
+// o: octant slot; lane_ok: the lane carries work.  Form: kFormMassInv,
+// kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
+// blocks of full waves).  Must be reached by every thread of the block.
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
+__device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g, int tid, int ti,
+                                          int o, bool lane_ok, TileLds<Real> &L, AnnLds *al)
+{
+    static_assert(Form != kFormAnn || sizeof(Real) == 4, "the ANN solver runs in FP32");
+    const int mask = kAdjoint ? (o ^ 7) : o;
+    const bool tvalid = lane_ok && ti < (int)A.ncp;
+    const uint32_t dg = d + A.Do * g;
+    const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
+    const Real w = lane_ok ? dp[kDirW] : Real(0);
+    const Real kap[3] = {dp[kDirK], dp[kDirK + 1], dp[kDirK + 2]};
+    AnnRegs R;
+    if (Form == kFormAnn) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
+    uint32_t I0 = 0, J0 = 0, K0 = 0;
+    if (tvalid) {
+        const uint32_t pt = A.cells[ti];
+        I0 = (pt & 1023u) * B;
+        J0 = ((pt >> 10) & 1023u) * B;
+        K0 = (pt >> 20) * B;
+    }
+    const uint32_t slot = (o * A.Do + d) * A.G + g;
+    Real xf[4] = {0, 0, 0, 0}, yf[B][4] = {}, zf[B][B][4] = {};
+#pragma unroll
+    for (int kl = 0; kl < B; ++kl)
+#pragma unroll
+        for (int jl = 0; jl < B; ++jl)
+#pragma unroll
+            for (int il = 0; il < B; ++il) {
+                const int cidx = il + B * (jl + B * kl);
+                const uint32_t ic = I0 + il, jc = J0 + jl, kc = K0 + kl;
+                const bool ok = tvalid && ic < A.nx && jc < A.ny && kc < A.nz;
+                Real psi[8];
+                uint32_t c = 0;
+                Real gs = 0, gq = 0;
+                Real st = 0, sc[8], vx[4], vy[4], vz[4];
+                Real *fxp = nullptr, *fyp = nullptr, *fzp = nullptr;
+                // gather: sigma_t, the reflected source and the three inflows
+                if (ok) {
+                    const uint32_t i = (mask & 1) ? A.nx - 1 - ic : ic;
+                    const uint32_t j = (mask & 2) ? A.ny - 1 - jc : jc;
+                    const uint32_t k = (mask & 4) ? A.nz - 1 - kc : kc;
+                    c = i + A.nx * (j + A.ny * k);
+                    const uint32_t gc = g * A.ncell + c;
+                    st = A.sigma_t[gc];
+                    const Real *sp = A.src + gc * 8;
+                    load4(sp, sc);
+                    load4(sp + 4, sc + 4);
+                    reflect8(sc, mask);
+                    fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
+                    fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
+                    fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
+                    if (il > 0) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) vx[e] = xf[e];
+                    } else if (ic) {
+                        load4(fxp, vx);
+                    } else {
+                        vx[0] = vx[1] = vx[2] = vx[3] = A.inc[o][0];
+                    }
+                    if (jl > 0) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) vy[e] = yf[il][e];
+                    } else if (jc) {
+                        load4(fyp, vy);
+                    } else {
+                        vy[0] = vy[1] = vy[2] = vy[3] = A.inc[o][1];
+                    }
+                    if (kl > 0) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) vz[e] = zf[jl][il][e];
+                    } else if (kc) {
+                        load4(fzp, vz);
+                    } else {
+                        vz[0] = vz[1] = vz[2] = vz[3] = A.inc[o][2];
+                    }
+                }
+                // local solve
+                if constexpr (Form == kFormAnn) {
+                    float feat[24], y[8];
+                    float m = 0.0f;
+                    if (ok) {
+                        m = ann_features(kap, A.hh, st, sc, vx, vy, vz, feat);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 24; ++e) feat[e] = 0.0f;
+                    }
+                    ann_wave(R, feat, al->lin + (tid >> 6) * (64 * 32),
+                             al->lout + (tid >> 6) * (64 * 8), y);
+#pragma unroll
+                    for (int n = 0; n < 8; ++n) psi[n] = ok ? m * y[n] : 0.0f;
+                } else {
+                    if (ok) {
+                        cell_solve<Real, Form>(dp, kap, st, sc, vx, vy, vz, psi);
+                    } else {
+#pragma unroll
+                        for (int n = 0; n < 8; ++n) psi[n] = 0;
+                    }
+                }
+                // scatter: register fronts, tile-boundary fronts, psi store or
+                // adjoint contraction
+                if (ok) {
+                    xf[0] = psi[1]; xf[1] = psi[3]; xf[2] = psi[5]; xf[3] = psi[7];
+                    yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
+                    zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
+                    zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
+                    if (il == B - 1 && ic + 1 < A.nx) store4(fxp, psi[1], psi[3], psi[5], psi[7]);
+                    if (jl == B - 1 && jc + 1 < A.ny) store4(fyp, psi[2], psi[3], psi[6], psi[7]);
+                    if (kl == B - 1 && kc + 1 < A.nz) store4(fzp, psi[4], psi[5], psi[6], psi[7]);
+                    if (kStorePsi || (kAdjoint && A.grad_oct)) {
+                        Real *pp = A.psi + ((size_t)slot * A.ncell + c) * 8;
+                        if (kStorePsi) {
+                            Real ph[8];
+#pragma unroll
+                            for (int n = 0; n < 8; ++n) ph[n] = psi[n];
+                            reflect8(ph, mask);
+                            store4(pp, ph[0], ph[1], ph[2], ph[3]);
+                            store4(pp + 4, ph[4], ph[5], ph[6], ph[7]);
+                        } else {
+                            // mu^T M psi with the stored forward flux, M = V M3
+                            Real pf[8], m[8];
+                            load4(pp, pf);
+                            load4(pp + 4, pf + 4);
+                            reflect8(pf, mask);
+                            mass3_216(pf, m);
+                            Real s = 0, sm = 0;
+#pragma unroll
+                            for (int n = 0; n < 8; ++n) {
+                                s = fma(psi[n], m[n], s);
+                                sm += psi[n];
+                            }
+                            gs = -w * A.vol * s * Real(1.0 / 216.0);
+                            gq = w * A.vol * sm * Real(0.125);
+                        }
+                    }
+                }
+                // deterministic per-octant reduction over the directions
+                Real *rb = L.red + (cidx & 1) * (256 * 9);
+#pragma unroll
+                for (int n = 0; n < 8; ++n) rb[tid * 9 + n] = w * psi[n];
+                if (kAdjoint) {
+                    L.gred[tid * 2 + 0] = gs;
+                    L.gred[tid * 2 + 1] = gq;
+                }
+                __syncthreads();
+                if (ok) {
+                    const int base = tid - d;
+                    const uint32_t out = ((o * A.G + g) * A.ncell + c) * 8;
+                    for (int n = d; n < 8; n += (int)A.Do) {
+                        Real s = 0;
+                        for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
+                        A.phi_oct[out + (n ^ mask)] = s;
+                    }
+                    if (kAdjoint && A.grad_oct) {
+                        for (int k2 = d; k2 < 2; k2 += (int)A.Do) {
+                            Real s = 0;
+                            for (int e = 0; e < (int)A.Do; ++e) s += L.gred[(base + e) * 2 + k2];
+                            A.grad_oct[((o * A.G + g) * A.ncell + c) * 2 + k2] = s;
+                        }
+                    }
+                }
+                if (kAdjoint) __syncthreads();
+            }
+}
+
+}  // namespace dgsn

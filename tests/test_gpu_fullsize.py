@@ -1,0 +1,111 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The oracle sweeps these sizes on the host in seconds (one sweep, OpenMP), so
+the full-size checks compare every output; the source-iteration fixed point
+is checked through properties that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1906_04017_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1906_04017_amd import api as _api
+    return _api
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def print_case(case, **kw):
+    print(f"[case] {case} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def test_blocky_scatter_full_sweep_fp32(api, ctx):
+    # the benchmark workload (64^3, S8, 8 groups, FP32, default tiling): one
+    # sweep with the source of the first source iteration, against the oracle
+    p = inputs.blocky_scatter()
+    print_case("fullsize_sweep", name=p["name"])
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    S = np.repeat(p["q"][..., None], 8, axis=-1)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om_o, w_o = oracle.lq_n(8)
+    ref = oracle.sweep((*p["n"], *p["length"]), om_o, w_o, p["sigma_t"], S, p["psi_inc"])
+    for g in range(p["groups"]):
+        assert rel(phi[g], ref[g]) <= 1e-5, g
+
+
+def test_paper_problems_full_sweep_fp32(api, ctx):
+    # the paper's four problems at 128^3, S8: the two pure absorbers with
+    # incident flux and a thin medium (groups 1-3 are one sweep from the
+    # solution); checked against the oracle on the first three groups
+    p = inputs.paper_problems()
+    print_case("fullsize_sweep", name=p["name"])
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.set_inflow(p["psi_inc"])
+    S = np.repeat(p["q"][..., None], 8, axis=-1)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om_o, w_o = oracle.lq_n(8)
+    for g in (0, 1, 2):
+        ref = oracle.sweep((*p["n"], *p["length"]), om_o, w_o, p["sigma_t"][g:g + 1],
+                           S[g:g + 1], p["psi_inc"])
+        # the absorbers decay over 100 mean free paths: compare against the
+        # largest value, plus the relative error where the flux is above 1e-6
+        # of its maximum
+        assert rel(phi[g], ref[0]) <= 1e-5, g
+        big = np.abs(ref[0]) > 1e-6 * np.abs(ref[0]).max()
+        assert np.abs(phi[g][big] / ref[0][big] - 1).max() <= 1e-3, g
+
+
+def test_constant_solution_at_bench_size(api, ctx):
+    # uniform sigma_t, sigma_s = c sigma_t, q and inflow q / (sigma_t (1 - c))
+    # on every face: the source-iteration fixed point is psi = q/(sigma_t(1-c))
+    n = 64
+    ncell = n ** 3
+    st, c, qv = 2.0, 0.5, 1.0
+    psi0 = qv / (st * (1 - c))
+    print_case("fullsize_constant", n=n)
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, (n, n, n), (1.0, 1.0, 1.0), 8, om, w, precision="fp32")
+    prob.set_materials(np.full((8, ncell), st), np.full((8, ncell), c * st),
+                       np.full((8, ncell), qv))
+    prob.set_inflow(np.full(6, psi0))
+    phi, info = prob.source_iterate(tol=1e-7, max_iter=200, allow_notconv=True)
+    assert info["resid"] < 1e-5
+    assert float((phi / (4 * np.pi * psi0) - 1).abs().max()) < 2e-5
+
+
+def test_reflection_symmetry_at_bench_size(api, ctx):
+    # materials symmetric under x -> 1 - x and a symmetric quadrature: the
+    # FP32 sweep must be symmetric to rounding
+    n = 64
+    p = inputs.blocky_scatter(n=n, groups=2, seed=12)
+    st = p["sigma_t"].reshape(2, n, n, n)
+    st = 0.5 * (st + st[:, :, :, ::-1])
+    print_case("fullsize_symmetry", n=n)
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, (n, n, n), (1.0, 1.0, 1.0), 2, om, w, precision="fp32")
+    prob.set_materials(st.reshape(2, -1), None, np.ones((2, n ** 3)))
+    phi = prob.sweep(torch.ones((2, n ** 3, 8), device="cuda")).cpu().numpy()
+    f = phi.reshape(2, n, n, n, 2, 2, 2)
+    assert np.abs(f - f[:, :, :, ::-1, :, :, ::-1]).max() <= 1e-5 * np.abs(f).max()

@@ -301,7 +301,8 @@ def _identity_net(select):
                 W2=W2.astype(np.float32), b2=np.zeros(8, np.float32))
 
 
-def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path):
+@pytest.mark.parametrize("tile", [1, 2])
+def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path, tile):
     # psi = h S exactly (network y[n'] = x[16 + n']): checks features,
     # reflection, normalisation and rescaling of the ANN sweep kernel; the
     # only error is BF16 rounding of the normalised input and hidden value
@@ -311,6 +312,7 @@ def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path):
     print_case("ann_sweep_source_passthrough", name=p["name"])
     prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
     prob.set_ann(ann)
+    prob.set_tile(tile)
     S = nodal_source(p, seed=13)
     phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
     om, w = oracle.lq_n(6)
@@ -318,7 +320,8 @@ def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path):
     assert rel(phi, ref) <= 2 * 2.0 ** -8
 
 
-def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path):
+@pytest.mark.parametrize("tile", [1, 2])
+def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path, tile):
     # psi[n] = x-face inflow at the partner node: values are copied cell to
     # cell along x, so the fronts and their boundary values are exercised;
     # each hop re-rounds to BF16 at most twice
@@ -331,8 +334,74 @@ def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path):
     print_case("ann_sweep_inflow_passthrough", name=p["name"])
     prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
     prob.set_ann(ann)
+    prob.set_tile(tile)
     S = nodal_source(p)
     phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
     om, w = oracle.lq_n(4)
     ref = oracle.ann_sweep(net, mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
     assert rel(phi, ref) <= 2 * 6 * 2.0 ** -8
+
+
+# ---------------------------------------------------------------------------
+# autotuner and batched execution
+# ---------------------------------------------------------------------------
+
+def test_problem_autotune_keeps_results(api, ctx):
+    p = inputs.random_problem((10, 9, 8), 6, 3, seed=51)
+    print_case("autotune", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32")
+    tile, ms1, ms2 = prob.autotune()
+    assert tile in (1, 2) and ms1 > 0 and ms2 > 0
+    assert prob.tile() == tile
+    S = nodal_source(p, seed=5)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(6)
+    ref = oracle.sweep(mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    assert rel(phi, ref) <= FP32_TOL
+
+
+BATCH = [((5, 4, 3), 4, 2, "ge"), ((9, 9, 9), 8, 3, "ge"), ((3, 7, 2), 12, 1, "ge"),
+         ((6, 5, 4), 6, 2, "ann"), ((1, 1, 1), 2, 1, "ge"), ((8, 6, 7), 4, 4, "ann"),
+         ((12, 10, 11), 8, 2, "ge")]
+
+
+@pytest.mark.parametrize("tiles", ["default", "ones", "autotune"])
+def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles):
+    print_case("batch", tiles=tiles, problems=len(BATCH))
+    net = _random_net(77)
+    ann = api.Ann(ctx, _write_net(tmp_path, net, "batch.dgsnann"))
+    probs, srcs, phis, ps = [], [], [], []
+    for k, (n, order, G, solver) in enumerate(BATCH):
+        p = inputs.random_problem(n, order, G, seed=600 + k,
+                                  length=tuple(0.1 * v + 0.3 for v in n))
+        prob = gpu_problem(api, ctx, p, "fp32", solver=solver)
+        if solver == "ann":
+            prob.set_ann(ann)
+        S = torch.tensor(nodal_source(p, seed=700 + k), dtype=torch.float32, device="cuda")
+        probs.append(prob)
+        srcs.append(S)
+        phis.append(torch.full_like(S, float("nan")))
+        ps.append(p)
+    batch = api.Batch(ctx, probs)
+    for k in range(len(probs)):
+        batch.set_io(k, srcs[k], phis[k])
+    if tiles == "ones":
+        batch.set_tiles([1] * len(probs))
+    elif tiles == "autotune":
+        assert batch.autotune() > 0
+    batch.run()
+    torch.cuda.synchronize()
+    lat = batch.latencies_us()
+    assert np.all(lat > 0)
+    for k, (n, order, G, solver) in enumerate(BATCH):
+        got = phis[k].cpu().numpy()
+        if solver == "ge":
+            om, w = oracle.lq_n(order)
+            ref = oracle.sweep(mesh_of(ps[k]), om, w, ps[k]["sigma_t"], srcs[k].cpu().numpy(),
+                               ps[k]["psi_inc"])
+            assert rel(got, ref) <= FP32_TOL, (k, rel(got, ref))
+        else:
+            # same device arithmetic as the single-problem ANN sweep
+            ref = probs[k].sweep(srcs[k]).cpu().numpy()
+            assert np.array_equal(got, ref), k
+    batch.close()
