@@ -85,8 +85,9 @@ def main():
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
     prob.set_inflow(p["psi_inc"])
-    tile, ms1, ms2 = prob.autotune()
-    log(f"autotune: tile {tile} (one sweep {ms1:.3f} ms with 1x1x1, {ms2:.3f} ms with 2x2x2)")
+    tile, ms = prob.autotune()
+    log(f"autotune: tile {tile} (one sweep " +
+        ", ".join(f"{m:.3f} ms with {b}^3" for b, m in enumerate(ms, 1)) + ")")
     st = prob.stats()
     solves = st["solves_per_sweep"]
     phi = torch.zeros((p["groups"], prob.ncell, 8), dtype=torch.float32, device="cuda")
@@ -129,6 +130,8 @@ def main():
 
     fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
     ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann)
+    adj = None if args.skip_extras else adjoint_box(api, ctx)
+    batch = None if args.skip_extras else uneven_batch(api, ctx, args.ann)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -146,6 +149,8 @@ def main():
         "cpu_baseline": cpu,
         "fp64_ge": fp64,
         "ann_vs_ge": ann,
+        "adjoint": adj,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 
@@ -231,6 +236,120 @@ def ann_vs_ge(api, ctx, ann_path, n=128, reps=3):
     out["problem4_si_iterations"] = {"ge": si["ge"][1]["iters"], "ann": si["ann"][1]["iters"]}
     out["paper_context"] = ("paper, 100^3 S8, unstated hardware: ANN saves 68.4 % of the solve time "
                             "(3.16x); eps_P 1.59 / 2.45 / 0.45 / 0.87 % on Problems 1-4")
+    ann.close()
+    return out
+
+
+def adjoint_box(api, ctx, n=32, cells=8, h=1e-6):
+    """Gradient of the absorption in the central box (cells 12..19 of a 32^3
+    cube, S4, 2 groups, c = 0.5) with respect to sigma_t and q through the
+    FP32 forward and adjoint source iterations, checked at seeded cells against
+    central differences of FP64 forward solves (sigma_s held fixed)."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    p = inputs.adjoint_box(n=n)
+    om, w = api.quadrature_ls(p["order"])
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    box = torch.tensor(p["box_mask"], device="cuda")
+
+    def response(phi, st, ss):
+        # J = sum_g sum_box (sigma_t - sigma_s) int phi, int phi = V/8 sum_nodes
+        return (((st - ss) * box)[..., None] * phi).sum() * (V / 8)
+
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32",
+                       store_psi=True)
+    st = torch.tensor(p["sigma_t"], dtype=torch.float32, device="cuda", requires_grad=True)
+    q = torch.tensor(p["q"], dtype=torch.float32, device="cuda", requires_grad=True)
+    ss = torch.tensor(p["sigma_s"], dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi = api.TransportSolve.apply(prob, st, q, ss, 1e-7, 500)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J = response(phi, st, ss)
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gst = st.grad.double().cpu().numpy()
+    gq = q.grad.double().cpu().numpy()
+    # FP64 forward solves for central differences at seeded cells
+    p64 = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp64")
+    rng = np.random.default_rng(44)
+    sel = [(int(rng.integers(0, p["groups"])), int(rng.integers(0, n ** 3))) for _ in range(cells)]
+    sel[0] = (0, int(np.flatnonzero(p["box_mask"])[7]))
+
+    def J64(st_np, q_np):
+        p64.set_materials(st_np, p["sigma_s"], q_np)
+        ph, _ = p64.source_iterate(tol=1e-13, max_iter=2000)
+        stt = torch.tensor(st_np, dtype=torch.float64, device="cuda")
+        sst = torch.tensor(p["sigma_s"], dtype=torch.float64, device="cuda")
+        return float(response(ph, stt, sst))
+
+    err_t, err_q = [], []
+    for g, c in sel:
+        e = np.zeros_like(p["sigma_t"])
+        e[g, c] = h
+        fd_t = (J64(p["sigma_t"] + e, p["q"]) - J64(p["sigma_t"] - e, p["q"])) / (2 * h)
+        fd_q = (J64(p["sigma_t"], p["q"] + e) - J64(p["sigma_t"], p["q"] - e)) / (2 * h)
+        err_t.append(abs(gst[g, c] - fd_t) / max(abs(fd_t), 1e-300))
+        err_q.append(abs(gq[g, c] - fd_q) / max(abs(fd_q), 1e-300))
+    log(f"adjoint: forward SI {1e3 * (t1 - t0):.1f} ms, adjoint {1e3 * (t2 - t1):.1f} ms, "
+        f"max rel err vs FD: sigma_t {max(err_t):.2e}, q {max(err_q):.2e}")
+    prob.close()
+    p64.close()
+    return {"workload": p["name"], "forward_si_ms": 1e3 * (t1 - t0), "adjoint_ms": 1e3 * (t2 - t1),
+            "fd_cells": len(sel), "fd_step": h, "max_rel_err_dsigma_t": max(err_t),
+            "max_rel_err_dq": max(err_q), "precision": "fp32 adjoint vs fp64 central differences"}
+
+
+def uneven_batch(api, ctx, ann_path, count=64):
+    """64 independent problems (cubes of 16^3 to 96^3 cells, S4 to S12, 1 to
+    8 groups, GE or ANN with probability 1/2, blocky random materials): one
+    sweep of every problem in one graph launch; autotuned tiles; p50 / p99
+    per-problem latency and aggregate solves per second."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    ps = inputs.uneven_batch(count=count)
+    ann = api.Ann(ctx, ann_path)
+    probs, srcs, phis = [], [], []
+    solves = 0
+    for p in ps:
+        om, w = api.quadrature_ls(p["order"])
+        prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32",
+                           solver=p["solver"])
+        prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+        if p["solver"] == "ann":
+            prob.set_ann(ann)
+        S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32,
+                         device="cuda")
+        probs.append(prob)
+        srcs.append(S)
+        phis.append(torch.empty_like(S))
+        solves += prob.stats()["solves_per_sweep"]
+    batch = api.Batch(ctx, probs)
+    for k in range(count):
+        batch.set_io(k, srcs[k], phis[k])
+    best_ms = batch.autotune()
+    batch.run()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    lat = batch.latencies_us()
+    log(f"batch: {count} problems, {solves} solves, {1e3 * dt:.2f} ms per run, "
+        f"p50 {np.percentile(lat, 50):.0f} us, p99 {np.percentile(lat, 99):.0f} us")
+    out = {"problems": count, "solves_per_run": solves, "ms_per_run": 1e3 * dt,
+           "solves_per_s": solves / dt, "autotune_best_ms": best_ms,
+           "latency_us_p50": float(np.percentile(lat, 50)),
+           "latency_us_p99": float(np.percentile(lat, 99)),
+           "ann_problems": sum(1 for p in ps if p["solver"] == "ann"),
+           "execution": "one HIP graph: one batched kernel per step over all problems"}
+    batch.close()
+    for prob in probs:
+        prob.close()
     ann.close()
     return out
 

@@ -162,23 +162,23 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                         double *resid, double *eps_s, void *stream);
 
 /*
- * Sweep tiling of the GE solvers: with b = 2 every lane solves a 2x2x2 tile
- * of cells for its (direction, group), keeping the faces between them in
- * registers (half of the face traffic), one launch per tile hyperplane; with
- * b = 1 every lane solves one cell per hyperplane launch.  Default 2 for
- * FP32 problems, 1 for FP64; dgsn_problem_autotune picks the faster.
+ * Sweep tiling: with b > 1 every lane solves a b x b x b tile of cells for
+ * its (direction, group) in upwind order, keeping the faces between them in
+ * registers (the face traffic through HBM drops from 24 to 24/b values per
+ * solve), one launch per tile hyperplane; with b = 1 every lane solves one
+ * cell per hyperplane launch.  b in 1..3; default 2 for FP32 problems and 1
+ * for FP64.  dgsn_problem_set_tile / _get_tile set and read it.
  */
 int dgsn_problem_set_tile(dgsn_problem *p, int b);
 int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
 
 /*
- * Autotuner: times one sweep of the problem with each tile edge (on its
- * internal buffers; user arrays are not touched), keeps the faster, and
- * returns the choice and both times in ms (any pointer may be NULL).
- * Synchronizes stream.
+ * Autotuner: times one sweep of the problem with each tile edge 1..3 (on its
+ * internal buffers; user arrays are not touched), keeps the fastest, and
+ * returns the choice and the times in ms (ms_per_tile: host [3], may be
+ * NULL).  Synchronizes stream.
  */
-int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_tile1,
-                          double *ms_tile2);
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_per_tile);
 
 /*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses
@@ -255,13 +255,14 @@ int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
  * quadrature and group count, solver DGSN_GE or DGSN_ANN per problem): one
  * sweep of every problem in a single HIP-graph launch.  Step t of the graph
  * is one batched kernel that advances every problem that still has a step t
- * (a tile hyperplane for GE, a cell hyperplane for ANN); the per-problem
+ * (a tile or cell hyperplane, by its tile edge); the per-problem
  * octant reductions follow.  Not in the paper.
  * dgsn_batch_create: probs must stay alive while the batch exists; each
  *   problem's materials, inflow and ANN are read at run time.
  * dgsn_batch_set_io: device src / phi of problem `index`, layouts as in
  *   dgsn_sweep; must be set for every problem before the first run.
- * dgsn_batch_set_tiles: per-problem GE tile edge (1 or 2), host [n].
+ * dgsn_batch_set_tiles: per-problem tile edge (1 or 2; a problem set to 3
+ *   runs with 2 in a batch), host [n].
  * dgsn_batch_autotune: times the batch with candidate tile assignments (all
  *   2, all 1, 2 for meshes of >= 32^3 cells) and keeps the fastest; returns
  *   its time in ms.  Runs the batch several times; synchronizes stream.

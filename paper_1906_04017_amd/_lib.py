@@ -81,7 +81,7 @@ SIGNATURES = {
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_set_tile": (_I, [_VP, _I]),
     "dgsn_problem_get_tile": (_I, [_VP, _PI]),
-    "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PD, _PD]),
+    "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PD]),
     "dgsn_problem_kernel_time": (_I, [_VP, _PD, _PI]),
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),

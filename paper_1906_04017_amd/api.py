@@ -190,15 +190,13 @@ class Problem:
         return b.value
 
     def autotune(self):
-        """Time one sweep with each tile edge and keep the faster;
-        returns (tile, ms_tile1, ms_tile2)."""
+        """Time one sweep with each tile edge 1..3 and keep the fastest;
+        returns (tile, [ms with edge 1, 2, 3])."""
         t = ctypes.c_int(0)
-        a = ctypes.c_double(0)
-        b = ctypes.c_double(0)
+        ms = np.zeros(3)
         _lib.check(_lib.load().dgsn_problem_autotune(self._h, _stream(self.ctx.device),
-                                                     ctypes.byref(t), ctypes.byref(a),
-                                                     ctypes.byref(b)))
-        return t.value, a.value, b.value
+                                                     ctypes.byref(t), ms.ctypes.data_as(_lib._PD)))
+        return t.value, ms.tolist()
 
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))

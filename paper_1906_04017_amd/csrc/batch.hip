@@ -130,7 +130,7 @@ int build_tables(dgsn_batch *B)
     B->nsteps = 0;
     for (int b = 0; b < n; ++b) {
         const dgsn_problem *p = B->probs[b];
-        steps[b] = B->tileb[b] == 1 ? p->n_planes : p->n_tplanes2;
+        steps[b] = B->tileb[b] == 1 ? p->n_planes : p->n_tplanes[B->tileb[b]];
         B->nsteps = std::max(B->nsteps, steps[b]);
     }
     std::vector<PlaneArgs<float>> args((size_t)B->nsteps * n);
@@ -139,9 +139,8 @@ int build_tables(dgsn_batch *B)
     B->blocks_per_step.assign(B->nsteps, 0);
     for (int b = 0; b < n; ++b) {
         dgsn_problem *p = B->probs[b];
-        const bool tiled = B->tileb[b] == 2;
         meta[4 * b + 0] = p->solver == DGSN_ANN ? DGSN_ANN : DGSN_GE;
-        meta[4 * b + 1] = tiled ? 2 : 1;
+        meta[4 * b + 1] = B->tileb[b];
         meta[4 * b + 2] = steps[b] - 1;
         meta[4 * b + 3] = 0;
     }
@@ -150,10 +149,10 @@ int build_tables(dgsn_batch *B)
         for (int b = 0; b < n; ++b) {
             dgsn_problem *p = B->probs[b];
             PlaneArgs<float> A = batch_plane_args(p, B->src[b]);
-            const bool tiled = B->tileb[b] == 2;
-            const std::vector<int> &off = tiled ? p->tplane_off2 : p->plane_off;
+            const int tb = B->tileb[b];
+            const std::vector<int> &off = tb > 1 ? p->tplane_off[tb] : p->plane_off;
             const uint32_t *cells =
-                static_cast<const uint32_t *>(tiled ? p->d_tiles2.ptr : p->d_plane_cells.ptr);
+                static_cast<const uint32_t *>(tb > 1 ? p->d_tiles[tb].ptr : p->d_plane_cells.ptr);
             int ncp = 0;
             if (t < steps[b]) {
                 A.cells = cells + off[t];
@@ -260,7 +259,9 @@ int dgsn_batch_create(dgsn_ctx *ctx, dgsn_problem *const *probs, int n, dgsn_bat
     B->src.assign(n, nullptr);
     B->phi.assign(n, nullptr);
     B->tileb.resize(n);
-    for (int b = 0; b < n; ++b) B->tileb[b] = probs[b]->tile_b;
+    // the batched kernel instantiates tile edges 1 and 2 only (a 3^3 tile
+    // path would raise the register count of every block of the launch)
+    for (int b = 0; b < n; ++b) B->tileb[b] = std::min(probs[b]->tile_b, 2);
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
         rate <= 0) {

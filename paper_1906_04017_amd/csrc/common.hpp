@@ -39,12 +39,13 @@ constexpr int kDirK36 = 64;
 constexpr int kDirW = 67;
 constexpr int kDirK = 68;
 constexpr int kMaxHidden = 256;
+constexpr int kMaxTile = 3;       // largest tile edge of the sweep
 
 // ---- host-side quadrature ---------------------------------------------------
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
 
 const void *ann_device_params(const dgsn_ann *a);
-int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2]);
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[3]);
 
 // ---- device allocation helper ------------------------------------------------
 struct DevBuf {
@@ -90,11 +91,13 @@ struct dgsn_problem {
     std::vector<int> dir_user;       // octant-sorted slot -> user direction index
     std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64
     std::vector<int> plane_off;      // [n_planes + 1]
-    // tile hyperplane schedule for B x B x B tiles (B = 2): packed tile coords
-    int tile_b = 2;                  // tile edge used by the GE sweep (1 or 2)
-    int n_tplanes2 = 0;
-    std::vector<int> tplane_off2;    // [n_tplanes2 + 1]
-    dgsn::DevBuf d_tiles2;
+    // tile hyperplane schedules for B x B x B tiles (B = 2, 3; index B):
+    // packed tile coordinates, tile-hyperplane major (B = 1 is the cell
+    // schedule above)
+    int tile_b = 2;                  // tile edge used by the sweep (1, 2 or 3)
+    int n_tplanes[4] = {0, 0, 0, 0};
+    std::vector<int> tplane_off[4];  // [n_tplanes[B] + 1]
+    dgsn::DevBuf d_tiles[4];
 
     dgsn::DevBuf d_dir;              // [8][Do][kDirStride] real
     dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major

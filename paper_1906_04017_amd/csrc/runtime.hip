@@ -191,11 +191,12 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         A.ann_params = ann_device_params(p->ann);
     }
     const int form = p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv;
-    const bool tiled = p->tile_b == 2;
-    const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles2.ptr
+    const int tb = p->tile_b;
+    const bool tiled = tb > 1;
+    const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles[tb].ptr
                                                                : p->d_plane_cells.ptr);
-    const std::vector<int> &off = tiled ? p->tplane_off2 : p->plane_off;
-    const int nsteps = tiled ? p->n_tplanes2 : p->n_planes;
+    const std::vector<int> &off = tiled ? p->tplane_off[tb] : p->plane_off;
+    const int nsteps = tiled ? p->n_tplanes[tb] : p->n_planes;
     p->last_stream = s;
     p->ev_used = 0;
     for (int pl = 0; pl < nsteps; ++pl) {
@@ -205,11 +206,11 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         bool done = false;
         if constexpr (sizeof(Real) == 4) {
             if (ann) {
-                DGSN_TRY(launch_tile_ann(A, tiled ? 2 : 1, s));
+                DGSN_TRY(launch_tile_ann(A, tb, s));
                 done = true;
             }
         }
-        if (!done) DGSN_TRY(launch_tile<Real>(A, form, tiled ? 2 : 1, store_psi, adjoint, s));
+        if (!done) DGSN_TRY(launch_tile<Real>(A, form, tb, store_psi, adjoint, s));
         if (p->timing) {
             DGSN_HIP(hipEventRecord(p->ev[2 * pl + 1], s));
             p->ev_used = pl + 1;
@@ -366,7 +367,7 @@ int batch_reduce(dgsn_problem *p, void *phi, hipStream_t s)
 // Time one sweep of the problem with each tile edge on its internal source
 // buffer and keep the faster (ties keep 2).  The problem's outputs are not
 // touched (only its internal partials and fronts).
-int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2])
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[kMaxTile])
 {
     if (p->solver == DGSN_ANN && !p->ann) return set_error(DGSN_EINVAL, "no ANN attached");
     hipEvent_t e0, e1;
@@ -374,9 +375,10 @@ int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2])
     DGSN_HIP(hipEventCreate(&e1));
     const int saved_timing = p->timing;
     p->timing = 0;
-    double best[2] = {INFINITY, INFINITY};
+    double best[kMaxTile] = {};
+    for (int b = 0; b < kMaxTile; ++b) best[b] = INFINITY;
     int rc = DGSN_OK;
-    for (int b = 1; b <= 2 && rc == DGSN_OK; ++b) {
+    for (int b = 1; b <= kMaxTile && rc == DGSN_OK; ++b) {
         p->tile_b = b;
         for (int rep = 0; rep < 3 && rc == DGSN_OK; ++rep) {
             (void)hipEventRecord(e0, s);
@@ -393,9 +395,11 @@ int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2])
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->timing = saved_timing;
-    p->tile_b = best[0] < best[1] ? 1 : 2;
-    ms_out[0] = best[0];
-    ms_out[1] = best[1];
+    int bi = 1;
+    for (int b = 2; b <= kMaxTile; ++b)
+        if (best[b - 1] < best[bi - 1]) bi = b;
+    p->tile_b = bi;
+    for (int b = 0; b < kMaxTile; ++b) ms_out[b] = best[b];
     return rc;
 }
 
@@ -405,17 +409,16 @@ extern "C" {
 
 int dgsn_version(void) { return 10000; }
 
-int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_tile1,
-                          double *ms_tile2)
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_per_tile)
 {
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
-    double ms[2];
+    double ms[kMaxTile];
     DGSN_TRY(autotune_problem(p, as_stream(stream), ms));
     if (tile) *tile = p->tile_b;
-    if (ms_tile1) *ms_tile1 = ms[0];
-    if (ms_tile2) *ms_tile2 = ms[1];
+    if (ms_per_tile)
+        for (int b = 0; b < kMaxTile; ++b) ms_per_tile[b] = ms[b];
     return DGSN_OK;
 }
 
@@ -545,15 +548,15 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     }
     p->plane_off[p->n_planes] = (int)cells.size();
 
-    // 2 x 2 x 2 tile hyperplanes
-    {
-        const int T[3] = {(d->nx + 1) / 2, (d->ny + 1) / 2, (d->nz + 1) / 2};
-        p->n_tplanes2 = T[0] + T[1] + T[2] - 2;
+    // B x B x B tile hyperplanes, B = 2 .. kMaxTile
+    for (int tb = 2; tb <= kMaxTile; ++tb) {
+        const int T[3] = {(d->nx + tb - 1) / tb, (d->ny + tb - 1) / tb, (d->nz + tb - 1) / tb};
+        p->n_tplanes[tb] = T[0] + T[1] + T[2] - 2;
         std::vector<uint32_t> tl;
         tl.reserve((size_t)T[0] * T[1] * T[2]);
-        p->tplane_off2.assign(p->n_tplanes2 + 1, 0);
-        for (int pl = 0; pl < p->n_tplanes2; ++pl) {
-            p->tplane_off2[pl] = (int)tl.size();
+        p->tplane_off[tb].assign(p->n_tplanes[tb] + 1, 0);
+        for (int pl = 0; pl < p->n_tplanes[tb]; ++pl) {
+            p->tplane_off[tb][pl] = (int)tl.size();
             for (int k = 0; k < T[2]; ++k)
                 for (int j = 0; j < T[1]; ++j) {
                     const int i = pl - j - k;
@@ -561,10 +564,10 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
                     tl.push_back((uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20));
                 }
         }
-        p->tplane_off2[p->n_tplanes2] = (int)tl.size();
-        int rc2 = p->d_tiles2.alloc(tl.size() * sizeof(uint32_t));
+        p->tplane_off[tb][p->n_tplanes[tb]] = (int)tl.size();
+        int rc2 = p->d_tiles[tb].alloc(tl.size() * sizeof(uint32_t));
         if (rc2) return fail(rc2);
-        if (hipMemcpy(p->d_tiles2.ptr, tl.data(), tl.size() * sizeof(uint32_t),
+        if (hipMemcpy(p->d_tiles[tb].ptr, tl.data(), tl.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice) != hipSuccess)
             return fail(set_error(DGSN_EHIP, "upload of the tile schedule failed"));
     }
@@ -676,7 +679,8 @@ int dgsn_problem_set_tile(dgsn_problem *p, int b)
 {
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
-    if (b != 1 && b != 2) return set_error(DGSN_EINVAL, "tile edge must be 1 or 2");
+    if (b < 1 || b > kMaxTile)
+        return set_error(DGSN_EINVAL, "tile edge must be in 1..%d", kMaxTile);
     p->tile_b = b;
     return DGSN_OK;
 }
@@ -705,7 +709,7 @@ int dgsn_problem_set_timing(dgsn_problem *p, int enable)
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     if (enable && p->ev.empty()) {
-        p->ev.assign(2 * std::max(p->n_planes, p->n_tplanes2), nullptr);
+        p->ev.assign(2 * p->n_planes, nullptr);   // the cell schedule has the most steps
         for (auto &e : p->ev) DGSN_HIP(hipEventCreate(&e));
     }
     p->timing = enable ? 1 : 0;

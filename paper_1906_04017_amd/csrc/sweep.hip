@@ -226,16 +226,22 @@ template <typename Real, int Form>
 void launch_tile_b(const PlaneArgs<Real> &A, int b, bool store_psi, bool adjoint, dim3 grid,
                    dim3 block, hipStream_t s)
 {
-    if (b == 2) launch_tile_form<Real, Form, 2>(A, store_psi, adjoint, grid, block, s);
-    else launch_tile_form<Real, Form, 1>(A, store_psi, adjoint, grid, block, s);
+    switch (b) {
+    case 3: launch_tile_form<Real, Form, 3>(A, store_psi, adjoint, grid, block, s); break;
+    case 2: launch_tile_form<Real, Form, 2>(A, store_psi, adjoint, grid, block, s); break;
+    default: launch_tile_form<Real, Form, 1>(A, store_psi, adjoint, grid, block, s); break;
+    }
 }
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s)
 {
     const int nc = cells_per_block(A.Do, A.G);
     const dim3 grid((A.ncp + nc - 1) / nc, 8);
-    if (b == 2) hipLaunchKernelGGL(sweep_tile_ann<2>, grid, dim3(256), 0, s, A);
-    else hipLaunchKernelGGL(sweep_tile_ann<1>, grid, dim3(256), 0, s, A);
+    switch (b) {
+    case 3: hipLaunchKernelGGL(sweep_tile_ann<3>, grid, dim3(256), 0, s, A); break;
+    case 2: hipLaunchKernelGGL(sweep_tile_ann<2>, grid, dim3(256), 0, s, A); break;
+    default: hipLaunchKernelGGL(sweep_tile_ann<1>, grid, dim3(256), 0, s, A); break;
+    }
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

@@ -206,7 +206,9 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
     }
     const uint32_t slot = (o * A.Do + d) * A.G + g;
     Real xf[4] = {0, 0, 0, 0}, yf[B][4] = {}, zf[B][B][4] = {};
-#pragma unroll
+    // layers of the tile (kl) are a rolled loop for B > 2 (the layer body,
+    // B^2 cells, is unrolled so that every register front index is static)
+#pragma unroll(B <= 2 ? B : 1)
     for (int kl = 0; kl < B; ++kl)
 #pragma unroll
         for (int jl = 0; jl < B; ++jl)

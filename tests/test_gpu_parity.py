@@ -123,7 +123,7 @@ RAGGED = [
 ]
 
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 @pytest.mark.parametrize("solver", ["ge", "ge_dense"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in RAGGED])
@@ -225,7 +225,7 @@ def test_source_iteration_resume_from_saved_phi(api, ctx):
 # adjoint
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 @pytest.mark.parametrize("solver", ["ge", "ge_dense"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
 def test_adjoint_matches_oracle(api, ctx, precision, tol, solver, tile):
@@ -301,7 +301,7 @@ def _identity_net(select):
                 W2=W2.astype(np.float32), b2=np.zeros(8, np.float32))
 
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path, tile):
     # psi = h S exactly (network y[n'] = x[16 + n']): checks features,
     # reflection, normalisation and rescaling of the ANN sweep kernel; the
@@ -320,7 +320,7 @@ def test_ann_sweep_source_passthrough_net(api, ctx, tmp_path, tile):
     assert rel(phi, ref) <= 2 * 2.0 ** -8
 
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path, tile):
     # psi[n] = x-face inflow at the partner node: values are copied cell to
     # cell along x, so the fronts and their boundary values are exercised;
@@ -350,8 +350,9 @@ def test_problem_autotune_keeps_results(api, ctx):
     p = inputs.random_problem((10, 9, 8), 6, 3, seed=51)
     print_case("autotune", name=p["name"])
     prob = gpu_problem(api, ctx, p, "fp32")
-    tile, ms1, ms2 = prob.autotune()
-    assert tile in (1, 2) and ms1 > 0 and ms2 > 0
+    tile, ms = prob.autotune()
+    assert tile in (1, 2, 3) and len(ms) == 3 and min(ms) > 0
+    assert ms[tile - 1] == min(ms)
     assert prob.tile() == tile
     S = nodal_source(p, seed=5)
     phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
@@ -405,3 +406,36 @@ def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles):
             ref = probs[k].sweep(srcs[k]).cpu().numpy()
             assert np.array_equal(got, ref), k
     batch.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_transport_solve_autograd(api, ctx, precision, tol):
+    # J = sum_box (sigma_t - sigma_s) int phi through torch autograd: the
+    # direct term by torch, the solve term by the adjoint sweep; against the
+    # oracle's adjoint plus the same direct term
+    p = inputs.adjoint_box(n=6, groups=2, seed=9, box=(1, 4))
+    print_case("autograd", name=p["name"], precision=precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    om, w = api.quadrature_ls(p["order"])
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision=precision,
+                       store_psi=True)
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    box = torch.tensor(p["box_mask"], device="cuda")
+    st = torch.tensor(p["sigma_t"], dtype=dt, device="cuda", requires_grad=True)
+    q = torch.tensor(p["q"], dtype=dt, device="cuda", requires_grad=True)
+    ss = torch.tensor(p["sigma_s"], dtype=dt, device="cuda")
+    si_tol = 1e-13 if precision == "fp64" else 1e-7
+    phi = api.TransportSolve.apply(prob, st, q, ss, si_tol, 2000)
+    J = (((st - ss) * box)[..., None] * phi).sum() * (V / 8)
+    J.backward()
+    om_o, w_o = oracle.lq_n(p["order"])
+    mesh = mesh_of(p)
+    ref = oracle.source_iterate(mesh, om_o, w_o, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-14, max_iter=3000, store_psi=True)
+    g = np.zeros((p["groups"], 216, 8))
+    g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
+    a = oracle.adjoint(mesh, om_o, w_o, p["sigma_t"], p["sigma_s"], ref["psi"], ref["phi"], g,
+                       tol=1e-14)
+    direct = p["box_mask"][None, :] * ref["phi"].sum(-1) * (V / 8)
+    assert rel(st.grad.cpu().numpy(), a["grad_sigma_t"] + direct) <= tol
+    assert rel(q.grad.cpu().numpy(), a["grad_q"]) <= tol
