@@ -9,10 +9,11 @@ build, one full sweep (all hyperplanes, octants, directions, groups), octant
 reduction and the FP64 residual.  value = cell*direction*group solves per
 second over the timed steps.
 
-Also reported: the roofline of the dominant kernel (the hyperplane sweep
-kernel, HBM-bound by its algorithmic bytes s*(24*solves + 17*cells*groups)),
-timed with HIP events around every sweep launch, and the FP64 CPU oracle on a
-bounded sample of the same workload.
+Also reported: the roofline of the dominant kernel (the sweep kernel chosen
+by the autotuner -- one dataflow launch per sweep or one launch per tile
+hyperplane -- HBM-bound by its algorithmic bytes), timed with HIP events
+around every sweep launch, and the FP64 CPU oracle on a bounded sample of the
+same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -85,9 +86,9 @@ def main():
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
     prob.set_inflow(p["psi_inc"])
-    tile, ms = prob.autotune()
-    log(f"autotune: tile {tile} (one sweep " +
-        ", ".join(f"{m:.3f} ms with {b}^3" for b, m in enumerate(ms, 1)) + ")")
+    tile, sched, times = prob.autotune()
+    log(f"autotune: tile {tile}, {sched} schedule (one sweep: " +
+        ", ".join(f"{s} {b}^3 {m:.3f} ms" for (s, b), m in times.items()) + ")")
     st = prob.stats()
     solves = st["solves_per_sweep"]
     phi = torch.zeros((p["groups"], prob.ncell, 8), dtype=torch.float32, device="cuda")
@@ -122,7 +123,10 @@ def main():
     achieved = st["algo_bytes_per_sweep"] / (sweep_kernel_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"sweep_tile_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles>",
+            "kernel": (f"sweep_flow_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles> "
+                       "(one dataflow launch per sweep)" if sched == "dataflow" else
+                       f"sweep_tile_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles> "
+                       "(one launch per tile hyperplane)"),
             "launches_per_sweep": kern_launches // args.steps,
             "kernel_ms_per_sweep": round(sweep_kernel_ms, 4),
             "avg_launch_us": round(1e3 * kern_ms / max(kern_launches, 1), 3),

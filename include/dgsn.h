@@ -173,12 +173,35 @@ int dgsn_problem_set_tile(dgsn_problem *p, int b);
 int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
 
 /*
- * Autotuner: times one sweep of the problem with each tile edge 1..3 (on its
- * internal buffers; user arrays are not touched), keeps the fastest, and
- * returns the choice and the times in ms (ms_per_tile: host [3], may be
- * NULL).  Synchronizes stream.
+ * Sweep schedule (GE solvers; the ANN solver always uses the hyperplane
+ * schedule).  The sweep order follows from the upwind dependence of each cell
+ * on its three inflow neighbours (the sweep paragraph after Eq. (T12)).
+ *   DGSN_SCHED_PLANES: one kernel launch per (tile) hyperplane (default).
+ *   DGSN_SCHED_DATAFLOW: one launch per sweep; workgroups take blocks of
+ *     tiles in hyperplane order from a device ticket counter and wait on
+ *     device counters until their octant's previous hyperplane is complete.
+ *     Every wait is bounded by poll_limit polls (0: the library default,
+ *     about a second); if one expires the launch still completes, its results
+ *     are invalid, and the next dgsn_problem_check (also run inside
+ *     dgsn_source_iterate, dgsn_adjoint_solve and the autotuner) returns
+ *     DGSN_EHIP and clears the condition.  Two dataflow sweeps of one problem
+ *     must not run concurrently (they share the counters).
+ * dgsn_problem_check: synchronizes stream and reports an expired dataflow
+ *   wait since the last check.
  */
-int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_per_tile);
+enum { DGSN_SCHED_PLANES = 0, DGSN_SCHED_DATAFLOW = 1 };
+int dgsn_problem_set_schedule(dgsn_problem *p, int schedule, unsigned poll_limit);
+int dgsn_problem_get_schedule(const dgsn_problem *p, int *schedule);
+int dgsn_problem_check(dgsn_problem *p, void *stream);
+
+/*
+ * Autotuner: times one sweep of the problem with each tile edge 1..3 and each
+ * schedule (on its internal buffers; user arrays are not touched), keeps the
+ * fastest, and returns the choice and the times in ms (ms: host [6], entry
+ * schedule * 3 + edge - 1, INFINITY where not applicable; tile, schedule, ms
+ * may be NULL).  Synchronizes stream.
+ */
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, int *schedule, double *ms);
 
 /*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses

@@ -24,6 +24,8 @@ DGSN_ANN = 1
 DGSN_GE_DENSE = 2
 DGSN_SI_MAXNORM = 0
 DGSN_SI_EPS_S = 1
+DGSN_SCHED_PLANES = 0
+DGSN_SCHED_DATAFLOW = 1
 
 ERROR_NAMES = {
     DGSN_EINVAL: "DGSN_EINVAL", DGSN_ENOMEM: "DGSN_ENOMEM", DGSN_EHIP: "DGSN_EHIP",
@@ -81,7 +83,10 @@ SIGNATURES = {
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_set_tile": (_I, [_VP, _I]),
     "dgsn_problem_get_tile": (_I, [_VP, _PI]),
-    "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PD]),
+    "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PI, _PD]),
+    "dgsn_problem_set_schedule": (_I, [_VP, _I, ctypes.c_uint]),
+    "dgsn_problem_get_schedule": (_I, [_VP, _PI]),
+    "dgsn_problem_check": (_I, [_VP, _VP]),
     "dgsn_problem_kernel_time": (_I, [_VP, _PD, _PI]),
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),

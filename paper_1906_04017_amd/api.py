@@ -189,14 +189,33 @@ class Problem:
         _lib.check(_lib.load().dgsn_problem_get_tile(self._h, ctypes.byref(b)))
         return b.value
 
+    def set_schedule(self, schedule, poll_limit=0):
+        """'planes' (one launch per hyperplane) or 'dataflow' (one launch per
+        sweep, device counters between hyperplanes; GE solvers)."""
+        sc = {"planes": _lib.DGSN_SCHED_PLANES, "dataflow": _lib.DGSN_SCHED_DATAFLOW}[schedule]
+        _lib.check(_lib.load().dgsn_problem_set_schedule(self._h, sc, int(poll_limit)))
+
+    def schedule(self):
+        s = ctypes.c_int(0)
+        _lib.check(_lib.load().dgsn_problem_get_schedule(self._h, ctypes.byref(s)))
+        return ("planes", "dataflow")[s.value]
+
+    def check(self):
+        """Synchronize and raise if a dataflow wait expired since the last check."""
+        _lib.check(_lib.load().dgsn_problem_check(self._h, _stream(self.ctx.device)))
+
     def autotune(self):
-        """Time one sweep with each tile edge 1..3 and keep the fastest;
-        returns (tile, [ms with edge 1, 2, 3])."""
+        """Time one sweep with each tile edge 1..3 and schedule and keep the
+        fastest; returns (tile, schedule, {(schedule, tile): ms})."""
         t = ctypes.c_int(0)
-        ms = np.zeros(3)
+        s = ctypes.c_int(0)
+        ms = np.zeros(6)
         _lib.check(_lib.load().dgsn_problem_autotune(self._h, _stream(self.ctx.device),
-                                                     ctypes.byref(t), ms.ctypes.data_as(_lib._PD)))
-        return t.value, ms.tolist()
+                                                     ctypes.byref(t), ctypes.byref(s),
+                                                     ms.ctypes.data_as(_lib._PD)))
+        names = ("planes", "dataflow")
+        times = {(names[k // 3], k % 3 + 1): float(ms[k]) for k in range(6) if np.isfinite(ms[k])}
+        return t.value, names[s.value], times
 
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))

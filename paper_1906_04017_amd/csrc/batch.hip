@@ -69,19 +69,20 @@ __global__ __launch_bounds__(256) void batch_step(BatchStepArgs S)
     const int d = tid - q1 * (int)A.Do;
     const int g = q1 - z * (int)A.G;
     const bool lane_ok = z < nc;
-    const int ti = bx * nc + z;
     const int dl = lane_ok ? d : 0, gl = lane_ok ? g : 0;
+    bool tv;
+    const uint32_t pt = step_tile(A.cells, A.ncp, bx * nc + z, lane_ok, tv);
     if (solver == DGSN_ANN) {
         if (tileb == 2)
-            tile_body<float, kFormAnn, 2, false, false>(A, dl, gl, tid, ti, o, lane_ok, L, &al);
+            tile_body<float, kFormAnn, 2, false, false>(A, dl, gl, tid, tv, pt, o, lane_ok, L, &al);
         else
-            tile_body<float, kFormAnn, 1, false, false>(A, dl, gl, tid, ti, o, lane_ok, L, &al);
+            tile_body<float, kFormAnn, 1, false, false>(A, dl, gl, tid, tv, pt, o, lane_ok, L, &al);
     } else {
         if (tileb == 2)
-            tile_body<float, kFormMassInv, 2, false, false>(A, dl, gl, tid, ti, o, lane_ok, L,
+            tile_body<float, kFormMassInv, 2, false, false>(A, dl, gl, tid, tv, pt, o, lane_ok, L,
                                                             nullptr);
         else
-            tile_body<float, kFormMassInv, 1, false, false>(A, dl, gl, tid, ti, o, lane_ok, L,
+            tile_body<float, kFormMassInv, 1, false, false>(A, dl, gl, tid, tv, pt, o, lane_ok, L,
                                                             nullptr);
     }
     if (S.step == S.meta[4 * b + 2]) {

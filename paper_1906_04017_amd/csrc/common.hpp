@@ -45,7 +45,7 @@ constexpr int kMaxTile = 3;       // largest tile edge of the sweep
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
 
 const void *ann_device_params(const dgsn_ann *a);
-int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[3]);
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[6]);
 
 // ---- device allocation helper ------------------------------------------------
 struct DevBuf {
@@ -95,6 +95,15 @@ struct dgsn_problem {
     // packed tile coordinates, tile-hyperplane major (B = 1 is the cell
     // schedule above)
     int tile_b = 2;                  // tile edge used by the sweep (1, 2 or 3)
+    // dataflow schedule (one launch per sweep, GE solvers): per tile edge B
+    // (1 = cells) the first unit and the first tile of every step, on device
+    int schedule = DGSN_SCHED_PLANES;
+    int flow_ready = 0;
+    dgsn::DevBuf d_unit_map[4];      // uint4 per unit of one octant (built on first use)
+    dgsn::DevBuf d_unit_dep[4];      // uint2 per unit: range of units it waits for
+    unsigned flow_units[4] = {0, 0, 0, 0};   // units per octant
+    dgsn::DevBuf d_flow_sync;        // tickets, error word, done flags [8][units per octant]
+    unsigned flow_spin = 0;          // 0: default poll limit
     int n_tplanes[4] = {0, 0, 0, 0};
     std::vector<int> tplane_off[4];  // [n_tplanes[B] + 1]
     dgsn::DevBuf d_tiles[4];

@@ -1,0 +1,164 @@
+// Dataflow schedule of the tile sweep (the sweep paragraph after Eq. (T12):
+// a cell is solved once its upwind neighbours are known).
+//
+// The hyperplane schedule issues one launch per tile hyperplane and pays a
+// kernel boundary (drain, cache write-back, dispatch) at each of them, and
+// every block of a hyperplane waits for the slowest block of the previous
+// one.  Here one launch covers the whole sweep and each unit -- a block of
+// tiles of one octant in one step -- waits only for the units of the previous
+// step that hold the upwind neighbours of its tiles (a short range, computed
+// on the host), so consecutive steps overlap.  Workgroup b serves octant
+// b & 7 and takes the octant's next unit from its ticket counter, in
+// step-major order; eight counters on separate cache lines keep the
+// same-address atomics apart.
+//
+// Progress: a unit waits only on units of its octant with smaller tickets;
+// those were taken by workgroups that are already resident, so the oldest
+// unfinished unit of every octant can always run and the launch drains.
+// Every wait is also bounded (spin_limit polls); a unit whose wait expires
+// raises the error word, which makes every other wait give up too, and the
+// host reports the error.
+//
+// Reuse of the in-place fronts is safe: the three face slots a tile reads and
+// overwrites are touched only along one upwind chain of tiles, each of which
+// waits for the previous one.
+//
+// Visibility across the XCDs (each has its own L2): the fronts are accessed
+// with device-coherent buffer operations in this kernel (see front_load), so
+// a producer only waits until its front stores are acknowledged before it
+// sets its done flag, and a consumer that has seen the flags reads the fronts
+// without a cache invalidation.  The other arrays are read-only during the
+// launch or read only by later kernels.
+#include "sweep_body.hpp"
+
+namespace dgsn {
+
+namespace {
+
+__device__ __forceinline__ unsigned flow_load(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned flow_add(unsigned *p, unsigned v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0: take a ticket of octant o and wait for the unit's dependencies
+// (one flag per lane, up to 64 at a time); sh = the unit's map entry.
+__device__ __forceinline__ void flow_take(const FlowArgs &F, unsigned o, int lane, uint4 *sh)
+{
+    unsigned t = 0;
+    if (lane == 0) t = flow_add(F.sync + kFlowTicket + 32 * o, 1u);
+    t = __shfl(t, 0);
+    if (t >= F.units_o) t = F.units_o - 1;
+    const uint2 dep = F.unit_dep[t];
+    const unsigned *done = F.sync + kFlowDone + o * F.units_o;
+    for (unsigned base = dep.x; base <= dep.y; base += 64) {
+        const unsigned idx = base + lane;
+        bool ok = idx > dep.y;
+        for (unsigned it = 0;; ++it) {
+            if (!ok) ok = flow_load(done + idx) != 0u;
+            if (__all(ok)) break;
+            if (it >= F.spin_limit || __any(flow_load(F.sync + kFlowError) != 0u)) {
+                if (lane == 0)
+                    __hip_atomic_store(F.sync + kFlowError, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                base = dep.y;   // give up the remaining flags too
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    if (lane == 0) {
+        *sh = F.unit_map[t];
+        sh[1].x = t;
+    }
+}
+
+// Every thread: publish this unit's fronts and flag it done.
+__device__ __forceinline__ void flow_finish(const FlowArgs &F, int tid, unsigned o, unsigned t)
+{
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's coherent front stores are acknowledged
+    __syncthreads();
+    if (tid == 0)
+        __hip_atomic_store(F.sync + kFlowDone + o * F.units_o + t, 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Clears the tickets and done counts (not the error word) before a launch.
+__global__ __launch_bounds__(256) void flow_reset(unsigned *sync, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (i != kFlowError) sync[i] = 0u;
+}
+
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
+__global__ __launch_bounds__(256) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
+{
+    // block = (direction, group, tile) lanes as in the hyperplane kernel;
+    // A.cells is the whole tile list of the schedule
+    __shared__ TileLds<Real> L;
+    __shared__ uint4 sh[2];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const unsigned o = blockIdx.x & 7u;
+    if (tid < 64) flow_take(F, o, tid, sh);
+    __syncthreads();
+    const uint4 u = sh[0];
+    const unsigned t = sh[1].x;
+    bool tvalid;
+    const uint32_t pt = step_tile(A.cells + u.z, u.w, (int)u.y * blockDim.z + threadIdx.z, true,
+                                  tvalid);
+    tile_body<Real, Form, B, kStorePsi, kAdjoint, true>(A, threadIdx.x, threadIdx.y, tid, tvalid,
+                                                        pt, (int)o, true, L, nullptr);
+    flow_finish(F, tid, o, t);
+}
+
+template <typename Real, int Form, int B>
+void launch_flow_form(const PlaneArgs<Real> &A, const FlowArgs &F, bool store_psi, bool adjoint,
+                      dim3 grid, dim3 block, hipStream_t s)
+{
+    if (adjoint)
+        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true>), grid, block, 0, s, A, F);
+    else if (store_psi)
+        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false>), grid, block, 0, s, A, F);
+    else
+        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false>), grid, block, 0, s, A, F);
+}
+
+template <typename Real, int Form>
+void launch_flow_b(const PlaneArgs<Real> &A, const FlowArgs &F, int b, bool store_psi,
+                   bool adjoint, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (b) {
+    case 3: launch_flow_form<Real, Form, 3>(A, F, store_psi, adjoint, grid, block, s); break;
+    case 2: launch_flow_form<Real, Form, 2>(A, F, store_psi, adjoint, grid, block, s); break;
+    default: launch_flow_form<Real, Form, 1>(A, F, store_psi, adjoint, grid, block, s); break;
+    }
+}
+
+}  // namespace
+
+template <typename Real>
+int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bool store_psi,
+                bool adjoint, hipStream_t s)
+{
+    const dim3 block(A.Do, A.G, cells_per_block(A.Do, A.G));
+    const dim3 grid(8 * F.units_o);
+    const int words = kFlowDone + 8 * (int)F.units_o;
+    hipLaunchKernelGGL(flow_reset, dim3((words + 255) / 256), dim3(256), 0, s, F.sync, words);
+    if (form == kFormDense)
+        launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
+    else
+        launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template int launch_flow<float>(const PlaneArgs<float> &, const FlowArgs &, int, int, bool, bool,
+                                hipStream_t);
+template int launch_flow<double>(const PlaneArgs<double> &, const FlowArgs &, int, int, bool,
+                                 bool, hipStream_t);
+
+}  // namespace dgsn

@@ -36,6 +36,32 @@ struct PlaneArgs {
     Real inc[8][3];            // inflow value per octant slot and canonical axis
 };
 
+// Dataflow schedule of a sweep: one launch processes every step.  Workgroup
+// b serves octant b & 7; it takes the next unit of its octant (a block of
+// tiles in one step) from that octant's ticket counter, in step-major order,
+// waits until the units of the previous step that hold its tiles' upwind
+// neighbours are done, solves its tiles and flags itself done.  A unit only
+// waits on units of its octant with smaller tickets, held by workgroups that
+// are already running, so the launch always drains; every wait is also
+// bounded by spin_limit polls, after which the unit raises the error word and
+// proceeds.  A fill kernel clears the tickets and flags before each launch.
+struct FlowArgs {
+    // per unit of one octant, in ticket order: x = step, y = block of tiles
+    // within the step, z = first tile of the step in the tile list, w = tiles
+    // in the step
+    const uint4 *unit_map;
+    // per unit: the units (of the same octant) it waits for, [x, y]; x > y
+    // for none
+    const uint2 *unit_dep;
+    unsigned *sync;            // tickets (one 128-byte line per octant), error word, done[8][units_o]
+    unsigned units_o;          // units per octant; the launch has 8 * units_o workgroups
+    unsigned spin_limit;       // polls of one wait before it gives up
+};
+constexpr int kFlowTicket = 0;      // + 32 * octant
+constexpr int kFlowError = 256;
+constexpr int kFlowDone = 288;      // + octant * units_o + unit
+constexpr unsigned kFlowSpinDefault = 1u << 20;
+
 template <typename Real>
 struct ReduceArgs {
     const Real *phi_oct;       // [8][nv][8]
@@ -68,6 +94,9 @@ int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 template <typename Real>
 int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,
                 hipStream_t s);
+template <typename Real>
+int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bool store_psi,
+                bool adjoint, hipStream_t s);
 template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);
 template <typename Real>

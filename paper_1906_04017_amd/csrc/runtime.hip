@@ -177,6 +177,84 @@ PlaneArgs<Real> plane_args(dgsn_problem *p, const void *src, bool adjoint)
     return A;
 }
 
+// Unit maps of the dataflow schedule for every tile edge: units are blocks of
+// cells_per_block tiles of one octant in one step, in step-major order; each
+// depends on the units of the previous step that hold the upwind neighbours
+// (i-1, j, k), (i, j-1, k), (i, j, k-1) of its tiles.
+int flow_prepare(dgsn_problem *p)
+{
+    if (p->flow_ready) return DGSN_OK;
+    const long long nmax = std::max(std::max(p->n[0], p->n[1]), p->n[2]);
+    if (nmax * nmax * 8 * 4 * p->Do * p->G * (long long)p->real_size >= (1LL << 31))
+        return set_error(DGSN_EUNSUPPORTED, "the dataflow schedule needs face fronts under 2 GiB");
+    const int nc = cells_per_block(p->Do, p->G);
+    unsigned umax = 0;
+    for (int tb = 1; tb <= kMaxTile; ++tb) {
+        const std::vector<int> &off = tb == 1 ? p->plane_off : p->tplane_off[tb];
+        const int T[3] = {(p->n[0] + tb - 1) / tb, (p->n[1] + tb - 1) / tb,
+                          (p->n[2] + tb - 1) / tb};
+        const int ns = (int)off.size() - 1;
+        std::vector<uint4> map;
+        std::vector<uint2> dep;
+        std::vector<int> pos((size_t)T[1] * T[2], -1);   // (j, k) -> index in the previous step
+        std::vector<int> cur;
+        int ubase_prev = 0;
+        for (int st = 0; st < ns; ++st) {
+            const int cnt = off[st + 1] - off[st];
+            const unsigned nb = (unsigned)((cnt + nc - 1) / nc);
+            if (8ull * (map.size() + nb) > (1ull << 31))
+                return set_error(DGSN_EUNSUPPORTED, "too many dataflow units");
+            const int ubase = (int)map.size();
+            // tiles of this step, in the order of the tile list (k outer, j inner)
+            cur.clear();
+            for (int kk = 0; kk < T[2]; ++kk)
+                for (int jj = 0; jj < T[1]; ++jj) {
+                    const int ii = st - jj - kk;
+                    if (ii >= 0 && ii < T[0]) cur.push_back(ii | jj << 10 | kk << 20);
+                }
+            if ((int)cur.size() != cnt) return set_error(DGSN_EINVAL, "inconsistent tile schedule");
+            for (unsigned l = 0; l < nb; ++l) {
+                unsigned lo = UINT32_MAX, hi = 0;
+                for (int q = (int)l * nc; q < std::min(cnt, (int)(l + 1) * nc); ++q) {
+                    const int ii = cur[q] & 1023, jj = (cur[q] >> 10) & 1023, kk = cur[q] >> 20;
+                    int up[3] = {-1, -1, -1};
+                    if (ii > 0) up[0] = pos[(size_t)kk * T[1] + jj];
+                    if (jj > 0) up[1] = pos[(size_t)kk * T[1] + jj - 1];
+                    if (kk > 0) up[2] = pos[(size_t)(kk - 1) * T[1] + jj];
+                    for (int a = 0; a < 3; ++a)
+                        if (up[a] >= 0) {
+                            const unsigned u = (unsigned)(ubase_prev + up[a] / nc);
+                            lo = std::min(lo, u);
+                            hi = std::max(hi, u);
+                        }
+                }
+                if (lo == UINT32_MAX) {
+                    lo = 1;
+                    hi = 0;
+                }
+                map.push_back(make_uint4((unsigned)st, l, (unsigned)off[st], (unsigned)cnt));
+                dep.push_back(make_uint2(lo, hi));
+            }
+            for (int q = 0; q < cnt; ++q)
+                pos[(size_t)(cur[q] >> 20) * T[1] + ((cur[q] >> 10) & 1023)] = q;
+            ubase_prev = ubase;
+        }
+        DGSN_TRY(p->d_unit_map[tb].alloc(map.size() * sizeof(uint4)));
+        DGSN_TRY(p->d_unit_dep[tb].alloc(dep.size() * sizeof(uint2)));
+        DGSN_HIP(hipMemcpy(p->d_unit_map[tb].ptr, map.data(), map.size() * sizeof(uint4),
+                           hipMemcpyHostToDevice));
+        DGSN_HIP(hipMemcpy(p->d_unit_dep[tb].ptr, dep.data(), dep.size() * sizeof(uint2),
+                           hipMemcpyHostToDevice));
+        p->flow_units[tb] = (unsigned)map.size();
+        umax = std::max(umax, p->flow_units[tb]);
+    }
+    const size_t words = kFlowDone + 8 * (size_t)umax;
+    DGSN_TRY(p->d_flow_sync.alloc(words * sizeof(unsigned)));
+    DGSN_HIP(hipMemset(p->d_flow_sync.ptr, 0, words * sizeof(unsigned)));
+    p->flow_ready = 1;
+    return DGSN_OK;
+}
+
 template <typename Real>
 int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Real *grad_oct,
               hipStream_t s)
@@ -199,6 +277,24 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const int nsteps = tiled ? p->n_tplanes[tb] : p->n_planes;
     p->last_stream = s;
     p->ev_used = 0;
+    if (p->schedule == DGSN_SCHED_DATAFLOW && !ann) {
+        DGSN_TRY(flow_prepare(p));
+        FlowArgs F{};
+        F.unit_map = static_cast<const uint4 *>(p->d_unit_map[tb].ptr);
+        F.unit_dep = static_cast<const uint2 *>(p->d_unit_dep[tb].ptr);
+        F.sync = static_cast<unsigned *>(p->d_flow_sync.ptr);
+        F.units_o = p->flow_units[tb];
+        F.spin_limit = p->flow_spin ? p->flow_spin : kFlowSpinDefault;
+        A.cells = cells;
+        A.ncp = off[nsteps];
+        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[0], s));
+        DGSN_TRY(launch_flow<Real>(A, F, form, tb, store_psi, adjoint, s));
+        if (p->timing) {
+            DGSN_HIP(hipEventRecord(p->ev[1], s));
+            p->ev_used = 1;
+        }
+        return DGSN_OK;
+    }
     for (int pl = 0; pl < nsteps; ++pl) {
         A.cells = cells + off[pl];
         A.ncp = off[pl + 1] - off[pl];
@@ -231,9 +327,26 @@ ReduceArgs<Real> reduce_args(dgsn_problem *p, void *phi)
     return R;
 }
 
+// Reads the dataflow error word (stream-ordered) and clears it; fails if a
+// wait of a dataflow launch gave up.
+int check_flow(dgsn_problem *p, hipStream_t s)
+{
+    if (!p->flow_ready) return DGSN_OK;
+    unsigned err = 0;
+    DGSN_HIP(hipMemcpyAsync(&err, static_cast<unsigned *>(p->d_flow_sync.ptr) + kFlowError,
+                            sizeof(err), hipMemcpyDeviceToHost, s));
+    DGSN_HIP(hipStreamSynchronize(s));
+    if (err == 0u) return DGSN_OK;
+    DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
+    DGSN_HIP(hipStreamSynchronize(s));
+    return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its results are "
+                     "invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
+}
+
 int read_result(dgsn_problem *p, hipStream_t s, double out[3])
 {
     DGSN_HIP(hipMemcpyAsync(out, p->red_result.ptr, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (p->schedule == DGSN_SCHED_DATAFLOW) return check_flow(p, s);
     DGSN_HIP(hipStreamSynchronize(s));
     return DGSN_OK;
 }
@@ -367,7 +480,7 @@ int batch_reduce(dgsn_problem *p, void *phi, hipStream_t s)
 // Time one sweep of the problem with each tile edge on its internal source
 // buffer and keep the faster (ties keep 2).  The problem's outputs are not
 // touched (only its internal partials and fronts).
-int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[kMaxTile])
+int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2 * kMaxTile])
 {
     if (p->solver == DGSN_ANN && !p->ann) return set_error(DGSN_EINVAL, "no ANN attached");
     hipEvent_t e0, e1;
@@ -375,31 +488,46 @@ int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[kMaxTile])
     DGSN_HIP(hipEventCreate(&e1));
     const int saved_timing = p->timing;
     p->timing = 0;
-    double best[kMaxTile] = {};
-    for (int b = 0; b < kMaxTile; ++b) best[b] = INFINITY;
+    // candidates: every tile edge with the hyperplane schedule, and with the
+    // dataflow schedule where it applies (GE solvers)
+    const int nsched = p->solver == DGSN_ANN || flow_prepare(p) != DGSN_OK ? 1 : 2;
+    clear_error();
+    double best[2][kMaxTile];
+    for (int sc = 0; sc < 2; ++sc)
+        for (int b = 0; b < kMaxTile; ++b) best[sc][b] = INFINITY;
     int rc = DGSN_OK;
-    for (int b = 1; b <= kMaxTile && rc == DGSN_OK; ++b) {
-        p->tile_b = b;
-        for (int rep = 0; rep < 3 && rc == DGSN_OK; ++rep) {
-            (void)hipEventRecord(e0, s);
-            rc = p->precision == DGSN_FP64
-                     ? run_sweep<double>(p, p->src.ptr, false, false, nullptr, s)
-                     : run_sweep<float>(p, p->src.ptr, false, false, nullptr, s);
-            (void)hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) rc = set_error(DGSN_EHIP, "timing failed");
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) best[b - 1] = std::min(best[b - 1], (double)ms);
+    for (int sc = 0; sc < nsched && rc == DGSN_OK; ++sc)
+        for (int b = 1; b <= kMaxTile && rc == DGSN_OK; ++b) {
+            p->tile_b = b;
+            p->schedule = sc;
+            for (int rep = 0; rep < 3 && rc == DGSN_OK; ++rep) {
+                (void)hipEventRecord(e0, s);
+                rc = p->precision == DGSN_FP64
+                         ? run_sweep<double>(p, p->src.ptr, false, false, nullptr, s)
+                         : run_sweep<float>(p, p->src.ptr, false, false, nullptr, s);
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess)
+                    rc = set_error(DGSN_EHIP, "timing failed");
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) best[sc][b - 1] = std::min(best[sc][b - 1], (double)ms);
+            }
+            if (rc == DGSN_OK && sc == DGSN_SCHED_DATAFLOW) rc = check_flow(p, s);
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->timing = saved_timing;
-    int bi = 1;
-    for (int b = 2; b <= kMaxTile; ++b)
-        if (best[b - 1] < best[bi - 1]) bi = b;
+    int bi = 1, si = 0;
+    for (int sc = 0; sc < nsched; ++sc)
+        for (int b = 1; b <= kMaxTile; ++b)
+            if (best[sc][b - 1] < best[si][bi - 1]) {
+                bi = b;
+                si = sc;
+            }
     p->tile_b = bi;
-    for (int b = 0; b < kMaxTile; ++b) ms_out[b] = best[b];
+    p->schedule = si;
+    for (int sc = 0; sc < 2; ++sc)
+        for (int b = 0; b < kMaxTile; ++b) ms_out[sc * kMaxTile + b] = best[sc][b];
     return rc;
 }
 
@@ -409,17 +537,50 @@ extern "C" {
 
 int dgsn_version(void) { return 10000; }
 
-int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, double *ms_per_tile)
+int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, int *schedule,
+                          double *ms)
 {
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
-    double ms[kMaxTile];
-    DGSN_TRY(autotune_problem(p, as_stream(stream), ms));
+    double t[2 * kMaxTile];
+    DGSN_TRY(autotune_problem(p, as_stream(stream), t));
     if (tile) *tile = p->tile_b;
-    if (ms_per_tile)
-        for (int b = 0; b < kMaxTile; ++b) ms_per_tile[b] = ms[b];
+    if (schedule) *schedule = p->schedule;
+    if (ms)
+        for (int b = 0; b < 2 * kMaxTile; ++b) ms[b] = t[b];
     return DGSN_OK;
+}
+
+int dgsn_problem_set_schedule(dgsn_problem *p, int schedule, unsigned poll_limit)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (schedule != DGSN_SCHED_PLANES && schedule != DGSN_SCHED_DATAFLOW)
+        return set_error(DGSN_EINVAL, "unknown schedule %d", schedule);
+    if (schedule == DGSN_SCHED_DATAFLOW) {
+        DGSN_HIP(hipSetDevice(p->ctx->device));
+        DGSN_TRY(flow_prepare(p));
+    }
+    p->schedule = schedule;
+    p->flow_spin = poll_limit;
+    return DGSN_OK;
+}
+
+int dgsn_problem_get_schedule(const dgsn_problem *p, int *schedule)
+{
+    clear_error();
+    if (!p || !schedule) return set_error(DGSN_EINVAL, "problem and schedule must be set");
+    *schedule = p->schedule;
+    return DGSN_OK;
+}
+
+int dgsn_problem_check(dgsn_problem *p, void *stream)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    return check_flow(p, as_stream(stream));
 }
 
 const char *dgsn_last_error(void) { return dgsn::g_msg; }

@@ -29,8 +29,10 @@ __global__ __launch_bounds__(256) void sweep_tile_ge(PlaneArgs<Real> A)
     // block = (direction, group, tile) lanes, grid = (tile groups, octant)
     __shared__ TileLds<Real> L;
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    tile_body<Real, Form, B, kStorePsi, kAdjoint>(A, threadIdx.x, threadIdx.y, tid,
-                                                  blockIdx.x * blockDim.z + threadIdx.z,
+    bool tvalid;
+    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * blockDim.z + threadIdx.z, true,
+                                  tvalid);
+    tile_body<Real, Form, B, kStorePsi, kAdjoint>(A, threadIdx.x, threadIdx.y, tid, tvalid, pt,
                                                   blockIdx.y, true, L, nullptr);
 }
 
@@ -49,8 +51,10 @@ __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
     const int d = tid - q1 * (int)A.Do;
     const int g = q1 - z * (int)A.G;
     const bool lane_ok = z < nc;
-    tile_body<float, kFormAnn, B, false, false>(A, lane_ok ? d : 0, lane_ok ? g : 0, tid,
-                                                blockIdx.x * nc + z, blockIdx.y, lane_ok, L, &al);
+    bool tvalid;
+    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * nc + z, lane_ok, tvalid);
+    tile_body<float, kFormAnn, B, false, false>(A, lane_ok ? d : 0, lane_ok ? g : 0, tid, tvalid,
+                                                pt, blockIdx.y, lane_ok, L, &al);
 }
 
 // phi = sum_o phi_oct[o]; optionally the FP64 SI residual partials and the

@@ -49,6 +49,64 @@ __device__ __forceinline__ void store4(Real *p, Real a, Real b, Real c, Real d)
     p[3] = d;
 }
 
+// Face-front access.  The hyperplane kernels move fronts through the caches
+// (the kernel boundary between two steps writes the L2s back).  The dataflow
+// kernel hands fronts between workgroups of one launch that may run on
+// different XCDs, each with its own L2, so it uses device-scope coherent
+// buffer operations (cache policy sc1): loads do not hit stale L2 lines and
+// stores write through.  Byte offsets are 32-bit (fronts under 2 GiB) and the
+// hardware bounds-checks every access against the buffer size.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCpolDevice = 16;               // sc1
+constexpr int kRawBufferWord3 = 0x00020000;   // untyped 32-bit buffer, gfx9 family
+
+template <typename Real>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t front_rsrc(Real *base, uint32_t elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(elems * sizeof(Real)),
+                                             kRawBufferWord3);
+}
+
+template <typename Real, bool kCoh>
+__device__ __forceinline__ void front_load(const Real *base, __amdgpu_buffer_rsrc_t r, uint32_t e,
+                                           Real v[4])
+{
+    if constexpr (!kCoh) {
+        load4(base + e, v);
+    } else if constexpr (sizeof(Real) == 4) {
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, e * 4u, 0, kCpolDevice);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = __uint_as_float(u[k]);
+    } else {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, e * 8u, 0, kCpolDevice);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, e * 8u + 16u, 0, kCpolDevice);
+        v[0] = __hiloint2double((int)a[1], (int)a[0]);
+        v[1] = __hiloint2double((int)a[3], (int)a[2]);
+        v[2] = __hiloint2double((int)b[1], (int)b[0]);
+        v[3] = __hiloint2double((int)b[3], (int)b[2]);
+    }
+}
+
+template <typename Real, bool kCoh>
+__device__ __forceinline__ void front_store(Real *base, __amdgpu_buffer_rsrc_t r, uint32_t e,
+                                            Real a, Real b, Real c, Real d)
+{
+    if constexpr (!kCoh) {
+        store4(base + e, a, b, c, d);
+    } else if constexpr (sizeof(Real) == 4) {
+        const u32x4 u = {__float_as_uint(a), __float_as_uint(b), __float_as_uint(c),
+                         __float_as_uint(d)};
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, e * 4u, 0, kCpolDevice);
+    } else {
+        const u32x4 u = {(unsigned)__double2loint(a), (unsigned)__double2hiint(a),
+                         (unsigned)__double2loint(b), (unsigned)__double2hiint(b)};
+        const u32x4 w = {(unsigned)__double2loint(c), (unsigned)__double2hiint(c),
+                         (unsigned)__double2loint(d), (unsigned)__double2hiint(d)};
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, e * 8u, 0, kCpolDevice);
+        __builtin_amdgcn_raw_buffer_store_b128(w, r, e * 8u + 16u, 0, kCpolDevice);
+    }
+}
+
 // Mass-inverse cell system (P_d + sigma_t I, S + sum_a kappa_a c_a), with the
 // structural zeros of P_d as literal zeros.
 template <typename Real>
@@ -166,6 +224,14 @@ __device__ __forceinline__ float ann_features(const float kap[3], float hh, floa
     return m;
 }
 
+// Tile ti of one schedule step (cells: the step's packed tiles, ncp of them).
+__device__ __forceinline__ uint32_t step_tile(const uint32_t *cells, uint32_t ncp, int ti,
+                                              bool lane_ok, bool &tvalid)
+{
+    tvalid = lane_ok && ti < (int)ncp;
+    return tvalid ? cells[ti] : 0u;
+}
+
 // LDS of the tile body: the direction reduction (double buffered), the
 // adjoint contraction reduction, and the ANN operand staging.
 template <typename Real>
@@ -180,17 +246,19 @@ struct AnnLds {
 
 // Device body of the tile sweep for one lane.  d, g: direction-in-octant and
 // group of the lane; tid: its index in the block (segments of Do lanes with
-// equal (group, tile) are contiguous); ti: its tile in the tile hyperplane;
+// equal (group, tile) are contiguous); tvalid: the lane has a tile, pt: its
+// packed canonical tile coordinates (i | j << 10 | k << 20, in tiles);
 // o: octant slot; lane_ok: the lane carries work.  Form: kFormMassInv,
 // kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
-// blocks of full waves).  Must be reached by every thread of the block.
-template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
-__device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g, int tid, int ti,
-                                          int o, bool lane_ok, TileLds<Real> &L, AnnLds *al)
+// blocks of full waves).  kCoh: device-coherent front access (dataflow
+// kernel).  Must be reached by every thread of the block.
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kCoh = false>
+__device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g, int tid,
+                                          bool tvalid, uint32_t pt, int o, bool lane_ok,
+                                          TileLds<Real> &L, AnnLds *al)
 {
     static_assert(Form != kFormAnn || sizeof(Real) == 4, "the ANN solver runs in FP32");
     const int mask = kAdjoint ? (o ^ 7) : o;
-    const bool tvalid = lane_ok && ti < (int)A.ncp;
     const uint32_t dg = d + A.Do * g;
     const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
     const Real w = lane_ok ? dp[kDirW] : Real(0);
@@ -199,12 +267,14 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
     if (Form == kFormAnn) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
     uint32_t I0 = 0, J0 = 0, K0 = 0;
     if (tvalid) {
-        const uint32_t pt = A.cells[ti];
         I0 = (pt & 1023u) * B;
         J0 = ((pt >> 10) & 1023u) * B;
         K0 = (pt >> 20) * B;
     }
     const uint32_t slot = (o * A.Do + d) * A.G + g;
+    const __amdgpu_buffer_rsrc_t rx = front_rsrc(A.fx, 8 * A.fx_o);
+    const __amdgpu_buffer_rsrc_t ry = front_rsrc(A.fy, 8 * A.fy_o);
+    const __amdgpu_buffer_rsrc_t rz = front_rsrc(A.fz, 8 * A.fz_o);
     Real xf[4] = {0, 0, 0, 0}, yf[B][4] = {}, zf[B][B][4] = {};
     // layers of the tile (kl) are a rolled loop for B > 2 (the layer body,
     // B^2 cells, is unrolled so that every register front index is static)
@@ -221,7 +291,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                 uint32_t c = 0;
                 Real gs = 0, gq = 0;
                 Real st = 0, sc[8], vx[4], vy[4], vz[4];
-                Real *fxp = nullptr, *fyp = nullptr, *fzp = nullptr;
+                uint32_t ex = 0, ey = 0, ez = 0;   // front slots (elements)
                 // gather: sigma_t, the reflected source and the three inflows
                 if (ok) {
                     const uint32_t i = (mask & 1) ? A.nx - 1 - ic : ic;
@@ -234,14 +304,14 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     load4(sp, sc);
                     load4(sp + 4, sc + 4);
                     reflect8(sc, mask);
-                    fxp = A.fx + (o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4);
-                    fyp = A.fy + (o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4);
-                    fzp = A.fz + (o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4);
+                    ex = o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4;
+                    ey = o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4;
+                    ez = o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4;
                     if (il > 0) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) vx[e] = xf[e];
                     } else if (ic) {
-                        load4(fxp, vx);
+                        front_load<Real, kCoh>(A.fx, rx, ex, vx);
                     } else {
                         vx[0] = vx[1] = vx[2] = vx[3] = A.inc[o][0];
                     }
@@ -249,7 +319,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
 #pragma unroll
                         for (int e = 0; e < 4; ++e) vy[e] = yf[il][e];
                     } else if (jc) {
-                        load4(fyp, vy);
+                        front_load<Real, kCoh>(A.fy, ry, ey, vy);
                     } else {
                         vy[0] = vy[1] = vy[2] = vy[3] = A.inc[o][1];
                     }
@@ -257,7 +327,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
 #pragma unroll
                         for (int e = 0; e < 4; ++e) vz[e] = zf[jl][il][e];
                     } else if (kc) {
-                        load4(fzp, vz);
+                        front_load<Real, kCoh>(A.fz, rz, ez, vz);
                     } else {
                         vz[0] = vz[1] = vz[2] = vz[3] = A.inc[o][2];
                     }
@@ -291,9 +361,12 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
                     zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
                     zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
-                    if (il == B - 1 && ic + 1 < A.nx) store4(fxp, psi[1], psi[3], psi[5], psi[7]);
-                    if (jl == B - 1 && jc + 1 < A.ny) store4(fyp, psi[2], psi[3], psi[6], psi[7]);
-                    if (kl == B - 1 && kc + 1 < A.nz) store4(fzp, psi[4], psi[5], psi[6], psi[7]);
+                    if (il == B - 1 && ic + 1 < A.nx)
+                        front_store<Real, kCoh>(A.fx, rx, ex, psi[1], psi[3], psi[5], psi[7]);
+                    if (jl == B - 1 && jc + 1 < A.ny)
+                        front_store<Real, kCoh>(A.fy, ry, ey, psi[2], psi[3], psi[6], psi[7]);
+                    if (kl == B - 1 && kc + 1 < A.nz)
+                        front_store<Real, kCoh>(A.fz, rz, ez, psi[4], psi[5], psi[6], psi[7]);
                     if (kStorePsi || (kAdjoint && A.grad_oct)) {
                         Real *pp = A.psi + ((size_t)slot * A.ncell + c) * 8;
                         if (kStorePsi) {

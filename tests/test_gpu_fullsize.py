@@ -53,6 +53,27 @@ def test_blocky_scatter_full_sweep_fp32(api, ctx):
         assert rel(phi[g], ref[g]) <= 1e-5, g
 
 
+def test_blocky_scatter_dataflow_schedule(api, ctx):
+    # the benchmark workload with the one-launch dataflow schedule, every
+    # tile edge: bitwise equal to the hyperplane schedule over repeated sweeps
+    p = inputs.blocky_scatter()
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32,
+                     device="cuda")
+    for tile in (1, 2, 3):
+        print_case("fullsize_dataflow", name=p["name"], tile=tile)
+        prob.set_tile(tile)
+        prob.set_schedule("planes")
+        ref = prob.sweep(S).clone()
+        prob.set_schedule("dataflow")
+        for _ in range(4):
+            got = prob.sweep(S)
+            prob.check()
+            assert torch.equal(got, ref), tile
+
+
 def test_paper_problems_full_sweep_fp32(api, ctx):
     # the paper's four problems at 128^3, S8: the two pure absorbers with
     # incident flux and a thin medium (groups 1-3 are one sweep from the

@@ -343,6 +343,80 @@ def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path, tile):
 
 
 # ---------------------------------------------------------------------------
+# dataflow schedule (one launch per sweep, device counters between steps)
+# ---------------------------------------------------------------------------
+
+FLOW_CASES = RAGGED + [((24, 20, 18), (1.2, 1.0, 0.9), 8, 3)]
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", FLOW_CASES, ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in FLOW_CASES])
+def test_dataflow_matches_planes_bitwise(api, ctx, precision, case, tile):
+    # same arithmetic in the same order: any stale front read across the
+    # device's caches would show up as a difference
+    n, L, order, G = case
+    print_case("dataflow", n=n, order=order, G=G, precision=precision, tile=tile)
+    p = inputs.random_problem(n, order, G, seed=(hash(case) + 1) % 1000, length=L)
+    prob = gpu_problem(api, ctx, p, precision)
+    prob.set_tile(tile)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    S = torch.tensor(nodal_source(p, seed=8), dtype=dt, device="cuda")
+    ref = prob.sweep(S).clone()
+    prob.set_schedule("dataflow")
+    assert prob.schedule() == "dataflow"
+    for _ in range(3):
+        got = prob.sweep(S)
+        prob.check()
+        assert torch.equal(got, ref)
+    om, w = oracle.lq_n(order)
+    want = oracle.sweep(mesh_of(p), om, w, p["sigma_t"], S.cpu().numpy(), p["psi_inc"])
+    assert rel(got.cpu().numpy(), want) <= (FP64_SWEEP_TOL if precision == "fp64" else FP32_TOL)
+
+
+def test_dataflow_source_iteration_and_adjoint(api, ctx):
+    p = inputs.adjoint_box(n=7, groups=2, seed=4, box=(2, 5))
+    print_case("dataflow_si_adjoint", name=p["name"])
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    g = np.zeros((p["groups"], 343, 8))
+    g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
+    out = {}
+    for sched in ("planes", "dataflow"):
+        prob = gpu_problem(api, ctx, p, "fp64", store_psi=True)
+        prob.set_tile(2)
+        prob.set_schedule(sched)
+        phi, info = prob.source_iterate(tol=1e-13, max_iter=1000)
+        gst, gq, _ = prob.adjoint(torch.tensor(g, device="cuda"), tol=1e-13, max_iter=1000)
+        out[sched] = (phi.cpu(), gst.cpu(), gq.cpu(), info["iters"])
+    a, b = out["planes"], out["dataflow"]
+    assert a[3] == b[3]
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+
+
+def test_dataflow_expired_wait_is_reported(api, ctx):
+    # a column of 64 cells: the unit of the last step waits for 63 sequential
+    # solves, far beyond a poll limit of 1; the launch must still complete,
+    # the host must report the expired wait, and the next sweep (default
+    # limit) must be exact again
+    p = inputs.random_problem((1, 1, 64), 2, 1, seed=5, length=(0.1, 0.1, 6.4))
+    print_case("dataflow_expired_wait", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32")
+    prob.set_tile(1)
+    S = torch.tensor(nodal_source(p, seed=3), dtype=torch.float32, device="cuda")
+    ref = prob.sweep(S).clone()
+    prob.set_schedule("dataflow", poll_limit=1)
+    prob.sweep(S)
+    with pytest.raises(api.DgsnError, match="dataflow"):
+        prob.check()
+    prob.check()   # the condition was cleared
+    prob.set_schedule("dataflow")
+    got = prob.sweep(S)
+    prob.check()
+    assert torch.equal(got, ref)
+
+
+# ---------------------------------------------------------------------------
 # autotuner and batched execution
 # ---------------------------------------------------------------------------
 
@@ -350,9 +424,10 @@ def test_problem_autotune_keeps_results(api, ctx):
     p = inputs.random_problem((10, 9, 8), 6, 3, seed=51)
     print_case("autotune", name=p["name"])
     prob = gpu_problem(api, ctx, p, "fp32")
-    tile, ms = prob.autotune()
-    assert tile in (1, 2, 3) and len(ms) == 3 and min(ms) > 0
-    assert ms[tile - 1] == min(ms)
+    tile, sched, times = prob.autotune()
+    assert tile in (1, 2, 3) and sched in ("planes", "dataflow") and len(times) == 6
+    assert min(times.values()) > 0 and times[(sched, tile)] == min(times.values())
+    assert prob.schedule() == sched
     assert prob.tile() == tile
     S = nodal_source(p, seed=5)
     phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
