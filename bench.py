@@ -18,6 +18,7 @@ same workload.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,46 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILES = {
+    # dominant kernel -> committed rocprofv3 memory-counter summary
+    ("dataflow", 2): "profiles/sweep_flow_ge_f32_tile2_blocky_scatter_64cube_S8_G8_hbm_traffic.txt",
+}
+
+
+def kernel_source_digest():
+    """Digest of the HIP sources; a traffic profile applies only to the kernel
+    it was measured on."""
+    d = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1906_04017_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            d.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                d.update(f.read())
+    return d.hexdigest()[:16]
+
+
+def measured_traffic(sched, tile, workload):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
+    None if there is none for this kernel and workload or the kernel sources
+    changed since it was taken."""
+    rel = TRAFFIC_PROFILES.get((sched, tile))
+    if rel is None or workload != "blocky_scatter_64^3_S8_G8":
+        return None
+    path = os.path.join(ROOT, rel)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -122,7 +163,8 @@ def main():
     sweep_kernel_ms = kern_ms / args.steps
     achieved = st["algo_bytes_per_sweep"] / (sweep_kernel_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(sched, tile, p["name"]),
             "kernel": (f"sweep_flow_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles> "
                        "(one dataflow launch per sweep)" if sched == "dataflow" else
                        f"sweep_tile_ge<float, mass-inverse GE, {tile}x{tile}x{tile} tiles> "

@@ -146,12 +146,18 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
 {
     const dim3 block(A.Do, A.G, cells_per_block(A.Do, A.G));
     const dim3 grid(8 * F.units_o);
-    const int words = kFlowDone + 8 * (int)F.units_o;
-    hipLaunchKernelGGL(flow_reset, dim3((words + 255) / 256), dim3(256), 0, s, F.sync, words);
     if (form == kFormDense)
         launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
     else
         launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+int launch_flow_reset(const FlowArgs &F, hipStream_t s)
+{
+    const int words = kFlowDone + 8 * (int)F.units_o;
+    hipLaunchKernelGGL(flow_reset, dim3((words + 255) / 256), dim3(256), 0, s, F.sync, words);
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

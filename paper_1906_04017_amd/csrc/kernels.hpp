@@ -97,6 +97,7 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
 template <typename Real>
 int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bool store_psi,
                 bool adjoint, hipStream_t s);
+int launch_flow_reset(const FlowArgs &F, hipStream_t s);   // before every launch_flow
 template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);
 template <typename Real>

@@ -287,6 +287,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         F.spin_limit = p->flow_spin ? p->flow_spin : kFlowSpinDefault;
         A.cells = cells;
         A.ncp = off[nsteps];
+        DGSN_TRY(launch_flow_reset(F, s));
         if (p->timing) DGSN_HIP(hipEventRecord(p->ev[0], s));
         DGSN_TRY(launch_flow<Real>(A, F, form, tb, store_psi, adjoint, s));
         if (p->timing) {
