@@ -307,6 +307,10 @@ def adjoint_box(api, ctx, n=32, cells=8, h=1e-6):
     st = torch.tensor(p["sigma_t"], dtype=torch.float32, device="cuda", requires_grad=True)
     q = torch.tensor(p["q"], dtype=torch.float32, device="cuda", requires_grad=True)
     ss = torch.tensor(p["sigma_s"], dtype=torch.float32, device="cuda")
+    # one untimed forward + adjoint solve first (first-use allocations)
+    response(api.TransportSolve.apply(prob, st, q, ss, 1e-7, 500), st, ss).backward()
+    st.grad = None
+    q.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     phi = api.TransportSolve.apply(prob, st, q, ss, 1e-7, 500)
