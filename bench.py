@@ -380,23 +380,42 @@ def uneven_batch(api, ctx, ann_path, count=64):
     for k in range(count):
         batch.set_io(k, srcs[k], phis[k])
     best_ms = batch.autotune()
-    batch.run()
-    torch.cuda.synchronize()
+    sched = batch.schedule()
     reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def time_runs():
         batch.run()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batch.run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    # the other schedule with the same tile assignment, for comparison
+    other = "planes" if sched == "dataflow" else "dataflow"
+    batch.set_schedule(other)
+    dt_other = time_runs()
+    lat_other = batch.latencies_us()
+    batch.set_schedule(sched)
+    dt = time_runs()
     lat = batch.latencies_us()
-    log(f"batch: {count} problems, {solves} solves, {1e3 * dt:.2f} ms per run, "
+    log(f"batch: {other} schedule {1e3 * dt_other:.2f} ms per run, "
+        f"p50 {np.percentile(lat_other, 50):.0f} us, p99 {np.percentile(lat_other, 99):.0f} us")
+    log(f"batch: {count} problems, {solves} solves, {1e3 * dt:.2f} ms per run ({sched}), "
         f"p50 {np.percentile(lat, 50):.0f} us, p99 {np.percentile(lat, 99):.0f} us")
     out = {"problems": count, "solves_per_run": solves, "ms_per_run": 1e3 * dt,
            "solves_per_s": solves / dt, "autotune_best_ms": best_ms,
            "latency_us_p50": float(np.percentile(lat, 50)),
            "latency_us_p99": float(np.percentile(lat, 99)),
            "ann_problems": sum(1 for p in ps if p["solver"] == "ann"),
-           "execution": "one HIP graph: one batched kernel per step over all problems"}
+           "schedule": sched,
+           "other_schedule": {"schedule": other, "ms_per_run": 1e3 * dt_other,
+                              "latency_us_p50": float(np.percentile(lat_other, 50)),
+                              "latency_us_p99": float(np.percentile(lat_other, 99))},
+           "execution": ("one HIP graph: one dataflow launch over a per-octant work queue of "
+                         "all problems' tile blocks" if sched == "dataflow" else
+                         "one HIP graph: one batched kernel per step over all problems")}
     batch.close()
     for prob in probs:
         prob.close()

@@ -276,19 +276,30 @@ int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
 /*
  * Batched execution of many independent problems (FP32, any mesh size,
  * quadrature and group count, solver DGSN_GE or DGSN_ANN per problem): one
- * sweep of every problem in a single HIP-graph launch.  Step t of the graph
- * is one batched kernel that advances every problem that still has a step t
- * (a tile or cell hyperplane, by its tile edge); the per-problem
- * octant reductions follow.  Not in the paper.
+ * sweep of every problem in a single HIP-graph launch, followed by the
+ * per-problem octant reductions.  Not in the paper.  Two schedules:
+ *   DGSN_SCHED_PLANES (default): step t of the graph is one batched kernel
+ *     that advances every problem that still has a step t (a tile or cell
+ *     hyperplane, by its tile edge).
+ *   DGSN_SCHED_DATAFLOW: one launch; per octant the units (problem, step,
+ *     block of tiles) of all problems form one work queue in step-major
+ *     order, and each unit waits on device flags of the units holding its
+ *     tiles' upwind neighbours.  Waits are bounded as for a single problem;
+ *     an expired wait is reported by the next dgsn_batch_latencies_us or
+ *     dgsn_batch_autotune (DGSN_EHIP).
  * dgsn_batch_create: probs must stay alive while the batch exists; each
- *   problem's materials, inflow and ANN are read at run time.
+ *   problem's materials, inflow and ANN are read at run time.  Two runs of
+ *   one batch must not overlap (they share the device tables).
  * dgsn_batch_set_io: device src / phi of problem `index`, layouts as in
  *   dgsn_sweep; must be set for every problem before the first run.
  * dgsn_batch_set_tiles: per-problem tile edge (1 or 2; a problem set to 3
  *   runs with 2 in a batch), host [n].
- * dgsn_batch_autotune: times the batch with candidate tile assignments (all
- *   2, all 1, 2 for meshes of >= 32^3 cells) and keeps the fastest; returns
- *   its time in ms.  Runs the batch several times; synchronizes stream.
+ * dgsn_batch_set_schedule / _get_schedule: DGSN_SCHED_PLANES or
+ *   DGSN_SCHED_DATAFLOW.
+ * dgsn_batch_autotune: times the batch under both schedules with candidate
+ *   tile assignments (all 2, all 1, 2 for meshes of >= 32^3 cells) and keeps
+ *   the fastest; returns its time in ms.  Runs the batch several times;
+ *   synchronizes stream.
  * dgsn_batch_run: enqueues the graph on stream.
  * dgsn_batch_latencies_us: per-problem time from the start of the last run to
  *   the end of that problem's last sweep step, device wall clock, host [n];
@@ -297,6 +308,8 @@ int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
 int dgsn_batch_create(dgsn_ctx *ctx, dgsn_problem *const *probs, int n, dgsn_batch **out);
 int dgsn_batch_set_io(dgsn_batch *b, int index, const void *src, void *phi);
 int dgsn_batch_set_tiles(dgsn_batch *b, const int *tile_edges);
+int dgsn_batch_set_schedule(dgsn_batch *b, int schedule);
+int dgsn_batch_get_schedule(const dgsn_batch *b, int *schedule);
 int dgsn_batch_autotune(dgsn_batch *b, void *stream, double *best_ms);
 int dgsn_batch_run(dgsn_batch *b, void *stream);
 int dgsn_batch_latencies_us(const dgsn_batch *b, double *out);

@@ -91,6 +91,8 @@ SIGNATURES = {
     "dgsn_batch_create": (_I, [_VP, ctypes.POINTER(_VP), _I, ctypes.POINTER(_VP)]),
     "dgsn_batch_set_io": (_I, [_VP, _I, _VP, _VP]),
     "dgsn_batch_set_tiles": (_I, [_VP, _PI]),
+    "dgsn_batch_set_schedule": (_I, [_VP, _I]),
+    "dgsn_batch_get_schedule": (_I, [_VP, _PI]),
     "dgsn_batch_autotune": (_I, [_VP, _VP, _PD]),
     "dgsn_batch_run": (_I, [_VP, _VP]),
     "dgsn_batch_latencies_us": (_I, [_VP, _PD]),

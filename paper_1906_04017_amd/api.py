@@ -333,6 +333,16 @@ class Batch:
         arr = (ctypes.c_int * len(self.problems))(*[int(t) for t in tiles])
         _lib.check(_lib.load().dgsn_batch_set_tiles(self._h, arr))
 
+    def set_schedule(self, schedule):
+        """'planes' (one batched kernel per step) or 'dataflow' (one launch)."""
+        sc = {"planes": _lib.DGSN_SCHED_PLANES, "dataflow": _lib.DGSN_SCHED_DATAFLOW}[schedule]
+        _lib.check(_lib.load().dgsn_batch_set_schedule(self._h, sc))
+
+    def schedule(self):
+        s = ctypes.c_int(0)
+        _lib.check(_lib.load().dgsn_batch_get_schedule(self._h, ctypes.byref(s)))
+        return ("planes", "dataflow")[s.value]
+
     def autotune(self):
         ms = ctypes.c_double(0)
         _lib.check(_lib.load().dgsn_batch_autotune(self._h, _stream(self.ctx.device),

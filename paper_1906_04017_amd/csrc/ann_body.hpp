@@ -11,6 +11,20 @@ namespace dgsn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Orders this wave's LDS writes before its following LDS reads of other
+// lanes' slots.  The LDS processes the accesses of one wave in issue order, so
+// only the compiler has to be kept from moving accesses across: wavefront-
+// scope fences around the wave barrier emit no instruction.  (An explicit
+// s_waitcnt intrinsic would also do, but the compiler then treats it as a
+// store to global memory and stops keeping kernel-argument tables read
+// through pointers in scalar registers.)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 constexpr int kParamW1 = 0;                  // [4][64] bf16x8
 constexpr int kParamW2 = 4 * 64 * 16;        // [2][64] bf16x8
@@ -42,8 +56,8 @@ __device__ __forceinline__ void ann_load(const unsigned char *__restrict__ prm, 
 
 // Evaluates the network for the 64 samples held by the 64 lanes of the wave
 // (one sample per lane, 24 FP32 features).  lds_in: 64*32 bf16 of this wave,
-// lds_out: 64*8 floats of this wave.  Must be reached by every thread of the
-// block (it synchronises the block).
+// lds_out: 64*8 floats of this wave.  Must be reached by every lane of the
+// wave (it synchronises the wave's LDS traffic only).
 __device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
                                          __bf16 *lds_in, float *lds_out, float out[8])
 {
@@ -60,7 +74,7 @@ __device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
 #pragma unroll
         for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(lds_in + lane * 32 + 8 * q) = v[q];
     }
-    __syncthreads();
+    wave_lds_sync();
     const int col = lane & 15, grp = lane >> 4;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -85,7 +99,7 @@ __device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
             for (int r = 0; r < 4; ++r) lds_out[(16 * b + col) * 8 + 4 * grp + r] = y[r];
         }
     }
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int k = 0; k < 8; ++k) out[k] = lds_out[lane * 8 + k];
 }

@@ -45,6 +45,12 @@ constexpr int kMaxTile = 3;       // largest tile edge of the sweep
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
 
 const void *ann_device_params(const dgsn_ann *a);
+
+// one unit of the dataflow schedule (host copy; see flow_units_host)
+struct FlowUnitHost {
+    unsigned step, block, t0, cnt, dlo, dhi;
+};
+int flow_units_host(const dgsn_problem *p, int tb, std::vector<FlowUnitHost> &out);
 int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[6]);
 
 // ---- device allocation helper ------------------------------------------------

@@ -29,24 +29,19 @@
 // sets its done flag, and a consumer that has seen the flags reads the fronts
 // without a cache invalidation.  The other arrays are read-only during the
 // launch or read only by later kernels.
+#include <algorithm>
+
+#include "flow.hpp"
 #include "sweep_body.hpp"
 
 namespace dgsn {
 
 namespace {
 
-__device__ __forceinline__ unsigned flow_load(const unsigned *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ unsigned flow_add(unsigned *p, unsigned v)
-{
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Wave 0: take a ticket of octant o and wait for the unit's dependencies
-// (one flag per lane, up to 64 at a time); sh = the unit's map entry.
+// (one flag per lane, up to 64 at a time); sh = the unit's map entry and
+// ticket.  The launches of a sweep have exactly 8 * units_o workgroups, so
+// every ticket is in range (clamped defensively).
 __device__ __forceinline__ void flow_take(const FlowArgs &F, unsigned o, int lane, uint4 *sh)
 {
     unsigned t = 0;
@@ -54,26 +49,11 @@ __device__ __forceinline__ void flow_take(const FlowArgs &F, unsigned o, int lan
     t = __shfl(t, 0);
     if (t >= F.units_o) t = F.units_o - 1;
     const uint2 dep = F.unit_dep[t];
-    const unsigned *done = F.sync + kFlowDone + o * F.units_o;
-    for (unsigned base = dep.x; base <= dep.y; base += 64) {
-        const unsigned idx = base + lane;
-        bool ok = idx > dep.y;
-        for (unsigned it = 0;; ++it) {
-            if (!ok) ok = flow_load(done + idx) != 0u;
-            if (__all(ok)) break;
-            if (it >= F.spin_limit || __any(flow_load(F.sync + kFlowError) != 0u)) {
-                if (lane == 0)
-                    __hip_atomic_store(F.sync + kFlowError, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                base = dep.y;   // give up the remaining flags too
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-    }
+    flow_wait_range(F.sync + kFlowDone + o * F.units_o, dep.x, dep.y, 1u, lane, F.spin_limit,
+                    F.sync + kFlowError);
     if (lane == 0) {
-        *sh = F.unit_map[t];
-        sh[1].x = t;
+        sh[0] = F.unit_map[t];
+        sh[1] = make_uint4(t, 0u, 0u, 0u);
     }
 }
 
@@ -82,9 +62,7 @@ __device__ __forceinline__ void flow_finish(const FlowArgs &F, int tid, unsigned
 {
     __builtin_amdgcn_s_waitcnt(0);   // this wave's coherent front stores are acknowledged
     __syncthreads();
-    if (tid == 0)
-        __hip_atomic_store(F.sync + kFlowDone + o * F.units_o + t, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) flow_store(F.sync + kFlowDone + o * F.units_o + t, 1u);
 }
 
 // Clears the tickets and done counts (not the error word) before a launch.
@@ -97,21 +75,25 @@ __global__ __launch_bounds__(256) void flow_reset(unsigned *sync, int n)
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
 __global__ __launch_bounds__(256) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
 {
-    // block = (direction, group, tile) lanes as in the hyperplane kernel;
-    // A.cells is the whole tile list of the schedule
+    // 256 lanes as in the hyperplane kernel; A.cells is the whole tile list
+    // of the schedule
     __shared__ TileLds<Real> L;
     __shared__ uint4 sh[2];
-    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int tid = threadIdx.x;
     const unsigned o = blockIdx.x & 7u;
     if (tid < 64) flow_take(F, o, tid, sh);
     __syncthreads();
-    const uint4 u = sh[0];
-    const unsigned t = sh[1].x;
+    // the unit is uniform over the block: keep it in scalar registers
+    const unsigned blk = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].y);
+    const unsigned t0 = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].z);
+    const unsigned cnt = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].w);
+    const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[1].x);
+    const SegLane l = seg_lane(A, tid);
     bool tvalid;
-    const uint32_t pt = step_tile(A.cells + u.z, u.w, (int)u.y * blockDim.z + threadIdx.z, true,
-                                  tvalid);
-    tile_body<Real, Form, B, kStorePsi, kAdjoint, true>(A, threadIdx.x, threadIdx.y, tid, tvalid,
-                                                        pt, (int)o, true, L, nullptr);
+    const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
+    const Real inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
+    tile_body<Real, Form, B, kStorePsi, kAdjoint, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
+                                                        l.ok, L, nullptr);
     flow_finish(F, tid, o, t);
 }
 
@@ -144,12 +126,15 @@ template <typename Real>
 int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bool store_psi,
                 bool adjoint, hipStream_t s)
 {
-    const dim3 block(A.Do, A.G, cells_per_block(A.Do, A.G));
-    const dim3 grid(8 * F.units_o);
-    if (form == kFormDense)
-        launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
-    else
-        launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
+    const dim3 block(256);
+    for (unsigned done = 0; done < F.units_o; done += kFlowMaxGroupsPerOctant) {
+        const dim3 grid(8 * std::min(F.units_o - done, kFlowMaxGroupsPerOctant));
+        if (form == kFormDense)
+            launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
+        else
+            launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
+        DGSN_HIP(hipGetLastError());
+    }
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

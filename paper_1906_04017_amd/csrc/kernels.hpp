@@ -22,7 +22,12 @@ struct PlaneArgs {
     uint32_t fx_o, fx_k, fx_j; // front strides (elements): octant, outer, inner cell index
     uint32_t fy_o, fy_k, fy_j;
     uint32_t fz_o, fz_k, fz_j;
-    uint32_t mag_do, mag_dog;  // ceil(2^16 / Do), ceil(2^16 / (Do G)) for lane decoding
+    // lane layout of the 256-lane sweep blocks: each wave holds spw = 64 / Do
+    // segments of Do direction lanes; segment s of a block is group s % G of
+    // tile slot s / G, and a block covers nc = 4 spw / G tiles.  Segments never
+    // cross a wave, so the direction reductions need no block barrier.
+    uint32_t spw, nc;
+    uint32_t mag_do, mag_g;    // ceil(2^16 / Do), ceil(2^16 / G): exact quotients below 256
     const Real *dir;           // [8][Do][kDirStride]
     const Real *sigma_t;       // [G][ncell]
     const Real *src;           // [G][ncell][8]
@@ -54,13 +59,19 @@ struct FlowArgs {
     // for none
     const uint2 *unit_dep;
     unsigned *sync;            // tickets (one 128-byte line per octant), error word, done[8][units_o]
-    unsigned units_o;          // units per octant; the launch has 8 * units_o workgroups
+    unsigned units_o;          // units per octant
     unsigned spin_limit;       // polls of one wait before it gives up
 };
 constexpr int kFlowTicket = 0;      // + 32 * octant
 constexpr int kFlowError = 256;
 constexpr int kFlowDone = 288;      // + octant * units_o + unit
 constexpr unsigned kFlowSpinDefault = 1u << 20;
+// workgroups per octant of one dataflow launch at most (8 * 2^20 * 256 lanes
+// stay below the 2^32 work-items of a launch).  A longer queue runs as several
+// launches in stream order: the tickets continue across them, and a unit's
+// dependencies have smaller tickets, so they lie in an earlier launch or in
+// its own.
+constexpr unsigned kFlowMaxGroupsPerOctant = 1u << 20;
 
 template <typename Real>
 struct ReduceArgs {
@@ -96,7 +107,7 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
                 hipStream_t s);
 template <typename Real>
 int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bool store_psi,
-                bool adjoint, hipStream_t s);
+                bool adjoint, hipStream_t s);   // all launches of one sweep
 int launch_flow_reset(const FlowArgs &F, hipStream_t s);   // before every launch_flow
 template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);

@@ -154,8 +154,10 @@ PlaneArgs<Real> plane_args(dgsn_problem *p, const void *src, bool adjoint)
     A.fz_j = f4;
     A.fz_k = A.nx * f4;
     A.fz_o = A.ny * A.fz_k;
+    A.spw = 64u / A.Do;
+    A.nc = (uint32_t)cells_per_block(p->Do, p->G);
     A.mag_do = (65536u + A.Do - 1) / A.Do;
-    A.mag_dog = (65536u + A.Do * A.G - 1) / (A.Do * A.G);
+    A.mag_g = (65536u + A.G - 1) / A.G;
     A.dir = static_cast<const Real *>(p->d_dir.ptr);
     A.sigma_t = static_cast<const Real *>(p->sigma_t.ptr);
     A.src = static_cast<const Real *>(src);
@@ -177,67 +179,86 @@ PlaneArgs<Real> plane_args(dgsn_problem *p, const void *src, bool adjoint)
     return A;
 }
 
-// Unit maps of the dataflow schedule for every tile edge: units are blocks of
-// cells_per_block tiles of one octant in one step, in step-major order; each
-// depends on the units of the previous step that hold the upwind neighbours
-// (i-1, j, k), (i, j-1, k), (i, j, k-1) of its tiles.
+}  // namespace
+
+namespace dgsn {
+
+// Dataflow units of one tile edge: blocks of cells_per_block tiles of one
+// octant in one step, step-major; each depends on the units of the previous
+// step that hold the upwind neighbours (i-1, j, k), (i, j-1, k), (i, j, k-1)
+// of its tiles (problem-local unit indices, dlo > dhi for none).
+int flow_units_host(const dgsn_problem *p, int tb, std::vector<FlowUnitHost> &out)
+{
+    const std::vector<int> &off = tb == 1 ? p->plane_off : p->tplane_off[tb];
+    const int nc = cells_per_block(p->Do, p->G);
+    const int T[3] = {(p->n[0] + tb - 1) / tb, (p->n[1] + tb - 1) / tb, (p->n[2] + tb - 1) / tb};
+    const int ns = (int)off.size() - 1;
+    out.clear();
+    std::vector<int> pos((size_t)T[1] * T[2], -1);   // (j, k) -> index in the previous step
+    std::vector<int> cur;
+    int ubase_prev = 0;
+    for (int st = 0; st < ns; ++st) {
+        const int cnt = off[st + 1] - off[st];
+        const unsigned nb = (unsigned)((cnt + nc - 1) / nc);
+        if (8ull * (out.size() + nb) > (1ull << 31))
+            return set_error(DGSN_EUNSUPPORTED, "too many dataflow units");
+        const int ubase = (int)out.size();
+        // tiles of this step, in the order of the tile list (k outer, j inner)
+        cur.clear();
+        for (int kk = 0; kk < T[2]; ++kk)
+            for (int jj = 0; jj < T[1]; ++jj) {
+                const int ii = st - jj - kk;
+                if (ii >= 0 && ii < T[0]) cur.push_back(ii | jj << 10 | kk << 20);
+            }
+        if ((int)cur.size() != cnt) return set_error(DGSN_EINVAL, "inconsistent tile schedule");
+        for (unsigned l = 0; l < nb; ++l) {
+            unsigned lo = UINT32_MAX, hi = 0;
+            for (int q = (int)l * nc; q < std::min(cnt, (int)(l + 1) * nc); ++q) {
+                const int ii = cur[q] & 1023, jj = (cur[q] >> 10) & 1023, kk = cur[q] >> 20;
+                int up[3] = {-1, -1, -1};
+                if (ii > 0) up[0] = pos[(size_t)kk * T[1] + jj];
+                if (jj > 0) up[1] = pos[(size_t)kk * T[1] + jj - 1];
+                if (kk > 0) up[2] = pos[(size_t)(kk - 1) * T[1] + jj];
+                for (int a = 0; a < 3; ++a)
+                    if (up[a] >= 0) {
+                        const unsigned u = (unsigned)(ubase_prev + up[a] / nc);
+                        lo = std::min(lo, u);
+                        hi = std::max(hi, u);
+                    }
+            }
+            if (lo == UINT32_MAX) {
+                lo = 1;
+                hi = 0;
+            }
+            out.push_back(FlowUnitHost{(unsigned)st, l, (unsigned)off[st], (unsigned)cnt, lo, hi});
+        }
+        for (int q = 0; q < cnt; ++q)
+            pos[(size_t)(cur[q] >> 20) * T[1] + ((cur[q] >> 10) & 1023)] = q;
+        ubase_prev = ubase;
+    }
+    return DGSN_OK;
+}
+
+}  // namespace dgsn
+
+namespace {
+
+// Device unit maps of the single-problem dataflow schedule for every tile edge.
 int flow_prepare(dgsn_problem *p)
 {
     if (p->flow_ready) return DGSN_OK;
     const long long nmax = std::max(std::max(p->n[0], p->n[1]), p->n[2]);
     if (nmax * nmax * 8 * 4 * p->Do * p->G * (long long)p->real_size >= (1LL << 31))
         return set_error(DGSN_EUNSUPPORTED, "the dataflow schedule needs face fronts under 2 GiB");
-    const int nc = cells_per_block(p->Do, p->G);
     unsigned umax = 0;
+    std::vector<FlowUnitHost> units;
     for (int tb = 1; tb <= kMaxTile; ++tb) {
-        const std::vector<int> &off = tb == 1 ? p->plane_off : p->tplane_off[tb];
-        const int T[3] = {(p->n[0] + tb - 1) / tb, (p->n[1] + tb - 1) / tb,
-                          (p->n[2] + tb - 1) / tb};
-        const int ns = (int)off.size() - 1;
-        std::vector<uint4> map;
-        std::vector<uint2> dep;
-        std::vector<int> pos((size_t)T[1] * T[2], -1);   // (j, k) -> index in the previous step
-        std::vector<int> cur;
-        int ubase_prev = 0;
-        for (int st = 0; st < ns; ++st) {
-            const int cnt = off[st + 1] - off[st];
-            const unsigned nb = (unsigned)((cnt + nc - 1) / nc);
-            if (8ull * (map.size() + nb) > (1ull << 31))
-                return set_error(DGSN_EUNSUPPORTED, "too many dataflow units");
-            const int ubase = (int)map.size();
-            // tiles of this step, in the order of the tile list (k outer, j inner)
-            cur.clear();
-            for (int kk = 0; kk < T[2]; ++kk)
-                for (int jj = 0; jj < T[1]; ++jj) {
-                    const int ii = st - jj - kk;
-                    if (ii >= 0 && ii < T[0]) cur.push_back(ii | jj << 10 | kk << 20);
-                }
-            if ((int)cur.size() != cnt) return set_error(DGSN_EINVAL, "inconsistent tile schedule");
-            for (unsigned l = 0; l < nb; ++l) {
-                unsigned lo = UINT32_MAX, hi = 0;
-                for (int q = (int)l * nc; q < std::min(cnt, (int)(l + 1) * nc); ++q) {
-                    const int ii = cur[q] & 1023, jj = (cur[q] >> 10) & 1023, kk = cur[q] >> 20;
-                    int up[3] = {-1, -1, -1};
-                    if (ii > 0) up[0] = pos[(size_t)kk * T[1] + jj];
-                    if (jj > 0) up[1] = pos[(size_t)kk * T[1] + jj - 1];
-                    if (kk > 0) up[2] = pos[(size_t)(kk - 1) * T[1] + jj];
-                    for (int a = 0; a < 3; ++a)
-                        if (up[a] >= 0) {
-                            const unsigned u = (unsigned)(ubase_prev + up[a] / nc);
-                            lo = std::min(lo, u);
-                            hi = std::max(hi, u);
-                        }
-                }
-                if (lo == UINT32_MAX) {
-                    lo = 1;
-                    hi = 0;
-                }
-                map.push_back(make_uint4((unsigned)st, l, (unsigned)off[st], (unsigned)cnt));
-                dep.push_back(make_uint2(lo, hi));
-            }
-            for (int q = 0; q < cnt; ++q)
-                pos[(size_t)(cur[q] >> 20) * T[1] + ((cur[q] >> 10) & 1023)] = q;
-            ubase_prev = ubase;
+        DGSN_TRY(flow_units_host(p, tb, units));
+        std::vector<uint4> map(units.size());
+        std::vector<uint2> dep(units.size());
+        for (size_t u = 0; u < units.size(); ++u) {
+            map[u] = make_uint4(units[u].step, units[u].block, units[u].t0, units[u].cnt);
+            dep[u] = make_uint2(units[u].dlo, units[u].dhi);
         }
         DGSN_TRY(p->d_unit_map[tb].alloc(map.size() * sizeof(uint4)));
         DGSN_TRY(p->d_unit_dep[tb].alloc(dep.size() * sizeof(uint2)));
@@ -758,6 +779,10 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
         if (DG > 256)
             return fail(set_error(DGSN_EUNSUPPORTED,
                                   "directions per octant x groups must be <= 256 (got %lld)", DG));
+        if (p->Do > 64 || cells_per_block(p->Do, p->G) < 1)
+            return fail(set_error(DGSN_EUNSUPPORTED,
+                                  "groups must be <= 4 * floor(64 / directions per octant) "
+                                  "(got %d groups, %d directions per octant)", p->G, p->Do));
     }
     if ((rc = p->sigma_t.alloc(nv * rs)) || (rc = p->sigma_s.alloc(nv * rs)) ||
         (rc = p->q.alloc(nv * rs)) || (rc = p->src.alloc(nv * 8 * rs)) ||

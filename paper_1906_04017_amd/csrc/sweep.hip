@@ -26,35 +26,30 @@ namespace {
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
 __global__ __launch_bounds__(256) void sweep_tile_ge(PlaneArgs<Real> A)
 {
-    // block = (direction, group, tile) lanes, grid = (tile groups, octant)
+    // 256 lanes: (direction, group, tile slot) segments, grid = (tile blocks, octant)
     __shared__ TileLds<Real> L;
-    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int tid = threadIdx.x;
+    const SegLane l = seg_lane(A, tid);
     bool tvalid;
-    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * blockDim.z + threadIdx.z, true,
-                                  tvalid);
-    tile_body<Real, Form, B, kStorePsi, kAdjoint>(A, threadIdx.x, threadIdx.y, tid, tvalid, pt,
-                                                  blockIdx.y, true, L, nullptr);
+    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
+    const Real inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
+    tile_body<Real, Form, B, kStorePsi, kAdjoint>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
+                                                  l.ok, L, nullptr);
 }
 
-// ANN tile sweep: 256-thread blocks (full waves for the matrix cores), the
-// first Do * G * floor(256 / (Do G)) lanes carry work; q = (tid * ceil(2^16 /
-// div)) >> 16 is the exact quotient for tid < 256.
+// ANN tile sweep: the same lane layout (full waves for the matrix cores).
 template <int B>
 __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
 {
     __shared__ TileLds<float> L;
     __shared__ AnnLds al;
     const int tid = threadIdx.x;
-    const int nc = 256 / (int)(A.Do * A.G);
-    const int q1 = (tid * (int)A.mag_do) >> 16;
-    const int z = (tid * (int)A.mag_dog) >> 16;
-    const int d = tid - q1 * (int)A.Do;
-    const int g = q1 - z * (int)A.G;
-    const bool lane_ok = z < nc;
+    const SegLane l = seg_lane(A, tid);
     bool tvalid;
-    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * nc + z, lane_ok, tvalid);
-    tile_body<float, kFormAnn, B, false, false>(A, lane_ok ? d : 0, lane_ok ? g : 0, tid, tvalid,
-                                                pt, blockIdx.y, lane_ok, L, &al);
+    const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
+    const float inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
+    tile_body<float, kFormAnn, B, false, false>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
+                                                l.ok, L, &al);
 }
 
 // phi = sum_o phi_oct[o]; optionally the FP64 SI residual partials and the
@@ -210,7 +205,7 @@ int grid_for(long long n, int cap = 4096)
 
 int block_size_for(int Do) { return Do * (256 / Do); }
 
-int cells_per_block(int Do, int G) { return 256 / (Do * G); }
+int cells_per_block(int Do, int G) { return Do > 64 ? 0 : 4 * (64 / Do) / G; }
 
 
 
@@ -239,8 +234,7 @@ void launch_tile_b(const PlaneArgs<Real> &A, int b, bool store_psi, bool adjoint
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s)
 {
-    const int nc = cells_per_block(A.Do, A.G);
-    const dim3 grid((A.ncp + nc - 1) / nc, 8);
+    const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
     switch (b) {
     case 3: hipLaunchKernelGGL(sweep_tile_ann<3>, grid, dim3(256), 0, s, A); break;
     case 2: hipLaunchKernelGGL(sweep_tile_ann<2>, grid, dim3(256), 0, s, A); break;
@@ -254,8 +248,8 @@ template <typename Real>
 int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,
                 hipStream_t s)
 {
-    const dim3 block(A.Do, A.G, cells_per_block(A.Do, A.G));
-    const dim3 grid((A.ncp + block.z - 1) / block.z, 8);
+    const dim3 block(256);
+    const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
     if (form == kFormDense)
         launch_tile_b<Real, kFormDense>(A, b, store_psi, adjoint, grid, block, s);
     else

@@ -224,6 +224,29 @@ __device__ __forceinline__ float ann_features(const float kap[3], float hh, floa
     return m;
 }
 
+// Lane of a 256-lane sweep block (see PlaneArgs): direction d and group g of
+// segment slot z; ok is false for the lanes beyond the last whole segment of
+// the wave and beyond nc * G segments of the block.  All quotients are exact
+// (numerators below 256, divisors at most 256).
+struct SegLane {
+    int d, g, z;
+    bool ok;
+};
+template <typename Real>
+__device__ __forceinline__ SegLane seg_lane(const PlaneArgs<Real> &A, int tid)
+{
+    const int w = tid >> 6, lane = tid & 63;
+    const int sl = (lane * (int)A.mag_do) >> 16;   // segment within the wave
+    const int seg = w * (int)A.spw + sl;
+    const int z = (seg * (int)A.mag_g) >> 16;
+    SegLane l;
+    l.ok = sl < (int)A.spw && z < (int)A.nc;
+    l.d = l.ok ? lane - sl * (int)A.Do : 0;
+    l.g = l.ok ? seg - z * (int)A.G : 0;
+    l.z = l.ok ? z : 0;
+    return l;
+}
+
 // Tile ti of one schedule step (cells: the step's packed tiles, ncp of them).
 __device__ __forceinline__ uint32_t step_tile(const uint32_t *cells, uint32_t ncp, int ti,
                                               bool lane_ok, bool &tvalid)
@@ -248,14 +271,17 @@ struct AnnLds {
 // group of the lane; tid: its index in the block (segments of Do lanes with
 // equal (group, tile) are contiguous); tvalid: the lane has a tile, pt: its
 // packed canonical tile coordinates (i | j << 10 | k << 20, in tiles);
-// o: octant slot; lane_ok: the lane carries work.  Form: kFormMassInv,
+// o: octant slot; inc: the boundary inflow of octant slot o per canonical
+// axis; lane_ok: the lane carries work.  Form: kFormMassInv,
 // kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
 // blocks of full waves).  kCoh: device-coherent front access (dataflow
-// kernel).  Must be reached by every thread of the block.
+// kernel).  Must be reached by every lane of the wave; lanes of one
+// (group, tile) segment are in one wave (seg_lane), and the body synchronises
+// only within the wave.
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kCoh = false>
-__device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g, int tid,
-                                          bool tvalid, uint32_t pt, int o, bool lane_ok,
-                                          TileLds<Real> &L, AnnLds *al)
+__device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real inc[3], int d,
+                                          int g, int tid, bool tvalid, uint32_t pt, int o,
+                                          bool lane_ok, TileLds<Real> &L, AnnLds *al)
 {
     static_assert(Form != kFormAnn || sizeof(Real) == 4, "the ANN solver runs in FP32");
     const int mask = kAdjoint ? (o ^ 7) : o;
@@ -313,7 +339,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     } else if (ic) {
                         front_load<Real, kCoh>(A.fx, rx, ex, vx);
                     } else {
-                        vx[0] = vx[1] = vx[2] = vx[3] = A.inc[o][0];
+                        vx[0] = vx[1] = vx[2] = vx[3] = inc[0];
                     }
                     if (jl > 0) {
 #pragma unroll
@@ -321,7 +347,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     } else if (jc) {
                         front_load<Real, kCoh>(A.fy, ry, ey, vy);
                     } else {
-                        vy[0] = vy[1] = vy[2] = vy[3] = A.inc[o][1];
+                        vy[0] = vy[1] = vy[2] = vy[3] = inc[1];
                     }
                     if (kl > 0) {
 #pragma unroll
@@ -329,7 +355,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     } else if (kc) {
                         front_load<Real, kCoh>(A.fz, rz, ez, vz);
                     } else {
-                        vz[0] = vz[1] = vz[2] = vz[3] = A.inc[o][2];
+                        vz[0] = vz[1] = vz[2] = vz[3] = inc[2];
                     }
                 }
                 // local solve
@@ -402,7 +428,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                     L.gred[tid * 2 + 0] = gs;
                     L.gred[tid * 2 + 1] = gq;
                 }
-                __syncthreads();
+                wave_lds_sync();   // a segment's lanes are in one wave
                 if (ok) {
                     const int base = tid - d;
                     const uint32_t out = ((o * A.G + g) * A.ncell + c) * 8;
@@ -419,7 +445,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, int d, int g
                         }
                     }
                 }
-                if (kAdjoint) __syncthreads();
+                if (kAdjoint) wave_lds_sync();
             }
 }
 

@@ -441,9 +441,10 @@ BATCH = [((5, 4, 3), 4, 2, "ge"), ((9, 9, 9), 8, 3, "ge"), ((3, 7, 2), 12, 1, "g
          ((12, 10, 11), 8, 2, "ge")]
 
 
+@pytest.mark.parametrize("schedule", ["planes", "dataflow"])
 @pytest.mark.parametrize("tiles", ["default", "ones", "autotune"])
-def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles):
-    print_case("batch", tiles=tiles, problems=len(BATCH))
+def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles, schedule):
+    print_case("batch", tiles=tiles, schedule=schedule, problems=len(BATCH))
     net = _random_net(77)
     ann = api.Ann(ctx, _write_net(tmp_path, net, "batch.dgsnann"))
     probs, srcs, phis, ps = [], [], [], []
@@ -461,12 +462,17 @@ def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles):
     batch = api.Batch(ctx, probs)
     for k in range(len(probs)):
         batch.set_io(k, srcs[k], phis[k])
+    batch.set_schedule(schedule)
     if tiles == "ones":
         batch.set_tiles([1] * len(probs))
     elif tiles == "autotune":
         assert batch.autotune() > 0
-    batch.run()
-    torch.cuda.synchronize()
+        assert batch.schedule() in ("planes", "dataflow")
+    for _ in range(2):   # a graph replay must give the same results
+        for ph in phis:
+            ph.fill_(float("nan"))
+        batch.run()
+        torch.cuda.synchronize()
     lat = batch.latencies_us()
     assert np.all(lat > 0)
     for k, (n, order, G, solver) in enumerate(BATCH):
