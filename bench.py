@@ -85,6 +85,12 @@ def parse():
     ap.add_argument("--ann", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "paper_1906_04017_amd", "data",
                                                   "ann_s8_relu64.dgsnann"))
+    ap.add_argument("--ann-paper", default=os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "paper_1906_04017_amd", "data",
+        "ann_paper_tanh8.dgsnann"), help="paper-form per-octant network (version-2 artifact)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="only reproduce the paper's Problem 1-4 grids (S2-S8 at 100^3, "
+                         "10^3-100^3 at S8) with every local solver; prints one JSON line")
     ap.add_argument("--cpu-groups", type=int, default=8,
                     help="groups of the workload swept by the CPU oracle sample")
     return ap.parse_args()
@@ -119,6 +125,11 @@ def main():
 
     import torch
     from paper_1906_04017_amd import api, inputs
+
+    if args.paper_tables:
+        ctx = api.Context(0)
+        print(json.dumps(paper_tables(api, ctx, args.ann, args.ann_paper)), flush=True)
+        return
 
     p = inputs.blocky_scatter(n=args.n, groups=args.groups, seed=2, order=args.order)
     log(f"workload {p['name']}")
@@ -175,7 +186,7 @@ def main():
             "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
 
     fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
-    ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann)
+    ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann, args.ann_paper)
     adj = None if args.skip_extras else adjoint_box(api, ctx)
     batch = None if args.skip_extras else uneven_batch(api, ctx, args.ann)
 
@@ -229,27 +240,33 @@ def plain_fp64(api, ctx, p, reps=3):
     return {"solves_per_s": solves / dt, "ms_per_sweep": dt * 1e3, "solver": "GE", "dtype": "f64"}
 
 
-def ann_vs_ge(api, ctx, ann_path, n=128, reps=3):
+def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
     """The paper's comparison on its four problems (one group each, 10 cm
     cube, psi_inc = 1 on three faces), 128^3, S8: one sweep of all groups with
-    the FP32 GE solvers and with the BF16-MFMA ANN, and the ANN error eps_P
+    the FP32 GE solvers, with the BF16-MFMA ANN and with the paper-form
+    per-octant network (vector ALUs), and each network's error eps_P
     (cell-average mean relative difference) against GE per group; group 4
     (c = 0.99) by source iteration to the paper's eps_S < 1e-4."""
     import torch
     from paper_1906_04017_amd import inputs
     p = inputs.paper_problems(n=n, groups=4, order=8)
     om, w = api.quadrature_ls(8)
-    ann = api.Ann(ctx, ann_path)
+    nets = {"ann": api.Ann(ctx, ann_path)}
+    if pann_path and os.path.exists(pann_path):
+        nets["ann_paper"] = api.Ann(ctx, pann_path)
     S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32, device="cuda")
-    out = {"workload": p["name"], "ann_artifact": os.path.basename(ann_path)}
+    out = {"workload": p["name"], "ann_artifact": os.path.basename(ann_path),
+           "ann_paper_artifact": os.path.basename(pann_path) if "ann_paper" in nets else None}
     res = {}
-    for solver in ("ge", "ge_dense", "ann"):
-        prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32", solver=solver)
+    for solver in ("ge", "ge_dense") + tuple(nets):
+        prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32",
+                           solver="ann" if solver in nets else solver)
         prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
         prob.set_inflow(p["psi_inc"])
-        if solver == "ann":
-            prob.set_ann(ann)
-        prob.autotune()
+        if solver in nets:
+            prob.set_ann(nets[solver])
+        tile, sched, _ = prob.autotune()
+        out[f"{solver}_schedule"] = f"{sched}, {tile}^3 tiles"
         dt, phi = time_sweeps(prob, S, reps)
         solves = prob.stats()["solves_per_sweep"]
         out[f"{solver}_solves_per_s"] = solves / dt
@@ -257,33 +274,115 @@ def ann_vs_ge(api, ctx, ann_path, n=128, reps=3):
         res[solver] = phi.double().mean(-1)        # cell averages [G, ncell]
         log(f"paper problems {solver}: {dt * 1e3:.3f} ms per sweep")
         prob.close()
-    out["ann_over_ge_speed"] = out["ann_solves_per_s"] / out["ge_solves_per_s"]
-    out["ann_over_ge_dense_speed"] = out["ann_solves_per_s"] / out["ge_dense_solves_per_s"]
-    ref, got = res["ge"], res["ann"]
-    eps = ((got - ref).abs() / (ref.abs() + 1e-8)).mean(-1).cpu().numpy()
-    # group 4: scattering, converged by SI with both solvers (paper criterion)
+    ref = res["ge"]
+    for net in nets:
+        out[f"{net}_over_ge_speed"] = out[f"{net}_solves_per_s"] / out["ge_solves_per_s"]
+        out[f"{net}_over_ge_dense_speed"] = (out[f"{net}_solves_per_s"] /
+                                             out["ge_dense_solves_per_s"])
+        eps = ((res[net] - ref).abs() / (ref.abs() + 1e-8)).mean(-1).cpu().numpy()
+        out[f"{net}_eps_p_percent_single_sweep"] = [round(100 * float(v), 3) for v in eps]
+    # group 4: scattering, converged by SI with each solver (paper criterion)
     p4 = inputs.problem(p["n"], p["length"], 8, 1, p["sigma_t"][3:4], p["sigma_s"][3:4],
                         p["q"][3:4], p["psi_inc"], "problem4")
     si = {}
-    for solver in ("ge", "ann"):
-        prob = api.Problem(ctx, p4["n"], p4["length"], 1, om, w, precision="fp32", solver=solver)
+    for solver in ("ge",) + tuple(nets):
+        prob = api.Problem(ctx, p4["n"], p4["length"], 1, om, w, precision="fp32",
+                           solver="ann" if solver in nets else solver)
         prob.set_materials(p4["sigma_t"], p4["sigma_s"], p4["q"])
         prob.set_inflow(p4["psi_inc"])
-        if solver == "ann":
-            prob.set_ann(ann)
+        if solver in nets:
+            prob.set_ann(nets[solver])
         prob.set_si_criterion("eps_s")
         phi, info = prob.source_iterate(tol=1e-4, max_iter=2000, allow_notconv=True)
         si[solver] = (phi.double().mean(-1), info)
         log(f"problem 4 SI {solver}: {info['iters']} iterations, eps_S {info['eps_s']:.2e}")
         prob.close()
-    e4 = ((si["ann"][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
-    out["eps_p_percent_single_sweep"] = [round(100 * float(v), 3) for v in eps]
-    out["eps_p_percent_problem4_si"] = round(100 * e4, 3)
-    out["problem4_si_iterations"] = {"ge": si["ge"][1]["iters"], "ann": si["ann"][1]["iters"]}
+    for net in nets:
+        e4 = ((si[net][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
+        out[f"{net}_eps_p_percent_problem4_si"] = round(100 * e4, 3)
+    out["problem4_si_iterations"] = {k: v[1]["iters"] for k, v in si.items()}
     out["paper_context"] = ("paper, 100^3 S8, unstated hardware: ANN saves 68.4 % of the solve time "
-                            "(3.16x); eps_P 1.59 / 2.45 / 0.45 / 0.87 % on Problems 1-4")
-    ann.close()
+                            "(3.16x); eps_P 1.59 / 2.45 / 0.45 / 0.87 % on Problems 1-4; SI "
+                            "iterations GE / ANN 237 / 110 on Problem 4")
+    for a in nets.values():
+        a.close()
     return out
+
+
+def paper_tables(api, ctx, ann_path, pann_path, reps=3):
+    """The paper's evaluation grid (Sec. 4): Problems 1-4 in the 10 cm cube
+    with psi_inc = 1 on the x = 0, y = 0 and z = 0 faces, at 100^3 cells with
+    S2, S4, S6, S8 and at 10^3, 25^3, 50^3, 100^3 cells with S8.  For every
+    configuration and local solver (FP32 GE, the BF16-MFMA network, the
+    paper-form network): the time of one sweep of Problems 1-3 (no scattering,
+    one sweep is the solution) and eps_P of each network against GE; for
+    Problem 4 (c = 0.99) the source iterations to eps_S < 1e-4 and eps_P of the
+    converged flux."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    nets = {"ann": api.Ann(ctx, ann_path)}
+    if pann_path and os.path.exists(pann_path):
+        nets["ann_paper"] = api.Ann(ctx, pann_path)
+    solvers = ("ge",) + tuple(nets)
+    configs = [(100, 2), (100, 4), (100, 6), (100, 8), (10, 8), (25, 8), (50, 8)]
+    rows = []
+    for n, order in configs:
+        p = inputs.paper_problems(n=n, groups=4, order=order)
+        om, w = api.quadrature_ls(order)
+        S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32,
+                         device="cuda")
+        row = {"cells": f"{n}^3", "order": f"S{order}", "directions": len(w)}
+        avg = {}
+        for sv in solvers:
+            prob = api.Problem(ctx, p["n"], p["length"], 3, om, w, precision="fp32",
+                               solver="ann" if sv in nets else "ge")
+            prob.set_materials(p["sigma_t"][:3], p["sigma_s"][:3], p["q"][:3])
+            prob.set_inflow(p["psi_inc"])
+            if sv in nets:
+                prob.set_ann(nets[sv])
+            prob.autotune()
+            dt, phi = time_sweeps(prob, S[:3], reps)
+            row[f"{sv}_ms_per_sweep_p123"] = round(dt * 1e3, 4)
+            avg[sv] = phi.double().mean(-1)
+            prob.close()
+        for sv in nets:
+            eps = ((avg[sv] - avg["ge"]).abs() / (avg["ge"].abs() + 1e-8)).mean(-1).cpu().numpy()
+            row[f"{sv}_eps_p_percent_p123"] = [round(100 * float(v), 3) for v in eps]
+        p4 = inputs.problem(p["n"], p["length"], order, 1, p["sigma_t"][3:4], p["sigma_s"][3:4],
+                            p["q"][3:4], p["psi_inc"], "problem4")
+        si = {}
+        for sv in solvers:
+            prob = api.Problem(ctx, p4["n"], p4["length"], 1, om, w, precision="fp32",
+                               solver="ann" if sv in nets else "ge")
+            prob.set_materials(p4["sigma_t"], p4["sigma_s"], p4["q"])
+            prob.set_inflow(p4["psi_inc"])
+            if sv in nets:
+                prob.set_ann(nets[sv])
+            prob.autotune()
+            prob.set_si_criterion("eps_s")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            phi, info = prob.source_iterate(tol=1e-4, max_iter=3000, allow_notconv=True)
+            torch.cuda.synchronize()
+            si[sv] = (phi.double().mean(-1), info, time.perf_counter() - t0)
+            prob.close()
+        row["p4_si_iterations"] = {sv: si[sv][1]["iters"] for sv in solvers}
+        row["p4_si_ms"] = {sv: round(1e3 * si[sv][2], 2) for sv in solvers}
+        for sv in nets:
+            e4 = ((si[sv][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
+            row[f"{sv}_eps_p_percent_p4"] = round(100 * e4, 3)
+        log(f"paper tables {n}^3 S{order}: " + json.dumps(row))
+        rows.append(row)
+    for a in nets.values():
+        a.close()
+    return {"table": "paper_problems_1_to_4", "rows": rows,
+            "ann_artifact": os.path.basename(ann_path),
+            "ann_paper_artifact": os.path.basename(pann_path) if "ann_paper" in nets else None,
+            "paper_context": ("paper (unstated hardware): eps_P P1 0.11/1.30/1.78/1.59 %, "
+                              "P2 0.07/1.09/2.57/2.45 %, P3 0.14/0.86/0.68/0.45 % at 100^3 "
+                              "S2-S8; P4 SI iterations GE/ANN 211/101, 220/102, 228/104, "
+                              "237/110 at 100^3 S2-S8 and 15/9, 42/20, 121/58 at 10^3, 25^3, "
+                              "50^3 S8")}
 
 
 def adjoint_box(api, ctx, n=32, cells=8, h=1e-6):

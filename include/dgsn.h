@@ -62,7 +62,11 @@ enum { DGSN_FP32 = 0, DGSN_FP64 = 1 };
  *                  premultiplied by the inverse element mass matrix, known in
  *                  closed form; the matrix has 32 structural zeros, which the
  *                  elimination skips.  Same solution, about half the flops.
- *   DGSN_ANN       the shallow network of Sec. 3 in place of assembly + GE.
+ *   DGSN_ANN       the shallow network of Sec. 3 in place of assembly + GE:
+ *                  with a version-1 artifact the 24-input canonical network on
+ *                  the BF16 matrix cores, with a version-2 artifact the
+ *                  paper-form per-octant network (26 inputs, tanh hidden
+ *                  layer, ELU output) on the vector ALUs.
  *   DGSN_GE_DENSE  the cell matrix and right-hand side assembled as in Sec. 2
  *                  (streaming, sigma_t times mass, upwind face terms) and
  *                  solved by dense Gaussian elimination.
@@ -129,7 +133,10 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
 int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
 
 /* Attach an ANN (required before sweeping with solver = DGSN_ANN).  The
-   problem keeps a reference; the ANN must outlive its use by the problem. */
+   problem keeps a reference; the ANN must outlive its use by the problem.
+   A paper-form (version-2) network is folded for this problem's cell sizes
+   here (a small device buffer owned by the problem; DGSN_ENOMEM if it cannot
+   be allocated). */
 int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
 
 /* Select the local solver of subsequent sweeps (DGSN_GE, DGSN_GE_DENSE or
@@ -243,15 +250,42 @@ int dgsn_local_solve(dgsn_ctx *ctx, const void *x, void *psi, long long n, int p
  * u32 n_hidden (<= 256), u32 n_out=8, u32 activation (0 = ReLU), u32 flags,
  * then float32 W1[n_hidden][n_in], b1[n_hidden], W2[n_out][n_hidden],
  * b2[n_out], then u32 CRC-32 (IEEE) of everything before it.
- * Returns DGSN_EFORMAT for a bad magic, shape, size or checksum.
+ *
+ * Version 2 holds the paper-form networks (Sec. 3, Eq. (ANN:Eq1)-(ANN:Eq4);
+ * one per octant, first paragraphs of Sec. 4): "DGSNANN1", u32 version=2,
+ * u32 n_in=26, u32 n_hidden (1..8), u32 n_out=8, u32 activation=1 (tanh),
+ * u32 flags=1 (ELU output layer), u32 n_nets=8, float32 alpha, float32
+ * beta_scale, float32 imin[26], float32 imax[26], then for octant
+ * o = [Ox<0] + 2[Oy<0] + 4[Oz<0] = 0..7: float32 W1[n_hidden][26],
+ * b1[n_hidden], W2[8][n_hidden], b2[8]; then the CRC-32.  The 26 inputs, in
+ * the cell's physical frame: the inflow values of the x, y and z faces (4
+ * each, face node = lower tangential bit + 2 * higher one), Omega_x,
+ * Omega_y, the 8 nodal sources, sigma_t, dx, dy, dz.  Each input is scaled
+ * as In = (I - alpha (imin + imax) / 2) / |imax - imin| (Eq. (ANN:Eq2)); the
+ * outputs are psi = z for z >= 0 and beta (exp(z) - 1) below, with
+ * beta = beta_scale * max of the 12 inflow values (Eq. (ANN:Eq4)).
+ * Returns DGSN_EFORMAT for a bad magic, shape, size, bound or checksum.
  */
 int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out);
 int dgsn_ann_destroy(dgsn_ann *ann);
 
+/* Artifact shape (host out, each pointer may be NULL): version (1 or 2),
+   inputs, hidden units, networks (1, or 8 per octant). */
+int dgsn_ann_info(const dgsn_ann *ann, int *version, int *n_in, int *n_hidden, int *n_nets);
+
+/*
+ * Paper-form network of one octant (version-2 artifacts) on raw inputs, on
+ * the vector ALUs in FP32: x device float [n][26] in the layout above, y
+ * device float [n][8] (physical node order).  DGSN_EINVAL for a version-1
+ * artifact or an octant outside 0..7.
+ */
+int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float *y,
+                          long long n, void *stream);
+
 /*
  * Raw network evaluation on the device with BF16 matrix cores and FP32
  * accumulation: y = W2 relu(W1 x + b1) + b2.  x: device float [n][24],
- * y: device float [n][8].
+ * y: device float [n][8].  Version-1 artifacts only (DGSN_EINVAL otherwise).
  */
 int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream);
 

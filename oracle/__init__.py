@@ -63,6 +63,18 @@ def _load():
     lib.orc_ann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 6 + [ctypes.c_int, ctypes.c_int] + [_D] * 5 + \
         [ctypes.c_double, ctypes.c_int, _I, _D, _D, ctypes.c_int]
+    lib.orc_pann_octant.argtypes = [_D]
+    lib.orc_pann_inputs.argtypes = [_D, _D, ctypes.c_double, _D, _D, _D]
+    lib.orc_pann_forward.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6 + \
+        [ctypes.c_int, _D, _D]
+    lib.orc_pann_cell_batch.argtypes = [ctypes.c_long] + [_D] * 5 + \
+        [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 7
+    _pann = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6
+    lib.orc_pann_sweep.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 5 + _pann + [_D, ctypes.c_int]
+    lib.orc_pann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 6 + _pann + [_D, ctypes.c_double, ctypes.c_int, _I, _D, _D,
+                                                 ctypes.c_int]
     _lib = lib
     return lib
 
@@ -326,6 +338,105 @@ def ann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=No
                                     float(tol), int(max_iter), ctypes.byref(it),
                                     ctypes.byref(resid), ctypes.byref(eps), int(nthreads))
     _check(rc, "ann_source_iterate")
+    return dict(phi=phi, iters=it.value, resid=resid.value, eps_s=eps.value, converged=(rc == 0))
+
+
+# ---------------------------------------------------------------------------
+# paper-form per-octant network (Sec. 3, Eq. (ANN:Eq1)-(ANN:Eq4))
+# ---------------------------------------------------------------------------
+# net = dict(kind="paper", W1 [8][nh][26], b1 [8][nh], W2 [8][8][nh], b2 [8][8],
+#            imin [26], imax [26], alpha, beta_scale)
+
+def pann_octant(omega):
+    """Octant o = [omega_x < 0] + 2 [omega_y < 0] + 4 [omega_z < 0]."""
+    return int(_load().orc_pann_octant(_p(_f64(omega, (3,)))))
+
+
+def pann_inputs(h, omega, sigma_t, S, psi_up):
+    """The 26 physical-frame inputs of one cell (see orc_pann_inputs)."""
+    I = np.zeros(26)
+    _load().orc_pann_inputs(_p(_f64(h, (3,))), _p(_f64(omega, (3,))), float(sigma_t),
+                            _p(_f64(S, (8,))), _p(_f64(psi_up, (6, 8))), _p(I))
+    return I
+
+
+def _pann_args(net):
+    W1 = _f64(net["W1"])
+    nh = W1.shape[1]
+    if W1.shape != (8, nh, 26):
+        raise ValueError("paper network W1 must be [8][nh][26]")
+    return (nh, float(net["alpha"]), float(net["beta_scale"]), _f64(net["imin"], (26,)),
+            _f64(net["imax"], (26,)), W1, _f64(net["b1"], (8, nh)), _f64(net["W2"], (8, 8, nh)),
+            _f64(net["b2"], (8, 8)))
+
+
+def _pann_ptrs(a):
+    nh, alpha, bs, imin, imax, W1, b1, W2, b2 = a
+    return [nh, alpha, bs] + [_p(x) for x in (imin, imax, W1, b1, W2, b2)]
+
+
+def pann_forward(net, octant, I):
+    """FP64 forward pass of octant's network on raw inputs I[26] -> psi[8]."""
+    a = _pann_args(net)
+    psi = np.zeros(8)
+    rc = _load().orc_pann_forward(*_pann_ptrs(a), int(octant), _p(_f64(I, (26,))), _p(psi))
+    _check(rc, "pann_forward")
+    return psi
+
+
+def pann_cell_batch(net, h, omega, sigma_t, S, psi_up):
+    """Batched one-cell solves by the paper-form network (physical orientation)."""
+    omega = _f64(omega)
+    n = omega.shape[0]
+    h = _f64(np.broadcast_to(np.asarray(h, np.float64), (n, 3)))
+    a = _pann_args(net)
+    out = np.zeros((n, 8))
+    rc = _load().orc_pann_cell_batch(n, _p(h), _p(omega), _p(_f64(sigma_t, (n,))),
+                                     _p(_f64(S, (n, 8))), _p(_f64(psi_up, (n, 6, 8))),
+                                     *_pann_ptrs(a), _p(out))
+    _check(rc, "pann_cell_batch")
+    return out
+
+
+def pann_sweep(net, mesh, omega, weight, sigma_t, src, psi_inc=None, nthreads=0):
+    """Sweep with the paper-form network in place of assembly + GE."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    phi = np.zeros((ng, ncell, 8))
+    rc = lib.orc_pann_sweep(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                            _p(sigma_t), _p(_f64(src, (ng, ncell, 8))), _p(inc),
+                            *_pann_ptrs(_pann_args(net)), _p(phi), int(nthreads))
+    _check(rc, "pann_sweep")
+    return phi
+
+
+def pann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-4,
+                        max_iter=1000, nthreads=0):
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    phi = np.zeros((ng, ncell, 8))
+    it = ctypes.c_int(0)
+    resid = ctypes.c_double(0)
+    eps = ctypes.c_double(0)
+    rc = lib.orc_pann_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                     _p(_f64(weight, (nd,))), _p(sigma_t),
+                                     _p(_f64(sigma_s, (ng, ncell))), _p(_f64(q, (ng, ncell))),
+                                     _p(inc), *_pann_ptrs(_pann_args(net)), _p(phi), float(tol),
+                                     int(max_iter), ctypes.byref(it), ctypes.byref(resid),
+                                     ctypes.byref(eps), int(nthreads))
+    _check(rc, "pann_source_iterate")
     return dict(phi=phi, iters=it.value, resid=resid.value, eps_s=eps.value, converged=(rc == 0))
 
 

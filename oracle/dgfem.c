@@ -717,9 +717,11 @@ int orc_cell_solve_batch(long n, const double *h, const double *omega, const dou
  *   hidden = act(W1 x + b1), y = W2 hidden + b2       (Eq. (ANN:Eq1))
  * W1 is [nh][nin] row-major, W2 is [nout][nh].  act 0 = ReLU, 1 = tanh.
  */
+struct orc_pann;
 struct orc_ann {
     int nin, nh, nout, act;
     const double *W1, *b1, *W2, *b2;
+    const struct orc_pann *paper;   /* not NULL: the paper-form per-octant network below */
 };
 
 /*
@@ -792,9 +794,96 @@ void orc_ann_forward(int nin, int nh, int nout, int act, const double *W1, const
     }
 }
 
+/*
+ * Paper-form network (Sec. 3 and the first paragraphs of Sec. 4), one per
+ * octant, evaluated on the cell in its physical orientation.
+ *   Input (26, in the order the paper lists them):
+ *     I[0..3]   inflow values of the x face, I[4..7] of the y face, I[8..11]
+ *               of the z face: the upwind traces at the cell's face nodes,
+ *               face node index = lower tangential bit + 2 * higher one
+ *               (a face with omega_a = 0 has no inflow and is fed as 0);
+ *     I[12], I[13] = omega_x, omega_y (the two independent direction
+ *               cosines; the octant fixes the sign of omega_z);
+ *     I[14..21] = nodal source S[n] (external + scattering, per steradian);
+ *     I[22]     = sigma_t;  I[23..25] = dx, dy, dz.
+ *   Scaling, Eq. (ANN:Eq2): In_j = (I_j - alpha (Imin_j + Imax_j) / 2) /
+ *               |Imax_j - Imin_j|, the norm read as the mean of the bounds.
+ *   Hidden:     h = tanh(W1 In + b1)                       (Eq. (ANN:Eq1), (ANN:Eq3))
+ *   Output:     z = W2 h + b2, psi_t = z_t if z_t >= 0, else beta (exp(z_t) - 1),
+ *               beta = beta_scale * max_j I_j over the 12 inflow values (Eq. (ANN:Eq4)).
+ * W1 [8][nh][26], b1 [8][nh], W2 [8][8][nh], b2 [8][8]; octant o = [omega_x < 0]
+ * + 2 [omega_y < 0] + 4 [omega_z < 0].  Output psi[n] in physical node order.
+ */
+struct orc_pann {
+    int nh;
+    double alpha, beta_scale;
+    const double *imin, *imax, *W1, *b1, *W2, *b2;
+};
+
+int orc_pann_octant(const double omega[3])
+{
+    return (omega[0] < 0.0 ? 1 : 0) + (omega[1] < 0.0 ? 2 : 0) + (omega[2] < 0.0 ? 4 : 0);
+}
+
+void orc_pann_inputs(const double h[3], const double omega[3], double sigma_t, const double S[8],
+                     const double psi_up[6][8], double I[26])
+{
+    for (int a = 0; a < 3; ++a) {
+        const int side = omega[a] < 0.0 ? 1 : 0;   /* inflow through the low face if omega_a > 0 */
+        const int f = 2 * a + side;
+        const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        for (int fn = 0; fn < 4; ++fn) {
+            const int n = (side << a) | ((fn & 1) << t1) | (((fn >> 1) & 1) << t2);
+            I[4 * a + fn] = omega[a] != 0.0 ? psi_up[f][n] : 0.0;
+        }
+    }
+    I[12] = omega[0];
+    I[13] = omega[1];
+    for (int n = 0; n < 8; ++n) I[14 + n] = S[n];
+    I[22] = sigma_t;
+    for (int a = 0; a < 3; ++a) I[23 + a] = h[a];
+}
+
+int orc_pann_forward(int nh, double alpha, double beta_scale, const double *imin,
+                     const double *imax, const double *W1, const double *b1, const double *W2,
+                     const double *b2, int octant, const double I[26], double psi[8])
+{
+    double In[26], hid[64];
+    if (nh < 1 || nh > 64 || octant < 0 || octant > 7) return ORC_EINVAL;
+    for (int j = 0; j < 26; ++j)
+        In[j] = (I[j] - alpha * 0.5 * (imin[j] + imax[j])) / fabs(imax[j] - imin[j]);
+    const double *w1 = W1 + (long)octant * nh * 26, *c1 = b1 + (long)octant * nh;
+    const double *w2 = W2 + (long)octant * 8 * nh, *c2 = b2 + (long)octant * 8;
+    for (int k = 0; k < nh; ++k) {
+        double v = c1[k];
+        for (int j = 0; j < 26; ++j) v += w1[k * 26 + j] * In[j];
+        hid[k] = tanh(v);
+    }
+    double pmax = I[0];
+    for (int j = 1; j < 12; ++j)
+        if (I[j] > pmax) pmax = I[j];
+    const double beta = beta_scale * pmax;
+    for (int t = 0; t < 8; ++t) {
+        double z = c2[t];
+        for (int k = 0; k < nh; ++k) z += w2[t * nh + k] * hid[k];
+        psi[t] = z >= 0.0 ? z : beta * (exp(z) - 1.0);
+    }
+    return ORC_OK;
+}
+
+static int pann_cell(const struct orc_pann *p, const double h[3], const double omega[3],
+                     double sigma_t, const double S[8], const double psi_up[6][8], double psi[8])
+{
+    double I[26];
+    orc_pann_inputs(h, omega, sigma_t, S, psi_up, I);
+    return orc_pann_forward(p->nh, p->alpha, p->beta_scale, p->imin, p->imax, p->W1, p->b1, p->W2,
+                            p->b2, orc_pann_octant(omega), I, psi);
+}
+
 static int ann_cell(const orc_ann *net, const double h[3], const double omega[3], double sigma_t,
                     const double S[8], const double psi_up[6][8], double psi[8])
 {
+    if (net->paper) return pann_cell(net->paper, h, omega, sigma_t, S, psi_up, psi);
     double x[24], y[8], m;
     const int mask = orc_ann_features(h, omega, sigma_t, S, psi_up, x, &m);
     if (m == 0.0) {
@@ -812,7 +901,7 @@ int orc_ann_cell_batch(long n, const double *h, const double *omega, const doubl
                        const double *S, const double *psi_up, int nh, int act, const double *W1,
                        const double *b1, const double *W2, const double *b2, double *psi)
 {
-    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2, NULL};
     if (nh < 1 || nh > 1024) return ORC_EINVAL;
     for (long i = 0; i < n; ++i)
         ann_cell(&net, h + 3 * i, omega + 3 * i, sigma_t[i], S + 8 * i,
@@ -827,7 +916,7 @@ int orc_ann_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int n
                   const double *b1, const double *W2, const double *b2, double *phi,
                   int nthreads)
 {
-    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2, NULL};
     if (nh < 1 || nh > 1024) return ORC_EINVAL;
     return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
                      NULL, &net, nthreads);
@@ -841,8 +930,56 @@ int orc_ann_source_iterate(int nx, int ny, int nz, double lx, double ly, double 
                            double tol, int max_iter, int *iters, double *resid, double *eps_s,
                            int nthreads)
 {
-    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2};
+    orc_ann net = {24, nh, 8, act, W1, b1, W2, b2, NULL};
     if (nh < 1 || nh > 1024) return ORC_EINVAL;
+    return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads);
+}
+
+/* Batched paper-form network one-cell solves (physical orientation). */
+int orc_pann_cell_batch(long n, const double *h, const double *omega, const double *sigma_t,
+                        const double *S, const double *psi_up, int nh, double alpha,
+                        double beta_scale, const double *imin, const double *imax,
+                        const double *W1, const double *b1, const double *W2, const double *b2,
+                        double *psi)
+{
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
+    if (nh < 1 || nh > 64) return ORC_EINVAL;
+    for (long i = 0; i < n; ++i) {
+        const int rc = pann_cell(&p, h + 3 * i, omega + 3 * i, sigma_t[i], S + 8 * i,
+                                 (const double(*)[8])(psi_up + 48 * i), psi + 8 * i);
+        if (rc) return rc;
+    }
+    return ORC_OK;
+}
+
+/* Sweep / source iteration with the paper-form network in place of assembly + GE. */
+int orc_pann_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                   const double *omega, const double *weight, const double *sigma_t,
+                   const double *src, const double psi_inc[6], int nh, double alpha,
+                   double beta_scale, const double *imin, const double *imax, const double *W1,
+                   const double *b1, const double *W2, const double *b2, double *phi,
+                   int nthreads)
+{
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
+    orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
+    if (nh < 1 || nh > 64) return ORC_EINVAL;
+    return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
+                     NULL, &net, nthreads);
+}
+
+int orc_pann_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                            int nd, const double *omega, const double *weight,
+                            const double *sigma_t, const double *sigma_s, const double *q,
+                            const double psi_inc[6], int nh, double alpha, double beta_scale,
+                            const double *imin, const double *imax, const double *W1,
+                            const double *b1, const double *W2, const double *b2, double *phi,
+                            double tol, int max_iter, int *iters, double *resid, double *eps_s,
+                            int nthreads)
+{
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
+    orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
+    if (nh < 1 || nh > 64) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads);
 }

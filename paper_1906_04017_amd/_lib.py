@@ -78,6 +78,9 @@ SIGNATURES = {
     "dgsn_ann_load": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(_VP)]),
     "dgsn_ann_destroy": (_I, [_VP]),
     "dgsn_ann_infer": (_I, [_VP, _VP, _VP, _LL, _VP]),
+    "dgsn_ann_info": (_I, [_VP, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                           ctypes.POINTER(_I)]),
+    "dgsn_ann_infer_octant": (_I, [_VP, _I, _VP, _VP, _LL, _VP]),
     "dgsn_problem_stats": (_I, [_VP, ctypes.POINTER(_LL), _PI, _PD]),
     "dgsn_problem_set_timing": (_I, [_VP, _I]),
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),

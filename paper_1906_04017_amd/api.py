@@ -90,6 +90,27 @@ class Ann:
         self._h = ctypes.c_void_p()
         _lib.check(_lib.load().dgsn_ann_load(ctx._h, str(path).encode(), ctypes.byref(self._h)))
 
+    def info(self):
+        """(version, n_in, n_hidden, n_nets) of the artifact."""
+        v = [ctypes.c_int() for _ in range(4)]
+        _lib.check(_lib.load().dgsn_ann_info(self._h, *[ctypes.byref(a) for a in v]))
+        return tuple(a.value for a in v)
+
+    @property
+    def version(self):
+        return self.info()[0]
+
+    def infer_octant(self, octant, x, out=None):
+        """Paper-form network of one octant on raw inputs x [n,26] float32 -> [n,8]."""
+        x = x.contiguous()
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 26:
+            raise ValueError("x must be a float32 [n, 26] tensor")
+        y = out if out is not None else torch.empty((x.shape[0], 8), dtype=torch.float32,
+                                                    device=x.device)
+        _lib.check(_lib.load().dgsn_ann_infer_octant(self._h, int(octant), _ptr(x), _ptr(y),
+                                                     x.shape[0], _stream(x.device)))
+        return y
+
     def infer(self, x, out=None):
         """y = W2 relu(W1 x + b1) + b2 on the BF16 matrix cores; x [n,24] float32."""
         x = x.contiguous()

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "ann_body.hpp"
+#include "pann_body.hpp"
 
 namespace dgsn {
 
@@ -47,6 +48,26 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
             for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
         }
         __syncthreads();
+    }
+}
+
+// Paper-form network on raw inputs: one thread per sample, the octant's
+// image (scaling folded into the first layer) read with scalar loads.
+__global__ __launch_bounds__(256) void pann_infer_kernel(const float *__restrict__ w,
+                                                         const float *__restrict__ x,
+                                                         float *__restrict__ y, long long n)
+{
+    for (long long s = blockIdx.x * 256ll + threadIdx.x; s < n; s += (long long)gridDim.x * 256) {
+        float f[kPannIn], o[8];
+#pragma unroll
+        for (int k = 0; k < kPannIn; ++k) f[k] = x[s * kPannIn + k];
+        float pmax = f[0];
+#pragma unroll
+        for (int j = 1; j < 12; ++j) pmax = fmaxf(pmax, f[j]);
+        pann_layers<kPannIn, kPannRawW1, kPannRawB1, kPannRawW2, kPannRawB2, kPannRawBeta>(
+            w, f, pmax, o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
     }
 }
 
@@ -119,9 +140,91 @@ int build_params(dgsn_ann *a)
     return DGSN_OK;
 }
 
+// Version 2: the raw-input images of the 8 octant networks.  Eq. (ANN:Eq2)
+// In_j = (I_j - c_j) / r_j with c_j = alpha (Imin_j + Imax_j) / 2 and
+// r_j = |Imax_j - Imin_j| is folded into the first layer:
+// W1' = W1 / r, b1' = b1 - W1 c / r (hidden units beyond n_hidden are zero).
+int build_pann_params(dgsn_ann *a)
+{
+    const int H = a->n_hidden;
+    std::vector<float> img((size_t)8 * kPannRawStride, 0.0f);
+    for (int o = 0; o < 8; ++o) {
+        float *w = img.data() + (size_t)o * kPannRawStride;
+        const float *W1 = a->W1.data() + (size_t)o * H * kPannIn;
+        const float *b1 = a->b1.data() + (size_t)o * H;
+        const float *W2 = a->W2.data() + (size_t)o * 8 * H;
+        const float *b2 = a->b2.data() + (size_t)o * 8;
+        for (int k = 0; k < H; ++k) {
+            double bias = b1[k];
+            for (int j = 0; j < kPannIn; ++j) {
+                const double c = (double)a->alpha * 0.5 * ((double)a->imin[j] + a->imax[j]);
+                const double r = std::fabs((double)a->imax[j] - a->imin[j]);
+                w[kPannRawW1 + k * kPannIn + j] = (float)(W1[k * kPannIn + j] / r);
+                bias -= W1[k * kPannIn + j] * c / r;
+            }
+            w[kPannRawB1 + k] = (float)bias;
+            for (int t = 0; t < 8; ++t) w[kPannRawW2 + t * kPannHidden + k] = W2[t * H + k];
+        }
+        for (int t = 0; t < 8; ++t) w[kPannRawB2 + t] = b2[t];
+        w[kPannRawBeta] = a->beta_scale;
+    }
+    DGSN_TRY(a->d_params.alloc(img.size() * sizeof(float)));
+    DGSN_HIP(hipMemcpy(a->d_params.ptr, img.data(), img.size() * sizeof(float),
+                       hipMemcpyHostToDevice));
+    return DGSN_OK;
+}
+
 }  // namespace
 
 const void *ann_device_params(const dgsn_ann *a) { return a ? a->d_params.ptr : nullptr; }
+
+// Folding for one problem (cell sizes h), per octant o with reflection mask o
+// (bit a set: Omega_a < 0; canonical node n' is physical node n' ^ o):
+//   canonical inflow face node fn of axis a is physical face node
+//   fn ^ (mask bits of the two tangential axes, lower axis first);
+//   kappa_a = |Omega_a| / h_a, so Omega_a = s_a h_a kappa_a (s_a = -1 on set bits);
+//   canonical source node n' is physical node n' ^ o;
+//   the cell sizes are constant inputs, added to the bias;
+//   canonical output t' is the physical output t' ^ o.
+int pann_problem_image(const dgsn_ann *a, const double h[3], std::vector<float> &out)
+{
+    if (!a || a->version != 2) return set_error(DGSN_EINVAL, "not a paper-form network");
+    const int H = a->n_hidden;
+    out.assign((size_t)8 * kPannStride, 0.0f);
+    for (int o = 0; o < 8; ++o) {
+        float *w = out.data() + (size_t)o * kPannStride;
+        const float *W1 = a->W1.data() + (size_t)o * H * kPannIn;
+        const float *b1 = a->b1.data() + (size_t)o * H;
+        const float *W2 = a->W2.data() + (size_t)o * 8 * H;
+        const float *b2 = a->b2.data() + (size_t)o * 8;
+        const int mx = o & 1, my = (o >> 1) & 1, mz = (o >> 2) & 1;
+        const int tang[3] = {my | (mz << 1), mx | (mz << 1), mx | (my << 1)};
+        for (int k = 0; k < H; ++k) {
+            // scaled first layer on the raw physical inputs
+            double ws[kPannIn];
+            double bias = b1[k];
+            for (int j = 0; j < kPannIn; ++j) {
+                const double c = (double)a->alpha * 0.5 * ((double)a->imin[j] + a->imax[j]);
+                const double r = std::fabs((double)a->imax[j] - a->imin[j]);
+                ws[j] = W1[k * kPannIn + j] / r;
+                bias -= W1[k * kPannIn + j] * c / r;
+            }
+            float *r1 = w + kPannW1 + k * kPannFeat;
+            for (int ax = 0; ax < 3; ++ax)
+                for (int fn = 0; fn < 4; ++fn) r1[4 * ax + fn] = (float)ws[4 * ax + (fn ^ tang[ax])];
+            r1[12] = (float)(ws[12] * (mx ? -h[0] : h[0]));
+            r1[13] = (float)(ws[13] * (my ? -h[1] : h[1]));
+            for (int n = 0; n < 8; ++n) r1[14 + n] = (float)ws[14 + (n ^ o)];
+            r1[22] = (float)ws[22];
+            for (int ax = 0; ax < 3; ++ax) bias += ws[23 + ax] * h[ax];
+            w[kPannB1 + k] = (float)bias;
+            for (int t = 0; t < 8; ++t) w[kPannW2 + t * kPannHidden + k] = W2[(t ^ o) * H + k];
+        }
+        for (int t = 0; t < 8; ++t) w[kPannB2 + t] = b2[t ^ o];
+        w[kPannBeta] = a->beta_scale;
+    }
+    return DGSN_OK;
+}
 
 }  // namespace dgsn
 
@@ -144,16 +247,34 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
         if (data.size() > (1u << 24)) break;
     }
     std::fclose(f);
-    const size_t hdr = 8 + 6 * 4;
-    if (data.size() < hdr + 4 || std::memcmp(data.data(), "DGSNANN1", 8) != 0)
+    if (data.size() < 8 + 6 * 4 + 4 || std::memcmp(data.data(), "DGSNANN1", 8) != 0)
         return set_error(DGSN_EFORMAT, "%s: not a DGSNANN1 artifact", path);
     uint32_t v[6];
     std::memcpy(v, data.data() + 8, sizeof(v));
     const uint32_t version = v[0], n_in = v[1], n_hidden = v[2], n_out = v[3], act = v[4];
-    if (version != 1 || n_in != 24 || n_out != 8 || n_hidden < 1 || n_hidden > kMaxHidden)
+    const uint32_t flags = v[5];
+    uint32_t n_nets = 1;
+    size_t hdr = 8 + 6 * 4;
+    if (version == 2) {
+        // u32 n_nets, f32 alpha, f32 beta_scale, f32 imin[26], f32 imax[26]
+        if (data.size() < hdr + 4 + 8 + 8 * 26 + 4)
+            return set_error(DGSN_EFORMAT, "%s: truncated version-2 header", path);
+        std::memcpy(&n_nets, data.data() + hdr, 4);
+        hdr += 4 + 8 + 2 * 4 * 26;
+        if (n_in != (uint32_t)kPannIn || n_out != 8 || n_nets != 8 || n_hidden < 1 ||
+            n_hidden > (uint32_t)kPannHidden || act != 1 || flags != 1)
+            return set_error(DGSN_EFORMAT,
+                             "%s: unsupported version-2 shape (%u-%u-%u, %u nets, act %u, "
+                             "flags %u; expected 26-(1..8)-8, 8 nets, tanh, ELU output)",
+                             path, n_in, n_hidden, n_out, n_nets, act, flags);
+    } else if (version != 1 || n_in != 24 || n_out != 8 || n_hidden < 1 ||
+               n_hidden > kMaxHidden) {
         return set_error(DGSN_EFORMAT, "%s: unsupported shape (version %u, %u-%u-%u)", path,
                          version, n_in, n_hidden, n_out);
-    const size_t nparam = (size_t)n_hidden * n_in + n_hidden + (size_t)n_out * n_hidden + n_out;
+    }
+    const size_t per_net =
+        (size_t)n_hidden * n_in + n_hidden + (size_t)n_out * n_hidden + n_out;
+    const size_t nparam = per_net * n_nets;
     if (data.size() != hdr + 4 * nparam + 4)
         return set_error(DGSN_EFORMAT, "%s: size %zu does not match the header", path,
                          data.size());
@@ -161,12 +282,28 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
     std::memcpy(&crc, data.data() + data.size() - 4, 4);
     if (crc != crc32_ieee(data.data(), data.size() - 4))
         return set_error(DGSN_EFORMAT, "%s: checksum mismatch", path);
-    if (act != 0)
+    if (version == 1 && act != 0)
         return set_error(DGSN_EUNSUPPORTED, "%s: only ReLU hidden layers run on the matrix cores",
                          path);
-    if (n_hidden > kHiddenPad)
+    if (version == 1 && n_hidden > kHiddenPad)
         return set_error(DGSN_EUNSUPPORTED, "%s: at most %d hidden units are supported", path,
                          kHiddenPad);
+    float alpha = 0.0f, beta_scale = 0.0f;
+    std::vector<float> imin, imax;
+    if (version == 2) {
+        const unsigned char *q = data.data() + 8 + 6 * 4 + 4;
+        std::memcpy(&alpha, q, 4);
+        std::memcpy(&beta_scale, q + 4, 4);
+        imin.resize(kPannIn);
+        imax.resize(kPannIn);
+        std::memcpy(imin.data(), q + 8, 4 * kPannIn);
+        std::memcpy(imax.data(), q + 8 + 4 * kPannIn, 4 * kPannIn);
+        if (!std::isfinite(alpha) || !std::isfinite(beta_scale) || beta_scale < 0.0f)
+            return set_error(DGSN_EFORMAT, "%s: bad alpha / beta scale", path);
+        for (int j = 0; j < kPannIn; ++j)
+            if (!std::isfinite(imin[j]) || !std::isfinite(imax[j]) || imin[j] == imax[j])
+                return set_error(DGSN_EFORMAT, "%s: bad input bounds of input %d", path, j);
+    }
     {
         const float *pw = reinterpret_cast<const float *>(data.data() + hdr);
         for (size_t i = 0; i < nparam; ++i)
@@ -178,23 +315,32 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
     dgsn_ann *a = new (std::nothrow) dgsn_ann();
     if (!a) return set_error(DGSN_ENOMEM, "host allocation failed");
     a->ctx = ctx;
+    a->version = (int)version;
     a->n_in = (int)n_in;
     a->n_hidden = (int)n_hidden;
     a->n_out = (int)n_out;
     a->act = (int)act;
+    a->n_nets = (int)n_nets;
+    a->alpha = alpha;
+    a->beta_scale = beta_scale;
+    a->imin = imin;
+    a->imax = imax;
     const float *pf = reinterpret_cast<const float *>(data.data() + hdr);
-    a->W1.assign(pf, pf + (size_t)n_hidden * n_in);
-    pf += (size_t)n_hidden * n_in;
-    a->b1.assign(pf, pf + n_hidden);
-    pf += n_hidden;
-    a->W2.assign(pf, pf + (size_t)n_out * n_hidden);
-    pf += (size_t)n_out * n_hidden;
-    a->b2.assign(pf, pf + n_out);
+    for (uint32_t k = 0; k < n_nets; ++k) {
+        a->W1.insert(a->W1.end(), pf, pf + (size_t)n_hidden * n_in);
+        pf += (size_t)n_hidden * n_in;
+        a->b1.insert(a->b1.end(), pf, pf + n_hidden);
+        pf += n_hidden;
+        a->W2.insert(a->W2.end(), pf, pf + (size_t)n_out * n_hidden);
+        pf += (size_t)n_out * n_hidden;
+        a->b2.insert(a->b2.end(), pf, pf + n_out);
+        pf += n_out;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) {
         delete a;
         return set_error(DGSN_EHIP, "hipSetDevice failed");
     }
-    int rc = build_params(a);
+    int rc = version == 2 ? build_pann_params(a) : build_params(a);
     if (rc) {
         delete a;
         return rc;
@@ -210,10 +356,48 @@ int dgsn_ann_destroy(dgsn_ann *ann)
     return DGSN_OK;
 }
 
+int dgsn_ann_info(const dgsn_ann *ann, int *version, int *n_in, int *n_hidden, int *n_nets)
+{
+    clear_error();
+    if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
+    if (version) *version = ann->version;
+    if (n_in) *n_in = ann->n_in;
+    if (n_hidden) *n_hidden = ann->n_hidden;
+    if (n_nets) *n_nets = ann->n_nets;
+    return DGSN_OK;
+}
+
+int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float *y, long long n,
+                          void *stream)
+{
+    clear_error();
+    if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
+    if (ann->version != 2)
+        return set_error(DGSN_EINVAL, "dgsn_ann_infer_octant needs a paper-form (version 2) "
+                                      "artifact; use dgsn_ann_infer");
+    if (octant < 0 || octant > 7) return set_error(DGSN_EINVAL, "octant must be in 0..7");
+    if (n < 0) return set_error(DGSN_EINVAL, "n must be >= 0");
+    if (n == 0) return DGSN_OK;
+    if (!x || !y) return set_error(DGSN_EINVAL, "x and y must be set");
+    DGSN_HIP(hipSetDevice(ann->ctx->device));
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(pann_infer_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream),
+                       static_cast<const float *>(ann->d_params.ptr) +
+                           (size_t)octant * kPannRawStride,
+                       x, y, n);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
 int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream)
 {
     clear_error();
     if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
+    if (ann->version != 1)
+        return set_error(DGSN_EINVAL, "dgsn_ann_infer needs a version-1 artifact; use "
+                                      "dgsn_ann_infer_octant for the paper-form networks");
     if (n < 0) return set_error(DGSN_EINVAL, "n must be >= 0");
     if (n == 0) return DGSN_OK;
     if (!x || !y) return set_error(DGSN_EINVAL, "x and y must be set");

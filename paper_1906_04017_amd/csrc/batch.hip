@@ -88,13 +88,24 @@ __device__ __forceinline__ PlaneArgs<float> problem_args(const PlaneArgs<float> 
     return r;
 }
 
+// solver code of a problem in the batch tables: DGSN_GE, DGSN_ANN (the
+// matrix-core network) or the paper-form network
+constexpr int kBatchPaperAnn = 3;
+
 template <bool kCoh>
 __device__ __forceinline__ void batch_body(const PlaneArgs<float> &A, const float inc[3],
                                            int solver, int tileb, const SegLane &l, int tid,
                                            bool tv, uint32_t pt, int o, TileLds<float> &L,
                                            AnnLds &al)
 {
-    if (solver == DGSN_ANN) {
+    if (solver == kBatchPaperAnn) {
+        if (tileb == 2)
+            tile_body<float, kFormAnnPaper, 2, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
+                                                                   o, l.ok, L, nullptr);
+        else
+            tile_body<float, kFormAnnPaper, 1, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
+                                                                   o, l.ok, L, nullptr);
+    } else if (solver == DGSN_ANN) {
         if (tileb == 2)
             tile_body<float, kFormAnn, 2, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt, o,
                                                               l.ok, L, &al);
@@ -229,6 +240,12 @@ int blocks_of(const dgsn_problem *p, int ncp)
     return (ncp + nc - 1) / nc;
 }
 
+int batch_solver(const dgsn_problem *p)
+{
+    if (p->solver != DGSN_ANN) return DGSN_GE;
+    return p->ann->version == 2 ? kBatchPaperAnn : DGSN_ANN;
+}
+
 int build_tables(dgsn_batch *B)
 {
     const int n = (int)B->probs.size();
@@ -245,7 +262,7 @@ int build_tables(dgsn_batch *B)
     B->blocks_per_step.assign(B->nsteps, 0);
     for (int b = 0; b < n; ++b) {
         dgsn_problem *p = B->probs[b];
-        meta[4 * b + 0] = p->solver == DGSN_ANN ? DGSN_ANN : DGSN_GE;
+        meta[4 * b + 0] = batch_solver(p);
         meta[4 * b + 1] = B->tileb[b];
         meta[4 * b + 2] = steps[b] - 1;
         meta[4 * b + 3] = 0;
@@ -312,7 +329,7 @@ int build_flow_tables(dgsn_batch *B)
         A.cells = static_cast<const uint32_t *>(tb > 1 ? p->d_tiles[tb].ptr : p->d_plane_cells.ptr);
         A.ncp = 0;
         args[b] = A;
-        meta[4 * b + 0] = p->solver == DGSN_ANN ? DGSN_ANN : DGSN_GE;
+        meta[4 * b + 0] = batch_solver(p);
         meta[4 * b + 1] = tb;
         meta[4 * b + 2] = ns - 1;
         meta[4 * b + 3] = 0;

@@ -185,16 +185,22 @@ __host__ __device__ constexpr bool cube_nz(int k, int i, int j)
 }
 
 // Elimination restricted to the structurally non-zero entries of the
-// mass-inverse cell matrix, without row exchanges.  Returns, per lane,
-// whether partial pivoting would have exchanged rows in some column (a
-// structurally possible sub-diagonal entry larger than the pivot); the caller
-// then redoes the wave with the dense, pivoted ge_solve8, so the result is
-// always that of partial pivoting.  For these matrices the diagonal dominates
-// its column and the redo never happens.
+// mass-inverse cell matrix, without row exchanges, split into the
+// factorisation of the matrix and the solve of one right-hand side.  The
+// factorisation leaves the multipliers l_ik below the diagonal of a, the
+// eliminated upper triangle above it and the reciprocal pivots in rinv; it
+// returns, per lane, whether partial pivoting would have exchanged rows in
+// some column (a structurally possible sub-diagonal entry larger than the
+// pivot), in which case the caller uses the dense, pivoted ge_solve8 instead,
+// so the result is always that of partial pivoting.  For these matrices the
+// diagonal dominates its column and that never happens.  The solve applies
+// the multipliers to b in the order in which the elimination meets them, so
+// factor + solve performs exactly the operations of the interleaved
+// elimination: one factorisation serves every cell with the same matrix
+// (same direction and sigma_t) with bitwise the same result.
 template <typename Real>
-__device__ __forceinline__ bool ge_solve8_cube(Real a[8][8], Real b[8])
+__device__ __forceinline__ bool cube_factor(Real a[8][8], Real rinv[8])
 {
-    Real rinv[8];
     bool exchange = false;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -211,9 +217,20 @@ __device__ __forceinline__ bool ge_solve8_cube(Real a[8][8], Real b[8])
 #pragma unroll
             for (int j = k + 1; j < 8; ++j)
                 if (cube_nz(k, k, j)) a[i][j] = fma(-l, a[k][j], a[i][j]);
-            b[i] = fma(-l, b[k], b[i]);
+            a[i][k] = l;
         }
     }
+    return exchange;
+}
+
+template <typename Real>
+__device__ __forceinline__ void cube_solve(const Real a[8][8], const Real rinv[8], Real b[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = k + 1; i < 8; ++i)
+            if (cube_nz(k, i, k)) b[i] = fma(-a[i][k], b[k], b[i]);
 #pragma unroll
     for (int i = 7; i >= 0; --i) {
         Real s = b[i];
@@ -222,6 +239,14 @@ __device__ __forceinline__ bool ge_solve8_cube(Real a[8][8], Real b[8])
             if (cube_nz(8, i, j)) s = fma(-a[i][j], b[j], s);
         b[i] = s * rinv[i];
     }
+}
+
+template <typename Real>
+__device__ __forceinline__ bool ge_solve8_cube(Real a[8][8], Real b[8])
+{
+    Real rinv[8];
+    const bool exchange = cube_factor(a, rinv);
+    cube_solve(a, rinv, b);
     return exchange;
 }
 

@@ -45,6 +45,9 @@ constexpr int kMaxTile = 3;       // largest tile edge of the sweep
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
 
 const void *ann_device_params(const dgsn_ann *a);
+// Per-octant weight images of a paper-form network for a problem with cell
+// sizes h (canonical-frame features, layout in pann_body.hpp).
+int pann_problem_image(const dgsn_ann *a, const double h[3], std::vector<float> &out);
 
 // one unit of the dataflow schedule (host copy; see flow_units_host)
 struct FlowUnitHost {
@@ -72,9 +75,13 @@ struct dgsn_ctx {
 
 struct dgsn_ann {
     dgsn_ctx *ctx = nullptr;
-    int n_in = 24, n_hidden = 0, n_out = 8, act = 0;
-    std::vector<float> W1, b1, W2, b2;   // host copies (fp32)
-    // device: bf16 packed operand images and fp32 biases (layout in ann.hip)
+    int version = 1;                     // 1: canonical 24-input net, 2: paper-form per octant
+    int n_in = 24, n_hidden = 0, n_out = 8, act = 0, n_nets = 1;
+    float alpha = 0.0f, beta_scale = 0.0f;   // version 2: Eq. (ANN:Eq2) and (ANN:Eq4)
+    std::vector<float> imin, imax;       // version 2: input bounds [26]
+    std::vector<float> W1, b1, W2, b2;   // host copies (fp32), n_nets networks back to back
+    // device: version 1, bf16 packed operand images and fp32 biases (layout in
+    // ann.hip); version 2, the per-octant raw-input images (pann_body.hpp)
     dgsn::DevBuf d_params;
 };
 
@@ -93,6 +100,7 @@ struct dgsn_problem {
     size_t real_size = 4;
     double psi_inc[6] = {0, 0, 0, 0, 0, 0};
     const dgsn_ann *ann = nullptr;
+    dgsn::DevBuf d_pann;    // paper-form network folded for this problem (pann_body.hpp)
 
     std::vector<int> dir_user;       // octant-sorted slot -> user direction index
     std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64

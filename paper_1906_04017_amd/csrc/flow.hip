@@ -120,6 +120,26 @@ void launch_flow_b(const PlaneArgs<Real> &A, const FlowArgs &F, int b, bool stor
     }
 }
 
+// The paper-form network: FP32 forward sweeps only.
+void launch_flow_pann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 grid, dim3 block,
+                      hipStream_t s)
+{
+    switch (b) {
+    case 3:
+        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 3, false, false>), grid, block, 0,
+                           s, A, F);
+        break;
+    case 2:
+        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 2, false, false>), grid, block, 0,
+                           s, A, F);
+        break;
+    default:
+        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 1, false, false>), grid, block, 0,
+                           s, A, F);
+        break;
+    }
+}
+
 }  // namespace
 
 template <typename Real>
@@ -127,12 +147,17 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
                 bool adjoint, hipStream_t s)
 {
     const dim3 block(256);
+    if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
+        return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
     for (unsigned done = 0; done < F.units_o; done += kFlowMaxGroupsPerOctant) {
         const dim3 grid(8 * std::min(F.units_o - done, kFlowMaxGroupsPerOctant));
-        if (form == kFormDense)
+        if (form == kFormDense) {
             launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
-        else
+        } else if (form == kFormAnnPaper) {
+            if constexpr (sizeof(Real) == 4) launch_flow_pann(A, F, b, grid, block, s);
+        } else {
             launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
+        }
         DGSN_HIP(hipGetLastError());
     }
     DGSN_HIP(hipGetLastError());

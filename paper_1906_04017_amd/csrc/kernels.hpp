@@ -99,6 +99,7 @@ int reduce_blocks_for(long long nv);
 constexpr int kFormMassInv = 0;   // mass-inverse form, structured elimination
 constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense elimination
 constexpr int kFormAnn = 2;       // the shallow network in place of assembly + elimination
+constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector ALUs)
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 

@@ -282,14 +282,20 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
 {
     PlaneArgs<Real> A = plane_args<Real>(p, src, adjoint);
     A.grad_oct = grad_oct;
-    const bool ann = p->solver == DGSN_ANN && !adjoint;
-    if (ann) {
+    const bool anyann = p->solver == DGSN_ANN && !adjoint;
+    if (anyann) {
         if (!p->ann) return set_error(DGSN_EINVAL, "solver is DGSN_ANN but no ANN is attached");
         if (store_psi)
             return set_error(DGSN_EUNSUPPORTED, "store_psi is not available with the ANN solver");
-        A.ann_params = ann_device_params(p->ann);
     }
-    const int form = p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv;
+    // the matrix-core network (version 1) has its own kernel; the paper-form
+    // network (version 2) runs inside the GE kernels as another local solver
+    const bool paper = anyann && p->ann->version == 2;
+    const bool ann = anyann && !paper;
+    if (ann) A.ann_params = ann_device_params(p->ann);
+    if (paper) A.ann_params = p->d_pann.ptr;
+    const int form = paper ? kFormAnnPaper
+                           : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
     const int tb = p->tile_b;
     const bool tiled = tb > 1;
     const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles[tb].ptr
@@ -489,7 +495,8 @@ namespace dgsn {
 PlaneArgs<float> batch_plane_args(dgsn_problem *p, const void *src)
 {
     PlaneArgs<float> A = plane_args<float>(p, src, false);
-    if (p->solver == DGSN_ANN) A.ann_params = ann_device_params(p->ann);
+    if (p->solver == DGSN_ANN)
+        A.ann_params = p->ann->version == 2 ? p->d_pann.ptr : ann_device_params(p->ann);
     return A;
 }
 
@@ -511,8 +518,9 @@ int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2 * kMaxTile]
     const int saved_timing = p->timing;
     p->timing = 0;
     // candidates: every tile edge with the hyperplane schedule, and with the
-    // dataflow schedule where it applies (GE solvers)
-    const int nsched = p->solver == DGSN_ANN || flow_prepare(p) != DGSN_OK ? 1 : 2;
+    // dataflow schedule where it applies (all but the matrix-core network)
+    const bool mfma_ann = p->solver == DGSN_ANN && p->ann->version == 1;
+    const int nsched = mfma_ann || flow_prepare(p) != DGSN_OK ? 1 : 2;
     clear_error();
     double best[2][kMaxTile];
     for (int sc = 0; sc < 2; ++sc)
@@ -846,6 +854,15 @@ int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     if (ann && p->precision != DGSN_FP32)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    if (ann && ann->version == 2) {
+        // fold the scaling, the cell sizes and the octant relabelling in once
+        std::vector<float> img;
+        DGSN_TRY(pann_problem_image(ann, p->h, img));
+        DGSN_HIP(hipSetDevice(p->ctx->device));
+        DGSN_TRY(p->d_pann.alloc(img.size() * sizeof(float)));
+        DGSN_HIP(hipMemcpy(p->d_pann.ptr, img.data(), img.size() * sizeof(float),
+                           hipMemcpyHostToDevice));
+    }
     p->ann = ann;
     return DGSN_OK;
 }

@@ -244,16 +244,40 @@ int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s)
     return DGSN_OK;
 }
 
+// The paper-form network: FP32 forward sweeps only.
+void launch_tile_pann(const PlaneArgs<float> &A, int b, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (b) {
+    case 3:
+        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 3, false, false>), grid, block, 0,
+                           s, A);
+        break;
+    case 2:
+        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 2, false, false>), grid, block, 0,
+                           s, A);
+        break;
+    default:
+        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 1, false, false>), grid, block, 0,
+                           s, A);
+        break;
+    }
+}
+
 template <typename Real>
 int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,
                 hipStream_t s)
 {
     const dim3 block(256);
     const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
-    if (form == kFormDense)
+    if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
+        return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
+    if (form == kFormDense) {
         launch_tile_b<Real, kFormDense>(A, b, store_psi, adjoint, grid, block, s);
-    else
+    } else if (form == kFormAnnPaper) {
+        if constexpr (sizeof(Real) == 4) launch_tile_pann(A, b, grid, block, s);
+    } else {
         launch_tile_b<Real, kFormMassInv>(A, b, store_psi, adjoint, grid, block, s);
+    }
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

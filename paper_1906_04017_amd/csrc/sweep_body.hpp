@@ -5,6 +5,7 @@
 
 #include "ann_body.hpp"
 #include "cell.hpp"
+#include "pann_body.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -107,12 +108,10 @@ __device__ __forceinline__ void front_store(Real *base, __amdgpu_buffer_rsrc_t r
     }
 }
 
-// Mass-inverse cell system (P_d + sigma_t I, S + sum_a kappa_a c_a), with the
-// structural zeros of P_d as literal zeros.
+// Mass-inverse cell matrix P_d + sigma_t I, with the structural zeros of P_d
+// as literal zeros.
 template <typename Real>
-__device__ __forceinline__ void massinv_system(const Real k[3], Real st, const Real sc[8],
-                                               const Real vx[4], const Real vy[4],
-                                               const Real vz[4], Real a[8][8], Real b[8])
+__device__ __forceinline__ void massinv_matrix(const Real k[3], Real st, Real a[8][8])
 {
     const Real base = fma(Real(3), k[0] + k[1] + k[2], st);
 #pragma unroll
@@ -128,6 +127,13 @@ __device__ __forceinline__ void massinv_system(const Real k[3], Real st, const R
         }
         a[r][r] = dg;
     }
+}
+
+// Mass-inverse right-hand side S + sum_a kappa_a c_a.
+template <typename Real>
+__device__ __forceinline__ void massinv_rhs(const Real k[3], const Real sc[8], const Real vx[4],
+                                            const Real vy[4], const Real vz[4], Real b[8])
+{
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         const int ix = n & 1, iy = (n >> 1) & 1, iz = (n >> 2) & 1;
@@ -139,45 +145,34 @@ __device__ __forceinline__ void massinv_system(const Real k[3], Real st, const R
     }
 }
 
-// Canonical cell solve of one lane: builds the system in the chosen form from
-// the direction entry, sigma_t, the canonical source and the three inflow
-// faces, and returns psi (canonical node order) in b.
-template <typename Real, int Form>
-__device__ __forceinline__ void cell_solve(const Real *__restrict__ dp, const Real k[3], Real st,
-                                           const Real sc[8], const Real vx[4], const Real vy[4],
-                                           const Real vz[4], Real b[8])
+// Paper-form cell solve of one lane: A' = S_d + sigma_t M3 and
+// b' = M3 S + sum_a kappa_a Mf psi_a from the direction entry, sigma_t, the
+// canonical source and the three inflow faces, dense pivoted elimination;
+// returns psi (canonical node order) in b.
+template <typename Real>
+__device__ __forceinline__ void dense_cell_solve(const Real *__restrict__ dp, const Real k[3],
+                                                 Real st, const Real sc[8], const Real vx[4],
+                                                 const Real vy[4], const Real vz[4], Real b[8])
 {
     Real a[8][8];
-    if (Form == kFormDense) {
-        // paper form: A' = S_d + sigma_t M3, b' = M3 S + sum_a kappa_a Mf psi_a
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
+    for (int r = 0; r < 8; ++r)
 #pragma unroll
-            for (int c = 0; c < 8; ++c) a[r][c] = fma(st, Real(m3_entry(r, c)), dp[r * 8 + c]);
-        Real m[8], f[4];
-        mass3_216(sc, m);
+        for (int c = 0; c < 8; ++c) a[r][c] = fma(st, Real(m3_entry(r, c)), dp[r * 8 + c]);
+    Real m[8], f[4];
+    mass3_216(sc, m);
 #pragma unroll
-        for (int n = 0; n < 8; ++n) b[n] = m[n] * Real(1.0 / 216.0);
-        face_mass(vx, k[0] * Real(1.0 / 36.0), f);
+    for (int n = 0; n < 8; ++n) b[n] = m[n] * Real(1.0 / 216.0);
+    face_mass(vx, k[0] * Real(1.0 / 36.0), f);
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn) b[2 * fn] += f[fn];
-        face_mass(vy, k[1] * Real(1.0 / 36.0), f);
+    for (int fn = 0; fn < 4; ++fn) b[2 * fn] += f[fn];
+    face_mass(vy, k[1] * Real(1.0 / 36.0), f);
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn) b[(fn & 1) + 4 * (fn >> 1)] += f[fn];
-        face_mass(vz, k[2] * Real(1.0 / 36.0), f);
+    for (int fn = 0; fn < 4; ++fn) b[(fn & 1) + 4 * (fn >> 1)] += f[fn];
+    face_mass(vz, k[2] * Real(1.0 / 36.0), f);
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn) b[fn] += f[fn];
-        ge_solve8(a, b);
-    } else {
-        // mass-inverse form: (P_d + sigma_t I) psi = S + sum_a kappa_a c_a
-        massinv_system(k, st, sc, vx, vy, vz, a, b);
-        if (__any(ge_solve8_cube(a, b))) {
-            // some lane of the wave needs a row exchange: redo the wave with
-            // the dense elimination and its partial pivoting
-            massinv_system(k, st, sc, vx, vy, vz, a, b);
-            ge_solve8(a, b);
-        }
-    }
+    for (int fn = 0; fn < 4; ++fn) b[fn] += f[fn];
+    ge_solve8(a, b);
 }
 
 // Tile sweep.  Each lane owns one (octant, B x B x B tile of cells,
@@ -274,7 +269,8 @@ struct AnnLds {
 // o: octant slot; inc: the boundary inflow of octant slot o per canonical
 // axis; lane_ok: the lane carries work.  Form: kFormMassInv,
 // kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
-// blocks of full waves).  kCoh: device-coherent front access (dataflow
+// blocks of full waves) or kFormAnnPaper (the paper-form per-octant
+// network, FP32).  kCoh: device-coherent front access (dataflow
 // kernel).  Must be reached by every lane of the wave; lanes of one
 // (group, tile) segment are in one wave (seg_lane), and the body synchronises
 // only within the wave.
@@ -283,7 +279,8 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                                           int g, int tid, bool tvalid, uint32_t pt, int o,
                                           bool lane_ok, TileLds<Real> &L, AnnLds *al)
 {
-    static_assert(Form != kFormAnn || sizeof(Real) == 4, "the ANN solver runs in FP32");
+    static_assert((Form != kFormAnn && Form != kFormAnnPaper) || sizeof(Real) == 4,
+                  "the ANN solvers run in FP32");
     const int mask = kAdjoint ? (o ^ 7) : o;
     const uint32_t dg = d + A.Do * g;
     const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
@@ -372,9 +369,39 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                              al->lout + (tid >> 6) * (64 * 8), y);
 #pragma unroll
                     for (int n = 0; n < 8; ++n) psi[n] = ok ? m * y[n] : 0.0f;
+                } else if constexpr (Form == kFormAnnPaper) {
+                    if (ok) {
+                        pann_cell(static_cast<const float *>(A.ann_params) + o * kPannStride, kap,
+                                  st, sc, vx, vy, vz, psi);
+                    } else {
+#pragma unroll
+                        for (int n = 0; n < 8; ++n) psi[n] = 0;
+                    }
+                } else if constexpr (Form == kFormMassInv) {
+                    // (P_d + sigma_t I) psi = S + sum_a kappa_a c_a.  The
+                    // factorisation is redone per cell: keeping it for the
+                    // next cells of the tile (same sigma_t) saves half the
+                    // arithmetic but holds 50 more registers per lane, which
+                    // costs a wave per SIMD and more time than it saves.
+                    if (ok) {
+                        Real a[8][8];
+                        massinv_matrix(kap, st, a);
+                        massinv_rhs(kap, sc, vx, vy, vz, psi);
+                        if (__any(ge_solve8_cube(a, psi))) {
+                            // some lane of the wave needs a row exchange: the
+                            // wave redoes the cell with the dense pivoted
+                            // elimination
+                            massinv_matrix(kap, st, a);
+                            massinv_rhs(kap, sc, vx, vy, vz, psi);
+                            ge_solve8(a, psi);
+                        }
+                    } else {
+#pragma unroll
+                        for (int n = 0; n < 8; ++n) psi[n] = 0;
+                    }
                 } else {
                     if (ok) {
-                        cell_solve<Real, Form>(dp, kap, st, sc, vx, vy, vz, psi);
+                        dense_cell_solve(dp, kap, st, sc, vx, vy, vz, psi);
                     } else {
 #pragma unroll
                         for (int n = 0; n < 8; ++n) psi[n] = 0;

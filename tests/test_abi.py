@@ -187,3 +187,59 @@ def test_ann_load_checks_file_before_device(lib, tmp_path):
     assert lib.dgsn_ann_load(None, str(wide).encode(), ctypes.byref(out)) == _lib.DGSN_EUNSUPPORTED
     missing = tmp_path / "nope.dgsnann"
     assert lib.dgsn_ann_load(None, str(missing).encode(), ctypes.byref(out)) == _lib.DGSN_EINVAL
+
+
+def _paper_artifact(tmp_path, name="paper.dgsnann", nh=8, **kw):
+    rng = np.random.default_rng(5)
+    imin, imax = np.zeros(26), np.ones(26)
+    imin[12:14] = -1.0
+    p = tmp_path / name
+    ann_format.write_paper(p, rng.normal(size=(8, nh, 26)), rng.normal(size=(8, nh)),
+                           rng.normal(size=(8, 8, nh)), rng.normal(size=(8, 8)),
+                           kw.pop("imin", imin), kw.pop("imax", imax), **kw)
+    return p
+
+
+def test_paper_artifact_roundtrip(tmp_path):
+    p = _paper_artifact(tmp_path)
+    net = ann_format.read(p)
+    assert net["version"] == 2 and net["W1"].shape == (8, 8, 26) and net["W2"].shape == (8, 8, 8)
+    assert abs(net["alpha"] - 0.27) < 1e-7 and abs(net["beta_scale"] - 0.1) < 1e-7
+    raw = open(p, "rb").read()
+    assert struct.unpack("<7I", raw[8:36]) == (2, 26, 8, 8, 1, 1, 8)
+
+
+def test_paper_ann_load_checks_file_before_device(lib, tmp_path):
+    out = ctypes.c_void_p()
+    good = _paper_artifact(tmp_path)
+    assert lib.dgsn_ann_load(None, str(good).encode(), ctypes.byref(out)) == _lib.DGSN_EINVAL
+    assert b"ctx" in lib.dgsn_last_error()
+    wide = _paper_artifact(tmp_path, "wide.dgsnann", nh=9)
+    assert lib.dgsn_ann_load(None, str(wide).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    relu = _paper_artifact(tmp_path, "relu.dgsnann", activation=0)
+    assert lib.dgsn_ann_load(None, str(relu).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    noelu = _paper_artifact(tmp_path, "noelu.dgsnann", flags=0)
+    assert lib.dgsn_ann_load(None, str(noelu).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    flat = _paper_artifact(tmp_path, "flat.dgsnann", imin=np.ones(26), imax=np.ones(26))
+    assert lib.dgsn_ann_load(None, str(flat).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    assert b"bounds" in lib.dgsn_last_error()
+    raw = open(good, "rb").read()
+    short = tmp_path / "short.dgsnann"
+    short.write_bytes(raw[:60])
+    assert lib.dgsn_ann_load(None, str(short).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    assert lib.dgsn_ann_infer_octant(None, 0, None, None, 1, None) == _lib.DGSN_EINVAL
+    v = ctypes.c_int()
+    assert lib.dgsn_ann_info(None, ctypes.byref(v), None, None, None) == _lib.DGSN_EINVAL
+
+
+def test_trained_paper_artifact_shape():
+    # the shipped paper-form artifact: 8 octant networks of 26-8-8 with at most
+    # the paper's 272 connections each (Sec. 3; fewer after pruning)
+    from oracle import ann_paper_train
+    path = os.path.join(ROOT, "paper_1906_04017_amd", "data", "ann_paper_tanh8.dgsnann")
+    net = ann_paper_train.read_artifact(path)
+    assert net["W1"].shape == (8, 8, 26) and net["W2"].shape == (8, 8, 8)
+    for o in range(8):
+        conn = int(np.count_nonzero(net["W1"][o]) + np.count_nonzero(net["W2"][o]))
+        assert 0 < conn <= 26 * 8 + 8 * 8
+    assert abs(net["alpha"] - 0.27) < 1e-6 and abs(net["beta_scale"] - 0.1) < 1e-6

@@ -343,6 +343,127 @@ def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path, tile):
 
 
 # ---------------------------------------------------------------------------
+# paper-form per-octant network (26 inputs, tanh, ELU; vector ALUs)
+# ---------------------------------------------------------------------------
+
+def _random_pann(seed, nh=8):
+    rng = np.random.default_rng(seed)
+    imin, imax = np.zeros(26), np.ones(26)
+    imin[12:14] = -1.0
+    imax[22] = 10.0
+    imin[23:26] = 0.1
+    return dict(W1=(rng.normal(size=(8, nh, 26)) / 5), b1=(rng.normal(size=(8, nh)) / 5),
+                W2=(rng.normal(size=(8, 8, nh)) / 8), b2=(np.abs(rng.normal(size=(8, 8))) / 5),
+                imin=imin, imax=imax)
+
+
+def _write_pann(tmp_path, net, name):
+    """Writes the artifact and returns (path, the stored network as the oracle
+    reads it: float32 parameters)."""
+    from paper_1906_04017_amd import ann_format
+    path = tmp_path / name
+    ann_format.write_paper(path, net["W1"], net["b1"], net["W2"], net["b2"], net["imin"],
+                           net["imax"])
+    return path, ann_format.read(path)
+
+
+def _pann_bound(net, o, I):
+    """Bound on |FP32 device - FP64| for one sample of octant o's network: the
+    scaling is folded into the first layer (one rounding per weight), the
+    sums are FP32 (at most 30 roundings of the largest partial sum), tanh and
+    exp come from the hardware exp2 and reciprocal (a few 1e-8 absolute)."""
+    u = 2.0 ** -24
+    W1, b1 = net["W1"][o].astype(np.float64), net["b1"][o].astype(np.float64)
+    W2, b2 = net["W2"][o].astype(np.float64), net["b2"][o].astype(np.float64)
+    c = net["alpha"] * 0.5 * (net["imin"] + net["imax"])
+    r = np.abs(net["imax"] - net["imin"])
+    Wf = W1 / r[None, :]
+    bf = b1 - Wf @ c
+    dz = 30 * u * (np.abs(Wf) @ np.abs(I) + np.abs(bf) + np.abs(Wf) @ np.abs(c))
+    h = np.tanh(Wf @ I + bf)
+    dh = dz + 2e-7
+    do = np.abs(W2) @ dh + 12 * u * (np.abs(W2) @ np.abs(h) + np.abs(b2))
+    beta = net["beta_scale"] * I[:12].max()
+    return max(1.0, beta) * do + 4e-7 * beta
+
+
+@pytest.mark.parametrize("nh", [8, 5])
+def test_pann_infer_octant_within_fp32_bound(api, ctx, tmp_path, nh):
+    print_case("pann_infer", nh=nh)
+    path, net = _write_pann(tmp_path, _random_pann(400 + nh, nh), f"p{nh}.dgsnann")
+    ann = api.Ann(ctx, path)
+    assert ann.info() == (2, 26, nh, 8)
+    rng = np.random.default_rng(9)
+    n = 700 + 13
+    x = rng.uniform(-0.2, 1.2, size=(n, 26))
+    x[:, 22] *= 10.0
+    x = x.astype(np.float32)
+    xd = x.astype(np.float64)
+    for o in range(8):
+        y = ann.infer_octant(o, torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+        for i in range(0, n, 7):
+            ref = oracle.pann_forward(net, o, xd[i])
+            assert np.all(np.abs(y[i] - ref) <= 2 * _pann_bound(net, o, xd[i]) + 1e-7), (o, i)
+    with pytest.raises(Exception):
+        ann.infer(torch.zeros((4, 24), device="cuda"))
+
+
+PANN_CASES = [((5, 4, 6), (0.5, 0.4, 0.6), 4, 2), ((7, 5, 6), (0.7, 0.5, 0.6), 6, 1),
+              ((3, 8, 2), (0.3, 0.8, 0.2), 8, 3)]
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("case", PANN_CASES, ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in PANN_CASES])
+def test_pann_sweep_matches_oracle(api, ctx, tmp_path, case, tile):
+    n, L, order, G = case
+    print_case("pann_sweep", n=n, order=order, G=G, tile=tile)
+    path, net = _write_pann(tmp_path, _random_pann(500), "ps.dgsnann")
+    ann = api.Ann(ctx, path)
+    p = inputs.random_problem(n, order, G, seed=61 + tile, length=L)
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    prob.set_tile(tile)
+    S = torch.tensor(nodal_source(p, seed=17), dtype=torch.float32, device="cuda")
+    phi = prob.sweep(S).clone()
+    om, w = oracle.lq_n(order)
+    ref = oracle.pann_sweep(net, mesh_of(p), om, w, p["sigma_t"], S.cpu().numpy(), p["psi_inc"])
+    assert rel(phi.cpu().numpy(), ref) <= 2e-5
+    # the dataflow schedule runs the same arithmetic
+    prob.set_schedule("dataflow")
+    for _ in range(2):
+        got = prob.sweep(S)
+        prob.check()
+        assert torch.equal(got, phi)
+
+
+def test_pann_source_iteration_matches_oracle(api, ctx, tmp_path):
+    path, net = _write_pann(tmp_path, _random_pann(501), "psi.dgsnann")
+    ann = api.Ann(ctx, path)
+    p = inputs.random_problem((6, 5, 4), 4, 2, seed=71, c_max=0.5, length=(0.6, 0.5, 0.4))
+    print_case("pann_si", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    phi, info = prob.source_iterate(tol=1e-6, max_iter=200)
+    om, w = oracle.lq_n(4)
+    ref = oracle.pann_source_iterate(net, mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                     p["psi_inc"], tol=1e-10, max_iter=500)
+    assert rel(phi.cpu().numpy(), ref["phi"]) <= 5e-5
+
+
+def test_pann_rejects_fp64_and_adjoint(api, ctx, tmp_path):
+    path, _ = _write_pann(tmp_path, _random_pann(502), "pe.dgsnann")
+    ann = api.Ann(ctx, path)
+    p = inputs.random_problem((3, 3, 3), 2, 1, seed=72)
+    prob64 = gpu_problem(api, ctx, p, "fp64")
+    with pytest.raises(Exception):
+        prob64.set_ann(ann)
+    probs = gpu_problem(api, ctx, p, "fp32", solver="ann", store_psi=True)
+    probs.set_ann(ann)
+    with pytest.raises(Exception):
+        probs.sweep(torch.zeros((1, 27, 8), device="cuda"))
+
+
+# ---------------------------------------------------------------------------
 # dataflow schedule (one launch per sweep, device counters between steps)
 # ---------------------------------------------------------------------------
 
@@ -438,7 +559,7 @@ def test_problem_autotune_keeps_results(api, ctx):
 
 BATCH = [((5, 4, 3), 4, 2, "ge"), ((9, 9, 9), 8, 3, "ge"), ((3, 7, 2), 12, 1, "ge"),
          ((6, 5, 4), 6, 2, "ann"), ((1, 1, 1), 2, 1, "ge"), ((8, 6, 7), 4, 4, "ann"),
-         ((12, 10, 11), 8, 2, "ge")]
+         ((12, 10, 11), 8, 2, "ge"), ((7, 6, 5), 6, 3, "pann"), ((9, 4, 6), 4, 2, "pann")]
 
 
 @pytest.mark.parametrize("schedule", ["planes", "dataflow"])
@@ -447,13 +568,16 @@ def test_batch_matches_single_problem_sweeps(api, ctx, tmp_path, tiles, schedule
     print_case("batch", tiles=tiles, schedule=schedule, problems=len(BATCH))
     net = _random_net(77)
     ann = api.Ann(ctx, _write_net(tmp_path, net, "batch.dgsnann"))
+    pann = api.Ann(ctx, _write_pann(tmp_path, _random_pann(78), "batch_p.dgsnann")[0])
     probs, srcs, phis, ps = [], [], [], []
     for k, (n, order, G, solver) in enumerate(BATCH):
         p = inputs.random_problem(n, order, G, seed=600 + k,
                                   length=tuple(0.1 * v + 0.3 for v in n))
-        prob = gpu_problem(api, ctx, p, "fp32", solver=solver)
+        prob = gpu_problem(api, ctx, p, "fp32", solver="ge" if solver == "ge" else "ann")
         if solver == "ann":
             prob.set_ann(ann)
+        if solver == "pann":
+            prob.set_ann(pann)
         S = torch.tensor(nodal_source(p, seed=700 + k), dtype=torch.float32, device="cuda")
         probs.append(prob)
         srcs.append(S)

@@ -477,3 +477,146 @@ def test_eps_p_definition_on_hand_example():
     ann[0, 1] = 5.0
     # cell 0 exact, cell 1 off by |4-5|/(4+1e-8)
     assert abs(oracle.eps_p(ref, ann)[0] - 0.5 * 1.0 / (4.0 + 1e-8)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# paper-form per-octant network (Sec. 3, Eq. (ANN:Eq1)-(ANN:Eq4))
+# ---------------------------------------------------------------------------
+
+PANN_EPS = 1e-4   # tanh(eps x) / eps = x (1 - (eps x)^2 / 3 + ...): a near-identity hidden unit
+
+
+def _pann_selector(select, imin=None, imax=None, alpha=0.27):
+    """Paper-form net (all 8 octants alike) whose output t is In[select[t]] + 2,
+    up to 4e-9 for |In| <= 1.2: hidden unit t = tanh(eps In_j), output =
+    h / eps + 2 (> 0, so the ELU is the identity)."""
+    nh = 8
+    W1 = np.zeros((8, nh, 26))
+    W2 = np.zeros((8, 8, nh))
+    for t, j in enumerate(select):
+        W1[:, t, j] = PANN_EPS
+        W2[:, t, t] = 1.0 / PANN_EPS
+    return dict(kind="paper", W1=W1, b1=np.zeros((8, nh)), W2=W2, b2=np.full((8, 8), 2.0),
+                imin=np.zeros(26) if imin is None else imin,
+                imax=np.ones(26) if imax is None else imax, alpha=alpha, beta_scale=0.1)
+
+
+def _cell_problem(rng, o, h=(0.3, 0.5, 0.7)):
+    sg = np.array([-1.0 if (o >> a) & 1 else 1.0 for a in range(3)])
+    om = np.abs(rng.normal(size=3)) * sg
+    om /= np.linalg.norm(om)
+    return np.array(h), om, rng.uniform(0.5, 5.0), rng.uniform(0, 1, 8), rng.uniform(0, 1, (6, 8))
+
+
+def test_pann_scaling_is_eq_ann2_at_the_bounds():
+    # In_j = (I_j - alpha (Imin_j + Imax_j) / 2) / |Imax_j - Imin_j|: at I = Imin
+    # and I = Imax with bounds [2, 6] and alpha = 0.27 this is (2 - 1.08) / 4 =
+    # 0.23 and (6 - 1.08) / 4 = 1.23
+    imin, imax = np.full(26, 2.0), np.full(26, 6.0)
+    net = _pann_selector(range(8), imin=imin, imax=imax)
+    for I0, want in ((2.0, 0.23), (6.0, 1.23)):
+        I = np.full(26, I0)
+        psi = oracle.pann_forward(net, 0, I)
+        assert np.abs(psi - (want + 2.0)).max() < 1e-8
+
+
+def test_pann_elu_output_branch():
+    # one hidden unit fixed at tanh(b1) through a zero first layer; output
+    # z = w2 tanh(b1) + b2 < 0 goes through beta (exp(z) - 1) with
+    # beta = 0.1 max(psi_inc), and with all inflows 0 the negative part is 0
+    nh = 8
+    W1 = np.zeros((8, nh, 26))
+    b1 = np.zeros((8, nh))
+    b1[:, 0] = np.arctanh(0.5)               # h_0 = 0.5 exactly (up to rounding)
+    W2 = np.zeros((8, 8, nh))
+    W2[:, :, 0] = -2.0                       # z_t = -1 + b2_t
+    b2 = np.tile(np.array([0.0, -1.0, 0.5, 1.0, 1.5, 2.0, 3.0, -3.0]), (8, 1))
+    net = dict(kind="paper", W1=W1, b1=b1, W2=W2, b2=b2, imin=np.zeros(26), imax=np.ones(26),
+               alpha=0.27, beta_scale=0.1)
+    I = np.zeros(26)
+    I[:12] = np.linspace(0.1, 0.4, 12)       # max inflow 0.4 -> beta = 0.04
+    z = -1.0 + b2[0]
+    want = np.where(z >= 0, z, 0.04 * (np.exp(z) - 1.0))
+    for o in range(8):
+        assert np.abs(oracle.pann_forward(net, o, I) - want).max() < 1e-14
+    I[:12] = 0.0
+    got = oracle.pann_forward(net, 3, I)
+    assert np.all(got[z < 0] == 0.0)
+    assert np.abs(got[z >= 0] - z[z >= 0]).max() < 1e-14
+
+
+def test_pann_inputs_follow_the_cell_geometry():
+    # selector nets read back each input of the physical-frame layout: the
+    # inflow trace at the face nodes (face node = lower tangential bit + 2 *
+    # higher), omega_x, omega_y, the nodal sources, sigma_t and the cell sizes
+    rng = np.random.default_rng(51)
+    for o in range(8):
+        h, om, sig, S, up = _cell_problem(rng, o)
+        for a in range(3):
+            side = 1 if om[a] < 0 else 0
+            t1, t2 = [b for b in range(3) if b != a]
+            net = _pann_selector([4 * a + fn for fn in range(4)] + [12, 13, 22, 23])
+            psi = oracle.pann_cell_batch(net, h, om[None], [sig], S[None], up[None])[0] - 2.0
+            for fn in range(4):
+                node = (side << a) | ((fn & 1) << t1) | ((fn >> 1) << t2)
+                assert abs(psi[fn] - (up[2 * a + side][node] - 0.135)) < 1e-8
+            # omega bounds [0, 1] here: In = omega - 0.135; sigma_t and dx likewise
+            assert abs(psi[4] - (om[0] - 0.135)) < 1e-8
+            assert abs(psi[5] - (om[1] - 0.135)) < 1e-8
+            assert abs(psi[6] - (sig - 0.135)) < 1e-6
+            assert abs(psi[7] - (h[0] - 0.135)) < 1e-8
+        net = _pann_selector([14 + n for n in range(8)])
+        psi = oracle.pann_cell_batch(net, h, om[None], [sig], S[None], up[None])[0] - 2.0
+        assert np.abs(psi - (S - 0.135)).max() < 1e-8
+
+
+def test_pann_octant_mirror_equivariance():
+    # Mirroring a problem in x maps octant o to o ^ 1, node n to n ^ 1, the x
+    # inflow face to the opposite face with the same face-node order, the y
+    # and z face nodes fn to fn ^ 1 (their lower tangential axis is x) and
+    # omega_x to -omega_x.  A net for octant o ^ 1 built from octant o's by
+    # that relabelling must give the mirrored sweep.
+    rng = np.random.default_rng(52)
+    nh = 8
+    base = dict(W1=rng.normal(size=(8, nh, 26)) / 5, b1=rng.normal(size=(8, nh)) / 5,
+                W2=rng.normal(size=(8, 8, nh)) / 8, b2=np.abs(rng.normal(size=(8, 8))) / 5)
+    imin, imax = np.zeros(26), np.ones(26)
+    imin[12:14] = -1.0
+    perm_in = list(range(4)) + [4 + (fn ^ 1) for fn in range(4)] + [8 + (fn ^ 1) for fn in range(4)]
+    perm_in += [12, 13] + [14 + (n ^ 1) for n in range(8)] + [22, 23, 24, 25]
+    W1 = base["W1"].copy()
+    b1 = base["b1"].copy()
+    W2 = base["W2"].copy()
+    b2 = base["b2"].copy()
+    for o in range(8):
+        if o & 1:
+            continue
+        m = o | 1
+        W1[m] = base["W1"][o][:, perm_in]
+        W1[m][:, 12] = -base["W1"][o][:, 12]      # omega_x changes sign; bounds are symmetric
+        b1[m] = base["b1"][o]
+        W2[m] = base["W2"][o][[n ^ 1 for n in range(8)]]
+        b2[m] = base["b2"][o][[n ^ 1 for n in range(8)]]
+    net = dict(kind="paper", W1=W1, b1=b1, W2=W2, b2=b2, imin=imin, imax=imax, alpha=0.27,
+               beta_scale=0.1)
+    n = (4, 3, 3)
+    mesh = (*n, 0.8, 0.6, 0.9)
+    ncell = n[0] * n[1] * n[2]
+    om, w = oracle.lq_n(4)
+    sig = rng.uniform(0.5, 3.0, size=(1, ncell))
+    src = rng.uniform(0.0, 1.0, size=(1, ncell, 8))
+    inc = np.array([0.7, 0.2, 0.5, 0.1, 0.3, 0.9])
+    phi = oracle.pann_sweep(net, mesh, om, w, sig, src, inc)
+    # mirrored problem
+    c = np.arange(ncell)
+    i, j, k = c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1])
+    cm = (n[0] - 1 - i) + n[0] * (j + n[1] * k)
+    sig_m = np.empty_like(sig)
+    sig_m[:, cm] = sig
+    src_m = np.empty_like(src)
+    src_m[:, cm] = src[:, :, [nn ^ 1 for nn in range(8)]]
+    inc_m = inc[[1, 0, 2, 3, 4, 5]]
+    om_m = om * np.array([-1.0, 1.0, 1.0])
+    phi_m = oracle.pann_sweep(net, mesh, om_m, w, sig_m, src_m, inc_m)
+    back = phi_m[:, cm][:, :, [nn ^ 1 for nn in range(8)]]
+    assert np.abs(back - phi).max() < 1e-12 * np.abs(phi).max()
