@@ -32,6 +32,16 @@
  * The adjoint (discrete transpose of the source-iteration system) is not in the
  * paper; it is the exact transpose of the operator above, written out with
  * explicit transposed matrices and a reversed (downwind-to-upwind) sweep.
+ *
+ * Two shallow networks replace assembly + GE when asked (Sec. 3, Sec. 4):
+ *   - a canonical-octant network on 24 homogeneity-normalised features (the
+ *     library's matrix-core network), and
+ *   - the paper's own form, Eq. (ANN:Eq1)-(ANN:Eq4): 26 physical-frame inputs
+ *     scaled by Eq. (ANN:Eq2), tanh hidden layer, ELU output with
+ *     beta = 0.1 max(psi_inc), one network per octant (orc_pann_*).
+ * Both forward passes are written out literally in FP64; they are pinned by
+ * hand-built networks with closed-form outputs, selector networks that read
+ * the inputs back, homogeneity and mirror equivariance (tests).
  */
 #include <math.h>
 #include <stdlib.h>
