@@ -128,6 +128,21 @@ int dgsn_problem_destroy(dgsn_problem *p);
 int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void *sigma_s,
                                const void *q, void *stream);
 
+/*
+ * Multigroup isotropic scattering (the group sum of the scattering source,
+ * Eq. (T3)-(T8), at order P0): sigma_gg is a device array [G][G][Nz*Ny*Nx]
+ * in the problem precision, sigma_gg[g'][g][c] the cross section for
+ * scattering from group g' into group g in cell c.  Source iteration then
+ * uses S_g = q_g + (1/4pi) sum_{g'} sigma_gg[g'][g] phi_g' (all groups at
+ * once, Jacobi in the group index), and the adjoint the transposed coupling;
+ * the in-group sigma_s of dgsn_problem_set_materials is not used while a
+ * matrix is set.  The array is copied (asynchronously on the stream); the
+ * caller keeps ownership of its pointer.  NULL removes the matrix.  Single
+ * sweeps (dgsn_sweep, batches) take the caller's source and are unaffected.
+ * DGSN_ENOMEM if the copy cannot be allocated.
+ */
+int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *stream);
+
 /* Boundary inflow psi_inc per domain face (host [6]); applied to every
    direction entering through that face (Eq. (TBC)); 0 = vacuum. */
 int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);

@@ -53,6 +53,10 @@ def _load():
                                           ctypes.c_int]
     lib.orc_adjoint.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [ctypes.c_int] * 2 + \
         [_D] * 7 + [ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _I, ctypes.c_int]
+    lib.orc_source_iterate_gg.argtypes = lib.orc_source_iterate.argtypes
+    lib.orc_adjoint_gg.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 7 + [ctypes.c_double, ctypes.c_int, _D, _D, _D, _I,
+                                         ctypes.c_int]
     lib.orc_cell_balance.argtypes = [_D, _D, ctypes.c_double, _D, _D, _D]
     lib.orc_cell_balance.restype = ctypes.c_double
     lib.orc_cell_solve_batch.argtypes = [ctypes.c_long, _D, _D, _D, _D, _D, _D, ctypes.c_int]
@@ -191,8 +195,10 @@ def sweep(mesh, omega, weight, sigma_t, src, psi_inc=None, store_psi=False, nthr
 
 
 def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-8,
-                   max_iter=1000, phi0=None, store_psi=False, nthreads=0):
+                   max_iter=1000, phi0=None, store_psi=False, nthreads=0, sigma_gg=None):
     """Scattering source iteration to max-norm relative change < tol.
+    sigma_gg [G, G, ncell] (from g' into g at [g', g]) replaces the in-group
+    sigma_s with multigroup scattering when given.
     Returns dict(phi, iters, resid, eps_s, converged[, psi])."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
@@ -209,10 +215,19 @@ def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1
     it = ctypes.c_int(0)
     resid = ctypes.c_double(0)
     eps = ctypes.c_double(0)
-    rc = lib.orc_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
-                                _p(sigma_t), _p(sigma_s), _p(q), _p(inc), _p(phi), float(tol),
-                                int(max_iter), ctypes.byref(it), ctypes.byref(resid),
-                                ctypes.byref(eps), _p(psi), int(nthreads))
+    if sigma_gg is None:
+        rc = lib.orc_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                    _p(_f64(weight, (nd,))), _p(sigma_t), _p(sigma_s), _p(q),
+                                    _p(inc), _p(phi), float(tol), int(max_iter),
+                                    ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps),
+                                    _p(psi), int(nthreads))
+    else:
+        rc = lib.orc_source_iterate_gg(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                       _p(_f64(weight, (nd,))), _p(sigma_t),
+                                       _p(_f64(sigma_gg, (ng, ng, ncell))), _p(q), _p(inc),
+                                       _p(phi), float(tol), int(max_iter), ctypes.byref(it),
+                                       ctypes.byref(resid), ctypes.byref(eps), _p(psi),
+                                       int(nthreads))
     _check(rc, "source_iterate")
     out = dict(phi=phi, iters=it.value, resid=resid.value, eps_s=eps.value, converged=(rc == 0))
     if store_psi:
@@ -221,12 +236,13 @@ def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1
 
 
 def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, max_iter=2000,
-            nthreads=0):
+            nthreads=0, sigma_gg=None):
     """Exact discrete adjoint of the converged source iteration.
     gphi = dJ/dphi [G, ncell, 8].  Returns dict(grad_sigma_t, grad_q,
     grad_sigma_s [G, ncell], phi_dag [G, ncell, 8], iters); direct partial
-    derivatives of J are not included.  Pinned by duality, the dense transpose
-    and central finite differences."""
+    derivatives of J are not included.  With sigma_gg (multigroup scattering,
+    the transposed coupling in the adjoint) grad_sigma_s is not computed.
+    Pinned by duality, the dense transpose and central finite differences."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
     ncell = nx * ny * nz
@@ -239,11 +255,20 @@ def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, ma
     gss = np.zeros((ng, ncell))
     pd = np.zeros((ng, ncell, 8))
     it = ctypes.c_int(0)
-    rc = lib.orc_adjoint(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
-                         _p(sigma_t), _p(_f64(sigma_s, (ng, ncell))),
-                         _p(_f64(psi, (nd, ng, ncell, 8))), _p(_f64(phi, (ng, ncell, 8))),
-                         _p(_f64(gphi, (ng, ncell, 8))), float(tol), int(max_iter), _p(gst),
-                         _p(gq), _p(gss), _p(pd), ctypes.byref(it), int(nthreads))
+    if sigma_gg is None:
+        rc = lib.orc_adjoint(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                             _p(sigma_t), _p(_f64(sigma_s, (ng, ncell))),
+                             _p(_f64(psi, (nd, ng, ncell, 8))), _p(_f64(phi, (ng, ncell, 8))),
+                             _p(_f64(gphi, (ng, ncell, 8))), float(tol), int(max_iter), _p(gst),
+                             _p(gq), _p(gss), _p(pd), ctypes.byref(it), int(nthreads))
+    else:
+        gss = None
+        rc = lib.orc_adjoint_gg(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                _p(_f64(weight, (nd,))), _p(sigma_t),
+                                _p(_f64(sigma_gg, (ng, ng, ncell))),
+                                _p(_f64(psi, (nd, ng, ncell, 8))), _p(_f64(phi, (ng, ncell, 8))),
+                                _p(_f64(gphi, (ng, ncell, 8))), float(tol), int(max_iter),
+                                _p(gst), _p(gq), _p(pd), ctypes.byref(it), int(nthreads))
     _check(rc, "adjoint")
     return dict(grad_sigma_t=gst, grad_q=gq, grad_sigma_s=gss, phi_dag=pd, iters=it.value,
                 converged=(rc == 0))

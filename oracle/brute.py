@@ -42,11 +42,13 @@ def _cell_id(c, n):
     return c[0] + n[0] * (c[1] + n[1] * c[2])
 
 
-def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None):
+def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None):
     """Dense (L - K) and right-hand side Q for unknowns psi[d][g][c][8].
 
     sigma_t, sigma_s, q: [G, ncell]; psi_inc [6]; extra_src [G, ncell, 8]
-    optional nodal source (per steradian) added to q.  Returns (A, Q)."""
+    optional nodal source (per steradian) added to q; sigma_gg [G, G, ncell]
+    optional group-to-group scattering (from g' to g at [g', g]), which then
+    replaces the in-group sigma_s.  Returns (A, Q)."""
     nx, ny, nz, lx, ly, lz = mesh
     n = (nx, ny, nz)
     h = (lx / nx, ly / ny, lz / nz)
@@ -58,6 +60,8 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None):
     ng = sigma_t.shape[0]
     sigma_s = np.asarray(sigma_s, np.float64).reshape(ng, ncell)
     q = np.asarray(q, np.float64).reshape(ng, ncell)
+    if sigma_gg is not None:
+        sigma_gg = np.asarray(sigma_gg, np.float64).reshape(ng, ng, ncell)
     N = nd * ng * ncell * 8
     A = np.zeros((N, N))
     Q = np.zeros(N)
@@ -96,16 +100,22 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None):
                         else:
                             Q[r:r + 8] += (-on) * Mf[f] @ np.full(8, psi_inc[f])
                 A[r:r + 8, r:r + 8] += Ac
-                # isotropic scattering: - sigma_s/(4 pi) M sum_d' w_d' psi_d'
-                for d2 in range(nd):
-                    cb = blk(d2, g, ci)
-                    A[r:r + 8, cb:cb + 8] -= sigma_s[g, ci] / (4 * np.pi) * weight[d2] * M
+                # isotropic scattering: - sigma_s/(4 pi) M sum_d' w_d' psi_d' (from
+                # every group g2 with the matrix, from g itself without)
+                src_groups = [(g, sigma_s[g, ci])] if sigma_gg is None else \
+                    [(g2, sigma_gg[g2, g, ci]) for g2 in range(ng)]
+                for g2, sig in src_groups:
+                    if sig == 0.0:
+                        continue
+                    for d2 in range(nd):
+                        cb = blk(d2, g2, ci)
+                        A[r:r + 8, cb:cb + 8] -= sig / (4 * np.pi) * weight[d2] * M
     return A, Q
 
 
-def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None):
+def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None):
     """Returns (psi [D,G,ncell,8], phi [G,ncell,8]) of the dense global system."""
-    A, Q = assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src)
+    A, Q = assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src, sigma_gg)
     x = np.linalg.solve(A, Q)
     nx, ny, nz = mesh[:3]
     ncell = nx * ny * nz
@@ -116,13 +126,14 @@ def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None):
     return psi, phi
 
 
-def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi):
+def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi, sigma_gg=None):
     """Dense transpose solve (L - K)^T lambda = W^T g for a response with
     dJ/dphi = gphi [G, ncell, 8]; returns lambda [D, G, ncell, 8]."""
     nd = len(weight)
     ncell = mesh[0] * mesh[1] * mesh[2]
     ng = np.asarray(sigma_t).reshape(-1, ncell).shape[0]
-    A, _ = assemble(mesh, omega, weight, sigma_t, sigma_s, np.zeros((ng, ncell)), np.zeros(6))
+    A, _ = assemble(mesh, omega, weight, sigma_t, sigma_s, np.zeros((ng, ncell)), np.zeros(6),
+                    sigma_gg=sigma_gg)
     gphi = np.asarray(gphi, np.float64).reshape(ng, ncell, 8)
     r = np.concatenate([weight[d] * gphi.reshape(-1) for d in range(nd)])
     lam = np.linalg.solve(A.T, r)

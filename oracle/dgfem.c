@@ -410,6 +410,26 @@ static void build_source(long n, const double *q, const double *sigma_s, const d
 }
 
 /*
+ * Multigroup isotropic scattering (the group sum of Eq. (T3)-(T8) at P0):
+ *   S[g][c][k] = q[g][c] + sum_{g'} sigma_gg[g'][g][c] / (4 pi) phi[g'][c][k],
+ * sigma_gg[g'][g][c] being the scattering cross section from group g' into
+ * group g, summed over g' in ascending order.
+ */
+static void build_source_gg(int ng, long ncell, const double *q, const double *sigma_gg,
+                            const double *phi, double *S)
+{
+    for (int g = 0; g < ng; ++g)
+        for (long c = 0; c < ncell; ++c)
+            for (int k = 0; k < 8; ++k) {
+                double v = q[g * ncell + c];
+                for (int g2 = 0; g2 < ng; ++g2)
+                    v += sigma_gg[((long)g2 * ng + g) * ncell + c] / (4.0 * ORC_PI) *
+                         phi[((long)g2 * ncell + c) * 8 + k];
+                S[((long)g * ncell + c) * 8 + k] = v;
+            }
+}
+
+/*
  * Scattering source iteration.  phi [G][ncell][8] holds the initial guess on
  * entry and the last iterate on exit.  Iterate: S = q + sigma_s/(4 pi) phi^n,
  * sweep, phi^{n+1}.  Residual r = max|phi^{n+1} - phi^n| / max|phi^{n+1}| over
@@ -421,7 +441,7 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
                           const double *sigma_t, const double *sigma_s, const double *q,
                           const double psi_inc[6], double *phi, double tol, int max_iter,
                           int *iters, double *resid, double *eps_s, double *psi_store,
-                          const orc_ann *net, int nthreads)
+                          const orc_ann *net, int nthreads, const double *sigma_gg)
 {
     const long ncell = (long)nx * ny * nz;
     const long nv = (long)ng * ncell;
@@ -431,7 +451,8 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
     int it = 0, rc = ORC_OK;
     double r = INFINITY, es = INFINITY;
     while (it < max_iter) {
-        build_source(nv, q, sigma_s, phi, S);
+        if (sigma_gg) build_source_gg(ng, ncell, q, sigma_gg, phi, S);
+        else build_source(nv, q, sigma_s, phi, S);
         rc = sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, S, psi_inc, phin,
                        psi_store, net, nthreads);
         if (rc) break;
@@ -470,7 +491,22 @@ int orc_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, 
 {
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
-                          nthreads);
+                          nthreads, NULL);
+}
+
+/* Source iteration with multigroup scattering sigma_gg [G][G][ncell] (from g'
+   into g at [g'][g]); the in-group sigma_s is not used. */
+int orc_source_iterate_gg(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                          int nd, const double *omega, const double *weight,
+                          const double *sigma_t, const double *sigma_gg, const double *q,
+                          const double psi_inc[6], double *phi, double tol, int max_iter,
+                          int *iters, double *resid, double *eps_s, double *psi_store,
+                          int nthreads)
+{
+    if (!sigma_gg) return ORC_EINVAL;
+    return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, q,
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
+                          nthreads, sigma_gg);
 }
 
 /* ------------------------------------------------------------------ */
@@ -563,12 +599,39 @@ static int adjoint_sweep_one(const orc_mesh *m, const double omega[3], const dou
  * g = dJ/dphi [G][ncell][8]; psi [D][G][ncell][8] and phi [G][ncell][8] are the
  * converged forward solution.  Direct partial derivatives of J are not added.
  */
-int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
-                const double *omega, const double *weight, const double *sigma_t,
-                const double *sigma_s, const double *psi, const double *phi,
-                const double *gphi, double tol, int max_iter, double *grad_sigma_t,
-                double *grad_q, double *grad_sigma_s, double *phi_dag_out, int *iters,
-                int nthreads)
+/*
+ * Adjoint scattering load: load = g + (1/4 pi) sum_{g'} sigma(g -> g') M phi_dag[g']
+ * (the transpose of the forward group coupling; in-group only without a matrix).
+ */
+static void adjoint_load(int ng, long ncell, const double *sigma_s, const double *sigma_gg,
+                         const double M[64], const double *gphi, const double *phid,
+                         double *load)
+{
+    for (int g = 0; g < ng; ++g)
+        for (long c = 0; c < ncell; ++c) {
+            const long gc = (long)g * ncell + c;
+            for (int k = 0; k < 8; ++k) {
+                double acc = gphi[gc * 8 + k];
+                for (int g2 = 0; g2 < ng; ++g2) {
+                    const double sig = sigma_gg ? sigma_gg[((long)g * ng + g2) * ncell + c]
+                                                : (g2 == g ? sigma_s[gc] : 0.0);
+                    if (sig == 0.0) continue;
+                    const long g2c = (long)g2 * ncell + c;
+                    double v = 0.0;
+                    for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * phid[g2c * 8 + j];
+                    acc += sig / (4.0 * ORC_PI) * v;
+                }
+                load[gc * 8 + k] = acc;
+            }
+        }
+}
+
+static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                       const double *omega, const double *weight, const double *sigma_t,
+                       const double *sigma_s, const double *sigma_gg, const double *psi,
+                       const double *phi, const double *gphi, double tol, int max_iter,
+                       double *grad_sigma_t, double *grad_q, double *grad_sigma_s,
+                       double *phi_dag_out, int *iters, int nthreads)
 {
     orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
     const long ncell = (long)nx * ny * nz;
@@ -587,13 +650,8 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
     int it = 0, rc = ORC_OK;
     double r = INFINITY;
     while (it < max_iter) {
-        /* load = g + sigma_s/(4 pi) M phi_dag */
-        for (long gc = 0; gc < nv; ++gc)
-            for (int k = 0; k < 8; ++k) {
-                double v = 0.0;
-                for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * phid[gc * 8 + j];
-                load[gc * 8 + k] = gphi[gc * 8 + k] + sigma_s[gc] / (4.0 * ORC_PI) * v;
-            }
+        /* load = g + sigma_s^T/(4 pi) M phi_dag */
+        adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
 #pragma omp parallel for schedule(dynamic, 1)
         for (long u = 0; u < (long)nd * ng; ++u) {
             const int d = (int)(u / ng), g = (int)(u % ng);
@@ -621,12 +679,7 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
     if (!rc) {
         /* the mu of the last sweep are consistent with the phi_dag used to build
            its load; one more sweep with the converged phi_dag refines them */
-        for (long gc = 0; gc < nv; ++gc)
-            for (int k = 0; k < 8; ++k) {
-                double v = 0.0;
-                for (int j = 0; j < 8; ++j) v += M[k * 8 + j] * phid[gc * 8 + j];
-                load[gc * 8 + k] = gphi[gc * 8 + k] + sigma_s[gc] / (4.0 * ORC_PI) * v;
-            }
+        adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
 #pragma omp parallel for schedule(dynamic, 1)
         for (long u = 0; u < (long)nd * ng; ++u) {
             const int d = (int)(u / ng), g = (int)(u % ng);
@@ -662,6 +715,32 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
     if (iters) *iters = it;
     if (rc) return rc;
     return (r < tol) ? ORC_OK : ORC_ENOTCONV;
+}
+
+int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                const double *omega, const double *weight, const double *sigma_t,
+                const double *sigma_s, const double *psi, const double *phi,
+                const double *gphi, double tol, int max_iter, double *grad_sigma_t,
+                double *grad_q, double *grad_sigma_s, double *phi_dag_out, int *iters,
+                int nthreads)
+{
+    return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, NULL, psi,
+                       phi, gphi, tol, max_iter, grad_sigma_t, grad_q, grad_sigma_s, phi_dag_out,
+                       iters, nthreads);
+}
+
+/* Adjoint with multigroup scattering (the gradient with respect to the
+   in-group sigma_s is not defined there and is not returned). */
+int orc_adjoint_gg(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                   const double *omega, const double *weight, const double *sigma_t,
+                   const double *sigma_gg, const double *psi, const double *phi,
+                   const double *gphi, double tol, int max_iter, double *grad_sigma_t,
+                   double *grad_q, double *phi_dag_out, int *iters, int nthreads)
+{
+    if (!sigma_gg) return ORC_EINVAL;
+    return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, sigma_gg,
+                       psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
+                       iters, nthreads);
 }
 
 /* ------------------------------------------------------------------ */
@@ -943,7 +1022,8 @@ int orc_ann_source_iterate(int nx, int ny, int nz, double lx, double ly, double 
     orc_ann net = {24, nh, 8, act, W1, b1, W2, b2, NULL};
     if (nh < 1 || nh > 1024) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
-                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads);
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads,
+                          NULL);
 }
 
 /* Batched paper-form network one-cell solves (physical orientation). */
@@ -991,5 +1071,6 @@ int orc_pann_source_iterate(int nx, int ny, int nz, double lx, double ly, double
     orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
     if (nh < 1 || nh > 64) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
-                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads);
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads,
+                          NULL);
 }

@@ -70,6 +70,7 @@ SIGNATURES = {
     "dgsn_problem_set_materials": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "dgsn_problem_set_inflow": (_I, [_VP, _PD]),
     "dgsn_problem_set_ann": (_I, [_VP, _VP]),
+    "dgsn_problem_set_scattering": (_I, [_VP, _VP, _VP]),
     "dgsn_problem_set_solver": (_I, [_VP, _I]),
     "dgsn_sweep": (_I, [_VP, _VP, _VP, _VP]),
     "dgsn_source_iterate": (_I, [_VP, _VP, _D, _I, _PI, _PD, _PD, _VP]),

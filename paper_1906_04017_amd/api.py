@@ -178,6 +178,18 @@ class Problem:
                                                           _stream(self.ctx.device)))
         torch.cuda.current_stream(self.ctx.device).synchronize()
 
+    def set_scattering(self, sigma_gg):
+        """Multigroup isotropic scattering [G, G, ncell] (from g' into g at
+        [g', g]); None removes it."""
+        if sigma_gg is None:
+            _lib.check(_lib.load().dgsn_problem_set_scattering(self._h, None,
+                                                               _stream(self.ctx.device)))
+            return
+        m = self._dev(sigma_gg, (self.groups, self.groups, self.ncell))
+        _lib.check(_lib.load().dgsn_problem_set_scattering(self._h, _ptr(m),
+                                                           _stream(self.ctx.device)))
+        torch.cuda.current_stream(self.ctx.device).synchronize()
+
     def set_inflow(self, psi_inc):
         arr = np.ascontiguousarray(np.asarray(psi_inc, np.float64).reshape(6))
         _lib.check(_lib.load().dgsn_problem_set_inflow(self._h, arr.ctypes.data_as(_lib._PD)))

@@ -125,6 +125,7 @@ struct dgsn_problem {
     dgsn::DevBuf d_dir;              // [8][Do][kDirStride] real
     dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major
     dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
+    dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
     dgsn::DevBuf src;                         // [G][ncell][8]
     dgsn::DevBuf phi_oct;                     // [8][G][ncell][8]
     dgsn::DevBuf front_x, front_y, front_z;   // [8][..][..][4][Do*G]

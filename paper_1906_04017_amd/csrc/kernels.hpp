@@ -117,6 +117,12 @@ int launch_build_source(long long nv, const Real *q, const Real *ss, const Real 
                         hipStream_t s);
 template <typename Real>
 int launch_adjoint_load(long long nv, const Real *gphi, double vol, Real *gl, hipStream_t s);
+// multigroup source S_g = q_g + (1/4pi) sum_g' sigma(g' -> g) phi_g' (transpose:
+// sigma(g -> g')); q_cell [G][ncell] and/or q_nodal [G][ncell][8] may be null
+template <typename Real>
+int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Real *q_nodal,
+                           const Real *sigma_gg, const Real *phi, Real *src, bool transpose,
+                           hipStream_t s);
 template <typename Real>
 int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, hipStream_t s);
 

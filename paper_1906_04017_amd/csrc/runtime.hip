@@ -393,20 +393,35 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
 {
     const long long nv = (long long)p->G * p->ncell;
     Real *src = static_cast<Real *>(p->src.ptr);
-    DGSN_TRY(launch_build_source<Real>(nv, static_cast<const Real *>(p->q.ptr),
-                                       static_cast<const Real *>(p->sigma_s.ptr),
-                                       static_cast<const Real *>(phi), src, s));
+    // in-group scattering: the next source is fused into the octant
+    // reduction; with a multigroup matrix it is built after it from all groups
+    const Real *gg = static_cast<const Real *>(p->sigma_gg.ptr);
+    if (gg)
+        DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, static_cast<const Real *>(p->q.ptr),
+                                              nullptr, gg, static_cast<const Real *>(phi), src,
+                                              false, s));
+    else
+        DGSN_TRY(launch_build_source<Real>(nv, static_cast<const Real *>(p->q.ptr),
+                                           static_cast<const Real *>(p->sigma_s.ptr),
+                                           static_cast<const Real *>(phi), src, s));
     ReduceArgs<Real> R = reduce_args<Real>(p, phi);
     R.resid = 1;
-    R.src_next = src;
-    R.q_cell = static_cast<const Real *>(p->q.ptr);
-    R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    if (!gg) {
+        R.src_next = src;
+        R.q_cell = static_cast<const Real *>(p->q.ptr);
+        R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    }
     double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
     while (it < max_iter) {
         DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        if (gg)
+            DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G,
+                                                  static_cast<const Real *>(p->q.ptr), nullptr,
+                                                  gg, static_cast<const Real *>(phi), src, false,
+                                                  s));
         double res[3];
         DGSN_TRY(read_result(p, s, res));
         ++it;
@@ -447,17 +462,25 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
     DGSN_TRY(launch_adjoint_load<Real>(nv, static_cast<const Real *>(gphi), vol, load, s));
     DGSN_HIP(hipMemsetAsync(phid, 0, nv * 8 * sizeof(Real), s));
     DGSN_HIP(hipMemcpyAsync(asrc, load, nv * 8 * sizeof(Real), hipMemcpyDeviceToDevice, s));
+    // adjoint source load + sigma_s^T phi_dag / (4 pi): fused in-group, or
+    // the transposed multigroup coupling after the reduction
+    const Real *gg = static_cast<const Real *>(p->sigma_gg.ptr);
     ReduceArgs<Real> R = reduce_args<Real>(p, phid);
     R.resid = 1;
-    R.src_next = asrc;
-    R.q_nodal = load;
-    R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    if (!gg) {
+        R.src_next = asrc;
+        R.q_nodal = load;
+        R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+    }
     double r = INFINITY, best = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
     while (it < max_iter) {
         DGSN_TRY(run_sweep<Real>(p, asrc, false, true, nullptr, s));
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        if (gg)
+            DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg, phid, asrc,
+                                                  true, s));
         double res[3];
         DGSN_TRY(read_result(p, s, res));
         ++it;
@@ -834,6 +857,22 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
     else DGSN_HIP(hipMemsetAsync(p->sigma_s.ptr, 0, bytes, s));
     if (q) DGSN_HIP(hipMemcpyAsync(p->q.ptr, q, bytes, hipMemcpyDeviceToDevice, s));
     else DGSN_HIP(hipMemsetAsync(p->q.ptr, 0, bytes, s));
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *stream)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    if (!sigma_gg) {
+        p->sigma_gg.release();
+        return DGSN_OK;
+    }
+    const size_t bytes = (size_t)p->G * p->G * p->ncell * p->real_size;
+    if (p->sigma_gg.bytes != bytes) DGSN_TRY(p->sigma_gg.alloc(bytes));
+    DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, sigma_gg, bytes, hipMemcpyDeviceToDevice,
+                            as_stream(stream)));
     return DGSN_OK;
 }
 

@@ -161,6 +161,37 @@ __global__ __launch_bounds__(256) void build_source(long long nv, const Real *q,
     }
 }
 
+// Multigroup source (the group sum of the isotropic scattering source): one
+// thread per (cell, node); the G fluxes of the node and the G x G matrix of
+// the cell are read from L2-resident rows (the 8 threads of a cell share
+// them).  Summed over the source group in ascending order.
+template <typename Real>
+__global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
+                                                       const Real *__restrict__ q_cell,
+                                                       const Real *__restrict__ q_nodal,
+                                                       const Real *__restrict__ sigma_gg,
+                                                       const Real *__restrict__ phi,
+                                                       Real *__restrict__ src, int transpose)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ncell * 8;
+         e += stride) {
+        const long long c = e >> 3;
+        const int n = (int)(e & 7);
+        for (int g = 0; g < G; ++g) {
+            const long long gc = (long long)g * ncell + c;
+            Real v = q_cell ? q_cell[gc] : Real(0);
+            if (q_nodal) v += q_nodal[gc * 8 + n];
+            for (int g2 = 0; g2 < G; ++g2) {
+                const long long m = transpose ? ((long long)g * G + g2) * ncell + c
+                                              : ((long long)g2 * G + g) * ncell + c;
+                v = fma(sigma_gg[m] * Real(kInv4Pi), phi[((long long)g2 * ncell + c) * 8 + n], v);
+            }
+            src[gc * 8 + n] = v;
+        }
+    }
+}
+
 // adjoint load: gl = M3^{-1} g / V (so that M3 gl = g / V)
 template <typename Real>
 __global__ __launch_bounds__(256) void adjoint_load(long long nv, const Real *gphi, Real inv_vol,
@@ -296,6 +327,17 @@ int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s)
 }
 
 template <typename Real>
+int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Real *q_nodal,
+                           const Real *sigma_gg, const Real *phi, Real *src, bool transpose,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(build_source_gg<Real>, dim3(grid_for(ncell * 8)), dim3(256), 0, s, ncell,
+                       G, q_cell, q_nodal, sigma_gg, phi, src, transpose ? 1 : 0);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template <typename Real>
 int launch_build_source(long long nv, const Real *q, const Real *ss, const Real *phi, Real *src,
                         hipStream_t s)
 {
@@ -330,6 +372,9 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
     template int launch_reduce<Real>(const ReduceArgs<Real> &, int, hipStream_t);              \
     template int launch_build_source<Real>(long long, const Real *, const Real *, const Real *, \
                                            Real *, hipStream_t);                               \
+    template int launch_build_source_gg<Real>(long long, int, const Real *, const Real *,       \
+                                              const Real *, const Real *, Real *, bool,         \
+                                              hipStream_t);                                     \
     template int launch_adjoint_load<Real>(long long, const Real *, double, Real *,            \
                                            hipStream_t);                                       \
     template int launch_reduce_grad<Real>(long long, const Real *, Real *, Real *, hipStream_t);

@@ -222,6 +222,84 @@ def test_source_iteration_resume_from_saved_phi(api, ctx):
 
 
 # ---------------------------------------------------------------------------
+# multigroup scattering (group-to-group matrix, P0)
+# ---------------------------------------------------------------------------
+
+def _multigroup(p, seed, up=0.05, c=0.8):
+    """Group-to-group matrix [G, G, ncell] (from g' into g): downscatter and
+    in-group terms, a little upscatter, total scattering c sigma_t per group."""
+    rng = np.random.default_rng(seed)
+    G, nc = p["sigma_t"].shape
+    gg = rng.uniform(0.0, 1.0, (G, G, nc))
+    for g2 in range(G):
+        for g in range(g2):
+            gg[g2, g] *= up
+    return gg * (c * p["sigma_t"])[None] / gg.sum(axis=0, keepdims=True)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", FP32_TOL)])
+def test_multigroup_source_iteration_matches_oracle(api, ctx, precision, tol):
+    p = inputs.random_problem((6, 5, 4), 4, 3, seed=81, length=(0.6, 0.5, 0.4))
+    gg = _multigroup(p, 82)
+    print_case("multigroup_si", name=p["name"], precision=precision)
+    prob = gpu_problem(api, ctx, p, precision)
+    prob.set_scattering(gg)
+    si_tol = 1e-13 if precision == "fp64" else 1e-8
+    phi, info = prob.source_iterate(tol=si_tol, max_iter=1000, allow_notconv=precision == "fp32")
+    om, w = oracle.lq_n(4)
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], np.zeros_like(p["sigma_t"]),
+                                p["q"], p["psi_inc"], tol=1e-14, max_iter=3000, sigma_gg=gg)
+    assert ref["converged"]
+    for g in range(p["groups"]):
+        assert rel(phi.cpu().numpy()[g], ref["phi"][g]) <= tol, g
+    # removing the matrix returns to the in-group sigma_s of set_materials
+    prob.set_scattering(None)
+    phi0, _ = prob.source_iterate(tol=si_tol, max_iter=1000, allow_notconv=precision == "fp32")
+    ref0 = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                 p["psi_inc"], tol=1e-14, max_iter=3000)
+    assert rel(phi0.cpu().numpy(), ref0["phi"]) <= tol
+
+
+def test_multigroup_diagonal_matrix_is_in_group_scattering(api, ctx):
+    p = inputs.random_problem((5, 4, 4), 4, 2, seed=83, c_max=0.8)
+    print_case("multigroup_diag", name=p["name"])
+    diag = np.zeros((2, 2, p["sigma_t"].shape[1]))
+    for g in range(2):
+        diag[g, g] = p["sigma_s"][g]
+    prob = gpu_problem(api, ctx, p, "fp64")
+    a, ia = prob.source_iterate(tol=1e-12, max_iter=1000)
+    prob.set_scattering(diag)
+    b, ib = prob.source_iterate(tol=1e-12, max_iter=1000)
+    assert ia["iters"] == ib["iters"]
+    assert rel(b.cpu().numpy(), a.cpu().numpy()) <= 1e-14
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_multigroup_adjoint_matches_oracle(api, ctx, precision, tol):
+    p = inputs.adjoint_box(n=6, groups=3, seed=84, box=(1, 4))
+    gg = _multigroup(p, 85, c=0.6)
+    print_case("multigroup_adjoint", name=p["name"], precision=precision)
+    prob = gpu_problem(api, ctx, p, precision, store_psi=True)
+    prob.set_scattering(gg)
+    si_tol = 1e-13 if precision == "fp64" else 1e-7
+    prob.source_iterate(tol=si_tol, max_iter=1000, allow_notconv=True)
+    nc = p["sigma_t"].shape[1]
+    g = np.zeros((p["groups"], nc, 8))
+    g[:, p["box_mask"], :] = 1.0
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    gst, gq, _ = prob.adjoint(torch.tensor(g, dtype=dt, device="cuda"), tol=si_tol,
+                              max_iter=1000, allow_notconv=True)
+    om, w = oracle.lq_n(p["order"])
+    zero = np.zeros_like(p["sigma_t"])
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], zero, p["q"], p["psi_inc"],
+                                tol=1e-14, max_iter=3000, store_psi=True, sigma_gg=gg)
+    a = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], zero, ref["psi"], ref["phi"], g,
+                       tol=1e-14, sigma_gg=gg)
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= tol
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= tol
+
+
+# ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
 

@@ -620,3 +620,85 @@ def test_pann_octant_mirror_equivariance():
     phi_m = oracle.pann_sweep(net, mesh, om_m, w, sig_m, src_m, inc_m)
     back = phi_m[:, cm][:, :, [nn ^ 1 for nn in range(8)]]
     assert np.abs(back - phi).max() < 1e-12 * np.abs(phi).max()
+
+
+# ---------------------------------------------------------------------------
+# multigroup isotropic scattering (the group sum of Eq. (T3)-(T8) at P0)
+# ---------------------------------------------------------------------------
+
+def _multigroup_case(seed=61, ng=3):
+    rng = np.random.default_rng(seed)
+    mesh = (2, 2, 3, 0.8, 0.9, 1.2)
+    nc = 12
+    om, w = oracle.lq_n(2)
+    st = rng.uniform(1.0, 3.0, (ng, nc))
+    # downscatter, in-group and a little upscatter; every group keeps c < 0.8
+    gg = rng.uniform(0.0, 1.0, (ng, ng, nc))
+    for g2 in range(ng):
+        for g in range(ng):
+            if g < g2:
+                gg[g2, g] *= 0.05
+    gg *= 0.8 * st[None, :, :] / gg.sum(axis=0, keepdims=True)
+    q = rng.uniform(0.0, 1.0, (ng, nc))
+    inc = rng.uniform(0.0, 1.0, 6)
+    return mesh, om, w, st, gg, q, inc
+
+
+def test_multigroup_source_iteration_equals_dense_global_solve():
+    mesh, om, w, st, gg, q, inc = _multigroup_case()
+    r = oracle.source_iterate(mesh, om, w, st, np.zeros_like(st), q, inc, tol=1e-15,
+                              max_iter=3000, sigma_gg=gg)
+    assert r["converged"]
+    _, phi_b = brute.solve(mesh, om, w, st, np.zeros_like(st), q, inc, sigma_gg=gg)
+    assert np.abs(r["phi"] - phi_b).max() <= 1e-12 * np.abs(phi_b).max()
+
+
+def test_multigroup_diagonal_matrix_is_in_group_scattering():
+    mesh, om, w, st, gg, q, inc = _multigroup_case(seed=62)
+    ss = np.einsum("ggc->gc", gg)
+    diag = np.zeros_like(gg)
+    for g in range(gg.shape[0]):
+        diag[g, g] = ss[g]
+    a = oracle.source_iterate(mesh, om, w, st, ss, q, inc, tol=1e-14, max_iter=3000)
+    b = oracle.source_iterate(mesh, om, w, st, np.zeros_like(ss), q, inc, tol=1e-14,
+                              max_iter=3000, sigma_gg=diag)
+    assert a["iters"] == b["iters"]
+    assert np.abs(a["phi"] - b["phi"]).max() <= 1e-15 * np.abs(a["phi"]).max()
+
+
+def test_multigroup_constant_solution():
+    # uniform medium, every group psi_g = c with inflow c: the balance
+    # sigma_t,g c - sum_g' sigma(g' -> g) c = q_g gives psi == c everywhere
+    mesh = (3, 2, 2, 0.9, 0.6, 0.6)
+    nc = 12
+    om, w = oracle.lq_n(4)
+    st_g = np.array([2.0, 3.0, 2.5])
+    M = np.array([[0.5, 0.8, 0.3], [0.0, 1.2, 0.9], [0.1, 0.0, 1.0]])   # [g'][g]
+    cval = 0.7
+    q_g = cval * (st_g - M.sum(axis=0))
+    assert np.all(q_g > 0)
+    st = np.repeat(st_g[:, None], nc, axis=1)
+    gg = np.repeat(M[:, :, None], nc, axis=2)
+    q = np.repeat(q_g[:, None], nc, axis=1)
+    r = oracle.source_iterate(mesh, om, w, st, np.zeros_like(st), q, np.full(6, cval), tol=1e-15,
+                              max_iter=5000, sigma_gg=gg)
+    assert np.abs(r["phi"] / (4 * np.pi) - cval).max() < 1e-11
+
+
+def test_multigroup_adjoint_matches_dense_transpose():
+    mesh, om, w, st, gg, q, inc = _multigroup_case(seed=63)
+    rng = np.random.default_rng(64)
+    g = rng.uniform(0.0, 1.0, (st.shape[0], 12, 8))
+    zero = np.zeros_like(st)
+    r = oracle.source_iterate(mesh, om, w, st, zero, q, inc, tol=1e-15, max_iter=3000,
+                              store_psi=True, sigma_gg=gg)
+    a = oracle.adjoint(mesh, om, w, st, zero, r["psi"], r["phi"], g, tol=1e-15, sigma_gg=gg)
+    lam = brute.adjoint_solve(mesh, om, w, st, zero, g, sigma_gg=gg)
+    h = np.array(mesh[3:]) / np.array(mesh[:3])
+    M, _, _ = oracle.element_matrices(h)
+    gq = np.einsum("dgcn,nm->gc", lam, M)
+    assert np.abs(a["grad_q"] - gq).max() < 1e-12 * np.abs(gq).max()
+    # duality <W^T g, psi> = <lambda, Q>
+    _, phi_b = brute.solve(mesh, om, w, st, zero, q, inc, sigma_gg=gg)
+    _, Q = brute.assemble(mesh, om, w, st, zero, q, inc, sigma_gg=gg)
+    assert abs((g * phi_b).sum() - lam.reshape(-1) @ Q) < 1e-13 * abs((g * phi_b).sum())
