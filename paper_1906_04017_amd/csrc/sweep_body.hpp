@@ -34,6 +34,33 @@ __device__ __forceinline__ void reflect8(Real v[8], int mask)
     }
 }
 
+// 8-node record at p read into canonical order: v[n] = p[n ^ mask].  Node
+// pairs (n, n ^ 1) are contiguous, so the y and z reflections permute the four
+// pair addresses and only the x reflection moves registers (within a pair).
+template <typename Real>
+__device__ __forceinline__ void load8_reflect(const Real *p, int mask, Real v[8])
+{
+    const int pm = (mask >> 1) & 3;
+#pragma unroll
+    for (int pr = 0; pr < 4; ++pr) {
+        const Real a = p[2 * (pr ^ pm)], b = p[2 * (pr ^ pm) + 1];
+        v[2 * pr] = (mask & 1) ? b : a;
+        v[2 * pr + 1] = (mask & 1) ? a : b;
+    }
+}
+
+// Canonical 8-node vector v stored in physical order: p[n ^ mask] = v[n].
+template <typename Real>
+__device__ __forceinline__ void store8_reflect(Real *p, int mask, const Real v[8])
+{
+    const int pm = (mask >> 1) & 3;
+#pragma unroll
+    for (int pr = 0; pr < 4; ++pr) {
+        p[2 * (pr ^ pm)] = (mask & 1) ? v[2 * pr + 1] : v[2 * pr];
+        p[2 * (pr ^ pm) + 1] = (mask & 1) ? v[2 * pr] : v[2 * pr + 1];
+    }
+}
+
 template <typename Real>
 __device__ __forceinline__ void load4(const Real *p, Real v[4])
 {
@@ -323,10 +350,14 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     c = i + A.nx * (j + A.ny * k);
                     const uint32_t gc = g * A.ncell + c;
                     st = A.sigma_t[gc];
-                    const Real *sp = A.src + gc * 8;
-                    load4(sp, sc);
-                    load4(sp + 4, sc + 4);
-                    reflect8(sc, mask);
+                    if constexpr (Form == kFormDense) {
+                        // (the address form costs this kernel a wave per SIMD)
+                        load4(A.src + gc * 8, sc);
+                        load4(A.src + gc * 8 + 4, sc + 4);
+                        reflect8(sc, mask);
+                    } else {
+                        load8_reflect(A.src + gc * 8, mask, sc);
+                    }
                     ex = o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4;
                     ey = o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4;
                     ez = o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4;
@@ -423,18 +454,11 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     if (kStorePsi || (kAdjoint && A.grad_oct)) {
                         Real *pp = A.psi + ((size_t)slot * A.ncell + c) * 8;
                         if (kStorePsi) {
-                            Real ph[8];
-#pragma unroll
-                            for (int n = 0; n < 8; ++n) ph[n] = psi[n];
-                            reflect8(ph, mask);
-                            store4(pp, ph[0], ph[1], ph[2], ph[3]);
-                            store4(pp + 4, ph[4], ph[5], ph[6], ph[7]);
+                            store8_reflect(pp, mask, psi);
                         } else {
                             // mu^T M psi with the stored forward flux, M = V M3
                             Real pf[8], m[8];
-                            load4(pp, pf);
-                            load4(pp + 4, pf + 4);
-                            reflect8(pf, mask);
+                            load8_reflect(pp, mask, pf);
                             mass3_216(pf, m);
                             Real s = 0, sm = 0;
 #pragma unroll
