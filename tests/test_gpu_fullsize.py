@@ -130,3 +130,73 @@ def test_reflection_symmetry_at_bench_size(api, ctx):
     phi = prob.sweep(torch.ones((2, n ** 3, 8), device="cuda")).cpu().numpy()
     f = phi.reshape(2, n, n, n, 2, 2, 2)
     assert np.abs(f - f[:, :, :, ::-1, :, :, ::-1]).max() <= 1e-5 * np.abs(f).max()
+
+
+def test_adjoint_box_full_size(api, ctx):
+    # the adjoint workload (32^3, S4, 2 groups, c = 0.5, response box cells
+    # 12..19): FP32 GPU gradients of the box absorption with respect to sigma_t
+    # and q against the FP64 oracle adjoint
+    p = inputs.adjoint_box()
+    print_case("fullsize_adjoint", name=p["name"])
+    om, w = api.quadrature_ls(p["order"])
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32",
+                       store_psi=True)
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.source_iterate(tol=1e-7, max_iter=500, allow_notconv=True)
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    nc = p["sigma_t"].shape[1]
+    g = np.zeros((p["groups"], nc, 8))
+    g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
+    gst, gq, _ = prob.adjoint(torch.tensor(g, dtype=torch.float32, device="cuda"), tol=1e-7,
+                              max_iter=500, allow_notconv=True)
+    om_o, w_o = oracle.lq_n(p["order"])
+    mesh = (*p["n"], *p["length"])
+    ref = oracle.source_iterate(mesh, om_o, w_o, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-12, max_iter=2000, store_psi=True)
+    a = oracle.adjoint(mesh, om_o, w_o, p["sigma_t"], p["sigma_s"], ref["psi"], ref["phi"], g,
+                       tol=1e-12)
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= 1e-4
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= 1e-4
+
+
+def test_uneven_batch_full_size(api, ctx):
+    # the batched workload (64 problems, 16^3..96^3, S4..S12, 1..8 groups, GE
+    # or the matrix-core network), autotuned as bench.py runs it: every
+    # problem's result bitwise equal to its own single-problem sweep (the cell
+    # arithmetic does not depend on tiling or schedule), and the three
+    # smallest GE problems against the oracle
+    import os
+    ps = inputs.uneven_batch()
+    ann = api.Ann(ctx, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    "paper_1906_04017_amd", "data", "ann_s8_relu64.dgsnann"))
+    probs, srcs, phis = [], [], []
+    for p in ps:
+        om, w = api.quadrature_ls(p["order"])
+        prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32",
+                           solver=p["solver"])
+        prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+        if p["solver"] == "ann":
+            prob.set_ann(ann)
+        S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32,
+                         device="cuda")
+        probs.append(prob)
+        srcs.append(S)
+        phis.append(torch.full_like(S, float("nan")))
+    batch = api.Batch(ctx, probs)
+    for k in range(len(ps)):
+        batch.set_io(k, srcs[k], phis[k])
+    batch.autotune()
+    print_case("fullsize_batch", problems=len(ps), schedule=batch.schedule())
+    batch.run()
+    torch.cuda.synchronize()
+    for k, p in enumerate(ps):
+        ref = probs[k].sweep(srcs[k])
+        assert torch.equal(phis[k], ref), (k, p["name"])
+    ge = sorted((p["n"][0] ** 3 * p["groups"], k) for k, p in enumerate(ps) if p["solver"] == "ge")
+    for _, k in ge[:3]:
+        p = ps[k]
+        om_o, w_o = oracle.lq_n(p["order"])
+        want = oracle.sweep((*p["n"], *p["length"]), om_o, w_o, p["sigma_t"],
+                            srcs[k].cpu().numpy(), p["psi_inc"])
+        assert rel(phis[k].cpu().numpy(), want) <= 1e-5, p["name"]
+    batch.close()
