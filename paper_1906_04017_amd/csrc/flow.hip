@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void flow_reset(unsigned *sync, int n)
 }
 
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
-__global__ __launch_bounds__(256) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
+__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
 {
     // 256 lanes as in the hyperplane kernel; A.cells is the whole tile list
     // of the schedule

@@ -101,6 +101,13 @@ constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense eliminat
 constexpr int kFormAnn = 2;       // the shallow network in place of assembly + elimination
 constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector ALUs)
 
+// Occupancy request of a sweep kernel (waves per SIMD; 1 = no request).  The
+// FP64 single-cell mass-inverse kernel would take 176 registers and run at 2
+// waves per SIMD; held to 168 it runs at 3 with no spills.  The larger FP64
+// tiles and the dense form would spill, so they keep the compiler's choice.
+template <typename Real, int Form, int B>
+constexpr int kMinWavesPerSimd = (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv) ? 3 : 1;
+
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 
 template <typename Real>

@@ -24,7 +24,7 @@ namespace dgsn {
 namespace {
 
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
-__global__ __launch_bounds__(256) void sweep_tile_ge(PlaneArgs<Real> A)
+__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_tile_ge(PlaneArgs<Real> A)
 {
     // 256 lanes: (direction, group, tile slot) segments, grid = (tile blocks, octant)
     __shared__ TileLds<Real> L;
