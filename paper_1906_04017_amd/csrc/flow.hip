@@ -97,6 +97,31 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_
     flow_finish(F, tid, o, t);
 }
 
+// The matrix-core network under the dataflow schedule: the same unit
+// protocol, and the per-wave operand staging of the network in LDS.
+template <int B>
+__global__ __launch_bounds__(256) void sweep_flow_ann(PlaneArgs<float> A, FlowArgs F)
+{
+    __shared__ TileLds<float> L;
+    __shared__ AnnLds al;
+    __shared__ uint4 sh[2];
+    const int tid = threadIdx.x;
+    const unsigned o = blockIdx.x & 7u;
+    if (tid < 64) flow_take(F, o, tid, sh);
+    __syncthreads();
+    const unsigned blk = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].y);
+    const unsigned t0 = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].z);
+    const unsigned cnt = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].w);
+    const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[1].x);
+    const SegLane l = seg_lane(A, tid);
+    bool tvalid;
+    const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
+    const float inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
+    tile_body<float, kFormAnn, B, false, false, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
+                                                      l.ok, L, &al);
+    flow_finish(F, tid, o, t);
+}
+
 template <typename Real, int Form, int B>
 void launch_flow_form(const PlaneArgs<Real> &A, const FlowArgs &F, bool store_psi, bool adjoint,
                       dim3 grid, dim3 block, hipStream_t s)
@@ -117,6 +142,17 @@ void launch_flow_b(const PlaneArgs<Real> &A, const FlowArgs &F, int b, bool stor
     case 3: launch_flow_form<Real, Form, 3>(A, F, store_psi, adjoint, grid, block, s); break;
     case 2: launch_flow_form<Real, Form, 2>(A, F, store_psi, adjoint, grid, block, s); break;
     default: launch_flow_form<Real, Form, 1>(A, F, store_psi, adjoint, grid, block, s); break;
+    }
+}
+
+// The matrix-core network: FP32 forward sweeps only.
+void launch_flow_ann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 grid, dim3 block,
+                     hipStream_t s)
+{
+    switch (b) {
+    case 3: hipLaunchKernelGGL(sweep_flow_ann<3>, grid, block, 0, s, A, F); break;
+    case 2: hipLaunchKernelGGL(sweep_flow_ann<2>, grid, block, 0, s, A, F); break;
+    default: hipLaunchKernelGGL(sweep_flow_ann<1>, grid, block, 0, s, A, F); break;
     }
 }
 
@@ -147,14 +183,16 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
                 bool adjoint, hipStream_t s)
 {
     const dim3 block(256);
-    if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
-        return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
+    if ((form == kFormAnnPaper || form == kFormAnn) && (sizeof(Real) != 4 || store_psi || adjoint))
+        return set_error(DGSN_EUNSUPPORTED, "the network solvers run FP32 forward sweeps");
     for (unsigned done = 0; done < F.units_o; done += kFlowMaxGroupsPerOctant) {
         const dim3 grid(8 * std::min(F.units_o - done, kFlowMaxGroupsPerOctant));
         if (form == kFormDense) {
             launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
         } else if (form == kFormAnnPaper) {
             if constexpr (sizeof(Real) == 4) launch_flow_pann(A, F, b, grid, block, s);
+        } else if (form == kFormAnn) {
+            if constexpr (sizeof(Real) == 4) launch_flow_ann(A, F, b, grid, block, s);
         } else {
             launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
         }

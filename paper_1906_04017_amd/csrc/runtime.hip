@@ -295,7 +295,8 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     if (ann) A.ann_params = ann_device_params(p->ann);
     if (paper) A.ann_params = p->d_pann.ptr;
     const int form = paper ? kFormAnnPaper
-                           : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
+                           : ann ? kFormAnn
+                                 : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
     const int tb = p->tile_b;
     const bool tiled = tb > 1;
     const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles[tb].ptr
@@ -304,7 +305,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const int nsteps = tiled ? p->n_tplanes[tb] : p->n_planes;
     p->last_stream = s;
     p->ev_used = 0;
-    if (p->schedule == DGSN_SCHED_DATAFLOW && !ann) {
+    if (p->schedule == DGSN_SCHED_DATAFLOW) {
         DGSN_TRY(flow_prepare(p));
         FlowArgs F{};
         F.unit_map = static_cast<const uint4 *>(p->d_unit_map[tb].ptr);
@@ -541,9 +542,8 @@ int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2 * kMaxTile]
     const int saved_timing = p->timing;
     p->timing = 0;
     // candidates: every tile edge with the hyperplane schedule, and with the
-    // dataflow schedule where it applies (all but the matrix-core network)
-    const bool mfma_ann = p->solver == DGSN_ANN && p->ann->version == 1;
-    const int nsched = mfma_ann || flow_prepare(p) != DGSN_OK ? 1 : 2;
+    // dataflow schedule where its tables can be built
+    const int nsched = flow_prepare(p) != DGSN_OK ? 1 : 2;
     clear_error();
     double best[2][kMaxTile];
     for (int sc = 0; sc < 2; ++sc)

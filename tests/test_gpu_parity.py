@@ -420,6 +420,26 @@ def test_ann_sweep_inflow_passthrough_net(api, ctx, tmp_path, tile):
     assert rel(phi, ref) <= 2 * 6 * 2.0 ** -8
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_ann_dataflow_matches_planes_bitwise(api, ctx, tmp_path, tile):
+    # the matrix-core network under the one-launch dataflow schedule runs the
+    # same per-cell arithmetic as under the hyperplane launches
+    net = _random_net(91)
+    ann = api.Ann(ctx, _write_net(tmp_path, net, "flow_ann.dgsnann"))
+    p = inputs.random_problem((9, 7, 8), 8, 3, seed=92, length=(0.9, 0.7, 0.8))
+    print_case("ann_dataflow", name=p["name"], tile=tile)
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    prob.set_tile(tile)
+    S = torch.tensor(nodal_source(p, seed=93), dtype=torch.float32, device="cuda")
+    ref = prob.sweep(S).clone()
+    prob.set_schedule("dataflow")
+    for _ in range(3):
+        got = prob.sweep(S)
+        prob.check()
+        assert torch.equal(got, ref)
+
+
 # ---------------------------------------------------------------------------
 # paper-form per-octant network (26 inputs, tanh, ELU; vector ALUs)
 # ---------------------------------------------------------------------------
