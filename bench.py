@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--paper-tables", action="store_true",
                     help="only reproduce the paper's Problem 1-4 grids (S2-S8 at 100^3, "
                          "10^3-100^3 at S8) with every local solver; prints one JSON line")
+    ap.add_argument("--ann-only", action="store_true",
+                    help="only run --steps sweeps of the BF16-MFMA network on the paper problems "
+                         "(128^3, S8, 4 groups) after autotuning: the workload of the matrix-core "
+                         "counter passes")
     ap.add_argument("--cpu-groups", type=int, default=8,
                     help="groups of the workload swept by the CPU oracle sample")
     return ap.parse_args()
@@ -126,6 +130,10 @@ def main():
     import torch
     from paper_1906_04017_amd import api, inputs
 
+    if args.ann_only:
+        ctx = api.Context(0)
+        print(json.dumps(ann_sweeps(api, ctx, args.ann, args.steps)), flush=True)
+        return
     if args.paper_tables:
         ctx = api.Context(0)
         print(json.dumps(paper_tables(api, ctx, args.ann, args.ann_paper)), flush=True)
@@ -271,6 +279,13 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
         solves = prob.stats()["solves_per_sweep"]
         out[f"{solver}_solves_per_s"] = solves / dt
         out[f"{solver}_ms_per_sweep"] = dt * 1e3
+        if solver == "ann":
+            # the BF16 network's matrix-core rate: 6144 issued flops per solve
+            # (2 * (32 * 64 + 64 * 16), K padded 24 -> 32, N 8 -> 16)
+            tf = 6144 * solves / dt / 1e12
+            out["ann_mfma_roofline"] = {"bound": "mfma", "achieved": round(tf, 1),
+                                        "peak": 2500.0, "unit": "TFLOP/s",
+                                        "frac": round(tf / 2500.0, 4), "flops_per_solve": 6144}
         res[solver] = phi.double().mean(-1)        # cell averages [G, ncell]
         log(f"paper problems {solver}: {dt * 1e3:.3f} ms per sweep")
         prob.close()
@@ -306,6 +321,34 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
                             "iterations GE / ANN 237 / 110 on Problem 4")
     for a in nets.values():
         a.close()
+    return out
+
+
+def ann_sweeps(api, ctx, ann_path, reps, n=128):
+    """Sweeps of the paper problems (128^3, S8, 4 groups) with the BF16-MFMA
+    network alone, for the matrix-core counters: the network's two layers
+    issue 2 * (32 * 64 + 64 * 16) = 6144 MFMA flops per solve (K padded 24 ->
+    32, N 8 -> 16)."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    p = inputs.paper_problems(n=n, groups=4, order=8)
+    om, w = api.quadrature_ls(8)
+    ann = api.Ann(ctx, ann_path)
+    prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32", solver="ann")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.set_inflow(p["psi_inc"])
+    prob.set_ann(ann)
+    tile, sched, _ = prob.autotune()
+    S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32, device="cuda")
+    dt, _ = time_sweeps(prob, S, reps)
+    solves = prob.stats()["solves_per_sweep"]
+    log(f"ann sweeps: {sched} schedule, {tile}^3 tiles, {dt * 1e3:.3f} ms per sweep")
+    out = {"workload": p["name"], "schedule": sched, "tile": tile, "sweeps": reps + 1,
+           "ms_per_sweep": dt * 1e3, "solves_per_sweep": solves,
+           "mfma_flops_per_sweep": 6144 * solves,
+           "mfma_tflops": 6144 * solves / dt / 1e12}
+    prob.close()
+    ann.close()
     return out
 
 
