@@ -309,6 +309,7 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
             prob.set_ann(nets[solver])
         prob.set_si_criterion("eps_s")
         phi, info = prob.source_iterate(tol=1e-4, max_iter=2000, allow_notconv=True)
+        info["rho_eff"] = api.spectral_radius(prob.si_history()[0])
         si[solver] = (phi.double().mean(-1), info)
         log(f"problem 4 SI {solver}: {info['iters']} iterations, eps_S {info['eps_s']:.2e}")
         prob.close()
@@ -316,6 +317,7 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
         e4 = ((si[net][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
         out[f"{net}_eps_p_percent_problem4_si"] = round(100 * e4, 3)
     out["problem4_si_iterations"] = {k: v[1]["iters"] for k, v in si.items()}
+    out["problem4_rho_eff"] = {k: v[1]["rho_eff"] for k, v in si.items()}
     out["paper_context"] = ("paper, 100^3 S8, unstated hardware: ANN saves 68.4 % of the solve time "
                             "(3.16x); eps_P 1.59 / 2.45 / 0.45 / 0.87 % on Problems 1-4; SI "
                             "iterations GE / ANN 237 / 110 on Problem 4")
@@ -408,9 +410,15 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
             phi, info = prob.source_iterate(tol=1e-4, max_iter=3000, allow_notconv=True)
             torch.cuda.synchronize()
             si[sv] = (phi.double().mean(-1), info, time.perf_counter() - t0)
+            info["rho_eff"] = api.spectral_radius(prob.si_history()[0])
             prob.close()
         row["p4_si_iterations"] = {sv: si[sv][1]["iters"] for sv in solvers}
         row["p4_si_ms"] = {sv: round(1e3 * si[sv][2], 2) for sv in solvers}
+        row["p4_rho_eff"] = {sv: (None if si[sv][1]["rho_eff"] is None else
+                                  round(si[sv][1]["rho_eff"], 4)) for sv in solvers}
+        # the paper's overall acceleration: time of the GE solution over the
+        # network's (sweep speed and iteration count together)
+        row["p4_overall_acceleration"] = {sv: round(si["ge"][2] / si[sv][2], 3) for sv in nets}
         for sv in nets:
             e4 = ((si[sv][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
             row[f"{sv}_eps_p_percent_p4"] = round(100 * e4, 3)
@@ -425,7 +433,8 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
                               "P2 0.07/1.09/2.57/2.45 %, P3 0.14/0.86/0.68/0.45 % at 100^3 "
                               "S2-S8; P4 SI iterations GE/ANN 211/101, 220/102, 228/104, "
                               "237/110 at 100^3 S2-S8 and 15/9, 42/20, 121/58 at 10^3, 25^3, "
-                              "50^3 S8")}
+                              "50^3 S8; effective spectral radius 0.957 (GE) / 0.859 (ANN); "
+                              "overall acceleration on Problem 4 about 12")}
 
 
 def adjoint_box(api, ctx, n=32, cells=8, h=1e-6):

@@ -184,6 +184,18 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                         double *resid, double *eps_s, void *stream);
 
 /*
+ * Convergence history of the problem's last dgsn_source_iterate call: the
+ * residual (the max-norm relative change above) and eps_S of Eq. (Test:Eq3)
+ * after each of its iterations, the quantities from which the effective
+ * spectral radius of the iteration (Sec. 4, the discussion of Problem 4) is
+ * read as the ratio of successive residuals.  resid, eps_s: host arrays of cap
+ * entries (either may be NULL); the first min(cap, n) entries are written.
+ * n (host out): iterations recorded (0 before the first call).  A failed call
+ * records the iterations it completed.
+ */
+int dgsn_problem_si_history(const dgsn_problem *p, double *resid, double *eps_s, int cap, int *n);
+
+/*
  * Sweep tiling: with b > 1 every lane solves a b x b x b tile of cells for
  * its (direction, group) in upwind order, keeping the faces between them in
  * registers (the face traffic through HBM drops from 24 to 24/b values per
@@ -195,14 +207,14 @@ int dgsn_problem_set_tile(dgsn_problem *p, int b);
 int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
 
 /*
- * Sweep schedule (GE solvers; the ANN solver always uses the hyperplane
- * schedule).  The sweep order follows from the upwind dependence of each cell
- * on its three inflow neighbours (the sweep paragraph after Eq. (T12)).
+ * Sweep schedule (every local solver).  The sweep order follows from the
+ * upwind dependence of each cell on its three inflow neighbours (the sweep
+ * paragraph after Eq. (T12)).
  *   DGSN_SCHED_PLANES: one kernel launch per (tile) hyperplane (default).
- *   DGSN_SCHED_DATAFLOW: one launch per sweep; workgroups take blocks of
- *     tiles in hyperplane order from a device ticket counter and wait on
- *     device counters until their octant's previous hyperplane is complete.
- *     Every wait is bounded by poll_limit polls (0: the library default,
+ *   DGSN_SCHED_DATAFLOW: one launch per sweep; the workgroups of an octant
+ *     take blocks of tiles in hyperplane order from that octant's device
+ *     ticket counter and wait on the done flags of the blocks of the previous
+ *     hyperplane that hold their tiles' upwind neighbours.  Every wait is bounded by poll_limit polls (0: the library default,
  *     about a second); if one expires the launch still completes, its results
  *     are invalid, and the next dgsn_problem_check (also run inside
  *     dgsn_source_iterate, dgsn_adjoint_solve and the autotuner) returns

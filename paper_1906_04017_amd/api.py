@@ -146,6 +146,21 @@ def local_solve(ctx, x):
     return y
 
 
+def spectral_radius(resid, tail=0.5):
+    """Effective spectral radius of a source iteration from its residual
+    history: the geometric mean ratio of successive residuals over the last
+    `tail` fraction of the iterations (at least 2 steps), or None when fewer
+    than 4 iterations were run or a residual is zero."""
+    r = np.asarray(resid, dtype=np.float64)
+    n = r.size
+    if n < 4:
+        return None
+    m = min(n - 3, int(n * (1.0 - tail)))
+    if r[m] <= 0.0 or r[-1] <= 0.0:
+        return None
+    return float((r[-1] / r[m]) ** (1.0 / (n - 1 - m)))
+
+
 class Problem:
     """One DGFEM S_n problem on the GPU (uniform hex mesh, one quadrature)."""
 
@@ -285,6 +300,19 @@ class Problem:
         _lib.check(rc, allow=(_lib.DGSN_ENOTCONV,) if allow_notconv else ())
         return phi, dict(iters=it.value, resid=r.value, eps_s=es.value,
                          converged=(rc == _lib.DGSN_OK))
+
+    def si_history(self):
+        """Per-iteration residual (max-norm relative change) and eps_S of the
+        last source_iterate call, as two float64 arrays."""
+        n = ctypes.c_int(0)
+        lib = _lib.load()
+        _lib.check(lib.dgsn_problem_si_history(self._h, None, None, 0, ctypes.byref(n)))
+        r = np.zeros(max(n.value, 1))
+        e = np.zeros(max(n.value, 1))
+        _lib.check(lib.dgsn_problem_si_history(
+            self._h, r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value, ctypes.byref(n)))
+        return r[:n.value], e[:n.value]
 
     def si_step(self, phi):
         """One source iteration in place on phi (source build, sweep, octant

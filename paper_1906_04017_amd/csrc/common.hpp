@@ -112,6 +112,7 @@ struct dgsn_problem {
     // dataflow schedule (one launch per sweep, GE solvers): per tile edge B
     // (1 = cells) the first unit and the first tile of every step, on device
     int schedule = DGSN_SCHED_PLANES;
+    std::vector<double> si_resid, si_eps;   // per iteration of the last source iteration
     int flow_ready = 0;
     dgsn::DevBuf d_unit_map[4];      // uint4 per unit of one octant (built on first use)
     dgsn::DevBuf d_unit_dep[4];      // uint2 per unit: range of units it waits for

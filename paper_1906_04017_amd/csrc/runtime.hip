@@ -415,6 +415,8 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
+    p->si_resid.clear();
+    p->si_eps.clear();
     while (it < max_iter) {
         DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
@@ -428,6 +430,8 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         ++it;
         r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
         es = res[2] / (double)nv;
+        p->si_resid.push_back(r);
+        p->si_eps.push_back(es);
         if (!std::isfinite(r))
             return set_error(DGSN_EINVAL, "source iteration produced a non-finite residual");
         crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
@@ -1012,6 +1016,20 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                                              as_stream(stream))
                : source_iterate_impl<float>(p, phi, tol, max_iter, iters, resid, eps_s,
                                             as_stream(stream));
+}
+
+int dgsn_problem_si_history(const dgsn_problem *p, double *resid, double *eps_s, int cap, int *n)
+{
+    clear_error();
+    if (!p || !n) return set_error(DGSN_EINVAL, "problem and n must be set");
+    if (cap < 0) return set_error(DGSN_EINVAL, "cap must be >= 0");
+    const int cnt = (int)p->si_resid.size();
+    *n = cnt;
+    for (int i = 0; i < cnt && i < cap; ++i) {
+        if (resid) resid[i] = p->si_resid[i];
+        if (eps_s) eps_s[i] = p->si_eps[i];
+    }
+    return DGSN_OK;
 }
 
 int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, double tol,

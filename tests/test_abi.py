@@ -145,6 +145,24 @@ def test_null_handles_are_rejected(lib):
     d, keep = _desc()
     assert lib.dgsn_problem_create(None, ctypes.byref(d), ctypes.byref(out)) == _lib.DGSN_EINVAL
     assert lib.dgsn_local_solve(None, None, None, 10, 0, None) == _lib.DGSN_EINVAL
+    n = ctypes.c_int(-1)
+    assert lib.dgsn_problem_si_history(None, None, None, 0, ctypes.byref(n)) == _lib.DGSN_EINVAL
+
+
+def test_spectral_radius_estimate():
+    from paper_1906_04017_amd.api import spectral_radius
+    # a geometric residual sequence has its ratio as the estimate, over any tail
+    for rho in (0.3, 0.859, 0.957):
+        r = 2.5 * rho ** np.arange(40)
+        assert abs(spectral_radius(r) - rho) < 1e-12
+        assert abs(spectral_radius(r, tail=0.1) - rho) < 1e-12
+    # a transient that has died out does not bias the tail estimate
+    k = np.arange(60)
+    r = 0.9 ** k + 5.0 * 0.2 ** k
+    assert abs(spectral_radius(r) - 0.9) < 1e-9
+    # too short or a zero residual: no estimate
+    assert spectral_radius([1.0, 0.5, 0.25]) is None
+    assert spectral_radius([1.0, 0.5, 0.25, 0.0]) is None
 
 
 def _artifact(tmp_path, nh=64, act=0, seed=0):

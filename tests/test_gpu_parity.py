@@ -221,6 +221,36 @@ def test_source_iteration_resume_from_saved_phi(api, ctx):
     assert rel(rest.cpu().numpy(), full.cpu().numpy()) <= 1e-10
 
 
+def test_source_iteration_history_matches_oracle_steps(api, ctx):
+    """The recorded residual and eps_S of every iteration equal the oracle's
+    after one step from the same iterate, and the effective spectral radius
+    they give lies below the largest scattering ratio."""
+    p = inputs.random_problem((5, 4, 4), 4, 2, seed=25, c_max=0.9)
+    print_case("source_iterate_history", name=p["name"], precision="fp64")
+    prob = gpu_problem(api, ctx, p, "fp64")
+    assert prob.si_history()[0].size == 0
+    phi, info = prob.source_iterate(tol=1e-11, max_iter=500)
+    r, e = prob.si_history()
+    assert info["converged"] and r.size == e.size == info["iters"]
+    assert r[-1] == info["resid"] and e[-1] == info["eps_s"]
+    om, w = oracle.lq_n(4)
+    ph, ref_r, ref_e = None, [], []
+    for _ in range(12):
+        out = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                    p["psi_inc"], tol=0.0, max_iter=1, phi0=ph)
+        ref_r.append(out["resid"])
+        ref_e.append(out["eps_s"])
+        ph = out["phi"]
+    np.testing.assert_allclose(r[:12], ref_r, rtol=1e-9)
+    np.testing.assert_allclose(e[:12], ref_e, rtol=1e-9)
+    rho = api.spectral_radius(r)
+    c = (p["sigma_s"] / p["sigma_t"]).max()
+    assert rho is not None and 0.0 < rho < c
+    # a second call replaces the history
+    prob.source_iterate(phi0=phi, tol=1e-11, max_iter=500)
+    assert prob.si_history()[0].size <= 2
+
+
 # ---------------------------------------------------------------------------
 # multigroup scattering (group-to-group matrix, P0)
 # ---------------------------------------------------------------------------
