@@ -81,6 +81,10 @@ def _load():
     lib.orc_pann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 6 + _pann + [_D, ctypes.c_double, ctypes.c_int, _I, _D, _D,
                                                  ctypes.c_int]
+    lib.orc_real_ylm.argtypes = [ctypes.c_int, _D, _D]
+    lib.orc_source_iterate_pl.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 3 + [ctypes.c_int] + [_D] * 5 + \
+        [ctypes.c_double, ctypes.c_int, _I, _D, _D, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -470,6 +474,55 @@ def pann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=N
 # ---------------------------------------------------------------------------
 # error metrics (Sec. 4)
 # ---------------------------------------------------------------------------
+
+def real_ylm(L, omega):
+    """Real orthonormal spherical harmonics Y[d][k], k = n^2 + n + m, n <= L,
+    at the unit directions omega [D, 3] (polar axis z, no (-1)^m phase)."""
+    lib = _load()
+    om = _f64(omega).reshape(-1, 3)
+    nm = (L + 1) ** 2
+    out = np.zeros((om.shape[0], nm))
+    for d in range(om.shape[0]):
+        row = np.zeros(nm)
+        _check(lib.orc_real_ylm(int(L), _p(np.ascontiguousarray(om[d])), _p(row)), "real_ylm")
+        out[d] = row
+    return out
+
+
+def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, tol=1e-8,
+                      max_iter=1000, phi0=None, mom0=None, nthreads=0):
+    """In-group P_L scattering source iteration (Eq. (T3)-(T8)).
+    sigma_sn [L+1, G, ncell], order 0 first; returns dict(phi [G, ncell, 8],
+    mom [(L+1)^2 - 1, G, ncell, 8] (the moments k = n^2 + n + m >= 1), iters,
+    resid, eps_s, converged)."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    sigma_sn = _f64(sigma_sn).reshape(-1, ng, ncell)
+    L = sigma_sn.shape[0] - 1
+    q = _f64(q, (ng, ncell))
+    inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
+    phi = np.zeros((ng, ncell, 8)) if phi0 is None else _f64(phi0, (ng, ncell, 8)).copy()
+    nm = (L + 1) ** 2
+    mom = np.zeros((nm - 1, ng, ncell, 8)) if mom0 is None else \
+        _f64(mom0, (nm - 1, ng, ncell, 8)).copy()
+    it = ctypes.c_int(0)
+    resid = ctypes.c_double(0)
+    eps = ctypes.c_double(0)
+    rc = lib.orc_source_iterate_pl(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                   _p(_f64(weight, (nd,))), _p(sigma_t), int(L), _p(sigma_sn),
+                                   _p(q), _p(inc), _p(phi), _p(mom), float(tol), int(max_iter),
+                                   ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps),
+                                   int(nthreads))
+    if rc not in (0, ORC_ENOTCONV):
+        _check(rc, "source_iterate_pl")
+    return dict(phi=phi, mom=mom, iters=it.value, resid=resid.value, eps_s=eps.value,
+                converged=(rc == 0))
+
 
 def cell_average(phi):
     """Cell average of a nodal trilinear field [G, ncell, 8] -> [G, ncell]."""

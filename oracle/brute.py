@@ -42,13 +42,18 @@ def _cell_id(c, n):
     return c[0] + n[0] * (c[1] + n[1] * c[2])
 
 
-def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None):
+def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None,
+             sigma_sn=None):
     """Dense (L - K) and right-hand side Q for unknowns psi[d][g][c][8].
 
     sigma_t, sigma_s, q: [G, ncell]; psi_inc [6]; extra_src [G, ncell, 8]
     optional nodal source (per steradian) added to q; sigma_gg [G, G, ncell]
     optional group-to-group scattering (from g' to g at [g', g]), which then
-    replaces the in-group sigma_s.  Returns (A, Q)."""
+    replaces the in-group sigma_s; sigma_sn [L, G, ncell] optional in-group
+    anisotropic Legendre moments of orders 1..L, coupling directions d and d'
+    through the kernel of Eq. (T3), sum_n (2n+1)/(4 pi) sigma_{s,n}
+    P_n(Omega_d . Omega_d') (Legendre polynomials of the scattering cosine,
+    not the spherical harmonics of the sweep's moments).  Returns (A, Q)."""
     nx, ny, nz, lx, ly, lz = mesh
     n = (nx, ny, nz)
     h = (lx / nx, ly / ny, lz / nz)
@@ -62,6 +67,14 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, 
     q = np.asarray(q, np.float64).reshape(ng, ncell)
     if sigma_gg is not None:
         sigma_gg = np.asarray(sigma_gg, np.float64).reshape(ng, ng, ncell)
+    aniso = None
+    if sigma_sn is not None:
+        sigma_sn = np.asarray(sigma_sn, np.float64).reshape(-1, ng, ncell)
+        cosines = np.clip(omega @ omega.T, -1.0, 1.0)
+        # aniso[n-1][d][d'] = (2n+1)/(4 pi) P_n(Omega_d . Omega_d')
+        aniso = np.stack([(2 * o + 1) / (4 * np.pi) *
+                          np.polynomial.legendre.legval(cosines, [0.0] * o + [1.0])
+                          for o in range(1, sigma_sn.shape[0] + 1)])
     N = nd * ng * ncell * 8
     A = np.zeros((N, N))
     Q = np.zeros(N)
@@ -110,12 +123,20 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, 
                     for d2 in range(nd):
                         cb = blk(d2, g2, ci)
                         A[r:r + 8, cb:cb + 8] -= sig / (4 * np.pi) * weight[d2] * M
+                if aniso is not None:
+                    for d2 in range(nd):
+                        k = float(np.dot(sigma_sn[:, g, ci], aniso[:, d, d2]))
+                        if k != 0.0:
+                            cb = blk(d2, g, ci)
+                            A[r:r + 8, cb:cb + 8] -= k * weight[d2] * M
     return A, Q
 
 
-def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None):
+def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None,
+          sigma_sn=None):
     """Returns (psi [D,G,ncell,8], phi [G,ncell,8]) of the dense global system."""
-    A, Q = assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src, sigma_gg)
+    A, Q = assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src, sigma_gg,
+                    sigma_sn)
     x = np.linalg.solve(A, Q)
     nx, ny, nz = mesh[:3]
     ncell = nx * ny * nz

@@ -11,8 +11,11 @@
  *
  * What it follows in the paper:
  *   - Sec. 2, Eq. (T1): steady mono-energetic transport, Omega.grad psi + sigma_t psi = Q.
- *   - Eq. (T2)-(T8), P0 (isotropic) part only: Q = q_ext + sigma_s/(4 pi) phi,
- *     phi = sum_d w_d psi_d.  Groups are decoupled (in-group scattering only).
+ *   - Eq. (T2)-(T8): Q = q_ext + sigma_s/(4 pi) phi, phi = sum_d w_d psi_d (P0,
+ *     in-group or with a group-to-group matrix), and the anisotropic in-group
+ *     P_L expansion, Q_d = q_ext + sum_{n,m} sigma_{s,n} Y_{n,m}(Omega_d)
+ *     phi_{n,m} with phi_{n,m} = sum_d w_d Y_{n,m}(Omega_d) psi_d (Eq. (T7),
+ *     (T8); real orthonormal spherical harmonics, orc_real_ylm).
  *   - Eq. (T9): trilinear nodal trial space on each hexahedron, 8 vertex nodes,
  *     local node n = ix + 2 iy + 4 iz.
  *   - The weak form below Eq. (T9): streaming by Green's theorem, element mass
@@ -507,6 +510,172 @@ int orc_source_iterate_gg(int nx, int ny, int nz, double lx, double ly, double l
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
                           nthreads, sigma_gg);
+}
+
+/* ------------------------------------------------------------------ */
+/* Anisotropic P_L scattering (Eq. (T3)-(T8))                           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Real orthonormal spherical harmonics up to order L (L <= 8) at the unit
+ * direction omega, polar axis z: mu = omega_z, azimuth phi = atan2(omega_y,
+ * omega_x).  Y[k], k = n^2 + n + m:
+ *   m = 0:  N_n0 P_n(mu)
+ *   m > 0:  sqrt(2) N_nm P_n^m(mu) cos(m phi)
+ *   m < 0:  sqrt(2) N_n|m| P_n^|m|(mu) sin(|m| phi)
+ * with N_nm = sqrt((2n+1)/(4 pi) (n-m)!/(n+m)!) and the associated Legendre
+ * functions P_n^m = (1 - mu^2)^(m/2) d^m/dmu^m P_n without the (-1)^m phase,
+ * from the standard recurrences in n at fixed m:
+ *   P_m^m = (2m-1)!! (1-mu^2)^(m/2),  P_{m+1}^m = (2m+1) mu P_m^m,
+ *   (n-m) P_n^m = (2n-1) mu P_{n-1}^m - (n+m-1) P_{n-2}^m.
+ * They satisfy the addition theorem sum_m Y_nm(a) Y_nm(b) = (2n+1)/(4 pi)
+ * P_n(a.b) behind Eq. (T4) (pinned in the tests).
+ */
+int orc_real_ylm(int L, const double omega[3], double *Y)
+{
+    if (L < 0 || L > 8) return ORC_EINVAL;
+    const double mu = omega[2];
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    const double az = atan2(omega[1], omega[0]);
+    for (int m = 0; m <= L; ++m) {
+        /* P_m^m */
+        double pmm = 1.0;
+        for (int i = 1; i <= m; ++i) pmm *= (2.0 * i - 1.0) * st;
+        double p_prev = 0.0, p_cur = pmm;
+        for (int n = m; n <= L; ++n) {
+            double p;
+            if (n == m) p = pmm;
+            else if (n == m + 1) p = (2.0 * m + 1.0) * mu * pmm;
+            else p = ((2.0 * n - 1.0) * mu * p_cur - (n + m - 1.0) * p_prev) / (double)(n - m);
+            if (n > m) { p_prev = p_cur; p_cur = p; }
+            /* (n-m)!/(n+m)! */
+            double ratio = 1.0;
+            for (int i = n - m + 1; i <= n + m; ++i) ratio /= (double)i;
+            const double N = sqrt((2.0 * n + 1.0) / (4.0 * ORC_PI) * ratio);
+            if (m == 0) {
+                Y[n * n + n] = N * p;
+            } else {
+                Y[n * n + n + m] = sqrt(2.0) * N * p * cos(m * az);
+                Y[n * n + n - m] = sqrt(2.0) * N * p * sin(m * az);
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * Source iteration with in-group P_L scattering, L >= 1.
+ *   sigma_sn [L+1][G][ncell]: the Legendre moments sigma_{s,n} of Eq. (T3),
+ *     order 0 first (the isotropic sigma_s);
+ *   phi [G][ncell][8]: scalar flux (= the moment phi_{0,0} / Y_00), initial
+ *     guess on entry, last iterate on exit;
+ *   mom [(L+1)^2 - 1][G][ncell][8]: the flux moments phi_{n,m} of Eq. (T8)
+ *     for k = n^2 + n + m >= 1, initial guess on entry, last iterate on exit.
+ * Iteration: Q_d = q + sigma_{s,0}/(4 pi) phi + sum_{k>=1} sigma_{s,n(k)}
+ * Y_k(Omega_d) mom_k, one sweep per (direction, group) with that source, then
+ * phi = sum_d w_d psi_d and mom_k = sum_d w_d Y_k(Omega_d) psi_d, accumulated
+ * in direction order.  Residual and eps_s on phi as in source_iterate.
+ */
+int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                          int nd, const double *omega, const double *weight,
+                          const double *sigma_t, int L, const double *sigma_sn, const double *q,
+                          const double psi_inc[6], double *phi, double *mom, double tol,
+                          int max_iter, int *iters, double *resid, double *eps_s, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || ng < 1 || nd < 1 || L < 1 || L > 8) return ORC_EINVAL;
+    orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
+    const long ncell = (long)nx * ny * nz;
+    const long nv = (long)ng * ncell;
+    const int nm = (L + 1) * (L + 1);
+    double M[64], G[3][64], Mf[6][64];
+    orc_element_matrices(m.h, M, G, Mf);
+    const int nt = set_threads(nthreads);
+    double *Y = (double *)malloc((size_t)nd * nm * sizeof(double));
+    double *buf = (double *)malloc((size_t)nt * ncell * 8 * sizeof(double));
+    double *src = (double *)malloc((size_t)nt * ncell * 8 * sizeof(double));
+    double *phin = (double *)malloc((size_t)nv * 8 * sizeof(double));
+    double *momn = (double *)malloc((size_t)(nm - 1) * nv * 8 * sizeof(double));
+    if (!Y || !buf || !src || !phin || !momn) {
+        free(Y); free(buf); free(src); free(phin); free(momn);
+        return ORC_ENOMEM;
+    }
+    for (int d = 0; d < nd; ++d) orc_real_ylm(L, omega + 3 * d, Y + (long)d * nm);
+    int it = 0, err = ORC_OK;
+    double r = INFINITY, es = INFINITY;
+    const long nunits = (long)nd * ng;
+    while (it < max_iter && !err) {
+        memset(phin, 0, (size_t)nv * 8 * sizeof(double));
+        memset(momn, 0, (size_t)(nm - 1) * nv * 8 * sizeof(double));
+        for (long u0 = 0; u0 < nunits && !err; u0 += nt) {
+            const long nb = (nunits - u0 < nt) ? nunits - u0 : nt;
+#pragma omp parallel for schedule(static, 1)
+            for (long t = 0; t < nb; ++t) {
+                const long u = u0 + t;
+                const int d = (int)(u / ng), g = (int)(u % ng);
+                const double *yd = Y + (long)d * nm;
+                double *S = src + t * ncell * 8;
+                for (long c = 0; c < ncell; ++c) {
+                    const long gc = (long)g * ncell + c;
+                    for (int n = 0; n < 8; ++n) {
+                        double v = q[gc] + sigma_sn[gc] / (4.0 * ORC_PI) * phi[gc * 8 + n];
+                        for (int o = 1; o <= L; ++o)
+                            for (int mm = -o; mm <= o; ++mm) {
+                                const int k = o * o + o + mm;
+                                v += sigma_sn[(long)o * nv + gc] * yd[k] *
+                                     mom[((long)(k - 1) * nv + gc) * 8 + n];
+                            }
+                        S[c * 8 + n] = v;
+                    }
+                }
+                int rc = sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, S, psi_inc, M, G, Mf,
+                                   NULL, buf + t * ncell * 8);
+                if (rc) {
+#pragma omp critical
+                    err = rc;
+                }
+            }
+            if (err) break;
+            for (long t = 0; t < nb; ++t) {
+                const long u = u0 + t;
+                const int d = (int)(u / ng), g = (int)(u % ng);
+                const double *yd = Y + (long)d * nm;
+                for (long c = 0; c < ncell; ++c) {
+                    const long gc = (long)g * ncell + c;
+                    const double *p = buf + (t * ncell + c) * 8;
+                    for (int n = 0; n < 8; ++n) {
+                        phin[gc * 8 + n] += weight[d] * p[n];
+                        for (int k = 1; k < nm; ++k)
+                            momn[((long)(k - 1) * nv + gc) * 8 + n] += weight[d] * yd[k] * p[n];
+                    }
+                }
+            }
+        }
+        if (err) break;
+        double dmax = 0.0, fmax = 0.0, esum = 0.0;
+        for (long i = 0; i < nv * 8; ++i) {
+            const double dd = fabs(phin[i] - phi[i]);
+            if (dd > dmax) dmax = dd;
+            if (fabs(phin[i]) > fmax) fmax = fabs(phin[i]);
+        }
+        for (long gc = 0; gc < nv; ++gc) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 8; ++k) { a += phin[gc * 8 + k]; b += phi[gc * 8 + k]; }
+            a /= 8.0; b /= 8.0;
+            esum += (a != 0.0) ? fabs(a - b) / fabs(a) : (b != 0.0 ? 1.0 : 0.0);
+        }
+        r = fmax > 0.0 ? dmax / fmax : 0.0;
+        es = esum / (double)nv;
+        memcpy(phi, phin, (size_t)nv * 8 * sizeof(double));
+        memcpy(mom, momn, (size_t)(nm - 1) * nv * 8 * sizeof(double));
+        ++it;
+        if (r < tol) break;
+    }
+    free(Y); free(buf); free(src); free(phin); free(momn);
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (eps_s) *eps_s = es;
+    if (err) return err;
+    return (r < tol) ? ORC_OK : ORC_ENOTCONV;
 }
 
 /* ------------------------------------------------------------------ */

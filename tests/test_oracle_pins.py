@@ -702,3 +702,109 @@ def test_multigroup_adjoint_matches_dense_transpose():
     _, phi_b = brute.solve(mesh, om, w, st, zero, q, inc, sigma_gg=gg)
     _, Q = brute.assemble(mesh, om, w, st, zero, q, inc, sigma_gg=gg)
     assert abs((g * phi_b).sum() - lam.reshape(-1) @ Q) < 1e-13 * abs((g * phi_b).sum())
+
+
+# ---------------------------------------------------------------------------
+# anisotropic P_L scattering (Eq. (T3)-(T8))
+# ---------------------------------------------------------------------------
+
+def _unit_vectors(rng, n):
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def test_real_ylm_low_orders_are_the_cartesian_forms():
+    # textbook Cartesian forms of the real orthonormal harmonics, no (-1)^m phase
+    rng = np.random.default_rng(90)
+    om = _unit_vectors(rng, 7)
+    Y = oracle.real_ylm(2, om)
+    x, y, z = om.T
+    c1 = np.sqrt(3 / (4 * np.pi))
+    c2 = np.sqrt(15 / (4 * np.pi))
+    ref = np.stack([np.full(7, 0.5 / np.sqrt(np.pi)), c1 * y, c1 * z, c1 * x, c2 * x * y,
+                    c2 * y * z, np.sqrt(5 / (16 * np.pi)) * (3 * z * z - 1), c2 * x * z,
+                    np.sqrt(15 / (16 * np.pi)) * (x * x - y * y)], axis=1)
+    assert np.abs(Y - ref).max() < 1e-14
+
+
+def test_real_ylm_orthonormal_on_the_sphere():
+    # product rule: Gauss-Legendre in mu (exact to degree 23) times the
+    # midpoint rule in azimuth (exact for trigonometric degree < 24)
+    L = 5
+    mu, wm = np.polynomial.legendre.leggauss(12)
+    az = (np.arange(24) + 0.5) * (2 * np.pi / 24)
+    s = np.sqrt(1 - mu ** 2)
+    om = np.array([[si * np.cos(a), si * np.sin(a), m] for m, si in zip(mu, s) for a in az])
+    wt = np.array([wi * 2 * np.pi / 24 for wi in wm for _ in az])
+    Y = oracle.real_ylm(L, om)
+    G = (Y * wt[:, None]).T @ Y
+    assert np.abs(G - np.eye((L + 1) ** 2)).max() < 1e-13
+
+
+def test_real_ylm_addition_theorem():
+    # sum_m Y_nm(a) Y_nm(b) = (2n+1)/(4 pi) P_n(a.b), the identity behind Eq. (T4)
+    rng = np.random.default_rng(91)
+    a = _unit_vectors(rng, 20)
+    b = _unit_vectors(rng, 20)
+    L = 6
+    Ya, Yb = oracle.real_ylm(L, a), oracle.real_ylm(L, b)
+    cos = np.sum(a * b, axis=1)
+    for n in range(L + 1):
+        ks = slice(n * n, (n + 1) ** 2)
+        lhs = np.sum(Ya[:, ks] * Yb[:, ks], axis=1)
+        rhs = (2 * n + 1) / (4 * np.pi) * np.polynomial.legendre.legval(cos, [0] * n + [1])
+        assert np.abs(lhs - rhs).max() < 1e-13
+
+
+def _pl_case(seed, L=2, ng=2):
+    rng = np.random.default_rng(seed)
+    mesh = (2, 2, 1, 0.8, 0.6, 0.5)
+    nc = 4
+    om, w = oracle.lq_n(4)
+    st = rng.uniform(1.0, 3.0, (ng, nc))
+    ratios = np.array([0.7, 0.4, 0.2, 0.1][:L + 1])
+    sn = ratios[:, None, None] * st[None] * rng.uniform(0.8, 1.0, (L + 1, ng, nc))
+    q = rng.uniform(0.2, 1.0, (ng, nc))
+    inc = rng.uniform(0.0, 1.0, 6)
+    return mesh, om, w, st, sn, q, inc
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_pl_source_iteration_equals_dense_global_solve(L):
+    # the moment form of the scattering source (spherical harmonics) against
+    # the global system coupled through Legendre polynomials of the cosine
+    mesh, om, w, st, sn, q, inc = _pl_case(92 + L, L=L)
+    r = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-15, max_iter=3000)
+    assert r["converged"]
+    psi_b, phi_b = brute.solve(mesh, om, w, st, sn[0], q, inc, sigma_sn=sn[1:])
+    assert np.abs(r["phi"] - phi_b).max() <= 1e-12 * np.abs(phi_b).max()
+    Y = oracle.real_ylm(L, om)
+    mom_b = np.einsum("d,dk,dgcn->kgcn", w, Y[:, 1:], psi_b)
+    assert np.abs(r["mom"] - mom_b).max() <= 1e-12 * np.abs(phi_b).max()
+
+
+def test_pl_with_zero_higher_orders_is_isotropic_iteration():
+    mesh, om, w, st, sn, q, inc = _pl_case(96, L=2)
+    sn[1:] = 0.0
+    a = oracle.source_iterate(mesh, om, w, st, sn[0], q, inc, tol=1e-14, max_iter=3000)
+    b = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-14, max_iter=3000)
+    assert a["iters"] == b["iters"]
+    assert np.abs(a["phi"] - b["phi"]).max() <= 1e-15 * np.abs(a["phi"]).max()
+
+
+def test_pl_constant_solution():
+    # uniform medium with inflow c and q = (sigma_t - sigma_s0) c: psi == c;
+    # the level-symmetric set integrates the harmonics of orders 1 and 2
+    # exactly, so every moment k >= 1 of the constant flux vanishes and the
+    # anisotropic orders do not disturb it
+    mesh = (3, 2, 2, 0.9, 0.6, 0.6)
+    nc = 12
+    om, w = oracle.lq_n(4)
+    cval = 0.7
+    st = np.full((1, nc), 2.0)
+    sn = np.stack([np.full((1, nc), v) for v in (1.2, 0.6, 0.3)])
+    q = cval * (st - sn[0])
+    r = oracle.source_iterate_pl(mesh, om, w, st, sn, q, np.full(6, cval), tol=1e-15,
+                                 max_iter=3000)
+    assert np.abs(r["phi"] / (4 * np.pi) - cval).max() < 1e-12
+    assert np.abs(r["mom"]).max() < 1e-12
