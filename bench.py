@@ -196,6 +196,7 @@ def main():
     fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
     ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann, args.ann_paper)
     adj = None if args.skip_extras else adjoint_box(api, ctx)
+    aniso = None if args.skip_extras else anisotropic_steps(api, ctx, p)
     batch = None if args.skip_extras else uneven_batch(api, ctx, args.ann)
 
     cpu = None
@@ -215,6 +216,7 @@ def main():
         "fp64_ge": fp64,
         "ann_vs_ge": ann,
         "adjoint": adj,
+        "anisotropic": aniso,
         "batch": batch,
     }
     print(json.dumps(out), flush=True)
@@ -435,6 +437,33 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
                               "237/110 at 100^3 S2-S8 and 15/9, 42/20, 121/58 at 10^3, 25^3, "
                               "50^3 S8; effective spectral radius 0.957 (GE) / 0.859 (ANN); "
                               "overall acceleration on Problem 4 about 12")}
+
+
+def anisotropic_steps(api, ctx, p, iters=10):
+    """Source iterations of the benchmark workload with in-group P_L
+    scattering (sigma_{s,n} = (0.5, 0.25, 0.12)_n sigma_s), L = 1 and 3, FP32
+    GE: ms per iteration against the isotropic iteration."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    om, w = api.quadrature_ls(p["order"])
+    out = {"workload": p["name"], "iterations": iters}
+    for L in (0, 1, 3):
+        prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+        prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+        prob.set_inflow(p["psi_inc"])
+        prob.autotune()
+        if L:
+            prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], L, seed=7))
+        prob.source_iterate(tol=0.0, max_iter=2, allow_notconv=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.source_iterate(tol=0.0, max_iter=iters, allow_notconv=True)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / iters
+        out[f"P{L}_ms_per_iteration"] = ms
+        log(f"anisotropic scattering P{L}: {ms:.3f} ms per source iteration")
+        prob.close()
+    return out
 
 
 def adjoint_box(api, ctx, n=32, cells=8, h=1e-6):

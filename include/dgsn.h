@@ -143,6 +143,45 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
  */
 int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *stream);
 
+/*
+ * Anisotropic in-group scattering of order L (Eq. (T3)-(T8)): the scattering
+ * kernel sum_{n<=L} (2n+1)/(4 pi) sigma_{s,n} P_n(Omega'.Omega), expanded in
+ * real orthonormal spherical harmonics Y_k, k = n^2 + n + m (dgsn_real_ylm).
+ * Source iteration then uses for direction d
+ *   Q_d = q + sigma_s/(4 pi) phi + sum_{k>=1} sigma_{s,n(k)} Y_k(Omega_d) phi_k,
+ *   phi_k = sum_d w_d Y_k(Omega_d) psi_d,
+ * with sigma_s (order 0) from dgsn_problem_set_materials.  order: 0..3 (0
+ * removes the anisotropic orders and frees their buffers).  sigma_sn: device
+ * [order][G][Nz*Ny*Nx] in the problem precision, orders 1..order (copied
+ * asynchronously on the stream; the caller keeps ownership).  The moments
+ * start from zero in every dgsn_source_iterate call (a resumed run restarts
+ * them).  Single sweeps (dgsn_sweep, batches), the autotuner and the adjoint
+ * take isotropic sources only: dgsn_adjoint_solve, and dgsn_source_iterate
+ * with a network solver or with store_psi, return DGSN_EUNSUPPORTED while an
+ * order is set, and so does this call while a group-to-group matrix
+ * is set (and dgsn_problem_set_scattering while an order is set).
+ * DGSN_ENOMEM if the moment buffers (9 (L+1)^2 G*cells*8 reals) cannot be
+ * allocated.
+ */
+int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream);
+
+/*
+ * Flux moments phi_k, k = 1 .. (L+1)^2 - 1, of the last source iteration's
+ * final sweep (Eq. (T8) for n >= 1): mom is a device array
+ * [(L+1)^2 - 1][G][Nz*Ny*Nx][8] in the problem precision (copied on the
+ * stream).  DGSN_EINVAL without anisotropic scattering.
+ */
+int dgsn_problem_get_moments(const dgsn_problem *p, void *mom, void *stream);
+
+/*
+ * Real orthonormal spherical harmonics of the scattering expansion (the Y of
+ * Eq. (T4), real form), host only: Y[i][k], k = n^2 + n + m for n <= order
+ * (order 0..3) and m = -n..n, at the unit directions omega[i] (host [n][3]).
+ * Polar axis z, no (-1)^m phase: Y_{1,-1}, Y_{1,0}, Y_{1,1} = sqrt(3/(4 pi))
+ * (y, z, x); m < 0 are the sine-type harmonics.
+ */
+int dgsn_real_ylm(int order, const double *omega, int n, double *Y);
+
 /* Boundary inflow psi_inc per domain face (host [6]); applied to every
    direction entering through that face (Eq. (TBC)); 0 = vacuum. */
 int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);

@@ -146,6 +146,17 @@ def local_solve(ctx, x):
     return y
 
 
+def real_ylm(order, omega):
+    """The library's real orthonormal spherical harmonics [n, (order+1)^2]
+    at unit directions omega [n, 3] (host computation)."""
+    om = np.ascontiguousarray(np.asarray(omega, np.float64).reshape(-1, 3))
+    nm = (order + 1) ** 2
+    out = np.zeros((om.shape[0], nm))
+    _lib.check(_lib.load().dgsn_real_ylm(int(order), om.ctypes.data_as(_lib._PD), om.shape[0],
+                                         out.ctypes.data_as(_lib._PD)))
+    return out
+
+
 def spectral_radius(resid, tail=0.5):
     """Effective spectral radius of a source iteration from its residual
     history: the geometric mean ratio of successive residuals over the last
@@ -205,6 +216,35 @@ class Problem:
                                                            _stream(self.ctx.device)))
         torch.cuda.current_stream(self.ctx.device).synchronize()
 
+    def set_anisotropy(self, sigma_sn):
+        """In-group anisotropic scattering: sigma_sn [L, G, ncell], the Legendre
+        moments of orders 1..L (L <= 3); None removes them."""
+        lib = _lib.load()
+        if sigma_sn is None:
+            _lib.check(lib.dgsn_problem_set_anisotropy(self._h, 0, None,
+                                                       _stream(self.ctx.device)))
+            self.pl_order = 0
+            return
+        size = int(np.prod(tuple(sigma_sn.shape)))
+        L = size // (self.groups * self.ncell)
+        if L < 1 or L * self.groups * self.ncell != size:
+            raise ValueError("sigma_sn must hold [L, G, ncell] values")
+        m = self._dev(sigma_sn, (L, self.groups, self.ncell))
+        _lib.check(lib.dgsn_problem_set_anisotropy(self._h, L, _ptr(m),
+                                                   _stream(self.ctx.device)))
+        torch.cuda.current_stream(self.ctx.device).synchronize()
+        self.pl_order = L
+
+    def moments(self):
+        """Flux moments k = 1 .. (L+1)^2 - 1 of the last source iteration,
+        [(L+1)^2 - 1, G, ncell, 8] on the device."""
+        nm = (getattr(self, "pl_order", 0) + 1) ** 2
+        out = torch.empty((max(nm - 1, 1), self.groups, self.ncell, 8), dtype=self.dtype,
+                          device=self.ctx.device)
+        _lib.check(_lib.load().dgsn_problem_get_moments(self._h, _ptr(out),
+                                                        _stream(self.ctx.device)))
+        return out
+
     def set_inflow(self, psi_inc):
         arr = np.ascontiguousarray(np.asarray(psi_inc, np.float64).reshape(6))
         _lib.check(_lib.load().dgsn_problem_set_inflow(self._h, arr.ctypes.data_as(_lib._PD)))
@@ -239,7 +279,7 @@ class Problem:
 
     def set_schedule(self, schedule, poll_limit=0):
         """'planes' (one launch per hyperplane) or 'dataflow' (one launch per
-        sweep, device counters between hyperplanes; GE solvers)."""
+        sweep, device counters between hyperplanes; every solver)."""
         sc = {"planes": _lib.DGSN_SCHED_PLANES, "dataflow": _lib.DGSN_SCHED_DATAFLOW}[schedule]
         _lib.check(_lib.load().dgsn_problem_set_schedule(self._h, sc, int(poll_limit)))
 

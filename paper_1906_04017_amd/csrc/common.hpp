@@ -40,9 +40,16 @@ constexpr int kDirW = 67;
 constexpr int kDirK = 68;
 constexpr int kMaxHidden = 256;
 constexpr int kMaxTile = 3;       // largest tile edge of the sweep
+// anisotropic scattering: per direction the real harmonics Y_k(Omega),
+// k = 1 .. (L+1)^2 - 1 at index k - 1, orders L <= kMaxPlOrder
+constexpr int kYlmStride = 16;
+constexpr int kMaxPlOrder = 3;
 
 // ---- host-side quadrature ---------------------------------------------------
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
+// real orthonormal spherical harmonics Y_k, k = n^2 + n + m, n <= L <= 3, of
+// the unit direction om (Cartesian forms; polar axis z, no (-1)^m phase)
+void real_ylm(int L, const double om[3], double *Y);
 
 const void *ann_device_params(const dgsn_ann *a);
 // Per-octant weight images of a paper-form network for a problem with cell
@@ -104,6 +111,8 @@ struct dgsn_problem {
 
     std::vector<int> dir_user;       // octant-sorted slot -> user direction index
     std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64
+    std::vector<double> omega_host;  // [8][Do][3] the slot directions
+    int pl_order = 0;                // anisotropic in-group scattering order L (0: none)
     std::vector<int> plane_off;      // [n_planes + 1]
     // tile hyperplane schedules for B x B x B tiles (B = 2, 3; index B):
     // packed tile coordinates, tile-hyperplane major (B = 1 is the cell
@@ -127,6 +136,10 @@ struct dgsn_problem {
     dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major
     dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
     dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
+    dgsn::DevBuf sigma_sn;                   // [L][G][ncell] Legendre moments of orders 1..L
+    dgsn::DevBuf d_ylm;                      // [8][Do][kYlmStride] harmonics of the slot directions
+    dgsn::DevBuf mom_oct;                    // [8][nm-1][G][ncell][8] per-octant flux moments
+    dgsn::DevBuf mom, msrc;                  // [nm-1][G][ncell][8] moments, sigma_{s,n} x moments
     dgsn::DevBuf src;                         // [G][ncell][8]
     dgsn::DevBuf phi_oct;                     // [8][G][ncell][8]
     dgsn::DevBuf front_x, front_y, front_z;   // [8][..][..][4][Do*G]

@@ -72,8 +72,8 @@ __global__ __launch_bounds__(256) void flow_reset(unsigned *sync, int n)
         if (i != kFlowError) sync[i] = 0u;
 }
 
-template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
-__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kMom = false>
+__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
 {
     // 256 lanes as in the hyperplane kernel; A.cells is the whole tile list
     // of the schedule
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_
     bool tvalid;
     const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
-    tile_body<Real, Form, B, kStorePsi, kAdjoint, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
-                                                        l.ok, L, nullptr);
+    tile_body<Real, Form, B, kStorePsi, kAdjoint, true, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
+                                                              (int)o, l.ok, L, nullptr);
     flow_finish(F, tid, o, t);
 }
 
@@ -126,7 +126,10 @@ template <typename Real, int Form, int B>
 void launch_flow_form(const PlaneArgs<Real> &A, const FlowArgs &F, bool store_psi, bool adjoint,
                       dim3 grid, dim3 block, hipStream_t s)
 {
-    if (adjoint)
+    if (A.nmom > 1)
+        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, true>), grid, block, 0, s,
+                           A, F);
+    else if (adjoint)
         hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true>), grid, block, 0, s, A, F);
     else if (store_psi)
         hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false>), grid, block, 0, s, A, F);
@@ -185,6 +188,9 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
     const dim3 block(256);
     if ((form == kFormAnnPaper || form == kFormAnn) && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the network solvers run FP32 forward sweeps");
+    if (A.nmom > 1 && (form == kFormAnnPaper || form == kFormAnn || store_psi || adjoint))
+        return set_error(DGSN_EUNSUPPORTED,
+                         "anisotropic sweeps are forward GE sweeps without a psi store");
     for (unsigned done = 0; done < F.units_o; done += kFlowMaxGroupsPerOctant) {
         const dim3 grid(8 * std::min(F.units_o - done, kFlowMaxGroupsPerOctant));
         if (form == kFormDense) {

@@ -39,6 +39,14 @@ struct PlaneArgs {
     Real hh;                   // cube root of the cell volume (ANN features)
     const void *ann_params;    // device ANN operand images (ANN solver)
     Real inc[8][3];            // inflow value per octant slot and canonical axis
+    // anisotropic in-group scattering (source iteration only; nmom <= 1:
+    // isotropic): nmom = (L+1)^2 moments, of which k >= 1 enter the source
+    // as sum_k Y_k(Omega_d) msrc_k and leave the sweep as the per-octant
+    // moments sum_{d in octant} w_d Y_k(Omega_d) psi_d
+    uint32_t nmom;
+    const Real *ylm;           // [8][Do][kYlmStride]
+    const Real *msrc;          // [nmom-1][G][ncell][8] sigma_{s,n(k)} phi_k
+    Real *mom_oct;             // [8][nmom-1][G][ncell][8]
 };
 
 // Dataflow schedule of a sweep: one launch processes every step.  Workgroup
@@ -105,8 +113,9 @@ constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector A
 // FP64 single-cell mass-inverse kernel would take 176 registers and run at 2
 // waves per SIMD; held to 168 it runs at 3 with no spills.  The larger FP64
 // tiles and the dense form would spill, so they keep the compiler's choice.
-template <typename Real, int Form, int B>
-constexpr int kMinWavesPerSimd = (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv) ? 3 : 1;
+template <typename Real, int Form, int B, bool kMom = false>
+constexpr int kMinWavesPerSimd =
+    (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv && !kMom) ? 3 : 1;
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 
@@ -130,6 +139,11 @@ template <typename Real>
 int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Real *q_nodal,
                            const Real *sigma_gg, const Real *phi, Real *src, bool transpose,
                            hipStream_t s);
+// flux moments of anisotropic scattering: mom = sum over octants of mom_oct,
+// msrc = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k))
+template <typename Real>
+int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
+                          Real *mom, Real *msrc, hipStream_t s);
 template <typename Real>
 int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, hipStream_t s);
 

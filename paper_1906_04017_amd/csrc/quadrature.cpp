@@ -180,3 +180,39 @@ int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &
 }
 
 }  // namespace dgsn
+
+namespace dgsn {
+
+// Real orthonormal spherical harmonics through order 3 in Cartesian form:
+// the normalised harmonic polynomials of degree n restricted to the unit
+// sphere, ordered k = n^2 + n + m (m < 0: the sine-type harmonics).
+void real_ylm(int L, const double om[3], double *Y)
+{
+    const double x = om[0], y = om[1], z = om[2];
+    const double pi = 3.14159265358979323846;
+    Y[0] = std::sqrt(1.0 / (4.0 * pi));
+    if (L < 1) return;
+    const double c1 = std::sqrt(3.0 / (4.0 * pi));
+    Y[1] = c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = c1 * x;
+    if (L < 2) return;
+    const double c2 = std::sqrt(15.0 / (4.0 * pi));
+    Y[4] = c2 * x * y;
+    Y[5] = c2 * y * z;
+    Y[6] = std::sqrt(5.0 / (16.0 * pi)) * (3.0 * z * z - 1.0);
+    Y[7] = c2 * x * z;
+    Y[8] = std::sqrt(15.0 / (16.0 * pi)) * (x * x - y * y);
+    if (L < 3) return;
+    const double c33 = std::sqrt(35.0 / (32.0 * pi));
+    const double c31 = std::sqrt(21.0 / (32.0 * pi));
+    Y[9] = c33 * y * (3.0 * x * x - y * y);
+    Y[10] = std::sqrt(105.0 / (4.0 * pi)) * x * y * z;
+    Y[11] = c31 * y * (5.0 * z * z - 1.0);
+    Y[12] = std::sqrt(7.0 / (16.0 * pi)) * z * (5.0 * z * z - 3.0);
+    Y[13] = c31 * x * (5.0 * z * z - 1.0);
+    Y[14] = std::sqrt(105.0 / (16.0 * pi)) * z * (x * x - y * y);
+    Y[15] = c33 * x * (x * x - 3.0 * y * y);
+}
+
+}  // namespace dgsn

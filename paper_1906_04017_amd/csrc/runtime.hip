@@ -278,10 +278,17 @@ int flow_prepare(dgsn_problem *p)
 
 template <typename Real>
 int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Real *grad_oct,
-              hipStream_t s)
+              hipStream_t s, bool moments = false)
 {
     PlaneArgs<Real> A = plane_args<Real>(p, src, adjoint);
     A.grad_oct = grad_oct;
+    if (moments && p->pl_order > 0) {
+        // anisotropic scattering inside source iteration
+        A.nmom = (uint32_t)((p->pl_order + 1) * (p->pl_order + 1));
+        A.ylm = static_cast<const Real *>(p->d_ylm.ptr);
+        A.msrc = static_cast<const Real *>(p->msrc.ptr);
+        A.mom_oct = static_cast<Real *>(p->mom_oct.ptr);
+    }
     const bool anyann = p->solver == DGSN_ANN && !adjoint;
     if (anyann) {
         if (!p->ann) return set_error(DGSN_EINVAL, "solver is DGSN_ANN but no ANN is attached");
@@ -417,9 +424,27 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     const bool fp32 = p->precision == DGSN_FP32;
     p->si_resid.clear();
     p->si_eps.clear();
+    const bool pl = p->pl_order > 0;
+    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
+    if (pl && p->solver == DGSN_ANN)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "anisotropic scattering is available with the GE solvers");
+    if (pl && p->store_psi)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "anisotropic scattering does not store the angular flux");
+    if (pl) {
+        // the anisotropic moments start from zero
+        DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
+        DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    }
     while (it < max_iter) {
-        DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
+        DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s, pl));
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        if (pl)
+            DGSN_TRY(launch_reduce_moments<Real>(
+                nv, nm, static_cast<const Real *>(p->mom_oct.ptr),
+                static_cast<const Real *>(p->sigma_sn.ptr), static_cast<Real *>(p->mom.ptr),
+                static_cast<Real *>(p->msrc.ptr), s));
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G,
                                                   static_cast<const Real *>(p->q.ptr), nullptr,
@@ -734,6 +759,7 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     // directions sorted by octant, user order inside an octant
     p->dir_user.assign(p->D, -1);
     p->dir_host.assign((size_t)8 * p->Do * kDirStride, 0.0);
+    p->omega_host.assign((size_t)8 * p->Do * 3, 0.0);
     int fill[8] = {0};
     for (int u = 0; u < p->D; ++u) {
         const double *om = d->omega + 3 * u;
@@ -743,6 +769,7 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
         double kappa[3];
         for (int a = 0; a < 3; ++a) kappa[a] = std::fabs(om[a]) / p->h[a];
         double *e = &p->dir_host[(size_t)slot * kDirStride];
+        for (int a = 0; a < 3; ++a) p->omega_host[(size_t)slot * 3 + a] = om[a];
         streaming_matrix(kappa, e);
         for (int a = 0; a < 3; ++a) {
             e[kDirK36 + a] = kappa[a] / 36.0;
@@ -873,10 +900,86 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
         p->sigma_gg.release();
         return DGSN_OK;
     }
+    if (p->pl_order > 0)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "a group-to-group matrix and anisotropic scattering are exclusive");
     const size_t bytes = (size_t)p->G * p->G * p->ncell * p->real_size;
     if (p->sigma_gg.bytes != bytes) DGSN_TRY(p->sigma_gg.alloc(bytes));
     DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, sigma_gg, bytes, hipMemcpyDeviceToDevice,
                             as_stream(stream)));
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (order < 0 || order > kMaxPlOrder)
+        return set_error(DGSN_EINVAL, "scattering order %d is outside 0..%d", order, kMaxPlOrder);
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    if (order == 0) {
+        p->pl_order = 0;
+        p->sigma_sn.release();
+        p->d_ylm.release();
+        p->mom_oct.release();
+        p->mom.release();
+        p->msrc.release();
+        return DGSN_OK;
+    }
+    if (!sigma_sn) return set_error(DGSN_EINVAL, "sigma_sn is NULL");
+    if (p->sigma_gg.ptr)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "a group-to-group matrix and anisotropic scattering are exclusive");
+    const int nm = (order + 1) * (order + 1);
+    const size_t nv = (size_t)p->G * p->ncell;
+    std::vector<double> y((size_t)8 * p->Do * kYlmStride, 0.0);
+    for (int slot = 0; slot < 8 * p->Do; ++slot) {
+        double all[kYlmStride];
+        real_ylm(order, &p->omega_host[(size_t)slot * 3], all);
+        for (int k = 1; k < nm; ++k) y[(size_t)slot * kYlmStride + k - 1] = all[k];
+    }
+    DGSN_TRY(p->precision == DGSN_FP64 ? upload_real<double>(p->d_ylm, y)
+                                       : upload_real<float>(p->d_ylm, y));
+    const size_t mbytes = (size_t)(nm - 1) * nv * 8 * p->real_size;
+    if (p->mom.bytes != mbytes) {
+        DGSN_TRY(p->mom.alloc(mbytes));
+        DGSN_TRY(p->msrc.alloc(mbytes));
+        DGSN_TRY(p->mom_oct.alloc(8 * mbytes));
+    }
+    const size_t sbytes = (size_t)order * nv * p->real_size;
+    if (p->sigma_sn.bytes != sbytes) DGSN_TRY(p->sigma_sn.alloc(sbytes));
+    hipStream_t s = as_stream(stream);
+    DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, sigma_sn, sbytes, hipMemcpyDeviceToDevice, s));
+    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, mbytes, s));
+    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, mbytes, s));
+    p->pl_order = order;
+    return DGSN_OK;
+}
+
+int dgsn_problem_get_moments(const dgsn_problem *p, void *mom, void *stream)
+{
+    clear_error();
+    if (!p || !mom) return set_error(DGSN_EINVAL, "problem and mom must be set");
+    if (p->pl_order == 0)
+        return set_error(DGSN_EINVAL, "the problem has no anisotropic scattering");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    DGSN_HIP(hipMemcpyAsync(mom, p->mom.ptr, p->mom.bytes, hipMemcpyDeviceToDevice,
+                            as_stream(stream)));
+    return DGSN_OK;
+}
+
+int dgsn_real_ylm(int order, const double *omega, int n, double *Y)
+{
+    clear_error();
+    if (order < 0 || order > kMaxPlOrder)
+        return set_error(DGSN_EINVAL, "order %d is outside 0..%d", order, kMaxPlOrder);
+    if (n < 0 || (n > 0 && (!omega || !Y))) return set_error(DGSN_EINVAL, "bad arguments");
+    const int nm = (order + 1) * (order + 1);
+    for (int i = 0; i < n; ++i) {
+        double all[kYlmStride];
+        real_ylm(order, omega + 3 * i, all);
+        for (int k = 0; k < nm; ++k) Y[(size_t)i * nm + k] = all[k];
+    }
     return DGSN_OK;
 }
 
@@ -1041,6 +1144,8 @@ int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, d
         return set_error(DGSN_EINVAL, "the adjoint needs a problem created with store_psi = 1");
     if (p->solver == DGSN_ANN)
         return set_error(DGSN_EUNSUPPORTED, "the adjoint is defined for the GE solvers");
+    if (p->pl_order > 0)
+        return set_error(DGSN_EUNSUPPORTED, "the adjoint has isotropic scattering only");
     if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     return p->precision == DGSN_FP64

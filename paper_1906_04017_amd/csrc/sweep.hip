@@ -23,8 +23,8 @@ namespace dgsn {
 
 namespace {
 
-template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint>
-__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_tile_ge(PlaneArgs<Real> A)
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kMom = false>
+__global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void sweep_tile_ge(PlaneArgs<Real> A)
 {
     // 256 lanes: (direction, group, tile slot) segments, grid = (tile blocks, octant)
     __shared__ TileLds<Real> L;
@@ -33,8 +33,8 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B>)) void sweep_
     bool tvalid;
     const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
-    tile_body<Real, Form, B, kStorePsi, kAdjoint>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
-                                                  l.ok, L, nullptr);
+    tile_body<Real, Form, B, kStorePsi, kAdjoint, false, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
+                                                               blockIdx.y, l.ok, L, nullptr);
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).
@@ -192,6 +192,30 @@ __global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
     }
 }
 
+// Flux moments of anisotropic scattering: one thread per (moment, group,
+// cell, node); the octant partials are summed in octant order, and the
+// source moment is sigma_{s,n} times the moment, n the order of moment k.
+template <typename Real>
+__global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
+                                                      const Real *__restrict__ mom_oct,
+                                                      const Real *__restrict__ sigma_sn,
+                                                      Real *__restrict__ mom,
+                                                      Real *__restrict__ msrc)
+{
+    const long long per = nv * 8;
+    const long long total = (long long)(nm - 1) * per;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int k = (int)(e / per) + 1;
+        const long long r = e - (long long)(k - 1) * per;
+        Real s = 0;
+        for (int o = 0; o < 8; ++o) s += mom_oct[(long long)o * total + e];
+        const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
+        mom[e] = s;
+        msrc[e] = sigma_sn[(long long)(order - 1) * nv + (r >> 3)] * s;
+    }
+}
+
 // adjoint load: gl = M3^{-1} g / V (so that M3 gl = g / V)
 template <typename Real>
 __global__ __launch_bounds__(256) void adjoint_load(long long nv, const Real *gphi, Real inv_vol,
@@ -244,7 +268,10 @@ template <typename Real, int Form, int B>
 void launch_tile_form(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, dim3 grid,
                       dim3 block, hipStream_t s)
 {
-    if (adjoint)
+    if (A.nmom > 1)
+        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, true>), grid, block, 0, s,
+                           A);
+    else if (adjoint)
         hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, true>), grid, block, 0, s, A);
     else if (store_psi)
         hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, true, false>), grid, block, 0, s, A);
@@ -302,6 +329,9 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
     const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
     if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
+    if (A.nmom > 1 && (form == kFormAnnPaper || store_psi || adjoint))
+        return set_error(DGSN_EUNSUPPORTED,
+                         "anisotropic sweeps are forward GE sweeps without a psi store");
     if (form == kFormDense) {
         launch_tile_b<Real, kFormDense>(A, b, store_psi, adjoint, grid, block, s);
     } else if (form == kFormAnnPaper) {
@@ -365,6 +395,17 @@ int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, 
     return DGSN_OK;
 }
 
+template <typename Real>
+int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
+                          Real *mom, Real *msrc, hipStream_t s)
+{
+    if (nm < 2 || nm > kYlmStride) return set_error(DGSN_EINVAL, "bad moment count %d", nm);
+    hipLaunchKernelGGL(reduce_moments<Real>, dim3(grid_for((long long)(nm - 1) * nv * 8)),
+                       dim3(256), 0, s, nv, nm, mom_oct, sigma_sn, mom, msrc);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
 int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
 
 #define DGSN_INST(Real)                                                                        \
@@ -377,7 +418,9 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
                                               hipStream_t);                                     \
     template int launch_adjoint_load<Real>(long long, const Real *, double, Real *,            \
                                            hipStream_t);                                       \
-    template int launch_reduce_grad<Real>(long long, const Real *, Real *, Real *, hipStream_t);
+    template int launch_reduce_grad<Real>(long long, const Real *, Real *, Real *, hipStream_t); \
+    template int launch_reduce_moments<Real>(long long, int, const Real *, const Real *, Real *,  \
+                                             Real *, hipStream_t);
 DGSN_INST(float)
 DGSN_INST(double)
 

@@ -160,6 +160,15 @@ def random_problem(n, order, groups, seed, length=(1.0, 1.0, 1.0), c_max=0.0, in
                    f"random_{n[0]}x{n[1]}x{n[2]}_S{order}_G{groups}_seed{seed}")
 
 
+def anisotropic_orders(sigma_s, L, seed, ratios=(0.5, 0.25, 0.12)):
+    """Legendre moments of orders 1..L of the scattering cross section
+    [L, G, ncell]: sigma_{s,n} = r_n u sigma_s with u ~ U[0.8, 1] per cell
+    (a forward-peaked kernel, |sigma_{s,n}| < sigma_s)."""
+    rng = np.random.default_rng(seed)
+    ss = np.asarray(sigma_s, np.float64)
+    return np.stack([ratios[n] * rng.uniform(0.8, 1.0, size=ss.shape) * ss for n in range(L)])
+
+
 def random_nodal(shape_cells, groups, seed, lo=0.0, hi=1.0):
     """Random nodal field [G, ncell, 8] ~ U[lo, hi]."""
     rng = np.random.default_rng(seed)

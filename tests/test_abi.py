@@ -261,3 +261,15 @@ def test_trained_paper_artifact_shape():
         conn = int(np.count_nonzero(net["W1"][o]) + np.count_nonzero(net["W2"][o]))
         assert 0 < conn <= 26 * 8 + 8 * 8
     assert abs(net["alpha"] - 0.27) < 1e-6 and abs(net["beta_scale"] - 0.1) < 1e-6
+
+
+def test_library_harmonics_match_oracle(lib):
+    from paper_1906_04017_amd import api
+    rng = np.random.default_rng(140)
+    om = rng.normal(size=(25, 3))
+    om /= np.linalg.norm(om, axis=1, keepdims=True)
+    om = np.concatenate([om, oracle.lq_n(8)[0]])
+    for L in range(4):
+        assert np.abs(api.real_ylm(L, om) - oracle.real_ylm(L, om)).max() < 1e-14
+    with pytest.raises(api.DgsnError):
+        api.real_ylm(4, om)

@@ -252,6 +252,124 @@ def test_source_iteration_history_matches_oracle_steps(api, ctx):
 
 
 # ---------------------------------------------------------------------------
+# anisotropic in-group P_L scattering
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp64", 3), ("fp32", 1),
+                                         ("fp32", 3)])
+def test_pl_source_iteration_matches_oracle(api, ctx, precision, L):
+    p = inputs.random_problem((6, 5, 4), 4, 2, seed=110 + L, c_max=0.8,
+                              length=(0.6, 0.5, 0.4))
+    sn = inputs.anisotropic_orders(p["sigma_s"], L, seed=120 + L)
+    print_case("pl_si", name=p["name"], precision=precision, L=L)
+    prob = gpu_problem(api, ctx, p, precision)
+    prob.set_anisotropy(sn)
+    tol = 1e-13 if precision == "fp64" else 1e-8
+    phi, info = prob.source_iterate(tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    mom = prob.moments().double().cpu().numpy()
+    om, w = oracle.lq_n(4)
+    ref = oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"],
+                                   np.concatenate([p["sigma_s"][None], sn]), p["q"], p["psi_inc"],
+                                   tol=1e-14, max_iter=3000)
+    assert ref["converged"]
+    bound = 1e-10 if precision == "fp64" else FP32_TOL
+    assert rel(phi.cpu().numpy(), ref["phi"]) <= bound
+    assert mom.shape == ref["mom"].shape
+    scale = np.abs(ref["phi"]).max()
+    assert np.abs(mom - ref["mom"]).max() <= bound * scale
+    # the anisotropy is felt: the isotropic iteration differs
+    iso = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-14, max_iter=3000)
+    assert rel(iso["phi"], ref["phi"]) > 100 * bound
+
+
+def test_pl_schedules_and_tiles_bitwise(api, ctx):
+    p = inputs.random_problem((7, 6, 5), 8, 2, seed=130, c_max=0.7)
+    sn = inputs.anisotropic_orders(p["sigma_s"], 2, seed=131)
+    print_case("pl_schedules", name=p["name"])
+    out = {}
+    for sched in ("planes", "dataflow"):
+        for b in (1, 2, 3):
+            prob = gpu_problem(api, ctx, p, "fp32")
+            prob.set_anisotropy(sn)
+            prob.set_schedule(sched)
+            prob.set_tile(b)
+            phi, _ = prob.source_iterate(tol=0.0, max_iter=6, allow_notconv=True)
+            out[(sched, b)] = (phi.cpu().numpy(), prob.moments().cpu().numpy())
+            prob.close()
+    for b in (1, 2, 3):
+        assert np.array_equal(out[("planes", b)][0], out[("dataflow", b)][0])
+        assert np.array_equal(out[("planes", b)][1], out[("dataflow", b)][1])
+    # tile edges differ only by the rounding of the solve order within a tile
+    assert rel(out[("planes", 2)][0], out[("planes", 1)][0]) <= FP32_TOL
+
+
+def test_pl_zero_orders_equal_isotropic_bitwise(api, ctx):
+    p = inputs.random_problem((5, 5, 4), 4, 2, seed=132, c_max=0.8)
+    print_case("pl_zero_orders", name=p["name"])
+    a = gpu_problem(api, ctx, p, "fp64")
+    phi_a, ia = a.source_iterate(tol=1e-12, max_iter=500)
+    b = gpu_problem(api, ctx, p, "fp64")
+    b.set_anisotropy(np.zeros((3, 2, p["sigma_t"].shape[1])))
+    phi_b, ib = b.source_iterate(tol=1e-12, max_iter=500)
+    assert ia["iters"] == ib["iters"]
+    assert np.array_equal(phi_a.cpu().numpy(), phi_b.cpu().numpy())
+    # the moments are those of the (anisotropic) angular flux itself, here
+    # of the isotropic-scattering solution: sum_d w_d Y_k(Omega_d) psi_d
+    om, w = oracle.lq_n(4)
+    ref = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], p["q"],
+                                p["psi_inc"], tol=1e-14, max_iter=3000, store_psi=True)
+    Y = oracle.real_ylm(3, om)
+    mom_ref = np.einsum("d,dk,dgcn->kgcn", w, Y[:, 1:], ref["psi"])
+    assert np.abs(b.moments().cpu().numpy() - mom_ref).max() <= 1e-10 * np.abs(ref["phi"]).max()
+    assert np.abs(mom_ref).max() > 1e-3 * np.abs(ref["phi"]).max()
+    # removing the orders restores the isotropic problem
+    b.set_anisotropy(None)
+    phi_c, _ = b.source_iterate(tol=1e-12, max_iter=500)
+    assert np.array_equal(phi_a.cpu().numpy(), phi_c.cpu().numpy())
+
+
+def test_pl_constant_solution(api, ctx):
+    # uniform medium, inflow c on every face, q = (sigma_t - sigma_s0) c:
+    # psi == c, and every moment of the constant flux vanishes for the
+    # level-symmetric set, so the anisotropic orders leave it unchanged
+    n = (6, 5, 4)
+    nc = 120
+    cval = 0.7
+    st = np.full((1, nc), 2.0)
+    ss = np.full((1, nc), 1.2)
+    p = inputs.problem(n, (0.6, 0.5, 0.4), 6, 1, st, ss, cval * (st - ss), np.full(6, cval),
+                       "pl_constant")
+    print_case("pl_constant", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp64")
+    prob.set_anisotropy(np.stack([np.full((1, nc), v) for v in (0.6, 0.3, 0.15)]))
+    phi, info = prob.source_iterate(tol=1e-14, max_iter=2000)
+    assert np.abs(phi.cpu().numpy() / (4 * np.pi) - cval).max() < 1e-12
+    assert prob.moments().abs().max().item() < 1e-12
+
+
+def test_pl_rejections(api, ctx):
+    p = inputs.random_problem((3, 3, 3), 4, 2, seed=133, c_max=0.5)
+    prob = gpu_problem(api, ctx, p, "fp32", store_psi=True)
+    sn = inputs.anisotropic_orders(p["sigma_s"], 1, seed=134)
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        prob.moments()
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        prob.set_anisotropy(np.zeros((4, 2, 27)))
+    prob.set_anisotropy(sn)
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.set_scattering(np.zeros((2, 2, 27)))
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.source_iterate(tol=1e-6, max_iter=200, allow_notconv=True)
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.adjoint(np.ones((2, 27, 8)))
+    prob.set_anisotropy(None)
+    prob.set_scattering(np.zeros((2, 2, 27)))
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.set_anisotropy(sn)
+
+
+# ---------------------------------------------------------------------------
 # multigroup scattering (group-to-group matrix, P0)
 # ---------------------------------------------------------------------------
 
