@@ -194,6 +194,7 @@ def main():
             "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
 
     fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
+    conv = None if args.skip_extras else si_convergence(api, ctx, p)
     ann = None if args.skip_extras else ann_vs_ge(api, ctx, args.ann, args.ann_paper)
     adj = None if args.skip_extras else adjoint_box(api, ctx)
     aniso = None if args.skip_extras else anisotropic_steps(api, ctx, p)
@@ -214,6 +215,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_ge": fp64,
+        "si_convergence": conv,
         "ann_vs_ge": ann,
         "adjoint": adj,
         "anisotropic": aniso,
@@ -248,6 +250,39 @@ def plain_fp64(api, ctx, p, reps=3):
     log(f"fp64 GE sweep: {dt * 1e3:.3f} ms")
     prob.close()
     return {"solves_per_s": solves / dt, "ms_per_sweep": dt * 1e3, "solver": "GE", "dtype": "f64"}
+
+
+def si_convergence(api, ctx, p, tol=1e-8):
+    """Source iteration of the benchmark workload to a 1e-8 max-norm
+    residual with the plain FP64 GE, and with FP32 GE until its own floor:
+    iterations, residuals, wall time, and the FP32 solution's norm-wise
+    relative difference from the FP64 one per group."""
+    import torch
+    om, w = api.quadrature_ls(p["order"])
+    out = {"workload": p["name"], "tol": tol}
+    res = {}
+    for prec in ("fp64", "fp32"):
+        prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision=prec)
+        prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+        prob.set_inflow(p["psi_inc"])
+        prob.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, info = prob.source_iterate(tol=tol, max_iter=2000, allow_notconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r, _ = prob.si_history()
+        out[prec] = {"iterations": info["iters"], "residual": info["resid"],
+                     "converged": info["converged"], "seconds": dt,
+                     "rho_eff": api.spectral_radius(r)}
+        res[prec] = phi.double()
+        log(f"SI {prec}: {info['iters']} iterations to residual {info['resid']:.2e} "
+            f"in {dt:.2f} s")
+        prob.close()
+    d = (res["fp32"] - res["fp64"]).abs().amax(dim=(1, 2)) / res["fp64"].abs().amax(dim=(1, 2))
+    out["fp32_vs_fp64_rel_per_group"] = [float(v) for v in d.cpu()]
+    log(f"SI fp32 vs fp64: max relative difference {float(d.max()):.2e}")
+    return out
 
 
 def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):

@@ -155,7 +155,9 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
  * [order][G][Nz*Ny*Nx] in the problem precision, orders 1..order (copied
  * asynchronously on the stream; the caller keeps ownership).  The moments
  * start from zero in every dgsn_source_iterate call (a resumed run restarts
- * them).  Single sweeps (dgsn_sweep, batches), the autotuner and the adjoint
+ * them).  Its sweeps use the problem's schedule and tile edge, at most 2
+ * (larger tiles would spill registers).  Single sweeps (dgsn_sweep, batches),
+ * the autotuner and the adjoint
  * take isotropic sources only: dgsn_adjoint_solve, and dgsn_source_iterate
  * with a network solver or with store_psi, return DGSN_EUNSUPPORTED while an
  * order is set, and so does this call while a group-to-group matrix

@@ -138,8 +138,9 @@ struct dgsn_problem {
     dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
     dgsn::DevBuf sigma_sn;                   // [L][G][ncell] Legendre moments of orders 1..L
     dgsn::DevBuf d_ylm;                      // [8][Do][kYlmStride] harmonics of the slot directions
-    dgsn::DevBuf mom_oct;                    // [8][nm-1][G][ncell][8] per-octant flux moments
-    dgsn::DevBuf mom, msrc;                  // [nm-1][G][ncell][8] moments, sigma_{s,n} x moments
+    dgsn::DevBuf mom_oct;                    // [8][G][ncell][8][nm-1] per-octant flux moments
+    dgsn::DevBuf mom;                        // [nm-1][G][ncell][8] flux moments
+    dgsn::DevBuf msrc;                       // [G][ncell][nm-1][8] sigma_{s,n} x moments
     dgsn::DevBuf src;                         // [G][ncell][8]
     dgsn::DevBuf phi_oct;                     // [8][G][ncell][8]
     dgsn::DevBuf front_x, front_y, front_z;   // [8][..][..][4][Do*G]

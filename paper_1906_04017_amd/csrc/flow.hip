@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void flow_reset(unsigned *sync, int n)
         if (i != kFlowError) sync[i] = 0u;
 }
 
-template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kMom = false>
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, int kMom = 0>
 __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void sweep_flow_ge(PlaneArgs<Real> A, FlowArgs F)
 {
     // 256 lanes as in the hyperplane kernel; A.cells is the whole tile list
@@ -92,8 +92,10 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     bool tvalid;
     const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
+    __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
+    if constexpr (kMom > 0) load_ylm_table(A, (int)o, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, true, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                              (int)o, l.ok, L, nullptr);
+                                                              (int)o, l.ok, L, nullptr, ytab);
     flow_finish(F, tid, o, t);
 }
 
@@ -126,10 +128,22 @@ template <typename Real, int Form, int B>
 void launch_flow_form(const PlaneArgs<Real> &A, const FlowArgs &F, bool store_psi, bool adjoint,
                       dim3 grid, dim3 block, hipStream_t s)
 {
-    if (A.nmom > 1)
-        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, true>), grid, block, 0, s,
-                           A, F);
-    else if (adjoint)
+    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles)
+    if constexpr (B <= 2) {
+        if (A.nmom > 1) {
+            if (A.nmom == 4)
+                hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, 3>), grid, block, 0,
+                                   s, A, F);
+            else if (A.nmom == 9)
+                hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, 8>), grid, block, 0,
+                                   s, A, F);
+            else
+                hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, 15>), grid, block,
+                                   0, s, A, F);
+            return;
+        }
+    }
+    if (adjoint)
         hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true>), grid, block, 0, s, A, F);
     else if (store_psi)
         hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false>), grid, block, 0, s, A, F);
@@ -191,6 +205,9 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
     if (A.nmom > 1 && (form == kFormAnnPaper || form == kFormAnn || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED,
                          "anisotropic sweeps are forward GE sweeps without a psi store");
+    if (A.nmom > 1 && ((A.nmom != 4 && A.nmom != 9 && A.nmom != 16) || b > 2))
+        return set_error(DGSN_EINVAL, "anisotropic sweeps take (L+1)^2 moments, L = 1..3, and "
+                         "tile edges 1..2 (moments %u, tile %d)", A.nmom, b);
     for (unsigned done = 0; done < F.units_o; done += kFlowMaxGroupsPerOctant) {
         const dim3 grid(8 * std::min(F.units_o - done, kFlowMaxGroupsPerOctant));
         if (form == kFormDense) {

@@ -45,8 +45,8 @@ struct PlaneArgs {
     // moments sum_{d in octant} w_d Y_k(Omega_d) psi_d
     uint32_t nmom;
     const Real *ylm;           // [8][Do][kYlmStride]
-    const Real *msrc;          // [nmom-1][G][ncell][8] sigma_{s,n(k)} phi_k
-    Real *mom_oct;             // [8][nmom-1][G][ncell][8]
+    const Real *msrc;          // [G][ncell][nmom-1][8] sigma_{s,n(k)} phi_k
+    Real *mom_oct;             // [8][G][ncell][8][nmom-1] (moment fastest)
 };
 
 // Dataflow schedule of a sweep: one launch processes every step.  Workgroup
@@ -113,9 +113,9 @@ constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector A
 // FP64 single-cell mass-inverse kernel would take 176 registers and run at 2
 // waves per SIMD; held to 168 it runs at 3 with no spills.  The larger FP64
 // tiles and the dense form would spill, so they keep the compiler's choice.
-template <typename Real, int Form, int B, bool kMom = false>
+template <typename Real, int Form, int B, int kMom = 0>
 constexpr int kMinWavesPerSimd =
-    (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv && !kMom) ? 3 : 1;
+    (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv && kMom == 0) ? 3 : 1;
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 
@@ -139,8 +139,9 @@ template <typename Real>
 int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Real *q_nodal,
                            const Real *sigma_gg, const Real *phi, Real *src, bool transpose,
                            hipStream_t s);
-// flux moments of anisotropic scattering: mom = sum over octants of mom_oct,
-// msrc = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k))
+// flux moments of anisotropic scattering: mom [nm-1][G][ncell][8] = the sum
+// over octants of mom_oct [8][G][ncell][8][nm-1], and msrc [G][ncell][nm-1][8]
+// = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k))
 template <typename Real>
 int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
                           Real *mom, Real *msrc, hipStream_t s);

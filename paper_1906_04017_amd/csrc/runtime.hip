@@ -304,7 +304,8 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const int form = paper ? kFormAnnPaper
                            : ann ? kFormAnn
                                  : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
-    const int tb = p->tile_b;
+    // anisotropic sweeps use tiles of edge 2 at most (larger tiles spill)
+    const int tb = (A.nmom > 1 && p->tile_b > 2) ? 2 : p->tile_b;
     const bool tiled = tb > 1;
     const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles[tb].ptr
                                                                : p->d_plane_cells.ptr);

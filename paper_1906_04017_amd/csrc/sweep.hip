@@ -23,7 +23,7 @@ namespace dgsn {
 
 namespace {
 
-template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kMom = false>
+template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, int kMom = 0>
 __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void sweep_tile_ge(PlaneArgs<Real> A)
 {
     // 256 lanes: (direction, group, tile slot) segments, grid = (tile blocks, octant)
@@ -33,8 +33,10 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     bool tvalid;
     const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
+    __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
+    if constexpr (kMom > 0) load_ylm_table(A, (int)blockIdx.y, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, false, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                               blockIdx.y, l.ok, L, nullptr);
+                                                               blockIdx.y, l.ok, L, nullptr, ytab);
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).
@@ -192,9 +194,10 @@ __global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
     }
 }
 
-// Flux moments of anisotropic scattering: one thread per (moment, group,
-// cell, node); the octant partials are summed in octant order, and the
-// source moment is sigma_{s,n} times the moment, n the order of moment k.
+// Flux moments of anisotropic scattering: one thread per (group, cell, node,
+// moment) in the sweep's layout; the octant partials are summed in octant
+// order, and the source moment is sigma_{s,n} times the moment, n the order
+// of moment k.
 template <typename Real>
 __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
                                                       const Real *__restrict__ mom_oct,
@@ -202,17 +205,19 @@ __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
                                                       Real *__restrict__ mom,
                                                       Real *__restrict__ msrc)
 {
-    const long long per = nv * 8;
-    const long long total = (long long)(nm - 1) * per;
+    const int nk = nm - 1;
+    const long long total = nv * nk * 8;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int k = (int)(e / per) + 1;
-        const long long r = e - (long long)(k - 1) * per;
+        const long long gc = e / (nk * 8);
+        const int r = (int)(e - gc * (nk * 8));
+        const int n = r / nk;
+        const int k = r - n * nk + 1;
         Real s = 0;
         for (int o = 0; o < 8; ++o) s += mom_oct[(long long)o * total + e];
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
-        mom[e] = s;
-        msrc[e] = sigma_sn[(long long)(order - 1) * nv + (r >> 3)] * s;
+        mom[((long long)(k - 1) * nv + gc) * 8 + n] = s;
+        msrc[(gc * nk + (k - 1)) * 8 + n] = sigma_sn[(long long)(order - 1) * nv + gc] * s;
     }
 }
 
@@ -268,10 +273,22 @@ template <typename Real, int Form, int B>
 void launch_tile_form(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, dim3 grid,
                       dim3 block, hipStream_t s)
 {
-    if (A.nmom > 1)
-        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, true>), grid, block, 0, s,
-                           A);
-    else if (adjoint)
+    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles)
+    if constexpr (B <= 2) {
+        if (A.nmom > 1) {
+            if (A.nmom == 4)
+                hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, 3>), grid, block, 0,
+                                   s, A);
+            else if (A.nmom == 9)
+                hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, 8>), grid, block, 0,
+                                   s, A);
+            else
+                hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, 15>), grid, block,
+                                   0, s, A);
+            return;
+        }
+    }
+    if (adjoint)
         hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, true>), grid, block, 0, s, A);
     else if (store_psi)
         hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, true, false>), grid, block, 0, s, A);
@@ -332,6 +349,9 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
     if (A.nmom > 1 && (form == kFormAnnPaper || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED,
                          "anisotropic sweeps are forward GE sweeps without a psi store");
+    if (A.nmom > 1 && ((A.nmom != 4 && A.nmom != 9 && A.nmom != 16) || b > 2))
+        return set_error(DGSN_EINVAL, "anisotropic sweeps take (L+1)^2 moments, L = 1..3, and "
+                         "tile edges 1..2 (moments %u, tile %d)", A.nmom, b);
     if (form == kFormDense) {
         launch_tile_b<Real, kFormDense>(A, b, store_psi, adjoint, grid, block, s);
     } else if (form == kFormAnnPaper) {

@@ -271,50 +271,35 @@ __device__ __forceinline__ SegLane seg_lane(const PlaneArgs<Real> &A, int tid)
 
 // Anisotropic scattering source of one lane's direction (Eq. (T7) terms of
 // order n >= 1): sc += sum_k Y_k(Omega_d) msrc_k at the cell's nodes
-// (reflected into the canonical octant like the isotropic source).
-template <typename Real>
+// (reflected into the canonical octant like the isotropic source).  NM
+// moments, stored contiguously per (group, cell) so that their loads leave
+// together.
+template <typename Real, int NM>
 __device__ __forceinline__ void add_moment_source(const PlaneArgs<Real> &A, const Real *yl,
                                                   uint32_t gc, int mask, Real sc[8])
 {
-    const size_t stride = (size_t)A.G * A.ncell * 8;
-#pragma unroll 1
-    for (uint32_t k = 1; k < A.nmom; ++k) {
-        Real m[8];
-        load8_reflect(A.msrc + (k - 1) * stride + (size_t)gc * 8, mask, m);
-        const Real y = yl[k - 1];
+    const Real *base = A.msrc + (size_t)gc * (NM * 8);
+    Real m[NM][8];
 #pragma unroll
-        for (int n = 0; n < 8; ++n) sc[n] = fma(y, m[n], sc[n]);
+    for (int k = 0; k < NM; ++k) load8_reflect(base + k * 8, mask, m[k]);
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        const Real y = yl[k];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) sc[n] = fma(y, m[k][n], sc[n]);
     }
 }
 
-// Per-octant flux moments k >= 1 of one cell (Eq. (T8) restricted to the
-// octant's directions), reduced over the segment's direction lanes in the
-// same fixed order as the scalar flux; rb is the lane's reduction buffer.
-// Reached by every lane of the wave.
+// The harmonics of octant o's directions into LDS, [Do][kYlmStride], for the
+// moment reduction of anisotropic sweeps (every thread of the block, then a
+// block barrier).
 template <typename Real>
-__device__ __forceinline__ void moment_reduce(const PlaneArgs<Real> &A, const Real *yl, Real w,
-                                              const Real psi[8], Real *rb, int tid, int d,
-                                              bool ok, int o, int g, uint32_t c, int mask)
+__device__ __forceinline__ void load_ylm_table(const PlaneArgs<Real> &A, int o, Real *ytab)
 {
-#pragma unroll 1
-    for (uint32_t k = 1; k < A.nmom; ++k) {
-        wave_lds_sync();   // the previous reads of rb are complete
-        const Real yw = w * yl[k - 1];
-#pragma unroll
-        for (int n = 0; n < 8; ++n) rb[tid * 9 + n] = yw * psi[n];
-        wave_lds_sync();
-        if (ok) {
-            const int base = tid - d;
-            const size_t out =
-                (((size_t)o * (A.nmom - 1) + (k - 1)) * A.G + g) * (size_t)A.ncell * 8 +
-                (size_t)c * 8;
-            for (int n = d; n < 8; n += (int)A.Do) {
-                Real s = 0;
-                for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
-                A.mom_oct[out + (n ^ mask)] = s;
-            }
-        }
-    }
+    const int n = (int)A.Do * kYlmStride;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        ytab[i] = A.ylm[(size_t)o * A.Do * kYlmStride + i];
+    __syncthreads();
 }
 
 // Tile ti of one schedule step (cells: the step's packed tiles, ncp of them).
@@ -346,17 +331,19 @@ struct AnnLds {
 // kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
 // blocks of full waves) or kFormAnnPaper (the paper-form per-octant
 // network, FP32).  kCoh: device-coherent front access (dataflow
-// kernel).  kMom: anisotropic scattering (the A.nmom - 1 moment sources
-// enter the gather, the moments leave with the scalar flux; source
-// iteration only, a separate instantiation so that the isotropic kernels
-// carry none of it).  Must be reached by every lane of the wave; lanes of one
+// kernel).  kMom: anisotropic scattering with kMom = A.nmom - 1 moments (their
+// sources enter the gather, the moments leave with the scalar flux; source
+// iteration only, separate instantiations so that the isotropic kernels
+// carry none of it; 0: isotropic); ytab: the block's octant's harmonics in
+// LDS, [Do][kYlmStride] (load_ylm_table).  Must be reached by every lane of the wave; lanes of one
 // (group, tile) segment are in one wave (seg_lane), and the body synchronises
 // only within the wave.
 template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kCoh = false,
-          bool kMom = false>
+          int kMom = 0>
 __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real inc[3], int d,
                                           int g, int tid, bool tvalid, uint32_t pt, int o,
-                                          bool lane_ok, TileLds<Real> &L, AnnLds *al)
+                                          bool lane_ok, TileLds<Real> &L, AnnLds *al,
+                                          const Real *ytab = nullptr)
 {
     static_assert((Form != kFormAnn && Form != kFormAnnPaper) || sizeof(Real) == 4,
                   "the ANN solvers run in FP32");
@@ -365,7 +352,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
     const Real w = lane_ok ? dp[kDirW] : Real(0);
     const Real kap[3] = {dp[kDirK], dp[kDirK + 1], dp[kDirK + 2]};
-    const Real *yl = kMom ? A.ylm + (o * A.Do + (lane_ok ? d : 0)) * kYlmStride : nullptr;
+    const Real *yl = kMom > 0 ? A.ylm + (o * A.Do + (lane_ok ? d : 0)) * kYlmStride : nullptr;
     AnnRegs R;
     if (Form == kFormAnn) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
     uint32_t I0 = 0, J0 = 0, K0 = 0;
@@ -411,7 +398,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     } else {
                         load8_reflect(A.src + gc * 8, mask, sc);
                     }
-                    if constexpr (kMom) add_moment_source(A, yl, gc, mask, sc);
+                    if constexpr (kMom > 0) add_moment_source<Real, kMom>(A, yl, gc, mask, sc);
                     ex = o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4;
                     ey = o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4;
                     ez = o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4;
@@ -539,7 +526,25 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     const uint32_t out = ((o * A.G + g) * A.ncell + c) * 8;
                     for (int n = d; n < 8; n += (int)A.Do) {
                         Real s = 0;
-                        for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
+                        if constexpr (kMom > 0) {
+                            // the octant's flux moments of this node from the
+                            // same weighted values (Eq. (T8) over the octant)
+                            Real mk[kMom];
+#pragma unroll
+                            for (int k = 0; k < kMom; ++k) mk[k] = 0;
+                            for (int e = 0; e < (int)A.Do; ++e) {
+                                const Real v = rb[(base + e) * 9 + n];
+                                s += v;
+#pragma unroll
+                                for (int k = 0; k < kMom; ++k)
+                                    mk[k] = fma(ytab[e * kYlmStride + k], v, mk[k]);
+                            }
+                            Real *mo = A.mom_oct + ((size_t)out + (n ^ mask)) * kMom;
+#pragma unroll
+                            for (int k = 0; k < kMom; ++k) mo[k] = mk[k];
+                        } else {
+                            for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
+                        }
                         A.phi_oct[out + (n ^ mask)] = s;
                     }
                     if (kAdjoint && A.grad_oct) {
@@ -550,7 +555,6 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                         }
                     }
                 }
-                if constexpr (kMom) moment_reduce(A, yl, w, psi, rb, tid, d, ok, o, g, c, mask);
                 if (kAdjoint) wave_lds_sync();
             }
 }
