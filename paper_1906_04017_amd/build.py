@@ -16,8 +16,12 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgsn.so")
 ARCH = "gfx950"
 
+# -amdgpu-mfma-vgpr-form: matrix-core results in ordinary VGPRs (CDNA3/4 have
+# one register file), which saves the copies out of accumulation registers in
+# the network kernels; kernels without matrix instructions are unaffected.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
           "-Wno-unknown-pragmas"]
 

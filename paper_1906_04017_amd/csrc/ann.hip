@@ -100,6 +100,15 @@ uint16_t bf16_bits(float f)
     return (uint16_t)((u + round) >> 16);
 }
 
+// the float value of the bf16 rounding of f
+float bf16_value(float f)
+{
+    const uint32_t u = (uint32_t)bf16_bits(f) << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
 int build_params(dgsn_ann *a)
 {
     std::vector<unsigned char> buf(kParamBytes, 0);
@@ -115,12 +124,10 @@ int build_params(dgsn_ann *a)
             const int hid = 16 * m + col;
             for (int e = 0; e < 8; ++e) {
                 const int f = 8 * grp + e;
-                const float v = (hid < H && f < NI) ? a->W1[hid * NI + f] : 0.0f;
+                float v = (hid < H && f < NI) ? a->W1[hid * NI + f] : 0.0f;
+                if (hid < H && f == kFeatBiasHi) v = bf16_value(a->b1[hid]);
+                if (hid < H && f == kFeatBiasLo) v = a->b1[hid] - bf16_value(a->b1[hid]);
                 put_bf16(kParamW1 + (m * 64 + lane) * 16 + 2 * e, v);
-            }
-            for (int r = 0; r < 4; ++r) {
-                const int hid2 = 16 * m + 4 * grp + r;
-                put_f32(kParamB1 + (m * 64 + lane) * 16 + 4 * r, hid2 < H ? a->b1[hid2] : 0.0f);
             }
         }
         for (int c = 0; c < 2; ++c)
@@ -130,11 +137,8 @@ int build_params(dgsn_ann *a)
                 const float v = (out < NO && hid < H) ? a->W2[out * H + hid] : 0.0f;
                 put_bf16(kParamW2 + (c * 64 + lane) * 16 + 2 * e, v);
             }
-        for (int r = 0; r < 4; ++r) {
-            const int out = 4 * grp + r;
-            put_f32(kParamB2 + lane * 16 + 4 * r, out < NO ? a->b2[out] : 0.0f);
-        }
     }
+    for (int out = 0; out < 8; ++out) put_f32(kParamB2 + 4 * out, out < NO ? a->b2[out] : 0.0f);
     DGSN_TRY(a->d_params.alloc(buf.size()));
     DGSN_HIP(hipMemcpy(a->d_params.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice));
     return DGSN_OK;
