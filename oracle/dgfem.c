@@ -635,11 +635,13 @@ int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double l
                 }
             }
             if (err) break;
-            for (long t = 0; t < nb; ++t) {
-                const long u = u0 + t;
-                const int d = (int)(u / ng), g = (int)(u % ng);
-                const double *yd = Y + (long)d * nm;
-                for (long c = 0; c < ncell; ++c) {
+            /* each (group, cell) accumulates its units in unit order */
+#pragma omp parallel for schedule(static)
+            for (long c = 0; c < ncell; ++c)
+                for (long t = 0; t < nb; ++t) {
+                    const long u = u0 + t;
+                    const int d = (int)(u / ng), g = (int)(u % ng);
+                    const double *yd = Y + (long)d * nm;
                     const long gc = (long)g * ncell + c;
                     const double *p = buf + (t * ncell + c) * 8;
                     for (int n = 0; n < 8; ++n) {
@@ -648,7 +650,6 @@ int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double l
                             momn[((long)(k - 1) * nv + gc) * 8 + n] += weight[d] * yd[k] * p[n];
                     }
                 }
-            }
         }
         if (err) break;
         double dmax = 0.0, fmax = 0.0, esum = 0.0;

@@ -98,6 +98,35 @@ def test_paper_problems_full_sweep_fp32(api, ctx):
         assert np.abs(phi[g][big] / ref[0][big] - 1).max() <= 1e-3, g
 
 
+def test_anisotropic_iterations_at_bench_size(api, ctx):
+    # the benchmark workload with P1 in-group scattering, FP32, the
+    # autotuned configuration: two source iterations from zero (the second
+    # sweep carries the first one's moments) against the P1 oracle, every
+    # output of the scalar flux and of the three flux moments
+    p = inputs.blocky_scatter()
+    sn = inputs.anisotropic_orders(p["sigma_s"], 1, seed=7)
+    print_case("fullsize_p1", name=p["name"])
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.autotune()
+    prob.set_anisotropy(sn)
+    phi, info = prob.source_iterate(tol=0.0, max_iter=2, allow_notconv=True)
+    assert info["iters"] == 2
+    mom = prob.moments().double().cpu().numpy()
+    phi = phi.double().cpu().numpy()
+    om_o, w_o = oracle.lq_n(8)
+    ref = oracle.source_iterate_pl((*p["n"], *p["length"]), om_o, w_o, p["sigma_t"],
+                                   np.concatenate([p["sigma_s"][None], sn]), p["q"],
+                                   p["psi_inc"], tol=0.0, max_iter=2)
+    assert ref["iters"] == 2
+    for g in range(p["groups"]):
+        scale = np.abs(ref["phi"][g]).max()
+        assert np.abs(phi[g] - ref["phi"][g]).max() <= 1e-5 * scale, g
+        assert np.abs(mom[:, g] - ref["mom"][:, g]).max() <= 1e-5 * scale, g
+    assert np.abs(ref["mom"]).max() > 1e-3 * np.abs(ref["phi"]).max()
+
+
 def test_constant_solution_at_bench_size(api, ctx):
     # uniform sigma_t, sigma_s = c sigma_t, q and inflow q / (sigma_t (1 - c))
     # on every face: the source-iteration fixed point is psi = q/(sigma_t(1-c))
