@@ -127,6 +127,37 @@ def test_anisotropic_iterations_at_bench_size(api, ctx):
     assert np.abs(ref["mom"]).max() > 1e-3 * np.abs(ref["phi"]).max()
 
 
+def test_trained_network_sweep_at_full_size(api, ctx):
+    # the trained BF16 matrix-core network on the paper's Problem 3 (sigma_t =
+    # 10, q = 1, psi_inc = 1 on three faces) at 128^3, S8, autotuned, against
+    # the oracle's FP64 forward of the same artifact in the same sweep.  The
+    # only differences are the BF16 rounding of the normalised features and
+    # of the hidden layer (about 2^-9 relative per cell) carried downstream;
+    # a cell passes on e^-0.78 of its inflow, so they stay near 2^-8
+    from paper_1906_04017_amd import ann_format
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1906_04017_amd", "data", "ann_s8_relu64.dgsnann")
+    p = inputs.paper_problems(n=128, groups=4, order=8)
+    print_case("fullsize_ann", name=p["name"], group=2)
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], 1, om, w, precision="fp32", solver="ann")
+    prob.set_materials(p["sigma_t"][2:3], p["sigma_s"][2:3], p["q"][2:3])
+    prob.set_inflow(p["psi_inc"])
+    ann = api.Ann(ctx, path)
+    prob.set_ann(ann)
+    prob.autotune()
+    S = np.repeat(p["q"][2:3, :, None], 8, axis=-1)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    om_o, w_o = oracle.lq_n(8)
+    ref = oracle.ann_sweep(ann_format.read(path), (*p["n"], *p["length"]), om_o, w_o,
+                           p["sigma_t"][2:3], S, p["psi_inc"])
+    assert rel(phi, ref) <= 8 * 2.0 ** -8
+    avg, avg_ref = phi.mean(-1), ref.mean(-1)
+    assert np.mean(np.abs(avg - avg_ref) / np.abs(avg_ref)) <= 2 * 2.0 ** -8
+    ann.close()
+
+
 def test_constant_solution_at_bench_size(api, ctx):
     # uniform sigma_t, sigma_s = c sigma_t, q and inflow q / (sigma_t (1 - c))
     # on every face: the source-iteration fixed point is psi = q/(sigma_t(1-c))
