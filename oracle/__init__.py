@@ -84,7 +84,10 @@ def _load():
     lib.orc_real_ylm.argtypes = [ctypes.c_int, _D, _D]
     lib.orc_source_iterate_pl.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 3 + [ctypes.c_int] + [_D] * 5 + \
-        [ctypes.c_double, ctypes.c_int, _I, _D, _D, ctypes.c_int]
+        [ctypes.c_double, ctypes.c_int, _I, _D, _D, _D, ctypes.c_int]
+    lib.orc_adjoint_pl.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 3 + [ctypes.c_int] + [_D] * 4 + \
+        [ctypes.c_double, ctypes.c_int, _D, _D, _D, _I, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -240,13 +243,15 @@ def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1
 
 
 def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, max_iter=2000,
-            nthreads=0, sigma_gg=None):
+            nthreads=0, sigma_gg=None, sigma_sn=None):
     """Exact discrete adjoint of the converged source iteration.
     gphi = dJ/dphi [G, ncell, 8].  Returns dict(grad_sigma_t, grad_q,
     grad_sigma_s [G, ncell], phi_dag [G, ncell, 8], iters); direct partial
     derivatives of J are not included.  With sigma_gg (multigroup scattering,
-    the transposed coupling in the adjoint) grad_sigma_s is not computed.
-    Pinned by duality, the dense transpose and central finite differences."""
+    the transposed coupling in the adjoint) grad_sigma_s is not computed;
+    with sigma_sn [L+1, G, ncell] (in-group P_L, order 0 first; sigma_s is
+    then ignored) neither.  Pinned by duality, the dense transpose and
+    central finite differences."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
     ncell = nx * ny * nz
@@ -259,7 +264,16 @@ def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, ma
     gss = np.zeros((ng, ncell))
     pd = np.zeros((ng, ncell, 8))
     it = ctypes.c_int(0)
-    if sigma_gg is None:
+    if sigma_sn is not None:
+        gss = None
+        sn = _f64(sigma_sn).reshape(-1, ng, ncell)
+        rc = lib.orc_adjoint_pl(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                                _p(_f64(weight, (nd,))), _p(sigma_t), int(sn.shape[0] - 1),
+                                _p(sn), _p(_f64(psi, (nd, ng, ncell, 8))),
+                                _p(_f64(phi, (ng, ncell, 8))), _p(_f64(gphi, (ng, ncell, 8))),
+                                float(tol), int(max_iter), _p(gst), _p(gq), _p(pd),
+                                ctypes.byref(it), int(nthreads))
+    elif sigma_gg is None:
         rc = lib.orc_adjoint(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
                              _p(sigma_t), _p(_f64(sigma_s, (ng, ncell))),
                              _p(_f64(psi, (nd, ng, ncell, 8))), _p(_f64(phi, (ng, ncell, 8))),
@@ -490,7 +504,7 @@ def real_ylm(L, omega):
 
 
 def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, tol=1e-8,
-                      max_iter=1000, phi0=None, mom0=None, nthreads=0):
+                      max_iter=1000, phi0=None, mom0=None, nthreads=0, store_psi=False):
     """In-group P_L scattering source iteration (Eq. (T3)-(T8)).
     sigma_sn [L+1, G, ncell], order 0 first; returns dict(phi [G, ncell, 8],
     mom [(L+1)^2 - 1, G, ncell, 8] (the moments k = n^2 + n + m >= 1), iters,
@@ -513,15 +527,19 @@ def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, t
     it = ctypes.c_int(0)
     resid = ctypes.c_double(0)
     eps = ctypes.c_double(0)
+    psi = np.zeros((nd, ng, ncell, 8)) if store_psi else None
     rc = lib.orc_source_iterate_pl(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
                                    _p(_f64(weight, (nd,))), _p(sigma_t), int(L), _p(sigma_sn),
                                    _p(q), _p(inc), _p(phi), _p(mom), float(tol), int(max_iter),
                                    ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps),
-                                   int(nthreads))
+                                   _p(psi), int(nthreads))
     if rc not in (0, ORC_ENOTCONV):
         _check(rc, "source_iterate_pl")
-    return dict(phi=phi, mom=mom, iters=it.value, resid=resid.value, eps_s=eps.value,
-                converged=(rc == 0))
+    out = dict(phi=phi, mom=mom, iters=it.value, resid=resid.value, eps_s=eps.value,
+               converged=(rc == 0))
+    if store_psi:
+        out["psi"] = psi
+    return out
 
 
 def cell_average(phi):

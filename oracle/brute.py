@@ -147,14 +147,14 @@ def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sig
     return psi, phi
 
 
-def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi, sigma_gg=None):
+def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi, sigma_gg=None, sigma_sn=None):
     """Dense transpose solve (L - K)^T lambda = W^T g for a response with
     dJ/dphi = gphi [G, ncell, 8]; returns lambda [D, G, ncell, 8]."""
     nd = len(weight)
     ncell = mesh[0] * mesh[1] * mesh[2]
     ng = np.asarray(sigma_t).reshape(-1, ncell).shape[0]
     A, _ = assemble(mesh, omega, weight, sigma_t, sigma_s, np.zeros((ng, ncell)), np.zeros(6),
-                    sigma_gg=sigma_gg)
+                    sigma_gg=sigma_gg, sigma_sn=sigma_sn)
     gphi = np.asarray(gphi, np.float64).reshape(ng, ncell, 8)
     r = np.concatenate([weight[d] * gphi.reshape(-1) for d in range(nd)])
     lam = np.linalg.solve(A.T, r)

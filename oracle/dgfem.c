@@ -575,12 +575,14 @@ int orc_real_ylm(int L, const double omega[3], double *Y)
  * Y_k(Omega_d) mom_k, one sweep per (direction, group) with that source, then
  * phi = sum_d w_d psi_d and mom_k = sum_d w_d Y_k(Omega_d) psi_d, accumulated
  * in direction order.  Residual and eps_s on phi as in source_iterate.
+ * psi_store, if not NULL, receives the last sweep's [D][G][ncell][8].
  */
 int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
                           int nd, const double *omega, const double *weight,
                           const double *sigma_t, int L, const double *sigma_sn, const double *q,
                           const double psi_inc[6], double *phi, double *mom, double tol,
-                          int max_iter, int *iters, double *resid, double *eps_s, int nthreads)
+                          int max_iter, int *iters, double *resid, double *eps_s,
+                          double *psi_store, int nthreads)
 {
     if (nx < 1 || ny < 1 || nz < 1 || ng < 1 || nd < 1 || L < 1 || L > 8) return ORC_EINVAL;
     orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
@@ -635,6 +637,13 @@ int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double l
                 }
             }
             if (err) break;
+            if (psi_store)
+                for (long t = 0; t < nb; ++t) {
+                    const long u = u0 + t;
+                    const int d = (int)(u / ng), g = (int)(u % ng);
+                    memcpy(psi_store + ((long)d * ng + g) * ncell * 8, buf + t * ncell * 8,
+                           (size_t)ncell * 8 * sizeof(double));
+                }
             /* each (group, cell) accumulates its units in unit order */
 #pragma omp parallel for schedule(static)
             for (long c = 0; c < ncell; ++c)
@@ -796,43 +805,123 @@ static void adjoint_load(int ng, long ncell, const double *sigma_s, const double
         }
 }
 
+/*
+ * The anisotropic part of the adjoint load for direction d of group g
+ * (in-group P_L, the transpose of the forward moment coupling):
+ *   lu[c] = load[g][c] + sum_{k>=1} sigma_{s,n(k)}[g][c] Y_k(Omega_d) M phid_k[g][c],
+ * with mmom[k-1][g][c] = M phid_k[g][c] precomputed.
+ */
+static void adjoint_load_pl(long ncell, int g, int L, const double *sigma_sn, const double *yd,
+                            const double *load, const double *mmom, long nv, double *lu)
+{
+    for (long c = 0; c < ncell; ++c) {
+        const long gc = (long)g * ncell + c;
+        for (int n = 0; n < 8; ++n) {
+            double v = load[gc * 8 + n];
+            for (int o = 1; o <= L; ++o)
+                for (int mm = -o; mm <= o; ++mm) {
+                    const int k = o * o + o + mm;
+                    v += sigma_sn[(long)(o - 1) * nv + gc] * yd[k] *
+                         mmom[((long)(k - 1) * nv + gc) * 8 + n];
+                }
+            lu[c * 8 + n] = v;
+        }
+    }
+}
+
+/* one adjoint sweep of every (direction, group): mu = (A^T)^-1 load_d */
+static int adjoint_sweep_all(const orc_mesh *m, int ng, int nd, const double *omega,
+                             const double *sigma_t, const double *load, const double M[64],
+                             const double G[3][64], const double Mf[6][64], int L,
+                             const double *sigma_sn, const double *Y, const double *mmom,
+                             double *ubuf, double *mu)
+{
+    const long ncell = (long)m->n[0] * m->n[1] * m->n[2];
+    const long nv = (long)ng * ncell;
+    const int nm = (L + 1) * (L + 1);
+    int rc = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long u = 0; u < (long)nd * ng; ++u) {
+        const int d = (int)(u / ng), g = (int)(u % ng);
+        const double *ld = load + 8 * g * ncell;
+        if (L > 0) {
+#ifdef _OPENMP
+            double *lu = ubuf + (long)omp_get_thread_num() * ncell * 8;
+#else
+            double *lu = ubuf;
+#endif
+            adjoint_load_pl(ncell, g, L, sigma_sn, Y + (long)d * nm, load, mmom, nv, lu);
+            ld = lu;
+        }
+        int e = adjoint_sweep_one(m, omega + 3 * d, sigma_t + g * ncell, ld, M, G, Mf,
+                                  mu + ((long)d * ng + g) * ncell * 8);
+        if (e) {
+#pragma omp critical
+            rc = e;
+        }
+    }
+    return rc;
+}
+
+/* mmom[k-1] = M phid_k with phid_k = sum_d w_d Y_k(Omega_d) mu_d */
+static void adjoint_moments(int nd, long nv, int nm, const double *weight, const double *Y,
+                            const double *mu, const double M[64], double *mmom)
+{
+#pragma omp parallel for schedule(static)
+    for (long gc = 0; gc < nv; ++gc)
+        for (int k = 1; k < nm; ++k) {
+            double pk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int d = 0; d < nd; ++d)
+                for (int n = 0; n < 8; ++n)
+                    pk[n] += weight[d] * Y[(long)d * nm + k] * mu[((long)d * nv + gc) * 8 + n];
+            for (int n = 0; n < 8; ++n) {
+                double v = 0.0;
+                for (int j = 0; j < 8; ++j) v += M[n * 8 + j] * pk[j];
+                mmom[((long)(k - 1) * nv + gc) * 8 + n] = v;
+            }
+        }
+}
+
 static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
                        const double *omega, const double *weight, const double *sigma_t,
                        const double *sigma_s, const double *sigma_gg, const double *psi,
                        const double *phi, const double *gphi, double tol, int max_iter,
                        double *grad_sigma_t, double *grad_q, double *grad_sigma_s,
-                       double *phi_dag_out, int *iters, int nthreads)
+                       double *phi_dag_out, int *iters, int nthreads, int L,
+                       const double *sigma_sn)
 {
     orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
     const long ncell = (long)nx * ny * nz;
     const long nv = (long)ng * ncell;
+    const int nm = (L + 1) * (L + 1);
     double M[64], G[3][64], Mf[6][64];
     orc_element_matrices(m.h, M, G, Mf);
-    set_threads(nthreads);
+    const int nt = set_threads(nthreads);
     double *phid = (double *)calloc((size_t)nv * 8, sizeof(double));
     double *phidn = (double *)malloc((size_t)nv * 8 * sizeof(double));
     double *load = (double *)malloc((size_t)nv * 8 * sizeof(double));
     double *mu = (double *)malloc((size_t)nd * nv * 8 * sizeof(double));
-    if (!phid || !phidn || !load || !mu) {
-        free(phid); free(phidn); free(load); free(mu);
+    double *Y = NULL, *mmom = NULL, *ubuf = NULL;
+    if (L > 0) {
+        Y = (double *)malloc((size_t)nd * nm * sizeof(double));
+        mmom = (double *)calloc((size_t)(nm - 1) * nv * 8, sizeof(double));
+        ubuf = (double *)malloc((size_t)nt * ncell * 8 * sizeof(double));
+    }
+    if (!phid || !phidn || !load || !mu || (L > 0 && (!Y || !mmom || !ubuf))) {
+        free(phid); free(phidn); free(load); free(mu); free(Y); free(mmom); free(ubuf);
         return ORC_ENOMEM;
     }
+    if (L > 0)
+        for (int d = 0; d < nd; ++d) orc_real_ylm(L, omega + 3 * d, Y + (long)d * nm);
     int it = 0, rc = ORC_OK;
     double r = INFINITY;
     while (it < max_iter) {
-        /* load = g + sigma_s^T/(4 pi) M phi_dag */
+        /* load = g + sigma_s^T/(4 pi) M phi_dag (+ the anisotropic moments) */
         adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
-#pragma omp parallel for schedule(dynamic, 1)
-        for (long u = 0; u < (long)nd * ng; ++u) {
-            const int d = (int)(u / ng), g = (int)(u % ng);
-            int e = adjoint_sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, load + 8 * g * ncell,
-                                      M, G, Mf, mu + ((long)d * ng + g) * ncell * 8);
-            if (e) {
-#pragma omp critical
-                rc = e;
-            }
-        }
+        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, Y, mmom,
+                               ubuf, mu);
         if (rc) break;
+        if (L > 0) adjoint_moments(nd, nv, nm, weight, Y, mu, M, mmom);
         memset(phidn, 0, (size_t)nv * 8 * sizeof(double));
         for (int d = 0; d < nd; ++d)
             for (long i = 0; i < nv * 8; ++i) phidn[i] += weight[d] * mu[(long)d * nv * 8 + i];
@@ -850,16 +939,8 @@ static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, 
         /* the mu of the last sweep are consistent with the phi_dag used to build
            its load; one more sweep with the converged phi_dag refines them */
         adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
-#pragma omp parallel for schedule(dynamic, 1)
-        for (long u = 0; u < (long)nd * ng; ++u) {
-            const int d = (int)(u / ng), g = (int)(u % ng);
-            int e = adjoint_sweep_one(&m, omega + 3 * d, sigma_t + g * ncell, load + 8 * g * ncell,
-                                      M, G, Mf, mu + ((long)d * ng + g) * ncell * 8);
-            if (e) {
-#pragma omp critical
-                rc = e;
-            }
-        }
+        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, Y, mmom,
+                               ubuf, mu);
     }
     if (!rc) {
         for (long gc = 0; gc < nv; ++gc) {
@@ -881,7 +962,7 @@ static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, 
         }
         if (phi_dag_out) memcpy(phi_dag_out, phid, (size_t)nv * 8 * sizeof(double));
     }
-    free(phid); free(phidn); free(load); free(mu);
+    free(phid); free(phidn); free(load); free(mu); free(Y); free(mmom); free(ubuf);
     if (iters) *iters = it;
     if (rc) return rc;
     return (r < tol) ? ORC_OK : ORC_ENOTCONV;
@@ -896,7 +977,7 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
 {
     return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, NULL, psi,
                        phi, gphi, tol, max_iter, grad_sigma_t, grad_q, grad_sigma_s, phi_dag_out,
-                       iters, nthreads);
+                       iters, nthreads, 0, NULL);
 }
 
 /* Adjoint with multigroup scattering (the gradient with respect to the
@@ -910,7 +991,23 @@ int orc_adjoint_gg(int nx, int ny, int nz, double lx, double ly, double lz, int 
     if (!sigma_gg) return ORC_EINVAL;
     return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, sigma_gg,
                        psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
-                       iters, nthreads);
+                       iters, nthreads, 0, NULL);
+}
+
+/* Adjoint with in-group P_L scattering: sigma_sn [L+1][G][ncell], order 0
+   first (the gradient with respect to the scattering moments is not
+   returned). */
+int orc_adjoint_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                   const double *omega, const double *weight, const double *sigma_t, int L,
+                   const double *sigma_sn, const double *psi, const double *phi,
+                   const double *gphi, double tol, int max_iter, double *grad_sigma_t,
+                   double *grad_q, double *phi_dag_out, int *iters, int nthreads)
+{
+    if (L < 1 || L > 8 || !sigma_sn) return ORC_EINVAL;
+    const long nv = (long)ng * nx * ny * nz;
+    return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_sn, NULL,
+                       psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
+                       iters, nthreads, L, sigma_sn + nv);
 }
 
 /* ------------------------------------------------------------------ */

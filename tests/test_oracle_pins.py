@@ -808,3 +808,33 @@ def test_pl_constant_solution():
                                  max_iter=3000)
     assert np.abs(r["phi"] / (4 * np.pi) - cval).max() < 1e-12
     assert np.abs(r["mom"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_pl_adjoint_matches_dense_transpose_and_differences(L):
+    mesh, om, w, st, sn, q, inc = _pl_case(97 + L, L=L)
+    ng, nc = st.shape
+    rng = np.random.default_rng(99)
+    g = rng.uniform(0.0, 1.0, (ng, nc, 8))
+    r = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-15, max_iter=3000,
+                                 store_psi=True)
+    assert r["converged"]
+    a = oracle.adjoint(mesh, om, w, st, sn[0], r["psi"], r["phi"], g, tol=1e-15, sigma_sn=sn)
+    lam = brute.adjoint_solve(mesh, om, w, st, sn[0], g, sigma_sn=sn[1:])
+    psi_b, phi_b = brute.solve(mesh, om, w, st, sn[0], q, inc, sigma_sn=sn[1:])
+    h = np.array(mesh[3:]) / np.array(mesh[:3])
+    M, _, _ = oracle.element_matrices(h)
+    gq = np.einsum("dgcn,nm->gc", lam, M)
+    gst = -np.einsum("dgcn,nm,dgcm->gc", lam, M, psi_b)
+    assert np.abs(a["grad_q"] - gq).max() < 1e-11 * np.abs(gq).max()
+    assert np.abs(a["grad_sigma_t"] - gst).max() < 1e-11 * np.abs(gst).max()
+    # central differences of J = <g, phi> through the dense global solve
+    # (sigma_s and the anisotropic moments held fixed)
+    hstep = 1e-6
+    for gi, c in ((0, 1), (ng - 1, nc - 1)):
+        e = np.zeros_like(st)
+        e[gi, c] = hstep
+        jp = (g * brute.solve(mesh, om, w, st + e, sn[0], q, inc, sigma_sn=sn[1:])[1]).sum()
+        jm = (g * brute.solve(mesh, om, w, st - e, sn[0], q, inc, sigma_sn=sn[1:])[1]).sum()
+        fd = (jp - jm) / (2 * hstep)
+        assert abs(a["grad_sigma_t"][gi, c] - fd) < 1e-7 * abs(fd)
