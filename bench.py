@@ -153,25 +153,25 @@ def main():
     solves = st["solves_per_sweep"]
     phi = torch.zeros((p["groups"], prob.ncell, 8), dtype=torch.float32, device="cuda")
 
-    for i in range(args.warmup):
-        prob.si_step(phi)
+    # the steps run as one source iteration of exactly K iterations (the
+    # library overlaps each iteration's sweep with the previous residual
+    # readback); warmup likewise
+    prob.set_si_criterion("fixed")
+    if args.warmup:
+        phi, _ = prob.source_iterate(phi0=phi, tol=0.0, max_iter=args.warmup)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
     prob.set_timing(True)
-    kern_ms = 0.0
-    kern_launches = 0
-    resid = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        resid = prob.si_step(phi)
-        ms, nl = prob.kernel_time()
-        kern_ms += ms
-        kern_launches += nl
+    phi, info = prob.source_iterate(phi0=phi, tol=0.0, max_iter=args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    kern_ms, kern_launches = prob.kernel_time()
     prob.set_timing(False)
+    resid = info["resid"]
+    assert info["iters"] == args.steps
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = solves * args.steps / wall

@@ -156,10 +156,12 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
  * asynchronously on the stream; the caller keeps ownership).  The moments
  * start from zero in every dgsn_source_iterate call (a resumed run restarts
  * them).  Its sweeps use the problem's schedule and tile edge, at most 2
- * (larger tiles would spill registers).  Single sweeps (dgsn_sweep, batches),
- * the autotuner and the adjoint
- * take isotropic sources only: dgsn_adjoint_solve, and dgsn_source_iterate
- * with a network solver or with store_psi, return DGSN_EUNSUPPORTED while an
+ * (larger tiles would spill registers).  dgsn_adjoint_solve takes the
+ * transposed coupling (the same moment form, with the adjoint flux's
+ * moments); it and a stored angular flux need the mass-inverse solver
+ * DGSN_GE.  Single sweeps (dgsn_sweep, batches) and the autotuner take
+ * isotropic sources only: dgsn_source_iterate with a network solver, and
+ * with store_psi under DGSN_GE_DENSE, returns DGSN_EUNSUPPORTED while an
  * order is set, and so does this call while a group-to-group matrix
  * is set (and dgsn_problem_set_scattering while an order is set).
  * DGSN_ENOMEM if the moment buffers (9 (L+1)^2 G*cells*8 reals) cannot be
@@ -168,8 +170,9 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
 int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream);
 
 /*
- * Flux moments phi_k, k = 1 .. (L+1)^2 - 1, of the last source iteration's
- * final sweep (Eq. (T8) for n >= 1): mom is a device array
+ * Flux moments phi_k, k = 1 .. (L+1)^2 - 1, of the final sweep of the last
+ * source iteration (Eq. (T8) for n >= 1), or of the adjoint flux after a
+ * dgsn_adjoint_solve: mom is a device array
  * [(L+1)^2 - 1][G][Nz*Ny*Nx][8] in the problem precision (copied on the
  * stream).  DGSN_EINVAL without anisotropic scattering.
  */
@@ -281,9 +284,12 @@ int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, int *schedul
 /*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses
  * the FP64 max-norm relative change; DGSN_SI_EPS_S uses the paper's mean
- * pointwise relative change of the cell-average scalar flux, Eq. (Test:Eq3).
+ * pointwise relative change of the cell-average scalar flux, Eq. (Test:Eq3);
+ * DGSN_SI_FIXED runs exactly max_iter iterations (tol and the FP32 stall
+ * stop are not applied; the residuals are still recorded) and returns
+ * DGSN_OK.
  */
-enum { DGSN_SI_MAXNORM = 0, DGSN_SI_EPS_S = 1 };
+enum { DGSN_SI_MAXNORM = 0, DGSN_SI_EPS_S = 1, DGSN_SI_FIXED = 2 };
 int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion);
 
 /*
@@ -368,8 +374,11 @@ int dgsn_problem_stats(const dgsn_problem *p, long long *solves_per_sweep, int *
 /*
  * Kernel timing of the sweep (instrumentation).  With enable != 0 every
  * sweep kernel launch of this problem is bracketed by HIP events on its
- * stream.  dgsn_problem_kernel_time returns, for the most recent sweep, the
- * sum of the kernel durations in milliseconds and the number of launches;
+ * stream.  dgsn_problem_kernel_time returns, for the most recent
+ * dgsn_sweep, dgsn_source_iterate or dgsn_adjoint_solve call, the sum of the
+ * durations of all its sweep kernel launches in milliseconds and the number
+ * of launches (a source iteration that stops at iteration k may also have
+ * timed the sweep of iteration k+1, enqueued ahead of the residual check);
  * it synchronizes the problem's last stream.
  */
 int dgsn_problem_set_timing(dgsn_problem *p, int enable);

@@ -24,6 +24,7 @@ DGSN_ANN = 1
 DGSN_GE_DENSE = 2
 DGSN_SI_MAXNORM = 0
 DGSN_SI_EPS_S = 1
+DGSN_SI_FIXED = 2
 DGSN_SCHED_PLANES = 0
 DGSN_SCHED_DATAFLOW = 1
 

@@ -265,8 +265,10 @@ class Problem:
         return dict(solves_per_sweep=s.value, n_planes=p.value, algo_bytes_per_sweep=b.value)
 
     def set_si_criterion(self, criterion):
-        """'maxnorm' (FP64 max-norm relative change) or 'eps_s' (Eq. (Test:Eq3))."""
-        c = {"maxnorm": _lib.DGSN_SI_MAXNORM, "eps_s": _lib.DGSN_SI_EPS_S}[criterion]
+        """'maxnorm' (FP64 max-norm relative change), 'eps_s' (Eq. (Test:Eq3)) or
+        'fixed' (exactly max_iter iterations)."""
+        c = {"maxnorm": _lib.DGSN_SI_MAXNORM, "eps_s": _lib.DGSN_SI_EPS_S,
+             "fixed": _lib.DGSN_SI_FIXED}[criterion]
         _lib.check(_lib.load().dgsn_problem_set_si_criterion(self._h, c))
 
     def set_tile(self, b):

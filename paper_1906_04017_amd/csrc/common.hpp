@@ -72,6 +72,15 @@ struct DevBuf {
     ~DevBuf() { release(); }
 };
 
+// pinned host memory (hipHostMalloc), for stream-ordered readbacks
+struct HostBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int alloc(size_t n);
+    void release();
+    ~HostBuf() { release(); }
+};
+
 }  // namespace dgsn
 
 struct dgsn_ctx {
@@ -147,7 +156,10 @@ struct dgsn_problem {
     dgsn::DevBuf psi;                         // [D][G][ncell][8] (store_psi)
     dgsn::DevBuf adj_phi, adj_src, grad_oct;  // adjoint work buffers
     dgsn::DevBuf red_partials;                // FP64 reduction partials
-    dgsn::DevBuf red_result;                  // FP64 [4]
+    dgsn::DevBuf red_result;                  // FP64 [2][4]: one slot per iteration in flight
+    dgsn::HostBuf h_result;                   // pinned [2][4] FP64 + [2] error words
+    hipEvent_t ev_result[2] = {nullptr, nullptr};   // each slot's readback is complete
+    dgsn::DevBuf phi_alt;                     // [G][ncell][8] second iterate buffer
     int red_blocks = 0;
 
     // optional per-launch kernel timing of the last sweep

@@ -128,9 +128,33 @@ template <typename Real, int Form, int B>
 void launch_flow_form(const PlaneArgs<Real> &A, const FlowArgs &F, bool store_psi, bool adjoint,
                       dim3 grid, dim3 block, hipStream_t s)
 {
-    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles)
+    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles);
+    // the psi store and the adjoint with the mass-inverse form only
     if constexpr (B <= 2) {
         if (A.nmom > 1) {
+            if constexpr (Form == kFormMassInv) {
+                if (adjoint || store_psi) {
+                    if (A.nmom == 4 && adjoint)
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true, 3>), grid, block,
+                                           0, s, A, F);
+                    else if (A.nmom == 4)
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false, 3>), grid, block,
+                                           0, s, A, F);
+                    else if (A.nmom == 9 && adjoint)
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true, 8>), grid, block,
+                                           0, s, A, F);
+                    else if (A.nmom == 9)
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false, 8>), grid, block,
+                                           0, s, A, F);
+                    else if (adjoint)
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, true, 15>), grid, block,
+                                           0, s, A, F);
+                    else
+                        hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, true, false, 15>), grid, block,
+                                           0, s, A, F);
+                    return;
+                }
+            }
             if (A.nmom == 4)
                 hipLaunchKernelGGL((sweep_flow_ge<Real, Form, B, false, false, 3>), grid, block, 0,
                                    s, A, F);
@@ -202,9 +226,10 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
     const dim3 block(256);
     if ((form == kFormAnnPaper || form == kFormAnn) && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the network solvers run FP32 forward sweeps");
-    if (A.nmom > 1 && (form == kFormAnnPaper || form == kFormAnn || store_psi || adjoint))
-        return set_error(DGSN_EUNSUPPORTED,
-                         "anisotropic sweeps are forward GE sweeps without a psi store");
+    if (A.nmom > 1 && (form == kFormAnnPaper || form == kFormAnn ||
+                       (form == kFormDense && (store_psi || adjoint))))
+        return set_error(DGSN_EUNSUPPORTED, "anisotropic sweeps run the GE solvers (the psi "
+                         "store and the adjoint with the mass-inverse form)");
     if (A.nmom > 1 && ((A.nmom != 4 && A.nmom != 9 && A.nmom != 16) || b > 2))
         return set_error(DGSN_EINVAL, "anisotropic sweeps take (L+1)^2 moments, L = 1..3, and "
                          "tile edges 1..2 (moments %u, tile %d)", A.nmom, b);

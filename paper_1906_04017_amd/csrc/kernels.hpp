@@ -84,7 +84,8 @@ constexpr unsigned kFlowMaxGroupsPerOctant = 1u << 20;
 template <typename Real>
 struct ReduceArgs {
     const Real *phi_oct;       // [8][nv][8]
-    Real *phi;                 // [nv][8] in: previous iterate (if resid), out: new
+    Real *phi;                 // [nv][8] in: previous iterate (if resid, unless phi_prev), out: new
+    const Real *phi_prev;      // [nv][8] previous iterate in a separate buffer (or null)
     long long nv;              // G * ncell
     int resid;                 // compute residual partials
     double *partials;          // [blocks][3]

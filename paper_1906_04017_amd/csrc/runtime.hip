@@ -48,6 +48,28 @@ void DevBuf::release()
     bytes = 0;
 }
 
+int HostBuf::alloc(size_t n)
+{
+    release();
+    if (n == 0) return DGSN_OK;
+    hipError_t e = hipHostMalloc(&ptr, n, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return set_error(DGSN_ENOMEM, "hipHostMalloc(%zu bytes) failed: %s", n,
+                         hipGetErrorString(e));
+    }
+    bytes = n;
+    return DGSN_OK;
+}
+
+void HostBuf::release()
+{
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
 }  // namespace dgsn
 
 using namespace dgsn;
@@ -276,6 +298,18 @@ int flow_prepare(dgsn_problem *p)
     return DGSN_OK;
 }
 
+// Event pairs for `pairs` timed launches in the current call (created on
+// first need and kept).
+int reserve_events(dgsn_problem *p, int pairs)
+{
+    while ((int)p->ev.size() < 2 * pairs) {
+        hipEvent_t e;
+        DGSN_HIP(hipEventCreate(&e));
+        p->ev.push_back(e);
+    }
+    return DGSN_OK;
+}
+
 template <typename Real>
 int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Real *grad_oct,
               hipStream_t s, bool moments = false)
@@ -312,7 +346,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const std::vector<int> &off = tiled ? p->tplane_off[tb] : p->plane_off;
     const int nsteps = tiled ? p->n_tplanes[tb] : p->n_planes;
     p->last_stream = s;
-    p->ev_used = 0;
+    if (p->timing) DGSN_TRY(reserve_events(p, p->ev_used + nsteps));
     if (p->schedule == DGSN_SCHED_DATAFLOW) {
         DGSN_TRY(flow_prepare(p));
         FlowArgs F{};
@@ -324,18 +358,20 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         A.cells = cells;
         A.ncp = off[nsteps];
         DGSN_TRY(launch_flow_reset(F, s));
-        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[0], s));
+        const int e0 = p->ev_used;
+        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[2 * e0], s));
         DGSN_TRY(launch_flow<Real>(A, F, form, tb, store_psi, adjoint, s));
         if (p->timing) {
-            DGSN_HIP(hipEventRecord(p->ev[1], s));
-            p->ev_used = 1;
+            DGSN_HIP(hipEventRecord(p->ev[2 * e0 + 1], s));
+            p->ev_used = e0 + 1;
         }
         return DGSN_OK;
     }
+    const int e0 = p->ev_used;
     for (int pl = 0; pl < nsteps; ++pl) {
         A.cells = cells + off[pl];
         A.ncp = off[pl + 1] - off[pl];
-        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[2 * pl], s));
+        if (p->timing) DGSN_HIP(hipEventRecord(p->ev[2 * (e0 + pl)], s));
         bool done = false;
         if constexpr (sizeof(Real) == 4) {
             if (ann) {
@@ -345,8 +381,8 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         }
         if (!done) DGSN_TRY(launch_tile<Real>(A, form, tb, store_psi, adjoint, s));
         if (p->timing) {
-            DGSN_HIP(hipEventRecord(p->ev[2 * pl + 1], s));
-            p->ev_used = pl + 1;
+            DGSN_HIP(hipEventRecord(p->ev[2 * (e0 + pl) + 1], s));
+            p->ev_used = e0 + pl + 1;
         }
     }
     return DGSN_OK;
@@ -402,6 +438,14 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
 {
     const long long nv = (long long)p->G * p->ncell;
     Real *src = static_cast<Real *>(p->src.ptr);
+    const bool pl = p->pl_order > 0;
+    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
+    if (pl && p->solver == DGSN_ANN)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "anisotropic scattering is available with the GE solvers");
+    if (pl && p->store_psi && p->solver == DGSN_GE_DENSE)
+        return set_error(DGSN_EUNSUPPORTED, "anisotropic scattering stores the angular flux "
+                         "with the mass-inverse GE solver");
     // in-group scattering: the next source is fused into the octant
     // reduction; with a multigroup matrix it is built after it from all groups
     const Real *gg = static_cast<const Real *>(p->sigma_gg.ptr);
@@ -413,33 +457,44 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         DGSN_TRY(launch_build_source<Real>(nv, static_cast<const Real *>(p->q.ptr),
                                            static_cast<const Real *>(p->sigma_s.ptr),
                                            static_cast<const Real *>(phi), src, s));
-    ReduceArgs<Real> R = reduce_args<Real>(p, phi);
-    R.resid = 1;
-    if (!gg) {
-        R.src_next = src;
-        R.q_cell = static_cast<const Real *>(p->q.ptr);
-        R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
-    }
-    double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
-    int it = 0, stall = 0;
-    const bool fp32 = p->precision == DGSN_FP32;
-    p->si_resid.clear();
-    p->si_eps.clear();
-    const bool pl = p->pl_order > 0;
-    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
-    if (pl && p->solver == DGSN_ANN)
-        return set_error(DGSN_EUNSUPPORTED,
-                         "anisotropic scattering is available with the GE solvers");
-    if (pl && p->store_psi)
-        return set_error(DGSN_EUNSUPPORTED,
-                         "anisotropic scattering does not store the angular flux");
     if (pl) {
         // the anisotropic moments start from zero
         DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
         DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
     }
-    while (it < max_iter) {
+    // Pipelined iteration: the sweep of iteration k+1 is enqueued before the
+    // host reads iteration k's residual, so the GPU does not idle during the
+    // readback.  The iterates alternate between the caller's buffer and an
+    // internal one; if iteration k stops the loop, the extra iteration's
+    // outputs are discarded (its sweep's side outputs -- a stored psi, the
+    // anisotropic moments -- would not match the returned iterate, so those
+    // modes iterate without the overlap).  Results are identical either way.
+    const bool overlap = !p->store_psi && !pl;
+    Real *buf[2] = {static_cast<Real *>(phi), nullptr};
+    if (overlap) {
+        if (p->phi_alt.bytes != (size_t)nv * 8 * sizeof(Real))
+            DGSN_TRY(p->phi_alt.alloc((size_t)nv * 8 * sizeof(Real)));
+        buf[1] = static_cast<Real *>(p->phi_alt.ptr);
+    }
+    double *dres = static_cast<double *>(p->red_result.ptr);
+    double *hres = static_cast<double *>(p->h_result.ptr);
+    unsigned *herr = reinterpret_cast<unsigned *>(hres + 8);
+    const bool flow = p->schedule == DGSN_SCHED_DATAFLOW;
+    auto enqueue = [&](int k) -> int {
+        const int slot = k & 1;
         DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s, pl));
+        ReduceArgs<Real> R = reduce_args<Real>(p, buf[0]);
+        R.resid = 1;
+        if (overlap) {
+            R.phi_prev = buf[slot];
+            R.phi = buf[slot ^ 1];
+        }
+        R.result = dres + 4 * slot;
+        if (!gg) {
+            R.src_next = src;
+            R.q_cell = static_cast<const Real *>(p->q.ptr);
+            R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+        }
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
         if (pl)
             DGSN_TRY(launch_reduce_moments<Real>(
@@ -449,27 +504,67 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G,
                                                   static_cast<const Real *>(p->q.ptr), nullptr,
-                                                  gg, static_cast<const Real *>(phi), src, false,
-                                                  s));
-        double res[3];
-        DGSN_TRY(read_result(p, s, res));
-        ++it;
+                                                  gg, R.phi, src, false, s));
+        DGSN_HIP(hipMemcpyAsync(hres + 4 * slot, dres + 4 * slot, 3 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        if (flow)
+            DGSN_HIP(hipMemcpyAsync(herr + slot,
+                                    static_cast<unsigned *>(p->d_flow_sync.ptr) + kFlowError,
+                                    sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        DGSN_HIP(hipEventRecord(p->ev_result[slot], s));
+        return DGSN_OK;
+    };
+    double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
+    int it = 0, stall = 0;
+    const bool fp32 = p->precision == DGSN_FP32;
+    const bool fixed = p->si_criterion == DGSN_SI_FIXED;
+    p->si_resid.clear();
+    p->si_eps.clear();
+    DGSN_TRY(enqueue(0));
+    for (int k = 0;; ++k) {
+        const bool ahead = overlap && k + 1 < max_iter;
+        if (ahead) DGSN_TRY(enqueue(k + 1));
+        DGSN_HIP(hipEventSynchronize(p->ev_result[k & 1]));
+        if (flow && herr[k & 1] != 0u) {
+            DGSN_HIP(hipStreamSynchronize(s));
+            DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
+            DGSN_HIP(hipStreamSynchronize(s));
+            return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its "
+                             "results are invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
+        }
+        const double *res = hres + 4 * (k & 1);
+        it = k + 1;
         r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
         es = res[2] / (double)nv;
         p->si_resid.push_back(r);
         p->si_eps.push_back(es);
-        if (!std::isfinite(r))
+        if (!std::isfinite(r)) {
+            DGSN_HIP(hipStreamSynchronize(s));
             return set_error(DGSN_EINVAL, "source iteration produced a non-finite residual");
-        crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
-        if (crit < tol) break;
-        if (fp32) {
-            if (crit < best) { best = crit; stall = 0; }
-            else if (++stall >= 5) break;
         }
+        crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
+        bool stop = it >= max_iter;
+        if (!fixed) {
+            if (crit < tol) stop = true;
+            if (fp32) {
+                if (crit < best) { best = crit; stall = 0; }
+                else if (++stall >= 5) stop = true;
+            }
+        }
+        if (stop) {
+            // iterate `it` is in buf[it & 1] (overlap) or in place
+            if (overlap && (it & 1))
+                DGSN_HIP(hipMemcpyAsync(phi, buf[1], (size_t)nv * 8 * sizeof(Real),
+                                        hipMemcpyDeviceToDevice, s));
+            break;
+        }
+        if (!ahead) DGSN_TRY(enqueue(k + 1));
     }
+    DGSN_HIP(hipStreamSynchronize(s));
     if (iters) *iters = it;
     if (resid) *resid = r;
     if (eps_s) *eps_s = es;
+    if (fixed) return DGSN_OK;
     if (!(crit < tol))
         return set_error(DGSN_ENOTCONV, "source iteration stopped after %d sweeps at residual %.3e",
                          it, crit);
@@ -506,9 +601,21 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
     double r = INFINITY, best = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
+    // anisotropic scattering: the moments of the adjoint flux, from zero
+    const bool pl = p->pl_order > 0;
+    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
+    if (pl) {
+        DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
+        DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    }
     while (it < max_iter) {
-        DGSN_TRY(run_sweep<Real>(p, asrc, false, true, nullptr, s));
+        DGSN_TRY(run_sweep<Real>(p, asrc, false, true, nullptr, s, pl));
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+        if (pl)
+            DGSN_TRY(launch_reduce_moments<Real>(
+                nv, nm, static_cast<const Real *>(p->mom_oct.ptr),
+                static_cast<const Real *>(p->sigma_sn.ptr), static_cast<Real *>(p->mom.ptr),
+                static_cast<Real *>(p->msrc.ptr), s));
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg, phid, asrc,
                                                   true, s));
@@ -526,7 +633,7 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
     }
     // contraction sweep with the converged adjoint scalar flux
     Real *goct = static_cast<Real *>(p->grad_oct.ptr);
-    DGSN_TRY(run_sweep<Real>(p, asrc, false, true, goct, s));
+    DGSN_TRY(run_sweep<Real>(p, asrc, false, true, goct, s, pl));
     DGSN_TRY(launch_reduce_grad<Real>(nv, goct, static_cast<Real *>(gst), static_cast<Real *>(gq),
                                       s));
     DGSN_HIP(hipStreamSynchronize(s));
@@ -541,6 +648,8 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
 dgsn_problem::~dgsn_problem()
 {
     for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_result)
         if (e) (void)hipEventDestroy(e);
 }
 
@@ -857,8 +966,12 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     if (p->store_psi && (rc = p->psi.alloc((size_t)p->D * nv * 8 * rs))) return fail(rc);
     p->red_blocks = reduce_blocks_for(nv);
     if ((rc = p->red_partials.alloc((size_t)p->red_blocks * 3 * sizeof(double))) ||
-        (rc = p->red_result.alloc(4 * sizeof(double))))
+        (rc = p->red_result.alloc(8 * sizeof(double))) ||
+        (rc = p->h_result.alloc(8 * sizeof(double) + 2 * sizeof(unsigned))))
         return fail(rc);
+    if (hipEventCreateWithFlags(&p->ev_result[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_result[1], hipEventDisableTiming) != hipSuccess)
+        return fail(set_error(DGSN_EHIP, "event creation failed"));
     if (hipMemset(p->sigma_t.ptr, 0, nv * rs) != hipSuccess ||
         hipMemset(p->sigma_s.ptr, 0, nv * rs) != hipSuccess ||
         hipMemset(p->q.ptr, 0, nv * rs) != hipSuccess)
@@ -1048,8 +1161,9 @@ int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion)
 {
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
-    if (criterion != DGSN_SI_MAXNORM && criterion != DGSN_SI_EPS_S)
-        return set_error(DGSN_EINVAL, "criterion must be DGSN_SI_MAXNORM or DGSN_SI_EPS_S");
+    if (criterion != DGSN_SI_MAXNORM && criterion != DGSN_SI_EPS_S && criterion != DGSN_SI_FIXED)
+        return set_error(DGSN_EINVAL,
+                         "criterion must be DGSN_SI_MAXNORM, DGSN_SI_EPS_S or DGSN_SI_FIXED");
     p->si_criterion = criterion;
     return DGSN_OK;
 }
@@ -1059,10 +1173,6 @@ int dgsn_problem_set_timing(dgsn_problem *p, int enable)
     clear_error();
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
-    if (enable && p->ev.empty()) {
-        p->ev.assign(2 * p->n_planes, nullptr);   // the cell schedule has the most steps
-        for (auto &e : p->ev) DGSN_HIP(hipEventCreate(&e));
-    }
     p->timing = enable ? 1 : 0;
     p->ev_used = 0;
     return DGSN_OK;
@@ -1103,6 +1213,7 @@ int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream)
     if (!p || !src || !phi) return set_error(DGSN_EINVAL, "problem, src and phi must be set");
     if (src == phi) return set_error(DGSN_EINVAL, "src and phi must not overlap");
     DGSN_HIP(hipSetDevice(p->ctx->device));
+    p->ev_used = 0;
     return p->precision == DGSN_FP64 ? sweep_impl<double>(p, src, phi, as_stream(stream))
                                      : sweep_impl<float>(p, src, phi, as_stream(stream));
 }
@@ -1115,6 +1226,7 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
     if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
     if (!(tol >= 0.0)) return set_error(DGSN_EINVAL, "tol must be >= 0");
     DGSN_HIP(hipSetDevice(p->ctx->device));
+    p->ev_used = 0;
     return p->precision == DGSN_FP64
                ? source_iterate_impl<double>(p, phi, tol, max_iter, iters, resid, eps_s,
                                              as_stream(stream))
@@ -1145,10 +1257,12 @@ int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, d
         return set_error(DGSN_EINVAL, "the adjoint needs a problem created with store_psi = 1");
     if (p->solver == DGSN_ANN)
         return set_error(DGSN_EUNSUPPORTED, "the adjoint is defined for the GE solvers");
-    if (p->pl_order > 0)
-        return set_error(DGSN_EUNSUPPORTED, "the adjoint has isotropic scattering only");
+    if (p->pl_order > 0 && p->solver == DGSN_GE_DENSE)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "the anisotropic adjoint runs with the mass-inverse GE solver");
     if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
     DGSN_HIP(hipSetDevice(p->ctx->device));
+    p->ev_used = 0;
     return p->precision == DGSN_FP64
                ? adjoint_impl<double>(p, gphi, gst, gq, tol, max_iter, iters, as_stream(stream))
                : adjoint_impl<float>(p, gphi, gst, gq, tol, max_iter, iters, as_stream(stream));

@@ -74,10 +74,11 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
         }
         Real *ph = R.phi + e * 8;
         if (R.resid) {
+            const Real *po = R.phi_prev ? R.phi_prev + e * 8 : ph;
             double an = 0.0, ao = 0.0;
 #pragma unroll
             for (int n = 0; n < 8; ++n) {
-                const double vn = (double)nw[n], vo = (double)ph[n];
+                const double vn = (double)nw[n], vo = (double)po[n];
                 dmax = fmax_d(dmax, fabs(vn - vo));
                 fmax = fmax_d(fmax, fabs(vn));
                 an += vn;
@@ -273,9 +274,33 @@ template <typename Real, int Form, int B>
 void launch_tile_form(const PlaneArgs<Real> &A, bool store_psi, bool adjoint, dim3 grid,
                       dim3 block, hipStream_t s)
 {
-    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles)
+    // anisotropic sweeps: tile edges 1 and 2 (the run clamps larger tiles);
+    // the psi store and the adjoint with the mass-inverse form only
     if constexpr (B <= 2) {
         if (A.nmom > 1) {
+            if constexpr (Form == kFormMassInv) {
+                if (adjoint || store_psi) {
+                    if (A.nmom == 4 && adjoint)
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, true, 3>), grid, block,
+                                           0, s, A);
+                    else if (A.nmom == 4)
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, true, false, 3>), grid, block,
+                                           0, s, A);
+                    else if (A.nmom == 9 && adjoint)
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, true, 8>), grid, block,
+                                           0, s, A);
+                    else if (A.nmom == 9)
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, true, false, 8>), grid, block,
+                                           0, s, A);
+                    else if (adjoint)
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, true, 15>), grid, block,
+                                           0, s, A);
+                    else
+                        hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, true, false, 15>), grid, block,
+                                           0, s, A);
+                    return;
+                }
+            }
             if (A.nmom == 4)
                 hipLaunchKernelGGL((sweep_tile_ge<Real, Form, B, false, false, 3>), grid, block, 0,
                                    s, A);
@@ -346,9 +371,9 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
     const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
     if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
-    if (A.nmom > 1 && (form == kFormAnnPaper || store_psi || adjoint))
-        return set_error(DGSN_EUNSUPPORTED,
-                         "anisotropic sweeps are forward GE sweeps without a psi store");
+    if (A.nmom > 1 && (form == kFormAnnPaper || (form == kFormDense && (store_psi || adjoint))))
+        return set_error(DGSN_EUNSUPPORTED, "anisotropic sweeps run the GE solvers (the psi "
+                         "store and the adjoint with the mass-inverse form)");
     if (A.nmom > 1 && ((A.nmom != 4 && A.nmom != 9 && A.nmom != 16) || b > 2))
         return set_error(DGSN_EINVAL, "anisotropic sweeps take (L+1)^2 moments, L = 1..3, and "
                          "tile edges 1..2 (moments %u, tile %d)", A.nmom, b);

@@ -221,6 +221,44 @@ def test_source_iteration_resume_from_saved_phi(api, ctx):
     assert rel(rest.cpu().numpy(), full.cpu().numpy()) <= 1e-10
 
 
+@pytest.mark.parametrize("precision,schedule", [("fp32", "dataflow"), ("fp32", "planes"),
+                                                 ("fp64", "planes")])
+def test_overlapped_iteration_equals_serial(api, ctx, precision, schedule):
+    # source iteration overlaps each sweep with the previous residual
+    # readback on alternating iterate buffers; a problem that stores psi
+    # iterates serially in place.  Both must give the same iterates, residuals
+    # and counts, for stops at odd and even iteration counts.
+    p = inputs.blocky_scatter(n=12, groups=3, seed=5, order=4)
+    print_case("overlapped_si", name=p["name"], precision=precision, schedule=schedule)
+    a = gpu_problem(api, ctx, p, precision)
+    b = gpu_problem(api, ctx, p, precision, store_psi=True)
+    for prob in (a, b):
+        prob.set_schedule(schedule)
+        prob.set_si_criterion("fixed")
+    for k in (1, 2, 3, 6):
+        pa, ia = a.source_iterate(tol=0.0, max_iter=k)
+        pb, ib = b.source_iterate(tol=0.0, max_iter=k)
+        assert ia["iters"] == ib["iters"] == k
+        assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy()), k
+        assert np.array_equal(a.si_history()[0], b.si_history()[0])
+    # stopping by the tolerance
+    for prob in (a, b):
+        prob.set_si_criterion("maxnorm")
+    tol = 1e-5 if precision == "fp32" else 1e-9
+    pa, ia = a.source_iterate(tol=tol, max_iter=500, allow_notconv=True)
+    pb, ib = b.source_iterate(tol=tol, max_iter=500, allow_notconv=True)
+    assert ia["iters"] == ib["iters"] and ia["resid"] == ib["resid"]
+    assert np.array_equal(pa.cpu().numpy(), pb.cpu().numpy())
+    # the kernel timing covers every sweep of the call
+    a.set_timing(True)
+    a.set_si_criterion("fixed")
+    a.source_iterate(tol=0.0, max_iter=4)
+    ms, launches = a.kernel_time()
+    assert ms > 0 and launches >= 4 and launches % 4 == 0
+    assert schedule != "dataflow" or launches == 4
+    a.set_timing(False)
+
+
 def test_source_iteration_history_matches_oracle_steps(api, ctx):
     """The recorded residual and eps_S of every iteration equal the oracle's
     after one step from the same iterate, and the effective spectral radius
@@ -350,7 +388,7 @@ def test_pl_constant_solution(api, ctx):
 
 def test_pl_rejections(api, ctx):
     p = inputs.random_problem((3, 3, 3), 4, 2, seed=133, c_max=0.5)
-    prob = gpu_problem(api, ctx, p, "fp32", store_psi=True)
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ge_dense", store_psi=True)
     sn = inputs.anisotropic_orders(p["sigma_s"], 1, seed=134)
     with pytest.raises(api.DgsnError, match="EINVAL"):
         prob.moments()
@@ -359,6 +397,7 @@ def test_pl_rejections(api, ctx):
     prob.set_anisotropy(sn)
     with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
         prob.set_scattering(np.zeros((2, 2, 27)))
+    # the psi store and the adjoint take the mass-inverse form
     with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
         prob.source_iterate(tol=1e-6, max_iter=200, allow_notconv=True)
     with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
@@ -367,6 +406,34 @@ def test_pl_rejections(api, ctx):
     prob.set_scattering(np.zeros((2, 2, 27)))
     with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
         prob.set_anisotropy(sn)
+
+
+@pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 3)])
+def test_pl_adjoint_matches_oracle(api, ctx, precision, L):
+    p = inputs.random_problem((5, 4, 4), 4, 2, seed=140 + L, c_max=0.7,
+                              length=(0.5, 0.4, 0.4))
+    sn = inputs.anisotropic_orders(p["sigma_s"], L, seed=150 + L)
+    print_case("pl_adjoint", name=p["name"], precision=precision, L=L)
+    prob = gpu_problem(api, ctx, p, precision, store_psi=True)
+    prob.set_anisotropy(sn)
+    tol = 1e-13 if precision == "fp64" else 1e-7
+    prob.source_iterate(tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    rng = np.random.default_rng(160 + L)
+    g = rng.uniform(0.0, 1.0, (2, p["sigma_t"].shape[1], 8))
+    gst, gq, info = prob.adjoint(g, tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    om, w = oracle.lq_n(4)
+    full = np.concatenate([p["sigma_s"][None], sn])
+    r = oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"], full, p["q"], p["psi_inc"],
+                                 tol=1e-15, max_iter=3000, store_psi=True)
+    a = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], r["psi"], r["phi"], g,
+                       tol=1e-15, sigma_sn=full)
+    bound = 1e-9 if precision == "fp64" else 1e-4
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= bound
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= bound
+    # the anisotropy is felt in the gradients
+    iso = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], r["psi"], r["phi"], g,
+                         tol=1e-15)
+    assert rel(iso["grad_q"], a["grad_q"]) > 100 * bound
 
 
 # ---------------------------------------------------------------------------
