@@ -576,31 +576,22 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
                  int *iters, hipStream_t s)
 {
     const long long nv = (long long)p->G * p->ncell;
-    if (!p->adj_phi.ptr) {
-        DGSN_TRY(p->adj_phi.alloc(nv * 8 * p->real_size));
-        DGSN_TRY(p->adj_src.alloc(2 * nv * 8 * p->real_size));   // load and source
+    if (p->adj_phi.bytes != (size_t)(2 * nv * 8) * p->real_size) {
+        DGSN_TRY(p->adj_phi.alloc(2 * nv * 8 * p->real_size));   // two adjoint iterates
+        DGSN_TRY(p->adj_src.alloc(3 * nv * 8 * p->real_size));   // load and two sources
         DGSN_TRY(p->grad_oct.alloc(8 * nv * 2 * p->real_size));
     }
-    Real *phid = static_cast<Real *>(p->adj_phi.ptr);
+    Real *phid[2] = {static_cast<Real *>(p->adj_phi.ptr),
+                     static_cast<Real *>(p->adj_phi.ptr) + nv * 8};
     Real *load = static_cast<Real *>(p->adj_src.ptr);
-    Real *asrc = load + nv * 8;
+    Real *asrc[2] = {load + nv * 8, load + 2 * nv * 8};
     const double vol = p->h[0] * p->h[1] * p->h[2];
     DGSN_TRY(launch_adjoint_load<Real>(nv, static_cast<const Real *>(gphi), vol, load, s));
-    DGSN_HIP(hipMemsetAsync(phid, 0, nv * 8 * sizeof(Real), s));
-    DGSN_HIP(hipMemcpyAsync(asrc, load, nv * 8 * sizeof(Real), hipMemcpyDeviceToDevice, s));
+    DGSN_HIP(hipMemsetAsync(phid[0], 0, nv * 8 * sizeof(Real), s));
+    DGSN_HIP(hipMemcpyAsync(asrc[0], load, nv * 8 * sizeof(Real), hipMemcpyDeviceToDevice, s));
     // adjoint source load + sigma_s^T phi_dag / (4 pi): fused in-group, or
     // the transposed multigroup coupling after the reduction
     const Real *gg = static_cast<const Real *>(p->sigma_gg.ptr);
-    ReduceArgs<Real> R = reduce_args<Real>(p, phid);
-    R.resid = 1;
-    if (!gg) {
-        R.src_next = asrc;
-        R.q_nodal = load;
-        R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
-    }
-    double r = INFINITY, best = INFINITY;
-    int it = 0, stall = 0;
-    const bool fp32 = p->precision == DGSN_FP32;
     // anisotropic scattering: the moments of the adjoint flux, from zero
     const bool pl = p->pl_order > 0;
     const int nm = (p->pl_order + 1) * (p->pl_order + 1);
@@ -608,8 +599,30 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
         DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
         DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
     }
-    while (it < max_iter) {
-        DGSN_TRY(run_sweep<Real>(p, asrc, false, true, nullptr, s, pl));
+    // Iteration k sweeps with asrc[k & 1] and reduces phid[k & 1] ->
+    // phid[(k + 1) & 1], writing the next source into asrc[(k + 1) & 1];
+    // as in source iteration, iteration k+1 is enqueued before the host
+    // reads iteration k's residual (serially with anisotropic scattering,
+    // whose moments are a single buffer).  A discarded look-ahead iteration
+    // touches neither the final iterate nor the source of the contraction
+    // sweep.
+    const bool overlap = !pl;
+    double *dres = static_cast<double *>(p->red_result.ptr);
+    double *hres = static_cast<double *>(p->h_result.ptr);
+    unsigned *herr = reinterpret_cast<unsigned *>(hres + 8);
+    const bool flow = p->schedule == DGSN_SCHED_DATAFLOW;
+    auto enqueue = [&](int k) -> int {
+        const int slot = k & 1;
+        DGSN_TRY(run_sweep<Real>(p, asrc[slot], false, true, nullptr, s, pl));
+        ReduceArgs<Real> R = reduce_args<Real>(p, phid[slot ^ 1]);
+        R.resid = 1;
+        R.phi_prev = phid[slot];
+        R.result = dres + 4 * slot;
+        if (!gg) {
+            R.src_next = asrc[slot ^ 1];
+            R.q_nodal = load;
+            R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
+        }
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
         if (pl)
             DGSN_TRY(launch_reduce_moments<Real>(
@@ -617,23 +630,50 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
                 static_cast<const Real *>(p->sigma_sn.ptr), static_cast<Real *>(p->mom.ptr),
                 static_cast<Real *>(p->msrc.ptr), s));
         if (gg)
-            DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg, phid, asrc,
-                                                  true, s));
-        double res[3];
-        DGSN_TRY(read_result(p, s, res));
-        ++it;
-        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
-        if (!std::isfinite(r))
-            return set_error(DGSN_EINVAL, "adjoint iteration produced a non-finite residual");
-        if (r < tol) break;
-        if (fp32) {
-            if (r < best) { best = r; stall = 0; }
-            else if (++stall >= 5) break;
+            DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg,
+                                                  phid[slot ^ 1], asrc[slot ^ 1], true, s));
+        DGSN_HIP(hipMemcpyAsync(hres + 4 * slot, dres + 4 * slot, 3 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        if (flow)
+            DGSN_HIP(hipMemcpyAsync(herr + slot,
+                                    static_cast<unsigned *>(p->d_flow_sync.ptr) + kFlowError,
+                                    sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        DGSN_HIP(hipEventRecord(p->ev_result[slot], s));
+        return DGSN_OK;
+    };
+    double r = INFINITY, best = INFINITY;
+    int it = 0, stall = 0;
+    const bool fp32 = p->precision == DGSN_FP32;
+    DGSN_TRY(enqueue(0));
+    for (int k = 0;; ++k) {
+        const bool ahead = overlap && k + 1 < max_iter;
+        if (ahead) DGSN_TRY(enqueue(k + 1));
+        DGSN_HIP(hipEventSynchronize(p->ev_result[k & 1]));
+        if (flow && herr[k & 1] != 0u) {
+            DGSN_HIP(hipStreamSynchronize(s));
+            DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
+            DGSN_HIP(hipStreamSynchronize(s));
+            return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its "
+                             "results are invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
         }
+        const double *res = hres + 4 * (k & 1);
+        it = k + 1;
+        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
+        if (!std::isfinite(r)) {
+            DGSN_HIP(hipStreamSynchronize(s));
+            return set_error(DGSN_EINVAL, "adjoint iteration produced a non-finite residual");
+        }
+        bool stop = it >= max_iter || r < tol;
+        if (fp32 && !stop) {
+            if (r < best) { best = r; stall = 0; }
+            else if (++stall >= 5) stop = true;
+        }
+        if (stop) break;
+        if (!ahead) DGSN_TRY(enqueue(k + 1));
     }
-    // contraction sweep with the converged adjoint scalar flux
+    // contraction sweep with the converged adjoint flux's source
     Real *goct = static_cast<Real *>(p->grad_oct.ptr);
-    DGSN_TRY(run_sweep<Real>(p, asrc, false, true, goct, s, pl));
+    DGSN_TRY(run_sweep<Real>(p, asrc[it & 1], false, true, goct, s, pl));
     DGSN_TRY(launch_reduce_grad<Real>(nv, goct, static_cast<Real *>(gst), static_cast<Real *>(gq),
                                       s));
     DGSN_HIP(hipStreamSynchronize(s));
