@@ -66,11 +66,13 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
         Real nw[8];
 #pragma unroll
         for (int n = 0; n < 8; ++n) nw[n] = 0;
+        // the octant partials are read once: non-temporal loads keep them
+        // from displacing the sweep's fronts in the last-level cache
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const Real *p = R.phi_oct + ((long long)o * R.nv + e) * 8;
 #pragma unroll
-            for (int n = 0; n < 8; ++n) nw[n] += p[n];
+            for (int n = 0; n < 8; ++n) nw[n] += __builtin_nontemporal_load(p + n);
         }
         Real *ph = R.phi + e * 8;
         if (R.resid) {
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
             double an = 0.0, ao = 0.0;
 #pragma unroll
             for (int n = 0; n < 8; ++n) {
-                const double vn = (double)nw[n], vo = (double)po[n];
+                const double vn = (double)nw[n], vo = (double)__builtin_nontemporal_load(po + n);
                 dmax = fmax_d(dmax, fabs(vn - vo));
                 fmax = fmax_d(fmax, fabs(vn));
                 an += vn;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
             esum += (an != 0.0) ? fabs(an - ao) / fabs(an) : (ao != 0.0 ? 1.0 : 0.0);
         }
 #pragma unroll
-        for (int n = 0; n < 8; ++n) ph[n] = nw[n];
+        for (int n = 0; n < 8; ++n) __builtin_nontemporal_store(nw[n], ph + n);
         if (R.src_next) {
             const Real ss = R.sigma_s ? R.sigma_s[e] * Real(kInv4Pi) : Real(0);
             const Real qc = R.q_cell ? R.q_cell[e] : Real(0);
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
         const int n = r / nk;
         const int k = r - n * nk + 1;
         Real s = 0;
-        for (int o = 0; o < 8; ++o) s += mom_oct[(long long)o * total + e];
+        for (int o = 0; o < 8; ++o) s += __builtin_nontemporal_load(mom_oct + (long long)o * total + e);
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
         mom[((long long)(k - 1) * nv + gc) * 8 + n] = s;
         msrc[(gc * nk + (k - 1)) * 8 + n] = sigma_sn[(long long)(order - 1) * nv + gc] * s;

@@ -541,11 +541,13 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                             }
                             Real *mo = A.mom_oct + ((size_t)out + (n ^ mask)) * kMom;
 #pragma unroll
-                            for (int k = 0; k < kMom; ++k) mo[k] = mk[k];
+                            for (int k = 0; k < kMom; ++k) __builtin_nontemporal_store(mk[k], mo + k);
                         } else {
                             for (int e = 0; e < (int)A.Do; ++e) s += rb[(base + e) * 9 + n];
                         }
-                        A.phi_oct[out + (n ^ mask)] = s;
+                        // written once, read once by the octant reduction: a
+                        // non-temporal store leaves the cache to the fronts
+                        __builtin_nontemporal_store(s, A.phi_oct + out + (n ^ mask));
                     }
                     if (kAdjoint && A.grad_oct) {
                         for (int k2 = d; k2 < 2; k2 += (int)A.Do) {
