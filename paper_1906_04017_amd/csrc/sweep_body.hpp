@@ -547,7 +547,13 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                         }
                         // written once, read once by the octant reduction: a
                         // non-temporal store leaves the cache to the fronts
-                        __builtin_nontemporal_store(s, A.phi_oct + out + (n ^ mask));
+                        // where one store covers a cell's nodes (6 or more
+                        // direction lanes); with fewer, a lane stores several
+                        // nodes and the cache has to merge them
+                        if (A.Do >= 6)
+                            __builtin_nontemporal_store(s, A.phi_oct + out + (n ^ mask));
+                        else
+                            A.phi_oct[out + (n ^ mask)] = s;
                     }
                     if (kAdjoint && A.grad_oct) {
                         for (int k2 = d; k2 < 2; k2 += (int)A.Do) {
