@@ -362,6 +362,19 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
         K0 = (pt >> 20) * B;
     }
     const uint32_t slot = (o * A.Do + d) * A.G + g;
+    // the tile's first cell: its front slots and its physical cell index; the
+    // other cells of the tile step from them by whole strides (il, jl, kl are
+    // compile-time in the unrolled body), so no per-cell multiplies remain
+    const uint32_t ex0 = o * A.fx_o + K0 * A.fx_k + J0 * A.fx_j + dg * 4;
+    const uint32_t ey0 = o * A.fy_o + K0 * A.fy_k + I0 * A.fy_j + dg * 4;
+    const uint32_t ez0 = o * A.fz_o + J0 * A.fz_k + I0 * A.fz_j + dg * 4;
+    const uint32_t nxy = A.nx * A.ny;
+    const uint32_t c0 = ((mask & 1) ? A.nx - 1 - I0 : I0) +
+                        A.nx * ((mask & 2) ? A.ny - 1 - J0 : J0) +
+                        nxy * ((mask & 4) ? A.nz - 1 - K0 : K0);
+    const uint32_t sx = (mask & 1) ? 0u - 1u : 1u;          // physical steps of il, jl, kl
+    const uint32_t sy = (mask & 2) ? 0u - A.nx : A.nx;      // (modulo 2^32)
+    const uint32_t sz = (mask & 4) ? 0u - nxy : nxy;
     const __amdgpu_buffer_rsrc_t rx = front_rsrc(A.fx, 8 * A.fx_o);
     const __amdgpu_buffer_rsrc_t ry = front_rsrc(A.fy, 8 * A.fy_o);
     const __amdgpu_buffer_rsrc_t rz = front_rsrc(A.fz, 8 * A.fz_o);
@@ -384,10 +397,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                 uint32_t ex = 0, ey = 0, ez = 0;   // front slots (elements)
                 // gather: sigma_t, the reflected source and the three inflows
                 if (ok) {
-                    const uint32_t i = (mask & 1) ? A.nx - 1 - ic : ic;
-                    const uint32_t j = (mask & 2) ? A.ny - 1 - jc : jc;
-                    const uint32_t k = (mask & 4) ? A.nz - 1 - kc : kc;
-                    c = i + A.nx * (j + A.ny * k);
+                    c = c0 + il * sx + jl * sy + kl * sz;
                     const uint32_t gc = g * A.ncell + c;
                     st = A.sigma_t[gc];
                     if constexpr (Form == kFormDense) {
@@ -399,9 +409,9 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                         load8_reflect(A.src + gc * 8, mask, sc);
                     }
                     if constexpr (kMom > 0) add_moment_source<Real, kMom>(A, yl, gc, mask, sc);
-                    ex = o * A.fx_o + kc * A.fx_k + jc * A.fx_j + dg * 4;
-                    ey = o * A.fy_o + kc * A.fy_k + ic * A.fy_j + dg * 4;
-                    ez = o * A.fz_o + jc * A.fz_k + ic * A.fz_j + dg * 4;
+                    ex = ex0 + kl * A.fx_k + jl * A.fx_j;
+                    ey = ey0 + kl * A.fy_k + il * A.fy_j;
+                    ez = ez0 + jl * A.fz_k + il * A.fz_j;
                     if (il > 0) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) vx[e] = xf[e];
