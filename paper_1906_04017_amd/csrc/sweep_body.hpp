@@ -379,6 +379,24 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     const __amdgpu_buffer_rsrc_t ry = front_rsrc(A.fy, 8 * A.fy_o);
     const __amdgpu_buffer_rsrc_t rz = front_rsrc(A.fz, 8 * A.fz_o);
     Real xf[4] = {0, 0, 0, 0}, yf[B][4] = {}, zf[B][B][4] = {};
+    // FP32 mass-inverse and matrix-core network kernels load the next cell's
+    // sigma_t and source while the current cell is solved: the loads are
+    // unconditional (an invalid cell reads element 0), so they can leave a
+    // cell ahead.  The dense, paper-form network and FP64 kernels would lose
+    // a wave per SIMD to the 9 (18) registers, and anisotropic sweeps load
+    // their moment sources per cell.
+    constexpr bool kPrefetch = sizeof(Real) == 4 && (Form == kFormMassInv || Form == kFormAnn) &&
+                               kMom == 0;
+    const uint32_t gbase = g * A.ncell;
+    auto cell_ok = [&](int il2, int jl2, int kl2) {
+        return tvalid && I0 + il2 < A.nx && J0 + jl2 < A.ny && K0 + kl2 < A.nz;
+    };
+    Real pst = 0, psc[8];
+    if constexpr (kPrefetch) {
+        const uint32_t gc = cell_ok(0, 0, 0) ? gbase + c0 : 0u;
+        pst = A.sigma_t[gc];
+        load8_reflect(A.src + gc * 8, mask, psc);
+    }
     // layers of the tile (kl) are a rolled loop for B > 2 (the layer body,
     // B^2 cells, is unrolled so that every register front index is static)
 #pragma unroll(B <= 2 ? B : 1)
@@ -395,18 +413,36 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                 Real gs = 0, gq = 0;
                 Real st = 0, sc[8], vx[4], vy[4], vz[4];
                 uint32_t ex = 0, ey = 0, ez = 0;   // front slots (elements)
+                if constexpr (kPrefetch) {
+                    st = pst;
+#pragma unroll
+                    for (int n = 0; n < 8; ++n) sc[n] = psc[n];
+                    // the next cell of the tile in upwind order
+                    const int il2 = il + 1 < B ? il + 1 : 0;
+                    const int jl2 = il + 1 < B ? jl : (jl + 1 < B ? jl + 1 : 0);
+                    const int kl2 = (il + 1 < B || jl + 1 < B) ? kl : kl + 1;
+                    if (kl2 < B) {
+                        const uint32_t gc = cell_ok(il2, jl2, kl2)
+                                                ? gbase + c0 + il2 * sx + jl2 * sy + kl2 * sz
+                                                : 0u;
+                        pst = A.sigma_t[gc];
+                        load8_reflect(A.src + gc * 8, mask, psc);
+                    }
+                }
                 // gather: sigma_t, the reflected source and the three inflows
                 if (ok) {
                     c = c0 + il * sx + jl * sy + kl * sz;
-                    const uint32_t gc = g * A.ncell + c;
-                    st = A.sigma_t[gc];
-                    if constexpr (Form == kFormDense) {
-                        // (the address form costs this kernel a wave per SIMD)
-                        load4(A.src + gc * 8, sc);
-                        load4(A.src + gc * 8 + 4, sc + 4);
-                        reflect8(sc, mask);
-                    } else {
-                        load8_reflect(A.src + gc * 8, mask, sc);
+                    const uint32_t gc = gbase + c;
+                    if constexpr (!kPrefetch) {
+                        st = A.sigma_t[gc];
+                        if constexpr (Form == kFormDense) {
+                            // (the address form costs this kernel a wave per SIMD)
+                            load4(A.src + gc * 8, sc);
+                            load4(A.src + gc * 8 + 4, sc + 4);
+                            reflect8(sc, mask);
+                        } else {
+                            load8_reflect(A.src + gc * 8, mask, sc);
+                        }
                     }
                     if constexpr (kMom > 0) add_moment_source<Real, kMom>(A, yl, gc, mask, sc);
                     ex = ex0 + kl * A.fx_k + jl * A.fx_j;
