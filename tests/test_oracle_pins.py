@@ -838,3 +838,31 @@ def test_pl_adjoint_matches_dense_transpose_and_differences(L):
         jm = (g * brute.solve(mesh, om, w, st - e, sn[0], q, inc, sigma_sn=sn[1:])[1]).sum()
         fd = (jp - jm) / (2 * hstep)
         assert abs(a["grad_sigma_t"][gi, c] - fd) < 1e-7 * abs(fd)
+
+
+def test_mass_inverse_cell_matrix_is_column_diagonally_dominant():
+    # In mass-inverse form the cell matrix of a direction in the canonical
+    # octant is sigma_t I + sum_a kappa_a T_a, T = [[3, 1], [-3, 1]] on axis a,
+    # so every column's diagonal exceeds the sum of its off-diagonal
+    # magnitudes by exactly sigma_t.  Column diagonal dominance survives
+    # elimination, so partial pivoting (lowest index on ties) never exchanges
+    # rows; the oracle's GE therefore agrees with the GPU's unexchanged
+    # structured elimination.
+    rng = np.random.default_rng(170)
+    for _ in range(200):
+        om = np.abs(rng.normal(size=3))
+        om /= np.linalg.norm(om)
+        if rng.uniform() < 0.3:          # axis-aligned and face-parallel directions
+            om[rng.integers(0, 3)] = 0.0
+            om /= np.linalg.norm(om)
+        h = rng.uniform(0.05, 2.0, 3)
+        st = rng.choice([0.0, rng.uniform(0.0, 0.5), rng.uniform(0.5, 50.0)])
+        M, _, _ = oracle.element_matrices(h)
+        B = np.linalg.solve(M, _cell_matrix(h, om, st))
+        off = np.abs(B).sum(axis=0) - np.abs(np.diag(B))
+        assert np.allclose(np.diag(B) - off, st, rtol=0, atol=1e-10 * (1 + np.abs(B).max()))
+        # GE with partial pivoting keeps the diagonal as the pivot at every step
+        S = B.copy()
+        for k in range(7):
+            assert np.abs(S[k, k]) >= np.abs(S[k + 1:, k]).max() - 1e-12 * np.abs(S).max()
+            S[k + 1:, k:] -= np.outer(S[k + 1:, k] / S[k, k], S[k, k:])
