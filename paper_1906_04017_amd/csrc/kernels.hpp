@@ -112,11 +112,15 @@ constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector A
 
 // Occupancy request of a sweep kernel (waves per SIMD; 1 = no request).  The
 // FP64 single-cell mass-inverse kernel would take 176 registers and run at 2
-// waves per SIMD; held to 168 it runs at 3 with no spills.  The larger FP64
-// tiles and the dense form would spill, so they keep the compiler's choice.
+// waves per SIMD; held to 168 it runs at 3 with no spills.  The FP64 2x2x2
+// mass-inverse kernel otherwise runs at 1 wave; held to 2 it spills about
+// 160 bytes per lane and is still faster (6.5 ms against 7.2 ms per sweep at
+// 64^3 S8 G8).  The FP64 3x3x3 tiles and the dense form keep the compiler's
+// choice.
 template <typename Real, int Form, int B, int kMom = 0>
 constexpr int kMinWavesPerSimd =
-    (sizeof(Real) == 8 && B == 1 && Form == kFormMassInv && kMom == 0) ? 3 : 1;
+    (sizeof(Real) == 8 && Form == kFormMassInv && kMom == 0) ? (B == 1 ? 3 : (B == 2 ? 2 : 1))
+                                                           : 1;
 
 int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
 
