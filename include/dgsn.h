@@ -244,8 +244,8 @@ int dgsn_problem_si_history(const dgsn_problem *p, double *resid, double *eps_s,
  * its (direction, group) in upwind order, keeping the faces between them in
  * registers (the face traffic through HBM drops from 24 to 24/b values per
  * solve), one launch per tile hyperplane; with b = 1 every lane solves one
- * cell per hyperplane launch.  b in 1..3; default 2 for FP32 problems and 1
- * for FP64.  dgsn_problem_set_tile / _get_tile set and read it.
+ * cell per hyperplane launch.  b in 1..3; default 2.  dgsn_problem_set_tile /
+ * _get_tile set and read it.
  */
 int dgsn_problem_set_tile(dgsn_problem *p, int b);
 int dgsn_problem_get_tile(const dgsn_problem *p, int *b);

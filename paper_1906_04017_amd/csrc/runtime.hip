@@ -900,9 +900,9 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     p->precision = d->precision;
     p->solver = d->solver;
     p->store_psi = d->store_psi ? 1 : 0;
-    // 2x2x2 tiles pay off in FP32; in FP64 they exceed the register file of
-    // one wave slot and single cells are faster (the autotuner can revisit)
-    p->tile_b = d->precision == DGSN_FP64 ? 1 : 2;
+    // 2x2x2 tiles halve the front traffic; they are the faster default in
+    // both precisions (the autotuner can revisit)
+    p->tile_b = 2;
     p->real_size = d->precision == DGSN_FP64 ? 8 : 4;
     p->n_planes = d->nx + d->ny + d->nz - 2;
 
