@@ -88,6 +88,8 @@ def _load():
     lib.orc_adjoint_pl.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 3 + [ctypes.c_int] + [_D] * 4 + \
         [ctypes.c_double, ctypes.c_int, _D, _D, _D, _I, ctypes.c_int]
+    lib.orc_source_iterate_pl_gg.argtypes = lib.orc_source_iterate_pl.argtypes
+    lib.orc_adjoint_pl_gg.argtypes = lib.orc_adjoint_pl.argtypes
     _lib = lib
     return lib
 
@@ -243,15 +245,17 @@ def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1
 
 
 def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, max_iter=2000,
-            nthreads=0, sigma_gg=None, sigma_sn=None):
+            nthreads=0, sigma_gg=None, sigma_sn=None, pl_gg=False):
     """Exact discrete adjoint of the converged source iteration.
     gphi = dJ/dphi [G, ncell, 8].  Returns dict(grad_sigma_t, grad_q,
     grad_sigma_s [G, ncell], phi_dag [G, ncell, 8], iters); direct partial
     derivatives of J are not included.  With sigma_gg (multigroup scattering,
     the transposed coupling in the adjoint) grad_sigma_s is not computed;
     with sigma_sn [L+1, G, ncell] (in-group P_L, order 0 first; sigma_s is
-    then ignored) neither.  Pinned by duality, the dense transpose and
-    central finite differences."""
+    then ignored), or with pl_gg a matrix per order [L+1, G, G, ncell]
+    (from g' into g at [n, g', g]; sigma_s and sigma_gg are then ignored),
+    neither.  Pinned by duality, the dense transpose and central finite
+    differences."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
     ncell = nx * ny * nz
@@ -266,13 +270,14 @@ def adjoint(mesh, omega, weight, sigma_t, sigma_s, psi, phi, gphi, tol=1e-13, ma
     it = ctypes.c_int(0)
     if sigma_sn is not None:
         gss = None
-        sn = _f64(sigma_sn).reshape(-1, ng, ncell)
-        rc = lib.orc_adjoint_pl(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
-                                _p(_f64(weight, (nd,))), _p(sigma_t), int(sn.shape[0] - 1),
-                                _p(sn), _p(_f64(psi, (nd, ng, ncell, 8))),
-                                _p(_f64(phi, (ng, ncell, 8))), _p(_f64(gphi, (ng, ncell, 8))),
-                                float(tol), int(max_iter), _p(gst), _p(gq), _p(pd),
-                                ctypes.byref(it), int(nthreads))
+        sn = _f64(sigma_sn).reshape((-1, ng, ng, ncell) if pl_gg else (-1, ng, ncell))
+        fn = lib.orc_adjoint_pl_gg if pl_gg else lib.orc_adjoint_pl
+        rc = fn(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
+                _p(_f64(weight, (nd,))), _p(sigma_t), int(sn.shape[0] - 1),
+                _p(sn), _p(_f64(psi, (nd, ng, ncell, 8))),
+                _p(_f64(phi, (ng, ncell, 8))), _p(_f64(gphi, (ng, ncell, 8))),
+                float(tol), int(max_iter), _p(gst), _p(gq), _p(pd),
+                ctypes.byref(it), int(nthreads))
     elif sigma_gg is None:
         rc = lib.orc_adjoint(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
                              _p(sigma_t), _p(_f64(sigma_s, (ng, ncell))),
@@ -504,11 +509,13 @@ def real_ylm(L, omega):
 
 
 def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, tol=1e-8,
-                      max_iter=1000, phi0=None, mom0=None, nthreads=0, store_psi=False):
-    """In-group P_L scattering source iteration (Eq. (T3)-(T8)).
-    sigma_sn [L+1, G, ncell], order 0 first; returns dict(phi [G, ncell, 8],
-    mom [(L+1)^2 - 1, G, ncell, 8] (the moments k = n^2 + n + m >= 1), iters,
-    resid, eps_s, converged)."""
+                      max_iter=1000, phi0=None, mom0=None, nthreads=0, store_psi=False,
+                      gg=False):
+    """P_L scattering source iteration (Eq. (T3)-(T8)).
+    sigma_sn [L+1, G, ncell] in-group, or with gg a group-to-group matrix
+    per order [L+1, G, G, ncell] (from g' into g at [n, g', g]), order 0
+    first; returns dict(phi [G, ncell, 8], mom [(L+1)^2 - 1, G, ncell, 8]
+    (the moments k = n^2 + n + m >= 1), iters, resid, eps_s, converged)."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
     ncell = nx * ny * nz
@@ -516,7 +523,7 @@ def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, t
     nd = omega.shape[0]
     sigma_t = _f64(sigma_t).reshape(-1, ncell)
     ng = sigma_t.shape[0]
-    sigma_sn = _f64(sigma_sn).reshape(-1, ng, ncell)
+    sigma_sn = _f64(sigma_sn).reshape((-1, ng, ng, ncell) if gg else (-1, ng, ncell))
     L = sigma_sn.shape[0] - 1
     q = _f64(q, (ng, ncell))
     inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
@@ -528,11 +535,10 @@ def source_iterate_pl(mesh, omega, weight, sigma_t, sigma_sn, q, psi_inc=None, t
     resid = ctypes.c_double(0)
     eps = ctypes.c_double(0)
     psi = np.zeros((nd, ng, ncell, 8)) if store_psi else None
-    rc = lib.orc_source_iterate_pl(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
-                                   _p(_f64(weight, (nd,))), _p(sigma_t), int(L), _p(sigma_sn),
-                                   _p(q), _p(inc), _p(phi), _p(mom), float(tol), int(max_iter),
-                                   ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps),
-                                   _p(psi), int(nthreads))
+    fn = lib.orc_source_iterate_pl_gg if gg else lib.orc_source_iterate_pl
+    rc = fn(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))), _p(sigma_t),
+            int(L), _p(sigma_sn), _p(q), _p(inc), _p(phi), _p(mom), float(tol), int(max_iter),
+            ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps), _p(psi), int(nthreads))
     if rc not in (0, ORC_ENOTCONV):
         _check(rc, "source_iterate_pl")
     out = dict(phi=phi, mom=mom, iters=it.value, resid=resid.value, eps_s=eps.value,

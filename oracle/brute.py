@@ -43,7 +43,7 @@ def _cell_id(c, n):
 
 
 def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None,
-             sigma_sn=None):
+             sigma_sn=None, sigma_sn_gg=None):
     """Dense (L - K) and right-hand side Q for unknowns psi[d][g][c][8].
 
     sigma_t, sigma_s, q: [G, ncell]; psi_inc [6]; extra_src [G, ncell, 8]
@@ -53,7 +53,9 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, 
     anisotropic Legendre moments of orders 1..L, coupling directions d and d'
     through the kernel of Eq. (T3), sum_n (2n+1)/(4 pi) sigma_{s,n}
     P_n(Omega_d . Omega_d') (Legendre polynomials of the scattering cosine,
-    not the spherical harmonics of the sweep's moments).  Returns (A, Q)."""
+    not the spherical harmonics of the sweep's moments); sigma_sn_gg
+    [L, G, G, ncell] optional group-to-group anisotropic moments of orders
+    1..L (from g' to g at [n-1, g', g]) in place of sigma_sn.  Returns (A, Q)."""
     nx, ny, nz, lx, ly, lz = mesh
     n = (nx, ny, nz)
     h = (lx / nx, ly / ny, lz / nz)
@@ -68,13 +70,20 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, 
     if sigma_gg is not None:
         sigma_gg = np.asarray(sigma_gg, np.float64).reshape(ng, ng, ncell)
     aniso = None
-    if sigma_sn is not None:
-        sigma_sn = np.asarray(sigma_sn, np.float64).reshape(-1, ng, ncell)
+    if sigma_sn is not None or sigma_sn_gg is not None:
+        if sigma_sn_gg is not None:
+            sn_gg = np.asarray(sigma_sn_gg, np.float64).reshape(-1, ng, ng, ncell)
+        else:
+            # in-group: the matrix of each order is diagonal in the groups
+            sn = np.asarray(sigma_sn, np.float64).reshape(-1, ng, ncell)
+            sn_gg = np.zeros((sn.shape[0], ng, ng, ncell))
+            for g in range(ng):
+                sn_gg[:, g, g, :] = sn[:, g, :]
         cosines = np.clip(omega @ omega.T, -1.0, 1.0)
         # aniso[n-1][d][d'] = (2n+1)/(4 pi) P_n(Omega_d . Omega_d')
         aniso = np.stack([(2 * o + 1) / (4 * np.pi) *
                           np.polynomial.legendre.legval(cosines, [0.0] * o + [1.0])
-                          for o in range(1, sigma_sn.shape[0] + 1)])
+                          for o in range(1, sn_gg.shape[0] + 1)])
     N = nd * ng * ncell * 8
     A = np.zeros((N, N))
     Q = np.zeros(N)
@@ -124,19 +133,20 @@ def assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, 
                         cb = blk(d2, g2, ci)
                         A[r:r + 8, cb:cb + 8] -= sig / (4 * np.pi) * weight[d2] * M
                 if aniso is not None:
-                    for d2 in range(nd):
-                        k = float(np.dot(sigma_sn[:, g, ci], aniso[:, d, d2]))
-                        if k != 0.0:
-                            cb = blk(d2, g, ci)
-                            A[r:r + 8, cb:cb + 8] -= k * weight[d2] * M
+                    for g2 in range(ng):
+                        for d2 in range(nd):
+                            k = float(np.dot(sn_gg[:, g2, g, ci], aniso[:, d, d2]))
+                            if k != 0.0:
+                                cb = blk(d2, g2, ci)
+                                A[r:r + 8, cb:cb + 8] -= k * weight[d2] * M
     return A, Q
 
 
 def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sigma_gg=None,
-          sigma_sn=None):
+          sigma_sn=None, sigma_sn_gg=None):
     """Returns (psi [D,G,ncell,8], phi [G,ncell,8]) of the dense global system."""
     A, Q = assemble(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src, sigma_gg,
-                    sigma_sn)
+                    sigma_sn, sigma_sn_gg)
     x = np.linalg.solve(A, Q)
     nx, ny, nz = mesh[:3]
     ncell = nx * ny * nz
@@ -147,14 +157,15 @@ def solve(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc, extra_src=None, sig
     return psi, phi
 
 
-def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi, sigma_gg=None, sigma_sn=None):
+def adjoint_solve(mesh, omega, weight, sigma_t, sigma_s, gphi, sigma_gg=None, sigma_sn=None,
+                  sigma_sn_gg=None):
     """Dense transpose solve (L - K)^T lambda = W^T g for a response with
     dJ/dphi = gphi [G, ncell, 8]; returns lambda [D, G, ncell, 8]."""
     nd = len(weight)
     ncell = mesh[0] * mesh[1] * mesh[2]
     ng = np.asarray(sigma_t).reshape(-1, ncell).shape[0]
     A, _ = assemble(mesh, omega, weight, sigma_t, sigma_s, np.zeros((ng, ncell)), np.zeros(6),
-                    sigma_gg=sigma_gg, sigma_sn=sigma_sn)
+                    sigma_gg=sigma_gg, sigma_sn=sigma_sn, sigma_sn_gg=sigma_sn_gg)
     gphi = np.asarray(gphi, np.float64).reshape(ng, ncell, 8)
     r = np.concatenate([weight[d] * gphi.reshape(-1) for d in range(nd)])
     lam = np.linalg.solve(A.T, r)

@@ -15,7 +15,8 @@
  *     in-group or with a group-to-group matrix), and the anisotropic in-group
  *     P_L expansion, Q_d = q_ext + sum_{n,m} sigma_{s,n} Y_{n,m}(Omega_d)
  *     phi_{n,m} with phi_{n,m} = sum_d w_d Y_{n,m}(Omega_d) psi_d (Eq. (T7),
- *     (T8); real orthonormal spherical harmonics, orc_real_ylm).
+ *     (T8); real orthonormal spherical harmonics, orc_real_ylm), also with a
+ *     group-to-group matrix per Legendre order (the group sum of Eq. (T3)).
  *   - Eq. (T9): trilinear nodal trial space on each hexahedron, 8 vertex nodes,
  *     local node n = ix + 2 iy + 4 iz.
  *   - The weak form below Eq. (T9): streaming by Green's theorem, element mass
@@ -563,26 +564,39 @@ int orc_real_ylm(int L, const double omega[3], double *Y)
     return ORC_OK;
 }
 
+/* sigma_{s,o} from group g2 into group g of cell c: in-group [o][g][c] (g2 =
+   g), or with a matrix per order [o][g2][g][c] */
+static double sn_coef(const double *sigma_sn, int gg, int o, int g2, int g, int ng, long ncell,
+                      long c)
+{
+    return gg ? sigma_sn[(((long)o * ng + g2) * ng + g) * ncell + c]
+              : sigma_sn[((long)o * ng + g) * ncell + c];
+}
+
 /*
- * Source iteration with in-group P_L scattering, L >= 1.
- *   sigma_sn [L+1][G][ncell]: the Legendre moments sigma_{s,n} of Eq. (T3),
- *     order 0 first (the isotropic sigma_s);
+ * Source iteration with P_L scattering, L >= 1.
+ *   sigma_sn: the Legendre moments sigma_{s,n} of Eq. (T3), order 0 first
+ *     (the isotropic part), either in-group, [L+1][G][ncell], or (gg != 0)
+ *     a group-to-group matrix per order, [L+1][G][G][ncell] with the
+ *     moment from group g' into group g at [n][g'][g];
  *   phi [G][ncell][8]: scalar flux (= the moment phi_{0,0} / Y_00), initial
  *     guess on entry, last iterate on exit;
  *   mom [(L+1)^2 - 1][G][ncell][8]: the flux moments phi_{n,m} of Eq. (T8)
  *     for k = n^2 + n + m >= 1, initial guess on entry, last iterate on exit.
- * Iteration: Q_d = q + sigma_{s,0}/(4 pi) phi + sum_{k>=1} sigma_{s,n(k)}
- * Y_k(Omega_d) mom_k, one sweep per (direction, group) with that source, then
- * phi = sum_d w_d psi_d and mom_k = sum_d w_d Y_k(Omega_d) psi_d, accumulated
- * in direction order.  Residual and eps_s on phi as in source_iterate.
- * psi_store, if not NULL, receives the last sweep's [D][G][ncell][8].
+ * Iteration: Q_{d,g} = q_g + sum_{g'} (sigma_{s,0}(g'->g)/(4 pi) phi_{g'} +
+ * sum_{k>=1} sigma_{s,n(k)}(g'->g) Y_k(Omega_d) mom_{k,g'}) over the source
+ * groups g' (g' = g only, in-group) in ascending order, one sweep per
+ * (direction, group) with that source, then phi = sum_d w_d psi_d and
+ * mom_k = sum_d w_d Y_k(Omega_d) psi_d, accumulated in direction order.
+ * Residual and eps_s on phi as in source_iterate.  psi_store, if not NULL,
+ * receives the last sweep's [D][G][ncell][8].
  */
-int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
-                          int nd, const double *omega, const double *weight,
-                          const double *sigma_t, int L, const double *sigma_sn, const double *q,
-                          const double psi_inc[6], double *phi, double *mom, double tol,
-                          int max_iter, int *iters, double *resid, double *eps_s,
-                          double *psi_store, int nthreads)
+static int source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                             int nd, const double *omega, const double *weight,
+                             const double *sigma_t, int L, const double *sigma_sn, int gg,
+                             const double *q, const double psi_inc[6], double *phi, double *mom,
+                             double tol, int max_iter, int *iters, double *resid, double *eps_s,
+                             double *psi_store, int nthreads)
 {
     if (nx < 1 || ny < 1 || nz < 1 || ng < 1 || nd < 1 || L < 1 || L > 8) return ORC_EINVAL;
     orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
@@ -619,13 +633,19 @@ int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double l
                 for (long c = 0; c < ncell; ++c) {
                     const long gc = (long)g * ncell + c;
                     for (int n = 0; n < 8; ++n) {
-                        double v = q[gc] + sigma_sn[gc] / (4.0 * ORC_PI) * phi[gc * 8 + n];
-                        for (int o = 1; o <= L; ++o)
-                            for (int mm = -o; mm <= o; ++mm) {
-                                const int k = o * o + o + mm;
-                                v += sigma_sn[(long)o * nv + gc] * yd[k] *
-                                     mom[((long)(k - 1) * nv + gc) * 8 + n];
+                        double v = q[gc];
+                        for (int g2 = gg ? 0 : g; g2 <= (gg ? ng - 1 : g); ++g2) {
+                            const long g2c = (long)g2 * ncell + c;
+                            v += sn_coef(sigma_sn, gg, 0, g2, g, ng, ncell, c) / (4.0 * ORC_PI) *
+                                 phi[g2c * 8 + n];
+                            for (int o = 1; o <= L; ++o) {
+                                const double sig = sn_coef(sigma_sn, gg, o, g2, g, ng, ncell, c);
+                                for (int mm = -o; mm <= o; ++mm) {
+                                    const int k = o * o + o + mm;
+                                    v += sig * yd[k] * mom[((long)(k - 1) * nv + g2c) * 8 + n];
+                                }
                             }
+                        }
                         S[c * 8 + n] = v;
                     }
                 }
@@ -686,6 +706,32 @@ int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double l
     if (eps_s) *eps_s = es;
     if (err) return err;
     return (r < tol) ? ORC_OK : ORC_ENOTCONV;
+}
+
+/* In-group P_L: sigma_sn [L+1][G][ncell]. */
+int orc_source_iterate_pl(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                          int nd, const double *omega, const double *weight,
+                          const double *sigma_t, int L, const double *sigma_sn, const double *q,
+                          const double psi_inc[6], double *phi, double *mom, double tol,
+                          int max_iter, int *iters, double *resid, double *eps_s,
+                          double *psi_store, int nthreads)
+{
+    return source_iterate_pl(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, L, sigma_sn,
+                             0, q, psi_inc, phi, mom, tol, max_iter, iters, resid, eps_s,
+                             psi_store, nthreads);
+}
+
+/* Group-to-group P_L: sigma_sn [L+1][G][G][ncell], from g' into g at [n][g'][g]. */
+int orc_source_iterate_pl_gg(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                             int nd, const double *omega, const double *weight,
+                             const double *sigma_t, int L, const double *sigma_sn,
+                             const double *q, const double psi_inc[6], double *phi, double *mom,
+                             double tol, int max_iter, int *iters, double *resid, double *eps_s,
+                             double *psi_store, int nthreads)
+{
+    return source_iterate_pl(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, L, sigma_sn,
+                             1, q, psi_inc, phi, mom, tol, max_iter, iters, resid, eps_s,
+                             psi_store, nthreads);
 }
 
 /* ------------------------------------------------------------------ */
@@ -806,24 +852,33 @@ static void adjoint_load(int ng, long ncell, const double *sigma_s, const double
 }
 
 /*
- * The anisotropic part of the adjoint load for direction d of group g
- * (in-group P_L, the transpose of the forward moment coupling):
- *   lu[c] = load[g][c] + sum_{k>=1} sigma_{s,n(k)}[g][c] Y_k(Omega_d) M phid_k[g][c],
- * with mmom[k-1][g][c] = M phid_k[g][c] precomputed.
+ * The anisotropic part of the adjoint load for direction d of group g (the
+ * transpose of the forward moment coupling):
+ *   lu[c] = load[g][c] + sum_{g'} sum_{k>=1} sigma_{s,n(k)}(g->g')[c]
+ *           Y_k(Omega_d) M phid_k[g'][c],
+ * over g' = g only (in-group, sigma_sn [L][G][ncell]) or every group
+ * (gg != 0, sigma_sn [L][G][G][ncell] with g -> g' at [n-1][g][g']), with
+ * mmom[k-1][g'][c] = M phid_k[g'][c] precomputed.
  */
-static void adjoint_load_pl(long ncell, int g, int L, const double *sigma_sn, const double *yd,
-                            const double *load, const double *mmom, long nv, double *lu)
+static void adjoint_load_pl(long ncell, int ng, int g, int L, const double *sigma_sn, int gg,
+                            const double *yd, const double *load, const double *mmom, long nv,
+                            double *lu)
 {
     for (long c = 0; c < ncell; ++c) {
         const long gc = (long)g * ncell + c;
         for (int n = 0; n < 8; ++n) {
             double v = load[gc * 8 + n];
-            for (int o = 1; o <= L; ++o)
-                for (int mm = -o; mm <= o; ++mm) {
-                    const int k = o * o + o + mm;
-                    v += sigma_sn[(long)(o - 1) * nv + gc] * yd[k] *
-                         mmom[((long)(k - 1) * nv + gc) * 8 + n];
+            for (int g2 = gg ? 0 : g; g2 <= (gg ? ng - 1 : g); ++g2) {
+                const long g2c = (long)g2 * ncell + c;
+                for (int o = 1; o <= L; ++o) {
+                    const double sig = gg ? sigma_sn[(((long)(o - 1) * ng + g) * ng + g2) * ncell + c]
+                                          : sigma_sn[(long)(o - 1) * nv + gc];
+                    for (int mm = -o; mm <= o; ++mm) {
+                        const int k = o * o + o + mm;
+                        v += sig * yd[k] * mmom[((long)(k - 1) * nv + g2c) * 8 + n];
+                    }
                 }
+            }
             lu[c * 8 + n] = v;
         }
     }
@@ -833,7 +888,7 @@ static void adjoint_load_pl(long ncell, int g, int L, const double *sigma_sn, co
 static int adjoint_sweep_all(const orc_mesh *m, int ng, int nd, const double *omega,
                              const double *sigma_t, const double *load, const double M[64],
                              const double G[3][64], const double Mf[6][64], int L,
-                             const double *sigma_sn, const double *Y, const double *mmom,
+                             const double *sigma_sn, int gg, const double *Y, const double *mmom,
                              double *ubuf, double *mu)
 {
     const long ncell = (long)m->n[0] * m->n[1] * m->n[2];
@@ -850,7 +905,7 @@ static int adjoint_sweep_all(const orc_mesh *m, int ng, int nd, const double *om
 #else
             double *lu = ubuf;
 #endif
-            adjoint_load_pl(ncell, g, L, sigma_sn, Y + (long)d * nm, load, mmom, nv, lu);
+            adjoint_load_pl(ncell, ng, g, L, sigma_sn, gg, Y + (long)d * nm, load, mmom, nv, lu);
             ld = lu;
         }
         int e = adjoint_sweep_one(m, omega + 3 * d, sigma_t + g * ncell, ld, M, G, Mf,
@@ -888,7 +943,7 @@ static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, 
                        const double *phi, const double *gphi, double tol, int max_iter,
                        double *grad_sigma_t, double *grad_q, double *grad_sigma_s,
                        double *phi_dag_out, int *iters, int nthreads, int L,
-                       const double *sigma_sn)
+                       const double *sigma_sn, int pl_gg)
 {
     orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
     const long ncell = (long)nx * ny * nz;
@@ -918,8 +973,8 @@ static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, 
     while (it < max_iter) {
         /* load = g + sigma_s^T/(4 pi) M phi_dag (+ the anisotropic moments) */
         adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
-        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, Y, mmom,
-                               ubuf, mu);
+        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, pl_gg, Y,
+                               mmom, ubuf, mu);
         if (rc) break;
         if (L > 0) adjoint_moments(nd, nv, nm, weight, Y, mu, M, mmom);
         memset(phidn, 0, (size_t)nv * 8 * sizeof(double));
@@ -939,8 +994,8 @@ static int adjoint_run(int nx, int ny, int nz, double lx, double ly, double lz, 
         /* the mu of the last sweep are consistent with the phi_dag used to build
            its load; one more sweep with the converged phi_dag refines them */
         adjoint_load(ng, ncell, sigma_s, sigma_gg, M, gphi, phid, load);
-        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, Y, mmom,
-                               ubuf, mu);
+        rc = adjoint_sweep_all(&m, ng, nd, omega, sigma_t, load, M, G, Mf, L, sigma_sn, pl_gg, Y,
+                               mmom, ubuf, mu);
     }
     if (!rc) {
         for (long gc = 0; gc < nv; ++gc) {
@@ -977,7 +1032,7 @@ int orc_adjoint(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
 {
     return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, NULL, psi,
                        phi, gphi, tol, max_iter, grad_sigma_t, grad_q, grad_sigma_s, phi_dag_out,
-                       iters, nthreads, 0, NULL);
+                       iters, nthreads, 0, NULL, 0);
 }
 
 /* Adjoint with multigroup scattering (the gradient with respect to the
@@ -991,7 +1046,7 @@ int orc_adjoint_gg(int nx, int ny, int nz, double lx, double ly, double lz, int 
     if (!sigma_gg) return ORC_EINVAL;
     return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, sigma_gg,
                        psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
-                       iters, nthreads, 0, NULL);
+                       iters, nthreads, 0, NULL, 0);
 }
 
 /* Adjoint with in-group P_L scattering: sigma_sn [L+1][G][ncell], order 0
@@ -1007,7 +1062,23 @@ int orc_adjoint_pl(int nx, int ny, int nz, double lx, double ly, double lz, int 
     const long nv = (long)ng * nx * ny * nz;
     return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_sn, NULL,
                        psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
-                       iters, nthreads, L, sigma_sn + nv);
+                       iters, nthreads, L, sigma_sn + nv, 0);
+}
+
+/* Adjoint with group-to-group P_L scattering: sigma_sn [L+1][G][G][ncell],
+   from g' into g at [n][g'][g], order 0 first (the adjoint couples through
+   the transpose of every order's matrix). */
+int orc_adjoint_pl_gg(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                      const double *omega, const double *weight, const double *sigma_t, int L,
+                      const double *sigma_sn, const double *psi, const double *phi,
+                      const double *gphi, double tol, int max_iter, double *grad_sigma_t,
+                      double *grad_q, double *phi_dag_out, int *iters, int nthreads)
+{
+    if (L < 1 || L > 8 || !sigma_sn) return ORC_EINVAL;
+    const long ngg = (long)ng * ng * nx * ny * nz;
+    return adjoint_run(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, sigma_sn,
+                       psi, phi, gphi, tol, max_iter, grad_sigma_t, grad_q, NULL, phi_dag_out,
+                       iters, nthreads, L, sigma_sn + ngg, 1);
 }
 
 /* ------------------------------------------------------------------ */

@@ -840,6 +840,90 @@ def test_pl_adjoint_matches_dense_transpose_and_differences(L):
         assert abs(a["grad_sigma_t"][gi, c] - fd) < 1e-7 * abs(fd)
 
 
+def _pl_gg_case(seed, L=2, ng=3):
+    # a group-to-group matrix per Legendre order, with down- and upscatter and
+    # no symmetry between g' -> g and g -> g', so a transposed matrix fails
+    rng = np.random.default_rng(seed)
+    mesh = (2, 2, 1, 0.8, 0.6, 0.5)
+    nc = 4
+    om, w = oracle.lq_n(4)
+    st = rng.uniform(1.0, 3.0, (ng, nc))
+    ratios = np.array([0.25, 0.12, 0.06, 0.03][:L + 1])
+    sn = np.zeros((L + 1, ng, ng, nc))
+    for g2 in range(ng):
+        for g in range(ng):
+            sn[:, g2, g] = ratios[:, None] * st[g2] * rng.uniform(0.3, 1.0, (L + 1, nc))
+    q = rng.uniform(0.2, 1.0, (ng, nc))
+    inc = rng.uniform(0.0, 1.0, 6)
+    return mesh, om, w, st, sn, q, inc
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_pl_gg_source_iteration_equals_dense_global_solve(L):
+    # group-to-group P_L: the moment form against the global system coupled
+    # through sum_n (2n+1)/(4 pi) sigma_{s,n}(g'->g) P_n(Omega_d . Omega_d')
+    mesh, om, w, st, sn, q, inc = _pl_gg_case(180 + L, L=L)
+    ng = st.shape[0]
+    r = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-15, max_iter=3000, gg=True)
+    assert r["converged"]
+    psi_b, phi_b = brute.solve(mesh, om, w, st, np.zeros_like(st), q, inc, sigma_gg=sn[0],
+                               sigma_sn_gg=sn[1:])
+    assert np.abs(r["phi"] - phi_b).max() <= 1e-12 * np.abs(phi_b).max()
+    Y = oracle.real_ylm(L, om)
+    mom_b = np.einsum("d,dk,dgcn->kgcn", w, Y[:, 1:], psi_b)
+    assert np.abs(r["mom"] - mom_b).max() <= 1e-12 * np.abs(phi_b).max()
+    # the groups really are coupled: the in-group iteration of the diagonal
+    # differs from it
+    diag = np.stack([sn[:, g, g] for g in range(ng)], axis=1)
+    d = oracle.source_iterate_pl(mesh, om, w, st, diag, q, inc, tol=1e-15, max_iter=3000)
+    assert np.abs(d["phi"] - phi_b).max() > 1e-3 * np.abs(phi_b).max()
+
+
+def test_pl_gg_with_diagonal_matrices_is_in_group_iteration():
+    mesh, om, w, st, sn, q, inc = _pl_case(183, L=2, ng=3)
+    ng, nc = st.shape
+    gg = np.zeros((sn.shape[0], ng, ng, nc))
+    for g in range(ng):
+        gg[:, g, g] = sn[:, g]
+    a = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-14, max_iter=3000)
+    b = oracle.source_iterate_pl(mesh, om, w, st, gg, q, inc, tol=1e-14, max_iter=3000, gg=True)
+    assert a["iters"] == b["iters"]
+    assert np.abs(a["phi"] - b["phi"]).max() <= 1e-15 * np.abs(a["phi"]).max()
+    assert np.abs(a["mom"] - b["mom"]).max() <= 1e-15 * np.abs(a["phi"]).max()
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_pl_gg_adjoint_matches_dense_transpose_and_differences(L):
+    mesh, om, w, st, sn, q, inc = _pl_gg_case(184 + L, L=L)
+    ng, nc = st.shape
+    z = np.zeros_like(st)
+    rng = np.random.default_rng(186)
+    g = rng.uniform(0.0, 1.0, (ng, nc, 8))
+    r = oracle.source_iterate_pl(mesh, om, w, st, sn, q, inc, tol=1e-15, max_iter=3000,
+                                 store_psi=True, gg=True)
+    assert r["converged"]
+    a = oracle.adjoint(mesh, om, w, st, z, r["psi"], r["phi"], g, tol=1e-15, sigma_sn=sn,
+                       pl_gg=True)
+    lam = brute.adjoint_solve(mesh, om, w, st, z, g, sigma_gg=sn[0], sigma_sn_gg=sn[1:])
+    psi_b, phi_b = brute.solve(mesh, om, w, st, z, q, inc, sigma_gg=sn[0], sigma_sn_gg=sn[1:])
+    h = np.array(mesh[3:]) / np.array(mesh[:3])
+    M, _, _ = oracle.element_matrices(h)
+    gq = np.einsum("dgcn,nm->gc", lam, M)
+    gst = -np.einsum("dgcn,nm,dgcm->gc", lam, M, psi_b)
+    assert np.abs(a["grad_q"] - gq).max() < 1e-11 * np.abs(gq).max()
+    assert np.abs(a["grad_sigma_t"] - gst).max() < 1e-11 * np.abs(gst).max()
+    hstep = 1e-6
+    for gi, c in ((0, 1), (ng - 1, nc - 1)):
+        e = np.zeros_like(st)
+        e[gi, c] = hstep
+        jp = (g * brute.solve(mesh, om, w, st + e, z, q, inc, sigma_gg=sn[0],
+                              sigma_sn_gg=sn[1:])[1]).sum()
+        jm = (g * brute.solve(mesh, om, w, st - e, z, q, inc, sigma_gg=sn[0],
+                              sigma_sn_gg=sn[1:])[1]).sum()
+        fd = (jp - jm) / (2 * hstep)
+        assert abs(a["grad_sigma_t"][gi, c] - fd) < 1e-7 * abs(fd)
+
+
 def test_mass_inverse_cell_matrix_is_column_diagonally_dominant():
     # In mass-inverse form the cell matrix of a direction in the canonical
     # octant is sigma_t I + sum_a kappa_a T_a, T = [[3, 1], [-3, 1]] on axis a,
