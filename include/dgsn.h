@@ -163,11 +163,36 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
  * isotropic sources only: dgsn_source_iterate with a network solver, and
  * with store_psi under DGSN_GE_DENSE, returns DGSN_EUNSUPPORTED while an
  * order is set, and so does this call while a group-to-group matrix
- * is set (and dgsn_problem_set_scattering while an order is set).
+ * is set (and dgsn_problem_set_scattering while an order is set; see
+ * dgsn_problem_set_anisotropy_gg for both).
  * DGSN_ENOMEM if the moment buffers (9 (L+1)^2 G*cells*8 reals) cannot be
  * allocated.
  */
 int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream);
+
+/*
+ * Anisotropic scattering of order L with a group-to-group matrix per
+ * Legendre order (the group sum of Eq. (T3)-(T8)): source iteration uses for
+ * direction d of group g
+ *   Q_{d,g} = q_g + sum_{g'} ( sigma_{s,0}(g'->g)/(4 pi) phi_{g'}
+ *             + sum_{k>=1} sigma_{s,n(k)}(g'->g) Y_k(Omega_d) phi_{k,g'} ),
+ * all groups at once (Jacobi in the group index), and dgsn_adjoint_solve the
+ * transpose of every order's matrix.  order: 1..3.  sigma_sn_gg: device
+ * [order+1][G][G][Nz*Ny*Nx] in the problem precision, order 0 first,
+ * sigma_sn_gg[n][g'][g][c] the moment of order n for scattering from group
+ * g' into group g in cell c (copied asynchronously on the stream; the caller
+ * keeps ownership).  The order-0 slice becomes the problem's multigroup
+ * matrix (as with dgsn_problem_set_scattering), so the in-group sigma_s of
+ * dgsn_problem_set_materials is not used.  This call replaces any in-group
+ * orders or group-to-group matrix set before; dgsn_problem_set_anisotropy
+ * with order 0 removes the orders 1..L and keeps the order-0 matrix.  The
+ * other rules are those of dgsn_problem_set_anisotropy (tile edge at most
+ * 2; GE solvers; the adjoint and a stored angular flux with DGSN_GE).
+ * DGSN_EINVAL for an order outside 1..3 or a NULL array; DGSN_ENOMEM if the
+ * buffers (the moment buffers and (L+1) G*G*cells reals) cannot be allocated.
+ */
+int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma_sn_gg,
+                                   void *stream);
 
 /*
  * Flux moments phi_k, k = 1 .. (L+1)^2 - 1, of the final sweep of the last

@@ -88,6 +88,7 @@ SIGNATURES = {
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_si_history": (_I, [_VP, _PD, _PD, _I, _PI]),
     "dgsn_problem_set_anisotropy": (_I, [_VP, _I, _VP, _VP]),
+    "dgsn_problem_set_anisotropy_gg": (_I, [_VP, _I, _VP, _VP]),
     "dgsn_problem_get_moments": (_I, [_VP, _VP, _VP]),
     "dgsn_real_ylm": (_I, [_I, _PD, _I, _PD]),
     "dgsn_problem_set_tile": (_I, [_VP, _I]),

@@ -235,6 +235,21 @@ class Problem:
         torch.cuda.current_stream(self.ctx.device).synchronize()
         self.pl_order = L
 
+    def set_anisotropy_gg(self, sigma_sn_gg):
+        """Anisotropic scattering with a group-to-group matrix per Legendre
+        order: sigma_sn_gg [L+1, G, G, ncell], order 0 first, from g' into g
+        at [n, g', g] (1 <= L <= 3).  Clear with set_anisotropy(None)."""
+        size = int(np.prod(tuple(sigma_sn_gg.shape)))
+        per = self.groups * self.groups * self.ncell
+        L = size // per - 1
+        if L < 1 or (L + 1) * per != size:
+            raise ValueError("sigma_sn_gg must hold [L+1, G, G, ncell] values with L >= 1")
+        m = self._dev(sigma_sn_gg, (L + 1, self.groups, self.groups, self.ncell))
+        _lib.check(_lib.load().dgsn_problem_set_anisotropy_gg(self._h, L, _ptr(m),
+                                                              _stream(self.ctx.device)))
+        torch.cuda.current_stream(self.ctx.device).synchronize()
+        self.pl_order = L
+
     def moments(self):
         """Flux moments k = 1 .. (L+1)^2 - 1 of the last source iteration,
         [(L+1)^2 - 1, G, ncell, 8] on the device."""

@@ -121,7 +121,8 @@ struct dgsn_problem {
     std::vector<int> dir_user;       // octant-sorted slot -> user direction index
     std::vector<double> dir_host;    // [8][Do][kDirStride] in FP64
     std::vector<double> omega_host;  // [8][Do][3] the slot directions
-    int pl_order = 0;                // anisotropic in-group scattering order L (0: none)
+    int pl_order = 0;                // anisotropic scattering order L (0: none)
+    int pl_gg = 0;                   // 1: the orders 1..L are group-to-group matrices
     std::vector<int> plane_off;      // [n_planes + 1]
     // tile hyperplane schedules for B x B x B tiles (B = 2, 3; index B):
     // packed tile coordinates, tile-hyperplane major (B = 1 is the cell
@@ -146,6 +147,7 @@ struct dgsn_problem {
     dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
     dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
     dgsn::DevBuf sigma_sn;                   // [L][G][ncell] Legendre moments of orders 1..L
+                                             // ([L][G][G][ncell] from g' into g with pl_gg)
     dgsn::DevBuf d_ylm;                      // [8][Do][kYlmStride] harmonics of the slot directions
     dgsn::DevBuf mom_oct;                    // [8][G][ncell][8][nm-1] per-octant flux moments
     dgsn::DevBuf mom;                        // [nm-1][G][ncell][8] flux moments

@@ -146,10 +146,16 @@ int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Rea
                            hipStream_t s);
 // flux moments of anisotropic scattering: mom [nm-1][G][ncell][8] = the sum
 // over octants of mom_oct [8][G][ncell][8][nm-1], and msrc [G][ncell][nm-1][8]
-// = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k))
+// = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k));
+// msrc (and sigma_sn) null: the moments only
 template <typename Real>
 int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
                           Real *mom, Real *msrc, hipStream_t s);
+// group-to-group source moments msrc[g] = sum_g' sigma_{s,n(k)}(g' -> g) mom[g']
+// (transpose: sigma(g -> g')), sigma_sn_gg [L][G][G][ncell] orders 1..L
+template <typename Real>
+int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_sn_gg, const Real *mom,
+                         Real *msrc, bool transpose, hipStream_t s);
 template <typename Real>
 int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, hipStream_t s);
 

@@ -432,6 +432,26 @@ int sweep_impl(dgsn_problem *p, const void *src, void *phi, hipStream_t s)
     return launch_reduce<Real>(R, p->red_blocks, s);
 }
 
+// Anisotropic moments after a sweep's octant reduction: the flux moments,
+// and the source moments of the next sweep -- sigma_{s,n} times the moment
+// in-group (fused), or the group sum through the per-order matrices
+// (transposed in the adjoint).
+template <typename Real>
+int moment_sources(dgsn_problem *p, bool adjoint, hipStream_t s)
+{
+    const long long nv = (long long)p->G * p->ncell;
+    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
+    const Real *sn = static_cast<const Real *>(p->sigma_sn.ptr);
+    Real *mom = static_cast<Real *>(p->mom.ptr);
+    Real *msrc = static_cast<Real *>(p->msrc.ptr);
+    DGSN_TRY(launch_reduce_moments<Real>(nv, nm, static_cast<const Real *>(p->mom_oct.ptr),
+                                         p->pl_gg ? nullptr : sn, mom, p->pl_gg ? nullptr : msrc,
+                                         s));
+    if (p->pl_gg)
+        DGSN_TRY(launch_build_msrc_gg<Real>(p->ncell, p->G, nm, sn, mom, msrc, adjoint, s));
+    return DGSN_OK;
+}
+
 template <typename Real>
 int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
                         double *resid, double *eps_s, hipStream_t s)
@@ -439,7 +459,6 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     const long long nv = (long long)p->G * p->ncell;
     Real *src = static_cast<Real *>(p->src.ptr);
     const bool pl = p->pl_order > 0;
-    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
     if (pl && p->solver == DGSN_ANN)
         return set_error(DGSN_EUNSUPPORTED,
                          "anisotropic scattering is available with the GE solvers");
@@ -496,11 +515,7 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
         }
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
-        if (pl)
-            DGSN_TRY(launch_reduce_moments<Real>(
-                nv, nm, static_cast<const Real *>(p->mom_oct.ptr),
-                static_cast<const Real *>(p->sigma_sn.ptr), static_cast<Real *>(p->mom.ptr),
-                static_cast<Real *>(p->msrc.ptr), s));
+        if (pl) DGSN_TRY(moment_sources<Real>(p, false, s));
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G,
                                                   static_cast<const Real *>(p->q.ptr), nullptr,
@@ -594,7 +609,6 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
     const Real *gg = static_cast<const Real *>(p->sigma_gg.ptr);
     // anisotropic scattering: the moments of the adjoint flux, from zero
     const bool pl = p->pl_order > 0;
-    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
     if (pl) {
         DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
         DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
@@ -624,11 +638,7 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
             R.sigma_s = static_cast<const Real *>(p->sigma_s.ptr);
         }
         DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
-        if (pl)
-            DGSN_TRY(launch_reduce_moments<Real>(
-                nv, nm, static_cast<const Real *>(p->mom_oct.ptr),
-                static_cast<const Real *>(p->sigma_sn.ptr), static_cast<Real *>(p->mom.ptr),
-                static_cast<Real *>(p->msrc.ptr), s));
+        if (pl) DGSN_TRY(moment_sources<Real>(p, true, s));
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg,
                                                   phid[slot ^ 1], asrc[slot ^ 1], true, s));
@@ -1056,7 +1066,8 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
     }
     if (p->pl_order > 0)
         return set_error(DGSN_EUNSUPPORTED,
-                         "a group-to-group matrix and anisotropic scattering are exclusive");
+                         "anisotropic scattering is set; dgsn_problem_set_anisotropy_gg sets the "
+                         "order-0 group-to-group matrix with the higher orders");
     const size_t bytes = (size_t)p->G * p->G * p->ncell * p->real_size;
     if (p->sigma_gg.bytes != bytes) DGSN_TRY(p->sigma_gg.alloc(bytes));
     DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, sigma_gg, bytes, hipMemcpyDeviceToDevice,
@@ -1064,26 +1075,11 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
     return DGSN_OK;
 }
 
-int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream)
+namespace {
+// Harmonics of the slot directions and the moment buffers of order L, with
+// room for sbytes of scattering moments (sigma_sn).
+int anisotropy_buffers(dgsn_problem *p, int order, size_t sbytes)
 {
-    clear_error();
-    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
-    if (order < 0 || order > kMaxPlOrder)
-        return set_error(DGSN_EINVAL, "scattering order %d is outside 0..%d", order, kMaxPlOrder);
-    DGSN_HIP(hipSetDevice(p->ctx->device));
-    if (order == 0) {
-        p->pl_order = 0;
-        p->sigma_sn.release();
-        p->d_ylm.release();
-        p->mom_oct.release();
-        p->mom.release();
-        p->msrc.release();
-        return DGSN_OK;
-    }
-    if (!sigma_sn) return set_error(DGSN_EINVAL, "sigma_sn is NULL");
-    if (p->sigma_gg.ptr)
-        return set_error(DGSN_EUNSUPPORTED,
-                         "a group-to-group matrix and anisotropic scattering are exclusive");
     const int nm = (order + 1) * (order + 1);
     const size_t nv = (size_t)p->G * p->ncell;
     std::vector<double> y((size_t)8 * p->Do * kYlmStride, 0.0);
@@ -1100,13 +1096,65 @@ int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn
         DGSN_TRY(p->msrc.alloc(mbytes));
         DGSN_TRY(p->mom_oct.alloc(8 * mbytes));
     }
-    const size_t sbytes = (size_t)order * nv * p->real_size;
     if (p->sigma_sn.bytes != sbytes) DGSN_TRY(p->sigma_sn.alloc(sbytes));
+    return DGSN_OK;
+}
+}  // namespace
+
+int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (order < 0 || order > kMaxPlOrder)
+        return set_error(DGSN_EINVAL, "scattering order %d is outside 0..%d", order, kMaxPlOrder);
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    if (order == 0) {
+        p->pl_order = 0;
+        p->pl_gg = 0;
+        p->sigma_sn.release();
+        p->d_ylm.release();
+        p->mom_oct.release();
+        p->mom.release();
+        p->msrc.release();
+        return DGSN_OK;
+    }
+    if (!sigma_sn) return set_error(DGSN_EINVAL, "sigma_sn is NULL");
+    if (p->sigma_gg.ptr)
+        return set_error(DGSN_EUNSUPPORTED,
+                         "a group-to-group matrix and in-group anisotropic scattering are "
+                         "exclusive (dgsn_problem_set_anisotropy_gg sets both)");
+    const size_t sbytes = (size_t)order * p->G * p->ncell * p->real_size;
+    DGSN_TRY(anisotropy_buffers(p, order, sbytes));
     hipStream_t s = as_stream(stream);
     DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, sigma_sn, sbytes, hipMemcpyDeviceToDevice, s));
-    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, mbytes, s));
-    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, mbytes, s));
+    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
     p->pl_order = order;
+    p->pl_gg = 0;
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma_sn_gg,
+                                   void *stream)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (order < 1 || order > kMaxPlOrder)
+        return set_error(DGSN_EINVAL, "scattering order %d is outside 1..%d", order, kMaxPlOrder);
+    if (!sigma_sn_gg) return set_error(DGSN_EINVAL, "sigma_sn_gg is NULL");
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    const size_t mat = (size_t)p->G * p->G * p->ncell * p->real_size;
+    DGSN_TRY(anisotropy_buffers(p, order, (size_t)order * mat));
+    if (p->sigma_gg.bytes != mat) DGSN_TRY(p->sigma_gg.alloc(mat));
+    hipStream_t s = as_stream(stream);
+    const char *src = static_cast<const char *>(sigma_sn_gg);
+    DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, src, mat, hipMemcpyDeviceToDevice, s));
+    DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, src + mat, (size_t)order * mat,
+                            hipMemcpyDeviceToDevice, s));
+    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
+    p->pl_order = order;
+    p->pl_gg = 1;
     return DGSN_OK;
 }
 

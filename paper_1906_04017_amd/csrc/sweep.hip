@@ -220,7 +220,43 @@ __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
         for (int o = 0; o < 8; ++o) s += __builtin_nontemporal_load(mom_oct + (long long)o * total + e);
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
         mom[((long long)(k - 1) * nv + gc) * 8 + n] = s;
-        msrc[(gc * nk + (k - 1)) * 8 + n] = sigma_sn[(long long)(order - 1) * nv + gc] * s;
+        if (msrc) msrc[(gc * nk + (k - 1)) * 8 + n] = sigma_sn[(long long)(order - 1) * nv + gc] * s;
+    }
+}
+
+// Source moments of group-to-group anisotropic scattering: one thread per
+// (cell, moment, node) in the layout of one group's msrc block, looping over
+// the destination group g and summing the source groups g' in ascending
+// order: msrc[g][c][k-1][n] = sum_g' sigma_{s,n(k)}(g' -> g)[c] mom[k-1][g'][c][n]
+// (transpose: sigma(g -> g')).  sigma_sn_gg [L][G][G][ncell] holds orders 1..L,
+// from g' into g at [n-1][g'][g].
+template <typename Real>
+__global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int nm,
+                                                     const Real *__restrict__ sigma_sn_gg,
+                                                     const Real *__restrict__ mom,
+                                                     Real *__restrict__ msrc, int transpose)
+{
+    const int nk = nm - 1;
+    const long long per_group = ncell * nk * 8;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < per_group;
+         e += stride) {
+        const long long c = e / (nk * 8);
+        const int r = (int)(e - c * (nk * 8));
+        const int k = (r >> 3) + 1;
+        const int n = r & 7;
+        const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
+        const Real *sig = sigma_sn_gg + (long long)(order - 1) * G * G * ncell + c;
+        const Real *mk = mom + (long long)(k - 1) * G * ncell * 8 + c * 8 + n;
+        for (int g = 0; g < G; ++g) {
+            Real v = 0;
+            for (int g2 = 0; g2 < G; ++g2) {
+                const long long m = transpose ? ((long long)g * G + g2) * ncell
+                                              : ((long long)g2 * G + g) * ncell;
+                v = fma(sig[m], mk[(long long)g2 * ncell * 8], v);
+            }
+            msrc[(long long)g * per_group + e] = v;
+        }
     }
 }
 
@@ -453,6 +489,17 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
     return DGSN_OK;
 }
 
+template <typename Real>
+int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_sn_gg, const Real *mom,
+                         Real *msrc, bool transpose, hipStream_t s)
+{
+    if (nm < 2 || nm > kYlmStride) return set_error(DGSN_EINVAL, "bad moment count %d", nm);
+    hipLaunchKernelGGL(build_msrc_gg<Real>, dim3(grid_for((long long)(nm - 1) * ncell * 8)),
+                       dim3(256), 0, s, ncell, G, nm, sigma_sn_gg, mom, msrc, transpose ? 1 : 0);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
 int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
 
 #define DGSN_INST(Real)                                                                        \
@@ -467,7 +514,9 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
                                            hipStream_t);                                       \
     template int launch_reduce_grad<Real>(long long, const Real *, Real *, Real *, hipStream_t); \
     template int launch_reduce_moments<Real>(long long, int, const Real *, const Real *, Real *,  \
-                                             Real *, hipStream_t);
+                                             Real *, hipStream_t);                             \
+    template int launch_build_msrc_gg<Real>(long long, int, int, const Real *, const Real *,    \
+                                            Real *, bool, hipStream_t);
 DGSN_INST(float)
 DGSN_INST(double)
 

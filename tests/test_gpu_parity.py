@@ -515,6 +515,156 @@ def test_multigroup_adjoint_matches_oracle(api, ctx, precision, tol):
 
 
 # ---------------------------------------------------------------------------
+# anisotropic scattering with a group-to-group matrix per Legendre order
+# ---------------------------------------------------------------------------
+
+def _multigroup_pl(p, L, seed, c=0.8, ratios=(0.5, 0.25, 0.12)):
+    """[L+1, G, G, ncell] (from g' into g at [n, g', g]): the order-0 matrix
+    of _multigroup and forward-peaked higher orders r_n u sigma_0(g' -> g)."""
+    rng = np.random.default_rng(seed + 1000)
+    gg = _multigroup(p, seed, c=c)
+    return np.stack([gg] + [ratios[n] * rng.uniform(0.8, 1.0, gg.shape) * gg for n in range(L)])
+
+
+def _pl_gg_reference(p, sn, store_psi=False):
+    om, w = oracle.lq_n(p["order"])
+    return oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"], sn, p["q"], p["psi_inc"],
+                                    tol=1e-14, max_iter=3000, gg=True, store_psi=store_psi)
+
+
+@pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp64", 3), ("fp32", 2)])
+def test_pl_gg_source_iteration_matches_oracle(api, ctx, precision, L):
+    p = inputs.random_problem((6, 5, 4), 4, 3, seed=190 + L, length=(0.6, 0.5, 0.4))
+    sn = _multigroup_pl(p, L, 195 + L)
+    print_case("pl_gg_si", name=p["name"], precision=precision, L=L)
+    prob = gpu_problem(api, ctx, p, precision)
+    prob.set_anisotropy_gg(sn)
+    tol = 1e-13 if precision == "fp64" else 1e-8
+    phi, info = prob.source_iterate(tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    mom = prob.moments().double().cpu().numpy()
+    ref = _pl_gg_reference(p, sn)
+    assert ref["converged"]
+    bound = 1e-10 if precision == "fp64" else FP32_TOL
+    for g in range(p["groups"]):
+        assert rel(phi.cpu().numpy()[g], ref["phi"][g]) <= bound, g
+    assert mom.shape == ref["mom"].shape
+    assert np.abs(mom - ref["mom"]).max() <= bound * np.abs(ref["phi"]).max()
+    # the higher orders couple the groups: the in-group iteration of the
+    # matrices' diagonals, with the same order-0 matrix, differs
+    om, w = oracle.lq_n(p["order"])
+    diag = sn.copy()
+    for g2 in range(p["groups"]):
+        for g in range(p["groups"]):
+            if g != g2:
+                diag[1:, g2, g] = 0.0
+    alt = oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"], diag, p["q"], p["psi_inc"],
+                                   tol=1e-14, max_iter=3000, gg=True)
+    assert rel(alt["phi"], ref["phi"]) > 100 * bound
+
+
+def test_pl_gg_schedules_and_tiles_bitwise(api, ctx):
+    p = inputs.random_problem((7, 6, 5), 4, 3, seed=200)
+    sn = _multigroup_pl(p, 2, 201)
+    print_case("pl_gg_schedules", name=p["name"])
+    out = {}
+    for sched in ("planes", "dataflow"):
+        for b in (1, 2):
+            prob = gpu_problem(api, ctx, p, "fp32")
+            prob.set_anisotropy_gg(sn)
+            prob.set_schedule(sched)
+            prob.set_tile(b)
+            phi, _ = prob.source_iterate(tol=0.0, max_iter=6, allow_notconv=True)
+            out[(sched, b)] = (phi.cpu().numpy(), prob.moments().cpu().numpy())
+            prob.close()
+    for b in (1, 2):
+        assert np.array_equal(out[("planes", b)][0], out[("dataflow", b)][0])
+        assert np.array_equal(out[("planes", b)][1], out[("dataflow", b)][1])
+    assert rel(out[("planes", 2)][0], out[("planes", 1)][0]) <= FP32_TOL
+
+
+def test_pl_gg_diagonal_matrices_equal_in_group(api, ctx):
+    p = inputs.random_problem((5, 4, 4), 4, 2, seed=202, c_max=0.8)
+    sn = inputs.anisotropic_orders(p["sigma_s"], 2, seed=203)
+    print_case("pl_gg_diagonal", name=p["name"])
+    nc = p["sigma_t"].shape[1]
+    full = np.concatenate([p["sigma_s"][None], sn])
+    gg = np.zeros((3, 2, 2, nc))
+    for g in range(2):
+        gg[:, g, g] = full[:, g]
+    a = gpu_problem(api, ctx, p, "fp64")
+    a.set_anisotropy(sn)
+    phi_a, ia = a.source_iterate(tol=1e-12, max_iter=1000)
+    b = gpu_problem(api, ctx, p, "fp64")
+    b.set_anisotropy_gg(gg)
+    phi_b, ib = b.source_iterate(tol=1e-12, max_iter=1000)
+    assert ia["iters"] == ib["iters"]
+    assert rel(phi_b.cpu().numpy(), phi_a.cpu().numpy()) <= 1e-13
+    assert rel(b.moments().cpu().numpy(), a.moments().cpu().numpy()) <= 1e-12
+
+
+def test_pl_gg_replace_clear_and_rejections(api, ctx):
+    p = inputs.random_problem((4, 4, 3), 4, 2, seed=204)
+    nc = p["sigma_t"].shape[1]
+    sn = _multigroup_pl(p, 1, 205)
+    print_case("pl_gg_rules", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp64")
+    lib = api._lib.load()
+    m = torch.tensor(sn, dtype=torch.float64, device="cuda")
+    for order in (0, 4):
+        assert lib.dgsn_problem_set_anisotropy_gg(prob._h, order, m.data_ptr(),
+                                                  None) == api._lib.DGSN_EINVAL
+    assert lib.dgsn_problem_set_anisotropy_gg(prob._h, 1, None, None) == api._lib.DGSN_EINVAL
+    with pytest.raises(ValueError):
+        prob.set_anisotropy_gg(sn[:1])
+    # it replaces in-group orders set before
+    prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], 2, seed=206))
+    prob.set_anisotropy_gg(sn)
+    phi, _ = prob.source_iterate(tol=1e-13, max_iter=1000)
+    ref = _pl_gg_reference(p, sn)
+    assert rel(phi.cpu().numpy(), ref["phi"]) <= 1e-10
+    assert prob.moments().shape[0] == 3
+    # exclusive with the separate calls while it is set
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.set_scattering(sn[0])
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], 1, seed=207))
+    # clearing the orders keeps the order-0 group-to-group matrix
+    prob.set_anisotropy(None)
+    phi0, _ = prob.source_iterate(tol=1e-13, max_iter=1000)
+    om, w = oracle.lq_n(p["order"])
+    ref0 = oracle.source_iterate(mesh_of(p), om, w, p["sigma_t"], np.zeros((2, nc)), p["q"],
+                                 p["psi_inc"], tol=1e-14, max_iter=3000, sigma_gg=sn[0])
+    assert rel(phi0.cpu().numpy(), ref0["phi"]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
+def test_pl_gg_adjoint_matches_oracle(api, ctx, precision, L):
+    p = inputs.random_problem((5, 4, 4), 4, 3, seed=210 + L, length=(0.5, 0.4, 0.4))
+    sn = _multigroup_pl(p, L, 215 + L, c=0.7)
+    print_case("pl_gg_adjoint", name=p["name"], precision=precision, L=L)
+    prob = gpu_problem(api, ctx, p, precision, store_psi=True)
+    prob.set_anisotropy_gg(sn)
+    tol = 1e-13 if precision == "fp64" else 1e-7
+    prob.source_iterate(tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    rng = np.random.default_rng(220 + L)
+    g = rng.uniform(0.0, 1.0, (3, p["sigma_t"].shape[1], 8))
+    gst, gq, info = prob.adjoint(g, tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+    om, w = oracle.lq_n(p["order"])
+    r = _pl_gg_reference(p, sn, store_psi=True)
+    zero = np.zeros_like(p["sigma_t"])
+    a = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], zero, r["psi"], r["phi"], g,
+                       tol=1e-15, sigma_sn=sn, pl_gg=True)
+    bound = 1e-9 if precision == "fp64" else 1e-4
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= bound
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= bound
+    # the transpose matters: the adjoint of the untransposed coupling differs
+    snt = np.ascontiguousarray(np.swapaxes(sn, 1, 2))
+    wrong = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], zero, r["psi"], r["phi"], g,
+                           tol=1e-15, sigma_sn=snt, pl_gg=True)
+    assert rel(wrong["grad_q"], a["grad_q"]) > 100 * bound
+
+
+# ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
 
