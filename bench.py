@@ -236,20 +236,22 @@ def time_sweeps(prob, src, reps):
     return (time.perf_counter() - t0) / reps, phi
 
 
-def plain_fp64(api, ctx, p, reps=3):
-    """Plain (FP64) GE sweep throughput on the same workload."""
+def plain_fp64(api, ctx, p, reps=10):
+    """Plain (FP64) GE sweep throughput on the same workload, autotuned."""
     import torch
     om, w = api.quadrature_ls(p["order"])
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp64")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
-    prob.autotune()
+    tile, sched, tune = prob.autotune()
     src = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float64,
                        device="cuda")
     dt, _ = time_sweeps(prob, src, reps)
     solves = prob.stats()["solves_per_sweep"]
-    log(f"fp64 GE sweep: {dt * 1e3:.3f} ms")
+    log(f"fp64 GE sweep: {dt * 1e3:.3f} ms (tile {tile}, {sched} schedule; autotuner "
+        + ", ".join(f"{k[0]} {k[1]}^3 {v:.3f} ms" for k, v in tune.items()) + ")")
     prob.close()
-    return {"solves_per_s": solves / dt, "ms_per_sweep": dt * 1e3, "solver": "GE", "dtype": "f64"}
+    return {"solves_per_s": solves / dt, "ms_per_sweep": dt * 1e3, "solver": "GE", "dtype": "f64",
+            "tile": tile, "schedule": sched}
 
 
 def si_convergence(api, ctx, p, tol=1e-8):
@@ -475,28 +477,40 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
 
 
 def anisotropic_steps(api, ctx, p, iters=10):
-    """Source iterations of the benchmark workload with in-group P_L
-    scattering (sigma_{s,n} = (0.5, 0.25, 0.12)_n sigma_s), L = 1 and 3, FP32
-    GE: ms per iteration against the isotropic iteration."""
+    """Source iterations of the benchmark workload with P_L scattering, FP32
+    GE, ms per iteration: in-group (sigma_{s,n} = (0.5, 0.25, 0.12)_n
+    sigma_s) at L = 0, 1, 3, and with a group-to-group matrix per order
+    (inputs.multigroup_orders: the same total scattering out of each group,
+    spread over in-group, down- and some upscatter) at L = 0 (the P0 matrix
+    alone), 1 and 3."""
     import torch
     from paper_1906_04017_amd import inputs
     om, w = api.quadrature_ls(p["order"])
     out = {"workload": p["name"], "iterations": iters}
-    for L in (0, 1, 3):
+    cases = [("P0", None), ("P1", None), ("P3", None), ("P0_gg", 0), ("P1_gg", 1), ("P3_gg", 3)]
+    for name, gg in cases:
         prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
         prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
         prob.set_inflow(p["psi_inc"])
         prob.autotune()
-        if L:
+        L = int(name[1])
+        if gg is None and L:
             prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], L, seed=7))
+        elif gg is not None:
+            m = inputs.multigroup_orders(p["sigma_s"], L, seed=8)
+            if L:
+                prob.set_anisotropy_gg(m)
+            else:
+                prob.set_scattering(m[0])
+            del m
         prob.source_iterate(tol=0.0, max_iter=2, allow_notconv=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prob.source_iterate(tol=0.0, max_iter=iters, allow_notconv=True)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / iters
-        out[f"P{L}_ms_per_iteration"] = ms
-        log(f"anisotropic scattering P{L}: {ms:.3f} ms per source iteration")
+        out[f"{name}_ms_per_iteration"] = ms
+        log(f"scattering {name}: {ms:.3f} ms per source iteration")
         prob.close()
     return out
 

@@ -169,6 +169,24 @@ def anisotropic_orders(sigma_s, L, seed, ratios=(0.5, 0.25, 0.12)):
     return np.stack([ratios[n] * rng.uniform(0.8, 1.0, size=ss.shape) * ss for n in range(L)])
 
 
+def multigroup_orders(sigma_s, L, seed, up=0.05, ratios=(0.5, 0.25, 0.12)):
+    """Group-to-group scattering moments of orders 0..L [L+1, G, G, ncell]
+    (from g' into g at [n, g', g]): order 0 spreads sigma_s[g'] over the
+    destination groups, in-group and downscatter with U[0, 1] weights and
+    upscatter damped by `up`, normalised so that the total out of g' is
+    sigma_s[g']; order n >= 1 is r_n u times order 0 with u ~ U[0.8, 1]
+    per entry (forward-peaked)."""
+    rng = np.random.default_rng(seed)
+    ss = np.asarray(sigma_s, np.float64)
+    G = ss.shape[0]
+    f = rng.uniform(0.0, 1.0, (G, G) + ss.shape[1:])
+    for g2 in range(G):
+        f[g2, :g2] *= up
+    m0 = f / f.sum(axis=1, keepdims=True) * ss[:, None]
+    out = [m0] + [ratios[n] * rng.uniform(0.8, 1.0, m0.shape) * m0 for n in range(L)]
+    return np.stack(out)
+
+
 def random_nodal(shape_cells, groups, seed, lo=0.0, hi=1.0):
     """Random nodal field [G, ncell, 8] ~ U[lo, hi]."""
     rng = np.random.default_rng(seed)

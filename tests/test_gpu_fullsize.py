@@ -127,6 +127,34 @@ def test_anisotropic_iterations_at_bench_size(api, ctx):
     assert np.abs(ref["mom"]).max() > 1e-3 * np.abs(ref["phi"]).max()
 
 
+def test_group_to_group_anisotropic_iterations_at_bench_size(api, ctx):
+    # the benchmark workload with a group-to-group P1 matrix per order (the
+    # bench's multigroup_orders case), FP32, autotuned: two source iterations
+    # from zero against the oracle, every output of phi and of the moments
+    p = inputs.blocky_scatter()
+    m = inputs.multigroup_orders(p["sigma_s"], 1, seed=8)
+    print_case("fullsize_p1_gg", name=p["name"])
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.autotune()
+    prob.set_anisotropy_gg(m)
+    phi, info = prob.source_iterate(tol=0.0, max_iter=2, allow_notconv=True)
+    assert info["iters"] == 2
+    mom = prob.moments().double().cpu().numpy()
+    phi = phi.double().cpu().numpy()
+    prob.close()
+    om_o, w_o = oracle.lq_n(8)
+    ref = oracle.source_iterate_pl((*p["n"], *p["length"]), om_o, w_o, p["sigma_t"], m, p["q"],
+                                   p["psi_inc"], tol=0.0, max_iter=2, gg=True)
+    assert ref["iters"] == 2
+    for g in range(p["groups"]):
+        scale = np.abs(ref["phi"][g]).max()
+        assert np.abs(phi[g] - ref["phi"][g]).max() <= 1e-5 * scale, g
+        assert np.abs(mom[:, g] - ref["mom"][:, g]).max() <= 1e-5 * scale, g
+    assert np.abs(ref["mom"]).max() > 1e-3 * np.abs(ref["phi"]).max()
+
+
 def test_trained_network_sweep_at_full_size(api, ctx):
     # the trained BF16 matrix-core network on the paper's Problem 3 (sigma_t =
     # 10, q = 1, psi_inc = 1 on three faces) at 128^3, S8, autotuned, against
