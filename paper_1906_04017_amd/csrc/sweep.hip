@@ -248,14 +248,28 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
         const Real *sig = sigma_sn_gg + (long long)(order - 1) * G * G * ncell + c;
         const Real *mk = mom + (long long)(k - 1) * G * ncell * 8 + c * 8 + n;
-        for (int g = 0; g < G; ++g) {
-            Real v = 0;
-            for (int g2 = 0; g2 < G; ++g2) {
-                const long long m = transpose ? ((long long)g * G + g2) * ncell
-                                              : ((long long)g2 * G + g) * ncell;
-                v = fma(sig[m], mk[(long long)g2 * ncell * 8], v);
+        // the source groups' moments of this (cell, moment, node) are read
+        // once, 16 at a time into registers (clamped loads, in bounds), and
+        // serve every destination group; past 16 groups the partial sums
+        // continue in msrc
+        for (int g0 = 0; g0 < G; g0 += 16) {
+            Real mv[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) mv[j] = mk[(long long)min(g0 + j, G - 1) * ncell * 8];
+            for (int g = 0; g < G; ++g) {
+                Real *out = msrc + (long long)g * per_group + e;
+                Real v = g0 ? *out : Real(0);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int g2 = g0 + j;
+                    if (g2 < G) {
+                        const long long m = transpose ? ((long long)g * G + g2) * ncell
+                                                      : ((long long)g2 * G + g) * ncell;
+                        v = fma(sig[m], mv[j], v);
+                    }
+                }
+                *out = v;
             }
-            msrc[(long long)g * per_group + e] = v;
         }
     }
 }

@@ -637,6 +637,27 @@ def test_pl_gg_replace_clear_and_rejections(api, ctx):
     assert rel(phi0.cpu().numpy(), ref0["phi"]) <= 1e-10
 
 
+def test_pl_gg_many_groups(api, ctx):
+    # more source groups than the 16 a thread stages in registers: the source
+    # moments continue their sums over a second chunk of groups
+    G = 18
+    p = inputs.random_problem((3, 3, 2), 2, G, seed=208, length=(0.3, 0.3, 0.2))
+    sn = _multigroup_pl(p, 1, 209, c=0.7)
+    print_case("pl_gg_many_groups", name=p["name"], groups=G)
+    for precision, bound in (("fp64", 1e-10), ("fp32", FP32_TOL)):
+        prob = gpu_problem(api, ctx, p, precision)
+        prob.set_anisotropy_gg(sn)
+        tol = 1e-13 if precision == "fp64" else 1e-8
+        phi, _ = prob.source_iterate(tol=tol, max_iter=1000, allow_notconv=precision == "fp32")
+        mom = prob.moments().double().cpu().numpy()
+        prob.close()
+        ref = _pl_gg_reference(p, sn)
+        assert ref["converged"]
+        for g in range(G):
+            assert rel(phi.cpu().numpy()[g], ref["phi"][g]) <= bound, (precision, g)
+        assert np.abs(mom - ref["mom"]).max() <= bound * np.abs(ref["phi"]).max()
+
+
 @pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
 def test_pl_gg_adjoint_matches_oracle(api, ctx, precision, L):
     p = inputs.random_problem((5, 4, 4), 4, 3, seed=210 + L, length=(0.5, 0.4, 0.4))
