@@ -95,6 +95,10 @@ def parse():
                     help="only run --steps sweeps of the BF16-MFMA network on the paper problems "
                          "(128^3, S8, 4 groups) after autotuning: the workload of the matrix-core "
                          "counter passes")
+    ap.add_argument("--aniso-only", action="store_true",
+                    help="only time source iterations of the workload with P_L scattering, "
+                         "in-group and with group-to-group matrices (P0, P1, P3): the workload "
+                         "of the anisotropic kernel trace; prints one JSON line")
     ap.add_argument("--cpu-groups", type=int, default=8,
                     help="groups of the workload swept by the CPU oracle sample")
     return ap.parse_args()
@@ -141,6 +145,10 @@ def main():
 
     p = inputs.blocky_scatter(n=args.n, groups=args.groups, seed=2, order=args.order)
     log(f"workload {p['name']}")
+    if args.aniso_only:
+        ctx = api.Context(0)
+        print(json.dumps(anisotropic_steps(api, ctx, p)), flush=True)
+        return
     ctx = api.Context(0)
     om, w = api.quadrature_ls(p["order"])
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
