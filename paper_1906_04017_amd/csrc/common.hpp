@@ -147,7 +147,8 @@ struct dgsn_problem {
     dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
     dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
     dgsn::DevBuf sigma_sn;                   // [L][G][ncell] Legendre moments of orders 1..L
-                                             // ([L][G][G][ncell] from g' into g with pl_gg)
+                                             // (with pl_gg cell-major [ncell][L][G][G], from
+                                             // g' into g at [c][n-1][g'][g])
     dgsn::DevBuf d_ylm;                      // [8][Do][kYlmStride] harmonics of the slot directions
     dgsn::DevBuf mom_oct;                    // [8][G][ncell][8][nm-1] per-octant flux moments
     dgsn::DevBuf mom;                        // [nm-1][G][ncell][8] flux moments

@@ -152,10 +152,13 @@ template <typename Real>
 int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
                           Real *mom, Real *msrc, hipStream_t s);
 // group-to-group source moments msrc[g] = sum_g' sigma_{s,n(k)}(g' -> g) mom[g']
-// (transpose: sigma(g -> g')), sigma_sn_gg [L][G][G][ncell] orders 1..L
+// (transpose: sigma(g -> g')), sigma_cm [ncell][L][G][G] orders 1..L, cell-major
 template <typename Real>
-int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_sn_gg, const Real *mom,
+int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s);
+// dst [ncell][nmat] = the cell-major copy of src [nmat][ncell]
+template <typename Real>
+int launch_cell_major(long long ncell, int nmat, const Real *src, Real *dst, hipStream_t s);
 template <typename Real>
 int launch_reduce_grad(long long nv, const Real *grad_oct, Real *gst, Real *gq, hipStream_t s);
 

@@ -1149,8 +1149,15 @@ int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma
     hipStream_t s = as_stream(stream);
     const char *src = static_cast<const char *>(sigma_sn_gg);
     DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, src, mat, hipMemcpyDeviceToDevice, s));
-    DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, src + mat, (size_t)order * mat,
-                            hipMemcpyDeviceToDevice, s));
+    // the orders 1..L cell-major, one G x G matrix per (cell, order) in one run
+    const int nmat = order * p->G * p->G;
+    if (p->precision == DGSN_FP64)
+        DGSN_TRY(launch_cell_major<double>(p->ncell, nmat,
+                                           reinterpret_cast<const double *>(src + mat),
+                                           static_cast<double *>(p->sigma_sn.ptr), s));
+    else
+        DGSN_TRY(launch_cell_major<float>(p->ncell, nmat, reinterpret_cast<const float *>(src + mat),
+                                          static_cast<float *>(p->sigma_sn.ptr), s));
     DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
     DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
     p->pl_order = order;

@@ -224,15 +224,32 @@ __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
     }
 }
 
+// Cell-major copy of per-cell matrices: dst[c][j] = src[j][c] for nmat
+// values j per cell (one thread per destination value).
+template <typename Real>
+__global__ __launch_bounds__(256) void cell_major(long long ncell, int nmat,
+                                                  const Real *__restrict__ src,
+                                                  Real *__restrict__ dst)
+{
+    const long long total = ncell * nmat;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const long long c = e / nmat;
+        const int j = (int)(e - c * nmat);
+        dst[e] = src[(long long)j * ncell + c];
+    }
+}
+
 // Source moments of group-to-group anisotropic scattering: one thread per
 // (cell, moment, node) in the layout of one group's msrc block, looping over
 // the destination group g and summing the source groups g' in ascending
 // order: msrc[g][c][k-1][n] = sum_g' sigma_{s,n(k)}(g' -> g)[c] mom[k-1][g'][c][n]
-// (transpose: sigma(g -> g')).  sigma_sn_gg [L][G][G][ncell] holds orders 1..L,
-// from g' into g at [n-1][g'][g].
+// (transpose: sigma(g -> g')).  sigma_cm [ncell][L][G][G] holds orders 1..L
+// cell-major, from g' into g at [c][n-1][g'][g], so that the G*G matrix a
+// thread reads lies in one run.
 template <typename Real>
-__global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int nm,
-                                                     const Real *__restrict__ sigma_sn_gg,
+__global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int nm, int L,
+                                                     const Real *__restrict__ sigma_cm,
                                                      const Real *__restrict__ mom,
                                                      Real *__restrict__ msrc, int transpose)
 {
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
         const int k = (r >> 3) + 1;
         const int n = r & 7;
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
-        const Real *sig = sigma_sn_gg + (long long)(order - 1) * G * G * ncell + c;
+        const Real *sig = sigma_cm + (c * L + (order - 1)) * G * G;
         const Real *mk = mom + (long long)(k - 1) * G * ncell * 8 + c * 8 + n;
         // the source groups' moments of this (cell, moment, node) are read
         // once, 16 at a time into registers (clamped loads, in bounds), and
@@ -263,9 +280,7 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
                 for (int j = 0; j < 16; ++j) {
                     const int g2 = g0 + j;
                     if (g2 < G) {
-                        const long long m = transpose ? ((long long)g * G + g2) * ncell
-                                                      : ((long long)g2 * G + g) * ncell;
-                        v = fma(sig[m], mv[j], v);
+                        v = fma(sig[transpose ? g * G + g2 : g2 * G + g], mv[j], v);
                     }
                 }
                 *out = v;
@@ -504,12 +519,24 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 }
 
 template <typename Real>
-int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_sn_gg, const Real *mom,
+int launch_cell_major(long long ncell, int nmat, const Real *src, Real *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(cell_major<Real>, dim3(grid_for(ncell * nmat)), dim3(256), 0, s, ncell,
+                       nmat, src, dst);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template <typename Real>
+int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s)
 {
-    if (nm < 2 || nm > kYlmStride) return set_error(DGSN_EINVAL, "bad moment count %d", nm);
+    int L = 1;
+    while ((L + 1) * (L + 1) < nm) ++L;
+    if (nm < 2 || nm > kYlmStride || (L + 1) * (L + 1) != nm)
+        return set_error(DGSN_EINVAL, "bad moment count %d", nm);
     hipLaunchKernelGGL(build_msrc_gg<Real>, dim3(grid_for((long long)(nm - 1) * ncell * 8)),
-                       dim3(256), 0, s, ncell, G, nm, sigma_sn_gg, mom, msrc, transpose ? 1 : 0);
+                       dim3(256), 0, s, ncell, G, nm, L, sigma_cm, mom, msrc, transpose ? 1 : 0);
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }
@@ -530,7 +557,8 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
     template int launch_reduce_moments<Real>(long long, int, const Real *, const Real *, Real *,  \
                                              Real *, hipStream_t);                             \
     template int launch_build_msrc_gg<Real>(long long, int, int, const Real *, const Real *,    \
-                                            Real *, bool, hipStream_t);
+                                            Real *, bool, hipStream_t);                        \
+    template int launch_cell_major<Real>(long long, int, const Real *, Real *, hipStream_t);
 DGSN_INST(float)
 DGSN_INST(double)
 
