@@ -145,7 +145,8 @@ struct dgsn_problem {
     dgsn::DevBuf d_dir;              // [8][Do][kDirStride] real
     dgsn::DevBuf d_plane_cells;      // uint32 packed canonical (i, j, k), plane-major
     dgsn::DevBuf sigma_t, sigma_s, q;        // [G][ncell]
-    dgsn::DevBuf sigma_gg;                   // [G][G][ncell] multigroup scattering (or empty)
+    dgsn::DevBuf sigma_gg;                   // [ncell][G][G] multigroup scattering, cell-major
+                                             // (from g' into g at [c][g'][g]; or empty)
     dgsn::DevBuf sigma_sn;                   // [L][G][ncell] Legendre moments of orders 1..L
                                              // (with pl_gg cell-major [ncell][L][G][G], from
                                              // g' into g at [c][n-1][g'][g])

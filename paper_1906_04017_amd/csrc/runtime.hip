@@ -1055,6 +1055,19 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
     return DGSN_OK;
 }
 
+namespace {
+// dst [ncell][nmat] (problem precision) = the cell-major copy of the
+// caller's src [nmat][ncell], on the stream
+int cell_major_matrix(const dgsn_problem *p, const void *src, int nmat, void *dst, hipStream_t s)
+{
+    if (p->precision == DGSN_FP64)
+        return launch_cell_major<double>(p->ncell, nmat, static_cast<const double *>(src),
+                                         static_cast<double *>(dst), s);
+    return launch_cell_major<float>(p->ncell, nmat, static_cast<const float *>(src),
+                                    static_cast<float *>(dst), s);
+}
+}  // namespace
+
 int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *stream)
 {
     clear_error();
@@ -1070,9 +1083,7 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
                          "order-0 group-to-group matrix with the higher orders");
     const size_t bytes = (size_t)p->G * p->G * p->ncell * p->real_size;
     if (p->sigma_gg.bytes != bytes) DGSN_TRY(p->sigma_gg.alloc(bytes));
-    DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, sigma_gg, bytes, hipMemcpyDeviceToDevice,
-                            as_stream(stream)));
-    return DGSN_OK;
+    return cell_major_matrix(p, sigma_gg, p->G * p->G, p->sigma_gg.ptr, as_stream(stream));
 }
 
 namespace {
@@ -1148,16 +1159,9 @@ int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma
     if (p->sigma_gg.bytes != mat) DGSN_TRY(p->sigma_gg.alloc(mat));
     hipStream_t s = as_stream(stream);
     const char *src = static_cast<const char *>(sigma_sn_gg);
-    DGSN_HIP(hipMemcpyAsync(p->sigma_gg.ptr, src, mat, hipMemcpyDeviceToDevice, s));
-    // the orders 1..L cell-major, one G x G matrix per (cell, order) in one run
-    const int nmat = order * p->G * p->G;
-    if (p->precision == DGSN_FP64)
-        DGSN_TRY(launch_cell_major<double>(p->ncell, nmat,
-                                           reinterpret_cast<const double *>(src + mat),
-                                           static_cast<double *>(p->sigma_sn.ptr), s));
-    else
-        DGSN_TRY(launch_cell_major<float>(p->ncell, nmat, reinterpret_cast<const float *>(src + mat),
-                                          static_cast<float *>(p->sigma_sn.ptr), s));
+    // cell-major, one G x G matrix per (cell, order) in one run
+    DGSN_TRY(cell_major_matrix(p, src, p->G * p->G, p->sigma_gg.ptr, s));
+    DGSN_TRY(cell_major_matrix(p, src + mat, order * p->G * p->G, p->sigma_sn.ptr, s));
     DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
     DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
     p->pl_order = order;

@@ -167,9 +167,9 @@ __global__ __launch_bounds__(256) void build_source(long long nv, const Real *q,
 }
 
 // Multigroup source (the group sum of the isotropic scattering source): one
-// thread per (cell, node); the G fluxes of the node and the G x G matrix of
-// the cell are read from L2-resident rows (the 8 threads of a cell share
-// them).  Summed over the source group in ascending order.
+// thread per (cell, node); the G fluxes of the node, and the cell's G x G
+// matrix from its cell-major run [c][g'][g] (the 8 threads of a cell share
+// it).  Summed over the source group in ascending order.
 template <typename Real>
 __global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
                                                        const Real *__restrict__ q_cell,
@@ -187,10 +187,10 @@ __global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
             const long long gc = (long long)g * ncell + c;
             Real v = q_cell ? q_cell[gc] : Real(0);
             if (q_nodal) v += q_nodal[gc * 8 + n];
+            const Real *sig = sigma_gg + c * G * G;
             for (int g2 = 0; g2 < G; ++g2) {
-                const long long m = transpose ? ((long long)g * G + g2) * ncell + c
-                                              : ((long long)g2 * G + g) * ncell + c;
-                v = fma(sigma_gg[m] * Real(kInv4Pi), phi[((long long)g2 * ncell + c) * 8 + n], v);
+                const Real s = sig[transpose ? g * G + g2 : g2 * G + g];
+                v = fma(s * Real(kInv4Pi), phi[((long long)g2 * ncell + c) * 8 + n], v);
             }
             src[gc * 8 + n] = v;
         }
