@@ -152,7 +152,8 @@ struct dgsn_problem {
                                              // g' into g at [c][n-1][g'][g])
     dgsn::DevBuf d_ylm;                      // [8][Do][kYlmStride] harmonics of the slot directions
     dgsn::DevBuf mom_oct;                    // [8][G][ncell][8][nm-1] per-octant flux moments
-    dgsn::DevBuf mom;                        // [nm-1][G][ncell][8] flux moments
+    dgsn::DevBuf mom;                        // [G][ncell][nm-1][8] flux moments (the public
+                                             // layout [nm-1][G][ncell][8] on request)
     dgsn::DevBuf msrc;                       // [G][ncell][nm-1][8] sigma_{s,n} x moments
     dgsn::DevBuf src;                         // [G][ncell][8]
     dgsn::DevBuf phi_oct;                     // [8][G][ncell][8]

@@ -144,18 +144,22 @@ template <typename Real>
 int launch_build_source_gg(long long ncell, int G, const Real *q_cell, const Real *q_nodal,
                            const Real *sigma_gg, const Real *phi, Real *src, bool transpose,
                            hipStream_t s);
-// flux moments of anisotropic scattering: mom [nm-1][G][ncell][8] = the sum
-// over octants of mom_oct [8][G][ncell][8][nm-1], and msrc [G][ncell][nm-1][8]
+// flux moments of anisotropic scattering: mom [G][ncell][nm-1][8] = the sum
+// over octants of mom_oct [8][G][ncell][8][nm-1], and msrc (same layout)
 // = sigma_{s,n(k)} mom (moments k = 1 .. nm-1, order n(k) = floor(sqrt k));
 // msrc (and sigma_sn) null: the moments only
 template <typename Real>
 int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real *sigma_sn,
                           Real *mom, Real *msrc, hipStream_t s);
 // group-to-group source moments msrc[g] = sum_g' sigma_{s,n(k)}(g' -> g) mom[g']
-// (transpose: sigma(g -> g')), sigma_cm [ncell][L][G][G] orders 1..L, cell-major
+// (transpose: sigma(g -> g')), both [G][ncell][nm-1][8], sigma_cm
+// [ncell][L][G][G] orders 1..L, cell-major
 template <typename Real>
 int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s);
+// the public layout of the moments: dst [nm-1][G][ncell][8] from src [G][ncell][nm-1][8]
+template <typename Real>
+int launch_moments_public(long long nv, int nm, const Real *src, Real *dst, hipStream_t s);
 // dst [ncell][nmat] = the cell-major copy of src [nmat][ncell]
 template <typename Real>
 int launch_cell_major(long long ncell, int nmat, const Real *src, Real *dst, hipStream_t s);

@@ -1176,9 +1176,13 @@ int dgsn_problem_get_moments(const dgsn_problem *p, void *mom, void *stream)
     if (p->pl_order == 0)
         return set_error(DGSN_EINVAL, "the problem has no anisotropic scattering");
     DGSN_HIP(hipSetDevice(p->ctx->device));
-    DGSN_HIP(hipMemcpyAsync(mom, p->mom.ptr, p->mom.bytes, hipMemcpyDeviceToDevice,
-                            as_stream(stream)));
-    return DGSN_OK;
+    const long long nv = (long long)p->G * p->ncell;
+    const int nm = (p->pl_order + 1) * (p->pl_order + 1);
+    if (p->precision == DGSN_FP64)
+        return launch_moments_public<double>(nv, nm, static_cast<const double *>(p->mom.ptr),
+                                             static_cast<double *>(mom), as_stream(stream));
+    return launch_moments_public<float>(nv, nm, static_cast<const float *>(p->mom.ptr),
+                                        static_cast<float *>(mom), as_stream(stream));
 }
 
 int dgsn_real_ylm(int order, const double *omega, int n, double *Y)

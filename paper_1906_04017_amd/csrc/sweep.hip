@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void build_source_gg(long long ncell, int G,
 // Flux moments of anisotropic scattering: one thread per (group, cell, node,
 // moment) in the sweep's layout; the octant partials are summed in octant
 // order, and the source moment is sigma_{s,n} times the moment, n the order
-// of moment k.
+// of moment k.  Moments and source moments are stored [G][ncell][nm-1][8],
+// so a wave's stores stay within a few cells.
 template <typename Real>
 __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
                                                       const Real *__restrict__ mom_oct,
@@ -219,8 +220,27 @@ __global__ __launch_bounds__(256) void reduce_moments(long long nv, int nm,
         Real s = 0;
         for (int o = 0; o < 8; ++o) s += __builtin_nontemporal_load(mom_oct + (long long)o * total + e);
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
-        mom[((long long)(k - 1) * nv + gc) * 8 + n] = s;
-        if (msrc) msrc[(gc * nk + (k - 1)) * 8 + n] = sigma_sn[(long long)(order - 1) * nv + gc] * s;
+        const long long m = (gc * nk + (k - 1)) * 8 + n;
+        mom[m] = s;
+        if (msrc) msrc[m] = sigma_sn[(long long)(order - 1) * nv + gc] * s;
+    }
+}
+
+// The public layout of the flux moments: dst[k][gc][n] = src[gc][k][n] (one
+// thread per destination value).
+template <typename Real>
+__global__ __launch_bounds__(256) void moments_public(long long nv, int nk,
+                                                      const Real *__restrict__ src,
+                                                      Real *__restrict__ dst)
+{
+    const long long total = nv * nk * 8;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const long long kg = e >> 3;
+        const int n = (int)(e & 7);
+        const int k = (int)(kg / nv);
+        const long long gc = kg - (long long)k * nv;
+        dst[e] = src[(gc * nk + k) * 8 + n];
     }
 }
 
@@ -241,9 +261,9 @@ __global__ __launch_bounds__(256) void cell_major(long long ncell, int nmat,
 }
 
 // Source moments of group-to-group anisotropic scattering: one thread per
-// (cell, moment, node) in the layout of one group's msrc block, looping over
-// the destination group g and summing the source groups g' in ascending
-// order: msrc[g][c][k-1][n] = sum_g' sigma_{s,n(k)}(g' -> g)[c] mom[k-1][g'][c][n]
+// (cell, moment, node) in the layout of one group's block of msrc and mom,
+// looping over the destination group g and summing the source groups g' in
+// ascending order: msrc[g][c][k-1][n] = sum_g' sigma_{s,n(k)}(g' -> g)[c] mom[g'][c][k-1][n]
 // (transpose: sigma(g -> g')).  sigma_cm [ncell][L][G][G] holds orders 1..L
 // cell-major, from g' into g at [c][n-1][g'][g], so that the G*G matrix a
 // thread reads lies in one run.
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
         const int n = r & 7;
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
         const Real *sig = sigma_cm + (c * L + (order - 1)) * G * G;
-        const Real *mk = mom + (long long)(k - 1) * G * ncell * 8 + c * 8 + n;
+        const Real *mk = mom + e;
         // the source groups' moments of this (cell, moment, node) are read
         // once, 16 at a time into registers (clamped loads, in bounds), and
         // serve every destination group; past 16 groups the partial sums
@@ -272,7 +292,7 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
         for (int g0 = 0; g0 < G; g0 += 16) {
             Real mv[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) mv[j] = mk[(long long)min(g0 + j, G - 1) * ncell * 8];
+            for (int j = 0; j < 16; ++j) mv[j] = mk[(long long)min(g0 + j, G - 1) * per_group];
             for (int g = 0; g < G; ++g) {
                 Real *out = msrc + (long long)g * per_group + e;
                 Real v = g0 ? *out : Real(0);
@@ -519,6 +539,16 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 }
 
 template <typename Real>
+int launch_moments_public(long long nv, int nm, const Real *src, Real *dst, hipStream_t s)
+{
+    if (nm < 2 || nm > kYlmStride) return set_error(DGSN_EINVAL, "bad moment count %d", nm);
+    hipLaunchKernelGGL(moments_public<Real>, dim3(grid_for((long long)(nm - 1) * nv * 8)),
+                       dim3(256), 0, s, nv, nm - 1, src, dst);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template <typename Real>
 int launch_cell_major(long long ncell, int nmat, const Real *src, Real *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(cell_major<Real>, dim3(grid_for(ncell * nmat)), dim3(256), 0, s, ncell,
@@ -558,7 +588,8 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
                                              Real *, hipStream_t);                             \
     template int launch_build_msrc_gg<Real>(long long, int, int, const Real *, const Real *,    \
                                             Real *, bool, hipStream_t);                        \
-    template int launch_cell_major<Real>(long long, int, const Real *, Real *, hipStream_t);
+    template int launch_cell_major<Real>(long long, int, const Real *, Real *, hipStream_t);   \
+    template int launch_moments_public<Real>(long long, int, const Real *, Real *, hipStream_t);
 DGSN_INST(float)
 DGSN_INST(double)
 
