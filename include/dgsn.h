@@ -165,8 +165,9 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
  * order is set, and so does this call while a group-to-group matrix
  * is set (and dgsn_problem_set_scattering while an order is set; see
  * dgsn_problem_set_anisotropy_gg for both).
- * DGSN_ENOMEM if the moment buffers (9 (L+1)^2 G*cells*8 reals) cannot be
- * allocated.
+ * DGSN_ENOMEM if the moment buffers (10 ((L+1)^2 - 1) G*cells*8 reals) cannot be
+ * allocated; a call that fails after its checks leaves the problem with no
+ * anisotropic orders.
  */
 int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream);
 
@@ -190,6 +191,8 @@ int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn
  * 2; GE solvers; the adjoint and a stored angular flux with DGSN_GE).
  * DGSN_EINVAL for an order outside 1..3 or a NULL array; DGSN_ENOMEM if the
  * buffers (the moment buffers and (L+1) G*G*cells reals) cannot be allocated.
+ * A call that fails after its checks leaves the problem with no anisotropic
+ * orders and no group-to-group matrix (in-group isotropic scattering).
  */
 int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma_sn_gg,
                                    void *stream);

@@ -230,8 +230,14 @@ class Problem:
         if L < 1 or L * self.groups * self.ncell != size:
             raise ValueError("sigma_sn must hold [L, G, ncell] values")
         m = self._dev(sigma_sn, (L, self.groups, self.ncell))
-        _lib.check(lib.dgsn_problem_set_anisotropy(self._h, L, _ptr(m),
-                                                   _stream(self.ctx.device)))
+        self._set_orders(lib.dgsn_problem_set_anisotropy(self._h, L, _ptr(m),
+                                                         _stream(self.ctx.device)), L)
+
+    def _set_orders(self, rc, L):
+        # a setter that fails after its argument checks leaves no orders
+        if rc in (_lib.DGSN_ENOMEM, _lib.DGSN_EHIP):
+            self.pl_order = 0
+        _lib.check(rc)
         torch.cuda.current_stream(self.ctx.device).synchronize()
         self.pl_order = L
 
@@ -245,10 +251,8 @@ class Problem:
         if L < 1 or (L + 1) * per != size:
             raise ValueError("sigma_sn_gg must hold [L+1, G, G, ncell] values with L >= 1")
         m = self._dev(sigma_sn_gg, (L + 1, self.groups, self.groups, self.ncell))
-        _lib.check(_lib.load().dgsn_problem_set_anisotropy_gg(self._h, L, _ptr(m),
-                                                              _stream(self.ctx.device)))
-        torch.cuda.current_stream(self.ctx.device).synchronize()
-        self.pl_order = L
+        self._set_orders(_lib.load().dgsn_problem_set_anisotropy_gg(self._h, L, _ptr(m),
+                                                                    _stream(self.ctx.device)), L)
 
     def moments(self):
         """Flux moments k = 1 .. (L+1)^2 - 1 of the last source iteration,

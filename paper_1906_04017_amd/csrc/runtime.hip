@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "cell.hpp"
@@ -27,10 +28,23 @@ int set_error(int code, const char *fmt, ...)
 
 void clear_error() { g_msg[0] = '\0'; }
 
+// DGSN_TEST_ALLOC_LIMIT (bytes, unset or 0: none): device allocations above
+// it fail as if the device were out of memory, so that the error paths of
+// the setters can be exercised without exhausting the device.
+static size_t test_alloc_limit()
+{
+    const char *e = getenv("DGSN_TEST_ALLOC_LIMIT");
+    return e ? (size_t)strtoull(e, nullptr, 10) : 0;
+}
+
 int DevBuf::alloc(size_t n)
 {
     release();
     if (n == 0) return DGSN_OK;
+    const size_t lim = test_alloc_limit();
+    if (lim && n > lim)
+        return set_error(DGSN_ENOMEM, "allocation of %zu bytes refused (DGSN_TEST_ALLOC_LIMIT %zu)",
+                         n, lim);
     hipError_t e = hipMalloc(&ptr, n);
     if (e != hipSuccess) {
         ptr = nullptr;
@@ -1112,6 +1126,50 @@ int anisotropy_buffers(dgsn_problem *p, int order, size_t sbytes)
 }
 }  // namespace
 
+namespace {
+// No anisotropic orders: the state after order 0, and after a setter fails
+// part way (its buffers may already be gone), so that no later iteration
+// reads a released buffer.
+void drop_anisotropy(dgsn_problem *p)
+{
+    p->pl_order = 0;
+    p->pl_gg = 0;
+    p->sigma_sn.release();
+    p->d_ylm.release();
+    p->mom_oct.release();
+    p->mom.release();
+    p->msrc.release();
+}
+
+int set_anisotropy_impl(dgsn_problem *p, int order, const void *sigma_sn, hipStream_t s)
+{
+    const size_t sbytes = (size_t)order * p->G * p->ncell * p->real_size;
+    DGSN_TRY(anisotropy_buffers(p, order, sbytes));
+    DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, sigma_sn, sbytes, hipMemcpyDeviceToDevice, s));
+    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
+    p->pl_order = order;
+    p->pl_gg = 0;
+    return DGSN_OK;
+}
+
+int set_anisotropy_gg_impl(dgsn_problem *p, int order, const void *sigma_sn_gg, hipStream_t s)
+{
+    const size_t mat = (size_t)p->G * p->G * p->ncell * p->real_size;
+    DGSN_TRY(anisotropy_buffers(p, order, (size_t)order * mat));
+    if (p->sigma_gg.bytes != mat) DGSN_TRY(p->sigma_gg.alloc(mat));
+    const char *src = static_cast<const char *>(sigma_sn_gg);
+    // cell-major, one G x G matrix per (cell, order) in one run
+    DGSN_TRY(cell_major_matrix(p, src, p->G * p->G, p->sigma_gg.ptr, s));
+    DGSN_TRY(cell_major_matrix(p, src + mat, order * p->G * p->G, p->sigma_sn.ptr, s));
+    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
+    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
+    p->pl_order = order;
+    p->pl_gg = 1;
+    return DGSN_OK;
+}
+}  // namespace
+
 int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn, void *stream)
 {
     clear_error();
@@ -1120,13 +1178,7 @@ int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn
         return set_error(DGSN_EINVAL, "scattering order %d is outside 0..%d", order, kMaxPlOrder);
     DGSN_HIP(hipSetDevice(p->ctx->device));
     if (order == 0) {
-        p->pl_order = 0;
-        p->pl_gg = 0;
-        p->sigma_sn.release();
-        p->d_ylm.release();
-        p->mom_oct.release();
-        p->mom.release();
-        p->msrc.release();
+        drop_anisotropy(p);
         return DGSN_OK;
     }
     if (!sigma_sn) return set_error(DGSN_EINVAL, "sigma_sn is NULL");
@@ -1134,15 +1186,9 @@ int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn
         return set_error(DGSN_EUNSUPPORTED,
                          "a group-to-group matrix and in-group anisotropic scattering are "
                          "exclusive (dgsn_problem_set_anisotropy_gg sets both)");
-    const size_t sbytes = (size_t)order * p->G * p->ncell * p->real_size;
-    DGSN_TRY(anisotropy_buffers(p, order, sbytes));
-    hipStream_t s = as_stream(stream);
-    DGSN_HIP(hipMemcpyAsync(p->sigma_sn.ptr, sigma_sn, sbytes, hipMemcpyDeviceToDevice, s));
-    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
-    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
-    p->pl_order = order;
-    p->pl_gg = 0;
-    return DGSN_OK;
+    const int rc = set_anisotropy_impl(p, order, sigma_sn, as_stream(stream));
+    if (rc != DGSN_OK) drop_anisotropy(p);
+    return rc;
 }
 
 int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma_sn_gg,
@@ -1154,19 +1200,13 @@ int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma
         return set_error(DGSN_EINVAL, "scattering order %d is outside 1..%d", order, kMaxPlOrder);
     if (!sigma_sn_gg) return set_error(DGSN_EINVAL, "sigma_sn_gg is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
-    const size_t mat = (size_t)p->G * p->G * p->ncell * p->real_size;
-    DGSN_TRY(anisotropy_buffers(p, order, (size_t)order * mat));
-    if (p->sigma_gg.bytes != mat) DGSN_TRY(p->sigma_gg.alloc(mat));
-    hipStream_t s = as_stream(stream);
-    const char *src = static_cast<const char *>(sigma_sn_gg);
-    // cell-major, one G x G matrix per (cell, order) in one run
-    DGSN_TRY(cell_major_matrix(p, src, p->G * p->G, p->sigma_gg.ptr, s));
-    DGSN_TRY(cell_major_matrix(p, src + mat, order * p->G * p->G, p->sigma_sn.ptr, s));
-    DGSN_HIP(hipMemsetAsync(p->mom.ptr, 0, p->mom.bytes, s));
-    DGSN_HIP(hipMemsetAsync(p->msrc.ptr, 0, p->msrc.bytes, s));
-    p->pl_order = order;
-    p->pl_gg = 1;
-    return DGSN_OK;
+    const int rc = set_anisotropy_gg_impl(p, order, sigma_sn_gg, as_stream(stream));
+    if (rc != DGSN_OK) {
+        // the order-0 matrix may be released or half copied: drop it too
+        drop_anisotropy(p);
+        p->sigma_gg.release();
+    }
+    return rc;
 }
 
 int dgsn_problem_get_moments(const dgsn_problem *p, void *mom, void *stream)

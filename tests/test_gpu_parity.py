@@ -658,6 +658,38 @@ def test_pl_gg_many_groups(api, ctx):
         assert np.abs(mom - ref["mom"]).max() <= bound * np.abs(ref["phi"]).max()
 
 
+def test_anisotropy_setters_fail_cleanly(api, ctx, monkeypatch):
+    # an allocation failure part way through either setter (forced from the
+    # host: allocations above DGSN_TEST_ALLOC_LIMIT are refused) leaves the
+    # problem without anisotropic orders, so the next source iteration is the
+    # isotropic one and reads no released buffer
+    p = inputs.random_problem((5, 4, 4), 4, 2, seed=230, c_max=0.7)
+    nc = p["sigma_t"].shape[1]
+    print_case("pl_alloc_failure", name=p["name"])
+    ref = gpu_problem(api, ctx, p, "fp32")
+    phi_ref, _ = ref.source_iterate(tol=0.0, max_iter=5, allow_notconv=True)
+    ref.close()
+    mbytes = 3 * 2 * nc * 8 * 4          # one moment buffer at L = 1 (mom_oct is 8 of them)
+    prob = gpu_problem(api, ctx, p, "fp32")
+    prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], 1, seed=231))
+    monkeypatch.setenv("DGSN_TEST_ALLOC_LIMIT", str(mbytes))
+    with pytest.raises(api.DgsnError, match="ENOMEM"):
+        prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], 2, seed=232))
+    with pytest.raises(api.DgsnError, match="ENOMEM"):
+        prob.set_anisotropy_gg(_multigroup_pl(p, 3, 233))
+    monkeypatch.delenv("DGSN_TEST_ALLOC_LIMIT")
+    assert prob.pl_order == 0
+    lib = api._lib.load()
+    out = torch.empty(1024, dtype=torch.float32, device="cuda")
+    assert lib.dgsn_problem_get_moments(prob._h, out.data_ptr(), None) == api._lib.DGSN_EINVAL
+    phi, _ = prob.source_iterate(tol=0.0, max_iter=5, allow_notconv=True)
+    assert np.array_equal(phi.cpu().numpy(), phi_ref.cpu().numpy())
+    # and the setters work again once allocations succeed
+    prob.set_anisotropy_gg(_multigroup_pl(p, 1, 234))
+    phi_gg, _ = prob.source_iterate(tol=1e-8, max_iter=1000, allow_notconv=True)
+    assert rel(phi_gg.cpu().numpy(), _pl_gg_reference(p, _multigroup_pl(p, 1, 234))["phi"]) <= FP32_TOL
+
+
 @pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
 def test_pl_gg_adjoint_matches_oracle(api, ctx, precision, L):
     p = inputs.random_problem((5, 4, 4), 4, 3, seed=210 + L, length=(0.5, 0.4, 0.4))
