@@ -223,7 +223,7 @@ int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
    problem keeps a reference; the ANN must outlive its use by the problem.
    A paper-form (version-2) network is folded for this problem's cell sizes
    here (a small device buffer owned by the problem; DGSN_ENOMEM if it cannot
-   be allocated). */
+   be allocated, and then no network is attached). */
 int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
 
 /* Select the local solver of subsequent sweeps (DGSN_GE, DGSN_GE_DENSE or

@@ -605,11 +605,14 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
                  int *iters, hipStream_t s)
 {
     const long long nv = (long long)p->G * p->ncell;
-    if (p->adj_phi.bytes != (size_t)(2 * nv * 8) * p->real_size) {
+    // each buffer checked on its own: a call that failed part way may have
+    // left some of them allocated and others released
+    if (p->adj_phi.bytes != (size_t)(2 * nv * 8) * p->real_size)
         DGSN_TRY(p->adj_phi.alloc(2 * nv * 8 * p->real_size));   // two adjoint iterates
+    if (p->adj_src.bytes != (size_t)(3 * nv * 8) * p->real_size)
         DGSN_TRY(p->adj_src.alloc(3 * nv * 8 * p->real_size));   // load and two sources
+    if (p->grad_oct.bytes != (size_t)(8 * nv * 2) * p->real_size)
         DGSN_TRY(p->grad_oct.alloc(8 * nv * 2 * p->real_size));
-    }
     Real *phid[2] = {static_cast<Real *>(p->adj_phi.ptr),
                      static_cast<Real *>(p->adj_phi.ptr) + nv * 8};
     Real *load = static_cast<Real *>(p->adj_src.ptr);
@@ -1116,11 +1119,9 @@ int anisotropy_buffers(dgsn_problem *p, int order, size_t sbytes)
     DGSN_TRY(p->precision == DGSN_FP64 ? upload_real<double>(p->d_ylm, y)
                                        : upload_real<float>(p->d_ylm, y));
     const size_t mbytes = (size_t)(nm - 1) * nv * 8 * p->real_size;
-    if (p->mom.bytes != mbytes) {
-        DGSN_TRY(p->mom.alloc(mbytes));
-        DGSN_TRY(p->msrc.alloc(mbytes));
-        DGSN_TRY(p->mom_oct.alloc(8 * mbytes));
-    }
+    if (p->mom.bytes != mbytes) DGSN_TRY(p->mom.alloc(mbytes));
+    if (p->msrc.bytes != mbytes) DGSN_TRY(p->msrc.alloc(mbytes));
+    if (p->mom_oct.bytes != 8 * mbytes) DGSN_TRY(p->mom_oct.alloc(8 * mbytes));
     if (p->sigma_sn.bytes != sbytes) DGSN_TRY(p->sigma_sn.alloc(sbytes));
     return DGSN_OK;
 }
@@ -1262,9 +1263,20 @@ int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
         std::vector<float> img;
         DGSN_TRY(pann_problem_image(ann, p->h, img));
         DGSN_HIP(hipSetDevice(p->ctx->device));
-        DGSN_TRY(p->d_pann.alloc(img.size() * sizeof(float)));
-        DGSN_HIP(hipMemcpy(p->d_pann.ptr, img.data(), img.size() * sizeof(float),
-                           hipMemcpyHostToDevice));
+        // past this point a failure leaves no network attached (the folded
+        // image of a network attached before may be gone)
+        int rc = p->d_pann.alloc(img.size() * sizeof(float));
+        if (rc == DGSN_OK) {
+            const hipError_t e = hipMemcpy(p->d_pann.ptr, img.data(), img.size() * sizeof(float),
+                                           hipMemcpyHostToDevice);
+            if (e != hipSuccess)
+                rc = set_error(DGSN_EHIP, "hipMemcpy failed: %s", hipGetErrorString(e));
+        }
+        if (rc != DGSN_OK) {
+            p->ann = nullptr;
+            p->d_pann.release();
+            return rc;
+        }
     }
     p->ann = ann;
     return DGSN_OK;

@@ -924,6 +924,28 @@ def test_pann_infer_octant_within_fp32_bound(api, ctx, tmp_path, nh):
         ann.infer(torch.zeros((4, 24), device="cuda"))
 
 
+def test_set_ann_failure_leaves_no_network(api, ctx, tmp_path, monkeypatch):
+    # the per-problem image of a paper-form network cannot be allocated
+    # (forced from the host): the problem is left with no network, so a
+    # sweep reports the missing network instead of reading a released image
+    path, _ = _write_pann(tmp_path, _random_pann(410), "pf.dgsnann")
+    ann = api.Ann(ctx, path)
+    p = inputs.random_problem((4, 4, 3), 4, 1, seed=235)
+    print_case("set_ann_failure", name=p["name"])
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    src = torch.ones((1, p["sigma_t"].shape[1], 8), dtype=torch.float32, device="cuda")
+    good = prob.sweep(src).cpu().numpy()
+    monkeypatch.setenv("DGSN_TEST_ALLOC_LIMIT", "64")
+    with pytest.raises(api.DgsnError, match="ENOMEM"):
+        prob.set_ann(ann)
+    monkeypatch.delenv("DGSN_TEST_ALLOC_LIMIT")
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        prob.sweep(src)
+    prob.set_ann(ann)
+    assert np.array_equal(prob.sweep(src).cpu().numpy(), good)
+
+
 PANN_CASES = [((5, 4, 6), (0.5, 0.4, 0.6), 4, 2), ((7, 5, 6), (0.7, 0.5, 0.6), 6, 1),
               ((3, 8, 2), (0.3, 0.8, 0.2), 8, 3)]
 
