@@ -46,7 +46,10 @@ typedef struct dgsn_batch dgsn_batch;
 enum {
     DGSN_OK = 0,
     DGSN_EINVAL = -1,        /* invalid argument */
-    DGSN_ENOMEM = -2,        /* host or device allocation failed */
+    DGSN_ENOMEM = -2,        /* host or device allocation failed (for tests, device
+                                allocations above DGSN_TEST_ALLOC_LIMIT bytes, an
+                                environment variable read at each allocation, fail
+                                with this code) */
     DGSN_EHIP = -3,          /* a HIP runtime call failed */
     DGSN_ENOTCONV = -4,      /* iteration limit reached; outputs hold the last iterate */
     DGSN_EFORMAT = -5,       /* malformed ANN artifact */
