@@ -690,6 +690,35 @@ def test_anisotropy_setters_fail_cleanly(api, ctx, monkeypatch):
     assert rel(phi_gg.cpu().numpy(), _pl_gg_reference(p, _multigroup_pl(p, 1, 234))["phi"]) <= FP32_TOL
 
 
+@pytest.mark.parametrize("gg", [False, True], ids=["in_group", "group_to_group"])
+def test_pl_adjoint_schedules_and_tiles_bitwise(api, ctx, gg):
+    # the anisotropic adjoint (reversed sweeps of the transposed cell systems
+    # with the adjoint flux's moments) runs the same arithmetic under both
+    # schedules; tile edges differ only by rounding
+    p = inputs.random_problem((6, 5, 4), 4, 2, seed=240, c_max=0.7)
+    print_case("pl_adjoint_schedules", name=p["name"], gg=gg)
+    rng = np.random.default_rng(241)
+    g = rng.uniform(0.0, 1.0, (2, p["sigma_t"].shape[1], 8))
+    out = {}
+    for sched in ("planes", "dataflow"):
+        for b in (1, 2):
+            prob = gpu_problem(api, ctx, p, "fp32", store_psi=True)
+            if gg:
+                prob.set_anisotropy_gg(_multigroup_pl(p, 1, 242, c=0.7))
+            else:
+                prob.set_anisotropy(inputs.anisotropic_orders(p["sigma_s"], 2, seed=243))
+            prob.set_schedule(sched)
+            prob.set_tile(b)
+            prob.source_iterate(tol=0.0, max_iter=8, allow_notconv=True)
+            gst, gq, _ = prob.adjoint(g, tol=0.0, max_iter=8, allow_notconv=True)
+            out[(sched, b)] = (gst.cpu().numpy(), gq.cpu().numpy())
+            prob.close()
+    for b in (1, 2):
+        assert np.array_equal(out[("planes", b)][0], out[("dataflow", b)][0])
+        assert np.array_equal(out[("planes", b)][1], out[("dataflow", b)][1])
+    assert rel(out[("planes", 2)][1], out[("planes", 1)][1]) <= 1e-4
+
+
 @pytest.mark.parametrize("precision,L", [("fp64", 1), ("fp64", 2), ("fp32", 2)])
 def test_pl_gg_adjoint_matches_oracle(api, ctx, precision, L):
     p = inputs.random_problem((5, 4, 4), 4, 3, seed=210 + L, length=(0.5, 0.4, 0.4))
