@@ -352,7 +352,9 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
     const Real w = lane_ok ? dp[kDirW] : Real(0);
     const Real kap[3] = {dp[kDirK], dp[kDirK + 1], dp[kDirK + 2]};
-    const Real *yl = kMom > 0 ? A.ylm + (o * A.Do + (lane_ok ? d : 0)) * kYlmStride : nullptr;
+    // the lane's harmonics, from the block's octant table in LDS (read per
+    // cell: cheaper than holding kMom more registers)
+    const Real *yl = kMom > 0 ? ytab + (lane_ok ? d : 0) * kYlmStride : nullptr;
     AnnRegs R;
     if (Form == kFormAnn) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
     uint32_t I0 = 0, J0 = 0, K0 = 0;
