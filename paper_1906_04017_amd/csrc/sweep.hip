@@ -280,8 +280,7 @@ __global__ __launch_bounds__(256) void build_msrc_gg(long long ncell, int G, int
          e += stride) {
         const long long c = e / (nk * 8);
         const int r = (int)(e - c * (nk * 8));
-        const int k = (r >> 3) + 1;
-        const int n = r & 7;
+        const int k = (r >> 3) + 1;   // the node is r & 7
         const int order = k >= 9 ? 3 : (k >= 4 ? 2 : 1);
         const Real *sig = sigma_cm + (c * L + (order - 1)) * G * G;
         const Real *mk = mom + e;
