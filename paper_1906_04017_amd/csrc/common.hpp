@@ -165,6 +165,7 @@ struct dgsn_problem {
     dgsn::HostBuf h_result;                   // pinned [2][4] FP64 + [2] error words
     hipEvent_t ev_result[2] = {nullptr, nullptr};   // each slot's readback is complete
     dgsn::DevBuf phi_alt;                     // [G][ncell][8] second iterate buffer
+    dgsn::DevBuf d_check;                     // one flag word of the materials check
     int red_blocks = 0;
 
     // optional per-launch kernel timing of the last sweep

@@ -157,6 +157,11 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 template <typename Real>
 int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s);
+// *bad |= 1 (sigma_t), 2 (sigma_s) where a value is negative or not finite,
+// 4 where q is not finite; n values each
+template <typename Real>
+int launch_check_materials(long long n, const Real *st, const Real *ss, const Real *q,
+                           unsigned *bad, hipStream_t s);
 // the public layout of the moments: dst [nm-1][G][ncell][8] from src [G][ncell][nm-1][8]
 template <typename Real>
 int launch_moments_public(long long nv, int nm, const Real *src, Real *dst, hipStream_t s);

@@ -1069,6 +1069,27 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
     else DGSN_HIP(hipMemsetAsync(p->sigma_s.ptr, 0, bytes, s));
     if (q) DGSN_HIP(hipMemcpyAsync(p->q.ptr, q, bytes, hipMemcpyDeviceToDevice, s));
     else DGSN_HIP(hipMemsetAsync(p->q.ptr, 0, bytes, s));
+    // validity of the copies (waits for the stream)
+    if (!p->d_check.ptr) DGSN_TRY(p->d_check.alloc(sizeof(unsigned)));
+    DGSN_HIP(hipMemsetAsync(p->d_check.ptr, 0, sizeof(unsigned), s));
+    const long long n = (long long)p->G * p->ncell;
+    unsigned *flag = static_cast<unsigned *>(p->d_check.ptr);
+    if (p->precision == DGSN_FP64)
+        DGSN_TRY(launch_check_materials<double>(n, static_cast<const double *>(p->sigma_t.ptr),
+                                                static_cast<const double *>(p->sigma_s.ptr),
+                                                static_cast<const double *>(p->q.ptr), flag, s));
+    else
+        DGSN_TRY(launch_check_materials<float>(n, static_cast<const float *>(p->sigma_t.ptr),
+                                               static_cast<const float *>(p->sigma_s.ptr),
+                                               static_cast<const float *>(p->q.ptr), flag, s));
+    unsigned bad = 0;
+    DGSN_HIP(hipMemcpyAsync(&bad, flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    DGSN_HIP(hipStreamSynchronize(s));
+    if (bad)
+        return set_error(DGSN_EINVAL, "invalid materials:%s%s%s",
+                         (bad & 1u) ? " sigma_t negative or not finite;" : "",
+                         (bad & 2u) ? " sigma_s negative or not finite;" : "",
+                         (bad & 4u) ? " q not finite;" : "");
     return DGSN_OK;
 }
 

@@ -244,6 +244,26 @@ __global__ __launch_bounds__(256) void moments_public(long long nv, int nk,
     }
 }
 
+// Validity of the materials: bit 0 when some sigma_t is negative or not
+// finite, bit 1 likewise for sigma_s, bit 2 when some q is not finite
+// (a vector atomic OR into *bad per offending thread).
+template <typename Real>
+__global__ __launch_bounds__(256) void check_materials(long long n, const Real *__restrict__ st,
+                                                       const Real *__restrict__ ss,
+                                                       const Real *__restrict__ q,
+                                                       unsigned *__restrict__ bad)
+{
+    unsigned b = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const Real t = st[e], s = ss[e], v = q[e];
+        if (!(t >= Real(0)) || isinf(t)) b |= 1u;   // a NaN fails the comparison
+        if (!(s >= Real(0)) || isinf(s)) b |= 2u;
+        if (!isfinite(v)) b |= 4u;
+    }
+    if (b) atomicOr(bad, b);
+}
+
 // Cell-major copy of per-cell matrices: dst[c][j] = src[j][c] for nmat
 // values j per cell (one thread per destination value).
 template <typename Real>
@@ -538,6 +558,16 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 }
 
 template <typename Real>
+int launch_check_materials(long long n, const Real *st, const Real *ss, const Real *q,
+                           unsigned *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_materials<Real>, dim3(grid_for(n)), dim3(256), 0, s, n, st, ss, q,
+                       bad);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template <typename Real>
 int launch_moments_public(long long nv, int nm, const Real *src, Real *dst, hipStream_t s)
 {
     if (nm < 2 || nm > kYlmStride) return set_error(DGSN_EINVAL, "bad moment count %d", nm);
@@ -588,7 +618,9 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
     template int launch_build_msrc_gg<Real>(long long, int, int, const Real *, const Real *,    \
                                             Real *, bool, hipStream_t);                        \
     template int launch_cell_major<Real>(long long, int, const Real *, Real *, hipStream_t);   \
-    template int launch_moments_public<Real>(long long, int, const Real *, Real *, hipStream_t);
+    template int launch_moments_public<Real>(long long, int, const Real *, Real *, hipStream_t); \
+    template int launch_check_materials<Real>(long long, const Real *, const Real *, const Real *, \
+                                              unsigned *, hipStream_t);
 DGSN_INST(float)
 DGSN_INST(double)
 

@@ -953,6 +953,32 @@ def test_pann_infer_octant_within_fp32_bound(api, ctx, tmp_path, nh):
         ann.infer(torch.zeros((4, 24), device="cuda"))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_set_materials_rejects_invalid_values(api, ctx, precision):
+    p = inputs.random_problem((4, 3, 3), 4, 2, seed=236, c_max=0.5)
+    print_case("invalid_materials", name=p["name"], precision=precision)
+    prob = gpu_problem(api, ctx, p, precision)
+    st, ss, q = p["sigma_t"].copy(), p["sigma_s"].copy(), p["q"].copy()
+    cases = [("sigma_t", dict(st=np.nan)), ("sigma_t", dict(st=-0.5)), ("sigma_t", dict(st=np.inf)),
+             ("sigma_s", dict(ss=-1e-3)), ("sigma_s", dict(ss=np.nan)), ("q", dict(q=-np.inf))]
+    for name, bad in cases:
+        a, b, c = st.copy(), ss.copy(), q.copy()
+        if "st" in bad: a[1, 7] = bad["st"]
+        if "ss" in bad: b[0, 3] = bad["ss"]
+        if "q" in bad: c[1, 0] = bad["q"]
+        with pytest.raises(api.DgsnError, match=f"EINVAL.*{name}"):
+            prob.set_materials(a, b, c)
+    # zero cross sections and a negative (finite) source are valid
+    z = np.zeros_like(st)
+    prob.set_materials(z, z, -q)
+    prob.set_materials(st, ss, q)
+    phi, info = prob.source_iterate(tol=1e-6, max_iter=500, allow_notconv=True)
+    om, w = oracle.lq_n(4)
+    ref = oracle.source_iterate(mesh_of(p), om, w, st, ss, q, p["psi_inc"], tol=1e-12,
+                                max_iter=3000)
+    assert rel(phi.cpu().numpy(), ref["phi"]) <= 1e-4
+
+
 def test_set_ann_failure_leaves_no_network(api, ctx, tmp_path, monkeypatch):
     # the per-problem image of a paper-form network cannot be allocated
     # (forced from the host): the problem is left with no network, so a
