@@ -82,6 +82,9 @@ def _load():
         [ctypes.c_int] * 2 + [_D] * 6 + _pann + [_D, ctypes.c_double, ctypes.c_int, _I, _D, _D,
                                                  ctypes.c_int]
     lib.orc_real_ylm.argtypes = [ctypes.c_int, _D, _D]
+    lib.orc_si_metrics.argtypes = [ctypes.c_long, _D, _D, _D, _D]
+    lib.orc_sweep_balance.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
+        [ctypes.c_int] * 2 + [_D] * 7
     lib.orc_source_iterate_pl.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 3 + [ctypes.c_int] + [_D] * 5 + \
         [ctypes.c_double, ctypes.c_int, _I, _D, _D, _D, ctypes.c_int]
@@ -201,6 +204,43 @@ def sweep(mesh, omega, weight, sigma_t, src, psi_inc=None, store_psi=False, nthr
                        _p(sigma_t), _p(src), _p(inc), _p(phi), _p(psi), int(nthreads))
     _check(rc, "sweep")
     return (phi, psi) if store_psi else phi
+
+
+def si_metrics(phi_new, phi_old):
+    """(r, eps_s) of one source-iteration step: the max-norm relative change
+    and Eq. (Test:Eq3) on cell averages (orc_si_metrics).  phi_* [..., 8]
+    nodal fluxes of the same shape (the last axis the cell's 8 nodes)."""
+    lib = _load()
+    a = _f64(phi_new).reshape(-1, 8)
+    b = _f64(phi_old).reshape(-1, 8)
+    if a.shape != b.shape:
+        raise ValueError("phi_new and phi_old must have the same shape")
+    r = ctypes.c_double(0)
+    e = ctypes.c_double(0)
+    lib.orc_si_metrics(a.shape[0], _p(a), _p(b), ctypes.byref(r), ctypes.byref(e))
+    return r.value, e.value
+
+
+def sweep_balance(mesh, omega, weight, sigma_t, src, psi_inc, psi):
+    """Particle balance of one sweep from its stored angular flux psi
+    [D, G, ncell, 8] (orc_sweep_balance): dict with the weighted outflow and
+    inflow over all cell faces and over the domain boundary, absorption and
+    source."""
+    lib = _load()
+    nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
+    ncell = nx * ny * nz
+    omega = _f64(omega)
+    nd = omega.shape[0]
+    sigma_t = _f64(sigma_t).reshape(-1, ncell)
+    ng = sigma_t.shape[0]
+    out = np.zeros(6)
+    rc = lib.orc_sweep_balance(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                               _p(sigma_t), _p(_f64(src, (ng, ncell, 8))),
+                               _p(_f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))),
+                               _p(_f64(psi, (nd, ng, ncell, 8))), _p(out))
+    _check(rc, "sweep_balance")
+    return dict(outflow_all=out[0], inflow_all=out[1], outflow=out[2], inflow=out[3],
+                absorption=out[4], source=out[5])
 
 
 def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-8,

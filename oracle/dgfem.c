@@ -404,6 +404,39 @@ int orc_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int ng, i
                      psi_store, NULL, nthreads);
 }
 
+/*
+ * Convergence measures of one source iteration step, from the new and the
+ * previous scalar flux (nv = G * ncell values of 8 nodes each):
+ *   r     = max_{g,c,n} |phi_new - phi_old| / max_{g,c,n} |phi_new|  (0 if phi_new = 0),
+ *           the max-norm relative change used as the stopping test;
+ *   eps_s = Eq. (Test:Eq3), the mean over the nv (group, cell) pairs of the
+ *           pointwise relative change of the cell-average flux
+ *           |avg_new - avg_old| / |avg_new|, avg the mean of the cell's 8
+ *           nodal values (the trilinear flux integrated over the cell and
+ *           divided by its volume).  A cell whose new average is 0 counts 0
+ *           if the old one is 0 as well and 1 otherwise (the relative change
+ *           of Eq. (Test:Eq3) is undefined there; a change from a non-zero
+ *           value to zero is a full change).
+ */
+void orc_si_metrics(long nv, const double *phi_new, const double *phi_old, double *r,
+                    double *eps_s)
+{
+    double dmax = 0.0, fmax = 0.0, esum = 0.0;
+    for (long i = 0; i < nv * 8; ++i) {
+        const double dd = fabs(phi_new[i] - phi_old[i]);
+        if (dd > dmax) dmax = dd;
+        if (fabs(phi_new[i]) > fmax) fmax = fabs(phi_new[i]);
+    }
+    for (long gc = 0; gc < nv; ++gc) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < 8; ++k) { a += phi_new[gc * 8 + k]; b += phi_old[gc * 8 + k]; }
+        a /= 8.0; b /= 8.0;
+        esum += (a != 0.0) ? fabs(a - b) / fabs(a) : (b != 0.0 ? 1.0 : 0.0);
+    }
+    *r = fmax > 0.0 ? dmax / fmax : 0.0;
+    *eps_s = esum / (double)nv;
+}
+
 /* Nodal total source S = q_ext + sigma_s / (4 pi) phi (isotropic, Eq. (T5) P0 term). */
 static void build_source(long n, const double *q, const double *sigma_s, const double *phi,
                          double *S)
@@ -460,20 +493,7 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
         rc = sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, S, psi_inc, phin,
                        psi_store, net, nthreads);
         if (rc) break;
-        double dmax = 0.0, fmax = 0.0, esum = 0.0;
-        for (long i = 0; i < nv * 8; ++i) {
-            const double dd = fabs(phin[i] - phi[i]);
-            if (dd > dmax) dmax = dd;
-            if (fabs(phin[i]) > fmax) fmax = fabs(phin[i]);
-        }
-        for (long gc = 0; gc < nv; ++gc) {
-            double a = 0.0, b = 0.0;
-            for (int k = 0; k < 8; ++k) { a += phin[gc * 8 + k]; b += phi[gc * 8 + k]; }
-            a /= 8.0; b /= 8.0;
-            esum += (a != 0.0) ? fabs(a - b) / fabs(a) : (b != 0.0 ? 1.0 : 0.0);
-        }
-        r = fmax > 0.0 ? dmax / fmax : 0.0;
-        es = esum / (double)nv;
+        orc_si_metrics(nv, phin, phi, &r, &es);
         memcpy(phi, phin, (size_t)nv * 8 * sizeof(double));
         ++it;
         if (r < tol) break;
@@ -681,20 +701,7 @@ static int source_iterate_pl(int nx, int ny, int nz, double lx, double ly, doubl
                 }
         }
         if (err) break;
-        double dmax = 0.0, fmax = 0.0, esum = 0.0;
-        for (long i = 0; i < nv * 8; ++i) {
-            const double dd = fabs(phin[i] - phi[i]);
-            if (dd > dmax) dmax = dd;
-            if (fabs(phin[i]) > fmax) fmax = fabs(phin[i]);
-        }
-        for (long gc = 0; gc < nv; ++gc) {
-            double a = 0.0, b = 0.0;
-            for (int k = 0; k < 8; ++k) { a += phin[gc * 8 + k]; b += phi[gc * 8 + k]; }
-            a /= 8.0; b /= 8.0;
-            esum += (a != 0.0) ? fabs(a - b) / fabs(a) : (b != 0.0 ? 1.0 : 0.0);
-        }
-        r = fmax > 0.0 ? dmax / fmax : 0.0;
-        es = esum / (double)nv;
+        orc_si_metrics(nv, phin, phi, &r, &es);
         memcpy(phi, phin, (size_t)nv * 8 * sizeof(double));
         memcpy(mom, momn, (size_t)(nm - 1) * nv * 8 * sizeof(double));
         ++it;
@@ -1104,6 +1111,80 @@ double orc_cell_balance(const double h[3], const double omega[3], double sigma_t
         s += v;
     }
     return s;
+}
+
+/*
+ * Particle balance of a whole sweep, term by term, from the stored angular
+ * flux psi [D][G][ncell][8] of that sweep (the same sigma_t, src and psi_inc).
+ * For each direction d, group g and cell c, with the partition of unity of
+ * the basis (sum_k b_k = 1), the integrals over a face f and over the cell
+ * are 1^T Mf_f v and 1^T M v of the nodal vector v.  Summed with the weights
+ * w_d:
+ *   out[0]  outflow through every cell face with omega.n_f > 0:  (omega.n_f) int_f psi
+ *   out[1]  inflow through every cell face with omega.n_f < 0:   |omega.n_f| int_f psi_up
+ *           (psi_up the upwind neighbour's trace, psi_inc on the domain boundary)
+ *   out[2]  out[0] restricted to faces on the domain boundary
+ *   out[3]  out[1] restricted to faces on the domain boundary
+ *   out[4]  absorption  sigma_t int_c psi
+ *   out[5]  source      int_c S
+ * For the exact cell solutions out[0] - out[1] + out[4] - out[5] = 0 (the
+ * weak form tested with 1), and the interior faces cancel in out[0] - out[1]
+ * (a downwind cell's inflow trace is its upwind neighbour's outflow), so
+ * out[2] - out[3] = out[0] - out[1].
+ */
+int orc_sweep_balance(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
+                      const double *omega, const double *weight, const double *sigma_t,
+                      const double *src, const double psi_inc[6], const double *psi,
+                      double out[6])
+{
+    if (nx < 1 || ny < 1 || nz < 1 || ng < 1 || nd < 1) return ORC_EINVAL;
+    orc_mesh m = {{nx, ny, nz}, {lx / nx, ly / ny, lz / nz}};
+    const long ncell = (long)nx * ny * nz;
+    double M[64], G[3][64], Mf[6][64];
+    orc_element_matrices(m.h, M, G, Mf);
+    for (int t = 0; t < 6; ++t) out[t] = 0.0;
+    for (int d = 0; d < nd; ++d)
+        for (int g = 0; g < ng; ++g) {
+            const double *om = omega + 3 * d;
+            const double *pd = psi + ((long)d * ng + g) * ncell * 8;
+            int c[3];
+            for (c[2] = 0; c[2] < nz; ++c[2])
+                for (c[1] = 0; c[1] < ny; ++c[1])
+                    for (c[0] = 0; c[0] < nx; ++c[0]) {
+                        const long ci = cell_index(&m, c);
+                        const double *pc = pd + 8 * ci;
+                        const double *sc = src + ((long)g * ncell + ci) * 8;
+                        double vol_psi = 0.0, vol_src = 0.0;
+                        for (int k = 0; k < 8; ++k)
+                            for (int j = 0; j < 8; ++j) {
+                                vol_psi += M[k * 8 + j] * pc[j];
+                                vol_src += M[k * 8 + j] * sc[j];
+                            }
+                        out[4] += weight[d] * sigma_t[(long)g * ncell + ci] * vol_psi;
+                        out[5] += weight[d] * vol_src;
+                        for (int f = 0; f < 6; ++f) {
+                            const double on = om[f / 2] * face_sign(f);
+                            if (on == 0.0) continue;
+                            int nb[3];
+                            const int boundary = !neighbour(&m, c, f, nb);
+                            double v[8];
+                            if (on > 0.0) memcpy(v, pc, sizeof(v));
+                            else upwind_trace(&m, c, f, pd, psi_inc, v);
+                            double face = 0.0;
+                            for (int k = 0; k < 8; ++k)
+                                for (int j = 0; j < 8; ++j) face += Mf[f][k * 8 + j] * v[j];
+                            const double term = weight[d] * fabs(on) * face;
+                            if (on > 0.0) {
+                                out[0] += term;
+                                if (boundary) out[2] += term;
+                            } else {
+                                out[1] += term;
+                                if (boundary) out[3] += term;
+                            }
+                        }
+                    }
+        }
+    return ORC_OK;
 }
 
 /* One-cell solve in physical orientation: assemble and GE. */

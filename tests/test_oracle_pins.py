@@ -950,3 +950,138 @@ def test_mass_inverse_cell_matrix_is_column_diagonally_dominant():
         for k in range(7):
             assert np.abs(S[k, k]) >= np.abs(S[k + 1:, k]).max() - 1e-12 * np.abs(S).max()
             S[k + 1:, k:] -= np.outer(S[k + 1:, k] / S[k, k], S[k, k:])
+
+
+# ---------------------------------------------------------------------------
+# source-iteration measures: the max-norm residual and eps_S (Eq. (Test:Eq3))
+# ---------------------------------------------------------------------------
+
+def _si_pair():
+    # two iterates over G = 2 groups x 2 cells, written by hand; cell averages
+    #   (g0,c0) old 1 -> new 2,   (g0,c1) old 4 -> new 0 (nodes +-1),
+    #   (g1,c0) old 0 -> new 0,   (g1,c1) old 3 (nodes 2/4) -> new 6
+    old = np.array([[[1.0] * 8, [4.0] * 8],
+                    [[0.0] * 8, [2.0, 4.0] * 4]])
+    new = np.array([[[3.0, 1.0] * 4, [1.0, -1.0] * 4],
+                    [[0.0] * 8, [6.0] * 8]])
+    return new, old
+
+
+def test_eps_s_hand_example():
+    # Eq. (Test:Eq3): mean over the (group, cell) pairs of |avg_new - avg_old|
+    # / |avg_new| on cell averages: (1/2 + 1 + 0 + 1/2) / 4 = 1/2.  A cell whose
+    # new average is 0 counts 1 (non-zero old) or 0 (zero old).  Mistakes this
+    # fails: nodal values instead of averages (1/3 for (g0,c0) alone),
+    # dividing by the old average (1 for (g0,c0)), averaging over cells only
+    # (1), and dropping the zero-average cells.
+    new, old = _si_pair()
+    r, es = oracle.si_metrics(new, old)
+    assert es == pytest.approx(0.5, abs=1e-15)
+    # max-norm residual: max |new - old| = 5 (node -1 against 4), over
+    # max |new| = 6 (not max |old| = 4, which would give 5/4)
+    assert r == pytest.approx(5.0 / 6.0, abs=1e-15)
+
+
+def test_eps_s_single_cell_cases():
+    # one cell: a uniform relative change of 10 % gives 0.1 / 1.1 in Eq.
+    # (Test:Eq3) (relative to the new value); new = old gives 0
+    old = np.full((1, 1, 8), 1.0)
+    new = np.full((1, 1, 8), 1.1)
+    r, es = oracle.si_metrics(new, old)
+    assert es == pytest.approx(0.1 / 1.1, rel=1e-14)
+    assert r == pytest.approx(0.1 / 1.1, rel=1e-14)
+    r, es = oracle.si_metrics(old, old)
+    assert r == 0.0 and es == 0.0
+    # all-zero new flux: r = 0 by convention, eps_S = 1 (every cell changed)
+    r, es = oracle.si_metrics(np.zeros((1, 1, 8)), old)
+    assert r == 0.0 and es == 1.0
+
+
+def test_source_iteration_reports_the_last_step_measures():
+    # the measures that source iteration returns are those of its last two
+    # iterates: run k-1 and k iterations from 0 and recompute them
+    rng = np.random.default_rng(61)
+    n, L = (3, 2, 2), (0.6, 0.4, 0.5)
+    om, w = oracle.lq_n(4)
+    st = rng.uniform(0.5, 2.0, (2, 12))
+    ss = 0.6 * st
+    q = rng.uniform(0.2, 1.0, (2, 12))
+    mesh = (*n, *L)
+    a = oracle.source_iterate(mesh, om, w, st, ss, q, tol=0.0, max_iter=4)
+    b = oracle.source_iterate(mesh, om, w, st, ss, q, tol=0.0, max_iter=5)
+    r, es = oracle.si_metrics(b["phi"], a["phi"])
+    assert b["iters"] == 5
+    assert b["resid"] == pytest.approx(r, rel=1e-13)
+    assert b["eps_s"] == pytest.approx(es, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# particle balance of a whole sweep (the weak form under Eq. (T9) tested with 1)
+# ---------------------------------------------------------------------------
+
+def _balance_case(seed, n=(3, 4, 2), L=(0.6, 0.8, 0.3), order=4, G=2, inc=None):
+    rng = np.random.default_rng(seed)
+    om, w = oracle.lq_n(order)
+    nc = n[0] * n[1] * n[2]
+    st = rng.uniform(0.3, 4.0, (G, nc))
+    S = rng.uniform(0.0, 1.0, (G, nc, 8))
+    inc = rng.uniform(0.0, 1.0, 6) if inc is None else np.asarray(inc, float)
+    mesh = (*n, *L)
+    phi, psi = oracle.sweep(mesh, om, w, st, S, inc, store_psi=True)
+    return mesh, om, w, st, S, inc, phi, psi
+
+
+def test_sweep_balance_closes_and_interior_faces_cancel():
+    mesh, om, w, st, S, inc, phi, psi = _balance_case(71)
+    b = oracle.sweep_balance(mesh, om, w, st, S, inc, psi)
+    scale = b["inflow"] + b["source"]
+    total = b["outflow_all"] - b["inflow_all"] + b["absorption"] - b["source"]
+    assert abs(total) < 1e-13 * scale
+    assert abs((b["outflow_all"] - b["inflow_all"]) - (b["outflow"] - b["inflow"])) < 1e-13 * scale
+    # interior faces are counted on both sides
+    assert b["outflow_all"] > b["outflow"] and b["inflow_all"] > b["inflow"]
+    # absorption is sigma_t times the volume integral of the scalar flux
+    V = np.prod(mesh[3:]) / (mesh[0] * mesh[1] * mesh[2])
+    assert b["absorption"] == pytest.approx((st * V * phi.mean(axis=2)).sum(), rel=1e-13)
+
+
+def test_sweep_balance_constant_solution():
+    # uniform sigma_t and q with inflow q/sigma_t on every face: psi = c
+    # everywhere, so absorption = source = 4 pi q V_domain, and the boundary
+    # outflow equals the inflow c sum_d w_d sum_a |Omega_a| (face area of a)
+    n, L = (3, 2, 4), (0.9, 0.5, 1.3)
+    om, w = oracle.lq_n(6)
+    nc = n[0] * n[1] * n[2]
+    st, q = 2.5, 0.8
+    c = q / st
+    mesh = (*n, *L)
+    S = np.full((1, nc, 8), q)
+    phi, psi = oracle.sweep(mesh, om, w, np.full((1, nc), st), S, np.full(6, c), store_psi=True)
+    b = oracle.sweep_balance(mesh, om, w, np.full((1, nc), st), S, np.full(6, c), psi)
+    Vd = L[0] * L[1] * L[2]
+    assert b["source"] == pytest.approx(w.sum() * q * Vd, rel=1e-13)
+    assert b["absorption"] == pytest.approx(w.sum() * q * Vd, rel=1e-12)
+    areas = np.array([L[1] * L[2], L[0] * L[2], L[0] * L[1]])
+    # every direction enters through one face per axis
+    expect = c * (w[:, None] * np.abs(om) * areas).sum()
+    assert b["inflow"] == pytest.approx(expect, rel=1e-13)
+    assert b["outflow"] == pytest.approx(expect, rel=1e-12)
+
+
+def test_sweep_balance_streaming_through_one_face():
+    # no collisions, no source, inflow 1 through x- only: everything entering
+    # leaves; the inflow is sum over directions with Omega_x > 0 of
+    # w Omega_x Ly Lz (a face area of the wrong axis fails on this machine)
+    n, L = (2, 3, 2), (0.4, 1.5, 0.7)
+    om, w = oracle.lq_n(4)
+    nc = n[0] * n[1] * n[2]
+    mesh = (*n, *L)
+    zero = np.zeros((1, nc))
+    S = np.zeros((1, nc, 8))
+    inc = np.array([1.0, 0, 0, 0, 0, 0])
+    _, psi = oracle.sweep(mesh, om, w, zero, S, inc, store_psi=True)
+    b = oracle.sweep_balance(mesh, om, w, zero, S, inc, psi)
+    expect = (w * np.clip(om[:, 0], 0, None)).sum() * L[1] * L[2]
+    assert b["inflow"] == pytest.approx(expect, rel=1e-14)
+    assert b["outflow"] == pytest.approx(expect, rel=1e-12)
+    assert b["absorption"] == 0.0 and b["source"] == 0.0
