@@ -143,7 +143,9 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
  * once, Jacobi in the group index), and the adjoint the transposed coupling;
  * the in-group sigma_s of dgsn_problem_set_materials is not used while a
  * matrix is set.  The array is copied (asynchronously on the stream); the
- * caller keeps ownership of its pointer.  NULL removes the matrix.  Single
+ * caller keeps ownership of its pointer.  NULL removes the matrix
+ * (DGSN_EUNSUPPORTED while group-to-group anisotropic orders are set: their
+ * order-0 matrix goes with them, see dgsn_problem_set_anisotropy_gg).  Single
  * sweeps (dgsn_sweep, batches) take the caller's source and are unaffected.
  * DGSN_ENOMEM if the copy cannot be allocated.
  */
@@ -256,7 +258,9 @@ int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream);
  * iterations (the FP32 noise floor) and then return DGSN_ENOTCONV unless
  * resid < tol.  iters, resid, eps_s (host out, may be NULL): iterations done,
  * last residual, and the paper's mean pointwise criterion Eq. (Test:Eq3) on
- * cell averages.  Synchronizes stream.
+ * cell averages.  Synchronizes stream.  An iterate holding a NaN or an
+ * infinity returns DGSN_EINVAL (the FP64 maxima of the residual carry NaNs
+ * to the host).
  */
 int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
                         double *resid, double *eps_s, void *stream);
@@ -292,11 +296,12 @@ int dgsn_problem_get_tile(const dgsn_problem *p, int *b);
  *   DGSN_SCHED_DATAFLOW: one launch per sweep; the workgroups of an octant
  *     take blocks of tiles in hyperplane order from that octant's device
  *     ticket counter and wait on the done flags of the blocks of the previous
- *     hyperplane that hold their tiles' upwind neighbours.  Every wait is bounded by poll_limit polls (0: the library default,
- *     about a second); if one expires the launch still completes, its results
- *     are invalid, and the next dgsn_problem_check (also run inside
- *     dgsn_source_iterate, dgsn_adjoint_solve and the autotuner) returns
- *     DGSN_EHIP and clears the condition.  Two dataflow sweeps of one problem
+ *     hyperplane that hold their tiles' upwind neighbours.  Every wait is
+ *     bounded by poll_limit polls (0: the library default, about a second);
+ *     if one expires the launch still completes, its results are invalid,
+ *     and the next dgsn_problem_check (also run inside dgsn_source_iterate,
+ *     dgsn_adjoint_solve and the autotuner) returns DGSN_ETIMEOUT and clears
+ *     the condition.  Two dataflow sweeps of one problem
  *     must not run concurrently (they share the counters).
  * dgsn_problem_check: synchronizes stream and reports an expired dataflow
  *   wait since the last check.
@@ -328,13 +333,15 @@ int dgsn_problem_set_si_criterion(dgsn_problem *p, int criterion);
 
 /*
  * Gradient of a scalar response J(phi) through the converged source
- * iteration by the discrete adjoint (not in the paper).  Requires the
- * problem's last source_iterate to have run with store_psi = 1.
+ * iteration by the discrete adjoint (not in the paper).  Requires a problem
+ * created with store_psi = 1 whose last source iteration ran after its last
+ * setter call and sweep (DGSN_EINVAL otherwise: the stored angular flux
+ * would not belong to the current inputs).
  * dJ_dphi: device [G][nz][ny][nx][8].  grad_sigma_t, grad_q: device
  * [G][nz][ny][nx] out (may be NULL): dJ/dsigma_t at fixed sigma_s and dJ/dq,
  * without any direct partial derivative of J.  The adjoint iteration stops at
  * relative change < tol or max_iter (DGSN_ENOTCONV).  iters may be NULL.
- * Synchronizes stream.
+ * Synchronizes stream.  A NaN or infinite adjoint flux returns DGSN_EINVAL.
  */
 int dgsn_adjoint_solve(dgsn_problem *p, const void *dJ_dphi, void *grad_sigma_t, void *grad_q,
                        double tol, int max_iter, int *iters, void *stream);
@@ -398,6 +405,42 @@ int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float
 int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream);
 
 /*
+ * Particle-balance tally of forward sweeps, in FP64 (the weak form below
+ * Eq. (T9) tested with the constant function: for each cell and direction,
+ * outflow - inflow + sigma_t int psi - int Q = 0 for the exact cell
+ * solution; summed over cells with the quadrature weights the interior
+ * faces cancel).  With enable != 0 every later dgsn_sweep and the iterations
+ * of dgsn_source_iterate also store each direction's outflow through the
+ * domain boundary into the fronts and tally, over the whole sweep:
+ *   terms[0] boundary outflow  sum_d w_d sum_{outflow faces} |Omega.n| int_f psi_d
+ *   terms[1] boundary inflow   the same over the inflow faces with psi_inc
+ *   terms[2] absorption        sum_c sigma_t int_c phi
+ *   terms[3] source            sum_c int_c sum_d w_d S_d (the isotropic source;
+ *            the anisotropic moment sources of orders 1..3 integrate to zero
+ *            over a level-symmetric set and are not tallied)
+ *   terms[4] terms[0] - terms[1] + terms[2] - terms[3]  (0 up to rounding for
+ *            the GE solvers; the conservation error of a network solver)
+ * for the last dgsn_sweep or the iterate returned by the last
+ * dgsn_source_iterate.  Integrals are exact for the trilinear fluxes (face:
+ * area x mean of the four face nodes, cell: volume x mean of the eight
+ * nodes); sums are in FP64 over the problem-precision values.
+ * dgsn_problem_balance synchronizes stream after a dgsn_sweep and returns
+ * DGSN_EINVAL when no tallied sweep has run since the tally was enabled.
+ * Cost: the boundary outflow stores and a pass over the fronts per sweep.
+ */
+int dgsn_problem_set_balance(dgsn_problem *p, int enable);
+int dgsn_problem_balance(dgsn_problem *p, double terms[5], void *stream);
+
+/*
+ * Generation counter of a problem (host out): changes whenever a setter
+ * (materials, scattering, anisotropy, inflow, network, solver) or a sweep or
+ * source iteration changes the problem's inputs or its stored angular flux.
+ * A caller that keeps results of a source iteration (an autograd tape) can
+ * tell whether the problem still holds the state they came from.
+ */
+int dgsn_problem_generation(const dgsn_problem *p, unsigned long long *gen);
+
+/*
  * Problem statistics (host out): solves per sweep (cells*dirs*groups),
  * hyperplane count, and the algorithmic HBM bytes of one sweep
  * (s*(24*solves + 17*cells*groups), s = sizeof(real)).
@@ -431,10 +474,13 @@ int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
  *     order, and each unit waits on device flags of the units holding its
  *     tiles' upwind neighbours.  Waits are bounded as for a single problem;
  *     an expired wait is reported by the next dgsn_batch_latencies_us or
- *     dgsn_batch_autotune (DGSN_EHIP).
- * dgsn_batch_create: probs must stay alive while the batch exists; each
- *   problem's materials, inflow and ANN are read at run time.  Two runs of
- *   one batch must not overlap (they share the device tables).
+ *     dgsn_batch_autotune (DGSN_ETIMEOUT).
+ * dgsn_batch_create: probs must stay alive while the batch exists.  Each
+ *   problem's materials are read from its buffers at run time; its inflow,
+ *   solver and network are part of the captured graph, which dgsn_batch_run
+ *   captures again when any of them changed since (a member set to
+ *   DGSN_GE_DENSE, or to DGSN_ANN without a network, is refused).  Two runs
+ *   of one batch must not overlap (they share the device tables).
  * dgsn_batch_set_io: device src / phi of problem `index`, layouts as in
  *   dgsn_sweep; must be set for every problem before the first run.
  * dgsn_batch_set_tiles: per-problem tile edge (1 or 2; a problem set to 3

@@ -77,7 +77,7 @@ def _load():
         [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 7
     _pann = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6
     lib.orc_pann_sweep.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
-        [ctypes.c_int] * 2 + [_D] * 5 + _pann + [_D, ctypes.c_int]
+        [ctypes.c_int] * 2 + [_D] * 5 + _pann + [_D, _D, ctypes.c_int]
     lib.orc_pann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 6 + _pann + [_D, ctypes.c_double, ctypes.c_int, _I, _D, _D,
                                                  ctypes.c_int]
@@ -488,8 +488,10 @@ def pann_cell_batch(net, h, omega, sigma_t, S, psi_up):
     return out
 
 
-def pann_sweep(net, mesh, omega, weight, sigma_t, src, psi_inc=None, nthreads=0):
-    """Sweep with the paper-form network in place of assembly + GE."""
+def pann_sweep(net, mesh, omega, weight, sigma_t, src, psi_inc=None, nthreads=0,
+               store_psi=False):
+    """Sweep with the paper-form network in place of assembly + GE (and
+    the angular flux [D, G, ncell, 8] with store_psi)."""
     lib = _load()
     nx, ny, nz, lx, ly, lz = _mesh_args(mesh)
     ncell = nx * ny * nz
@@ -499,11 +501,12 @@ def pann_sweep(net, mesh, omega, weight, sigma_t, src, psi_inc=None, nthreads=0)
     ng = sigma_t.shape[0]
     inc = _f64(np.zeros(6) if psi_inc is None else psi_inc, (6,))
     phi = np.zeros((ng, ncell, 8))
+    psi = np.zeros((nd, ng, ncell, 8)) if store_psi else None
     rc = lib.orc_pann_sweep(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
                             _p(sigma_t), _p(_f64(src, (ng, ncell, 8))), _p(inc),
-                            *_pann_ptrs(_pann_args(net)), _p(phi), int(nthreads))
+                            *_pann_ptrs(_pann_args(net)), _p(phi), _p(psi), int(nthreads))
     _check(rc, "pann_sweep")
-    return phi
+    return (phi, psi) if store_psi else phi
 
 
 def pann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-4,

@@ -1468,13 +1468,13 @@ int orc_pann_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int 
                    const double *src, const double psi_inc[6], int nh, double alpha,
                    double beta_scale, const double *imin, const double *imax, const double *W1,
                    const double *b1, const double *W2, const double *b2, double *phi,
-                   int nthreads)
+                   double *psi_store, int nthreads)
 {
     const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
     orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
     if (nh < 1 || nh > 64) return ORC_EINVAL;
     return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
-                     NULL, &net, nthreads);
+                     psi_store, &net, nthreads);
 }
 
 int orc_pann_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng,

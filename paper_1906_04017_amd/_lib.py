@@ -84,6 +84,9 @@ SIGNATURES = {
                            ctypes.POINTER(_I)]),
     "dgsn_ann_infer_octant": (_I, [_VP, _I, _VP, _VP, _LL, _VP]),
     "dgsn_problem_stats": (_I, [_VP, ctypes.POINTER(_LL), _PI, _PD]),
+    "dgsn_problem_set_balance": (_I, [_VP, _I]),
+    "dgsn_problem_balance": (_I, [_VP, _PD, _VP]),
+    "dgsn_problem_generation": (_I, [_VP, ctypes.POINTER(ctypes.c_ulonglong)]),
     "dgsn_problem_set_timing": (_I, [_VP, _I]),
     "dgsn_problem_set_si_criterion": (_I, [_VP, _I]),
     "dgsn_problem_si_history": (_I, [_VP, _PD, _PD, _I, _PI]),
@@ -121,6 +124,11 @@ def load():
         raise RuntimeError(
             f"libdgsn.so not found at {LIB_PATH}: build it with "
             "`python -m paper_1906_04017_amd.build` (hipcc, gfx950)")
+    # torch first: it ships its own HIP runtime (same soname), and the library
+    # must bind to that one.  Loaded the other way round, the process would
+    # hold two HIP runtimes, and torch's device pointers and streams would not
+    # be valid in the library's.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -6,6 +6,7 @@ include/dgsn.h: per-cell fields [G][nz][ny][nx], nodal fields
 [G][nz][ny][nx][8] (node n = ix + 2 iy + 4 iz fastest).
 """
 import ctypes
+import warnings
 
 import numpy as np
 import torch
@@ -326,6 +327,27 @@ class Problem:
         times = {(names[k // 3], k % 3 + 1): float(ms[k]) for k in range(6) if np.isfinite(ms[k])}
         return t.value, names[s.value], times
 
+    def set_balance(self, enable=True):
+        """Tally the FP64 particle balance of later forward sweeps."""
+        _lib.check(_lib.load().dgsn_problem_set_balance(self._h, int(bool(enable))))
+
+    def balance(self):
+        """Balance terms of the last tallied sweep: dict with the boundary
+        outflow, boundary inflow, absorption, source and their balance
+        outflow - inflow + absorption - source."""
+        t = np.zeros(5)
+        _lib.check(_lib.load().dgsn_problem_balance(self._h, t.ctypes.data_as(_lib._PD),
+                                                    _stream(self.ctx.device)))
+        return dict(outflow=float(t[0]), inflow=float(t[1]), absorption=float(t[2]),
+                    source=float(t[3]), balance=float(t[4]))
+
+    def generation(self):
+        """Counter that changes with every change of the problem's inputs or
+        of its stored angular flux."""
+        g = ctypes.c_ulonglong(0)
+        _lib.check(_lib.load().dgsn_problem_generation(self._h, ctypes.byref(g)))
+        return g.value
+
     def set_timing(self, enable=True):
         _lib.check(_lib.load().dgsn_problem_set_timing(self._h, int(bool(enable))))
 
@@ -416,22 +438,38 @@ class TransportSolve(torch.autograd.Function):
 
     forward(problem, sigma_t [G,ncell], q [G,ncell], sigma_s [G,ncell], tol,
     max_iter) -> phi [G,ncell,8].  The problem must be created with
-    store_psi=True.
+    store_psi=True.  The backward pass uses the angular flux and materials the
+    problem holds, so it raises if the problem changed after this forward
+    (another forward, a sweep or a setter on the same problem); use one
+    problem per pending backward.  A forward or adjoint iteration that stops
+    before tol warns.
     """
 
     @staticmethod
     def forward(ctx, problem, sigma_t, q, sigma_s, tol, max_iter):
         problem.set_materials(sigma_t.detach(), sigma_s.detach(), q.detach())
         phi, info = problem.source_iterate(tol=tol, max_iter=max_iter, allow_notconv=True)
+        if not info["converged"]:
+            warnings.warn(f"TransportSolve forward stopped after {info['iters']} iterations at "
+                          f"residual {info['resid']:.3e} (tol {tol:g}); gradients are those of "
+                          "the last iterate", RuntimeWarning, stacklevel=2)
         ctx.problem = problem
+        ctx.generation = problem.generation()
         ctx.tol = tol
         ctx.max_iter = max_iter
         return phi
 
     @staticmethod
     def backward(ctx, grad_phi):
-        gst, gq, _ = ctx.problem.adjoint(grad_phi.contiguous(), tol=ctx.tol,
-                                         max_iter=ctx.max_iter, allow_notconv=True)
+        if ctx.problem.generation() != ctx.generation:
+            raise RuntimeError("TransportSolve.backward: the problem changed after this forward "
+                               "(another forward, sweep or setter); its stored angular flux no "
+                               "longer belongs to this graph")
+        gst, gq, info = ctx.problem.adjoint(grad_phi.contiguous(), tol=ctx.tol,
+                                            max_iter=ctx.max_iter, allow_notconv=True)
+        if not info["converged"]:
+            warnings.warn(f"TransportSolve adjoint stopped after {info['iters']} iterations "
+                          f"(tol {ctx.tol:g})", RuntimeWarning, stacklevel=2)
         return None, gst, gq, None, None, None
 
 

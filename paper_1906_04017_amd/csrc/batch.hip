@@ -221,6 +221,9 @@ struct dgsn_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool dirty = true;
+    // each problem's cfg_gen when the graph was captured: the graph holds its
+    // inflow, solver and network pointer by value
+    std::vector<unsigned long long> cfg_gen;
     double clock_khz = 0.0;
     ~dgsn_batch()
     {
@@ -443,6 +446,26 @@ int capture(dgsn_batch *B)
     B->graph = g;
     DGSN_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
     B->dirty = false;
+    B->cfg_gen.resize(B->probs.size());
+    for (size_t b = 0; b < B->probs.size(); ++b) B->cfg_gen[b] = B->probs[b]->cfg_gen;
+    return DGSN_OK;
+}
+
+// The member problems as a batch can run them now (their solver and network
+// may have changed since the batch was created), and whether the captured
+// graph is stale.
+int batch_validate(dgsn_batch *B)
+{
+    for (size_t b = 0; b < B->probs.size(); ++b) {
+        const dgsn_problem *p = B->probs[b];
+        if (!B->src[b]) return set_error(DGSN_EINVAL, "problem %zu has no src/phi (set_io)", b);
+        if (p->solver == DGSN_GE_DENSE)
+            return set_error(DGSN_EUNSUPPORTED, "batched execution uses the DGSN_GE or DGSN_ANN "
+                             "solvers (problem %zu)", b);
+        if (p->solver == DGSN_ANN && !p->ann)
+            return set_error(DGSN_EINVAL, "problem %zu uses the ANN solver without an ANN", b);
+        if (B->cfg_gen.size() != B->probs.size() || B->cfg_gen[b] != p->cfg_gen) B->dirty = true;
+    }
     return DGSN_OK;
 }
 
@@ -458,7 +481,8 @@ int batch_check(dgsn_batch *B)
     const unsigned zero = 0u;
     DGSN_HIP(hipMemcpy(static_cast<unsigned *>(B->d_fsync.ptr) + kFlowError, &zero, sizeof(zero),
                        hipMemcpyHostToDevice));
-    return set_error(DGSN_EHIP, "a dataflow wait of the batch expired; its results are invalid");
+    return set_error(DGSN_ETIMEOUT, "a dataflow wait of the batch expired; its results are "
+                     "invalid");
 }
 
 }  // namespace
@@ -563,8 +587,7 @@ int dgsn_batch_autotune(dgsn_batch *B, void *stream, double *best_ms)
 {
     clear_error();
     if (!B) return set_error(DGSN_EINVAL, "batch is NULL");
-    for (size_t b = 0; b < B->probs.size(); ++b)
-        if (!B->src[b]) return set_error(DGSN_EINVAL, "problem %zu has no src/phi (set_io)", b);
+    DGSN_TRY(batch_validate(B));
     DGSN_HIP(hipSetDevice(B->ctx->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int n = (int)B->probs.size();
@@ -621,8 +644,7 @@ int dgsn_batch_run(dgsn_batch *B, void *stream)
 {
     clear_error();
     if (!B) return set_error(DGSN_EINVAL, "batch is NULL");
-    for (size_t b = 0; b < B->probs.size(); ++b)
-        if (!B->src[b]) return set_error(DGSN_EINVAL, "problem %zu has no src/phi (set_io)", b);
+    DGSN_TRY(batch_validate(B));
     DGSN_HIP(hipSetDevice(B->ctx->device));
     if (B->dirty) DGSN_TRY(capture(B));
     DGSN_HIP(hipGraphLaunch(B->exec, reinterpret_cast<hipStream_t>(stream)));

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/dgsn.h"
+#include "kernels.hpp"
 
 struct dgsn_problem;
 
@@ -167,6 +168,33 @@ struct dgsn_problem {
     dgsn::DevBuf phi_alt;                     // [G][ncell][8] second iterate buffer
     dgsn::DevBuf d_check;                     // one flag word of the materials check
     int red_blocks = 0;
+
+    // Generation counters.  gen changes with every call that changes the
+    // problem's inputs (materials, scattering, inflow, solver, network) or
+    // its stored angular flux (sweeps and source iterations); cfg_gen with
+    // the inputs a captured batch graph holds by value (inflow, solver,
+    // network).  psi_valid: the stored angular flux is that of a completed
+    // source iteration on the current inputs (what the adjoint needs).
+    unsigned long long gen = 1, cfg_gen = 1;
+    int psi_valid = 0;
+    void touch(bool cfg)
+    {
+        ++gen;
+        if (cfg) ++cfg_gen;
+        psi_valid = 0;
+    }
+
+    // FP64 particle-balance tally of forward sweeps (off by default): the
+    // sweep keeps the domain-boundary outflow in the fronts and the octant
+    // reduction adds the absorption and source partials.  bal_state: 0 none,
+    // 1 the terms of the last dgsn_sweep are in red_result slot 0, 2 bal_host
+    // holds the raw partial sums of the last source iteration's returned
+    // iterate.  bal_inflow and bal_wsum: the boundary inflow and the weight
+    // sum of the tallied sweep, from the direction table as the sweep used it.
+    int balance = 0;
+    int bal_state = 0;
+    double bal_host[dgsn::kRedStride] = {};
+    double bal_inflow = 0.0, bal_wsum = 0.0;
 
     // optional per-launch kernel timing of the last sweep
     int timing = 0;

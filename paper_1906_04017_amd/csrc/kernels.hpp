@@ -9,7 +9,10 @@ struct dgsn_problem;
 
 namespace dgsn {
 
-__device__ __forceinline__ double fmax_d(double a, double b) { return a > b ? a : b; }
+// Maximum that carries a NaN in either operand (a NaN compares false, so a
+// plain a > b ? a : b would drop a NaN in a).  The residual reductions rely
+// on it: a NaN flux must reach the host as a NaN residual.
+__device__ __forceinline__ double fmax_d(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // One hyperplane step of a sweep (all octants, directions, groups).
 template <typename Real>
@@ -44,6 +47,9 @@ struct PlaneArgs {
     // as sum_k Y_k(Omega_d) msrc_k and leave the sweep as the per-octant
     // moments sum_{d in octant} w_d Y_k(Omega_d) psi_d
     uint32_t nmom;
+    // 1: also store the outflow faces on the domain boundary into the fronts
+    // (no downstream cell reads them; the balance tally's leakage does)
+    uint32_t keep_out;
     const Real *ylm;           // [8][Do][kYlmStride]
     const Real *msrc;          // [G][ncell][nmom-1][8] sigma_{s,n(k)} phi_k
     Real *mom_oct;             // [8][G][ncell][8][nmom-1] (moment fastest)
@@ -81,6 +87,16 @@ constexpr unsigned kFlowSpinDefault = 1u << 20;
 // its own.
 constexpr unsigned kFlowMaxGroupsPerOctant = 1u << 20;
 
+// FP64 partials of the octant reduction, per block and in the result slot
+// of an iteration: the residual terms and the particle-balance terms.
+constexpr int kRedMaxD = 0;    // max |phi_new - phi_old|
+constexpr int kRedMaxF = 1;    // max |phi_new|
+constexpr int kRedEps = 2;     // sum of the eps_S terms (cell averages)
+constexpr int kRedAbs = 3;     // sum_{g,c} sigma_t * sum_n phi_n
+constexpr int kRedSrc = 4;     // sum_{g,c} sum_n S_n
+constexpr int kRedLeak = 5;    // sum over boundary outflow slots of w kappa_a sum_e psi_e
+constexpr int kRedStride = 8;  // doubles per block partial and per result slot
+
 template <typename Real>
 struct ReduceArgs {
     const Real *phi_oct;       // [8][nv][8]
@@ -88,8 +104,12 @@ struct ReduceArgs {
     const Real *phi_prev;      // [nv][8] previous iterate in a separate buffer (or null)
     long long nv;              // G * ncell
     int resid;                 // compute residual partials
-    double *partials;          // [blocks][3]
-    double *result;            // [3]: max|dphi|, max|phi|, sum eps_s terms
+    int balance;               // compute the absorption and source partials of the tally
+    const Real *sigma_t;       // [nv] (balance)
+    const Real *src_sweep;     // [nv][8] source of the sweep just reduced (balance; read
+                               // before src_next, which may be the same buffer, is written)
+    double *partials;          // [blocks][kRedStride]
+    double *result;            // [kRedStride]
     Real *src_next;            // next source (or null)
     const Real *q_cell;        // [nv] per-cell source (or null)
     const Real *q_nodal;       // [nv][8] nodal source (or null)
@@ -133,6 +153,12 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
 int launch_flow_reset(const FlowArgs &F, hipStream_t s);   // before every launch_flow
 template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s);
+// Boundary leakage partials of the balance tally: for every face slot of the
+// three fronts (which hold the domain-boundary outflow after a sweep run with
+// A.keep_out), w_d kappa_a(d) sum_e psi_e, summed per block into
+// partials[block][kRedLeak]; blocks must equal the octant reduction's.
+template <typename Real>
+int launch_leakage(const PlaneArgs<Real> &A, double *partials, int blocks, hipStream_t s);
 template <typename Real>
 int launch_build_source(long long nv, const Real *q, const Real *ss, const Real *phi, Real *src,
                         hipStream_t s);

@@ -330,6 +330,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
 {
     PlaneArgs<Real> A = plane_args<Real>(p, src, adjoint);
     A.grad_oct = grad_oct;
+    A.keep_out = (p->balance && !adjoint) ? 1u : 0u;
     if (moments && p->pl_order > 0) {
         // anisotropic scattering inside source iteration
         A.nmom = (uint32_t)((p->pl_order + 1) * (p->pl_order + 1));
@@ -414,6 +415,38 @@ ReduceArgs<Real> reduce_args(dgsn_problem *p, void *phi)
     return R;
 }
 
+// The balance tally of a forward sweep with source src: the boundary
+// leakage partials (from the fronts the sweep just left) and the absorption
+// and source partials of the reduction R, plus the host-side inflow and
+// weight sum of the sweep's direction table.  Enqueued between the sweep and
+// launch_reduce(R).
+template <typename Real>
+int balance_prepare(dgsn_problem *p, const void *src, ReduceArgs<Real> &R, hipStream_t s)
+{
+    PlaneArgs<Real> A = plane_args<Real>(p, src, false);
+    DGSN_TRY(launch_leakage<Real>(A, R.partials, p->red_blocks, s));
+    R.balance = 1;
+    R.sigma_t = static_cast<const Real *>(p->sigma_t.ptr);
+    R.src_sweep = static_cast<const Real *>(src);
+    // inflow through the boundary faces entering each direction: w kappa_a V
+    // psi_inc per boundary cell face, with the values as the sweep used them
+    // (rounded to the problem precision)
+    double inflow = 0.0, wsum = 0.0;
+    const double cells_on_face[3] = {(double)p->n[1] * p->n[2], (double)p->n[0] * p->n[2],
+                                     (double)p->n[0] * p->n[1]};
+    for (int o = 0; o < 8; ++o)
+        for (int d = 0; d < p->Do; ++d) {
+            const double *e = &p->dir_host[(size_t)(o * p->Do + d) * kDirStride];
+            const double w = (double)(Real)e[kDirW];
+            wsum += w;
+            for (int a = 0; a < 3; ++a)
+                inflow += w * (double)(Real)e[kDirK + a] * (double)A.inc[o][a] * cells_on_face[a];
+        }
+    p->bal_inflow = inflow * p->G * (p->h[0] * p->h[1] * p->h[2]);
+    p->bal_wsum = wsum;
+    return DGSN_OK;
+}
+
 // Reads the dataflow error word (stream-ordered) and clears it; fails if a
 // wait of a dataflow launch gave up.
 int check_flow(dgsn_problem *p, hipStream_t s)
@@ -426,24 +459,37 @@ int check_flow(dgsn_problem *p, hipStream_t s)
     if (err == 0u) return DGSN_OK;
     DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
     DGSN_HIP(hipStreamSynchronize(s));
-    return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its results are "
-                     "invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
+    return set_error(DGSN_ETIMEOUT, "a dataflow sweep wait expired (poll limit %u); its results "
+                     "are invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
 }
 
-int read_result(dgsn_problem *p, hipStream_t s, double out[3])
+// Residual r and eps_S from an iteration's FP64 result slot; DGSN_EINVAL if
+// any of them is not finite (a NaN or infinite flux), which the NaN-carrying
+// maxima of the reduction bring here.
+int residual_of(const double *res, long long nv, double &r, double &es)
 {
-    DGSN_HIP(hipMemcpyAsync(out, p->red_result.ptr, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (p->schedule == DGSN_SCHED_DATAFLOW) return check_flow(p, s);
-    DGSN_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(res[kRedMaxD]) || !std::isfinite(res[kRedMaxF]) ||
+        !std::isfinite(res[kRedEps]) || !(res[kRedMaxF] >= 0.0))
+        return set_error(DGSN_EINVAL, "the iteration produced a non-finite flux or residual");
+    r = res[kRedMaxF] > 0.0 ? res[kRedMaxD] / res[kRedMaxF] : 0.0;
+    es = res[kRedEps] / (double)nv;
     return DGSN_OK;
 }
 
 template <typename Real>
 int sweep_impl(dgsn_problem *p, const void *src, void *phi, hipStream_t s)
 {
+    p->touch(false);
+    p->bal_state = 0;
     DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s));
     ReduceArgs<Real> R = reduce_args<Real>(p, phi);
-    return launch_reduce<Real>(R, p->red_blocks, s);
+    // a single sweep's tally has a result slot of its own (the two others
+    // belong to the iterations in flight of source and adjoint iterations)
+    R.result = static_cast<double *>(p->red_result.ptr) + 2 * kRedStride;
+    if (p->balance) DGSN_TRY(balance_prepare<Real>(p, src, R, s));
+    DGSN_TRY(launch_reduce<Real>(R, p->red_blocks, s));
+    if (p->balance) p->bal_state = 1;
+    return DGSN_OK;
 }
 
 // Anisotropic moments after a sweep's octant reduction: the flux moments,
@@ -511,7 +557,7 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     }
     double *dres = static_cast<double *>(p->red_result.ptr);
     double *hres = static_cast<double *>(p->h_result.ptr);
-    unsigned *herr = reinterpret_cast<unsigned *>(hres + 8);
+    unsigned *herr = reinterpret_cast<unsigned *>(hres + 2 * kRedStride);
     const bool flow = p->schedule == DGSN_SCHED_DATAFLOW;
     auto enqueue = [&](int k) -> int {
         const int slot = k & 1;
@@ -522,7 +568,8 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             R.phi_prev = buf[slot];
             R.phi = buf[slot ^ 1];
         }
-        R.result = dres + 4 * slot;
+        R.result = dres + kRedStride * slot;
+        if (p->balance) DGSN_TRY(balance_prepare<Real>(p, src, R, s));
         if (!gg) {
             R.src_next = src;
             R.q_cell = static_cast<const Real *>(p->q.ptr);
@@ -534,8 +581,8 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G,
                                                   static_cast<const Real *>(p->q.ptr), nullptr,
                                                   gg, R.phi, src, false, s));
-        DGSN_HIP(hipMemcpyAsync(hres + 4 * slot, dres + 4 * slot, 3 * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
+        DGSN_HIP(hipMemcpyAsync(hres + kRedStride * slot, dres + kRedStride * slot,
+                                kRedStride * sizeof(double), hipMemcpyDeviceToHost, s));
         if (flow)
             DGSN_HIP(hipMemcpyAsync(herr + slot,
                                     static_cast<unsigned *>(p->d_flow_sync.ptr) + kFlowError,
@@ -543,6 +590,8 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         DGSN_HIP(hipEventRecord(p->ev_result[slot], s));
         return DGSN_OK;
     };
+    p->touch(false);
+    p->bal_state = 0;
     double r = INFINITY, es = INFINITY, best = INFINITY, crit = INFINITY;
     int it = 0, stall = 0;
     const bool fp32 = p->precision == DGSN_FP32;
@@ -558,19 +607,18 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             DGSN_HIP(hipStreamSynchronize(s));
             DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
             DGSN_HIP(hipStreamSynchronize(s));
-            return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its "
+            return set_error(DGSN_ETIMEOUT, "a dataflow sweep wait expired (poll limit %u); its "
                              "results are invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
         }
-        const double *res = hres + 4 * (k & 1);
+        const double *res = hres + kRedStride * (k & 1);
         it = k + 1;
-        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
-        es = res[2] / (double)nv;
+        if (residual_of(res, nv, r, es) != DGSN_OK) {
+            DGSN_HIP(hipStreamSynchronize(s));
+            return set_error(DGSN_EINVAL, "source iteration %d produced a non-finite flux or "
+                             "residual", it);
+        }
         p->si_resid.push_back(r);
         p->si_eps.push_back(es);
-        if (!std::isfinite(r)) {
-            DGSN_HIP(hipStreamSynchronize(s));
-            return set_error(DGSN_EINVAL, "source iteration produced a non-finite residual");
-        }
         crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
         bool stop = it >= max_iter;
         if (!fixed) {
@@ -585,11 +633,17 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             if (overlap && (it & 1))
                 DGSN_HIP(hipMemcpyAsync(phi, buf[1], (size_t)nv * 8 * sizeof(Real),
                                         hipMemcpyDeviceToDevice, s));
+            if (p->balance) {
+                std::memcpy(p->bal_host, res, sizeof(p->bal_host));
+                p->bal_state = 2;
+            }
             break;
         }
         if (!ahead) DGSN_TRY(enqueue(k + 1));
     }
     DGSN_HIP(hipStreamSynchronize(s));
+    // the stored angular flux (store_psi) is that of the returned iterate
+    p->psi_valid = p->store_psi ? 1 : 0;
     if (iters) *iters = it;
     if (resid) *resid = r;
     if (eps_s) *eps_s = es;
@@ -640,7 +694,7 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
     const bool overlap = !pl;
     double *dres = static_cast<double *>(p->red_result.ptr);
     double *hres = static_cast<double *>(p->h_result.ptr);
-    unsigned *herr = reinterpret_cast<unsigned *>(hres + 8);
+    unsigned *herr = reinterpret_cast<unsigned *>(hres + 2 * kRedStride);
     const bool flow = p->schedule == DGSN_SCHED_DATAFLOW;
     auto enqueue = [&](int k) -> int {
         const int slot = k & 1;
@@ -648,7 +702,7 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
         ReduceArgs<Real> R = reduce_args<Real>(p, phid[slot ^ 1]);
         R.resid = 1;
         R.phi_prev = phid[slot];
-        R.result = dres + 4 * slot;
+        R.result = dres + kRedStride * slot;
         if (!gg) {
             R.src_next = asrc[slot ^ 1];
             R.q_nodal = load;
@@ -659,8 +713,8 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
         if (gg)
             DGSN_TRY(launch_build_source_gg<Real>(p->ncell, p->G, nullptr, load, gg,
                                                   phid[slot ^ 1], asrc[slot ^ 1], true, s));
-        DGSN_HIP(hipMemcpyAsync(hres + 4 * slot, dres + 4 * slot, 3 * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
+        DGSN_HIP(hipMemcpyAsync(hres + kRedStride * slot, dres + kRedStride * slot,
+                                kRedStride * sizeof(double), hipMemcpyDeviceToHost, s));
         if (flow)
             DGSN_HIP(hipMemcpyAsync(herr + slot,
                                     static_cast<unsigned *>(p->d_flow_sync.ptr) + kFlowError,
@@ -680,15 +734,16 @@ int adjoint_impl(dgsn_problem *p, const void *gphi, void *gst, void *gq, double 
             DGSN_HIP(hipStreamSynchronize(s));
             DGSN_HIP(hipMemsetAsync(p->d_flow_sync.ptr, 0, p->d_flow_sync.bytes, s));
             DGSN_HIP(hipStreamSynchronize(s));
-            return set_error(DGSN_EHIP, "a dataflow sweep wait expired (poll limit %u); its "
+            return set_error(DGSN_ETIMEOUT, "a dataflow sweep wait expired (poll limit %u); its "
                              "results are invalid", p->flow_spin ? p->flow_spin : kFlowSpinDefault);
         }
-        const double *res = hres + 4 * (k & 1);
+        const double *res = hres + kRedStride * (k & 1);
         it = k + 1;
-        r = res[1] > 0.0 ? res[0] / res[1] : 0.0;
-        if (!std::isfinite(r)) {
+        double es_unused = 0.0;
+        if (residual_of(res, nv, r, es_unused) != DGSN_OK) {
             DGSN_HIP(hipStreamSynchronize(s));
-            return set_error(DGSN_EINVAL, "adjoint iteration produced a non-finite residual");
+            return set_error(DGSN_EINVAL, "adjoint iteration %d produced a non-finite flux or "
+                             "residual", it);
         }
         bool stop = it >= max_iter || r < tol;
         if (fp32 && !stop) {
@@ -1032,9 +1087,9 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
         return fail(rc);
     if (p->store_psi && (rc = p->psi.alloc((size_t)p->D * nv * 8 * rs))) return fail(rc);
     p->red_blocks = reduce_blocks_for(nv);
-    if ((rc = p->red_partials.alloc((size_t)p->red_blocks * 3 * sizeof(double))) ||
-        (rc = p->red_result.alloc(8 * sizeof(double))) ||
-        (rc = p->h_result.alloc(8 * sizeof(double) + 2 * sizeof(unsigned))))
+    if ((rc = p->red_partials.alloc((size_t)p->red_blocks * kRedStride * sizeof(double))) ||
+        (rc = p->red_result.alloc(3 * kRedStride * sizeof(double))) ||
+        (rc = p->h_result.alloc(2 * kRedStride * sizeof(double) + 2 * sizeof(unsigned))))
         return fail(rc);
     if (hipEventCreateWithFlags(&p->ev_result[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_result[1], hipEventDisableTiming) != hipSuccess)
@@ -1064,6 +1119,7 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
     if (!p || !sigma_t) return set_error(DGSN_EINVAL, "problem and sigma_t must be set");
     const size_t bytes = (size_t)p->G * p->ncell * p->real_size;
     hipStream_t s = as_stream(stream);
+    p->touch(false);
     DGSN_HIP(hipMemcpyAsync(p->sigma_t.ptr, sigma_t, bytes, hipMemcpyDeviceToDevice, s));
     if (sigma_s) DGSN_HIP(hipMemcpyAsync(p->sigma_s.ptr, sigma_s, bytes, hipMemcpyDeviceToDevice, s));
     else DGSN_HIP(hipMemsetAsync(p->sigma_s.ptr, 0, bytes, s));
@@ -1112,9 +1168,18 @@ int dgsn_problem_set_scattering(dgsn_problem *p, const void *sigma_gg, void *str
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     if (!sigma_gg) {
+        // the order-0 matrix of group-to-group anisotropic scattering stays
+        // with its higher orders (dropping it alone would mix the in-group
+        // order 0 with group-to-group orders 1..L)
+        if (p->pl_order > 0 && p->pl_gg)
+            return set_error(DGSN_EUNSUPPORTED,
+                             "group-to-group anisotropic scattering is set; remove its orders "
+                             "first (dgsn_problem_set_anisotropy with order 0)");
+        p->touch(false);
         p->sigma_gg.release();
         return DGSN_OK;
     }
+    p->touch(false);
     if (p->pl_order > 0)
         return set_error(DGSN_EUNSUPPORTED,
                          "anisotropic scattering is set; dgsn_problem_set_anisotropy_gg sets the "
@@ -1199,6 +1264,7 @@ int dgsn_problem_set_anisotropy(dgsn_problem *p, int order, const void *sigma_sn
     if (order < 0 || order > kMaxPlOrder)
         return set_error(DGSN_EINVAL, "scattering order %d is outside 0..%d", order, kMaxPlOrder);
     DGSN_HIP(hipSetDevice(p->ctx->device));
+    p->touch(false);
     if (order == 0) {
         drop_anisotropy(p);
         return DGSN_OK;
@@ -1222,6 +1288,7 @@ int dgsn_problem_set_anisotropy_gg(dgsn_problem *p, int order, const void *sigma
         return set_error(DGSN_EINVAL, "scattering order %d is outside 1..%d", order, kMaxPlOrder);
     if (!sigma_sn_gg) return set_error(DGSN_EINVAL, "sigma_sn_gg is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
+    p->touch(false);
     const int rc = set_anisotropy_gg_impl(p, order, sigma_sn_gg, as_stream(stream));
     if (rc != DGSN_OK) {
         // the order-0 matrix may be released or half copied: drop it too
@@ -1270,6 +1337,7 @@ int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6])
         if (!std::isfinite(psi_inc[f]))
             return set_error(DGSN_EINVAL, "psi_inc[%d] is not finite", f);
     std::memcpy(p->psi_inc, psi_inc, sizeof(p->psi_inc));
+    p->touch(true);
     return DGSN_OK;
 }
 
@@ -1279,6 +1347,8 @@ int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     if (ann && p->precision != DGSN_FP32)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    // a folded paper-form image may be replaced below: batches re-capture
+    p->touch(true);
     if (ann && ann->version == 2) {
         // fold the scaling, the cell sizes and the octant relabelling in once
         std::vector<float> img;
@@ -1311,6 +1381,7 @@ int dgsn_problem_set_solver(dgsn_problem *p, int solver)
         return set_error(DGSN_EINVAL, "solver must be DGSN_GE, DGSN_GE_DENSE or DGSN_ANN");
     if (solver == DGSN_ANN && p->precision != DGSN_FP32)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
+    if (solver != p->solver) p->touch(true);
     p->solver = solver;
     return DGSN_OK;
 }
@@ -1383,6 +1454,49 @@ int dgsn_problem_stats(const dgsn_problem *p, long long *solves, int *n_planes, 
     return DGSN_OK;
 }
 
+int dgsn_problem_generation(const dgsn_problem *p, unsigned long long *gen)
+{
+    clear_error();
+    if (!p || !gen) return set_error(DGSN_EINVAL, "problem and gen must be set");
+    *gen = p->gen;
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_balance(dgsn_problem *p, int enable)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    p->balance = enable ? 1 : 0;
+    p->bal_state = 0;
+    return DGSN_OK;
+}
+
+int dgsn_problem_balance(dgsn_problem *p, double terms[5], void *stream)
+{
+    clear_error();
+    if (!p || !terms) return set_error(DGSN_EINVAL, "problem and terms must be set");
+    double raw[kRedStride];
+    if (p->bal_state == 1) {
+        DGSN_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t s = as_stream(stream);
+        DGSN_HIP(hipMemcpyAsync(raw, static_cast<double *>(p->red_result.ptr) + 2 * kRedStride,
+                                sizeof(raw), hipMemcpyDeviceToHost, s));
+        DGSN_HIP(hipStreamSynchronize(s));
+    } else if (p->bal_state == 2) {
+        std::memcpy(raw, p->bal_host, sizeof(raw));
+    } else {
+        return set_error(DGSN_EINVAL, "no tallied sweep (enable the tally with "
+                         "dgsn_problem_set_balance before dgsn_sweep or dgsn_source_iterate)");
+    }
+    const double vol = p->h[0] * p->h[1] * p->h[2];
+    terms[0] = 0.25 * vol * raw[kRedLeak];                 // boundary outflow
+    terms[1] = p->bal_inflow;                              // boundary inflow
+    terms[2] = 0.125 * vol * raw[kRedAbs];                 // absorption sigma_t int phi
+    terms[3] = 0.125 * vol * p->bal_wsum * raw[kRedSrc];   // source int sum_d w_d S
+    terms[4] = terms[0] - terms[1] + terms[2] - terms[3];
+    return DGSN_OK;
+}
+
 int dgsn_sweep(dgsn_problem *p, const void *src, void *phi, void *stream)
 {
     clear_error();
@@ -1437,6 +1551,9 @@ int dgsn_adjoint_solve(dgsn_problem *p, const void *gphi, void *gst, void *gq, d
         return set_error(DGSN_EUNSUPPORTED,
                          "the anisotropic adjoint runs with the mass-inverse GE solver");
     if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
+    if (!p->psi_valid)
+        return set_error(DGSN_EINVAL, "no stored angular flux of a source iteration on the "
+                         "current inputs (run dgsn_source_iterate after the last setter or sweep)");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     p->ev_used = 0;
     return p->precision == DGSN_FP64

@@ -54,13 +54,14 @@ __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
                                                 l.ok, L, &al);
 }
 
-// phi = sum_o phi_oct[o]; optionally the FP64 SI residual partials and the
-// next source S = qn + qc + sigma_s/(4 pi) phi.
+// phi = sum_o phi_oct[o]; optionally the FP64 SI residual partials, the
+// absorption and source partials of the balance tally, and the next source
+// S = qn + qc + sigma_s/(4 pi) phi.
 template <typename Real>
 __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
 {
-    __shared__ double sh[3][256];
-    double dmax = 0.0, fmax = 0.0, esum = 0.0;
+    __shared__ double sh[5][256];
+    double dmax = 0.0, fmax = 0.0, esum = 0.0, babs = 0.0, bsrc = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < R.nv; e += stride) {
         Real nw[8];
@@ -90,6 +91,17 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
             ao *= 0.125;
             esum += (an != 0.0) ? fabs(an - ao) / fabs(an) : (ao != 0.0 ? 1.0 : 0.0);
         }
+        if (R.balance) {
+            // the sweep's source is read before the next one overwrites it
+            double fs = 0.0, ss = 0.0;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) {
+                fs += (double)nw[n];
+                ss += (double)R.src_sweep[e * 8 + n];
+            }
+            babs = fma((double)R.sigma_t[e], fs, babs);
+            bsrc += ss;
+        }
 #pragma unroll
         for (int n = 0; n < 8; ++n) __builtin_nontemporal_store(nw[n], ph + n);
         if (R.src_next) {
@@ -102,55 +114,114 @@ __global__ __launch_bounds__(256) void reduce_octants(ReduceArgs<Real> R)
             }
         }
     }
-    if (!R.resid) return;
+    if (!R.resid && !R.balance) return;
     const int tid = threadIdx.x;
     sh[0][tid] = dmax;
     sh[1][tid] = fmax;
     sh[2][tid] = esum;
+    sh[3][tid] = babs;
+    sh[4][tid] = bsrc;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if (tid < s) {
             sh[0][tid] = fmax_d(sh[0][tid], sh[0][tid + s]);
             sh[1][tid] = fmax_d(sh[1][tid], sh[1][tid + s]);
             sh[2][tid] += sh[2][tid + s];
+            sh[3][tid] += sh[3][tid + s];
+            sh[4][tid] += sh[4][tid + s];
         }
         __syncthreads();
     }
     if (tid == 0) {
-        R.partials[blockIdx.x * 3 + 0] = sh[0][0];
-        R.partials[blockIdx.x * 3 + 1] = sh[1][0];
-        R.partials[blockIdx.x * 3 + 2] = sh[2][0];
+        double *pb = R.partials + (size_t)blockIdx.x * kRedStride;
+        pb[kRedMaxD] = sh[0][0];
+        pb[kRedMaxF] = sh[1][0];
+        pb[kRedEps] = sh[2][0];
+        pb[kRedAbs] = sh[3][0];
+        pb[kRedSrc] = sh[4][0];
     }
 }
 
-__global__ __launch_bounds__(256) void finalize_partials(const double *partials, int nblocks,
-                                                         double *result)
+// Boundary leakage of the balance tally.  After a sweep run with keep_out,
+// the slot of every front row holds the outflow face of the row's last cell,
+// on the domain boundary.  Each thread takes one face slot (octant,
+// row, direction-group) of one of the three fronts and adds
+// w_d kappa_a(d) (psi_0 + psi_1 + psi_2 + psi_3) in FP64; the outflow
+// integral over the face is V kappa_a times the mean of the four values.
+template <typename Real>
+__global__ __launch_bounds__(256) void leakage(PlaneArgs<Real> A, double *partials)
 {
-    __shared__ double sh[3][256];
-    const int tid = threadIdx.x;
-    double a = 0.0, b = 0.0, s = 0.0;
-    for (int i = tid; i < nblocks; i += blockDim.x) {
-        a = fmax_d(a, partials[i * 3 + 0]);
-        b = fmax_d(b, partials[i * 3 + 1]);
-        s += partials[i * 3 + 2];
+    __shared__ double sh[256];
+    const uint32_t DG = A.DG;
+    const long long nx_slots = 8LL * A.nz * A.ny * DG;
+    const long long ny_slots = 8LL * A.nz * A.nx * DG;
+    const long long nz_slots = 8LL * A.ny * A.nx * DG;
+    const long long total = nx_slots + ny_slots + nz_slots;
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        // each front holds fewer than 2^31 elements, so a slot index fits 32 bits
+        int axis;
+        uint32_t r;
+        const Real *f;
+        uint32_t per_octant;
+        if (t < nx_slots) {
+            axis = 0; r = (uint32_t)t; f = A.fx; per_octant = A.nz * A.ny * DG;
+        } else if (t < nx_slots + ny_slots) {
+            axis = 1; r = (uint32_t)(t - nx_slots); f = A.fy; per_octant = A.nz * A.nx * DG;
+        } else {
+            axis = 2; r = (uint32_t)(t - nx_slots - ny_slots); f = A.fz;
+            per_octant = A.ny * A.nx * DG;
+        }
+        // r = (octant * rows + row) * DG + dg, dg = d + Do * g
+        const uint32_t o = r / per_octant;
+        const uint32_t dg = r % DG;
+        const uint32_t d = dg % A.Do;
+        const Real *dp = A.dir + (o * A.Do + d) * kDirStride;
+        const Real *v = f + (size_t)r * 4;
+        const double s = (double)v[0] + (double)v[1] + (double)v[2] + (double)v[3];
+        acc = fma((double)dp[kDirW] * (double)dp[kDirK + axis], s, acc);
     }
-    sh[0][tid] = a;
-    sh[1][tid] = b;
-    sh[2][tid] = s;
+    const int tid = threadIdx.x;
+    sh[tid] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) partials[(size_t)blockIdx.x * kRedStride + kRedLeak] = sh[0];
+}
+
+// result[k] over the block partials: maxima for the residual terms, sums for
+// the others (summed in block order, so the result is reproducible);
+// nterms = kRedLeak + 1 with the balance tally, kRedEps + 1 without.
+__global__ __launch_bounds__(256) void finalize_partials(const double *partials, int nblocks,
+                                                         int nterms, double *result)
+{
+    __shared__ double sh[kRedLeak + 1][256];
+    const int tid = threadIdx.x;
+    double v[kRedLeak + 1];
+#pragma unroll
+    for (int k = 0; k <= kRedLeak; ++k) v[k] = 0.0;
+    for (int i = tid; i < nblocks; i += blockDim.x) {
+        const double *pb = partials + (size_t)i * kRedStride;
+        v[kRedMaxD] = fmax_d(v[kRedMaxD], pb[kRedMaxD]);
+        v[kRedMaxF] = fmax_d(v[kRedMaxF], pb[kRedMaxF]);
+        for (int k = kRedEps; k < nterms; ++k) v[k] += pb[k];
+    }
+#pragma unroll
+    for (int k = 0; k <= kRedLeak; ++k) sh[k][tid] = v[k];
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
         if (tid < st) {
-            sh[0][tid] = fmax_d(sh[0][tid], sh[0][tid + st]);
-            sh[1][tid] = fmax_d(sh[1][tid], sh[1][tid + st]);
-            sh[2][tid] += sh[2][tid + st];
+            sh[kRedMaxD][tid] = fmax_d(sh[kRedMaxD][tid], sh[kRedMaxD][tid + st]);
+            sh[kRedMaxF][tid] = fmax_d(sh[kRedMaxF][tid], sh[kRedMaxF][tid + st]);
+#pragma unroll
+            for (int k = kRedEps; k <= kRedLeak; ++k) sh[k][tid] += sh[k][tid + st];
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        result[0] = sh[0][0];
-        result[1] = sh[1][0];
-        result[2] = sh[2][0];
-    }
+    if (tid < nterms) result[tid] = sh[tid][0];
 }
 
 // S = q + sigma_s/(4 pi) phi  (initial source of an SI run)
@@ -497,13 +568,28 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
 template <typename Real>
 int launch_reduce(const ReduceArgs<Real> &R, int blocks, hipStream_t s)
 {
+    if ((R.resid || R.balance) && (blocks < 1 || blocks > 2048))
+        return set_error(DGSN_EINVAL, "reduction over %d blocks (1..2048)", blocks);
     hipLaunchKernelGGL(reduce_octants<Real>, dim3(blocks), dim3(256), 0, s, R);
     DGSN_HIP(hipGetLastError());
-    if (R.resid) {
+    if (R.resid || R.balance) {
+        // with the balance tally the leakage partials of this reduction's
+        // blocks have been written by launch_leakage (enqueued before)
+        const int nterms = R.balance ? kRedLeak + 1 : kRedEps + 1;
         hipLaunchKernelGGL(finalize_partials, dim3(1), dim3(256), 0, s, R.partials, blocks,
-                           R.result);
+                           nterms, R.result);
         DGSN_HIP(hipGetLastError());
     }
+    return DGSN_OK;
+}
+
+template <typename Real>
+int launch_leakage(const PlaneArgs<Real> &A, double *partials, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || blocks > 2048)
+        return set_error(DGSN_EINVAL, "leakage over %d blocks (1..2048)", blocks);
+    hipLaunchKernelGGL(leakage<Real>, dim3(blocks), dim3(256), 0, s, A, partials);
+    DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }
 
@@ -605,6 +691,7 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
 #define DGSN_INST(Real)                                                                        \
     template int launch_tile<Real>(const PlaneArgs<Real> &, int, int, bool, bool, hipStream_t);         \
     template int launch_reduce<Real>(const ReduceArgs<Real> &, int, hipStream_t);              \
+    template int launch_leakage<Real>(const PlaneArgs<Real> &, double *, int, hipStream_t);    \
     template int launch_build_source<Real>(long long, const Real *, const Real *, const Real *, \
                                            Real *, hipStream_t);                               \
     template int launch_build_source_gg<Real>(long long, int, const Real *, const Real *,       \

@@ -534,11 +534,14 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
                     zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
                     zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
-                    if (il == B - 1 && ic + 1 < A.nx)
+                    // a tile's last cell hands its outflow downstream; a cell on
+                    // the domain boundary has no downstream cell and stores it
+                    // only for the balance tally (keep_out)
+                    if (ic + 1 < A.nx ? il == B - 1 : A.keep_out != 0u)
                         front_store<Real, kCoh>(A.fx, rx, ex, psi[1], psi[3], psi[5], psi[7]);
-                    if (jl == B - 1 && jc + 1 < A.ny)
+                    if (jc + 1 < A.ny ? jl == B - 1 : A.keep_out != 0u)
                         front_store<Real, kCoh>(A.fy, ry, ey, psi[2], psi[3], psi[6], psi[7]);
-                    if (kl == B - 1 && kc + 1 < A.nz)
+                    if (kc + 1 < A.nz ? kl == B - 1 : A.keep_out != 0u)
                         front_store<Real, kCoh>(A.fz, rz, ez, psi[4], psi[5], psi[6], psi[7]);
                     if (kStorePsi || (kAdjoint && A.grad_oct)) {
                         Real *pp = A.psi + ((size_t)slot * A.ncell + c) * 8;

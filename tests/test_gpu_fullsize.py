@@ -162,7 +162,7 @@ def test_trained_network_sweep_at_full_size(api, ctx):
     # only differences are the BF16 rounding of the normalised features and
     # of the hidden layer (about 2^-9 relative per cell) carried downstream;
     # a cell passes on e^-0.78 of its inflow, so they stay near 2^-8
-    from paper_1906_04017_amd import ann_format
+    from oracle import ann_train
     import os
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                         "paper_1906_04017_amd", "data", "ann_s8_relu64.dgsnann")
@@ -178,7 +178,7 @@ def test_trained_network_sweep_at_full_size(api, ctx):
     S = np.repeat(p["q"][2:3, :, None], 8, axis=-1)
     phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).double().cpu().numpy()
     om_o, w_o = oracle.lq_n(8)
-    ref = oracle.ann_sweep(ann_format.read(path), (*p["n"], *p["length"]), om_o, w_o,
+    ref = oracle.ann_sweep(ann_train.read_artifact(path), (*p["n"], *p["length"]), om_o, w_o,
                            p["sigma_t"][2:3], S, p["psi_inc"])
     assert rel(phi, ref) <= 8 * 2.0 ** -8
     avg, avg_ref = phi.mean(-1), ref.mean(-1)

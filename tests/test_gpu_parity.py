@@ -905,11 +905,13 @@ def _random_pann(seed, nh=8):
 def _write_pann(tmp_path, net, name):
     """Writes the artifact and returns (path, the stored network as the oracle
     reads it: float32 parameters)."""
+    from oracle import ann_paper_train
     from paper_1906_04017_amd import ann_format
     path = tmp_path / name
     ann_format.write_paper(path, net["W1"], net["b1"], net["W2"], net["b2"], net["imin"],
                            net["imax"])
-    return path, ann_format.read(path)
+    # the oracle reads the artifact with its own reader
+    return path, ann_paper_train.read_artifact(path)
 
 
 def _pann_bound(net, o, I):
@@ -1121,7 +1123,7 @@ def test_dataflow_expired_wait_is_reported(api, ctx):
     ref = prob.sweep(S).clone()
     prob.set_schedule("dataflow", poll_limit=1)
     prob.sweep(S)
-    with pytest.raises(api.DgsnError, match="dataflow"):
+    with pytest.raises(api.DgsnError, match="DGSN_ETIMEOUT.*dataflow"):
         prob.check()
     prob.check()   # the condition was cleared
     prob.set_schedule("dataflow")
