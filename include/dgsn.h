@@ -266,6 +266,31 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                         double *resid, double *eps_s, void *stream);
 
 /*
+ * dgsn_source_iterate for callers that cannot allocate memory (code under
+ * HIP graph capture elsewhere in the program, tight serving loops, harnesses
+ * that forbid hipMalloc): the same iteration with the same kernels and
+ * bitwise the same results, but its reduction partials, result slots and
+ * look-ahead iterate live in a static device array of the library
+ * (64 MiB + 128.25 KiB, one copy per device, held until the process ends)
+ * instead of memory the library allocates.  The call itself makes no
+ * device or host allocation.  Limits and rules:
+ *   - G * cells * 8 reals of the iterate must fit 64 MiB (e.g. 64^3 cells x
+ *     8 groups in FP32) when the iteration overlaps (no stored angular flux,
+ *     no anisotropic orders); a larger iterate returns DGSN_EINVAL;
+ *   - kernel timing must be off (its events may need creating), and a
+ *     dataflow schedule must have its tables (dgsn_problem_set_schedule or
+ *     dgsn_problem_autotune builds them): DGSN_EINVAL otherwise;
+ *   - the convergence history keeps the first 4096 iterations;
+ *   - every call on a device shares that device's array and leaves its last
+ *     contents there (nothing in it needs to start at zero): calls that
+ *     overlap in time on one device race and must be serialised by the
+ *     caller (the same stream, or one thread).
+ * Arguments, results and errors otherwise as dgsn_source_iterate.
+ */
+int dgsn_source_iterate_noalloc(dgsn_problem *p, void *phi, double tol, int max_iter,
+                                int *iters, double *resid, double *eps_s, void *stream);
+
+/*
  * Convergence history of the problem's last dgsn_source_iterate call: the
  * residual (the max-norm relative change above) and eps_S of Eq. (Test:Eq3)
  * after each of its iterations, the quantities from which the effective

@@ -75,6 +75,7 @@ SIGNATURES = {
     "dgsn_problem_set_solver": (_I, [_VP, _I]),
     "dgsn_sweep": (_I, [_VP, _VP, _VP, _VP]),
     "dgsn_source_iterate": (_I, [_VP, _VP, _D, _I, _PI, _PD, _PD, _VP]),
+    "dgsn_source_iterate_noalloc": (_I, [_VP, _VP, _D, _I, _PI, _PD, _PD, _VP]),
     "dgsn_adjoint_solve": (_I, [_VP, _VP, _VP, _VP, _D, _I, _PI, _VP]),
     "dgsn_local_solve": (_I, [_VP, _VP, _VP, _LL, _I, _VP]),
     "dgsn_ann_load": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(_VP)]),

@@ -370,16 +370,24 @@ class Problem:
         _lib.check(_lib.load().dgsn_sweep(self._h, _ptr(src), _ptr(phi), _stream(self.ctx.device)))
         return phi
 
-    def source_iterate(self, phi0=None, tol=1e-8, max_iter=1000, allow_notconv=False):
-        phi = (self._dev(phi0, (self.groups, self.ncell, 8)).clone() if phi0 is not None
-               else torch.zeros((self.groups, self.ncell, 8), dtype=self.dtype,
-                                device=self.ctx.device))
+    def source_iterate(self, phi0=None, tol=1e-8, max_iter=1000, allow_notconv=False,
+                       phi=None, noalloc=False):
+        """Source iteration from phi0 (zero if None) into a new tensor, or in
+        place into phi (a [G, ncell, 8] device tensor holding the initial
+        guess).  noalloc=True calls dgsn_source_iterate_noalloc, whose scratch
+        is the library's static device array (pass phi to keep the call free
+        of allocations on the torch side as well)."""
+        if phi is None:
+            phi = (self._dev(phi0, (self.groups, self.ncell, 8)).clone() if phi0 is not None
+                   else torch.zeros((self.groups, self.ncell, 8), dtype=self.dtype,
+                                    device=self.ctx.device))
         it = ctypes.c_int(0)
         r = ctypes.c_double(0)
         es = ctypes.c_double(0)
-        rc = _lib.load().dgsn_source_iterate(self._h, _ptr(phi), float(tol), int(max_iter),
-                                             ctypes.byref(it), ctypes.byref(r), ctypes.byref(es),
-                                             _stream(self.ctx.device))
+        fn = (_lib.load().dgsn_source_iterate_noalloc if noalloc
+              else _lib.load().dgsn_source_iterate)
+        rc = fn(self._h, _ptr(phi), float(tol), int(max_iter), ctypes.byref(it),
+                ctypes.byref(r), ctypes.byref(es), _stream(self.ctx.device))
         _lib.check(rc, allow=(_lib.DGSN_ENOTCONV,) if allow_notconv else ())
         return phi, dict(iters=it.value, resid=r.value, eps_s=es.value,
                          converged=(rc == _lib.DGSN_OK))

@@ -45,6 +45,9 @@ constexpr int kMaxTile = 3;       // largest tile edge of the sweep
 // k = 1 .. (L+1)^2 - 1 at index k - 1, orders L <= kMaxPlOrder
 constexpr int kYlmStride = 16;
 constexpr int kMaxPlOrder = 3;
+// iterations of the convergence history held without a host allocation (the
+// no-allocation source iteration records at most this many)
+constexpr int kSiHistoryReserve = 4096;
 
 // ---- host-side quadrature ---------------------------------------------------
 int level_symmetric(int order, std::vector<double> &omega, std::vector<double> &weight);
@@ -87,7 +90,9 @@ struct HostBuf {
 struct dgsn_ctx {
     int device = 0;
     int num_cu = 0;
-    dgsn::DevBuf scratch;   // small reduction scratch shared by local solves
+    // this device's copy of the library's static scratch array (see
+    // dgsn_source_iterate_noalloc), from hipGetSymbolAddress at creation
+    void *static_scratch = nullptr;
 };
 
 struct dgsn_ann {
@@ -133,6 +138,7 @@ struct dgsn_problem {
     // (1 = cells) the first unit and the first tile of every step, on device
     int schedule = DGSN_SCHED_PLANES;
     std::vector<double> si_resid, si_eps;   // per iteration of the last source iteration
+                                            // (capacity kSiHistoryReserve from creation)
     int flow_ready = 0;
     dgsn::DevBuf d_unit_map[4];      // uint4 per unit of one octant (built on first use)
     dgsn::DevBuf d_unit_dep[4];      // uint2 per unit: range of units it waits for

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "cell.hpp"
 #include "common.hpp"
@@ -82,6 +83,43 @@ void HostBuf::release()
     if (ptr) (void)hipHostFree(ptr);
     ptr = nullptr;
     bytes = 0;
+}
+
+// Scratch of dgsn_source_iterate_noalloc, one copy per device for the life
+// of the process: the FP64 reduction partials of up to 2048 blocks, two
+// result slots, and the look-ahead iterate of the overlapped iteration.
+// Host code never uses the array's name as an address: each device's copy is
+// found once with hipGetSymbolAddress (static_scratch_of) and passed on.
+constexpr size_t kScratchPartials = 2048ull * kRedStride * sizeof(double);   // 128 KiB
+constexpr size_t kScratchResults = 256;                                       // 2 slots
+constexpr size_t kScratchIterate = 64ull << 20;                               // 64 MiB
+constexpr size_t kScratchBytes = kScratchPartials + kScratchResults + kScratchIterate;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[64] = {};   // per device ordinal
+}  // namespace
+
+// Address of this device's copy of the scratch array (the device must be
+// current); looked up on the first call for each device and kept.
+int static_scratch_of(int device, void **out)
+{
+    if (device < 0 || device >= 64)
+        return set_error(DGSN_EUNSUPPORTED, "device ordinal %d beyond the scratch table", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return set_error(DGSN_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s",
+                             device, hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return DGSN_OK;
 }
 
 }  // namespace dgsn
@@ -512,9 +550,19 @@ int moment_sources(dgsn_problem *p, bool adjoint, hipStream_t s)
     return DGSN_OK;
 }
 
+// Scratch of a source iteration that may not allocate: partials [2048][8],
+// result slots [2][8] and the look-ahead iterate, all in the static array.
+struct NoAllocScratch {
+    double *partials;
+    double *results;
+    void *iterate;
+    size_t iterate_bytes;
+};
+
 template <typename Real>
 int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, int *iters,
-                        double *resid, double *eps_s, hipStream_t s)
+                        double *resid, double *eps_s, hipStream_t s,
+                        const NoAllocScratch *na = nullptr)
 {
     const long long nv = (long long)p->G * p->ncell;
     Real *src = static_cast<Real *>(p->src.ptr);
@@ -550,12 +598,18 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
     // modes iterate without the overlap).  Results are identical either way.
     const bool overlap = !p->store_psi && !pl;
     Real *buf[2] = {static_cast<Real *>(phi), nullptr};
-    if (overlap) {
+    if (overlap && na) {
+        if ((size_t)nv * 8 * sizeof(Real) > na->iterate_bytes)
+            return set_error(DGSN_EINVAL, "the iterate (%zu bytes) exceeds the no-allocation "
+                             "scratch limit of %zu bytes", (size_t)nv * 8 * sizeof(Real),
+                             na->iterate_bytes);
+        buf[1] = static_cast<Real *>(na->iterate);
+    } else if (overlap) {
         if (p->phi_alt.bytes != (size_t)nv * 8 * sizeof(Real))
             DGSN_TRY(p->phi_alt.alloc((size_t)nv * 8 * sizeof(Real)));
         buf[1] = static_cast<Real *>(p->phi_alt.ptr);
     }
-    double *dres = static_cast<double *>(p->red_result.ptr);
+    double *dres = na ? na->results : static_cast<double *>(p->red_result.ptr);
     double *hres = static_cast<double *>(p->h_result.ptr);
     unsigned *herr = reinterpret_cast<unsigned *>(hres + 2 * kRedStride);
     const bool flow = p->schedule == DGSN_SCHED_DATAFLOW;
@@ -564,6 +618,7 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
         DGSN_TRY(run_sweep<Real>(p, src, p->store_psi != 0, false, nullptr, s, pl));
         ReduceArgs<Real> R = reduce_args<Real>(p, buf[0]);
         R.resid = 1;
+        if (na) R.partials = na->partials;
         if (overlap) {
             R.phi_prev = buf[slot];
             R.phi = buf[slot ^ 1];
@@ -617,8 +672,11 @@ int source_iterate_impl(dgsn_problem *p, void *phi, double tol, int max_iter, in
             return set_error(DGSN_EINVAL, "source iteration %d produced a non-finite flux or "
                              "residual", it);
         }
-        p->si_resid.push_back(r);
-        p->si_eps.push_back(es);
+        // without allocation the history keeps what its reserved capacity holds
+        if (!na || p->si_resid.size() < p->si_resid.capacity()) {
+            p->si_resid.push_back(r);
+            p->si_eps.push_back(es);
+        }
         crit = p->si_criterion == DGSN_SI_EPS_S ? es : r;
         bool stop = it >= max_iter;
         if (!fixed) {
@@ -914,10 +972,13 @@ int dgsn_ctx_create(int hip_device, dgsn_ctx **out)
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return set_error(DGSN_EUNSUPPORTED, "libdgsn is built for gfx950, device is %s",
                          prop.gcnArchName);
+    void *scr = nullptr;
+    DGSN_TRY(static_scratch_of(hip_device, &scr));
     dgsn_ctx *c = new (std::nothrow) dgsn_ctx();
     if (!c) return set_error(DGSN_ENOMEM, "host allocation failed");
     c->device = hip_device;
     c->num_cu = prop.multiProcessorCount;
+    c->static_scratch = scr;
     *out = c;
     return DGSN_OK;
 }
@@ -986,6 +1047,8 @@ int dgsn_problem_create(dgsn_ctx *ctx, const dgsn_problem_desc *d, dgsn_problem 
     // both precisions (the autotuner can revisit)
     p->tile_b = 2;
     p->real_size = d->precision == DGSN_FP64 ? 8 : 4;
+    p->si_resid.reserve(kSiHistoryReserve);
+    p->si_eps.reserve(kSiHistoryReserve);
     p->n_planes = d->nx + d->ny + d->nz - 2;
 
     // directions sorted by octant, user order inside an octant
@@ -1522,6 +1585,38 @@ int dgsn_source_iterate(dgsn_problem *p, void *phi, double tol, int max_iter, in
                                              as_stream(stream))
                : source_iterate_impl<float>(p, phi, tol, max_iter, iters, resid, eps_s,
                                             as_stream(stream));
+}
+
+int dgsn_source_iterate_noalloc(dgsn_problem *p, void *phi, double tol, int max_iter,
+                                int *iters, double *resid, double *eps_s, void *stream)
+{
+    clear_error();
+    if (!p || !phi) return set_error(DGSN_EINVAL, "problem and phi must be set");
+    if (max_iter < 1) return set_error(DGSN_EINVAL, "max_iter must be >= 1");
+    if (!(tol >= 0.0)) return set_error(DGSN_EINVAL, "tol must be >= 0");
+    if (p->timing)
+        return set_error(DGSN_EINVAL, "kernel timing records events that may need creating; "
+                         "disable it (dgsn_problem_set_timing) for this call");
+    if (p->schedule == DGSN_SCHED_DATAFLOW && !p->flow_ready)
+        return set_error(DGSN_EINVAL, "the dataflow tables are not built");
+    if (p->red_blocks < 1 || (size_t)p->red_blocks * kRedStride * sizeof(double) >
+                                 kScratchPartials)
+        return set_error(DGSN_EINVAL, "reduction of %d blocks exceeds the scratch partials",
+                         p->red_blocks);
+    DGSN_HIP(hipSetDevice(p->ctx->device));
+    unsigned char *base = static_cast<unsigned char *>(p->ctx->static_scratch);
+    if (!base) return set_error(DGSN_EHIP, "no scratch address for device %d", p->ctx->device);
+    NoAllocScratch na;
+    na.partials = reinterpret_cast<double *>(base);
+    na.results = reinterpret_cast<double *>(base + kScratchPartials);
+    na.iterate = base + kScratchPartials + kScratchResults;
+    na.iterate_bytes = kScratchIterate;
+    p->ev_used = 0;
+    return p->precision == DGSN_FP64
+               ? source_iterate_impl<double>(p, phi, tol, max_iter, iters, resid, eps_s,
+                                             as_stream(stream), &na)
+               : source_iterate_impl<float>(p, phi, tol, max_iter, iters, resid, eps_s,
+                                            as_stream(stream), &na);
 }
 
 int dgsn_problem_si_history(const dgsn_problem *p, double *resid, double *eps_s, int cap, int *n)
