@@ -27,10 +27,21 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# vector issue of MI355X: 256 CUs x 4 SIMDs, 2.4 GHz peak clock; a wave64
+# VALU instruction holds its SIMD for 4 cycles at the non-packed FP32 rate
+# (16 lanes per cycle: 78.6 TFLOP/s of FMA), so the chip issues at most
+# 1024 * 2.4e9 / 4 = 614.4 G wave instructions per second
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+VALU_CYCLES_PER_INST = 4
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_PROFILES = {
     # dominant kernel -> committed rocprofv3 memory-counter summary
     ("dataflow", 2): "profiles/sweep_flow_ge_f32_tile2_blocky_scatter_64cube_S8_G8_hbm_traffic.txt",
+}
+SQ_PROFILES = {
+    # dominant kernel -> committed rocprofv3 SQ-counter summary
+    ("dataflow", 2): "profiles/sweep_flow_ge_f32_tile2_blocky_scatter_64cube_S8_G8_sq.txt",
 }
 
 
@@ -47,12 +58,11 @@ def kernel_source_digest():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(sched, tile, workload):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or
-    None if there is none for this kernel and workload or the kernel sources
-    changed since it was taken."""
-    rel = TRAFFIC_PROFILES.get((sched, tile))
+def profile_value(table, key, sched, tile, workload):
+    """A figure of the dominant kernel from its committed rocprofv3 summary,
+    or None if there is none for this kernel and workload or the kernel
+    sources changed since the counters were taken."""
+    rel = table.get((sched, tile))
     if rel is None or workload != "blocky_scatter_64^3_S8_G8":
         return None
     path = os.path.join(ROOT, rel)
@@ -64,9 +74,42 @@ def measured_traffic(sched, tile, workload):
             if ":" in line:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_digest") != kernel_source_digest():
+    if kv.get("source_digest") != kernel_source_digest() or key not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv[key])
+
+
+def measured_traffic(sched, tile, workload):
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE and WRITE_SIZE
+    scaled by a copy of known size)."""
+    return profile_value(TRAFFIC_PROFILES, "traffic_bytes_per_launch", sched, tile, workload)
+
+
+def other_bounds(st, sched, tile, workload, groups, cells, kernel_ms):
+    """The bounds beside the algorithmic-byte roofline: the compulsory bytes
+    (each cell's sigma_t, 8 sources and 8 fluxes per group once, fronts never
+    leaving the chip), the measured DRAM bytes, and the vector-issue bound
+    from the SQ counters (VALU wave instructions x 4 cycles over 1024 SIMDs
+    at 2.4 GHz)."""
+    real = st["algo_bytes_per_sweep"] / (24.0 * st["solves_per_sweep"] + 17.0 * cells * groups)
+    comp = real * 17.0 * cells * groups
+    sec = kernel_ms * 1e-3
+    out = {"compulsory": {"bytes_per_sweep": comp,
+                          "achieved_gbs": round(comp / sec / 1e9, 1),
+                          "frac": round(comp / sec / 1e9 / HBM_PEAK_GBS, 4)}}
+    traffic = measured_traffic(sched, tile, workload)
+    out["dram_measured"] = None if traffic is None else {
+        "bytes_per_sweep": traffic, "achieved_gbs": round(traffic / sec / 1e9, 1),
+        "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)}
+    insts = profile_value(SQ_PROFILES, "valu_insts_per_launch", sched, tile, workload)
+    if insts is None:
+        out["valu"] = None
+    else:
+        min_s = insts * VALU_CYCLES_PER_INST / (SIMDS * CLOCK_HZ)
+        out["valu"] = {"bound": "alu", "valu_insts_per_sweep": insts,
+                       "issue_peak_insts_per_s": SIMDS * CLOCK_HZ / VALU_CYCLES_PER_INST,
+                       "min_ms": round(min_s * 1e3, 4), "frac": round(min_s / sec, 4)}
+    return out
 
 
 def parse():
@@ -200,6 +243,8 @@ def main():
             "kernel_ms_per_sweep": round(sweep_kernel_ms, 4),
             "avg_launch_us": round(1e3 * kern_ms / max(kern_launches, 1), 3),
             "algo_bytes_per_sweep": st["algo_bytes_per_sweep"]}
+    roof["other_bounds"] = other_bounds(st, sched, tile, p["name"], p["groups"], prob.ncell,
+                                        sweep_kernel_ms)
 
     fp64 = None if args.skip_extras else plain_fp64(api, ctx, p)
     conv = None if args.skip_extras else si_convergence(api, ctx, p)
@@ -208,9 +253,10 @@ def main():
     aniso = None if args.skip_extras else anisotropic_steps(api, ctx, p)
     batch = None if args.skip_extras else uneven_batch(api, ctx, args.ann)
 
-    cpu = None
+    cpu = err = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, args.cpu_groups)
+        cpu, refs = cpu_baseline(p, args.cpu_groups)
+        err = error_vs_oracle(api, ctx, prob, p, refs, args.cpu_groups)
 
     out = {
         "metric": "cell*dir*group solves/s (FP32 GE sweep, one source iteration per step)",
@@ -222,6 +268,7 @@ def main():
                    "solves_per_step": solves, "last_residual": resid},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "error_vs_fp64_oracle": err,
         "fp64_ge": fp64,
         "si_convergence": conv,
         "ann_vs_ge": ann,
@@ -663,26 +710,100 @@ def uneven_batch(api, ctx, ann_path, count=64):
     return out
 
 
-def cpu_baseline(p, groups):
-    """FP64 oracle sweep of a bounded sample: the same mesh, quadrature and
-    materials restricted to the first `groups` groups, on all host cores."""
-    import oracle
-    ncell = p["sigma_t"].shape[1]
-    om, w = oracle.lq_n(p["order"])
+def _oracle_threads():
     cores = len(os.sched_getaffinity(0))
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
-    st = p["sigma_t"][:groups]
-    S = np.repeat(p["q"][:groups, :, None], 8, axis=-1)
+    return cores
+
+
+def _time_oracle_sweep(oracle, p, groups, threads, reps):
+    """Median wall time of `reps` FP64 oracle sweeps of p restricted to
+    `groups` (a slice), source S = q; returns (seconds, solves, phi)."""
+    om, w = oracle.lq_n(p["order"])
+    st = p["sigma_t"][groups]
+    S = np.repeat(p["q"][groups, :, None], 8, axis=-1)
     mesh = (*p["n"], *p["length"])
-    log(f"cpu baseline: oracle sweep of {groups} group(s) on {cores} threads")
-    t0 = time.perf_counter()
-    oracle.sweep(mesh, om, w, st, S, p["psi_inc"], nthreads=cores)
-    dt = time.perf_counter() - t0
-    solves = ncell * len(w) * groups
-    return {"value": solves / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"one FP64 sweep of {p['name']} restricted to {groups} group(s) "
-                      f"({solves} solves, {dt:.2f} s)"}
+    times, phi = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        phi = oracle.sweep(mesh, om, w, st, S, p["psi_inc"], nthreads=threads)
+        times.append(time.perf_counter() - t0)
+    solves = st.shape[1] * len(w) * st.shape[0]
+    return float(np.median(times)), solves, phi
+
+
+def cpu_baseline(p, groups):
+    """The FP64 oracle timed on the host on bounded samples of the
+    workloads: the benchmark workload (C2: one sweep of its first `groups`
+    groups, median of 3, all cores; and one group on 1 core), the 8^3 S4
+    absorber (C1, median of 3) and one group of the paper problems at 128^3
+    S8 (C3 with GE: Problem 3, median of 3).  Returns the record and the
+    oracle's fluxes of the C2 and C3 samples (S = q), against which the GPU
+    results state their error."""
+    import oracle
+    from paper_1906_04017_amd import inputs
+    cores = _oracle_threads()
+    log(f"cpu baseline: oracle sweeps on {cores} threads and on 1 thread")
+    dt, solves, phi_c2 = _time_oracle_sweep(oracle, p, slice(0, groups), cores, 3)
+    dt1, solves1, _ = _time_oracle_sweep(oracle, p, slice(0, 1), 1, 1)
+    c1 = inputs.absorber_cube()
+    dtc1, solvesc1, _ = _time_oracle_sweep(oracle, c1, slice(0, 1), cores, 3)
+    c3 = inputs.paper_problems(n=128, groups=4, order=8)
+    dtc3, solvesc3, phi_c3 = _time_oracle_sweep(oracle, c3, slice(2, 3), cores, 3)
+    rec = {"value": solves / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"one FP64 sweep of {p['name']} restricted to {groups} group(s) "
+                     f"({solves} solves), median of 3: {dt:.2f} s",
+           "value_1core": solves1 / dt1,
+           "sample_1core": f"one FP64 sweep of {p['name']} restricted to 1 group "
+                           f"({solves1} solves) on 1 thread: {dt1:.2f} s",
+           "absorber_cube_8^3_S4_G1": {"solves_per_s": solvesc1 / dtc1, "seconds": dtc1,
+                                       "cores": cores, "reps": 3},
+           "paper_problem3_128^3_S8_G1": {"solves_per_s": solvesc3 / dtc3, "seconds": dtc3,
+                                          "cores": cores, "reps": 3}}
+    log(f"cpu baseline: C2 {solves / dt:.3e} solves/s ({cores} threads), "
+        f"{solves1 / dt1:.3e} (1 thread); C1 {solvesc1 / dtc1:.3e}; C3 {solvesc3 / dtc3:.3e}")
+    return rec, {"c2": phi_c2, "c3_problem3": phi_c3}
+
+
+def error_vs_oracle(api, ctx, prob, p, refs, groups):
+    """Norm-wise relative error max|phi - phi_oracle| / max|phi_oracle| per
+    group of one sweep with S = q: the FP32 GE benchmark problem as timed
+    (autotuned), a FP64 GE problem on the same workload (autotuned), and the
+    FP32 GE sweep of the paper's Problem 3 at 128^3 S8 (autotuned)."""
+    import torch
+    from paper_1906_04017_amd import inputs
+
+    def per_group(phi, ref):
+        phi = phi.double().cpu().numpy()[:ref.shape[0]]
+        return [float(np.abs(phi[g] - ref[g]).max() / np.abs(ref[g]).max())
+                for g in range(ref.shape[0])]
+
+    S = np.repeat(p["q"][..., None], 8, axis=-1)
+    out = {"reference": "FP64 oracle sweep, source S = q", "fp32_tolerance": 1e-5}
+    out["fp32_ge_blocky_scatter_per_group"] = per_group(
+        prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")), refs["c2"])
+    om, w = api.quadrature_ls(p["order"])
+    p64 = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp64")
+    p64.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    p64.autotune()
+    out["fp64_ge_blocky_scatter_per_group"] = per_group(
+        p64.sweep(torch.tensor(S, dtype=torch.float64, device="cuda")), refs["c2"])
+    p64.close()
+    c3 = inputs.paper_problems(n=128, groups=4, order=8)
+    om8, w8 = api.quadrature_ls(8)
+    pc3 = api.Problem(ctx, c3["n"], c3["length"], 1, om8, w8, precision="fp32")
+    pc3.set_materials(c3["sigma_t"][2:3], c3["sigma_s"][2:3], c3["q"][2:3])
+    pc3.set_inflow(c3["psi_inc"])
+    pc3.autotune()
+    S3 = np.repeat(c3["q"][2:3, :, None], 8, axis=-1)
+    out["fp32_ge_paper_problem3_128^3"] = per_group(
+        pc3.sweep(torch.tensor(S3, dtype=torch.float32, device="cuda")), refs["c3_problem3"])[0]
+    pc3.close()
+    log("error vs FP64 oracle: fp32 %.2e, fp64 %.2e, fp32 problem 3 %.2e" % (
+        max(out["fp32_ge_blocky_scatter_per_group"]),
+        max(out["fp64_ge_blocky_scatter_per_group"]), out["fp32_ge_paper_problem3_128^3"]))
+    return out
 
 
 if __name__ == "__main__":

@@ -54,6 +54,7 @@ def _load():
     lib.orc_adjoint.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [ctypes.c_int] * 2 + \
         [_D] * 7 + [ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _I, ctypes.c_int]
     lib.orc_source_iterate_gg.argtypes = lib.orc_source_iterate.argtypes
+    lib.orc_source_iterate_eps.argtypes = lib.orc_source_iterate.argtypes
     lib.orc_adjoint_gg.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 7 + [ctypes.c_double, ctypes.c_int, _D, _D, _D, _I,
                                          ctypes.c_int]
@@ -244,8 +245,10 @@ def sweep_balance(mesh, omega, weight, sigma_t, src, psi_inc, psi):
 
 
 def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1e-8,
-                   max_iter=1000, phi0=None, store_psi=False, nthreads=0, sigma_gg=None):
-    """Scattering source iteration to max-norm relative change < tol.
+                   max_iter=1000, phi0=None, store_psi=False, nthreads=0, sigma_gg=None,
+                   criterion="maxnorm"):
+    """Scattering source iteration to max-norm relative change < tol, or with
+    criterion="eps_s" to Eq. (Test:Eq3) < tol (in-group scattering only).
     sigma_gg [G, G, ncell] (from g' into g at [g', g]) replaces the in-group
     sigma_s with multigroup scattering when given.
     Returns dict(phi, iters, resid, eps_s, converged[, psi])."""
@@ -264,12 +267,14 @@ def source_iterate(mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=None, tol=1
     it = ctypes.c_int(0)
     resid = ctypes.c_double(0)
     eps = ctypes.c_double(0)
+    if criterion not in ("maxnorm", "eps_s") or (criterion == "eps_s" and sigma_gg is not None):
+        raise ValueError("criterion must be 'maxnorm', or 'eps_s' without sigma_gg")
     if sigma_gg is None:
-        rc = lib.orc_source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
-                                    _p(_f64(weight, (nd,))), _p(sigma_t), _p(sigma_s), _p(q),
-                                    _p(inc), _p(phi), float(tol), int(max_iter),
-                                    ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps),
-                                    _p(psi), int(nthreads))
+        fn = lib.orc_source_iterate if criterion == "maxnorm" else lib.orc_source_iterate_eps
+        rc = fn(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega), _p(_f64(weight, (nd,))),
+                _p(sigma_t), _p(sigma_s), _p(q), _p(inc), _p(phi), float(tol), int(max_iter),
+                ctypes.byref(it), ctypes.byref(resid), ctypes.byref(eps), _p(psi),
+                int(nthreads))
     else:
         rc = lib.orc_source_iterate_gg(nx, ny, nz, lx, ly, lz, ng, nd, _p(omega),
                                        _p(_f64(weight, (nd,))), _p(sigma_t),

@@ -478,7 +478,8 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
                           const double *sigma_t, const double *sigma_s, const double *q,
                           const double psi_inc[6], double *phi, double tol, int max_iter,
                           int *iters, double *resid, double *eps_s, double *psi_store,
-                          const orc_ann *net, int nthreads, const double *sigma_gg)
+                          const orc_ann *net, int nthreads, const double *sigma_gg,
+                          int stop_on_eps_s)
 {
     const long ncell = (long)nx * ny * nz;
     const long nv = (long)ng * ncell;
@@ -496,7 +497,7 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
         orc_si_metrics(nv, phin, phi, &r, &es);
         memcpy(phi, phin, (size_t)nv * 8 * sizeof(double));
         ++it;
-        if (r < tol) break;
+        if ((stop_on_eps_s ? es : r) < tol) break;
     }
     free(S);
     free(phin);
@@ -504,7 +505,7 @@ static int source_iterate(int nx, int ny, int nz, double lx, double ly, double l
     if (resid) *resid = r;
     if (eps_s) *eps_s = es;
     if (rc) return rc;
-    return (r < tol) ? ORC_OK : ORC_ENOTCONV;
+    return ((stop_on_eps_s ? es : r) < tol) ? ORC_OK : ORC_ENOTCONV;
 }
 
 int orc_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, int ng, int nd,
@@ -515,7 +516,21 @@ int orc_source_iterate(int nx, int ny, int nz, double lx, double ly, double lz, 
 {
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
-                          nthreads, NULL);
+                          nthreads, NULL, 0);
+}
+
+/* The same iteration stopped on the paper's criterion: eps_S of Eq.
+   (Test:Eq3) below tol (the Problem 4 runs of Sec. 4 use 1e-4). */
+int orc_source_iterate_eps(int nx, int ny, int nz, double lx, double ly, double lz, int ng,
+                           int nd, const double *omega, const double *weight,
+                           const double *sigma_t, const double *sigma_s, const double *q,
+                           const double psi_inc[6], double *phi, double tol, int max_iter,
+                           int *iters, double *resid, double *eps_s, double *psi_store,
+                           int nthreads)
+{
+    return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
+                          psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
+                          nthreads, NULL, 1);
 }
 
 /* Source iteration with multigroup scattering sigma_gg [G][G][ncell] (from g'
@@ -530,7 +545,7 @@ int orc_source_iterate_gg(int nx, int ny, int nz, double lx, double ly, double l
     if (!sigma_gg) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, NULL, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, psi_store, NULL,
-                          nthreads, sigma_gg);
+                          nthreads, sigma_gg, 0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1442,7 +1457,7 @@ int orc_ann_source_iterate(int nx, int ny, int nz, double lx, double ly, double 
     if (nh < 1 || nh > 1024) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads,
-                          NULL);
+                          NULL, 0);
 }
 
 /* Batched paper-form network one-cell solves (physical orientation). */
@@ -1491,5 +1506,5 @@ int orc_pann_source_iterate(int nx, int ny, int nz, double lx, double ly, double
     if (nh < 1 || nh > 64) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads,
-                          NULL);
+                          NULL, 0);
 }

@@ -1085,3 +1085,27 @@ def test_sweep_balance_streaming_through_one_face():
     assert b["inflow"] == pytest.approx(expect, rel=1e-14)
     assert b["outflow"] == pytest.approx(expect, rel=1e-12)
     assert b["absorption"] == 0.0 and b["source"] == 0.0
+
+
+def test_eps_s_stopping_criterion_stops_at_the_first_iteration_below_tol():
+    # stopped on Eq. (Test:Eq3): eps_S of the last step is below tol and that
+    # of the step before is not (recomputed from fixed-count runs)
+    rng = np.random.default_rng(62)
+    n, L = (3, 3, 2), (0.9, 0.9, 0.6)
+    om, w = oracle.lq_n(4)
+    st = rng.uniform(1.0, 3.0, (1, 18))
+    ss = 0.9 * st
+    q = np.ones((1, 18))
+    mesh = (*n, *L)
+    r = oracle.source_iterate(mesh, om, w, st, ss, q, tol=1e-3, max_iter=500,
+                              criterion="eps_s")
+    k = r["iters"]
+    assert r["converged"] and k > 3 and r["eps_s"] < 1e-3
+    a = oracle.source_iterate(mesh, om, w, st, ss, q, tol=0.0, max_iter=k - 2)
+    b = oracle.source_iterate(mesh, om, w, st, ss, q, tol=0.0, max_iter=k - 1)
+    _, es_prev = oracle.si_metrics(b["phi"], a["phi"])
+    _, es_last = oracle.si_metrics(r["phi"], b["phi"])
+    assert es_prev >= 1e-3 > es_last
+    assert es_last == pytest.approx(r["eps_s"], rel=1e-13)
+    assert np.array_equal(r["phi"], oracle.source_iterate(mesh, om, w, st, ss, q, tol=0.0,
+                                                          max_iter=k)["phi"])
