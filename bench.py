@@ -138,6 +138,9 @@ def parse():
                     help="only run --steps sweeps of the BF16-MFMA network on the paper problems "
                          "(128^3, S8, 4 groups) after autotuning: the workload of the matrix-core "
                          "counter passes")
+    ap.add_argument("--paper-solver", default="ann", choices=("ann", "ann_paper", "ge"),
+                    help="local solver of --ann-only: the BF16-MFMA network (default), the "
+                         "paper-form network or FP32 GE, for counters on the same workload")
     ap.add_argument("--aniso-only", action="store_true",
                     help="only time source iterations of the workload with P_L scattering, "
                          "in-group and with group-to-group matrices (P0, P1, P3): the workload "
@@ -179,7 +182,8 @@ def main():
 
     if args.ann_only:
         ctx = api.Context(0)
-        print(json.dumps(ann_sweeps(api, ctx, args.ann, args.steps)), flush=True)
+        path = {"ann": args.ann, "ann_paper": args.ann_paper, "ge": None}[args.paper_solver]
+        print(json.dumps(ann_sweeps(api, ctx, path, args.steps)), flush=True)
         return
     if args.paper_tables:
         ctx = api.Context(0)
@@ -374,12 +378,14 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
         out[f"{solver}_solves_per_s"] = solves / dt
         out[f"{solver}_ms_per_sweep"] = dt * 1e3
         if solver == "ann":
-            # the BF16 network's matrix-core rate: 6144 issued flops per solve
-            # (2 * (32 * 64 + 64 * 16), K padded 24 -> 32, N 8 -> 16)
-            tf = 6144 * solves / dt / 1e12
-            out["ann_mfma_roofline"] = {"bound": "mfma", "achieved": round(tf, 1),
+            # the BF16 network's matrix-core rate by the method's 4096 flops
+            # per solve (2 * (24 * 64 + 64 * 8)); the kernel issues 8192 after
+            # padding K 24 -> 32 and the output rows 8 -> 32
+            tf = 4096 * solves / dt / 1e12
+            out["ann_mfma_roofline"] = {"bound": "mfma", "achieved": round(tf, 2),
                                         "peak": 2500.0, "unit": "TFLOP/s",
-                                        "frac": round(tf / 2500.0, 4), "flops_per_solve": 6144}
+                                        "frac": round(tf / 2500.0, 5), "flops_per_solve": 4096,
+                                        "issued_flops_per_solve": 8192}
         res[solver] = phi.double().mean(-1)        # cell averages [G, ncell]
         log(f"paper problems {solver}: {dt * 1e3:.3f} ms per sweep")
         prob.close()
@@ -421,30 +427,35 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
 
 
 def ann_sweeps(api, ctx, ann_path, reps, n=128):
-    """Sweeps of the paper problems (128^3, S8, 4 groups) with the BF16-MFMA
-    network alone, for the matrix-core counters: the network's two layers
-    issue 2 * (32 * 64 + 64 * 16) = 6144 MFMA flops per solve (K padded 24 ->
-    32, N 8 -> 16)."""
+    """Sweeps of the paper problems (128^3, S8, 4 groups) with one local
+    solver alone (a network artifact, or GE when ann_path is None), for the
+    counters: the BF16 network's two layers issue 2 * 32 * 32 * 16 * 8 = 8192
+    MFMA flops per solve (K padded 24 -> 32, the output rows 8 -> 32) for the
+    method's 2 * (24 * 64 + 64 * 8) = 4096."""
     import torch
     from paper_1906_04017_amd import inputs
     p = inputs.paper_problems(n=n, groups=4, order=8)
     om, w = api.quadrature_ls(8)
-    ann = api.Ann(ctx, ann_path)
-    prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32", solver="ann")
+    ann = api.Ann(ctx, ann_path) if ann_path else None
+    prob = api.Problem(ctx, p["n"], p["length"], 4, om, w, precision="fp32",
+                       solver="ann" if ann else "ge")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
     prob.set_inflow(p["psi_inc"])
-    prob.set_ann(ann)
+    if ann:
+        prob.set_ann(ann)
     tile, sched, _ = prob.autotune()
     S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32, device="cuda")
     dt, _ = time_sweeps(prob, S, reps)
     solves = prob.stats()["solves_per_sweep"]
-    log(f"ann sweeps: {sched} schedule, {tile}^3 tiles, {dt * 1e3:.3f} ms per sweep")
-    out = {"workload": p["name"], "schedule": sched, "tile": tile, "sweeps": reps + 1,
-           "ms_per_sweep": dt * 1e3, "solves_per_sweep": solves,
-           "mfma_flops_per_sweep": 6144 * solves,
-           "mfma_tflops": 6144 * solves / dt / 1e12}
+    log(f"paper problems, one solver: {sched} schedule, {tile}^3 tiles, {dt * 1e3:.3f} ms per "
+        "sweep")
+    out = {"workload": p["name"], "solver": os.path.basename(ann_path) if ann else "GE",
+           "schedule": sched, "tile": tile, "sweeps": reps + 1, "ms_per_sweep": dt * 1e3,
+           "solves_per_sweep": solves, "method_flops_per_sweep": 4096 * solves,
+           "method_tflops": 4096 * solves / dt / 1e12}
     prob.close()
-    ann.close()
+    if ann:
+        ann.close()
     return out
 
 

@@ -3,18 +3,22 @@
 // matrix cores with FP32 accumulation, and its use inside the sweep in place
 // of assembly + Gaussian elimination (Sec. 4, first paragraphs).
 //
-// Matrix-core mapping (v_mfma_f32_16x16x32_bf16, one wave = 64 samples in 4
-// batches of 16).  The layers are evaluated transposed so that no data moves
-// between them:
-//   H^T[64 x 16] = W1[64 x 32] X^T[32 x 16]   (4 tiles of 16 hidden units)
-//   Y^T[16 x 16] = W2p[16 x 64] relu(H^T)     (2 K-chunks of 32)
-// The B operand of layer 1 is the sample's 24 features padded to 32: lane l
-// holds 8 features (index 8 (l/16) + e) of sample l % 16.  Layer 1 returns in
-// lane l the hidden units 16 m + 4 (l/16) + r of sample l % 16; after bias
-// (accumulator initialised with b1), ReLU and BF16 rounding these 16 values
-// are exactly the lane's B operand of layer 2 if the columns of W2 are
-// permuted accordingly on the host (W2p).  The contraction order inside one
-// MFMA is irrelevant because A and B use the same lane/element pairing.
+// Matrix-core mapping (v_mfma_f32_32x32x16_bf16, one wave = 64 samples in
+// 2 batches of 32, ann_body.hpp).  The layers are evaluated transposed so
+// that no data moves between them:
+//   H^T[64 x 32] = W1[64 x 32] X^T[32 x 32]   (2 tiles of 32 hidden units x 2 K-steps)
+//   Y^T[32 x 32] = W2'[32 x 64] relu(H^T)     (4 K-steps of 16; rows 0..7 are the outputs)
+// The B operand of layer 1 is the samples' 24 features padded to 32 (two of
+// the padding features carry the hidden bias): lane half h of a K-step holds
+// 8 features of each of the batch's 32 samples.  Each lane computes its own
+// sample's features, so the operands are formed by exchanging the upper and
+// lower 32 lanes (v_permlane32_swap) instead of a round trip through LDS, and
+// so are the outputs at the end.  Layer 1 leaves in lane half h the hidden
+// units hid(kc, h, e) of its column's sample; after ReLU and BF16 rounding
+// these are exactly the lane's B operand of layer 2 once the columns of W2
+// are permuted accordingly on the host (W2').  The contraction order inside
+// one instruction is irrelevant because A and B use the same lane/element
+// pairing.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,10 +35,8 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
                                                         const float *__restrict__ x,
                                                         float *__restrict__ y, long long n)
 {
-    __shared__ __bf16 lin[4 * 64 * 32];
-    __shared__ float lout[4 * 64 * 8];
     AnnRegs R;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     ann_load(prm, lane, R);
     const long long nblk = (n + 255) / 256;
     for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -42,12 +44,11 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
         float f[24], o[8];
 #pragma unroll
         for (int k = 0; k < 24; ++k) f[k] = s < n ? x[s * 24 + k] : 0.0f;
-        ann_wave(R, f, lin + wv * (64 * 32), lout + wv * (64 * 8), o);
+        ann_wave(R, f, o);
         if (s < n) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
         }
-        __syncthreads();
     }
 }
 
@@ -118,24 +119,26 @@ int build_params(dgsn_ann *a)
     };
     auto put_f32 = [&](size_t off, float v) { std::memcpy(&buf[off], &v, 4); };
     const int H = a->n_hidden, NI = a->n_in, NO = a->n_out;
+    // operand layouts of v_mfma_f32_32x32x16_bf16 (see ann_body.hpp)
     for (int lane = 0; lane < 64; ++lane) {
-        const int col = lane & 15, grp = lane >> 4;
-        for (int m = 0; m < 4; ++m) {
-            const int hid = 16 * m + col;
-            for (int e = 0; e < 8; ++e) {
-                const int f = 8 * grp + e;
-                float v = (hid < H && f < NI) ? a->W1[hid * NI + f] : 0.0f;
-                if (hid < H && f == kFeatBiasHi) v = bf16_value(a->b1[hid]);
-                if (hid < H && f == kFeatBiasLo) v = a->b1[hid] - bf16_value(a->b1[hid]);
-                put_bf16(kParamW1 + (m * 64 + lane) * 16 + 2 * e, v);
+        const int row = lane & 31, half = lane >> 5;
+        for (int t = 0; t < 2; ++t)
+            for (int kk = 0; kk < 2; ++kk) {
+                const int hid = 32 * t + row;
+                for (int e = 0; e < 8; ++e) {
+                    const int f = 16 * kk + 8 * half + e;
+                    float v = (hid < H && f < NI) ? a->W1[hid * NI + f] : 0.0f;
+                    if (hid < H && f == kFeatBiasHi) v = bf16_value(a->b1[hid]);
+                    if (hid < H && f == kFeatBiasLo) v = a->b1[hid] - bf16_value(a->b1[hid]);
+                    put_bf16(kParamW1 + ((2 * t + kk) * 64 + lane) * 16 + 2 * e, v);
+                }
             }
-        }
-        for (int c = 0; c < 2; ++c)
+        for (int kc = 0; kc < 4; ++kc)
             for (int e = 0; e < 8; ++e) {
-                const int out = col;
-                const int hid = 16 * (2 * c + (e >> 2)) + 4 * grp + (e & 3);
+                const int out = row;
+                const int hid = 16 * kc + 8 * (e >> 2) + 4 * half + (e & 3);
                 const float v = (out < NO && hid < H) ? a->W2[out * H + hid] : 0.0f;
-                put_bf16(kParamW2 + (c * 64 + lane) * 16 + 2 * e, v);
+                put_bf16(kParamW2 + (kc * 64 + lane) * 16 + 2 * e, v);
             }
     }
     for (int out = 0; out < 8; ++out) put_f32(kParamB2 + 4 * out, out < NO ? a->b2[out] : 0.0f);

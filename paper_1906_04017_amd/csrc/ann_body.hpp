@@ -30,9 +30,18 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 
-constexpr int kParamW1 = 0;                  // [4][64] bf16x8
-constexpr int kParamW2 = 4 * 64 * 16;        // [2][64] bf16x8
-constexpr int kParamB2 = kParamW2 + 2 * 64 * 16;  // [8] f32, uniform over the wave
+// Operand images of the network (built by build_params in ann.hip), for
+// v_mfma_f32_32x32x16_bf16.  Lane l (half h = l / 32) holds:
+//   W1 tile t (hidden 32t .. 32t+31), K-step kk (features 16kk .. 16kk+15):
+//     W1[32t + l%32][16kk + 8h + e], e = 0..7, at [2t + kk][l];
+//   W2 K-step kc (16 hidden units): W2[l%32][hid(kc, h, e)] at [kc][l], where
+//     hid(kc, h, e) = 16kc + 8(e/4) + 4h + e%4 is the hidden unit that layer 1
+//     leaves in element e of lane half h (rows 0..7 of the output are the 8
+//     outputs, the other 24 are zero);
+//   b2: 8 floats, uniform over the wave.
+constexpr int kParamW1 = 0;                        // [4][64] bf16x8
+constexpr int kParamW2 = 4 * 64 * 16;              // [4][64] bf16x8
+constexpr int kParamB2 = kParamW2 + 4 * 64 * 16;   // [8] f32
 constexpr int kParamBytes = kParamB2 + 8 * 4;
 constexpr int kHiddenPad = 64;
 // the hidden bias b1 enters layer 1 through two padding features held at 1:
@@ -41,9 +50,11 @@ constexpr int kHiddenPad = 64;
 constexpr int kFeatBiasHi = 24;
 constexpr int kFeatBiasLo = 25;
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
 struct AnnRegs {
     bf16x8 w1[4];
-    bf16x8 w2[2];
+    bf16x8 w2[4];
     const float *b2;   // [8], read as scalars
 };
 
@@ -54,68 +65,99 @@ __device__ __forceinline__ void ann_load(const unsigned char *__restrict__ prm, 
     for (int m = 0; m < 4; ++m)
         R.w1[m] = *reinterpret_cast<const bf16x8 *>(prm + kParamW1 + (m * 64 + lane) * 16);
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
         R.w2[c] = *reinterpret_cast<const bf16x8 *>(prm + kParamW2 + (c * 64 + lane) * 16);
     R.b2 = reinterpret_cast<const float *>(prm + kParamB2);
 }
 
-// Evaluates the network for the 64 samples held by the 64 lanes of the wave
-// (one sample per lane, 24 FP32 features).  lds_in: 64*32 bf16 of this wave,
-// lds_out: 64*8 floats of this wave.  Must be reached by every lane of the
-// wave (it synchronises the wave's LDS traffic only).
-__device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
-                                         __bf16 *lds_in, float *lds_out, float out[8])
+// Exchanges the upper half of a (lanes 32..63) with the lower half of b
+// (lanes 0..31): a becomes [a.lo, b.lo] and b becomes [a.hi, b.hi].
+__device__ __forceinline__ void swap_halves(unsigned &a, unsigned &b)
 {
-    const int lane = threadIdx.x & 63;
-    {
-        bf16x8 v[4];
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+}
+
+// Evaluates the network for the 64 samples held by the 64 lanes of the wave
+// (one sample per lane, 24 FP32 features), with no LDS traffic.  The
+// samples of lanes 0..31 form batch 0 and those of lanes 32..63 batch 1; a
+// 32x32x16 matrix instruction takes 32 samples as its columns, so the
+// transposes between "one sample per lane" and the operand layout (lane
+// half h holding features 8h .. 8h+7 of a K-step) are exchanges between the
+// two halves of the wave.  Layer 1 computes H^T = W1 X^T per batch (two
+// tiles of 32 hidden units, two K-steps of 16 features); its output
+// registers, after ReLU and the rounding to bf16, are the B operand of
+// layer 2, Y^T = W2' relu(H^T) (four K-steps of 16 hidden units, W2' the
+// column order hid(kc, h, e) above).  Must be reached by every lane.
+__device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24], float out[8])
+{
+    // the lane's 32 padded features as bf16 pairs: chunk q holds 8q .. 8q+7
+    unsigned c[4][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int f = 8 * q + e;
-                v[q][e] = (__bf16)(f < 24 ? feat[f]
-                                          : (f == kFeatBiasHi || f == kFeatBiasLo ? 1.0f : 0.0f));
+        for (int p = 0; p < 4; ++p) {
+            float v[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int f = 8 * q + 2 * p + k;
+                v[k] = f < 24 ? feat[f] : (f == kFeatBiasHi || f == kFeatBiasLo ? 1.0f : 0.0f);
             }
+            const f32x2 pr = {v[0], v[1]};
+            c[q][p] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+        }
+    // K-step kk of batch bt needs chunk 2kk + h of the batch's samples in
+    // lane half h: after the exchange c[2kk + bt] is that operand
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8 *>(lds_in + lane * 32 + 8 * q) = v[q];
+    for (int p = 0; p < 4; ++p) {
+        swap_halves(c[0][p], c[1][p]);
+        swap_halves(c[2][p], c[3][p]);
     }
-    wave_lds_sync();
-    const int col = lane & 15, grp = lane >> 4;
+    unsigned y[2][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(lds_in + (16 * b + col) * 32 + 8 * grp);
-        f32x4 h[4];
+    for (int bt = 0; bt < 2; ++bt) {
+        const u32x4 u0 = {c[bt][0], c[bt][1], c[bt][2], c[bt][3]};
+        const u32x4 u1 = {c[2 + bt][0], c[2 + bt][1], c[2 + bt][2], c[2 + bt][3]};
+        const bf16x8 x0 = __builtin_bit_cast(bf16x8, u0);
+        const bf16x8 x1 = __builtin_bit_cast(bf16x8, u1);
+        f32x16 acc = (f32x16)0.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-            h[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w1[m], xb, (f32x4)0.0f, 0, 0, 0);
-        // ReLU after the rounding to bf16, on the packed pairs: bf16 is sign
-        // and magnitude, so as 16-bit integers every negative value (and -0)
-        // is below zero and max(x, 0) is the ReLU, equal to rounding the
-        // ReLU of the FP32 value
-        bf16x8 hb[2];
+        for (int t = 0; t < 2; ++t) {
+            f32x16 h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t], x0, (f32x16)0.0f, 0,
+                                                               0, 0);
+            h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t + 1], x1, h, 0, 0, 0);
+            // ReLU after the rounding to bf16, on the packed pairs: bf16 is
+            // sign and magnitude, so as 16-bit integers every negative value
+            // (and -0) is below zero and max(x, 0) is the ReLU, equal to
+            // rounding the ReLU of the FP32 value
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            u32x4 t;
+            for (int pp = 0; pp < 2; ++pp) {
+                u32x4 tq;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const f32x4 &hv = h[2 * c + (p >> 1)];
-                const f32x2 pr = {hv[2 * (p & 1)], hv[2 * (p & 1) + 1]};
-                t[p] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+                for (int p = 0; p < 4; ++p) {
+                    const f32x2 pr = {h[8 * pp + 2 * p], h[8 * pp + 2 * p + 1]};
+                    tq[p] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+                }
+                const i16x8 r = __builtin_elementwise_max(__builtin_bit_cast(i16x8, tq), (i16x8)0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[2 * t + pp],
+                                                              __builtin_bit_cast(bf16x8, r), acc,
+                                                              0, 0, 0);
             }
-            const i16x8 r = __builtin_elementwise_max(__builtin_bit_cast(i16x8, t), (i16x8)0);
-            hb[c] = __builtin_bit_cast(bf16x8, r);
         }
-        f32x4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[0], hb[0], (f32x4)0.0f, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(R.w2[1], hb[1], y, 0, 0, 0);
-        if (grp < 2) {
+        // rows 0..3 of lane half h are outputs 4h .. 4h+3 of the column's sample
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lds_out[(16 * b + col) * 8 + 4 * grp + r] = y[r];
-        }
+        for (int r = 0; r < 4; ++r) y[bt][r] = __float_as_uint(acc[r]);
     }
-    wave_lds_sync();
+    // each sample's outputs back to its lane: after the exchange y[0] holds
+    // outputs 0..3 and y[1] outputs 4..7 of the lane's own sample
 #pragma unroll
-    for (int k = 0; k < 8; ++k) out[k] = lds_out[lane * 8 + k] + R.b2[k];
+    for (int r = 0; r < 4; ++r) swap_halves(y[0][r], y[1][r]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out[r] = __uint_as_float(y[0][r]) + R.b2[r];
+        out[4 + r] = __uint_as_float(y[1][r]) + R.b2[4 + r];
+    }
 }
 
 }  // namespace dgsn

@@ -95,37 +95,35 @@ constexpr int kBatchPaperAnn = 3;
 template <bool kCoh>
 __device__ __forceinline__ void batch_body(const PlaneArgs<float> &A, const float inc[3],
                                            int solver, int tileb, const SegLane &l, int tid,
-                                           bool tv, uint32_t pt, int o, TileLds<float> &L,
-                                           AnnLds &al)
+                                           bool tv, uint32_t pt, int o, TileLds<float> &L)
 {
     if (solver == kBatchPaperAnn) {
         if (tileb == 2)
             tile_body<float, kFormAnnPaper, 2, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
-                                                                   o, l.ok, L, nullptr);
+                                                                   o, l.ok, L);
         else
             tile_body<float, kFormAnnPaper, 1, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
-                                                                   o, l.ok, L, nullptr);
+                                                                   o, l.ok, L);
     } else if (solver == DGSN_ANN) {
         if (tileb == 2)
             tile_body<float, kFormAnn, 2, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt, o,
-                                                              l.ok, L, &al);
+                                                              l.ok, L);
         else
             tile_body<float, kFormAnn, 1, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt, o,
-                                                              l.ok, L, &al);
+                                                              l.ok, L);
     } else {
         if (tileb == 2)
             tile_body<float, kFormMassInv, 2, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
-                                                                  o, l.ok, L, nullptr);
+                                                                  o, l.ok, L);
         else
             tile_body<float, kFormMassInv, 1, false, false, kCoh>(A, inc, l.d, l.g, tid, tv, pt,
-                                                                  o, l.ok, L, nullptr);
+                                                                  o, l.ok, L);
     }
 }
 
 __global__ __launch_bounds__(256) void batch_flow(BatchFlowArgs F)
 {
     __shared__ TileLds<float> L;
-    __shared__ AnnLds al;
     __shared__ uint4 sh[2];
     const int tid = threadIdx.x;
     const unsigned o = blockIdx.x & 7u;
@@ -160,8 +158,7 @@ __global__ __launch_bounds__(256) void batch_flow(BatchFlowArgs F)
     const SegLane l = seg_lane(A, tid);
     bool tv;
     const uint32_t pt = step_tile(A.cells + t0, cnt, blk * (int)A.nc + l.z, l.ok, tv);
-    batch_body<true>(A, inc, F.meta[4 * b + 0], F.meta[4 * b + 1], l, tid, tv, pt, (int)o, L,
-                     al);
+    batch_body<true>(A, inc, F.meta[4 * b + 0], F.meta[4 * b + 1], l, tid, tv, pt, (int)o, L);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's coherent front stores are acknowledged
     __syncthreads();
     if (tid == 0) {
@@ -173,7 +170,6 @@ __global__ __launch_bounds__(256) void batch_flow(BatchFlowArgs F)
 __global__ __launch_bounds__(256) void batch_step(BatchStepArgs S)
 {
     __shared__ TileLds<float> L;
-    __shared__ AnnLds al;
     // problem of this block: prefix[b] <= blockIdx.x < prefix[b + 1]
     int lo = 0, hi = S.nprob;
     const int bid = blockIdx.x;
@@ -192,7 +188,7 @@ __global__ __launch_bounds__(256) void batch_step(BatchStepArgs S)
     const SegLane l = seg_lane(A, tid);
     bool tv;
     const uint32_t pt = step_tile(A.cells, A.ncp, bx * (int)A.nc + l.z, l.ok, tv);
-    batch_body<false>(A, inc, S.meta[4 * b + 0], S.meta[4 * b + 1], l, tid, tv, pt, o, L, al);
+    batch_body<false>(A, inc, S.meta[4 * b + 0], S.meta[4 * b + 1], l, tid, tv, pt, o, L);
     if (S.step == S.meta[4 * b + 2]) {
         __syncthreads();
         if (threadIdx.x == 0) atomicMax(&S.t_end[b], (unsigned long long)wall_clock64());

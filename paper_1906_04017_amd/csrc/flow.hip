@@ -95,17 +95,16 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
     if constexpr (kMom > 0) load_ylm_table(A, (int)o, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, true, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                              (int)o, l.ok, L, nullptr, ytab);
+                                                              (int)o, l.ok, L, ytab);
     flow_finish(F, tid, o, t);
 }
 
 // The matrix-core network under the dataflow schedule: the same unit
-// protocol, and the per-wave operand staging of the network in LDS.
+// protocol.
 template <int B>
 __global__ __launch_bounds__(256) void sweep_flow_ann(PlaneArgs<float> A, FlowArgs F)
 {
     __shared__ TileLds<float> L;
-    __shared__ AnnLds al;
     __shared__ uint4 sh[2];
     const int tid = threadIdx.x;
     const unsigned o = blockIdx.x & 7u;
@@ -120,7 +119,7 @@ __global__ __launch_bounds__(256) void sweep_flow_ann(PlaneArgs<float> A, FlowAr
     const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
     const float inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
     tile_body<float, kFormAnn, B, false, false, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
-                                                      l.ok, L, &al);
+                                                      l.ok, L);
     flow_finish(F, tid, o, t);
 }
 

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
     if constexpr (kMom > 0) load_ylm_table(A, (int)blockIdx.y, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, false, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                               blockIdx.y, l.ok, L, nullptr, ytab);
+                                                               blockIdx.y, l.ok, L, ytab);
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).
@@ -44,14 +44,13 @@ template <int B>
 __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
 {
     __shared__ TileLds<float> L;
-    __shared__ AnnLds al;
     const int tid = threadIdx.x;
     const SegLane l = seg_lane(A, tid);
     bool tvalid;
     const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
     const float inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
     tile_body<float, kFormAnn, B, false, false>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
-                                                l.ok, L, &al);
+                                                l.ok, L);
 }
 
 // phi = sum_o phi_oct[o]; optionally the FP64 SI residual partials, the

@@ -310,16 +310,12 @@ __device__ __forceinline__ uint32_t step_tile(const uint32_t *cells, uint32_t nc
     return tvalid ? cells[ti] : 0u;
 }
 
-// LDS of the tile body: the direction reduction (double buffered), the
-// adjoint contraction reduction, and the ANN operand staging.
+// LDS of the tile body: the direction reduction (double buffered) and the
+// adjoint contraction reduction.
 template <typename Real>
 struct TileLds {
     Real red[2 * 256 * 9];
     Real gred[256 * 2];
-};
-struct AnnLds {
-    __bf16 lin[4 * 64 * 32];
-    float lout[4 * 64 * 8];
 };
 
 // Device body of the tile sweep for one lane.  d, g: direction-in-octant and
@@ -342,7 +338,7 @@ template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kC
           int kMom = 0>
 __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real inc[3], int d,
                                           int g, int tid, bool tvalid, uint32_t pt, int o,
-                                          bool lane_ok, TileLds<Real> &L, AnnLds *al,
+                                          bool lane_ok, TileLds<Real> &L,
                                           const Real *ytab = nullptr)
 {
     static_assert((Form != kFormAnn && Form != kFormAnnPaper) || sizeof(Real) == 4,
@@ -485,8 +481,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
 #pragma unroll
                         for (int e = 0; e < 24; ++e) feat[e] = 0.0f;
                     }
-                    ann_wave(R, feat, al->lin + (tid >> 6) * (64 * 32),
-                             al->lout + (tid >> 6) * (64 * 8), y);
+                    ann_wave(R, feat, y);
 #pragma unroll
                     for (int n = 0; n < 8; ++n) psi[n] = ok ? m * y[n] : 0.0f;
                 } else if constexpr (Form == kFormAnnPaper) {
