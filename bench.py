@@ -358,6 +358,8 @@ def ann_vs_ge(api, ctx, ann_path, pann_path, n=128, reps=3):
     p = inputs.paper_problems(n=n, groups=4, order=8)
     om, w = api.quadrature_ls(8)
     nets = {"ann": api.Ann(ctx, ann_path)}
+    nets["ann_x2"] = api.Ann(ctx, ann_path)   # split-BF16 activations
+    nets["ann_x2"].set_mode("bf16x2")
     if pann_path and os.path.exists(pann_path):
         nets["ann_paper"] = api.Ann(ctx, pann_path)
     S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32, device="cuda")
@@ -471,6 +473,12 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
     import torch
     from paper_1906_04017_amd import inputs
     nets = {"ann": api.Ann(ctx, ann_path)}
+    # the same network with split-BF16 activations: its result is the
+    # network's own to about 2^-16 (the parity tests bound its distance from
+    # the FP64 forward of the artifact), so its eps_P is the network's
+    # (training) error and the BF16 column's excess over it is rounding
+    nets["ann_x2"] = api.Ann(ctx, ann_path)
+    nets["ann_x2"].set_mode("bf16x2")
     if pann_path and os.path.exists(pann_path):
         nets["ann_paper"] = api.Ann(ctx, pann_path)
     solvers = ("ge",) + tuple(nets)
@@ -702,12 +710,31 @@ def uneven_batch(api, ctx, ann_path, count=64):
         f"p50 {np.percentile(lat_other, 50):.0f} us, p99 {np.percentile(lat_other, 99):.0f} us")
     log(f"batch: {count} problems, {solves} solves, {1e3 * dt:.2f} ms per run ({sched}), "
         f"p50 {np.percentile(lat, 50):.0f} us, p99 {np.percentile(lat, 99):.0f} us")
+    # the sequential baseline: the same problems one after another, each
+    # autotuned on its own and swept by its own call (sweep and octant
+    # reduction), back to back on one stream
+    for prob in probs:
+        prob.autotune()
+    for k in range(count):
+        probs[k].sweep(srcs[k], phis[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for k in range(count):
+            probs[k].sweep(srcs[k], phis[k])
+    torch.cuda.synchronize()
+    dt_seq = (time.perf_counter() - t0) / reps
+    log(f"sequential: {1e3 * dt_seq:.2f} ms per run of the {count} problems one by one")
     out = {"problems": count, "solves_per_run": solves, "ms_per_run": 1e3 * dt,
            "solves_per_s": solves / dt, "autotune_best_ms": best_ms,
            "latency_us_p50": float(np.percentile(lat, 50)),
            "latency_us_p99": float(np.percentile(lat, 99)),
            "ann_problems": sum(1 for p in ps if p["solver"] == "ann"),
            "schedule": sched,
+           "sequential": {"ms_per_run": 1e3 * dt_seq, "solves_per_s": solves / dt_seq,
+                          "speedup_of_batch": dt_seq / dt,
+                          "execution": "each problem autotuned alone, then one dgsn_sweep per "
+                                       "problem back to back on one stream"},
            "other_schedule": {"schedule": other, "ms_per_run": 1e3 * dt_other,
                               "latency_us_p50": float(np.percentile(lat_other, 50)),
                               "latency_us_p99": float(np.percentile(lat_other, 99))},

@@ -409,6 +409,25 @@ int dgsn_local_solve(dgsn_ctx *ctx, const void *x, void *psi, long long n, int p
 int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out);
 int dgsn_ann_destroy(dgsn_ann *ann);
 
+/*
+ * Evaluation precision of a version-1 network on the matrix cores (every
+ * sweep and dgsn_ann_infer call that uses it; Sec. 3, Eq. (ANN:Eq1)):
+ *   DGSN_ANN_BF16   (default) features and hidden activations rounded to
+ *                   BF16 (relative 2^-9 each), FP32 accumulation;
+ *   DGSN_ANN_BF16X2 split BF16: each of them enters as hi + lo BF16 parts
+ *                   (hi = bf16(v), lo = bf16(v - hi), together v to about
+ *                   2^-17), one matrix instruction per part, FP32
+ *                   accumulation: the network's result to about FP32 accuracy
+ *                   for weights held exactly in BF16 (as the trainer writes
+ *                   them), at twice the matrix instructions.
+ * The weights are BF16 in both modes.  Batches take BF16 networks only
+ * (DGSN_EUNSUPPORTED at dgsn_batch_run).  DGSN_EINVAL for a version-2
+ * artifact (the paper-form networks run in FP32 on the vector ALUs) with a
+ * mode other than DGSN_ANN_BF16.
+ */
+enum { DGSN_ANN_BF16 = 0, DGSN_ANN_BF16X2 = 1 };
+int dgsn_ann_set_mode(dgsn_ann *ann, int mode);
+
 /* Artifact shape (host out, each pointer may be NULL): version (1 or 2),
    inputs, hidden units, networks (1, or 8 per octant). */
 int dgsn_ann_info(const dgsn_ann *ann, int *version, int *n_in, int *n_hidden, int *n_nets);

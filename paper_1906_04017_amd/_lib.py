@@ -25,6 +25,8 @@ DGSN_GE_DENSE = 2
 DGSN_SI_MAXNORM = 0
 DGSN_SI_EPS_S = 1
 DGSN_SI_FIXED = 2
+DGSN_ANN_BF16 = 0
+DGSN_ANN_BF16X2 = 1
 DGSN_SCHED_PLANES = 0
 DGSN_SCHED_DATAFLOW = 1
 
@@ -81,6 +83,7 @@ SIGNATURES = {
     "dgsn_ann_load": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(_VP)]),
     "dgsn_ann_destroy": (_I, [_VP]),
     "dgsn_ann_infer": (_I, [_VP, _VP, _VP, _LL, _VP]),
+    "dgsn_ann_set_mode": (_I, [_VP, _I]),
     "dgsn_ann_info": (_I, [_VP, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                            ctypes.POINTER(_I)]),
     "dgsn_ann_infer_octant": (_I, [_VP, _I, _VP, _VP, _LL, _VP]),

@@ -101,6 +101,12 @@ class Ann:
     def version(self):
         return self.info()[0]
 
+    def set_mode(self, mode):
+        """'bf16' (default) or 'bf16x2' (split-BF16 activations) for the
+        matrix-core network."""
+        m = {"bf16": _lib.DGSN_ANN_BF16, "bf16x2": _lib.DGSN_ANN_BF16X2}[mode]
+        _lib.check(_lib.load().dgsn_ann_set_mode(self._h, m))
+
     def infer_octant(self, octant, x, out=None):
         """Paper-form network of one octant on raw inputs x [n,26] float32 -> [n,8]."""
         x = x.contiguous()

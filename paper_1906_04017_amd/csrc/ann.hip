@@ -31,6 +31,7 @@ namespace dgsn {
 
 namespace {
 
+template <bool kSplit>
 __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__restrict__ prm,
                                                         const float *__restrict__ x,
                                                         float *__restrict__ y, long long n)
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void ann_infer_kernel(const unsigned char *__r
         float f[24], o[8];
 #pragma unroll
         for (int k = 0; k < 24; ++k) f[k] = s < n ? x[s * 24 + k] : 0.0f;
-        ann_wave(R, f, o);
+        ann_wave<kSplit>(R, f, o);
         if (s < n) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) y[s * 8 + k] = o[k];
@@ -398,6 +399,18 @@ int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float
     return DGSN_OK;
 }
 
+int dgsn_ann_set_mode(dgsn_ann *ann, int mode)
+{
+    clear_error();
+    if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
+    if (mode != DGSN_ANN_BF16 && mode != DGSN_ANN_BF16X2)
+        return set_error(DGSN_EINVAL, "mode must be DGSN_ANN_BF16 or DGSN_ANN_BF16X2");
+    if (ann->version != 1 && mode != DGSN_ANN_BF16)
+        return set_error(DGSN_EINVAL, "the paper-form networks run in FP32 on the vector ALUs");
+    ann->mode = mode;
+    return DGSN_OK;
+}
+
 int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, void *stream)
 {
     clear_error();
@@ -411,9 +424,14 @@ int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, v
     DGSN_HIP(hipSetDevice(ann->ctx->device));
     long long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(ann_infer_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(stream),
-                       static_cast<const unsigned char *>(ann->d_params.ptr), x, y, n);
+    if (ann->mode == DGSN_ANN_BF16X2)
+        hipLaunchKernelGGL(ann_infer_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           reinterpret_cast<hipStream_t>(stream),
+                           static_cast<const unsigned char *>(ann->d_params.ptr), x, y, n);
+    else
+        hipLaunchKernelGGL(ann_infer_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           reinterpret_cast<hipStream_t>(stream),
+                           static_cast<const unsigned char *>(ann->d_params.ptr), x, y, n);
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;
 }

@@ -79,6 +79,21 @@ __device__ __forceinline__ void swap_halves(unsigned &a, unsigned &b)
     b = r[1];
 }
 
+// bf16 pairs of two floats (round to nearest even), and of what the rounding
+// left: hi = bf16(v), lo = bf16(v - hi), so that hi + lo carries v to about
+// 2^-17 relative
+__device__ __forceinline__ unsigned bf16_pair(float a, float b)
+{
+    const f32x2 pr = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+}
+__device__ __forceinline__ void bf16_split_pair(float a, float b, unsigned &hi, unsigned &lo)
+{
+    hi = bf16_pair(a, b);
+    const bf16x2 h = __builtin_bit_cast(bf16x2, hi);
+    lo = bf16_pair(a - (float)h[0], b - (float)h[1]);
+}
+
 // Evaluates the network for the 64 samples held by the 64 lanes of the wave
 // (one sample per lane, 24 FP32 features), with no LDS traffic.  The
 // samples of lanes 0..31 form batch 0 and those of lanes 32..63 batch 1; a
@@ -89,11 +104,17 @@ __device__ __forceinline__ void swap_halves(unsigned &a, unsigned &b)
 // tiles of 32 hidden units, two K-steps of 16 features); its output
 // registers, after ReLU and the rounding to bf16, are the B operand of
 // layer 2, Y^T = W2' relu(H^T) (four K-steps of 16 hidden units, W2' the
-// column order hid(kc, h, e) above).  Must be reached by every lane.
+// column order hid(kc, h, e) above).  kSplit: the features and the hidden
+// activations enter as bf16 hi + lo pairs, each part through its own matrix
+// instruction against the (bf16) weights, which removes their 2^-9 rounding
+// and leaves about 2^-17 (twice the matrix instructions).  Must be reached
+// by every lane.
+template <bool kSplit = false>
 __device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24], float out[8])
 {
+    constexpr int NP = kSplit ? 2 : 1;   // parts of each activation
     // the lane's 32 padded features as bf16 pairs: chunk q holds 8q .. 8q+7
-    unsigned c[4][4];
+    unsigned c[NP][4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -104,45 +125,73 @@ __device__ __forceinline__ void ann_wave(const AnnRegs &R, const float feat[24],
                 const int f = 8 * q + 2 * p + k;
                 v[k] = f < 24 ? feat[f] : (f == kFeatBiasHi || f == kFeatBiasLo ? 1.0f : 0.0f);
             }
-            const f32x2 pr = {v[0], v[1]};
-            c[q][p] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+            if constexpr (kSplit) bf16_split_pair(v[0], v[1], c[0][q][p], c[NP - 1][q][p]);
+            else c[0][q][p] = bf16_pair(v[0], v[1]);
         }
     // K-step kk of batch bt needs chunk 2kk + h of the batch's samples in
     // lane half h: after the exchange c[2kk + bt] is that operand
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        swap_halves(c[0][p], c[1][p]);
-        swap_halves(c[2][p], c[3][p]);
-    }
+    for (int part = 0; part < NP; ++part)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            swap_halves(c[part][0][p], c[part][1][p]);
+            swap_halves(c[part][2][p], c[part][3][p]);
+        }
     unsigned y[2][4];
 #pragma unroll
     for (int bt = 0; bt < 2; ++bt) {
-        const u32x4 u0 = {c[bt][0], c[bt][1], c[bt][2], c[bt][3]};
-        const u32x4 u1 = {c[2 + bt][0], c[2 + bt][1], c[2 + bt][2], c[2 + bt][3]};
-        const bf16x8 x0 = __builtin_bit_cast(bf16x8, u0);
-        const bf16x8 x1 = __builtin_bit_cast(bf16x8, u1);
+        bf16x8 x0[NP], x1[NP];
+#pragma unroll
+        for (int part = 0; part < NP; ++part) {
+            const unsigned *a0 = c[part][bt], *a1 = c[part][2 + bt];
+            const u32x4 u0 = {a0[0], a0[1], a0[2], a0[3]};
+            const u32x4 u1 = {a1[0], a1[1], a1[2], a1[3]};
+            x0[part] = __builtin_bit_cast(bf16x8, u0);
+            x1[part] = __builtin_bit_cast(bf16x8, u1);
+        }
         f32x16 acc = (f32x16)0.0f;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            f32x16 h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t], x0, (f32x16)0.0f, 0,
-                                                               0, 0);
-            h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t + 1], x1, h, 0, 0, 0);
-            // ReLU after the rounding to bf16, on the packed pairs: bf16 is
-            // sign and magnitude, so as 16-bit integers every negative value
-            // (and -0) is below zero and max(x, 0) is the ReLU, equal to
-            // rounding the ReLU of the FP32 value
+            f32x16 h = (f32x16)0.0f;
+#pragma unroll
+            for (int part = 0; part < NP; ++part) {
+                h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t], x0[part], h, 0, 0, 0);
+                h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w1[2 * t + 1], x1[part], h, 0, 0,
+                                                            0);
+            }
 #pragma unroll
             for (int pp = 0; pp < 2; ++pp) {
-                u32x4 tq;
+                bf16x8 hb[NP];
+                if constexpr (kSplit) {
+                    // ReLU in FP32, then the hi + lo parts
+                    u32x4 th, tl;
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const f32x2 pr = {h[8 * pp + 2 * p], h[8 * pp + 2 * p + 1]};
-                    tq[p] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+                    for (int p = 0; p < 4; ++p) {
+                        unsigned a, b;
+                        bf16_split_pair(fmaxf(h[8 * pp + 2 * p], 0.0f),
+                                        fmaxf(h[8 * pp + 2 * p + 1], 0.0f), a, b);
+                        th[p] = a;
+                        tl[p] = b;
+                    }
+                    hb[0] = __builtin_bit_cast(bf16x8, th);
+                    hb[NP - 1] = __builtin_bit_cast(bf16x8, tl);
+                } else {
+                    // ReLU after the rounding to bf16, on the packed pairs: bf16
+                    // is sign and magnitude, so as 16-bit integers every
+                    // negative value (and -0) is below zero and max(x, 0) is
+                    // the ReLU, equal to rounding the ReLU of the FP32 value
+                    u32x4 tq;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        tq[p] = bf16_pair(h[8 * pp + 2 * p], h[8 * pp + 2 * p + 1]);
+                    const i16x8 r =
+                        __builtin_elementwise_max(__builtin_bit_cast(i16x8, tq), (i16x8)0);
+                    hb[0] = __builtin_bit_cast(bf16x8, r);
                 }
-                const i16x8 r = __builtin_elementwise_max(__builtin_bit_cast(i16x8, tq), (i16x8)0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[2 * t + pp],
-                                                              __builtin_bit_cast(bf16x8, r), acc,
-                                                              0, 0, 0);
+#pragma unroll
+                for (int part = 0; part < NP; ++part)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.w2[2 * t + pp], hb[part], acc,
+                                                                  0, 0, 0);
             }
         }
         // rows 0..3 of lane half h are outputs 4h .. 4h+3 of the column's sample

@@ -460,6 +460,9 @@ int batch_validate(dgsn_batch *B)
                              "solvers (problem %zu)", b);
         if (p->solver == DGSN_ANN && !p->ann)
             return set_error(DGSN_EINVAL, "problem %zu uses the ANN solver without an ANN", b);
+        if (p->solver == DGSN_ANN && p->ann->mode != DGSN_ANN_BF16)
+            return set_error(DGSN_EUNSUPPORTED, "batched execution evaluates the networks in "
+                             "BF16 (problem %zu uses split BF16)", b);
         if (B->cfg_gen.size() != B->probs.size() || B->cfg_gen[b] != p->cfg_gen) B->dirty = true;
     }
     return DGSN_OK;

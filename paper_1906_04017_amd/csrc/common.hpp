@@ -98,6 +98,7 @@ struct dgsn_ctx {
 struct dgsn_ann {
     dgsn_ctx *ctx = nullptr;
     int version = 1;                     // 1: canonical 24-input net, 2: paper-form per octant
+    int mode = DGSN_ANN_BF16;            // version 1: evaluation precision on the matrix cores
     int n_in = 24, n_hidden = 0, n_out = 8, act = 0, n_nets = 1;
     float alpha = 0.0f, beta_scale = 0.0f;   // version 2: Eq. (ANN:Eq2) and (ANN:Eq4)
     std::vector<float> imin, imax;       // version 2: input bounds [26]

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
 
 // The matrix-core network under the dataflow schedule: the same unit
 // protocol.
-template <int B>
+template <int B, int Form>
 __global__ __launch_bounds__(256) void sweep_flow_ann(PlaneArgs<float> A, FlowArgs F)
 {
     __shared__ TileLds<float> L;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void sweep_flow_ann(PlaneArgs<float> A, FlowAr
     bool tvalid;
     const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
     const float inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
-    tile_body<float, kFormAnn, B, false, false, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
+    tile_body<float, Form, B, false, false, true>(A, inc, l.d, l.g, tid, tvalid, pt, (int)o,
                                                       l.ok, L);
     flow_finish(F, tid, o, t);
 }
@@ -186,13 +186,14 @@ void launch_flow_b(const PlaneArgs<Real> &A, const FlowArgs &F, int b, bool stor
 }
 
 // The matrix-core network: FP32 forward sweeps only.
+template <int Form>
 void launch_flow_ann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 grid, dim3 block,
                      hipStream_t s)
 {
     switch (b) {
-    case 3: hipLaunchKernelGGL(sweep_flow_ann<3>, grid, block, 0, s, A, F); break;
-    case 2: hipLaunchKernelGGL(sweep_flow_ann<2>, grid, block, 0, s, A, F); break;
-    default: hipLaunchKernelGGL(sweep_flow_ann<1>, grid, block, 0, s, A, F); break;
+    case 3: hipLaunchKernelGGL((sweep_flow_ann<3, Form>), grid, block, 0, s, A, F); break;
+    case 2: hipLaunchKernelGGL((sweep_flow_ann<2, Form>), grid, block, 0, s, A, F); break;
+    default: hipLaunchKernelGGL((sweep_flow_ann<1, Form>), grid, block, 0, s, A, F); break;
     }
 }
 
@@ -223,9 +224,10 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
                 bool adjoint, hipStream_t s)
 {
     const dim3 block(256);
-    if ((form == kFormAnnPaper || form == kFormAnn) && (sizeof(Real) != 4 || store_psi || adjoint))
+    const bool net = form == kFormAnn || form == kFormAnnSplit;
+    if ((form == kFormAnnPaper || net) && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the network solvers run FP32 forward sweeps");
-    if (A.nmom > 1 && (form == kFormAnnPaper || form == kFormAnn ||
+    if (A.nmom > 1 && (form == kFormAnnPaper || net ||
                        (form == kFormDense && (store_psi || adjoint))))
         return set_error(DGSN_EUNSUPPORTED, "anisotropic sweeps run the GE solvers (the psi "
                          "store and the adjoint with the mass-inverse form)");
@@ -239,7 +241,10 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
         } else if (form == kFormAnnPaper) {
             if constexpr (sizeof(Real) == 4) launch_flow_pann(A, F, b, grid, block, s);
         } else if (form == kFormAnn) {
-            if constexpr (sizeof(Real) == 4) launch_flow_ann(A, F, b, grid, block, s);
+            if constexpr (sizeof(Real) == 4) launch_flow_ann<kFormAnn>(A, F, b, grid, block, s);
+        } else if (form == kFormAnnSplit) {
+            if constexpr (sizeof(Real) == 4)
+                launch_flow_ann<kFormAnnSplit>(A, F, b, grid, block, s);
         } else {
             launch_flow_b<Real, kFormMassInv>(A, F, b, store_psi, adjoint, grid, block, s);
         }

@@ -129,6 +129,7 @@ constexpr int kFormMassInv = 0;   // mass-inverse form, structured elimination
 constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense elimination
 constexpr int kFormAnn = 2;       // the shallow network in place of assembly + elimination
 constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector ALUs)
+constexpr int kFormAnnSplit = 4;  // the shallow network with split-BF16 activations
 
 // Occupancy request of a sweep kernel (waves per SIMD; 1 = no request).  The
 // FP64 single-cell mass-inverse kernel would take 176 registers and run at 2
@@ -142,7 +143,7 @@ constexpr int kMinWavesPerSimd =
     (sizeof(Real) == 8 && Form == kFormMassInv && kMom == 0) ? (B == 1 ? 3 : (B == 2 ? 2 : 1))
                                                            : 1;
 
-int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s);
+int launch_tile_ann(const PlaneArgs<float> &A, int b, bool split, hipStream_t s);
 
 template <typename Real>
 int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool adjoint,

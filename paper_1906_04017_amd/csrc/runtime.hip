@@ -388,8 +388,9 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const bool ann = anyann && !paper;
     if (ann) A.ann_params = ann_device_params(p->ann);
     if (paper) A.ann_params = p->d_pann.ptr;
+    const bool split = ann && p->ann->mode == DGSN_ANN_BF16X2;
     const int form = paper ? kFormAnnPaper
-                           : ann ? kFormAnn
+                           : ann ? (split ? kFormAnnSplit : kFormAnn)
                                  : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
     // anisotropic sweeps use tiles of edge 2 at most (larger tiles spill)
     const int tb = (A.nmom > 1 && p->tile_b > 2) ? 2 : p->tile_b;
@@ -428,7 +429,7 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
         bool done = false;
         if constexpr (sizeof(Real) == 4) {
             if (ann) {
-                DGSN_TRY(launch_tile_ann(A, tb, s));
+                DGSN_TRY(launch_tile_ann(A, tb, split, s));
                 done = true;
             }
         }

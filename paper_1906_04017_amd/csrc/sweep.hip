@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).
-template <int B>
+template <int B, int Form>
 __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
 {
     __shared__ TileLds<float> L;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void sweep_tile_ann(PlaneArgs<float> A)
     bool tvalid;
     const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
     const float inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
-    tile_body<float, kFormAnn, B, false, false>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
+    tile_body<float, Form, B, false, false>(A, inc, l.d, l.g, tid, tvalid, pt, blockIdx.y,
                                                 l.ok, L);
 }
 
@@ -508,13 +508,21 @@ void launch_tile_b(const PlaneArgs<Real> &A, int b, bool store_psi, bool adjoint
     }
 }
 
-int launch_tile_ann(const PlaneArgs<float> &A, int b, hipStream_t s)
+int launch_tile_ann(const PlaneArgs<float> &A, int b, bool split, hipStream_t s)
 {
     const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
-    switch (b) {
-    case 3: hipLaunchKernelGGL(sweep_tile_ann<3>, grid, dim3(256), 0, s, A); break;
-    case 2: hipLaunchKernelGGL(sweep_tile_ann<2>, grid, dim3(256), 0, s, A); break;
-    default: hipLaunchKernelGGL(sweep_tile_ann<1>, grid, dim3(256), 0, s, A); break;
+    if (split) {
+        switch (b) {
+        case 3: hipLaunchKernelGGL((sweep_tile_ann<3, kFormAnnSplit>), grid, dim3(256), 0, s, A); break;
+        case 2: hipLaunchKernelGGL((sweep_tile_ann<2, kFormAnnSplit>), grid, dim3(256), 0, s, A); break;
+        default: hipLaunchKernelGGL((sweep_tile_ann<1, kFormAnnSplit>), grid, dim3(256), 0, s, A); break;
+        }
+    } else {
+        switch (b) {
+        case 3: hipLaunchKernelGGL((sweep_tile_ann<3, kFormAnn>), grid, dim3(256), 0, s, A); break;
+        case 2: hipLaunchKernelGGL((sweep_tile_ann<2, kFormAnn>), grid, dim3(256), 0, s, A); break;
+        default: hipLaunchKernelGGL((sweep_tile_ann<1, kFormAnn>), grid, dim3(256), 0, s, A); break;
+        }
     }
     DGSN_HIP(hipGetLastError());
     return DGSN_OK;

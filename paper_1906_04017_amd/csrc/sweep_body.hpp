@@ -341,7 +341,8 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                                           bool lane_ok, TileLds<Real> &L,
                                           const Real *ytab = nullptr)
 {
-    static_assert((Form != kFormAnn && Form != kFormAnnPaper) || sizeof(Real) == 4,
+    constexpr bool kNet = Form == kFormAnn || Form == kFormAnnSplit;   // matrix-core network
+    static_assert((!kNet && Form != kFormAnnPaper) || sizeof(Real) == 4,
                   "the ANN solvers run in FP32");
     const int mask = kAdjoint ? (o ^ 7) : o;
     const uint32_t dg = d + A.Do * g;
@@ -352,7 +353,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     // cell: cheaper than holding kMom more registers)
     const Real *yl = kMom > 0 ? ytab + (lane_ok ? d : 0) * kYlmStride : nullptr;
     AnnRegs R;
-    if (Form == kFormAnn) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
+    if (kNet) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
     uint32_t I0 = 0, J0 = 0, K0 = 0;
     if (tvalid) {
         I0 = (pt & 1023u) * B;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     // cell ahead.  The dense, paper-form network and FP64 kernels would lose
     // a wave per SIMD to the 9 (18) registers, and anisotropic sweeps load
     // their moment sources per cell.
-    constexpr bool kPrefetch = sizeof(Real) == 4 && (Form == kFormMassInv || Form == kFormAnn) &&
+    constexpr bool kPrefetch = sizeof(Real) == 4 && (Form == kFormMassInv || kNet) &&
                                kMom == 0;
     const uint32_t gbase = g * A.ncell;
     auto cell_ok = [&](int il2, int jl2, int kl2) {
@@ -472,7 +473,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     }
                 }
                 // local solve
-                if constexpr (Form == kFormAnn) {
+                if constexpr (kNet) {
                     float feat[24], y[8];
                     float m = 0.0f;
                     if (ok) {
@@ -481,7 +482,7 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
 #pragma unroll
                         for (int e = 0; e < 24; ++e) feat[e] = 0.0f;
                     }
-                    ann_wave(R, feat, y);
+                    ann_wave<Form == kFormAnnSplit>(R, feat, y);
 #pragma unroll
                     for (int n = 0; n < 8; ++n) psi[n] = ok ? m * y[n] : 0.0f;
                 } else if constexpr (Form == kFormAnnPaper) {

@@ -195,6 +195,13 @@ def test_trained_network_sweep_at_full_size(api, ctx):
     assert rel(phi, ref) <= 8 * 2.0 ** -8
     avg, avg_ref = phi.mean(-1), ref.mean(-1)
     assert np.mean(np.abs(avg - avg_ref) / np.abs(avg_ref)) <= 2 * 2.0 ** -8
+    # split BF16: the same derivation with 4 * 2^-18 per activation in place
+    # of 2^-8 (the trained weights are BF16-exact)
+    ann.set_mode("bf16x2")
+    phi2 = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    assert rel(phi2, ref) <= 32 * 2.0 ** -18, rel(phi2, ref)
+    avg2 = phi2.mean(-1)
+    assert np.mean(np.abs(avg2 - avg_ref) / np.abs(avg_ref)) <= 8 * 2.0 ** -18
     ann.close()
 
 

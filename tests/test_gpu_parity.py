@@ -1239,3 +1239,100 @@ def test_transport_solve_autograd(api, ctx, precision, tol):
     direct = p["box_mask"][None, :] * ref["phi"].sum(-1) * (V / 8)
     assert rel(st.grad.cpu().numpy(), a["grad_sigma_t"] + direct) <= tol
     assert rel(q.grad.cpu().numpy(), a["grad_q"]) <= tol
+
+
+# ---------------------------------------------------------------------------
+# split-BF16 evaluation of the matrix-core network
+# ---------------------------------------------------------------------------
+
+def _bf16_exact(a):
+    """a rounded to the nearest BF16 value (ties to even), as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("nh", [64, 40])
+def test_ann_infer_split_bf16_within_bound(api, ctx, tmp_path, nh):
+    # weights held exactly in BF16 (as the trainer writes them): the split
+    # mode carries every feature and hidden activation as hi + lo to 2^-18
+    # relative (hi = bf16(v) to 2^-9, lo = bf16(v - hi) to 2^-9 of the rest),
+    # the bias likewise, products are exact in FP32 and the K <= 64 FP32 sums
+    # add at most 64 * 2^-24 relative to the absolute sums: 4 * 2^-18 covers
+    # both for each layer
+    print_case("ann_infer_split", nh=nh)
+    net = {k: _bf16_exact(v) for k, v in _random_net(310 + nh, nh).items()}
+    ann = api.Ann(ctx, _write_net(tmp_path, net, f"s{nh}.dgsnann"))
+    ann.set_mode("bf16x2")
+    rng = np.random.default_rng(8)
+    n = 1000 + 41
+    x = rng.uniform(-1, 1, size=(n, 24)).astype(np.float32)
+    y = ann.infer(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    W1, b1, W2, b2 = (net[k].astype(np.float64) for k in ("W1", "b1", "W2", "b2"))
+    xd = x.astype(np.float64)
+    ref = np.stack([oracle.ann_forward(net, xi) for xi in xd])
+    hid = np.maximum(xd @ W1.T + b1, 0)
+    u = 4 * 2.0 ** -18
+    dh = u * (np.abs(xd) @ np.abs(W1).T + np.abs(b1))
+    bound = u * (np.abs(hid) @ np.abs(W2).T + np.abs(b2)) + (dh @ np.abs(W2).T)
+    err = np.abs(y - ref)
+    assert np.all(err <= bound + 2.0 ** -22 * np.abs(ref))
+    # and well below the BF16 mode's error on the same inputs
+    ann.set_mode("bf16")
+    y16 = ann.infer(torch.tensor(x, device="cuda")).cpu().numpy().astype(np.float64)
+    assert err.max() < np.abs(y16 - ref).max() / 50
+    ann.close()
+
+
+def test_ann_split_mode_rules(api, ctx, tmp_path):
+    print_case("ann_split_rules")
+    pann = api.Ann(ctx, _write_pann(tmp_path, _random_pann(91), "rules_p.dgsnann")[0])
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        pann.set_mode("bf16x2")
+    pann.set_mode("bf16")
+    ann = api.Ann(ctx, _write_net(tmp_path, _random_net(92), "rules.dgsnann"))
+    ann.set_mode("bf16x2")
+    p = inputs.random_problem((4, 3, 3), 4, 1, seed=93)
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    S = torch.tensor(nodal_source(p), dtype=torch.float32, device="cuda")
+    batch = api.Batch(ctx, [prob])
+    batch.set_io(0, S, torch.empty_like(S))
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED"):
+        batch.run()
+    ann.set_mode("bf16")
+    batch.run()
+    torch.cuda.synchronize()
+    batch.close()
+    prob.close()
+
+
+@pytest.mark.parametrize("schedule", ["planes", "dataflow"])
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_ann_split_sweep_matches_fp64_forward(api, ctx, tmp_path, tile, schedule):
+    # a BF16-exact network in a whole sweep (ragged mesh, S6, 2 groups)
+    # against the oracle's FP64 forward of the same artifact in the same
+    # sweep: the per-cell network error (about 2^-16 of its output) carried
+    # downstream; the BF16 mode on the same sweep is far off in comparison
+    net = {k: _bf16_exact(v) for k, v in _random_net(95, 64).items()}
+    net["W2"] = _bf16_exact(net["W2"] * 0.25)   # a contracting network
+    ann = api.Ann(ctx, _write_net(tmp_path, net, "split_sweep.dgsnann"))
+    ann.set_mode("bf16x2")
+    p = inputs.random_problem((7, 5, 6), 6, 2, seed=96, length=(0.7, 0.5, 0.6))
+    print_case("ann_split_sweep", name=p["name"], tile=tile, schedule=schedule)
+    prob = gpu_problem(api, ctx, p, "fp32", solver="ann")
+    prob.set_ann(ann)
+    prob.set_tile(tile)
+    prob.set_schedule(schedule)
+    S = nodal_source(p, seed=97)
+    St = torch.tensor(S, dtype=torch.float32, device="cuda")
+    phi = prob.sweep(St).cpu().numpy()
+    om, w = oracle.lq_n(6)
+    ref = oracle.ann_sweep(net, mesh_of(p), om, w, p["sigma_t"], S, p["psi_inc"])
+    e_split = rel(phi, ref)
+    assert e_split <= 32 * 2.0 ** -18, e_split
+    ann.set_mode("bf16")
+    e16 = rel(prob.sweep(St).cpu().numpy(), ref)
+    assert e_split < e16 / 20, (e_split, e16)
+    prob.close()
+    ann.close()
