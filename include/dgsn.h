@@ -470,7 +470,9 @@ int dgsn_ann_infer(const dgsn_ann *ann, const float *x, float *y, long long n, v
  * nodes); sums are in FP64 over the problem-precision values.
  * dgsn_problem_balance synchronizes stream after a dgsn_sweep and returns
  * DGSN_EINVAL when no tallied sweep has run since the tally was enabled.
- * Cost: the boundary outflow stores and a pass over the fronts per sweep.
+ * Cost: the boundary outflow stores and a pass over the fronts per sweep; on
+ * a mesh that the tile edge does not divide, a tallied sweep runs single
+ * cells (same results, every tiling does the same cell arithmetic).
  */
 int dgsn_problem_set_balance(dgsn_problem *p, int enable);
 int dgsn_problem_balance(dgsn_problem *p, double terms[5], void *stream);

@@ -121,7 +121,9 @@ __device__ __forceinline__ void batch_body(const PlaneArgs<float> &A, const floa
     }
 }
 
-__global__ __launch_bounds__(256) void batch_flow(BatchFlowArgs F)
+// held to 3 waves per SIMD (168 registers): the tile bodies of all solvers
+// together would take 171 and fall to 2
+__global__ __launch_bounds__(256, 3) void batch_flow(BatchFlowArgs F)
 {
     __shared__ TileLds<float> L;
     __shared__ uint4 sh[2];

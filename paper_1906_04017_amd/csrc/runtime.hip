@@ -393,7 +393,12 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
                            : ann ? (split ? kFormAnnSplit : kFormAnn)
                                  : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
     // anisotropic sweeps use tiles of edge 2 at most (larger tiles spill)
-    const int tb = (A.nmom > 1 && p->tile_b > 2) ? 2 : p->tile_b;
+    int tb = (A.nmom > 1 && p->tile_b > 2) ? 2 : p->tile_b;
+    // the balance tally reads each row's boundary outflow from the fronts,
+    // which only a tile's last cell writes: on a mesh that the tile edge
+    // does not divide, the tallied sweep runs single cells (the cell
+    // arithmetic is the same for every tiling)
+    if (A.keep_out && tb > 1 && (p->n[0] % tb || p->n[1] % tb || p->n[2] % tb)) tb = 1;
     const bool tiled = tb > 1;
     const uint32_t *cells = static_cast<const uint32_t *>(tiled ? p->d_tiles[tb].ptr
                                                                : p->d_plane_cells.ptr);

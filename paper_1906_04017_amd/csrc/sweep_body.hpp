@@ -530,14 +530,16 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
                     zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
                     zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
-                    // a tile's last cell hands its outflow downstream; a cell on
-                    // the domain boundary has no downstream cell and stores it
-                    // only for the balance tally (keep_out)
-                    if (ic + 1 < A.nx ? il == B - 1 : A.keep_out != 0u)
+                    // a tile's last cell hands its outflow downstream; on the
+                    // domain boundary there is no downstream cell, and the
+                    // outflow is stored only for the balance tally (keep_out;
+                    // the run uses whole tiles then, so the boundary cell is a
+                    // tile's last)
+                    if (il == B - 1 && (ic + 1 < A.nx || A.keep_out))
                         front_store<Real, kCoh>(A.fx, rx, ex, psi[1], psi[3], psi[5], psi[7]);
-                    if (jc + 1 < A.ny ? jl == B - 1 : A.keep_out != 0u)
+                    if (jl == B - 1 && (jc + 1 < A.ny || A.keep_out))
                         front_store<Real, kCoh>(A.fy, ry, ey, psi[2], psi[3], psi[6], psi[7]);
-                    if (kc + 1 < A.nz ? kl == B - 1 : A.keep_out != 0u)
+                    if (kl == B - 1 && (kc + 1 < A.nz || A.keep_out))
                         front_store<Real, kCoh>(A.fz, rz, ez, psi[4], psi[5], psi[6], psi[7]);
                     if (kStorePsi || (kAdjoint && A.grad_oct)) {
                         Real *pp = A.psi + ((size_t)slot * A.ncell + c) * 8;
