@@ -535,7 +535,15 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
         for sv in nets:
             e4 = ((si[sv][0] - si["ge"][0]).abs() / (si["ge"][0].abs() + 1e-8)).mean().item()
             row[f"{sv}_eps_p_percent_p4"] = round(100 * e4, 3)
+        if order == 8:
+            row.update(per_direction_leg(api, ctx, n, avg["ge"], si["ge"][0], reps))
         log(f"paper tables {n}^3 S{order}: " + json.dumps(row))
+        rows.append(row)
+    # the per-direction networks also at the 128^3 cells of the network benchmark
+    row = {"cells": "128^3", "order": "S8", "directions": 80}
+    row.update(per_direction_leg(api, ctx, 128, None, None, reps))
+    if len(row) > 3:
+        log("paper tables 128^3 S8 (per-direction networks): " + json.dumps(row))
         rows.append(row)
     for a in nets.values():
         a.close()
@@ -548,6 +556,86 @@ def paper_tables(api, ctx, ann_path, pann_path, reps=3):
                               "237/110 at 100^3 S2-S8 and 15/9, 42/20, 121/58 at 10^3, 25^3, "
                               "50^3 S8; effective spectral radius 0.957 (GE) / 0.859 (ANN); "
                               "overall acceleration on Problem 4 about 12")}
+
+
+def per_direction_artifact(sigma_t, n, length=10.0, ranges=""):
+    """Path of the shipped per-direction paper-form networks trained at
+    sigma_t and the cell edge length / n (ranges: the suffix of networks
+    trained on other inflow / source ranges), or None."""
+    s = {10.0: "10", 0.001: "0.001"}.get(float(sigma_t))
+    h = {100: "0.1", 128: "0.078125"}.get(int(n)) if length == 10.0 else None
+    if s is None or h is None:
+        return None
+    path = os.path.join(ROOT, "paper_1906_04017_amd", "data",
+                        f"ann_paper_dir_s8_sigma{s}_h{h}{ranges}.dgsnann")
+    return path if os.path.exists(path) else None
+
+
+def per_direction_leg(api, ctx, n, ge_avg, ge_p4, reps):
+    """The paper-form networks held per quadrature direction, each Problem
+    with the artifact trained at its sigma_t and cell size (S8): per Problem
+    1-3 the time of one sweep (each Problem its own one-group problem) and
+    eps_P against GE; Problem 4 the eps_S source iterations and eps_P of the
+    converged flux.  ge_avg / ge_p4: GE cell averages from the caller (None:
+    computed here with FP32 GE)."""
+    import torch
+    from paper_1906_04017_amd import inputs
+    p = inputs.paper_problems(n=n, groups=4, order=8)
+    paths = [per_direction_artifact(p["sigma_t"][g][0], n) for g in range(3)]
+    # Problem 4's converged flux reaches 4 pi q / (sigma_t - sigma_s) = 126
+    # (psi up to 10, sources up to 100): its networks are trained on those
+    # ranges
+    paths.append(per_direction_artifact(p["sigma_t"][3][0], n, ranges="_psi12_s120"))
+    if any(x is None for x in paths):
+        return {}
+    om, w = api.quadrature_ls(8)
+    out = {"ann_paper_dir_artifacts": [os.path.basename(x) for x in paths]}
+    eps, ms = [], []
+    for g in range(3):
+        sl = slice(g, g + 1)
+        S = torch.tensor(np.repeat(p["q"][sl][..., None], 8, axis=-1), dtype=torch.float32,
+                         device="cuda")
+        res = {}
+        for sv in ("ge", "ann") if ge_avg is None else ("ann",):
+            prob = api.Problem(ctx, p["n"], p["length"], 1, om, w, precision="fp32", solver=sv)
+            prob.set_materials(p["sigma_t"][sl], p["sigma_s"][sl], p["q"][sl])
+            prob.set_inflow(p["psi_inc"])
+            if sv == "ann":
+                ann = api.Ann(ctx, paths[g])
+                prob.set_ann(ann)
+            prob.autotune()
+            dt, phi = time_sweeps(prob, S, reps)
+            res[sv] = phi.double().mean(-1)[0]
+            if sv == "ann":
+                ms.append(round(dt * 1e3, 4))
+                ann.close()
+            prob.close()
+        ge = res["ge"] if ge_avg is None else ge_avg[g]
+        eps.append(round(100 * float(((res["ann"] - ge).abs() / (ge.abs() + 1e-8)).mean()), 3))
+    out["ann_paper_dir_eps_p_percent_p123"] = eps
+    out["ann_paper_dir_ms_per_sweep_p123"] = ms
+    g = 3
+    sl = slice(g, g + 1)
+    res = {}
+    for sv in ("ge", "ann") if ge_p4 is None else ("ann",):
+        prob = api.Problem(ctx, p["n"], p["length"], 1, om, w, precision="fp32", solver=sv)
+        prob.set_materials(p["sigma_t"][sl], p["sigma_s"][sl], p["q"][sl])
+        prob.set_inflow(p["psi_inc"])
+        if sv == "ann":
+            ann = api.Ann(ctx, paths[g])
+            prob.set_ann(ann)
+        prob.autotune()
+        prob.set_si_criterion("eps_s")
+        phi, info = prob.source_iterate(tol=1e-4, max_iter=3000, allow_notconv=True)
+        res[sv] = (phi.double().mean(-1), info["iters"])
+        if sv == "ann":
+            ann.close()
+        prob.close()
+    ge4 = res["ge"][0] if ge_p4 is None else ge_p4
+    out["ann_paper_dir_p4_si_iterations"] = res["ann"][1]
+    out["ann_paper_dir_eps_p_percent_p4"] = round(
+        100 * float(((res["ann"][0] - ge4).abs() / (ge4.abs() + 1e-8)).mean()), 3)
+    return out
 
 
 def anisotropic_steps(api, ctx, p, iters=10):

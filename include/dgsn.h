@@ -68,8 +68,10 @@ enum { DGSN_FP32 = 0, DGSN_FP64 = 1 };
  *   DGSN_ANN       the shallow network of Sec. 3 in place of assembly + GE:
  *                  with a version-1 artifact the 24-input canonical network on
  *                  the BF16 matrix cores, with a version-2 artifact the
- *                  paper-form per-octant network (26 inputs, tanh hidden
- *                  layer, ELU output) on the vector ALUs.
+ *                  paper-form per-octant networks (26 inputs, tanh hidden
+ *                  layer, ELU output) on the vector ALUs, with a version-3
+ *                  artifact the paper-form networks of each quadrature
+ *                  direction (same form, one per direction).
  *   DGSN_GE_DENSE  the cell matrix and right-hand side assembled as in Sec. 2
  *                  (streaming, sigma_t times mass, upwind face terms) and
  *                  solved by dense Gaussian elimination.
@@ -229,9 +231,12 @@ int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
 
 /* Attach an ANN (required before sweeping with solver = DGSN_ANN).  The
    problem keeps a reference; the ANN must outlive its use by the problem.
-   A paper-form (version-2) network is folded for this problem's cell sizes
-   here (a small device buffer owned by the problem; DGSN_ENOMEM if it cannot
-   be allocated, and then no network is attached). */
+   A paper-form (version-2 or -3) network is folded for this problem's cell
+   sizes here (a small device buffer owned by the problem; DGSN_ENOMEM if it
+   cannot be allocated, and then no network is attached).  With a version-3
+   artifact each direction of the problem takes the network whose stored
+   direction equals it (every cosine within 1e-6); DGSN_EINVAL, with the
+   previous network left attached, if some direction has none. */
 int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
 
 /* Select the local solver of subsequent sweeps (DGSN_GE, DGSN_GE_DENSE or
@@ -404,7 +409,15 @@ int dgsn_local_solve(dgsn_ctx *ctx, const void *x, void *psi, long long n, int p
  * as In = (I - alpha (imin + imax) / 2) / |imax - imin| (Eq. (ANN:Eq2)); the
  * outputs are psi = z for z >= 0 and beta (exp(z) - 1) below, with
  * beta = beta_scale * max of the 12 inflow values (Eq. (ANN:Eq4)).
- * Returns DGSN_EFORMAT for a bad magic, shape, size, bound or checksum.
+ *
+ * Version 3 holds paper-form networks of the same form, one per quadrature
+ * direction (the reading of Sec. 4's training paragraph that trains an ANN
+ * for each direction, typically at one problem's sigma_t and cell size): the
+ * version-2 layout with version=3 and n_nets = K (1..4096) directions,
+ * followed after imax by float32 omega[K][3] (unit vectors, no two within
+ * 1e-6), then the K networks in the order of omega.
+ * Returns DGSN_EFORMAT for a bad magic, shape, size, bound, direction or
+ * checksum.
  */
 int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out);
 int dgsn_ann_destroy(dgsn_ann *ann);
@@ -421,22 +434,23 @@ int dgsn_ann_destroy(dgsn_ann *ann);
  *                   for weights held exactly in BF16 (as the trainer writes
  *                   them), at twice the matrix instructions.
  * The weights are BF16 in both modes.  Batches take BF16 networks only
- * (DGSN_EUNSUPPORTED at dgsn_batch_run).  DGSN_EINVAL for a version-2
- * artifact (the paper-form networks run in FP32 on the vector ALUs) with a
- * mode other than DGSN_ANN_BF16.
+ * (DGSN_EUNSUPPORTED at dgsn_batch_run).  DGSN_EINVAL for a version-2 or
+ * -3 artifact (the paper-form networks run in FP32 on the vector ALUs) with
+ * a mode other than DGSN_ANN_BF16.
  */
 enum { DGSN_ANN_BF16 = 0, DGSN_ANN_BF16X2 = 1 };
 int dgsn_ann_set_mode(dgsn_ann *ann, int mode);
 
-/* Artifact shape (host out, each pointer may be NULL): version (1 or 2),
-   inputs, hidden units, networks (1, or 8 per octant). */
+/* Artifact shape (host out, each pointer may be NULL): version (1, 2 or 3),
+   inputs, hidden units, networks (1; 8 per octant; K per direction). */
 int dgsn_ann_info(const dgsn_ann *ann, int *version, int *n_in, int *n_hidden, int *n_nets);
 
 /*
- * Paper-form network of one octant (version-2 artifacts) on raw inputs, on
- * the vector ALUs in FP32: x device float [n][26] in the layout above, y
- * device float [n][8] (physical node order).  DGSN_EINVAL for a version-1
- * artifact or an octant outside 0..7.
+ * Paper-form network `octant` on raw inputs, on the vector ALUs in FP32: for
+ * version-2 artifacts the network of that octant (0..7), for version-3 the
+ * network of the artifact's direction omega[octant] (0..K-1).  x device
+ * float [n][26] in the layout above, y device float [n][8] (physical node
+ * order).  DGSN_EINVAL for a version-1 artifact or an index out of range.
  */
 int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float *y,
                           long long n, void *stream);
@@ -525,7 +539,8 @@ int dgsn_problem_kernel_time(dgsn_problem *p, double *ms_sum, int *launches);
  *   problem's materials are read from its buffers at run time; its inflow,
  *   solver and network are part of the captured graph, which dgsn_batch_run
  *   captures again when any of them changed since (a member set to
- *   DGSN_GE_DENSE, or to DGSN_ANN without a network, is refused).  Two runs
+ *   DGSN_GE_DENSE, or to DGSN_ANN without a network, is refused; so, with
+ *   DGSN_EUNSUPPORTED, is one with split-BF16 or per-direction networks).  Two runs
  *   of one batch must not overlap (they share the device tables).
  * dgsn_batch_set_io: device src / phi of problem `index`, layouts as in
  *   dgsn_sweep; must be set for every problem before the first run.

@@ -72,11 +72,9 @@ def _load():
         [ctypes.c_double, ctypes.c_int, _I, _D, _D, ctypes.c_int]
     lib.orc_pann_octant.argtypes = [_D]
     lib.orc_pann_inputs.argtypes = [_D, _D, ctypes.c_double, _D, _D, _D]
-    lib.orc_pann_forward.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6 + \
-        [ctypes.c_int, _D, _D]
-    lib.orc_pann_cell_batch.argtypes = [ctypes.c_long] + [_D] * 5 + \
-        [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 7
-    _pann = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6
+    _pann = [ctypes.c_int, ctypes.c_double, ctypes.c_double] + [_D] * 6 + [ctypes.c_int, _D]
+    lib.orc_pann_forward.argtypes = _pann + [ctypes.c_int, _D, _D]
+    lib.orc_pann_cell_batch.argtypes = [ctypes.c_long] + [_D] * 5 + _pann + [_D]
     lib.orc_pann_sweep.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
         [ctypes.c_int] * 2 + [_D] * 5 + _pann + [_D, _D, ctypes.c_int]
     lib.orc_pann_source_iterate.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + \
@@ -439,8 +437,10 @@ def ann_source_iterate(net, mesh, omega, weight, sigma_t, sigma_s, q, psi_inc=No
 # ---------------------------------------------------------------------------
 # paper-form per-octant network (Sec. 3, Eq. (ANN:Eq1)-(ANN:Eq4))
 # ---------------------------------------------------------------------------
-# net = dict(kind="paper", W1 [8][nh][26], b1 [8][nh], W2 [8][8][nh], b2 [8][8],
-#            imin [26], imax [26], alpha, beta_scale)
+# net = dict(kind="paper", W1 [K][nh][26], b1 [K][nh], W2 [K][8][nh], b2 [K][8],
+#            imin [26], imax [26], alpha, beta_scale[, omega [K][3]]):
+# K = 8 networks, one per octant, or with omega one network per quadrature
+# direction (net k serves the direction omega[k])
 
 def pann_octant(omega):
     """Octant o = [omega_x < 0] + 2 [omega_y < 0] + 4 [omega_z < 0]."""
@@ -458,20 +458,24 @@ def pann_inputs(h, omega, sigma_t, S, psi_up):
 def _pann_args(net):
     W1 = _f64(net["W1"])
     nh = W1.shape[1]
-    if W1.shape != (8, nh, 26):
-        raise ValueError("paper network W1 must be [8][nh][26]")
+    om = net.get("omega")
+    k = 8 if om is None else _f64(om).shape[0]
+    if W1.shape != (k, nh, 26):
+        raise ValueError(f"paper network W1 must be [{k}][nh][26]")
+    om = np.zeros((1, 3)) if om is None else _f64(om, (k, 3))
     return (nh, float(net["alpha"]), float(net["beta_scale"]), _f64(net["imin"], (26,)),
-            _f64(net["imax"], (26,)), W1, _f64(net["b1"], (8, nh)), _f64(net["W2"], (8, 8, nh)),
-            _f64(net["b2"], (8, 8)))
+            _f64(net["imax"], (26,)), W1, _f64(net["b1"], (k, nh)), _f64(net["W2"], (k, 8, nh)),
+            _f64(net["b2"], (k, 8)), 0 if net.get("omega") is None else k, om)
 
 
 def _pann_ptrs(a):
-    nh, alpha, bs, imin, imax, W1, b1, W2, b2 = a
-    return [nh, alpha, bs] + [_p(x) for x in (imin, imax, W1, b1, W2, b2)]
+    nh, alpha, bs, imin, imax, W1, b1, W2, b2, ndir, om = a
+    return [nh, alpha, bs] + [_p(x) for x in (imin, imax, W1, b1, W2, b2)] + [ndir, _p(om)]
 
 
 def pann_forward(net, octant, I):
-    """FP64 forward pass of octant's network on raw inputs I[26] -> psi[8]."""
+    """FP64 forward pass of net `octant` (the octant's network, or with
+    per-direction networks the direction's index) on raw inputs I[26] -> psi[8]."""
     a = _pann_args(net)
     psi = np.zeros(8)
     rc = _load().orc_pann_forward(*_pann_ptrs(a), int(octant), _p(_f64(I, (26,))), _p(psi))

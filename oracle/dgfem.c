@@ -1334,13 +1334,20 @@ void orc_ann_forward(int nin, int nh, int nout, int act, const double *W1, const
  *   Hidden:     h = tanh(W1 In + b1)                       (Eq. (ANN:Eq1), (ANN:Eq3))
  *   Output:     z = W2 h + b2, psi_t = z_t if z_t >= 0, else beta (exp(z_t) - 1),
  *               beta = beta_scale * max_j I_j over the 12 inflow values (Eq. (ANN:Eq4)).
- * W1 [8][nh][26], b1 [8][nh], W2 [8][8][nh], b2 [8][8]; octant o = [omega_x < 0]
- * + 2 [omega_y < 0] + 4 [omega_z < 0].  Output psi[n] in physical node order.
+ * W1 [K][nh][26], b1 [K][nh], W2 [K][8][nh], b2 [K][8].  One network per
+ * octant (ndir = 0, K = 8): the cell's net is its octant's, o = [omega_x < 0]
+ * + 2 [omega_y < 0] + 4 [omega_z < 0].  One network per quadrature direction
+ * (the reading of Sec. 4's training paragraph that trains an ANN for each
+ * direction; ndir = K > 0): the net k whose stored direction dir_omega[k]
+ * is the cell's direction (every component within 1e-6; the stored
+ * directions are FP32).  Output psi[n] in physical node order.
  */
 struct orc_pann {
     int nh;
     double alpha, beta_scale;
     const double *imin, *imax, *W1, *b1, *W2, *b2;
+    int ndir;                  /* 0: per octant; else the number of per-direction nets */
+    const double *dir_omega;   /* [ndir][3] */
 };
 
 int orc_pann_octant(const double omega[3])
@@ -1367,16 +1374,33 @@ void orc_pann_inputs(const double h[3], const double omega[3], double sigma_t, c
     for (int a = 0; a < 3; ++a) I[23 + a] = h[a];
 }
 
+/* Index of the net that serves direction omega (see above), -1 if none. */
+static int pann_net_index(const struct orc_pann *p, const double omega[3])
+{
+    if (p->ndir == 0) return orc_pann_octant(omega);
+    for (int k = 0; k < p->ndir; ++k) {
+        const double *w = p->dir_omega + 3 * k;
+        if (fabs(w[0] - omega[0]) <= 1e-6 && fabs(w[1] - omega[1]) <= 1e-6 &&
+            fabs(w[2] - omega[2]) <= 1e-6)
+            return k;
+    }
+    return -1;
+}
+
+/* Forward pass of net `index` (an octant, or a direction with ndir > 0). */
 int orc_pann_forward(int nh, double alpha, double beta_scale, const double *imin,
                      const double *imax, const double *W1, const double *b1, const double *W2,
-                     const double *b2, int octant, const double I[26], double psi[8])
+                     const double *b2, int ndir, const double *dir_omega, int index,
+                     const double I[26], double psi[8])
 {
     double In[26], hid[64];
-    if (nh < 1 || nh > 64 || octant < 0 || octant > 7) return ORC_EINVAL;
+    (void)dir_omega;
+    if (nh < 1 || nh > 64 || ndir < 0 || index < 0 || index >= (ndir ? ndir : 8))
+        return ORC_EINVAL;
     for (int j = 0; j < 26; ++j)
         In[j] = (I[j] - alpha * 0.5 * (imin[j] + imax[j])) / fabs(imax[j] - imin[j]);
-    const double *w1 = W1 + (long)octant * nh * 26, *c1 = b1 + (long)octant * nh;
-    const double *w2 = W2 + (long)octant * 8 * nh, *c2 = b2 + (long)octant * 8;
+    const double *w1 = W1 + (long)index * nh * 26, *c1 = b1 + (long)index * nh;
+    const double *w2 = W2 + (long)index * 8 * nh, *c2 = b2 + (long)index * 8;
     for (int k = 0; k < nh; ++k) {
         double v = c1[k];
         for (int j = 0; j < 26; ++j) v += w1[k * 26 + j] * In[j];
@@ -1398,9 +1422,11 @@ static int pann_cell(const struct orc_pann *p, const double h[3], const double o
                      double sigma_t, const double S[8], const double psi_up[6][8], double psi[8])
 {
     double I[26];
+    const int k = pann_net_index(p, omega);
+    if (k < 0) return ORC_EINVAL;   /* no network for this direction */
     orc_pann_inputs(h, omega, sigma_t, S, psi_up, I);
     return orc_pann_forward(p->nh, p->alpha, p->beta_scale, p->imin, p->imax, p->W1, p->b1, p->W2,
-                            p->b2, orc_pann_octant(omega), I, psi);
+                            p->b2, p->ndir, p->dir_omega, k, I, psi);
 }
 
 static int ann_cell(const orc_ann *net, const double h[3], const double omega[3], double sigma_t,
@@ -1465,10 +1491,11 @@ int orc_pann_cell_batch(long n, const double *h, const double *omega, const doub
                         const double *S, const double *psi_up, int nh, double alpha,
                         double beta_scale, const double *imin, const double *imax,
                         const double *W1, const double *b1, const double *W2, const double *b2,
-                        double *psi)
+                        int ndir, const double *dir_omega, double *psi)
 {
-    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
-    if (nh < 1 || nh > 64) return ORC_EINVAL;
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2, ndir,
+                               dir_omega};
+    if (nh < 1 || nh > 64 || ndir < 0) return ORC_EINVAL;
     for (long i = 0; i < n; ++i) {
         const int rc = pann_cell(&p, h + 3 * i, omega + 3 * i, sigma_t[i], S + 8 * i,
                                  (const double(*)[8])(psi_up + 48 * i), psi + 8 * i);
@@ -1482,12 +1509,13 @@ int orc_pann_sweep(int nx, int ny, int nz, double lx, double ly, double lz, int 
                    const double *omega, const double *weight, const double *sigma_t,
                    const double *src, const double psi_inc[6], int nh, double alpha,
                    double beta_scale, const double *imin, const double *imax, const double *W1,
-                   const double *b1, const double *W2, const double *b2, double *phi,
-                   double *psi_store, int nthreads)
+                   const double *b1, const double *W2, const double *b2, int ndir,
+                   const double *dir_omega, double *phi, double *psi_store, int nthreads)
 {
-    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2, ndir,
+                               dir_omega};
     orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
-    if (nh < 1 || nh > 64) return ORC_EINVAL;
+    if (nh < 1 || nh > 64 || ndir < 0) return ORC_EINVAL;
     return sweep_all(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, src, psi_inc, phi,
                      psi_store, &net, nthreads);
 }
@@ -1497,13 +1525,14 @@ int orc_pann_source_iterate(int nx, int ny, int nz, double lx, double ly, double
                             const double *sigma_t, const double *sigma_s, const double *q,
                             const double psi_inc[6], int nh, double alpha, double beta_scale,
                             const double *imin, const double *imax, const double *W1,
-                            const double *b1, const double *W2, const double *b2, double *phi,
-                            double tol, int max_iter, int *iters, double *resid, double *eps_s,
-                            int nthreads)
+                            const double *b1, const double *W2, const double *b2, int ndir,
+                            const double *dir_omega, double *phi, double tol, int max_iter,
+                            int *iters, double *resid, double *eps_s, int nthreads)
 {
-    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2};
+    const struct orc_pann p = {nh, alpha, beta_scale, imin, imax, W1, b1, W2, b2, ndir,
+                               dir_omega};
     orc_ann net = {26, nh, 8, 1, NULL, NULL, NULL, NULL, &p};
-    if (nh < 1 || nh > 64) return ORC_EINVAL;
+    if (nh < 1 || nh > 64 || ndir < 0) return ORC_EINVAL;
     return source_iterate(nx, ny, nz, lx, ly, lz, ng, nd, omega, weight, sigma_t, sigma_s, q,
                           psi_inc, phi, tol, max_iter, iters, resid, eps_s, NULL, &net, nthreads,
                           NULL, 0);

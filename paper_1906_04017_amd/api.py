@@ -108,7 +108,8 @@ class Ann:
         _lib.check(_lib.load().dgsn_ann_set_mode(self._h, m))
 
     def infer_octant(self, octant, x, out=None):
-        """Paper-form network of one octant on raw inputs x [n,26] float32 -> [n,8]."""
+        """Paper-form network `octant` on raw inputs x [n,26] float32 -> [n,8]
+        (per-direction artifacts: the index of the direction's network)."""
         x = x.contiguous()
         if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 26:
             raise ValueError("x must be a float32 [n, 26] tensor")

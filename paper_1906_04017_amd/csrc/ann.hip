@@ -148,15 +148,15 @@ int build_params(dgsn_ann *a)
     return DGSN_OK;
 }
 
-// Version 2: the raw-input images of the 8 octant networks.  Eq. (ANN:Eq2)
+// Versions 2 and 3: the raw-input images of the networks.  Eq. (ANN:Eq2)
 // In_j = (I_j - c_j) / r_j with c_j = alpha (Imin_j + Imax_j) / 2 and
 // r_j = |Imax_j - Imin_j| is folded into the first layer:
 // W1' = W1 / r, b1' = b1 - W1 c / r (hidden units beyond n_hidden are zero).
 int build_pann_params(dgsn_ann *a)
 {
     const int H = a->n_hidden;
-    std::vector<float> img((size_t)8 * kPannRawStride, 0.0f);
-    for (int o = 0; o < 8; ++o) {
+    std::vector<float> img((size_t)a->n_nets * kPannRawStride, 0.0f);
+    for (int o = 0; o < a->n_nets; ++o) {
         float *w = img.data() + (size_t)o * kPannRawStride;
         const float *W1 = a->W1.data() + (size_t)o * H * kPannIn;
         const float *b1 = a->b1.data() + (size_t)o * H;
@@ -186,7 +186,7 @@ int build_pann_params(dgsn_ann *a)
 
 const void *ann_device_params(const dgsn_ann *a) { return a ? a->d_params.ptr : nullptr; }
 
-// Folding for one problem (cell sizes h), per octant o with reflection mask o
+// Folding of net k for one problem (cell sizes h) and reflection mask o
 // (bit a set: Omega_a < 0; canonical node n' is physical node n' ^ o):
 //   canonical inflow face node fn of axis a is physical face node
 //   fn ^ (mask bits of the two tangential axes, lower axis first);
@@ -194,43 +194,77 @@ const void *ann_device_params(const dgsn_ann *a) { return a ? a->d_params.ptr : 
 //   canonical source node n' is physical node n' ^ o;
 //   the cell sizes are constant inputs, added to the bias;
 //   canonical output t' is the physical output t' ^ o.
+static void fold_pann(const dgsn_ann *a, int k, int o, const double h[3], float *w)
+{
+    const int H = a->n_hidden;
+    const float *W1 = a->W1.data() + (size_t)k * H * kPannIn;
+    const float *b1 = a->b1.data() + (size_t)k * H;
+    const float *W2 = a->W2.data() + (size_t)k * 8 * H;
+    const float *b2 = a->b2.data() + (size_t)k * 8;
+    const int mx = o & 1, my = (o >> 1) & 1, mz = (o >> 2) & 1;
+    const int tang[3] = {my | (mz << 1), mx | (mz << 1), mx | (my << 1)};
+    for (int u = 0; u < H; ++u) {
+        // scaled first layer on the raw physical inputs
+        double ws[kPannIn];
+        double bias = b1[u];
+        for (int j = 0; j < kPannIn; ++j) {
+            const double c = (double)a->alpha * 0.5 * ((double)a->imin[j] + a->imax[j]);
+            const double r = std::fabs((double)a->imax[j] - a->imin[j]);
+            ws[j] = W1[u * kPannIn + j] / r;
+            bias -= W1[u * kPannIn + j] * c / r;
+        }
+        float *r1 = w + kPannW1 + u * kPannFeat;
+        for (int ax = 0; ax < 3; ++ax)
+            for (int fn = 0; fn < 4; ++fn) r1[4 * ax + fn] = (float)ws[4 * ax + (fn ^ tang[ax])];
+        r1[12] = (float)(ws[12] * (mx ? -h[0] : h[0]));
+        r1[13] = (float)(ws[13] * (my ? -h[1] : h[1]));
+        for (int n = 0; n < 8; ++n) r1[14 + n] = (float)ws[14 + (n ^ o)];
+        r1[22] = (float)ws[22];
+        for (int ax = 0; ax < 3; ++ax) bias += ws[23 + ax] * h[ax];
+        w[kPannB1 + u] = (float)bias;
+        for (int t = 0; t < 8; ++t) w[kPannW2 + t * kPannHidden + u] = W2[(t ^ o) * H + u];
+    }
+    for (int t = 0; t < 8; ++t) w[kPannB2 + t] = b2[t ^ o];
+    w[kPannBeta] = a->beta_scale;
+}
+
 int pann_problem_image(const dgsn_ann *a, const double h[3], std::vector<float> &out)
 {
-    if (!a || a->version != 2) return set_error(DGSN_EINVAL, "not a paper-form network");
-    const int H = a->n_hidden;
+    if (!a || a->version != 2) return set_error(DGSN_EINVAL, "not a per-octant paper-form network");
     out.assign((size_t)8 * kPannStride, 0.0f);
-    for (int o = 0; o < 8; ++o) {
-        float *w = out.data() + (size_t)o * kPannStride;
-        const float *W1 = a->W1.data() + (size_t)o * H * kPannIn;
-        const float *b1 = a->b1.data() + (size_t)o * H;
-        const float *W2 = a->W2.data() + (size_t)o * 8 * H;
-        const float *b2 = a->b2.data() + (size_t)o * 8;
-        const int mx = o & 1, my = (o >> 1) & 1, mz = (o >> 2) & 1;
-        const int tang[3] = {my | (mz << 1), mx | (mz << 1), mx | (my << 1)};
-        for (int k = 0; k < H; ++k) {
-            // scaled first layer on the raw physical inputs
-            double ws[kPannIn];
-            double bias = b1[k];
-            for (int j = 0; j < kPannIn; ++j) {
-                const double c = (double)a->alpha * 0.5 * ((double)a->imin[j] + a->imax[j]);
-                const double r = std::fabs((double)a->imax[j] - a->imin[j]);
-                ws[j] = W1[k * kPannIn + j] / r;
-                bias -= W1[k * kPannIn + j] * c / r;
+    for (int o = 0; o < 8; ++o) fold_pann(a, o, o, h, out.data() + (size_t)o * kPannStride);
+    return DGSN_OK;
+}
+
+// Per-direction networks: slot (o, d) of the problem's octant-sorted
+// direction table takes the net whose stored direction equals the slot's
+// (every component within kPannDirTol: the artifact holds FP32 cosines).
+// Padding slots (valid[o * Do + d] == 0) get zero images.
+int pann_problem_image_dir(const dgsn_ann *a, const double h[3], const double *omega, int Do,
+                           const int *valid, std::vector<float> &out)
+{
+    if (!a || a->version != 3)
+        return set_error(DGSN_EINVAL, "not a per-direction paper-form network");
+    out.assign((size_t)8 * Do * kPannStride, 0.0f);
+    for (int o = 0; o < 8; ++o)
+        for (int d = 0; d < Do; ++d) {
+            const int s = o * Do + d;
+            if (!valid[s]) continue;
+            const double *om = omega + 3 * (size_t)s;
+            int k = -1;
+            for (int j = 0; j < a->n_nets && k < 0; ++j) {
+                const float *w = a->omega.data() + 3 * (size_t)j;
+                if (std::fabs(w[0] - om[0]) <= kPannDirTol && std::fabs(w[1] - om[1]) <= kPannDirTol &&
+                    std::fabs(w[2] - om[2]) <= kPannDirTol)
+                    k = j;
             }
-            float *r1 = w + kPannW1 + k * kPannFeat;
-            for (int ax = 0; ax < 3; ++ax)
-                for (int fn = 0; fn < 4; ++fn) r1[4 * ax + fn] = (float)ws[4 * ax + (fn ^ tang[ax])];
-            r1[12] = (float)(ws[12] * (mx ? -h[0] : h[0]));
-            r1[13] = (float)(ws[13] * (my ? -h[1] : h[1]));
-            for (int n = 0; n < 8; ++n) r1[14 + n] = (float)ws[14 + (n ^ o)];
-            r1[22] = (float)ws[22];
-            for (int ax = 0; ax < 3; ++ax) bias += ws[23 + ax] * h[ax];
-            w[kPannB1 + k] = (float)bias;
-            for (int t = 0; t < 8; ++t) w[kPannW2 + t * kPannHidden + k] = W2[(t ^ o) * H + k];
+            if (k < 0)
+                return set_error(DGSN_EINVAL,
+                                 "direction (%.7f, %.7f, %.7f) of the problem has no network in "
+                                 "the per-direction artifact",
+                                 om[0], om[1], om[2]);
+            fold_pann(a, k, o, h, out.data() + (size_t)s * kPannStride);
         }
-        for (int t = 0; t < 8; ++t) w[kPannB2 + t] = b2[t ^ o];
-        w[kPannBeta] = a->beta_scale;
-    }
     return DGSN_OK;
 }
 
@@ -263,18 +297,26 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
     const uint32_t flags = v[5];
     uint32_t n_nets = 1;
     size_t hdr = 8 + 6 * 4;
-    if (version == 2) {
+    if (version == 2 || version == 3) {
         // u32 n_nets, f32 alpha, f32 beta_scale, f32 imin[26], f32 imax[26]
+        // (version 3: then f32 omega[n_nets][3])
         if (data.size() < hdr + 4 + 8 + 8 * 26 + 4)
-            return set_error(DGSN_EFORMAT, "%s: truncated version-2 header", path);
+            return set_error(DGSN_EFORMAT, "%s: truncated version-%u header", path, version);
         std::memcpy(&n_nets, data.data() + hdr, 4);
         hdr += 4 + 8 + 2 * 4 * 26;
-        if (n_in != (uint32_t)kPannIn || n_out != 8 || n_nets != 8 || n_hidden < 1 ||
+        const bool nets_ok = version == 2 ? n_nets == 8 : (n_nets >= 1 && n_nets <= kPannMaxDirs);
+        if (n_in != (uint32_t)kPannIn || n_out != 8 || !nets_ok || n_hidden < 1 ||
             n_hidden > (uint32_t)kPannHidden || act != 1 || flags != 1)
             return set_error(DGSN_EFORMAT,
-                             "%s: unsupported version-2 shape (%u-%u-%u, %u nets, act %u, "
-                             "flags %u; expected 26-(1..8)-8, 8 nets, tanh, ELU output)",
-                             path, n_in, n_hidden, n_out, n_nets, act, flags);
+                             "%s: unsupported version-%u shape (%u-%u-%u, %u nets, act %u, "
+                             "flags %u; expected 26-(1..8)-8, %s, tanh, ELU output)",
+                             path, version, n_in, n_hidden, n_out, n_nets, act, flags,
+                             version == 2 ? "8 nets" : "1..4096 nets");
+        if (version == 3) {
+            if (data.size() < hdr + 12 * (size_t)n_nets + 4)
+                return set_error(DGSN_EFORMAT, "%s: truncated direction table", path);
+            hdr += 12 * (size_t)n_nets;
+        }
     } else if (version != 1 || n_in != 24 || n_out != 8 || n_hidden < 1 ||
                n_hidden > kMaxHidden) {
         return set_error(DGSN_EFORMAT, "%s: unsupported shape (version %u, %u-%u-%u)", path,
@@ -297,8 +339,8 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
         return set_error(DGSN_EUNSUPPORTED, "%s: at most %d hidden units are supported", path,
                          kHiddenPad);
     float alpha = 0.0f, beta_scale = 0.0f;
-    std::vector<float> imin, imax;
-    if (version == 2) {
+    std::vector<float> imin, imax, omega;
+    if (version >= 2) {
         const unsigned char *q = data.data() + 8 + 6 * 4 + 4;
         std::memcpy(&alpha, q, 4);
         std::memcpy(&beta_scale, q + 4, 4);
@@ -311,6 +353,24 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
         for (int j = 0; j < kPannIn; ++j)
             if (!std::isfinite(imin[j]) || !std::isfinite(imax[j]) || imin[j] == imax[j])
                 return set_error(DGSN_EFORMAT, "%s: bad input bounds of input %d", path, j);
+        if (version == 3) {
+            omega.resize(3 * (size_t)n_nets);
+            std::memcpy(omega.data(), q + 8 + 8 * kPannIn, 12 * (size_t)n_nets);
+            for (uint32_t k = 0; k < n_nets; ++k) {
+                const float *w = omega.data() + 3 * (size_t)k;
+                const double len2 = (double)w[0] * w[0] + (double)w[1] * w[1] + (double)w[2] * w[2];
+                if (!std::isfinite(len2) || std::fabs(len2 - 1.0) > 1e-5)
+                    return set_error(DGSN_EFORMAT, "%s: direction %u is not a unit vector", path,
+                                     k);
+                for (uint32_t j = 0; j < k; ++j) {
+                    const float *v = omega.data() + 3 * (size_t)j;
+                    if (std::fabs(w[0] - v[0]) <= kPannDirTol && std::fabs(w[1] - v[1]) <= kPannDirTol &&
+                        std::fabs(w[2] - v[2]) <= kPannDirTol)
+                        return set_error(DGSN_EFORMAT, "%s: directions %u and %u coincide", path,
+                                         j, k);
+                }
+            }
+        }
     }
     {
         const float *pw = reinterpret_cast<const float *>(data.data() + hdr);
@@ -333,6 +393,7 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
     a->beta_scale = beta_scale;
     a->imin = imin;
     a->imax = imax;
+    a->omega = omega;
     const float *pf = reinterpret_cast<const float *>(data.data() + hdr);
     for (uint32_t k = 0; k < n_nets; ++k) {
         a->W1.insert(a->W1.end(), pf, pf + (size_t)n_hidden * n_in);
@@ -348,7 +409,7 @@ int dgsn_ann_load(dgsn_ctx *ctx, const char *path, dgsn_ann **out)
         delete a;
         return set_error(DGSN_EHIP, "hipSetDevice failed");
     }
-    int rc = version == 2 ? build_pann_params(a) : build_params(a);
+    int rc = version >= 2 ? build_pann_params(a) : build_params(a);
     if (rc) {
         delete a;
         return rc;
@@ -380,10 +441,11 @@ int dgsn_ann_infer_octant(const dgsn_ann *ann, int octant, const float *x, float
 {
     clear_error();
     if (!ann) return set_error(DGSN_EINVAL, "ann is NULL");
-    if (ann->version != 2)
-        return set_error(DGSN_EINVAL, "dgsn_ann_infer_octant needs a paper-form (version 2) "
-                                      "artifact; use dgsn_ann_infer");
-    if (octant < 0 || octant > 7) return set_error(DGSN_EINVAL, "octant must be in 0..7");
+    if (ann->version < 2)
+        return set_error(DGSN_EINVAL, "dgsn_ann_infer_octant needs a paper-form (version 2 or "
+                                      "3) artifact; use dgsn_ann_infer");
+    if (octant < 0 || octant >= ann->n_nets)
+        return set_error(DGSN_EINVAL, "net index %d is outside 0..%d", octant, ann->n_nets - 1);
     if (n < 0) return set_error(DGSN_EINVAL, "n must be >= 0");
     if (n == 0) return DGSN_OK;
     if (!x || !y) return set_error(DGSN_EINVAL, "x and y must be set");

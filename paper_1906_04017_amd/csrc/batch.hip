@@ -465,6 +465,9 @@ int batch_validate(dgsn_batch *B)
         if (p->solver == DGSN_ANN && p->ann->mode != DGSN_ANN_BF16)
             return set_error(DGSN_EUNSUPPORTED, "batched execution evaluates the networks in "
                              "BF16 (problem %zu uses split BF16)", b);
+        if (p->solver == DGSN_ANN && p->ann->version == 3)
+            return set_error(DGSN_EUNSUPPORTED, "batched execution takes per-octant networks "
+                             "(problem %zu has per-direction networks)", b);
         if (B->cfg_gen.size() != B->probs.size() || B->cfg_gen[b] != p->cfg_gen) B->dirty = true;
     }
     return DGSN_OK;

@@ -59,6 +59,11 @@ const void *ann_device_params(const dgsn_ann *a);
 // Per-octant weight images of a paper-form network for a problem with cell
 // sizes h (canonical-frame features, layout in pann_body.hpp).
 int pann_problem_image(const dgsn_ann *a, const double h[3], std::vector<float> &out);
+// Per-slot images of a per-direction paper-form network ([8][Do] slots of the
+// problem's octant-sorted directions omega [8][Do][3]; valid[s] = 0 marks a
+// padding slot); DGSN_EINVAL if a direction has no net.
+int pann_problem_image_dir(const dgsn_ann *a, const double h[3], const double *omega, int Do,
+                           const int *valid, std::vector<float> &out);
 
 // one unit of the dataflow schedule (host copy; see flow_units_host)
 struct FlowUnitHost {
@@ -97,11 +102,13 @@ struct dgsn_ctx {
 
 struct dgsn_ann {
     dgsn_ctx *ctx = nullptr;
-    int version = 1;                     // 1: canonical 24-input net, 2: paper-form per octant
+    int version = 1;                     // 1: canonical 24-input net, 2: paper-form per
+                                         // octant, 3: paper-form per quadrature direction
     int mode = DGSN_ANN_BF16;            // version 1: evaluation precision on the matrix cores
     int n_in = 24, n_hidden = 0, n_out = 8, act = 0, n_nets = 1;
     float alpha = 0.0f, beta_scale = 0.0f;   // version 2: Eq. (ANN:Eq2) and (ANN:Eq4)
-    std::vector<float> imin, imax;       // version 2: input bounds [26]
+    std::vector<float> imin, imax;       // versions 2, 3: input bounds [26]
+    std::vector<float> omega;            // version 3: the direction of each net [n_nets][3]
     std::vector<float> W1, b1, W2, b2;   // host copies (fp32), n_nets networks back to back
     // device: version 1, bf16 packed operand images and fp32 biases (layout in
     // ann.hip); version 2, the per-octant raw-input images (pann_body.hpp)

@@ -197,22 +197,21 @@ void launch_flow_ann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 g
     }
 }
 
-// The paper-form network: FP32 forward sweeps only.
+// The paper-form networks (per octant or per direction): FP32 forward
+// sweeps only.
+template <int Form>
 void launch_flow_pann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 grid, dim3 block,
                       hipStream_t s)
 {
     switch (b) {
     case 3:
-        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 3, false, false>), grid, block, 0,
-                           s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 3, false, false>), grid, block, 0, s, A, F);
         break;
     case 2:
-        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 2, false, false>), grid, block, 0,
-                           s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 2, false, false>), grid, block, 0, s, A, F);
         break;
     default:
-        hipLaunchKernelGGL((sweep_flow_ge<float, kFormAnnPaper, 1, false, false>), grid, block, 0,
-                           s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 1, false, false>), grid, block, 0, s, A, F);
         break;
     }
 }
@@ -225,9 +224,10 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
 {
     const dim3 block(256);
     const bool net = form == kFormAnn || form == kFormAnnSplit;
-    if ((form == kFormAnnPaper || net) && (sizeof(Real) != 4 || store_psi || adjoint))
+    const bool paper = form == kFormAnnPaper || form == kFormAnnPaperDir;
+    if ((paper || net) && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the network solvers run FP32 forward sweeps");
-    if (A.nmom > 1 && (form == kFormAnnPaper || net ||
+    if (A.nmom > 1 && (paper || net ||
                        (form == kFormDense && (store_psi || adjoint))))
         return set_error(DGSN_EUNSUPPORTED, "anisotropic sweeps run the GE solvers (the psi "
                          "store and the adjoint with the mass-inverse form)");
@@ -239,7 +239,11 @@ int launch_flow(const PlaneArgs<Real> &A, const FlowArgs &F, int form, int b, bo
         if (form == kFormDense) {
             launch_flow_b<Real, kFormDense>(A, F, b, store_psi, adjoint, grid, block, s);
         } else if (form == kFormAnnPaper) {
-            if constexpr (sizeof(Real) == 4) launch_flow_pann(A, F, b, grid, block, s);
+            if constexpr (sizeof(Real) == 4)
+                launch_flow_pann<kFormAnnPaper>(A, F, b, grid, block, s);
+        } else if (form == kFormAnnPaperDir) {
+            if constexpr (sizeof(Real) == 4)
+                launch_flow_pann<kFormAnnPaperDir>(A, F, b, grid, block, s);
         } else if (form == kFormAnn) {
             if constexpr (sizeof(Real) == 4) launch_flow_ann<kFormAnn>(A, F, b, grid, block, s);
         } else if (form == kFormAnnSplit) {

@@ -130,6 +130,7 @@ constexpr int kFormDense = 1;     // the paper's assembled A_psi, dense eliminat
 constexpr int kFormAnn = 2;       // the shallow network in place of assembly + elimination
 constexpr int kFormAnnPaper = 3;  // the paper-form per-octant network (vector ALUs)
 constexpr int kFormAnnSplit = 4;  // the shallow network with split-BF16 activations
+constexpr int kFormAnnPaperDir = 5;   // the paper-form networks, one per direction
 
 // Occupancy request of a sweep kernel (waves per SIMD; 1 = no request).  The
 // FP64 single-cell mass-inverse kernel would take 176 registers and run at 2

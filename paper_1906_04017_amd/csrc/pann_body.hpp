@@ -1,12 +1,16 @@
 // Device code of the paper-form shallow network (Sec. 3, Eq. (ANN:Eq1)-
 // (ANN:Eq4)): one hidden layer of tanh units and an ELU output layer, one
-// network per octant, evaluated on the vector ALUs.  With 8 hidden units the
-// network is 272 multiply-adds per cell, far too narrow for the matrix cores.
+// network per octant or one per quadrature direction, evaluated on the vector
+// ALUs.  With 8 hidden units the network is 272 multiply-adds per cell, far
+// too narrow for the matrix cores.
 //
-// Every lane of a block serves the same octant, so the weights are uniform
-// over the block: they are read through the constant address space, which
-// makes them scalar loads (scalar registers as FMA operands, no LDS, no vector
-// memory traffic).  The input scaling of Eq. (ANN:Eq2), the problem's cell
+// Every lane of a block serves the same octant, so per-octant weights are
+// uniform over the block: they are read through the constant address space,
+// which makes them scalar loads (scalar registers as FMA operands, no LDS, no
+// vector memory traffic).  The lanes of a wave serve several directions, so
+// per-direction weights are vector loads of the lane's own image (the
+// octant's images, 1 KB per direction, stay in the vector cache).  The input
+// scaling of Eq. (ANN:Eq2), the problem's cell
 // sizes (constant inputs), the signs of the direction cosines and the node and
 // face-node relabelling between the physical and the canonical (reflected)
 // frame are folded into the weights on the host, so the kernel feeds the
@@ -30,6 +34,10 @@ constexpr int kPannW2 = kPannB1 + kPannHidden;              // [8][8]
 constexpr int kPannB2 = kPannW2 + 8 * kPannHidden;          // [8]
 constexpr int kPannBeta = kPannB2 + 8;                      // beta / max(psi_inc)
 constexpr int kPannStride = 272;
+// per-direction networks: at most this many nets in an artifact, matched to
+// the problem's directions by every cosine within this distance
+constexpr int kPannMaxDirs = 4096;
+constexpr double kPannDirTol = 1e-6;
 // per-octant image of the raw-input evaluation (dgsn_ann_infer_octant)
 constexpr int kPannRawW1 = 0;                                  // [8][26], scaling folded in
 constexpr int kPannRawB1 = kPannRawW1 + kPannHidden * kPannIn;  // [8]
@@ -38,16 +46,16 @@ constexpr int kPannRawB2 = kPannRawW2 + 8 * kPannHidden;        // [8]
 constexpr int kPannRawBeta = kPannRawB2 + 8;
 constexpr int kPannRawStride = 296;
 
-// Read-only weight at base[i] through the constant address space (a scalar
-// load for a wave-uniform address; the address space exists in the device
-// pass only).
+// Read-only weight at base[i]: kUniform, through the constant address space
+// (a scalar load for a wave-uniform address; the address space exists in the
+// device pass only); else an ordinary per-lane load.
+template <bool kUniform>
 __device__ __forceinline__ float pann_w(const float *base, int i)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return ((const __attribute__((address_space(4))) float *)base)[i];
-#else
-    return base[i];
+    if constexpr (kUniform) return ((const __attribute__((address_space(4))) float *)base)[i];
 #endif
+    return base[i];
 }
 
 // tanh(z) = sign(z) (1 - 2 / (exp(2|z|) + 1)), with the hardware base-2
@@ -67,31 +75,34 @@ __device__ __forceinline__ float pann_elu(float z, float beta)
 
 // Hidden and output layers on features f[nf] with the image at w (layout
 // W1 [8][nf], b1 [8], W2 [8][8], b2 [8], beta scale).
-template <int NF, int W1, int B1, int W2, int B2, int BETA>
+template <int NF, int W1, int B1, int W2, int B2, int BETA, bool kUniform = true>
 __device__ __forceinline__ void pann_layers(const float *w, const float f[NF], float pmax,
                                             float out[8])
 {
     float h[kPannHidden];
 #pragma unroll
     for (int k = 0; k < kPannHidden; ++k) {
-        float z = pann_w(w, B1 + k);
+        float z = pann_w<kUniform>(w, B1 + k);
 #pragma unroll
-        for (int j = 0; j < NF; ++j) z = fmaf(pann_w(w, W1 + k * NF + j), f[j], z);
+        for (int j = 0; j < NF; ++j) z = fmaf(pann_w<kUniform>(w, W1 + k * NF + j), f[j], z);
         h[k] = pann_tanh(z);
     }
-    const float beta = pann_w(w, BETA) * pmax;
+    const float beta = pann_w<kUniform>(w, BETA) * pmax;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        float z = pann_w(w, B2 + t);
+        float z = pann_w<kUniform>(w, B2 + t);
 #pragma unroll
-        for (int k = 0; k < kPannHidden; ++k) z = fmaf(pann_w(w, W2 + t * kPannHidden + k), h[k], z);
+        for (int k = 0; k < kPannHidden; ++k)
+            z = fmaf(pann_w<kUniform>(w, W2 + t * kPannHidden + k), h[k], z);
         out[t] = pann_elu(z, beta);
     }
 }
 
 // One canonical cell of the sweep: kap = |Omega_a| / dx_a, st = sigma_t,
 // sc = canonical source nodes, vx/vy/vz = canonical inflow faces.  A face
-// with kappa_a = 0 carries no inflow and is fed as 0.  w: the octant's image.
+// with kappa_a = 0 carries no inflow and is fed as 0.  w: the octant's image
+// (kUniform) or the lane's direction's.
+template <bool kUniform = true>
 __device__ __forceinline__ void pann_cell(const float *w, const float kap[3], float st,
                                           const float sc[8], const float vx[4], const float vy[4],
                                           const float vz[4], float psi[8])
@@ -111,7 +122,8 @@ __device__ __forceinline__ void pann_cell(const float *w, const float kap[3], fl
 #pragma unroll
     for (int n = 0; n < 8; ++n) f[14 + n] = sc[n];
     f[22] = st;
-    pann_layers<kPannFeat, kPannW1, kPannB1, kPannW2, kPannB2, kPannBeta>(w, f, pmax, psi);
+    pann_layers<kPannFeat, kPannW1, kPannB1, kPannW2, kPannB2, kPannBeta, kUniform>(w, f, pmax,
+                                                                                   psi);
 }
 
 }  // namespace dgsn

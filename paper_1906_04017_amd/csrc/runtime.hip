@@ -383,13 +383,14 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
             return set_error(DGSN_EUNSUPPORTED, "store_psi is not available with the ANN solver");
     }
     // the matrix-core network (version 1) has its own kernel; the paper-form
-    // network (version 2) runs inside the GE kernels as another local solver
-    const bool paper = anyann && p->ann->version == 2;
+    // networks (version 2 per octant, 3 per direction) run inside the GE
+    // kernels as another local solver
+    const bool paper = anyann && p->ann->version >= 2;
     const bool ann = anyann && !paper;
     if (ann) A.ann_params = ann_device_params(p->ann);
     if (paper) A.ann_params = p->d_pann.ptr;
     const bool split = ann && p->ann->mode == DGSN_ANN_BF16X2;
-    const int form = paper ? kFormAnnPaper
+    const int form = paper ? (p->ann->version == 3 ? kFormAnnPaperDir : kFormAnnPaper)
                            : ann ? (split ? kFormAnnSplit : kFormAnn)
                                  : (p->solver == DGSN_GE_DENSE ? kFormDense : kFormMassInv);
     // anisotropic sweeps use tiles of edge 2 at most (larger tiles spill)
@@ -845,7 +846,7 @@ PlaneArgs<float> batch_plane_args(dgsn_problem *p, const void *src)
 {
     PlaneArgs<float> A = plane_args<float>(p, src, false);
     if (p->solver == DGSN_ANN)
-        A.ann_params = p->ann->version == 2 ? p->d_pann.ptr : ann_device_params(p->ann);
+        A.ann_params = p->ann->version >= 2 ? p->d_pann.ptr : ann_device_params(p->ann);
     return A;
 }
 
@@ -1418,10 +1419,18 @@ int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
         return set_error(DGSN_EUNSUPPORTED, "the ANN solver runs on FP32 problems only");
     // a folded paper-form image may be replaced below: batches re-capture
     p->touch(true);
-    if (ann && ann->version == 2) {
+    if (ann && ann->version >= 2) {
         // fold the scaling, the cell sizes and the octant relabelling in once
+        // (per octant, or per direction slot)
         std::vector<float> img;
-        DGSN_TRY(pann_problem_image(ann, p->h, img));
+        if (ann->version == 2) {
+            DGSN_TRY(pann_problem_image(ann, p->h, img));
+        } else {
+            std::vector<int> valid(p->dir_user.size());
+            for (size_t k = 0; k < valid.size(); ++k) valid[k] = p->dir_user[k] >= 0;
+            DGSN_TRY(pann_problem_image_dir(ann, p->h, p->omega_host.data(), p->Do, valid.data(),
+                                            img));
+        }
         DGSN_HIP(hipSetDevice(p->ctx->device));
         // past this point a failure leaves no network attached (the folded
         // image of a network attached before may be gone)

@@ -528,21 +528,20 @@ int launch_tile_ann(const PlaneArgs<float> &A, int b, bool split, hipStream_t s)
     return DGSN_OK;
 }
 
-// The paper-form network: FP32 forward sweeps only.
+// The paper-form networks (per octant or per direction): FP32 forward
+// sweeps only.
+template <int Form>
 void launch_tile_pann(const PlaneArgs<float> &A, int b, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (b) {
     case 3:
-        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 3, false, false>), grid, block, 0,
-                           s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 3, false, false>), grid, block, 0, s, A);
         break;
     case 2:
-        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 2, false, false>), grid, block, 0,
-                           s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 2, false, false>), grid, block, 0, s, A);
         break;
     default:
-        hipLaunchKernelGGL((sweep_tile_ge<float, kFormAnnPaper, 1, false, false>), grid, block, 0,
-                           s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 1, false, false>), grid, block, 0, s, A);
         break;
     }
 }
@@ -553,9 +552,10 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
 {
     const dim3 block(256);
     const dim3 grid((A.ncp + A.nc - 1) / A.nc, 8);
-    if (form == kFormAnnPaper && (sizeof(Real) != 4 || store_psi || adjoint))
+    const bool paper = form == kFormAnnPaper || form == kFormAnnPaperDir;
+    if (paper && (sizeof(Real) != 4 || store_psi || adjoint))
         return set_error(DGSN_EUNSUPPORTED, "the paper-form network runs FP32 forward sweeps");
-    if (A.nmom > 1 && (form == kFormAnnPaper || (form == kFormDense && (store_psi || adjoint))))
+    if (A.nmom > 1 && (paper || (form == kFormDense && (store_psi || adjoint))))
         return set_error(DGSN_EUNSUPPORTED, "anisotropic sweeps run the GE solvers (the psi "
                          "store and the adjoint with the mass-inverse form)");
     if (A.nmom > 1 && ((A.nmom != 4 && A.nmom != 9 && A.nmom != 16) || b > 2))
@@ -564,7 +564,9 @@ int launch_tile(const PlaneArgs<Real> &A, int form, int b, bool store_psi, bool 
     if (form == kFormDense) {
         launch_tile_b<Real, kFormDense>(A, b, store_psi, adjoint, grid, block, s);
     } else if (form == kFormAnnPaper) {
-        if constexpr (sizeof(Real) == 4) launch_tile_pann(A, b, grid, block, s);
+        if constexpr (sizeof(Real) == 4) launch_tile_pann<kFormAnnPaper>(A, b, grid, block, s);
+    } else if (form == kFormAnnPaperDir) {
+        if constexpr (sizeof(Real) == 4) launch_tile_pann<kFormAnnPaperDir>(A, b, grid, block, s);
     } else {
         launch_tile_b<Real, kFormMassInv>(A, b, store_psi, adjoint, grid, block, s);
     }

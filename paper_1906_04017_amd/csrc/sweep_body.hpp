@@ -325,8 +325,8 @@ struct TileLds {
 // o: octant slot; inc: the boundary inflow of octant slot o per canonical
 // axis; lane_ok: the lane carries work.  Form: kFormMassInv,
 // kFormDense (Gaussian elimination) or kFormAnn (the network, FP32 problems,
-// blocks of full waves) or kFormAnnPaper (the paper-form per-octant
-// network, FP32).  kCoh: device-coherent front access (dataflow
+// blocks of full waves) or kFormAnnPaper / kFormAnnPaperDir (the
+// paper-form networks per octant / per direction, FP32).  kCoh: device-coherent front access (dataflow
 // kernel).  kMom: anisotropic scattering with kMom = A.nmom - 1 moments (their
 // sources enter the gather, the moments leave with the scalar flux; source
 // iteration only, separate instantiations so that the isotropic kernels
@@ -342,8 +342,8 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                                           const Real *ytab = nullptr)
 {
     constexpr bool kNet = Form == kFormAnn || Form == kFormAnnSplit;   // matrix-core network
-    static_assert((!kNet && Form != kFormAnnPaper) || sizeof(Real) == 4,
-                  "the ANN solvers run in FP32");
+    constexpr bool kPaper = Form == kFormAnnPaper || Form == kFormAnnPaperDir;
+    static_assert((!kNet && !kPaper) || sizeof(Real) == 4, "the ANN solvers run in FP32");
     const int mask = kAdjoint ? (o ^ 7) : o;
     const uint32_t dg = d + A.Do * g;
     const Real *dp = A.dir + (o * A.Do + (lane_ok ? d : 0)) * kDirStride;
@@ -485,10 +485,14 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     ann_wave<Form == kFormAnnSplit>(R, feat, y);
 #pragma unroll
                     for (int n = 0; n < 8; ++n) psi[n] = ok ? m * y[n] : 0.0f;
-                } else if constexpr (Form == kFormAnnPaper) {
+                } else if constexpr (kPaper) {
                     if (ok) {
-                        pann_cell(static_cast<const float *>(A.ann_params) + o * kPannStride, kap,
-                                  st, sc, vx, vy, vz, psi);
+                        // the octant's network, or the lane's direction's
+                        constexpr bool kUni = Form == kFormAnnPaper;
+                        const int net = kUni ? o : o * A.Do + (lane_ok ? d : 0);
+                        pann_cell<kUni>(static_cast<const float *>(A.ann_params) +
+                                            (size_t)net * kPannStride,
+                                        kap, st, sc, vx, vy, vz, psi);
                     } else {
 #pragma unroll
                         for (int n = 0; n < 8; ++n) psi[n] = 0;

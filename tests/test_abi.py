@@ -250,6 +250,64 @@ def test_paper_ann_load_checks_file_before_device(lib, tmp_path):
     assert lib.dgsn_ann_info(None, ctypes.byref(v), None, None, None) == _lib.DGSN_EINVAL
 
 
+def _paper_dir_artifact(tmp_path, name="pdir.dgsnann", omega=None, nh=8):
+    rng = np.random.default_rng(6)
+    om = oracle.lq_n(4)[0] if omega is None else np.asarray(omega)
+    k = len(om)
+    imin, imax = np.zeros(26), np.ones(26)
+    imin[12:14] = -1.0
+    p = tmp_path / name
+    ann_format.write_paper_dir(p, rng.normal(size=(k, nh, 26)), rng.normal(size=(k, nh)),
+                               rng.normal(size=(k, 8, nh)), rng.normal(size=(k, 8)), imin, imax,
+                               om)
+    return p
+
+
+def test_paper_dir_artifact_roundtrip_and_load_checks(lib, tmp_path):
+    from oracle import ann_paper_train
+    p = _paper_dir_artifact(tmp_path)
+    net = ann_format.read(p)
+    assert net["version"] == 3 and net["W1"].shape == (24, 8, 26) and net["omega"].shape == (24, 3)
+    raw = open(p, "rb").read()
+    assert struct.unpack("<7I", raw[8:36]) == (3, 26, 8, 8, 1, 1, 24)
+    # the oracle's reader sees the same networks and directions
+    o = ann_paper_train.read_artifact(p)
+    assert np.array_equal(o["W1"], net["W1"].astype(np.float64))
+    assert np.array_equal(o["omega"], net["omega"].astype(np.float64))
+    out = ctypes.c_void_p()
+    assert lib.dgsn_ann_load(None, str(p).encode(), ctypes.byref(out)) == _lib.DGSN_EINVAL
+    assert b"ctx" in lib.dgsn_last_error()
+    om = oracle.lq_n(4)[0].copy()
+    om[3] *= 1.01
+    bad = _paper_dir_artifact(tmp_path, "norm.dgsnann", omega=om)
+    assert lib.dgsn_ann_load(None, str(bad).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    assert b"unit" in lib.dgsn_last_error()
+    om = oracle.lq_n(4)[0].copy()
+    om[5] = om[2]
+    dup = _paper_dir_artifact(tmp_path, "dup.dgsnann", omega=om)
+    assert lib.dgsn_ann_load(None, str(dup).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+    assert b"coincide" in lib.dgsn_last_error()
+    short = tmp_path / "short_dir.dgsnann"
+    short.write_bytes(raw[:44 + 8 * 26 + 40])
+    assert lib.dgsn_ann_load(None, str(short).encode(), ctypes.byref(out)) == _lib.DGSN_EFORMAT
+
+
+@pytest.mark.parametrize("name", ["sigma10_h0.078125", "sigma0.001_h0.078125", "sigma10_h0.1",
+                                  "sigma0.001_h0.1"])
+def test_trained_per_direction_artifacts(name):
+    # the shipped per-direction networks: one 26-8-8 network for each of the
+    # 80 LQ_8 directions, stored with the direction it serves; the input
+    # bounds are the training ranges (inflow and source maxima)
+    from oracle import ann_paper_train
+    path = os.path.join(ROOT, "paper_1906_04017_amd", "data", f"ann_paper_dir_s8_{name}.dgsnann")
+    net = ann_paper_train.read_artifact(path)
+    om, _ = oracle.lq_n(8)
+    assert net["W1"].shape == (80, 8, 26) and net["W2"].shape == (80, 8, 8)
+    assert np.abs(net["omega"] - om).max() < 1e-6
+    psi_max, s_max = (12.0, 120.0) if name.endswith("_psi12_s120") else (1.0, 1.0)
+    assert np.all(net["imax"][:12] == psi_max) and np.all(net["imax"][14:22] == s_max)
+
+
 def test_trained_paper_artifact_shape():
     # the shipped paper-form artifact: 8 octant networks of 26-8-8 with at most
     # the paper's 272 connections each (Sec. 3; fewer after pruning)

@@ -432,6 +432,46 @@ def test_paper_form_network_sweep_at_full_size(api, ctx, group):
     prob.close()
 
 
+PANN_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1906_04017_amd", "data", "ann_paper_dir_s8_sigma{}_h0.078125.dgsnann")
+PANN_DIR_EPS_P = 0.1
+
+
+@pytest.mark.parametrize("group,sigma", [(1, "0.001"), (2, "10")])
+def test_per_direction_networks_at_full_size(api, ctx, group, sigma):
+    # the per-direction paper-form networks trained at the problem's sigma_t
+    # and cell size (10 cm / 128) on Problem 2 or 3 at 128^3 S8, autotuned:
+    # the sweep against the oracle's FP64 forward of the same artifact, and
+    # the network's eps_P (Sec. 4) against the oracle's GE sweep in single
+    # digits (a property of the shipped artifact)
+    from oracle import ann_paper_train
+    path = PANN_DIR.format(sigma)
+    p = inputs.paper_problems(n=128, groups=4, order=8)
+    print_case("fullsize_pann_dir", name=p["name"], group=group)
+    om, w = api.quadrature_ls(8)
+    prob = api.Problem(ctx, p["n"], p["length"], 1, om, w, precision="fp32", solver="ann")
+    prob.set_materials(p["sigma_t"][group:group + 1], p["sigma_s"][group:group + 1],
+                       p["q"][group:group + 1])
+    prob.set_inflow(p["psi_inc"])
+    ann = api.Ann(ctx, path)
+    prob.set_ann(ann)
+    prob.autotune()
+    S = np.repeat(p["q"][group:group + 1, :, None], 8, axis=-1)
+    phi = prob.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    om_o, w_o = oracle.lq_n(8)
+    mesh = (*p["n"], *p["length"])
+    st = p["sigma_t"][group:group + 1]
+    ref = oracle.pann_sweep(ann_paper_train.read_artifact(path), mesh, om_o, w_o, st, S,
+                            p["psi_inc"])
+    assert rel(phi, ref) <= PANN_FULLSIZE_TOL, rel(phi, ref)
+    ge = oracle.sweep(mesh, om_o, w_o, st, S, p["psi_inc"]).mean(-1)
+    eps = float((np.abs(phi.mean(-1) - ge) / (np.abs(ge) + 1e-8)).mean())
+    print(f"eps_P {100 * eps:.3f} %", flush=True)
+    assert eps < PANN_DIR_EPS_P, eps
+    ann.close()
+    prob.close()
+
+
 def test_problem4_eps_s_source_iteration(api, ctx):
     # the paper's Problem 4 (sigma_t = 10, sigma_s = 9.9, q = 1, psi_inc = 1 on
     # three faces, 10 cm cube) at 16^3 S8 with the paper's stopping rule eps_S

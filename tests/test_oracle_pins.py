@@ -622,6 +622,74 @@ def test_pann_octant_mirror_equivariance():
     assert np.abs(back - phi).max() < 1e-12 * np.abs(phi).max()
 
 
+def _pann_per_direction(rng, om, nh=8):
+    k = len(om)
+    imin, imax = np.zeros(26), np.ones(26)
+    imin[12:14] = -1.0
+    return dict(kind="paper", W1=rng.normal(size=(k, nh, 26)) / 5, b1=rng.normal(size=(k, nh)) / 5,
+                W2=rng.normal(size=(k, 8, nh)) / 8, b2=np.abs(rng.normal(size=(k, 8))) / 5,
+                imin=imin, imax=imax, alpha=0.27, beta_scale=0.1, omega=np.array(om))
+
+
+def test_pann_per_direction_constant_nets_give_the_weighted_index_sum():
+    # net k outputs the constant k + 1 (zero weights, bias k + 1 >= 0 through
+    # the ELU's linear branch), so every cell of the sweep holds psi = k + 1 in
+    # direction k and phi = sum_k w_k (k + 1) at every node; a net taken from
+    # the wrong direction changes the sum
+    om, w = oracle.lq_n(4)
+    k = len(w)
+    net = dict(kind="paper", W1=np.zeros((k, 8, 26)), b1=np.zeros((k, 8)),
+               W2=np.zeros((k, 8, 8)), b2=np.repeat(np.arange(1.0, k + 1)[:, None], 8, 1),
+               imin=np.zeros(26), imax=np.ones(26), alpha=0.27, beta_scale=0.1, omega=om)
+    mesh = (3, 2, 2, 0.9, 0.5, 0.7)
+    rng = np.random.default_rng(53)
+    phi = oracle.pann_sweep(net, mesh, om, w, rng.uniform(0.5, 3.0, (1, 12)),
+                            rng.uniform(0.0, 1.0, (1, 12, 8)), np.full(6, 0.4))
+    want = float(np.dot(w, np.arange(1.0, k + 1)))
+    assert np.abs(phi - want).max() < 1e-12 * want
+    # a permuted quadrature (same directions, other order) finds the same nets
+    perm = rng.permutation(k)
+    phi_p = oracle.pann_sweep(net, mesh, om[perm], w[perm], rng.uniform(0.5, 3.0, (1, 12)),
+                              rng.uniform(0.0, 1.0, (1, 12, 8)), np.full(6, 0.4))
+    assert np.abs(phi_p - want).max() < 1e-12 * want
+
+
+def test_pann_per_direction_sweep_is_the_sum_of_single_direction_sweeps():
+    # each direction's sweep with its own net (placed in every octant slot of
+    # a per-octant set) summed over the directions is the per-direction sweep;
+    # per-direction nets copied from the octant nets give the per-octant sweep
+    rng = np.random.default_rng(54)
+    om, w = oracle.lq_n(4)
+    net = _pann_per_direction(rng, om)
+    mesh = (3, 4, 2, 0.6, 0.8, 0.5)
+    sig = rng.uniform(0.5, 3.0, (1, 24))
+    src = rng.uniform(0.0, 1.0, (1, 24, 8))
+    inc = np.array([0.7, 0.2, 0.5, 0.1, 0.3, 0.9])
+    phi = oracle.pann_sweep(net, mesh, om, w, sig, src, inc)
+    acc = np.zeros_like(phi)
+    for d in range(len(w)):
+        one = {key: (np.repeat(net[key][d][None], 8, 0) if key in ("W1", "b1", "W2", "b2")
+                     else net[key]) for key in net if key != "omega"}
+        acc += oracle.pann_sweep(one, mesh, om[d:d + 1], w[d:d + 1], sig, src, inc)
+    assert np.abs(acc - phi).max() < 1e-12 * np.abs(phi).max()
+    octs = {key: net[key][:8] for key in ("W1", "b1", "W2", "b2")}
+    per_oct = dict(net, **octs)
+    del per_oct["omega"]
+    ko = [oracle.pann_octant(o) for o in om]
+    as_dir = dict(net, **{key: octs[key][ko] for key in octs})
+    assert np.array_equal(oracle.pann_sweep(per_oct, mesh, om, w, sig, src, inc),
+                          oracle.pann_sweep(as_dir, mesh, om, w, sig, src, inc))
+
+
+def test_pann_per_direction_needs_a_net_for_every_direction():
+    rng = np.random.default_rng(55)
+    om, w = oracle.lq_n(4)
+    net = _pann_per_direction(rng, om[1:])
+    with pytest.raises(oracle.OracleError):
+        oracle.pann_sweep(net, (2, 2, 2, 1.0, 1.0, 1.0), om, w, np.ones((1, 8)),
+                          np.ones((1, 8, 8)), np.zeros(6))
+
+
 # ---------------------------------------------------------------------------
 # multigroup isotropic scattering (the group sum of Eq. (T3)-(T8) at P0)
 # ---------------------------------------------------------------------------
