@@ -131,6 +131,9 @@ def parse():
     ap.add_argument("--ann-paper", default=os.path.join(
         os.path.dirname(os.path.abspath(__file__)), "paper_1906_04017_amd", "data",
         "ann_paper_tanh8.dgsnann"), help="paper-form per-octant network (version-2 artifact)")
+    ap.add_argument("--per-direction-only", action="store_true",
+                    help="only the per-direction paper-form networks on Problems 1-4 at 100^3 "
+                         "and 128^3 S8 against GE")
     ap.add_argument("--paper-tables", action="store_true",
                     help="only reproduce the paper's Problem 1-4 grids (S2-S8 at 100^3, "
                          "10^3-100^3 at S8) with every local solver; prints one JSON line")
@@ -188,6 +191,16 @@ def main():
     if args.paper_tables:
         ctx = api.Context(0)
         print(json.dumps(paper_tables(api, ctx, args.ann, args.ann_paper)), flush=True)
+        return
+    if args.per_direction_only:
+        ctx = api.Context(0)
+        rows = []
+        for n in (100, 128):
+            row = {"cells": f"{n}^3", "order": "S8"}
+            row.update(per_direction_leg(api, ctx, n, None, None, 3))
+            log(f"per-direction networks {n}^3 S8: " + json.dumps(row))
+            rows.append(row)
+        print(json.dumps({"table": "per_direction_networks", "rows": rows}), flush=True)
         return
 
     p = inputs.blocky_scatter(n=args.n, groups=args.groups, seed=2, order=args.order)

@@ -293,7 +293,8 @@ def test_paper_dir_artifact_roundtrip_and_load_checks(lib, tmp_path):
 
 
 @pytest.mark.parametrize("name", ["sigma10_h0.078125", "sigma0.001_h0.078125", "sigma10_h0.1",
-                                  "sigma0.001_h0.1"])
+                                  "sigma0.001_h0.1", "sigma10_h0.078125_psi12_s120",
+                                  "sigma10_h0.1_psi12_s120"])
 def test_trained_per_direction_artifacts(name):
     # the shipped per-direction networks: one 26-8-8 network for each of the
     # 80 LQ_8 directions, stored with the direction it serves; the input
