@@ -93,9 +93,10 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     const uint32_t pt = step_tile(A.cells + t0, cnt, (int)(blk * A.nc) + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[o][0], A.inc[o][1], A.inc[o][2]};
     __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
+    __shared__ __align__(16) Real mstage[kStageFloats<Real, kMom>];
     if constexpr (kMom > 0) load_ylm_table(A, (int)o, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, true, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                              (int)o, l.ok, L, ytab);
+                                                              (int)o, l.ok, L, ytab, mstage);
     flow_finish(F, tid, o, t);
 }
 

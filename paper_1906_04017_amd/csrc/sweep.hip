@@ -34,9 +34,10 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     const uint32_t pt = step_tile(A.cells, A.ncp, blockIdx.x * (int)A.nc + l.z, l.ok, tvalid);
     const Real inc[3] = {A.inc[blockIdx.y][0], A.inc[blockIdx.y][1], A.inc[blockIdx.y][2]};
     __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
+    __shared__ __align__(16) Real mstage[kStageFloats<Real, kMom>];
     if constexpr (kMom > 0) load_ylm_table(A, (int)blockIdx.y, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, false, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                               blockIdx.y, l.ok, L, ytab);
+                                                               blockIdx.y, l.ok, L, ytab, mstage);
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).

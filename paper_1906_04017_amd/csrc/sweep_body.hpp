@@ -290,6 +290,38 @@ __device__ __forceinline__ void add_moment_source(const PlaneArgs<Real> &A, cons
     }
 }
 
+// Staged form of the same source: the NM x 8 values of the cell were written
+// to LDS (stage, canonical order not yet applied) by the lanes of the
+// segment, which all sweep that cell.
+template <typename Real, int NM>
+__device__ __forceinline__ void add_moment_source_staged(const Real *stage, const Real *yl,
+                                                         int mask, Real sc[8])
+{
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        Real m[8];
+        load8_reflect(stage + k * 8, mask, m);
+        const Real y = yl[k];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) sc[n] = fma(y, m[n], sc[n]);
+    }
+}
+
+// Moment-source staging of anisotropic FP32 sweeps with 8 or more moments
+// (P2, P3): the Do lanes of a segment load their cell's NM x 8 sources once
+// between them (16-byte pieces, piece q by lane q mod Do) into the segment's
+// LDS slot, and each lane then reads all of them from LDS, instead of every
+// lane loading all of them through the vector cache (at P3, 30 16-byte loads
+// per lane and cell, which keep the texture-address pipe busy; at P1 the 6
+// loads cost less than the staging's wave sync).  A block holds at most
+// 4 * floor(64 / Do) segments; with Do >= kStageMinDo that is kStageSegs slots.
+constexpr int kStageMinDo = 6;
+constexpr int kStageSegs = 4 * (64 / kStageMinDo);
+template <typename Real, int kMom>
+constexpr bool kStageMoments = kMom >= 8 && sizeof(Real) == 4;
+template <typename Real, int kMom>
+constexpr int kStageFloats = kStageMoments<Real, kMom> ? kStageSegs * kMom * 8 : 4;
+
 // The harmonics of octant o's directions into LDS, [Do][kYlmStride], for the
 // moment reduction of anisotropic sweeps (every thread of the block, then a
 // block barrier).
@@ -339,7 +371,7 @@ template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kC
 __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real inc[3], int d,
                                           int g, int tid, bool tvalid, uint32_t pt, int o,
                                           bool lane_ok, TileLds<Real> &L,
-                                          const Real *ytab = nullptr)
+                                          const Real *ytab = nullptr, Real *mstage = nullptr)
 {
     constexpr bool kNet = Form == kFormAnn || Form == kFormAnnSplit;   // matrix-core network
     constexpr bool kPaper = Form == kFormAnnPaper || Form == kFormAnnPaperDir;
@@ -352,6 +384,16 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
     // the lane's harmonics, from the block's octant table in LDS (read per
     // cell: cheaper than holding kMom more registers)
     const Real *yl = kMom > 0 ? ytab + (lane_ok ? d : 0) * kYlmStride : nullptr;
+    // moment-source staging (FP32, 8 or more moments, Do >= kStageMinDo):
+    // the lane's segment slot, from the same exact quotient as the lane layout
+    constexpr bool kStage = kStageMoments<Real, kMom>;
+    const bool stage = kStage && A.Do >= (uint32_t)kStageMinDo;
+    Real *mslot = nullptr;
+    if constexpr (kStage) {
+        const int sl = ((tid & 63) * (int)A.mag_do) >> 16;
+        const int seg = (tid >> 6) * (int)A.spw + sl;
+        mslot = mstage + (lane_ok && stage ? seg : 0) * (kMom * 8);
+    }
     AnnRegs R;
     if (kNet) ann_load(static_cast<const unsigned char *>(A.ann_params), tid & 63, R);
     uint32_t I0 = 0, J0 = 0, K0 = 0;
@@ -428,6 +470,20 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                         load8_reflect(A.src + gc * 8, mask, psc);
                     }
                 }
+                if constexpr (kStage) {
+                    // the segment's lanes share the cell (ok is uniform over
+                    // the segment); every lane of the wave reaches the sync
+                    if (stage) {
+                        if (ok) {
+                            const uint32_t gcs = gbase + c0 + il * sx + jl * sy + kl * sz;
+                            const f32x4 *srcv =
+                                reinterpret_cast<const f32x4 *>(A.msrc + (size_t)gcs * (kMom * 8));
+                            f32x4 *dst = reinterpret_cast<f32x4 *>(mslot);
+                            for (int q = d; q < 2 * kMom; q += (int)A.Do) dst[q] = srcv[q];
+                        }
+                        wave_lds_sync();
+                    }
+                }
                 // gather: sigma_t, the reflected source and the three inflows
                 if (ok) {
                     c = c0 + il * sx + jl * sy + kl * sz;
@@ -443,7 +499,12 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                             load8_reflect(A.src + gc * 8, mask, sc);
                         }
                     }
-                    if constexpr (kMom > 0) add_moment_source<Real, kMom>(A, yl, gc, mask, sc);
+                    if constexpr (kMom > 0) {
+                        if (stage)
+                            add_moment_source_staged<Real, kMom>(mslot, yl, mask, sc);
+                        else
+                            add_moment_source<Real, kMom>(A, yl, gc, mask, sc);
+                    }
                     ex = ex0 + kl * A.fx_k + jl * A.fx_j;
                     ey = ey0 + kl * A.fy_k + il * A.fy_j;
                     ez = ez0 + jl * A.fz_k + il * A.fz_j;

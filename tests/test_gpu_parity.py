@@ -321,6 +321,60 @@ def test_pl_source_iteration_matches_oracle(api, ctx, precision, L):
     assert rel(iso["phi"], ref["phi"]) > 100 * bound
 
 
+@pytest.mark.parametrize("order,L,gg", [(6, 1, False), (6, 2, False), (8, 3, False),
+                                        (8, 2, True), (12, 3, False)])
+def test_pl_staged_sources_fp32_match_oracle(api, ctx, order, L, gg):
+    # FP32 sweeps with 8 or more moments and 6 or more directions per octant
+    # stage each cell's moment sources in LDS once per direction segment
+    # (L = 2, 3 at S8 and S12 here; L = 1 and S4 load them per lane):
+    # source iteration against the oracle
+    p = inputs.random_problem((5, 4, 6), order, 2, seed=240 + order + L, c_max=0.7,
+                              length=(0.5, 0.4, 0.6))
+    print_case("pl_staged", name=p["name"], L=L, gg=gg)
+    prob = gpu_problem(api, ctx, p, "fp32")
+    om, w = oracle.lq_n(order)
+    if gg:
+        sn = _multigroup_pl(p, L, 250 + L)
+        prob.set_anisotropy_gg(sn)
+        full = sn
+    else:
+        sn = inputs.anisotropic_orders(p["sigma_s"], L, seed=250 + L)
+        prob.set_anisotropy(sn)
+        full = np.concatenate([p["sigma_s"][None], sn])
+    for sched in ("planes", "dataflow"):
+        prob.set_schedule(sched)
+        phi, info = prob.source_iterate(tol=1e-8, max_iter=1000, allow_notconv=True)
+        mom = prob.moments().double().cpu().numpy()
+        ref = oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"], full, p["q"],
+                                       p["psi_inc"], tol=1e-14, max_iter=3000, gg=gg)
+        assert ref["converged"]
+        for g in range(p["groups"]):
+            assert rel(phi.cpu().numpy()[g], ref["phi"][g]) <= FP32_TOL, (sched, g)
+        assert np.abs(mom - ref["mom"]).max() <= FP32_TOL * np.abs(ref["phi"]).max(), sched
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_pl_staged_sources_fp32_adjoint(api, ctx, L):
+    p = inputs.random_problem((4, 5, 4), 8, 2, seed=260 + L, c_max=0.7,
+                              length=(0.4, 0.5, 0.4))
+    sn = inputs.anisotropic_orders(p["sigma_s"], L, seed=265 + L)
+    print_case("pl_staged_adjoint", name=p["name"], L=L)
+    prob = gpu_problem(api, ctx, p, "fp32", store_psi=True)
+    prob.set_anisotropy(sn)
+    prob.source_iterate(tol=1e-7, max_iter=1000, allow_notconv=True)
+    rng = np.random.default_rng(270 + L)
+    g = rng.uniform(0.0, 1.0, (2, p["sigma_t"].shape[1], 8))
+    gst, gq, info = prob.adjoint(g, tol=1e-7, max_iter=1000, allow_notconv=True)
+    om, w = oracle.lq_n(8)
+    full = np.concatenate([p["sigma_s"][None], sn])
+    r = oracle.source_iterate_pl(mesh_of(p), om, w, p["sigma_t"], full, p["q"], p["psi_inc"],
+                                 tol=1e-15, max_iter=3000, store_psi=True)
+    a = oracle.adjoint(mesh_of(p), om, w, p["sigma_t"], p["sigma_s"], r["psi"], r["phi"], g,
+                       tol=1e-15, sigma_sn=full)
+    assert rel(gst.cpu().numpy(), a["grad_sigma_t"]) <= 1e-4
+    assert rel(gq.cpu().numpy(), a["grad_q"]) <= 1e-4
+
+
 def test_pl_schedules_and_tiles_bitwise(api, ctx):
     p = inputs.random_problem((7, 6, 5), 8, 2, seed=130, c_max=0.7)
     sn = inputs.anisotropic_orders(p["sigma_s"], 2, seed=131)
