@@ -603,7 +603,7 @@ def per_direction_leg(api, ctx, n, ge_avg, ge_p4, reps):
         return {}
     om, w = api.quadrature_ls(8)
     out = {"ann_paper_dir_artifacts": [os.path.basename(x) for x in paths]}
-    eps, ms = [], []
+    eps, ms, ms_ge = [], [], []
     for g in range(3):
         sl = slice(g, g + 1)
         S = torch.tensor(np.repeat(p["q"][sl][..., None], 8, axis=-1), dtype=torch.float32,
@@ -622,11 +622,15 @@ def per_direction_leg(api, ctx, n, ge_avg, ge_p4, reps):
             if sv == "ann":
                 ms.append(round(dt * 1e3, 4))
                 ann.close()
+            else:
+                ms_ge.append(round(dt * 1e3, 4))
             prob.close()
         ge = res["ge"] if ge_avg is None else ge_avg[g]
         eps.append(round(100 * float(((res["ann"] - ge).abs() / (ge.abs() + 1e-8)).mean()), 3))
     out["ann_paper_dir_eps_p_percent_p123"] = eps
     out["ann_paper_dir_ms_per_sweep_p123"] = ms
+    if ms_ge:
+        out["ge_ms_per_sweep_p123_one_group"] = ms_ge
     g = 3
     sl = slice(g, g + 1)
     res = {}

@@ -236,7 +236,9 @@ int dgsn_problem_set_inflow(dgsn_problem *p, const double psi_inc[6]);
    cannot be allocated, and then no network is attached).  With a version-3
    artifact each direction of the problem takes the network whose stored
    direction equals it (every cosine within 1e-6); DGSN_EINVAL, with the
-   previous network left attached, if some direction has none. */
+   previous network left attached, if some direction has none, and
+   DGSN_EUNSUPPORTED for more than 59 directions per octant (a sweep block
+   holds its octant's networks in LDS). */
 int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann);
 
 /* Select the local solver of subsequent sweeps (DGSN_GE, DGSN_GE_DENSE or

@@ -82,6 +82,9 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     const int tid = threadIdx.x;
     const unsigned o = blockIdx.x & 7u;
     if (tid < 64) flow_take(F, o, tid, sh);
+    if constexpr (Form == kFormAnnPaperDir)
+        load_pann_dir_table(static_cast<const float *>(A.ann_params), (int)o, (int)A.Do,
+                            dgsn_dyn_lds);
     __syncthreads();
     // the unit is uniform over the block: keep it in scalar registers
     const unsigned blk = (unsigned)__builtin_amdgcn_readfirstlane((int)sh[0].y);
@@ -96,7 +99,8 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     __shared__ __align__(16) Real mstage[kStageFloats<Real, kMom>];
     if constexpr (kMom > 0) load_ylm_table(A, (int)o, ytab);
     tile_body<Real, Form, B, kStorePsi, kAdjoint, true, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                              (int)o, l.ok, L, ytab, mstage);
+                                                              (int)o, l.ok, L, ytab, mstage,
+                                                              dgsn_dyn_lds);
     flow_finish(F, tid, o, t);
 }
 
@@ -204,15 +208,20 @@ template <int Form>
 void launch_flow_pann(const PlaneArgs<float> &A, const FlowArgs &F, int b, dim3 grid, dim3 block,
                       hipStream_t s)
 {
+    // the per-direction images of the block's octant in dynamic LDS
+    const size_t lds = Form == kFormAnnPaperDir ? (size_t)A.Do * kPannLdsStride * 4 : 0;
     switch (b) {
     case 3:
-        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 3, false, false>), grid, block, 0, s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 3, false, false>), grid, block, lds, s, A,
+                           F);
         break;
     case 2:
-        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 2, false, false>), grid, block, 0, s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 2, false, false>), grid, block, lds, s, A,
+                           F);
         break;
     default:
-        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 1, false, false>), grid, block, 0, s, A, F);
+        hipLaunchKernelGGL((sweep_flow_ge<float, Form, 1, false, false>), grid, block, lds, s, A,
+                           F);
         break;
     }
 }

@@ -8,8 +8,8 @@
 // uniform over the block: they are read through the constant address space,
 // which makes them scalar loads (scalar registers as FMA operands, no LDS, no
 // vector memory traffic).  The lanes of a wave serve several directions, so
-// per-direction weights are vector loads of the lane's own image (the
-// octant's images, 1 KB per direction, stay in the vector cache).  The input
+// per-direction weights are read from the octant's images, which the block
+// first copies to LDS (1 KB per direction).  The input
 // scaling of Eq. (ANN:Eq2), the problem's cell
 // sizes (constant inputs), the signs of the direction cosines and the node and
 // face-node relabelling between the physical and the canonical (reflected)
@@ -38,6 +38,26 @@ constexpr int kPannStride = 272;
 // the problem's directions by every cosine within this distance
 constexpr int kPannMaxDirs = 4096;
 constexpr double kPannDirTol = 1e-6;
+// A sweep block holds its octant's per-direction images in LDS, padded from
+// 272 to kPannLdsStride floats so that the 16-byte reads of ten directions
+// at one weight index fall in disjoint banks; at most kPannLdsMaxDo
+// directions per octant fit the 64 KB of dynamic LDS.
+constexpr int kPannLdsStride = 276;
+constexpr int kPannLdsMaxDo = 65536 / (4 * kPannLdsStride);
+
+typedef float pann_f32x4 __attribute__((ext_vector_type(4)));
+
+// The Do per-direction images of octant o (img: [8][Do][kPannStride]) into
+// LDS, [Do][kPannLdsStride]; the caller synchronises the block afterwards.
+__device__ __forceinline__ void load_pann_dir_table(const float *img, int o, int Do, float *lds)
+{
+    constexpr int n4 = kPannStride / 4;
+    const pann_f32x4 *src = reinterpret_cast<const pann_f32x4 *>(img + (size_t)o * Do * kPannStride);
+    for (int i = threadIdx.x; i < Do * n4; i += blockDim.x) {
+        const int d = i / n4, q = i - d * n4;
+        reinterpret_cast<pann_f32x4 *>(lds + d * kPannLdsStride)[q] = src[i];
+    }
+}
 // per-octant image of the raw-input evaluation (dgsn_ann_infer_octant)
 constexpr int kPannRawW1 = 0;                                  // [8][26], scaling folded in
 constexpr int kPannRawB1 = kPannRawW1 + kPannHidden * kPannIn;  // [8]
@@ -48,7 +68,7 @@ constexpr int kPannRawStride = 296;
 
 // Read-only weight at base[i]: kUniform, through the constant address space
 // (a scalar load for a wave-uniform address; the address space exists in the
-// device pass only); else an ordinary per-lane load.
+// device pass only); else an ordinary per-lane load (from LDS in the sweeps).
 template <bool kUniform>
 __device__ __forceinline__ float pann_w(const float *base, int i)
 {

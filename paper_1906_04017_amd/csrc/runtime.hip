@@ -11,6 +11,7 @@
 #include "cell.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "pann_body.hpp"
 
 namespace dgsn {
 
@@ -1426,6 +1427,10 @@ int dgsn_problem_set_ann(dgsn_problem *p, const dgsn_ann *ann)
         if (ann->version == 2) {
             DGSN_TRY(pann_problem_image(ann, p->h, img));
         } else {
+            if (p->Do > kPannLdsMaxDo)
+                return set_error(DGSN_EUNSUPPORTED, "per-direction networks take at most %d "
+                                 "directions per octant (the problem has %d)", kPannLdsMaxDo,
+                                 p->Do);
             std::vector<int> valid(p->dir_user.size());
             for (size_t k = 0; k < valid.size(); ++k) valid[k] = p->dir_user[k] >= 0;
             DGSN_TRY(pann_problem_image_dir(ann, p->h, p->omega_host.data(), p->Do, valid.data(),

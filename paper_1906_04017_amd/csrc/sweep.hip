@@ -36,8 +36,14 @@ __global__ __launch_bounds__(256, (kMinWavesPerSimd<Real, Form, B, kMom>)) void 
     __shared__ Real ytab[kMom > 0 ? 64 * kYlmStride : 1];
     __shared__ __align__(16) Real mstage[kStageFloats<Real, kMom>];
     if constexpr (kMom > 0) load_ylm_table(A, (int)blockIdx.y, ytab);
+    if constexpr (Form == kFormAnnPaperDir) {
+        load_pann_dir_table(static_cast<const float *>(A.ann_params), (int)blockIdx.y, (int)A.Do,
+                            dgsn_dyn_lds);
+        __syncthreads();
+    }
     tile_body<Real, Form, B, kStorePsi, kAdjoint, false, kMom>(A, inc, l.d, l.g, tid, tvalid, pt,
-                                                               blockIdx.y, l.ok, L, ytab, mstage);
+                                                               blockIdx.y, l.ok, L, ytab, mstage,
+                                                               dgsn_dyn_lds);
 }
 
 // ANN tile sweep: the same lane layout (full waves for the matrix cores).
@@ -534,15 +540,17 @@ int launch_tile_ann(const PlaneArgs<float> &A, int b, bool split, hipStream_t s)
 template <int Form>
 void launch_tile_pann(const PlaneArgs<float> &A, int b, dim3 grid, dim3 block, hipStream_t s)
 {
+    // the per-direction images of the block's octant in dynamic LDS
+    const size_t lds = Form == kFormAnnPaperDir ? (size_t)A.Do * kPannLdsStride * 4 : 0;
     switch (b) {
     case 3:
-        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 3, false, false>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 3, false, false>), grid, block, lds, s, A);
         break;
     case 2:
-        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 2, false, false>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 2, false, false>), grid, block, lds, s, A);
         break;
     default:
-        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 1, false, false>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((sweep_tile_ge<float, Form, 1, false, false>), grid, block, lds, s, A);
         break;
     }
 }

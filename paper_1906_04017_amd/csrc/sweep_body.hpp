@@ -13,6 +13,9 @@ namespace dgsn {
 
 constexpr double kInv4Pi = 0.07957747154594767;   // 1 / (4 pi)
 
+// dynamic LDS of the sweep kernels (the per-direction network images)
+extern __shared__ __align__(16) float dgsn_dyn_lds[];
+
 // Reflect an 8-node vector between physical and canonical node order
 // (v[n] <-> v[n ^ mask]); mask is uniform over the block, so each stage is a
 // scalar branch around register moves.
@@ -371,7 +374,8 @@ template <typename Real, int Form, int B, bool kStorePsi, bool kAdjoint, bool kC
 __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real inc[3], int d,
                                           int g, int tid, bool tvalid, uint32_t pt, int o,
                                           bool lane_ok, TileLds<Real> &L,
-                                          const Real *ytab = nullptr, Real *mstage = nullptr)
+                                          const Real *ytab = nullptr, Real *mstage = nullptr,
+                                          const float *pann_lds = nullptr)
 {
     constexpr bool kNet = Form == kFormAnn || Form == kFormAnnSplit;   // matrix-core network
     constexpr bool kPaper = Form == kFormAnnPaper || Form == kFormAnnPaperDir;
@@ -549,11 +553,12 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                 } else if constexpr (kPaper) {
                     if (ok) {
                         // the octant's network, or the lane's direction's
+                        // (from the block's LDS copy, pann_lds)
                         constexpr bool kUni = Form == kFormAnnPaper;
-                        const int net = kUni ? o : o * A.Do + (lane_ok ? d : 0);
-                        pann_cell<kUni>(static_cast<const float *>(A.ann_params) +
-                                            (size_t)net * kPannStride,
-                                        kap, st, sc, vx, vy, vz, psi);
+                        const float *wimg =
+                            kUni ? static_cast<const float *>(A.ann_params) + o * kPannStride
+                                 : pann_lds + (lane_ok ? d : 0) * kPannLdsStride;
+                        pann_cell<kUni>(wimg, kap, st, sc, vx, vy, vz, psi);
                     } else {
 #pragma unroll
                         for (int n = 0; n < 8; ++n) psi[n] = 0;
