@@ -211,3 +211,21 @@ def test_per_direction_attach_and_batch_rules(api, ctx, tmp_path):
     prob64 = api.Problem(ctx, p4["n"], p4["length"], 1, om, w, precision="fp64")
     with pytest.raises(api.DgsnError):
         prob64.set_ann(ann)
+
+
+def test_per_direction_refuses_more_directions_than_lds_holds(api, ctx, tmp_path):
+    # a sweep block holds its octant's per-direction images in 64 KB of LDS
+    # (59 directions per octant): a 60-direction-per-octant set is refused
+    rng = np.random.default_rng(640)
+    base = np.abs(rng.normal(size=(60, 3)))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    signs = [np.array([-1.0 if (o >> a) & 1 else 1.0 for a in range(3)]) for o in range(8)]
+    om = np.concatenate([base * s for s in signs])
+    w = np.full(len(om), 4.0 * np.pi / len(om))
+    print_case("pann_dir_lds_limit", directions=len(om))
+    path, _ = write_dir(tmp_path, random_nets(641, len(om)), om, "dl.dgsnann")
+    ann = api.Ann(ctx, path)
+    prob = api.Problem(ctx, (2, 2, 2), (1.0, 1.0, 1.0), 1, om, w, precision="fp32",
+                       solver="ann")
+    with pytest.raises(api.DgsnError, match="EUNSUPPORTED.*59"):
+        prob.set_ann(ann)
