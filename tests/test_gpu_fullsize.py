@@ -266,6 +266,69 @@ def test_adjoint_box_full_size(api, ctx):
     assert rel(gq.cpu().numpy(), a["grad_q"]) <= 1e-4
 
 
+def test_adjoint_box_fp64_against_finite_differences(api, ctx):
+    # the adjoint workload in FP64: gradients of J = <g, phi> (g the box
+    # absorption weights of the unperturbed materials, held fixed) with
+    # respect to sigma_t (at fixed sigma_s) and q, against central differences
+    # of FP64 source iterations at 64 seeded cells (half of them in the
+    # response box), and one directional derivative along a random sigma_t
+    # perturbation of every cell.  Every forward runs the same 100 iterations
+    # (c = 0.5: converged to rounding), so J(+h) and J(-h) differ only through
+    # the perturbation; h = 1e-5 keeps the truncation (~h^2) and the rounding
+    # (~1e-15 J / h) of the differences far below 1e-6 of the gradients.
+    p = inputs.adjoint_box()
+    print_case("fullsize_adjoint_fd64", name=p["name"])
+    om, w = api.quadrature_ls(p["order"])
+    G, nc = p["sigma_t"].shape
+    V = np.prod(np.array(p["length"]) / np.array(p["n"]))
+    g = np.zeros((G, nc, 8))
+    g[:, p["box_mask"], :] = ((p["sigma_t"] - p["sigma_s"])[:, p["box_mask"]] * V / 8)[..., None]
+    prob = api.Problem(ctx, p["n"], p["length"], G, om, w, precision="fp64", store_psi=True)
+    prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.autotune()
+    prob.source_iterate(tol=1e-13, max_iter=2000)
+    gst, gq, _ = prob.adjoint(torch.tensor(g, dtype=torch.float64, device="cuda"), tol=1e-13,
+                              max_iter=2000)
+    gst = gst.cpu().numpy()
+    gq = gq.cpu().numpy()
+    fwd = api.Problem(ctx, p["n"], p["length"], G, om, w, precision="fp64")
+    fwd.autotune()
+
+    def J(st, q):
+        fwd.set_materials(st, p["sigma_s"], q)
+        phi, info = fwd.source_iterate(tol=0.0, max_iter=100, allow_notconv=True)
+        assert info["iters"] == 100
+        return float((phi.cpu().numpy() * g).sum())
+
+    rng = np.random.default_rng(47)
+    box = np.flatnonzero(p["box_mask"])
+    cells = [(int(rng.integers(0, G)), int(rng.choice(box))) for _ in range(32)]
+    cells += [(int(rng.integers(0, G)), int(rng.integers(0, nc))) for _ in range(32)]
+    h = 1e-5
+    fd_t, fd_q, ad_t, ad_q = [], [], [], []
+    for gg, c in cells:
+        e = np.zeros((G, nc))
+        e[gg, c] = h
+        fd_t.append((J(p["sigma_t"] + e, p["q"]) - J(p["sigma_t"] - e, p["q"])) / (2 * h))
+        fd_q.append((J(p["sigma_t"], p["q"] + e) - J(p["sigma_t"], p["q"] - e)) / (2 * h))
+        ad_t.append(gst[gg, c])
+        ad_q.append(gq[gg, c])
+    fd_t, fd_q, ad_t, ad_q = map(np.array, (fd_t, fd_q, ad_t, ad_q))
+    et = np.abs(ad_t - fd_t).max() / np.abs(fd_t).max()
+    eq = np.abs(ad_q - fd_q).max() / np.abs(fd_q).max()
+    print(f"adjoint vs FD at 64 cells: sigma_t {et:.2e}, q {eq:.2e}", flush=True)
+    assert et <= 1e-6 and eq <= 1e-6
+    # directional derivative along a random relative perturbation of sigma_t
+    v = rng.uniform(-1.0, 1.0, size=(G, nc)) * p["sigma_t"]
+    hd = 1e-7
+    dd = (J(p["sigma_t"] + hd * v, p["q"]) - J(p["sigma_t"] - hd * v, p["q"])) / (2 * hd)
+    ed = abs(float((gst * v).sum()) - dd) / abs(dd)
+    print(f"directional derivative: {ed:.2e}", flush=True)
+    assert ed <= 1e-6
+    prob.close()
+    fwd.close()
+
+
 def test_uneven_batch_full_size(api, ctx):
     # the batched workload (64 problems, 16^3..96^3, S4..S12, 1..8 groups, GE
     # or the matrix-core network), autotuned as bench.py runs it: every
