@@ -129,9 +129,9 @@ int dgsn_problem_destroy(dgsn_problem *p);
  * cross section sigma_s >= 0 (sigma_s may be NULL = 0), external source q per
  * steradian (NULL = 0).  Enqueued on stream, then checked on the device (the
  * call waits for the stream): DGSN_EINVAL, naming the offending array, if a
- * sigma_t or sigma_s value is negative or not finite or a q value is not
- * finite; the copies are kept, and the problem must get valid materials
- * before it is swept.  Table P1-P4 of Sec. 4 give the paper's values.
+ * sigma_t or sigma_s value is negative or not finite, a q value is not
+ * finite, or a cell's sigma_s exceeds its sigma_t; the copies are kept, and
+ * the problem must get valid materials before it is swept.  Table P1-P4 of Sec. 4 give the paper's values.
  */
 int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void *sigma_s,
                                const void *q, void *stream);

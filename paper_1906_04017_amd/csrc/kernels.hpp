@@ -186,7 +186,7 @@ template <typename Real>
 int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s);
 // *bad |= 1 (sigma_t), 2 (sigma_s) where a value is negative or not finite,
-// 4 where q is not finite; n values each
+// 4 where q is not finite, 8 where sigma_s > sigma_t; n values each
 template <typename Real>
 int launch_check_materials(long long n, const Real *st, const Real *ss, const Real *q,
                            unsigned *bad, hipStream_t s);

@@ -1213,10 +1213,11 @@ int dgsn_problem_set_materials(dgsn_problem *p, const void *sigma_t, const void 
     DGSN_HIP(hipMemcpyAsync(&bad, flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     DGSN_HIP(hipStreamSynchronize(s));
     if (bad)
-        return set_error(DGSN_EINVAL, "invalid materials:%s%s%s",
+        return set_error(DGSN_EINVAL, "invalid materials:%s%s%s%s",
                          (bad & 1u) ? " sigma_t negative or not finite;" : "",
                          (bad & 2u) ? " sigma_s negative or not finite;" : "",
-                         (bad & 4u) ? " q not finite;" : "");
+                         (bad & 4u) ? " q not finite;" : "",
+                         (bad & 8u) ? " sigma_s exceeds sigma_t;" : "");
     return DGSN_OK;
 }
 

@@ -322,8 +322,9 @@ __global__ __launch_bounds__(256) void moments_public(long long nv, int nk,
 }
 
 // Validity of the materials: bit 0 when some sigma_t is negative or not
-// finite, bit 1 likewise for sigma_s, bit 2 when some q is not finite
-// (a vector atomic OR into *bad per offending thread).
+// finite, bit 1 likewise for sigma_s, bit 2 when some q is not finite, bit 3
+// when some sigma_s exceeds its cell's sigma_t (a vector atomic OR into *bad
+// per offending thread).
 template <typename Real>
 __global__ __launch_bounds__(256) void check_materials(long long n, const Real *__restrict__ st,
                                                        const Real *__restrict__ ss,
@@ -337,6 +338,7 @@ __global__ __launch_bounds__(256) void check_materials(long long n, const Real *
         if (!(t >= Real(0)) || isinf(t)) b |= 1u;   // a NaN fails the comparison
         if (!(s >= Real(0)) || isinf(s)) b |= 2u;
         if (!isfinite(v)) b |= 4u;
+        if (s > t) b |= 8u;
     }
     if (b) atomicOr(bad, b);
 }

@@ -1016,7 +1016,8 @@ def test_set_materials_rejects_invalid_values(api, ctx, precision):
     prob = gpu_problem(api, ctx, p, precision)
     st, ss, q = p["sigma_t"].copy(), p["sigma_s"].copy(), p["q"].copy()
     cases = [("sigma_t", dict(st=np.nan)), ("sigma_t", dict(st=-0.5)), ("sigma_t", dict(st=np.inf)),
-             ("sigma_s", dict(ss=-1e-3)), ("sigma_s", dict(ss=np.nan)), ("q", dict(q=-np.inf))]
+             ("sigma_s", dict(ss=-1e-3)), ("sigma_s", dict(ss=np.nan)), ("q", dict(q=-np.inf)),
+             ("sigma_s exceeds", dict(ss=st[0, 3] * 1.01))]
     for name, bad in cases:
         a, b, c = st.copy(), ss.copy(), q.copy()
         if "st" in bad: a[1, 7] = bad["st"]
