@@ -348,9 +348,27 @@ int dgsn_problem_check(dgsn_problem *p, void *stream);
  * schedule (on its internal buffers; user arrays are not touched), keeps the
  * fastest, and returns the choice and the times in ms (ms: host [6], entry
  * schedule * 3 + edge - 1, INFINITY where not applicable; tile, schedule, ms
- * may be NULL).  Synchronizes stream.
+ * may be NULL).  Synchronizes stream.  The choice is cached for the process
+ * under the problem's shape (device architecture and compute units, mesh,
+ * directions per octant, groups, precision, solver and network form,
+ * anisotropic order, psi store): a later call for a problem of the same
+ * shape applies the cached tile and schedule without timing and returns the
+ * cached times.  Not in the paper.
  */
 int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, int *schedule, double *ms);
+
+/*
+ * The autotuner cache (host only, no device work): _clear empties it, _size
+ * counts its entries, _save writes it to path as JSON (one entry per line:
+ * key, tile, schedule, the six times, -1 for INFINITY), _load merges a file
+ * written by _save (entries of the file replace those of the same key).
+ * DGSN_EINVAL for a NULL or unopenable path, DGSN_EFORMAT for a file that is
+ * not such a cache (the cache is then unchanged).
+ */
+int dgsn_autotune_cache_clear(void);
+int dgsn_autotune_cache_size(int *n);
+int dgsn_autotune_cache_save(const char *path);
+int dgsn_autotune_cache_load(const char *path);
 
 /*
  * Stopping criterion of dgsn_source_iterate: DGSN_SI_MAXNORM (default) uses

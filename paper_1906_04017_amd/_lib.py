@@ -101,6 +101,10 @@ SIGNATURES = {
     "dgsn_problem_set_tile": (_I, [_VP, _I]),
     "dgsn_problem_get_tile": (_I, [_VP, _PI]),
     "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PI, _PD]),
+    "dgsn_autotune_cache_clear": (_I, []),
+    "dgsn_autotune_cache_size": (_I, [_PI]),
+    "dgsn_autotune_cache_save": (_I, [ctypes.c_char_p]),
+    "dgsn_autotune_cache_load": (_I, [ctypes.c_char_p]),
     "dgsn_problem_set_schedule": (_I, [_VP, _I, ctypes.c_uint]),
     "dgsn_problem_get_schedule": (_I, [_VP, _PI]),
     "dgsn_problem_check": (_I, [_VP, _VP]),

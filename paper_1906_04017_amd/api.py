@@ -165,6 +165,28 @@ def real_ylm(order, omega):
     return out
 
 
+def autotune_cache_clear():
+    """Forget every autotuner choice of this process."""
+    _lib.check(_lib.load().dgsn_autotune_cache_clear())
+
+
+def autotune_cache_size():
+    n = ctypes.c_int(0)
+    _lib.check(_lib.load().dgsn_autotune_cache_size(ctypes.byref(n)))
+    return n.value
+
+
+def autotune_cache_save(path):
+    """Write the autotuner's choices of this process to path (JSON)."""
+    _lib.check(_lib.load().dgsn_autotune_cache_save(str(path).encode()))
+
+
+def autotune_cache_load(path):
+    """Merge choices saved by autotune_cache_save; later Problem.autotune
+    calls for those shapes apply them without timing."""
+    _lib.check(_lib.load().dgsn_autotune_cache_load(str(path).encode()))
+
+
 def spectral_radius(resid, tail=0.5):
     """Effective spectral radius of a source iteration from its residual
     history: the geometric mean ratio of successive residuals over the last

@@ -6,7 +6,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 
 #include "cell.hpp"
 #include "common.hpp"
@@ -860,6 +862,50 @@ int batch_reduce(dgsn_problem *p, void *phi, hipStream_t s)
 // Time one sweep of the problem with each tile edge on its internal source
 // buffer and keep the faster (ties keep 2).  The problem's outputs are not
 // touched (only its internal partials and fronts).
+// Autotuner cache: the choice for a problem shape, kept for the process and
+// saved to / loaded from a file on request.  The key holds what decides the
+// timing: the device's architecture and compute-unit count, the mesh, the
+// directions per octant, the groups, the precision, the local solver (and
+// network form), the anisotropy and the psi store.
+namespace {
+struct TuneEntry {
+    int tile = 2, schedule = DGSN_SCHED_PLANES;
+    double ms[2 * kMaxTile] = {};
+};
+std::map<std::string, TuneEntry> g_tune;
+std::mutex g_tune_mu;
+
+std::string tune_key(const dgsn_problem *p)
+{
+    int ver = 0, mode = 0;
+    if (p->solver == DGSN_ANN && p->ann) {
+        ver = p->ann->version;
+        mode = p->ann->mode;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "gfx950/%dcu|%dx%dx%d|Do%d|G%d|%s|solver%d|ann%d.%d|L%d%s|psi%d",
+                  p->ctx->num_cu, p->n[0], p->n[1], p->n[2], p->Do, p->G,
+                  p->precision == DGSN_FP64 ? "fp64" : "fp32", p->solver, ver, mode, p->pl_order,
+                  p->pl_gg ? "gg" : "", p->store_psi);
+    return buf;
+}
+
+bool tune_lookup(const std::string &key, TuneEntry &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneEntry &e)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = e;
+}
+}  // namespace
+
 int autotune_problem(dgsn_problem *p, hipStream_t s, double ms_out[2 * kMaxTile])
 {
     if (p->solver == DGSN_ANN && !p->ann) return set_error(DGSN_EINVAL, "no ANN attached");
@@ -924,11 +970,104 @@ int dgsn_problem_autotune(dgsn_problem *p, void *stream, int *tile, int *schedul
     if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
     DGSN_HIP(hipSetDevice(p->ctx->device));
     double t[2 * kMaxTile];
-    DGSN_TRY(autotune_problem(p, as_stream(stream), t));
+    const std::string key = tune_key(p);
+    TuneEntry hit;
+    if (tune_lookup(key, hit)) {
+        // a problem of the same shape was timed before in this process (or
+        // loaded from a cache file): take its choice
+        if (hit.schedule == DGSN_SCHED_DATAFLOW) DGSN_TRY(flow_prepare(p));
+        p->tile_b = hit.tile;
+        p->schedule = hit.schedule;
+        for (int b = 0; b < 2 * kMaxTile; ++b) t[b] = hit.ms[b];
+    } else {
+        DGSN_TRY(autotune_problem(p, as_stream(stream), t));
+        TuneEntry e;
+        e.tile = p->tile_b;
+        e.schedule = p->schedule;
+        for (int b = 0; b < 2 * kMaxTile; ++b) e.ms[b] = t[b];
+        tune_store(key, e);
+    }
     if (tile) *tile = p->tile_b;
     if (schedule) *schedule = p->schedule;
     if (ms)
         for (int b = 0; b < 2 * kMaxTile; ++b) ms[b] = t[b];
+    return DGSN_OK;
+}
+
+int dgsn_autotune_cache_clear(void)
+{
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return DGSN_OK;
+}
+
+int dgsn_autotune_cache_size(int *n)
+{
+    clear_error();
+    if (!n) return set_error(DGSN_EINVAL, "n is NULL");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *n = (int)g_tune.size();
+    return DGSN_OK;
+}
+
+int dgsn_autotune_cache_save(const char *path)
+{
+    clear_error();
+    if (!path) return set_error(DGSN_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return set_error(DGSN_EINVAL, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    // one entry per line (a JSON document that the loader reads line by line)
+    std::fprintf(f, "{\"dgsn_autotune_cache\": 1, \"entries\": [\n");
+    size_t k = 0;
+    for (const auto &kv : g_tune) {
+        std::fprintf(f, "  {\"key\": \"%s\", \"tile\": %d, \"schedule\": %d, \"ms\": [",
+                     kv.first.c_str(), kv.second.tile, kv.second.schedule);
+        for (int b = 0; b < 2 * kMaxTile; ++b)
+            std::fprintf(f, "%s%.17g", b ? ", " : "",
+                         std::isfinite(kv.second.ms[b]) ? kv.second.ms[b] : -1.0);
+        std::fprintf(f, "]}%s\n", ++k < g_tune.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? DGSN_OK : set_error(DGSN_EHIP, "writing %s failed", path);
+}
+
+int dgsn_autotune_cache_load(const char *path)
+{
+    clear_error();
+    if (!path) return set_error(DGSN_EINVAL, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return set_error(DGSN_EINVAL, "cannot open %s", path);
+    std::vector<std::pair<std::string, TuneEntry>> got;
+    char line[1024];
+    bool header = false;
+    int rc = DGSN_OK;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::strstr(line, "\"dgsn_autotune_cache\": 1")) header = true;
+        const char *k = std::strstr(line, "{\"key\": \"");
+        if (!k) continue;
+        k += 9;
+        const char *ke = std::strchr(k, '"');
+        TuneEntry e;
+        double m[2 * kMaxTile];
+        if (!ke || ke - k >= 512 ||
+            std::sscanf(ke, "\", \"tile\": %d, \"schedule\": %d, \"ms\": [%lf, %lf, %lf, %lf, %lf, %lf]",
+                        &e.tile, &e.schedule, &m[0], &m[1], &m[2], &m[3], &m[4], &m[5]) != 8 ||
+            e.tile < 1 || e.tile > kMaxTile ||
+            (e.schedule != DGSN_SCHED_PLANES && e.schedule != DGSN_SCHED_DATAFLOW)) {
+            rc = set_error(DGSN_EFORMAT, "%s: malformed autotune cache entry", path);
+            break;
+        }
+        for (int b = 0; b < 2 * kMaxTile; ++b) e.ms[b] = m[b] < 0.0 ? INFINITY : m[b];
+        got.emplace_back(std::string(k, ke), e);
+    }
+    std::fclose(f);
+    if (rc == DGSN_OK && !header)
+        rc = set_error(DGSN_EFORMAT, "%s: not an autotune cache", path);
+    if (rc != DGSN_OK) return rc;
+    for (const auto &kv : got) tune_store(kv.first, kv.second);
     return DGSN_OK;
 }
 

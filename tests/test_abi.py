@@ -5,6 +5,7 @@ and do its host-only work (quadrature, descriptor validation, artifact
 parsing) correctly.  No device call is made here.
 """
 import ctypes
+import json
 import os
 import re
 import struct
@@ -332,3 +333,39 @@ def test_library_harmonics_match_oracle(lib):
         assert np.abs(api.real_ylm(L, om) - oracle.real_ylm(L, om)).max() < 1e-14
     with pytest.raises(api.DgsnError):
         api.real_ylm(4, om)
+
+
+def test_autotune_cache_file_roundtrip(lib, tmp_path):
+    # the autotuner cache is host state: a file written by hand loads, saves
+    # back with the same entries, and malformed files leave it unchanged
+    from paper_1906_04017_amd import api
+    api.autotune_cache_clear()
+    assert api.autotune_cache_size() == 0
+    src = tmp_path / "tune.json"
+    src.write_text('{"dgsn_autotune_cache": 1, "entries": [\n'
+                   '  {"key": "shape-a", "tile": 2, "schedule": 1, "ms": [1.5, 1.25, 2, -1, 1.125, 3]},\n'
+                   '  {"key": "shape-b", "tile": 3, "schedule": 0, "ms": [4, 3.5, 3, -1, -1, -1]}\n'
+                   ']}\n')
+    api.autotune_cache_load(src)
+    assert api.autotune_cache_size() == 2
+    out = tmp_path / "out.json"
+    api.autotune_cache_save(out)
+    lines = [l.strip() for l in out.read_text().splitlines()]
+    assert lines[0].startswith('{"dgsn_autotune_cache": 1')
+    assert '{"key": "shape-a", "tile": 2, "schedule": 1, "ms": [1.5, 1.25, 2, -1, 1.125, 3]},' in lines
+    assert '{"key": "shape-b", "tile": 3, "schedule": 0, "ms": [4, 3.5, 3, -1, -1, -1]}' in lines
+    json.loads(out.read_text())   # a JSON document
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"dgsn_autotune_cache": 1, "entries": [\n'
+                   '  {"key": "shape-c", "tile": 7, "schedule": 0, "ms": [1, 1, 1, 1, 1, 1]}\n]}\n')
+    with pytest.raises(api.DgsnError, match="EFORMAT"):
+        api.autotune_cache_load(bad)
+    other = tmp_path / "other.json"
+    other.write_text('{"entries": []}\n')
+    with pytest.raises(api.DgsnError, match="EFORMAT"):
+        api.autotune_cache_load(other)
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        api.autotune_cache_load(tmp_path / "missing.json")
+    assert api.autotune_cache_size() == 2
+    api.autotune_cache_clear()
+    assert api.autotune_cache_size() == 0

@@ -1207,6 +1207,38 @@ def test_problem_autotune_keeps_results(api, ctx):
     assert rel(phi, ref) <= FP32_TOL
 
 
+def test_autotune_cache_reuses_choices(api, ctx, tmp_path):
+    # a second problem of the same shape takes the first one's choice and
+    # times without timing again (the times come back identical); the cache
+    # survives a save, clear and load; another shape is timed anew
+    api.autotune_cache_clear()
+    p = inputs.random_problem((9, 8, 7), 8, 2, seed=53)
+    print_case("autotune_cache", name=p["name"])
+    a = gpu_problem(api, ctx, p, "fp32")
+    first = a.autotune()
+    assert api.autotune_cache_size() == 1
+    q = dict(p, sigma_t=p["sigma_t"] * 1.5)
+    b = gpu_problem(api, ctx, q, "fp32")
+    assert b.autotune() == first
+    assert b.schedule() == first[1] and b.tile() == first[0]
+    path = tmp_path / "tune.json"
+    api.autotune_cache_save(path)
+    api.autotune_cache_clear()
+    api.autotune_cache_load(path)
+    c = gpu_problem(api, ctx, p, "fp32")
+    assert c.autotune() == first
+    # the cached choice sweeps correctly (a dataflow choice builds its tables)
+    S = nodal_source(q, seed=6)
+    phi = b.sweep(torch.tensor(S, dtype=torch.float32, device="cuda")).cpu().numpy()
+    om, w = oracle.lq_n(8)
+    assert rel(phi, oracle.sweep(mesh_of(q), om, w, q["sigma_t"], S, q["psi_inc"])) <= FP32_TOL
+    d = gpu_problem(api, ctx, inputs.random_problem((9, 8, 6), 8, 2, seed=54), "fp32")
+    d.autotune()
+    assert api.autotune_cache_size() == 2
+    for prob in (a, b, c, d):
+        prob.close()
+
+
 BATCH = [((5, 4, 3), 4, 2, "ge"), ((9, 9, 9), 8, 3, "ge"), ((3, 7, 2), 12, 1, "ge"),
          ((6, 5, 4), 6, 2, "ann"), ((1, 1, 1), 2, 1, "ge"), ((8, 6, 7), 4, 4, "ann"),
          ((12, 10, 11), 8, 2, "ge"), ((7, 6, 5), 6, 3, "pann"), ((9, 4, 6), 4, 2, "pann")]
