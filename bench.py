@@ -175,8 +175,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(groups, directions or KBA slabs would shard across GPUs; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(groups, then directions, then KBA slabs would shard across GPUs)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -53,7 +53,7 @@ enum {
     DGSN_EHIP = -3,          /* a HIP runtime call failed */
     DGSN_ENOTCONV = -4,      /* iteration limit reached; outputs hold the last iterate */
     DGSN_EFORMAT = -5,       /* malformed ANN artifact */
-    DGSN_EUNSUPPORTED = -6,  /* valid request outside what this build supports */
+    DGSN_EUNSUPPORTED = -6,  /* valid request outside what the library supports */
     DGSN_ETIMEOUT = -7       /* a bounded device-side wait expired */
 };
 
