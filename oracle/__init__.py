@@ -7,8 +7,8 @@ from the paper: element matrices by Gauss quadrature, cell systems assembled
 term by term, Gaussian elimination with partial pivoting, sweeps by nested
 loops in upwind order, source iteration, the exact discrete adjoint, and the
 FP64 forward passes of the two shallow networks (the canonical 24-input one
-and the paper's per-octant 26-input tanh/ELU form).  It shares no code with
-the HIP library.
+and the paper's 26-input tanh/ELU form, per octant or per quadrature
+direction).  It shares no code with the HIP library.
 
 Array conventions (identical to the library's public layout, but implemented
 separately): cell index c = i + nx (j + ny k); nodal fields are

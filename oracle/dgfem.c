@@ -42,10 +42,13 @@
  *     library's matrix-core network), and
  *   - the paper's own form, Eq. (ANN:Eq1)-(ANN:Eq4): 26 physical-frame inputs
  *     scaled by Eq. (ANN:Eq2), tanh hidden layer, ELU output with
- *     beta = 0.1 max(psi_inc), one network per octant (orc_pann_*).
+ *     beta = 0.1 max(psi_inc), one network per octant or one per quadrature
+ *     direction (orc_pann_*).
  * Both forward passes are written out literally in FP64; they are pinned by
  * hand-built networks with closed-form outputs, selector networks that read
- * the inputs back, homogeneity and mirror equivariance (tests).
+ * the inputs back, homogeneity, mirror equivariance, and for the
+ * per-direction set constant networks whose sweep is a weighted index sum
+ * (tests).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -1244,7 +1247,7 @@ struct orc_pann;
 struct orc_ann {
     int nin, nh, nout, act;
     const double *W1, *b1, *W2, *b2;
-    const struct orc_pann *paper;   /* not NULL: the paper-form per-octant network below */
+    const struct orc_pann *paper;   /* not NULL: the paper-form networks below */
 };
 
 /*
