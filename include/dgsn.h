@@ -344,6 +344,19 @@ int dgsn_problem_get_schedule(const dgsn_problem *p, int *schedule);
 int dgsn_problem_check(dgsn_problem *p, void *stream);
 
 /*
+ * Debug modes (not in the paper), flags OR-ed together (0 = none):
+ *   DGSN_DEBUG_POISON_FRONTS  every sweep of the problem first fills its face
+ *     fronts with NaN (a fill kernel on the sweep's stream).  A correct sweep
+ *     reads a front slot only after the upstream cell wrote it in the same
+ *     sweep, so its results are unchanged; a read out of order (a missing
+ *     dataflow wait, a wrong index) yields NaN, which source iteration reports
+ *     as DGSN_EINVAL.  Single-problem sweeps only (batches ignore it).
+ * DGSN_EINVAL for unknown flags.
+ */
+enum { DGSN_DEBUG_POISON_FRONTS = 1 };
+int dgsn_problem_set_debug(dgsn_problem *p, int flags);
+
+/*
  * Autotuner: times one sweep of the problem with each tile edge 1..3 and each
  * schedule (on its internal buffers; user arrays are not touched), keeps the
  * fastest, and returns the choice and the times in ms (ms: host [6], entry

@@ -27,6 +27,7 @@ DGSN_SI_EPS_S = 1
 DGSN_SI_FIXED = 2
 DGSN_ANN_BF16 = 0
 DGSN_ANN_BF16X2 = 1
+DGSN_DEBUG_POISON_FRONTS = 1
 DGSN_SCHED_PLANES = 0
 DGSN_SCHED_DATAFLOW = 1
 
@@ -101,6 +102,7 @@ SIGNATURES = {
     "dgsn_problem_set_tile": (_I, [_VP, _I]),
     "dgsn_problem_get_tile": (_I, [_VP, _PI]),
     "dgsn_problem_autotune": (_I, [_VP, _VP, _PI, _PI, _PD]),
+    "dgsn_problem_set_debug": (_I, [_VP, _I]),
     "dgsn_autotune_cache_clear": (_I, []),
     "dgsn_autotune_cache_size": (_I, [_PI]),
     "dgsn_autotune_cache_save": (_I, [ctypes.c_char_p]),

@@ -328,6 +328,12 @@ class Problem:
         _lib.check(_lib.load().dgsn_problem_get_tile(self._h, ctypes.byref(b)))
         return b.value
 
+    def set_debug(self, poison_fronts=False):
+        """poison_fronts: fill the face fronts with NaN before every sweep,
+        so that an out-of-order front read shows up as NaN."""
+        flags = _lib.DGSN_DEBUG_POISON_FRONTS if poison_fronts else 0
+        _lib.check(_lib.load().dgsn_problem_set_debug(self._h, flags))
+
     def set_schedule(self, schedule, poll_limit=0):
         """'planes' (one launch per hyperplane) or 'dataflow' (one launch per
         sweep, device counters between hyperplanes; every solver)."""

@@ -205,6 +205,10 @@ struct dgsn_problem {
     // holds the raw partial sums of the last source iteration's returned
     // iterate.  bal_inflow and bal_wsum: the boundary inflow and the weight
     // sum of the tallied sweep, from the direction table as the sweep used it.
+    // debug flags (DGSN_DEBUG_*): POISON_FRONTS fills the face fronts with
+    // NaN before every sweep
+    int debug = 0;
+
     int balance = 0;
     int bal_state = 0;
     double bal_host[dgsn::kRedStride] = {};

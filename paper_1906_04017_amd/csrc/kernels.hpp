@@ -185,6 +185,9 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 template <typename Real>
 int launch_build_msrc_gg(long long ncell, int G, int nm, const Real *sigma_cm, const Real *mom,
                          Real *msrc, bool transpose, hipStream_t s);
+// n elements at p set to NaN (debug poisoning of the fronts)
+template <typename Real>
+int launch_fill_nan(long long n, Real *p, hipStream_t s);
 // *bad |= 1 (sigma_t), 2 (sigma_s) where a value is negative or not finite,
 // 4 where q is not finite, 8 where sigma_s > sigma_t; n values each
 template <typename Real>

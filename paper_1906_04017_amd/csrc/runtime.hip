@@ -409,6 +409,13 @@ int run_sweep(dgsn_problem *p, const void *src, bool store_psi, bool adjoint, Re
     const std::vector<int> &off = tiled ? p->tplane_off[tb] : p->plane_off;
     const int nsteps = tiled ? p->n_tplanes[tb] : p->n_planes;
     p->last_stream = s;
+    if (p->debug & DGSN_DEBUG_POISON_FRONTS) {
+        // a sweep reads a front slot only after its upstream cell wrote it in
+        // this sweep: poisoned, any other read turns the flux into NaN
+        DGSN_TRY(launch_fill_nan<Real>(8ll * A.fx_o, A.fx, s));
+        DGSN_TRY(launch_fill_nan<Real>(8ll * A.fy_o, A.fy, s));
+        DGSN_TRY(launch_fill_nan<Real>(8ll * A.fz_o, A.fz, s));
+    }
     if (p->timing) DGSN_TRY(reserve_events(p, p->ev_used + nsteps));
     if (p->schedule == DGSN_SCHED_DATAFLOW) {
         DGSN_TRY(flow_prepare(p));
@@ -1068,6 +1075,15 @@ int dgsn_autotune_cache_load(const char *path)
         rc = set_error(DGSN_EFORMAT, "%s: not an autotune cache", path);
     if (rc != DGSN_OK) return rc;
     for (const auto &kv : got) tune_store(kv.first, kv.second);
+    return DGSN_OK;
+}
+
+int dgsn_problem_set_debug(dgsn_problem *p, int flags)
+{
+    clear_error();
+    if (!p) return set_error(DGSN_EINVAL, "problem is NULL");
+    if (flags & ~DGSN_DEBUG_POISON_FRONTS) return set_error(DGSN_EINVAL, "unknown debug flags");
+    p->debug = flags;
     return DGSN_OK;
 }
 

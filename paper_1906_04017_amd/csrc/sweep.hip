@@ -321,6 +321,15 @@ __global__ __launch_bounds__(256) void moments_public(long long nv, int nk,
     }
 }
 
+// Debug poisoning of the face fronts: every element set to a quiet NaN.
+template <typename Real>
+__global__ __launch_bounds__(256) void fill_nan(long long n, Real *__restrict__ p)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        p[e] = __builtin_nan("");
+}
+
 // Validity of the materials: bit 0 when some sigma_t is negative or not
 // finite, bit 1 likewise for sigma_s, bit 2 when some q is not finite, bit 3
 // when some sigma_s exceeds its cell's sigma_t (a vector atomic OR into *bad
@@ -664,6 +673,16 @@ int launch_reduce_moments(long long nv, int nm, const Real *mom_oct, const Real 
 }
 
 template <typename Real>
+int launch_fill_nan(long long n, Real *p, hipStream_t s)
+{
+    if (n <= 0) return DGSN_OK;
+    const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(fill_nan<Real>, dim3((unsigned)blocks), dim3(256), 0, s, n, p);
+    DGSN_HIP(hipGetLastError());
+    return DGSN_OK;
+}
+
+template <typename Real>
 int launch_check_materials(long long n, const Real *st, const Real *ss, const Real *q,
                            unsigned *bad, hipStream_t s)
 {
@@ -726,6 +745,7 @@ int reduce_blocks_for(long long nv) { return grid_for(nv, 2048); }
                                             Real *, bool, hipStream_t);                        \
     template int launch_cell_major<Real>(long long, int, const Real *, Real *, hipStream_t);   \
     template int launch_moments_public<Real>(long long, int, const Real *, Real *, hipStream_t); \
+    template int launch_fill_nan<Real>(long long, Real *, hipStream_t);                            \
     template int launch_check_materials<Real>(long long, const Real *, const Real *, const Real *, \
                                               unsigned *, hipStream_t);
 DGSN_INST(float)

@@ -67,11 +67,15 @@ def test_blocky_scatter_full_sweep_fp32(api, ctx):
 
 def test_blocky_scatter_dataflow_schedule(api, ctx):
     # the benchmark workload with the one-launch dataflow schedule, every
-    # tile edge: bitwise equal to the hyperplane schedule over repeated sweeps
+    # tile edge: bitwise equal to the hyperplane schedule over repeated sweeps,
+    # with the fronts poisoned (NaN) before every sweep, so that a read of a
+    # slot before its upstream tile wrote it cannot pass as the previous
+    # sweep's (equal) value
     p = inputs.blocky_scatter()
     om, w = api.quadrature_ls(8)
     prob = api.Problem(ctx, p["n"], p["length"], p["groups"], om, w, precision="fp32")
     prob.set_materials(p["sigma_t"], p["sigma_s"], p["q"])
+    prob.set_debug(poison_fronts=True)
     S = torch.tensor(np.repeat(p["q"][..., None], 8, axis=-1), dtype=torch.float32,
                      device="cuda")
     for tile in (1, 2, 3):

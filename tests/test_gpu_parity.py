@@ -1188,6 +1188,52 @@ def test_dataflow_expired_wait_is_reported(api, ctx):
 
 
 # ---------------------------------------------------------------------------
+# poisoned fronts (debug mode): every front slot a sweep reads was written
+# earlier in the same sweep
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", RAGGED[:3], ids=[f"{c[0]}_S{c[2]}_G{c[3]}" for c in RAGGED[:3]])
+def test_poisoned_fronts_leave_sweeps_unchanged(api, ctx, precision, case):
+    n, L, order, G = case
+    p = inputs.random_problem(n, order, G, seed=170, length=L, c_max=0.5)
+    print_case("poison_fronts", name=p["name"], precision=precision)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    S = torch.tensor(nodal_source(p, seed=171), dtype=dt, device="cuda")
+    for solver in (("ge", "ge_dense") if precision == "fp32" else ("ge",)):
+        prob = gpu_problem(api, ctx, p, precision, solver=solver)
+        for sched in ("planes", "dataflow"):
+            prob.set_schedule(sched)
+            for b in (1, 2, 3):
+                prob.set_tile(b)
+                prob.set_debug(poison_fronts=False)
+                ref = prob.sweep(S).clone()
+                prob.set_debug(poison_fronts=True)
+                got = prob.sweep(S)
+                prob.check()
+                assert torch.equal(got, ref), (solver, sched, b)
+                assert torch.isfinite(got).all()
+        # a poisoned source iteration converges to the same iterate
+        prob.set_debug(poison_fronts=False)
+        a, ia = prob.source_iterate(tol=1e-7, max_iter=300, allow_notconv=True)
+        prob.set_debug(poison_fronts=True)
+        b2, ib = prob.source_iterate(tol=1e-7, max_iter=300, allow_notconv=True)
+        assert torch.equal(a, b2) and ia["iters"] == ib["iters"]
+        prob.close()
+    with pytest.raises(api.DgsnError, match="EINVAL"):
+        _lib_set_debug(api, p, ctx, 2)
+
+
+def _lib_set_debug(api, p, ctx, flags):
+    from paper_1906_04017_amd import _lib
+    prob = gpu_problem(api, ctx, p, "fp32")
+    try:
+        _lib.check(_lib.load().dgsn_problem_set_debug(prob._h, flags))
+    finally:
+        prob.close()
+
+
+# ---------------------------------------------------------------------------
 # autotuner and batched execution
 # ---------------------------------------------------------------------------
 
