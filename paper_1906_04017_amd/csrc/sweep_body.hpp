@@ -240,10 +240,13 @@ __device__ __forceinline__ float ann_features(const float kap[3], float hh, floa
         feat[16 + n] = hh * sc[n];
         smax = fmaxf(smax, fabsf(feat[16 + n]));
     }
+    // the two quotients by v_rcp_f32 (1 ulp): m only sets the scale of the
+    // features and of the outputs, so its last bits do not matter, and the
+    // correctly rounded division costs about ten instructions each
     float m = pmax;
     const float den = tau + kmax;
-    if (den > 0.0f) m = fmaxf(m, smax / den);
-    const float rm = m > 0.0f ? 1.0f / m : 0.0f;
+    if (den > 0.0f) m = fmaxf(m, smax * recip(den));
+    const float rm = m > 0.0f ? recip(m) : 0.0f;
 #pragma unroll
     for (int k = 4; k < 24; ++k) feat[k] *= rm;
     return m;
@@ -544,8 +547,13 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                     if (ok) {
                         m = ann_features(kap, A.hh, st, sc, vx, vy, vz, feat);
                     } else {
+                        // a lane without a cell takes whatever its feature
+                        // registers hold (an empty asm defines them, no
+                        // instruction): each sample is its own column of the
+                        // matrix products, so these inputs reach only this
+                        // lane's outputs, which the select below drops
 #pragma unroll
-                        for (int e = 0; e < 24; ++e) feat[e] = 0.0f;
+                        for (int e = 0; e < 24; ++e) asm volatile("" : "=v"(feat[e]));
                     }
                     ann_wave<Form == kFormAnnSplit>(R, feat, y);
 #pragma unroll
