@@ -603,11 +603,15 @@ __device__ __forceinline__ void tile_body(const PlaneArgs<Real> &A, const Real i
                 }
                 // scatter: register fronts, tile-boundary fronts, psi store or
                 // adjoint contraction
+                // the register fronts take psi on every lane (zero where the
+                // lane has no cell): a cell of the tile that exists never
+                // reads a front written by one that does not, since the
+                // cells beyond the mesh in a tile lie downstream of it
+                xf[0] = psi[1]; xf[1] = psi[3]; xf[2] = psi[5]; xf[3] = psi[7];
+                yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
+                zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
+                zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
                 if (ok) {
-                    xf[0] = psi[1]; xf[1] = psi[3]; xf[2] = psi[5]; xf[3] = psi[7];
-                    yf[il][0] = psi[2]; yf[il][1] = psi[3]; yf[il][2] = psi[6]; yf[il][3] = psi[7];
-                    zf[jl][il][0] = psi[4]; zf[jl][il][1] = psi[5];
-                    zf[jl][il][2] = psi[6]; zf[jl][il][3] = psi[7];
                     // a tile's last cell hands its outflow downstream; on the
                     // domain boundary there is no downstream cell, and the
                     // outflow is stored only for the balance tally (keep_out;
